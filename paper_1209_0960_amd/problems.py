@@ -1,0 +1,253 @@
+"""Seeded synthetic workloads: 7-point cell-centred finite-volume diffusion
+matrices on structured boxes, their coefficient fields and right-hand sides.
+
+This module holds no part of the multigrid method: it only discretises the
+model problem -div(K grad u) = f (the SPD sign convention of the paper's model
+problem, Sec. 2, eqs. (model) and (ls)) so that both the CPU oracle and the GPU
+path receive the same CSR arrays.
+
+Discretisation (lowest-order cell-centred finite volumes on an nx*ny*nz box):
+  * interior face between cells a and b: transmissibility t = 2 Ka Kb / (Ka + Kb)
+    (harmonic average of the two cell coefficients);
+  * boundary face: homogeneous Dirichlet at distance h/2, t = 2 K_cell;
+  * A_ii = sum of the six face values (fixed order -x,+x,-y,+y,-z,+z),
+    A_ij = -t for the shared face; the common factor h is dropped so that
+    K == 1 yields integer entries.
+
+Row order: Morton (bit-interleaved x, y, z with x in the lowest bit), so that
+512 consecutive rows of a box whose edges are multiples of 8 form an 8^3 cube.
+For edges that are not powers of two the Morton codes are sorted and compacted.
+Random draws are always taken in lexicographic cell order (x fastest) and then
+permuted, so fields and right-hand sides do not depend on the row order.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class CSRSystem:
+    """A CSR matrix (int32 row pointers / columns, float64 values) plus a RHS."""
+
+    rowptr: np.ndarray
+    colind: np.ndarray
+    vals: np.ndarray
+    b: np.ndarray
+    shape: tuple  # (nx, ny, nz)
+    order: np.ndarray  # order[r] = lexicographic cell index of row r
+
+    @property
+    def n(self) -> int:
+        return int(self.rowptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colind.shape[0])
+
+
+def morton_order(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Return order[r] = lexicographic index (x fastest) of the r-th Morton cell."""
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.int64), np.arange(ny, dtype=np.int64),
+                          np.arange(nx, dtype=np.int64), indexing="ij")
+    x = x.ravel(); y = y.ravel(); z = z.ravel()
+    code = np.zeros(x.shape, dtype=np.int64)
+    bits = max(1, int(math.ceil(math.log2(max(nx, ny, nz, 2)))))
+    for b in range(bits):
+        code |= ((x >> b) & 1) << (3 * b)
+        code |= ((y >> b) & 1) << (3 * b + 1)
+        code |= ((z >> b) & 1) << (3 * b + 2)
+    n = nx * ny * nz
+    if nx == ny == nz and (nx & (nx - 1)) == 0:
+        order = np.empty(n, dtype=np.int64)
+        order[code] = np.arange(n, dtype=np.int64)
+        return order
+    return np.argsort(code, kind="stable")
+
+
+def ccfv7(K: np.ndarray) -> tuple:
+    """Assemble the 7-point CCFV operator for a coefficient field K[z, y, x].
+
+    Returns (rowptr, colind, vals, order) in Morton row order with ascending
+    columns in every row and the diagonal stored.
+    """
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    nz, ny, nx = K.shape
+    n = nx * ny * nz
+
+    def harm(a, b):
+        return 2.0 * a * b / (a + b)
+
+    # face values per direction, shape of the cell array, boundary faces 2K
+    txm = np.empty_like(K); txp = np.empty_like(K)
+    tym = np.empty_like(K); typ = np.empty_like(K)
+    tzm = np.empty_like(K); tzp = np.empty_like(K)
+    fx = harm(K[:, :, :-1], K[:, :, 1:])
+    txp[:, :, :-1] = fx; txp[:, :, -1] = 2.0 * K[:, :, -1]
+    txm[:, :, 1:] = fx; txm[:, :, 0] = 2.0 * K[:, :, 0]
+    fy = harm(K[:, :-1, :], K[:, 1:, :])
+    typ[:, :-1, :] = fy; typ[:, -1, :] = 2.0 * K[:, -1, :]
+    tym[:, 1:, :] = fy; tym[:, 0, :] = 2.0 * K[:, 0, :]
+    fz = harm(K[:-1, :, :], K[1:, :, :])
+    tzp[:-1, :, :] = fz; tzp[-1, :, :] = 2.0 * K[-1, :, :]
+    tzm[1:, :, :] = fz; tzm[0, :, :] = 2.0 * K[0, :, :]
+    del fx, fy, fz
+    diag = txm + txp
+    diag += tym
+    diag += typ
+    diag += tzm
+    diag += tzp
+
+    order = morton_order(nx, ny, nz)
+    inv = np.empty(n, dtype=np.int64)
+    inv[order] = np.arange(n, dtype=np.int64)
+
+    z, y, x = np.unravel_index(order, (nz, ny, nx))
+    sentinel = n
+    cols = np.full((n, 7), sentinel, dtype=np.int64)
+    vals = np.zeros((n, 7), dtype=np.float64)
+    rows = np.arange(n, dtype=np.int64)
+    cols[:, 0] = rows
+    vals[:, 0] = diag.ravel()[order]
+    del diag
+    lex = order
+    stride = {"x": 1, "y": nx, "z": nx * ny}
+    slot = 1
+    for axis, coord, ext, tm, tp in (("x", x, nx, txm, txp), ("y", y, ny, tym, typ),
+                                     ("z", z, nz, tzm, tzp)):
+        s = stride[axis]
+        lo = coord > 0
+        cols[lo, slot] = inv[lex[lo] - s]
+        vals[lo, slot] = -tm.ravel()[lex[lo]]
+        slot += 1
+        hi = coord < ext - 1
+        cols[hi, slot] = inv[lex[hi] + s]
+        vals[hi, slot] = -tp.ravel()[lex[hi]]
+        slot += 1
+    del x, y, z, inv
+    perm = np.argsort(cols, axis=1, kind="stable")
+    cols = np.take_along_axis(cols, perm, axis=1)
+    vals = np.take_along_axis(vals, perm, axis=1)
+    del perm
+    valid = cols < sentinel
+    counts = valid.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    colind = cols[valid].astype(np.int32)
+    v = vals[valid]
+    return rowptr.astype(np.int32), colind, np.ascontiguousarray(v), order
+
+
+def field_constant(n: int, shape=None) -> np.ndarray:
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    return np.ones((nz, ny, nx), dtype=np.float64)
+
+
+def field_lognormal(rng: np.random.Generator, n: int, sigma2: float, window: int,
+                    divisor: float) -> np.ndarray:
+    """K = exp(sigma * g') with g' a window-summed white noise field.
+
+    g ~ N(0,1) i.i.d. on (n+window-1)^3 points (lexicographic draw, x fastest);
+    g'[z,y,x] = (sum of the window^3 block starting at [z,y,x]) / divisor.
+    """
+    m = n + window - 1
+    g = rng.standard_normal(m * m * m).reshape(m, m, m)
+    gs = np.zeros((n, n, n), dtype=np.float64)
+    for dz in range(window):
+        for dy in range(window):
+            for dx in range(window):
+                gs += g[dz:dz + n, dy:dy + n, dx:dx + n]
+    gs /= divisor
+    return np.exp(math.sqrt(sigma2) * gs)
+
+
+def field_layered(rng: np.random.Generator, n: int, layer: int = 4) -> np.ndarray:
+    """K = 10^{u_z} * exp(eps): u_z ~ U[-3,3] per z-layer of `layer` cells, eps ~ N(0,1)."""
+    nl = (n + layer - 1) // layer
+    u = rng.uniform(-3.0, 3.0, nl)
+    eps = rng.standard_normal(n * n * n).reshape(n, n, n)
+    zlayer = np.arange(n) // layer
+    return (10.0 ** u[zlayer])[:, None, None] * np.exp(eps)
+
+
+def field_jump_cube(n: int) -> np.ndarray:
+    """Coefficient of the jump problem: k = 1e3 in a centred cube of width 0.8,
+    k = 1e-2 in the eight corner cubes of width 0.1, k = 1 elsewhere (cell centres)."""
+    c = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    K = np.ones((n, n, n))
+    inner = (np.abs(X - 0.5) < 0.4) & (np.abs(Y - 0.5) < 0.4) & (np.abs(Z - 0.5) < 0.4)
+    K[inner] = 1e3
+
+    def corner(v):
+        return (v < 0.1) | (v > 0.9)
+
+    K[corner(X) & corner(Y) & corner(Z)] = 1e-2
+    return K
+
+
+def _rhs(rng: np.random.Generator, order: np.ndarray) -> np.ndarray:
+    b_lex = rng.uniform(-1.0, 1.0, order.shape[0])
+    return np.ascontiguousarray(b_lex[order])
+
+
+def poisson(n: int, seed: int = 0, shape=None) -> CSRSystem:
+    """K == 1 on an n^3 (or nx*ny*nz) box; b ~ U[-1,1] from default_rng(seed)."""
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    K = field_constant(n, (nx, ny, nz))
+    rowptr, colind, vals, order = ccfv7(K)
+    rng = np.random.default_rng(seed)
+    return CSRSystem(rowptr, colind, vals, _rhs(rng, order), (nx, ny, nz), order)
+
+
+def lognormal(n: int, seed: int = 1, sigma2: float = 4.0, window: int = 2,
+              divisor: float = math.sqrt(8.0)) -> CSRSystem:
+    """Heterogeneous lognormal K (defaults: sigma^2 = 4, normalised 2x2x2 box filter)."""
+    rng = np.random.default_rng(seed)
+    K = field_lognormal(rng, n, sigma2, window, divisor)
+    rowptr, colind, vals, order = ccfv7(K)
+    return CSRSystem(rowptr, colind, vals, _rhs(rng, order), (n, n, n), order)
+
+
+def layered(n: int, seed: int = 2) -> CSRSystem:
+    """Layered lognormal K with contrast about 1e6."""
+    rng = np.random.default_rng(seed)
+    K = field_layered(rng, n)
+    rowptr, colind, vals, order = ccfv7(K)
+    return CSRSystem(rowptr, colind, vals, _rhs(rng, order), (n, n, n), order)
+
+
+def jump_cube(n: int, seed: int = 5) -> CSRSystem:
+    K = field_jump_cube(n)
+    rowptr, colind, vals, order = ccfv7(K)
+    rng = np.random.default_rng(seed)
+    return CSRSystem(rowptr, colind, vals, _rhs(rng, order), (n, n, n), order)
+
+
+def from_field(K: np.ndarray, seed: int = 0) -> CSRSystem:
+    nz, ny, nx = K.shape
+    rowptr, colind, vals, order = ccfv7(K)
+    rng = np.random.default_rng(seed)
+    return CSRSystem(rowptr, colind, vals, _rhs(rng, order), (nx, ny, nz), order)
+
+
+def batched_systems(count: int = 64, seed: int = 3, edges=(16, 24, 32, 48, 64),
+                    nrhs: int = 4, sigma2: float = 2.0) -> list:
+    """Independent lognormal systems with edges drawn from `edges` (4^3 window / 8)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(edges), size=count)
+    out = []
+    for n in ns:
+        n = int(n)
+        K = field_lognormal(rng, n, sigma2, 4, 8.0)
+        rowptr, colind, vals, order = ccfv7(K)
+        B = rng.uniform(-1.0, 1.0, (nrhs, n * n * n))[:, order]
+        out.append(CSRSystem(rowptr, colind, vals, np.ascontiguousarray(B), (n, n, n), order))
+    return out
+
+
+def nnz_7pt(nx: int, ny: int, nz: int) -> int:
+    """Stored entries of the 7-point operator with eliminated Dirichlet boundaries."""
+    return nx * ny * nz + 2 * ((nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1))

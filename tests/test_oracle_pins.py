@@ -1,0 +1,515 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: a closed
+form, a hand-derived result stored under tests/golden (with its citation), an
+invariant the definitions imply, or an independent library computation.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle as O
+from paper_1209_0960_amd import problems as P
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def dense(rp, ci, v):
+    n = rp.shape[0] - 1
+    return sp.csr_matrix((v, ci, rp), shape=(n, n)).toarray()
+
+
+def csr_from_rows(rows):
+    rp = [0]
+    ci, v = [], []
+    for r in rows:
+        ci += r["cols"]
+        v += r["vals"]
+        rp.append(len(ci))
+    return np.array(rp, np.int32), np.array(ci, np.int32), np.array(v, np.float64)
+
+
+# ----------------------------------------------------------------- generator
+def test_generator_k1_integer_entries_and_boundary_diagonal():
+    """K = 1: off-diagonals -1, diagonal 6 + (number of boundary faces)."""
+    s = P.poisson(5)
+    A = dense(s.rowptr, s.colind, s.vals)
+    assert np.array_equal(A, A.T)
+    off = A - np.diag(np.diag(A))
+    assert set(np.unique(off)) <= {0.0, -1.0}
+    # boundary faces of each cell from its coordinates
+    z, y, x = np.unravel_index(s.order, (5, 5, 5))
+    nb = sum((c == 0).astype(int) + (c == 4).astype(int) for c in (x, y, z))
+    assert np.array_equal(np.diag(A), 6.0 + nb)
+    assert s.nnz == P.nnz_7pt(5, 5, 5)
+
+
+def test_generator_morton_tiles_are_cubes():
+    s = P.poisson(16)
+    z, y, x = np.unravel_index(s.order, (16, 16, 16))
+    for t in range(8):
+        sl = slice(512 * t, 512 * (t + 1))
+        for c in (x, y, z):
+            assert c[sl].max() - c[sl].min() == 7
+
+
+# ----------------------------------------------------------------- strength
+def test_strength_k1_all_in_tile_edges_strong_none_isolated():
+    """K = 1: s_ij = 1/(d_i d_j) with d in [6, 9]; s >= 1/81 > 0.08/36 >= delta*min(eta),
+    so every in-tile off-diagonal edge is strong, no row is isolated, and edges
+    leaving the tile are never flagged (Sec. 2.1; Alg. 4 restricts to owned edges)."""
+    s = P.poisson(12)
+    T = 64
+    strong, iso = O.strength(s.rowptr, s.colind, s.vals, tile_rows=T)
+    assert iso.sum() == 0
+    rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    in_tile = (rows // T == s.colind // T) & (rows != s.colind)
+    assert np.array_equal(strong.astype(bool), in_tile)
+
+
+def test_strength_interface_of_two_materials_is_weak():
+    """Two-material brick, contrast 1e3: interface s ~ 1e-4 < delta*min(eta) ~ 2e-3,
+    so no interface edge is strong, while every in-material edge is (Sec. 2.1:
+    aggregates must not cross coefficient jumps)."""
+    n = 8
+    K = np.ones((n, n, n))
+    K[:, :, n // 2:] = 1e3
+    s = P.from_field(K)
+    strong, iso = O.strength(s.rowptr, s.colind, s.vals, tile_rows=n ** 3)
+    z, y, x = np.unravel_index(s.order, (n, n, n))
+    side = x >= n // 2
+    rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    off = rows != s.colind
+    cross = side[rows] != side[s.colind]
+    assert not strong[off & cross].any()
+    assert strong[off & ~cross].all()
+    assert iso.sum() == 0
+
+
+def test_strength_positive_offdiagonal_is_never_strong():
+    """w_E is zero for positive off-diagonals, so such edges are never strong."""
+    s = P.poisson(4)
+    v = s.vals.copy()
+    rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    # flip the sign of the coupling between rows 0 and 1 (both directions)
+    for i, j in ((0, 1), (1, 0)):
+        k = np.nonzero((rows == i) & (s.colind == j))[0][0]
+        v[k] = 1.0
+    strong, _ = O.strength(s.rowptr, s.colind, v, tile_rows=64)
+    k01 = np.nonzero((rows == 0) & (s.colind == 1))[0][0]
+    assert strong[k01] == 0
+    k02 = np.nonzero((rows == 0) & (s.colind == 2))[0][0]
+    assert strong[k02] == 1
+
+
+# ----------------------------------------------------------------- aggregation
+def run_agg(s, T, smin, smax, dmax, delta=0.08, beta=1e-5):
+    strong, iso = O.strength(s.rowptr, s.colind, s.vals, tile_rows=T, delta=delta, beta=beta)
+    agg, nc, tc = O.aggregate(s.rowptr, s.colind, strong, iso, tile_rows=T, smin=smin, smax=smax, dmax=dmax)
+    return agg, nc, tc, strong, iso
+
+
+def test_chain_aggregates_hand_derived():
+    g = gold("chain_aggregates.json")
+    p = g["params"]
+    for case in g["cases"]:
+        m = case["m"]
+        s = P.poisson(0, shape=(m, 1, 1))
+        agg, nc, _, _, _ = run_agg(s, 512, p["smin"], p["smax"], p["dmax"])
+        assert agg.tolist() == case["agg"], m
+
+
+def test_diameter_limit_hand_derived():
+    g = gold("diameter_limit.json")
+    p = g["params"]
+    s = P.poisson(0, shape=(g["m"], 1, 1))
+    agg, nc, _, _, _ = run_agg(s, 512, p["smin"], p["smax"], p["dmax"])
+    assert agg.tolist() == g["agg"]
+
+
+def test_singleton_merge_hand_derived():
+    g = gold("chain_merge.json")
+    p = g["params"]
+    s = P.poisson(0, shape=(g["m"], 1, 1))
+    agg, nc, _, _, _ = run_agg(s, 512, p["smin"], p["smax"], p["dmax"])
+    assert agg.tolist() == g["agg"] and nc == g["nc"]
+
+
+def test_first_aggregate_of_4cube_hand_derived():
+    g = gold("cube4_first_aggregate.json")
+    p = g["params"]
+    s = P.poisson(g["n"])
+    agg, nc, _, _, _ = run_agg(s, 512, p["smin"], p["smax"], p["dmax"])
+    assert sorted(np.nonzero(agg == 0)[0].tolist()) == g["first_aggregate_rows"]
+
+
+def test_isolated_phase_hand_derived():
+    g = gold("iso_pairs.json")
+    p = g["params"]
+    for rows, expect in ((g["rows"], g["agg"]), (g["variant_without_1_3"]["rows"], g["variant_without_1_3"]["agg"])):
+        rp, ci, v = csr_from_rows(rows)
+        strong, iso = O.strength(rp, ci, v, tile_rows=512, delta=p["delta"], beta=p["beta"])
+        assert iso.tolist() == [0, 0, 1, 1]
+        agg, nc, _ = O.aggregate(rp, ci, strong, iso, tile_rows=512, smin=p["smin"], smax=p["smax"], dmax=p["dmax"])
+        assert agg.tolist() == expect
+
+
+def graph_matrix(nv, strong_edges, weak_edges, diag=4.0, weak=-1e-3):
+    A = np.zeros((nv, nv))
+    np.fill_diagonal(A, diag)
+    for i, j in strong_edges:
+        A[i, j] = A[j, i] = -1.0
+    for i, j in weak_edges:
+        A[i, j] = A[j, i] = weak
+    M = sp.csr_matrix(A)
+    M.sort_indices()
+    return M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64)
+
+
+def test_strength_threshold_hand_derived():
+    g = gold("strength_threshold.json")
+    for case in g["cases"]:
+        c = case["c"]
+        A = np.diag([4.0] * 4)
+        A[0, 1] = A[1, 0] = -1.0
+        A[2, 3] = A[3, 2] = -1.0
+        A[0, 2] = A[2, 0] = -c
+        M = sp.csr_matrix(A)
+        M.sort_indices()
+        rp, ci, v = M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data
+        strong, iso = O.strength(rp, ci, v, tile_rows=4, delta=g["delta"])
+        rows = np.repeat(np.arange(4), np.diff(rp))
+        flag = {(int(r), int(cc)): int(f) for r, cc, f in zip(rows, ci, strong)}
+        assert flag[(0, 2)] == flag[(2, 0)] == case["strong_02"]
+        assert flag[(0, 1)] == flag[(2, 3)] == 1
+        assert iso.sum() == 0
+
+
+@pytest.mark.parametrize("name", ["tie_connect_ratio.json", "tie_neighbors.json", "merge_tie.json",
+                                  "connect_adjacent_weight.json"])
+def test_grow_tie_breaks_hand_derived(name):
+    g = gold(name)
+    p = g["params"]
+    nv = len(g["agg"])
+    rp, ci, v = graph_matrix(nv, g["edges_strong"], g["edges_weak"])
+    strong, iso = O.strength(rp, ci, v, tile_rows=512, delta=p["delta"], beta=p["beta"])
+    assert iso.sum() == 0
+    agg, nc, _ = O.aggregate(rp, ci, strong, iso, tile_rows=512, smin=p["smin"], smax=p["smax"], dmax=p["dmax"])
+    assert agg.tolist() == g["agg"]
+
+
+def test_diagonal_matrix_gives_singletons():
+    n = 10
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    v = np.full(n, 3.0)
+    strong, iso = O.strength(rp, ci, v, tile_rows=4)
+    assert iso.all()
+    agg, nc, tc = O.aggregate(rp, ci, strong, iso, tile_rows=4)
+    assert nc == n and agg.tolist() == list(range(n)) and tc.tolist() == [4, 4, 2]
+
+
+def bfs_diameter(adj_sets, S):
+    S = list(S)
+    best = 0
+    for s0 in S:
+        dist = {s0: 0}
+        q = [s0]
+        for u in q:
+            for w in adj_sets[u]:
+                if w in S and w not in dist:
+                    dist[w] = dist[u] + 1
+                    q.append(w)
+        if len(dist) != len(S):
+            return 10 ** 9
+        best = max(best, max(dist.values()))
+    return best
+
+
+@pytest.mark.parametrize("case", ["k1_20", "hetero_24", "jump_20", "layered_16"])
+def test_aggregation_invariants(case):
+    """Partition of all rows; every aggregate inside one tile; ids dense and
+    tile-major; aggregates of non-isolated rows connected by strong edges;
+    size at most s_max plus merged singletons; deterministic."""
+    T = 512
+    s = {"k1_20": lambda: P.poisson(20), "hetero_24": lambda: P.lognormal(24),
+         "jump_20": lambda: P.jump_cube(20), "layered_16": lambda: P.layered(16)}[case]()
+    agg, nc, tc, strong, iso = run_agg(s, T, 8, 12, 3)
+    agg2, nc2, _, _, _ = run_agg(s, T, 8, 12, 3)
+    assert np.array_equal(agg, agg2) and nc == nc2
+    assert agg.min() == 0 and agg.max() == nc - 1
+    assert len(np.unique(agg)) == nc
+    assert tc.sum() == nc
+    offs = np.concatenate([[0], np.cumsum(tc)])
+    rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    for I in range(nc):
+        mem = np.nonzero(agg == I)[0]
+        t = mem[0] // T
+        assert (mem // T == t).all()
+        assert offs[t] <= I < offs[t + 1]
+    # strong connectivity of non-isolated aggregates
+    sadj = [set() for _ in range(s.n)]
+    for k in np.nonzero(strong)[0]:
+        sadj[rows[k]].add(int(s.colind[k]))
+    sizes = np.bincount(agg, minlength=nc)
+    assert sizes.max() <= 12 + 6
+    for I in range(nc):
+        mem = set(np.nonzero(agg == I)[0].tolist())
+        if iso[list(mem)].any():
+            continue
+        assert bfs_diameter(sadj, mem) < 10 ** 9, I
+
+
+def test_coarsening_rate_k1():
+    s = P.poisson(16)
+    agg, nc, tc, _, _ = run_agg(s, 512, 8, 12, 3)
+    assert 4096 / nc > 6.0
+
+
+# ----------------------------------------------------------------- Galerkin
+def test_galerkin_equals_dense_ptap():
+    """A_c = P^T A P with P(i,J) = 1 iff i in a_J (Sec. 2.1, eq. (prolongation))."""
+    for s in (P.poisson(10), P.lognormal(10, seed=7)):
+        agg, nc, _, _, _ = run_agg(s, 512, 8, 12, 3)
+        cp, cc, cv = O.galerkin(s.rowptr, s.colind, s.vals, agg, nc)
+        A = dense(s.rowptr, s.colind, s.vals)
+        Pm = np.zeros((s.n, nc))
+        Pm[np.arange(s.n), agg] = 1.0
+        Ac = Pm.T @ A @ Pm
+        G = dense(cp, cc, cv)
+        if np.all(A == np.round(A)):
+            assert np.array_equal(G, Ac)
+        else:
+            assert np.abs(G - Ac).max() <= 1e-14 * np.abs(Ac).max()
+        # pattern = pairs (agg i, agg j) over stored entries, columns ascending
+        rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+        pairs = set(zip(agg[rows].tolist(), agg[s.colind].tolist()))
+        crow = np.repeat(np.arange(nc), np.diff(cp))
+        assert set(zip(crow.tolist(), cc.tolist())) == pairs
+        assert all((np.diff(cc[cp[I]:cp[I + 1]]) > 0).all() for I in range(nc))
+        # symmetry and row sums: A_c 1 = P^T (A 1)
+        assert np.abs(G - G.T).max() <= 1e-14 * np.abs(G).max()
+        assert np.allclose(G.sum(1), Pm.T @ A.sum(1), rtol=1e-13, atol=1e-12)
+
+
+def test_galerkin_closed_form_aligned_cubes():
+    """K = 1 with aligned 2x2x2 aggregates: P^T A_n P = 4 A_{n/2} exactly."""
+    n = 8
+    s = P.poisson(n)
+    sc = P.poisson(n // 2)
+    # with Morton order the aligned 2x2x2 block of row r is r // 8, and coarse
+    # Morton order of the blocks is the same index
+    agg = (np.arange(s.n) // 8).astype(np.int32)
+    cp, cc, cv = O.galerkin(s.rowptr, s.colind, s.vals, agg, s.n // 8)
+    assert np.array_equal(cp, sc.rowptr) and np.array_equal(cc, sc.colind)
+    assert np.array_equal(cv, 4.0 * sc.vals)
+
+
+# ----------------------------------------------------------------- colouring
+def test_colouring_proper_and_first_fit():
+    for s in (P.poisson(12), P.lognormal(10)):
+        c, k = O.colour(s.rowptr, s.colind, seed=3)
+        rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+        off = rows != s.colind
+        assert not np.any(c[rows[off]] == c[s.colind[off]])
+        assert c.max() == k - 1
+        # first fit along descending keys: each colour below c(i) appears on a
+        # higher-key neighbour of i
+        h = np.array([O.fmix32(i ^ 3) for i in range(s.n)], dtype=np.uint64)
+        key = (h << np.uint64(32)) | np.arange(s.n, dtype=np.uint64)
+        for i in range(s.n):
+            nb = s.colind[s.rowptr[i]:s.rowptr[i + 1]]
+            nb = nb[(nb != i) & (key[nb] > key[i])]
+            assert set(range(c[i])) <= set(c[nb].tolist())
+
+
+def test_fmix32_known_properties():
+    assert O.fmix32(0) == 0
+    vals = {O.fmix32(i) for i in range(4096)}
+    assert len(vals) == 4096  # a bijection on 32-bit words
+
+
+# ----------------------------------------------------------------- smoother
+def test_mcsgs_equals_textbook_sgs_on_colour_permuted_matrix():
+    s = P.lognormal(8, seed=11)
+    c, k = O.colour(s.rowptr, s.colind, seed=0)
+    rng = np.random.default_rng(0)
+    b = rng.standard_normal(s.n)
+    x0 = rng.standard_normal(s.n)
+    x = O.mcsgs(s.rowptr, s.colind, s.vals, c, k, b, x0)
+    A = dense(s.rowptr, s.colind, s.vals)
+    perm = np.lexsort((np.arange(s.n), c))
+    Ap = A[np.ix_(perm, perm)]
+    bp, xp = b[perm], x0[perm]
+    Lw = np.tril(Ap)
+    Up = np.triu(Ap, 1)
+    xp = sla.solve_triangular(Lw, bp - Up @ xp, lower=True)
+    Uw = np.triu(Ap)
+    Lp = np.tril(Ap, -1)
+    xp = sla.solve_triangular(Uw, bp - Lp @ xp, lower=False)
+    ref = np.empty(s.n)
+    ref[perm] = xp
+    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ----------------------------------------------------------------- Cholesky
+def test_cholesky_matches_library_and_rejects_indefinite():
+    rng = np.random.default_rng(1)
+    M = rng.standard_normal((40, 40))
+    A = M @ M.T + 40 * np.eye(40)
+    st, L = O.cholesky(A)
+    assert st == O.OK
+    assert np.abs(L - np.linalg.cholesky(A)).max() <= 1e-12
+    B = A.copy()
+    B[5, 5] = -1.0
+    st, _ = O.cholesky(B)
+    assert st == O.NOT_SPD
+
+
+# ----------------------------------------------------------------- V-cycle / PCG
+def vcycle_operator(H, n):
+    return np.column_stack([H.vcycle(e) for e in np.eye(n)])
+
+
+def test_single_level_vcycle_is_exact_inverse():
+    s = P.lognormal(6, seed=4)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals)
+    assert H.levels == 1
+    A = dense(s.rowptr, s.colind, s.vals)
+    z = H.vcycle(s.b)
+    assert np.abs(A @ z - s.b).max() <= 1e-12
+    out = H.pcg(s.b)
+    assert out["status"] == O.OK and out["iterations"] == 1
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.6])
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_two_grid_operator_spd_and_contracting(omega, smoother):
+    """Two-level V-cycle B: symmetric positive definite; E = I - B A has rho < 1."""
+    s = P.lognormal(8, seed=2)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=100, omega=omega, smoother=smoother)
+    assert H.levels == 2
+    A = dense(s.rowptr, s.colind, s.vals)
+    B = vcycle_operator(H, s.n)
+    assert np.abs(B - B.T).max() <= 1e-10 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    rho = np.abs(np.linalg.eigvals(np.eye(s.n) - B @ A)).max()
+    assert rho < 1.0
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.6])
+def test_coarse_correction_is_omega_scaled_galerkin_inverse(omega):
+    """Without smoothing, the two-level cycle is the coarse correction with the
+    paper's A_c = (1/omega) P^T A P: B = P A_c^-1 P^T = omega P (P^T A P)^-1 P^T."""
+    s = P.lognormal(8, seed=5)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=100, omega=omega, pre_sweeps=0, post_sweeps=0)
+    assert H.levels == 2
+    agg = H.level(0).agg
+    nc = H.level(1).n
+    A = dense(s.rowptr, s.colind, s.vals)
+    Pm = np.zeros((s.n, nc))
+    Pm[np.arange(s.n), agg] = 1.0
+    Ac = (Pm.T @ A @ Pm) / omega
+    Bref = Pm @ np.linalg.solve(Ac, Pm.T)
+    B = vcycle_operator(H, s.n)
+    assert np.abs(B - Bref).max() <= 1e-10 * np.abs(Bref).max()
+
+
+def test_pcg_matches_dense_solve_8cube():
+    s = P.lognormal(8, seed=3)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=100)
+    out = H.pcg(s.b, rtol=1e-8)
+    assert out["status"] == O.OK
+    A = dense(s.rowptr, s.colind, s.vals)
+    x = np.linalg.solve(A, s.b)
+    kappa = np.linalg.cond(A)
+    err = np.linalg.norm(out["x"] - x) / np.linalg.norm(x)
+    assert err <= kappa * 1e-8
+    assert out["true_rel_residual"] <= 1.01e-8
+
+
+def test_pcg_identity_like_cg_residuals():
+    """With a one-level hierarchy M = A^-1 and CG stops after one step; with the
+    multilevel V-cycle the recursive residual history is monotone in A-norm
+    terms and ends below rtol; FCG and PCG agree for the symmetric FP64 cycle."""
+    s = P.poisson(12)
+    Hp = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, flexible=0)
+    Hf = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, flexible=1)
+    a = Hp.pcg(s.b, keep_iterates=True)
+    b = Hf.pcg(s.b, keep_iterates=True)
+    assert a["status"] == b["status"] == O.OK
+    assert abs(a["iterations"] - b["iterations"]) <= 1
+    k = min(a["iterations"], b["iterations"])
+    d = np.abs(a["iterates"][:k + 1] - b["iterates"][:k + 1]).max()
+    assert d <= 1e-6 * np.abs(a["iterates"][k]).max()
+
+
+def test_pcg_reports_breakdown_on_indefinite():
+    s = P.poisson(4)
+    v = s.vals.copy()
+    # make row/col 0 strongly negative-definite while keeping a positive diagonal
+    rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    v[(rows == 0) & (s.colind != 0)] *= 50
+    v[(s.colind == 0) & (rows != 0)] *= 50
+    st = O.validate(s.rowptr, s.colind, v)
+    assert st == O.OK
+    with pytest.raises(O.OracleError) as e:
+        O.Hierarchy(s.rowptr, s.colind, v)
+    assert e.value.status == O.NOT_SPD
+
+
+def test_validate_error_paths():
+    s = P.poisson(3)
+    assert O.validate(s.rowptr, s.colind, s.vals) == O.OK
+    ci = s.colind.copy()
+    ci[1], ci[2] = ci[2], ci[1]
+    assert O.validate(s.rowptr, ci, s.vals) == O.INVALID
+    v = s.vals.copy()
+    v[0] = -1.0
+    assert O.validate(s.rowptr, s.colind, v) == O.BAD_DIAGONAL
+    v = s.vals.copy()
+    v[1] = -0.5
+    assert O.validate(s.rowptr, s.colind, v) == O.NOT_SYMMETRIC
+    v = s.vals.copy()
+    v[3] = np.nan
+    assert O.validate(s.rowptr, s.colind, v) == O.INVALID
+
+
+def test_fp32_vcycle_close_to_fp64():
+    s = P.lognormal(12, seed=9)
+    H64 = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60)
+    H32 = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, vcycle_fp32=1)
+    z64 = H64.vcycle(s.b)
+    z32 = H32.vcycle(s.b)
+    assert np.abs(z32 - z64).max() <= 1e-4 * np.abs(z64).max()
+    out = H32.pcg(s.b)
+    assert out["status"] == O.OK and out["true_rel_residual"] <= 1.5e-8
+
+
+def test_fcg_directions_stay_conjugate_with_asymmetric_cycle():
+    """Flexible CG with the Polak-Ribiere beta (Notay 2000, FCG(1)) A-orthogonalises
+    each new direction against the previous one for any preconditioner, so
+    (x_{k+1}-x_k)^T A (x_k-x_{k-1}) = 0; plain PCG loses this with a
+    non-symmetric cycle (one pre-smoothing step, no post-smoothing)."""
+    s = P.lognormal(12, seed=1)
+    A = sp.csr_matrix((s.vals, s.colind, s.rowptr), shape=(s.n, s.n))
+
+    def conj(flexible):
+        H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, flexible=flexible, pre_sweeps=1, post_sweeps=0)
+        out = H.pcg(s.b, keep_iterates=True)
+        assert out["status"] == O.OK
+        D = np.diff(out["iterates"], axis=0)
+        return max(abs(D[k] @ (A @ D[k - 1])) / np.sqrt((D[k] @ (A @ D[k])) * (D[k - 1] @ (A @ D[k - 1])))
+                   for k in range(1, len(D)))
+
+    assert conj(1) <= 1e-8
+    assert conj(0) >= 1e-3
