@@ -1,0 +1,182 @@
+/*
+ * amg.h - C interface of the MI355X (gfx950) aggregation AMG-preconditioned CG.
+ *
+ * The method is the non-smoothed aggregation algebraic multigrid of Blatt,
+ * Ippisch and Bastian ("A Massively Parallel Algebraic Multigrid
+ * Preconditioner based on Aggregation for Elliptic Problems with
+ * Heterogeneous Coefficients"): strength of connection and greedy
+ * aggregation (Sec. 2.1, Alg. 1-3) run decoupled per tile of rows (Sec. 3.3,
+ * Alg. 4), piecewise-constant prolongation and the Galerkin coarse operator
+ * (Sec. 2.1, eq. (prolongation)), and a V-cycle (Sec. 2) used as the
+ * preconditioner of a conjugate-gradient solve of A x = b (Sec. 2, eq. (ls)).
+ *
+ * Conventions for every call:
+ *  - Array pointers are HIP DEVICE pointers unless the comment says "host".
+ *  - `stream` is a hipStream_t passed as void*; NULL selects the null stream.
+ *    All device work of a call is enqueued on that stream.
+ *  - Every call returns a status; on failure nothing leaks, output handles
+ *    are set to NULL, and a message is available from amg_last_error()
+ *    (per thread).  Errors of asynchronous kernels surface at the next
+ *    synchronising call as AMG_ERR_HIP.
+ *  - CSR matrices use int32 row pointers and columns (ascending within each
+ *    row, diagonal stored, no duplicates) and float64 values, and must be
+ *    structurally symmetric.
+ */
+#ifndef AMG_MI355X_AMG_H
+#define AMG_MI355X_AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define AMG_API __attribute__((visibility("default")))
+#else
+#define AMG_API
+#endif
+
+typedef enum amg_status {
+  AMG_OK = 0,
+  AMG_ERR_INVALID_ARG = 1,        /* malformed CSR or argument                        */
+  AMG_ERR_BAD_DIAGONAL = 2,       /* missing diagonal or a_ii <= 0                   */
+  AMG_ERR_NOT_SYMMETRIC = 3,      /* a_ij != a_ji (when check_symmetry is set)       */
+  AMG_ERR_NOT_SPD = 4,            /* coarsest Cholesky pivot <= 0                     */
+  AMG_ERR_COARSENING_STALLED = 5, /* coarsest level larger than 4096 rows             */
+  AMG_ERR_OUT_OF_MEMORY = 6,
+  AMG_ERR_BREAKDOWN = 7,          /* CG: p^T A p <= 0 or r^T z <= 0                   */
+  AMG_ERR_NOT_CONVERGED = 8,      /* maxit reached; x holds the last iterate          */
+  AMG_ERR_HIP = 9,                /* a HIP runtime call failed                        */
+  AMG_ERR_UNSUPPORTED = 10        /* parameter outside what the kernels support       */
+} amg_status;
+
+/* Sparse SPD matrix A (Sec. 2, eq. (ls)), device CSR.  The library copies it
+ * during amg_setup; the caller may free it afterwards. */
+typedef struct amg_csr {
+  int32_t n;              /* rows = columns, > 0                              */
+  int32_t nnz;            /* stored entries = rowptr[n]                       */
+  const int32_t *rowptr;  /* device, n+1                                      */
+  const int32_t *colind;  /* device, nnz, ascending per row                   */
+  const double *vals;     /* device, nnz                                      */
+} amg_csr;
+
+enum { AMG_SMOOTHER_MCSGS = 0, AMG_SMOOTHER_L1_JACOBI = 1 };
+
+/* Parameters.  Defaults from amg_default_params() in brackets. */
+typedef struct amg_params {
+  double strength_threshold; /* delta of eq. (symmetric_strong2)               [0.08] */
+  double isolated_threshold; /* beta: eta_max(i) < beta marks i isolated       [1e-5] */
+  int32_t agg_min;           /* s_min of Alg. 2                                [8]    */
+  int32_t agg_max;           /* s_max of Alg. 3 (at most 32)                   [12]   */
+  int32_t agg_diameter;      /* d_max of Alg. 2 (at least 1)                   [3]    */
+  double omega;              /* over-correction of the coarse correction       [1.6]  */
+  int32_t coarse_max;        /* stop coarsening at <= this many rows           [500]  */
+  int32_t max_levels;        /*                                                [25]   */
+  int32_t tile_rows;         /* rows per decoupled aggregation tile (64..1024) [512]  */
+  int32_t smoother;          /* AMG_SMOOTHER_MCSGS or AMG_SMOOTHER_L1_JACOBI   [MCSGS]*/
+  int32_t pre_sweeps;        /* symmetric GS steps (fwd+bwd) or Jacobi sweeps  [1]    */
+  int32_t post_sweeps;       /*                                                [1]    */
+  int32_t vcycle_fp32;       /* 1: V-cycle in FP32 on levels 0..L-1            [0]    */
+  int32_t flexible;          /* 1: flexible CG (Polak-Ribiere beta); -1: = vcycle_fp32 [-1] */
+  uint32_t colour_seed;      /* seed of the colouring priorities               [0]    */
+  int32_t check_symmetry;    /* 1: reject A with a_ij != a_ji                  [1]    */
+  int32_t keep_setup_data;   /* 1: keep strong/isolated flags for amg_copy_level [0]  */
+} amg_params;
+
+typedef struct amg_solve_info {
+  int32_t iterations;
+  int32_t converged;          /* 1 if ||r||/||r0|| <= rtol                           */
+  int32_t levels;
+  double rel_residual;        /* recursive ||r_k|| / ||r_0||                         */
+  double true_rel_residual;   /* ||b - A x|| / ||b|| in FP64                         */
+  double setup_ms;            /* of the hierarchy used                               */
+  double solve_ms;
+} amg_solve_info;
+
+typedef struct amg_hierarchy amg_hierarchy; /* opaque, library-owned */
+
+/* Fills *p with the defaults listed above. */
+AMG_API amg_status amg_default_params(amg_params *p);
+
+/* Builds the AMG hierarchy of A (Sec. 2.1 and Sec. 3.3): per level, strength
+ * of connection (eqs. (symmetric_strong1), (symmetric_strong2)), greedy
+ * aggregation per tile of `tile_rows` rows (Alg. 1-4), numbering of the coarse
+ * rows, Galerkin product P^T A P (stored unscaled; omega is applied at
+ * prolongation), multicolouring for the smoother, optional FP32 copies; the
+ * coarsest level (<= coarse_max rows) is factorised by a dense FP64 Cholesky.
+ * Validates A first (INVALID_ARG, BAD_DIAGONAL, NOT_SYMMETRIC).  Blocks until
+ * the hierarchy is complete.  *out receives the handle (NULL on failure). */
+AMG_API amg_status amg_setup(const amg_csr *A, const amg_params *p, void *stream, amg_hierarchy **out);
+
+/* One V-cycle z = M r (Sec. 2): pre-smoothing, residual restriction with P^T,
+ * recursion, coarsest solve, prolongation with omega, post-smoothing.
+ * r and z are device vectors of length n (level 0) and must not alias.
+ * Asynchronous: returns after enqueueing. */
+AMG_API amg_status amg_precond_apply(amg_hierarchy *h, const double *r, double *z, void *stream);
+
+/* Preconditioned CG (flexible CG if the hierarchy was built with flexible=1)
+ * for A x = b with x holding x0 on entry and the solution on return.  Stops
+ * when ||r_k||_2 <= rtol ||r_0||_2 (recursive residual) or after maxit
+ * iterations (then AMG_ERR_NOT_CONVERGED with x = last iterate and *info
+ * filled).  Blocks until done.
+ *   info      host, nullable
+ *   res_hist  host, nullable, maxit+1 doubles: ||r_k||/||r_0||
+ *   iter_hist device, nullable, n*(maxit+1) doubles: x_k for k = 0.. */
+AMG_API amg_status pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+                     amg_solve_info *info, double *res_hist, double *iter_hist, void *stream);
+
+/* Releases everything the hierarchy owns.  NULL-safe. */
+AMG_API void amg_free(amg_hierarchy *h);
+
+/* ---- support ---------------------------------------------------------- */
+AMG_API const char *amg_status_string(amg_status s);
+AMG_API const char *amg_last_error(void);
+
+/* Device allocator used for all library memory (default: stream-ordered
+ * hipMallocAsync/hipFreeAsync).  alloc returns NULL on failure.  Passing
+ * NULL for both restores the default.  Not thread-safe with running setups. */
+typedef void *(*amg_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*amg_free_fn)(void *ptr, void *stream, void *ctx);
+AMG_API amg_status amg_set_allocator(amg_alloc_fn alloc, amg_free_fn free_fn, void *ctx);
+
+/* Device bytes held by the hierarchy. */
+AMG_API amg_status amg_hierarchy_bytes(const amg_hierarchy *h, size_t *bytes);
+
+/* Number of levels (level 0 is the input matrix). */
+AMG_API amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels);
+
+/* Shape of level l: rows, stored entries, colours, rows of level l+1 (0 on
+ * the coarsest level). */
+AMG_API amg_status amg_level_info(const amg_hierarchy *h, int32_t l, int32_t *n, int32_t *nnz, int32_t *ncolours,
+                          int32_t *n_next);
+
+/* Copies level l to HOST arrays (each nullable): aggregate id per row (n; not
+ * on the coarsest level), colour per row (n), CSR (n+1, nnz, nnz), and, when
+ * built with keep_setup_data, the strong flag per stored entry (nnz) and the
+ * isolated flag per row (n).  Synchronises the null stream. */
+AMG_API amg_status amg_copy_level(const amg_hierarchy *h, int32_t l, int32_t *agg, int32_t *colour, int32_t *rowptr,
+                          int32_t *colind, double *vals, uint8_t *strong, uint8_t *iso);
+
+/* Per-kernel-class timing with HIP events recorded around each launch on the
+ * launch stream (off by default; adds a small overhead when on).  kind is one
+ * of the AMG_KIND_* values; *ms is the summed duration, *launches the count,
+ * *bytes the summed algorithmic HBM bytes of those launches. */
+enum {
+  AMG_KIND_SPMV_F64 = 0,      /* outer CG product q = A p                        */
+  AMG_KIND_SWEEP = 1,         /* one colour pass of the level-0 smoother         */
+  AMG_KIND_RESTRICT = 2,      /* level-0 residual + restriction                  */
+  AMG_KIND_PROLONG = 3,       /* level-0 prolongation                            */
+  AMG_KIND_CG_VEC = 4,        /* CG vector updates and dot products              */
+  AMG_KIND_COARSE_LEVELS = 5, /* every launch of levels >= 1                     */
+  AMG_KIND_COUNT = 6
+};
+AMG_API amg_status amg_set_kernel_timing(int32_t enable);
+AMG_API amg_status amg_get_kernel_timing(int32_t kind, double *ms, int64_t *launches, double *bytes);
+AMG_API amg_status amg_reset_kernel_timing(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG_MI355X_AMG_H */

@@ -1,0 +1,554 @@
+// C interface of the MI355X aggregation AMG-PCG: hierarchy construction,
+// preconditioner application, (flexible) preconditioned CG, introspection.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "amg_internal.h"
+
+namespace amgx {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+void fail(amg_status st, const std::string& msg) {
+  set_error(msg);
+  throw Failure{st};
+}
+
+// ------------------------------------------------------------------ allocator
+static amg_alloc_fn g_alloc = nullptr;
+static amg_free_fn g_free = nullptr;
+static void* g_ctx = nullptr;
+static std::once_flag g_pool_once;
+
+void* dalloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 16;
+  if (g_alloc) {
+    void* p = g_alloc(bytes, (void*)s, g_ctx);
+    if (!p) fail(AMG_ERR_OUT_OF_MEMORY, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+    return p;
+  }
+  std::call_once(g_pool_once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+      }
+    }
+  });
+  void* p = nullptr;
+  hipError_t e = hipMallocAsync(&p, bytes, s);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? AMG_ERR_OUT_OF_MEMORY : AMG_ERR_HIP,
+         std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  }
+  return p;
+}
+
+void dfree(void* p, hipStream_t s) {
+  if (!p) return;
+  if (g_free) {
+    g_free(p, (void*)s, g_ctx);
+    return;
+  }
+  (void)hipFreeAsync(p, s);
+}
+
+void Hierarchy::release(hipStream_t s) {
+  for (void* p : owned) dfree(p, s);
+  owned.clear();
+  if (host_scal) {
+    (void)hipHostFree(host_scal);
+    host_scal = nullptr;
+  }
+  bytes = 0;
+}
+
+// ------------------------------------------------------------------ timing
+struct TimingRec {
+  int kind;
+  double bytes;
+  hipEvent_t e0, e1;
+};
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimingRec> g_pending;
+static std::vector<hipEvent_t> g_event_pool;
+static double g_ms[AMG_KIND_COUNT];
+static int64_t g_launches[AMG_KIND_COUNT];
+static double g_bytes[AMG_KIND_COUNT];
+
+bool timing_on() { return g_timing; }
+
+static hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  AMG_HIP(hipEventCreate(&e));
+  return e;
+}
+
+KTimer::KTimer(int k, hipStream_t st, double b) : kind(k), s(st), bytes(b) {
+  if (!g_timing || k < 0) return;
+  std::lock_guard<std::mutex> g(g_tmu);
+  e0 = take_event();
+  e1 = take_event();
+  AMG_HIP(hipEventRecord(e0, s));
+}
+
+KTimer::~KTimer() {
+  if (!e0) return;
+  std::lock_guard<std::mutex> g(g_tmu);
+  (void)hipEventRecord(e1, s);
+  g_pending.push_back(TimingRec{kind, bytes, e0, e1});
+}
+
+static void drain_timing() {
+  for (auto& r : g_pending) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(r.e1);
+    (void)hipEventElapsedTime(&ms, r.e0, r.e1);
+    g_ms[r.kind] += ms;
+    g_launches[r.kind] += 1;
+    g_bytes[r.kind] += r.bytes;
+    g_event_pool.push_back(r.e0);
+    g_event_pool.push_back(r.e1);
+  }
+  g_pending.clear();
+}
+
+}  // namespace amgx
+
+using namespace amgx;
+
+struct amg_hierarchy {
+  Hierarchy H;
+};
+
+namespace {
+
+template <typename F>
+amg_status guarded(F&& f) {
+  try {
+    f();
+    return AMG_OK;
+  } catch (const Failure& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return AMG_ERR_OUT_OF_MEMORY;
+  }
+}
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void check_params(const amg_params& p) {
+  if (!(p.strength_threshold > 0.0 && p.strength_threshold < 1.0)) fail(AMG_ERR_INVALID_ARG, "strength_threshold");
+  if (!(p.isolated_threshold >= 0.0)) fail(AMG_ERR_INVALID_ARG, "isolated_threshold");
+  if (p.agg_min < 1 || p.agg_max < p.agg_min) fail(AMG_ERR_INVALID_ARG, "agg_min/agg_max");
+  if (p.agg_max > 32) fail(AMG_ERR_UNSUPPORTED, "agg_max above 32");
+  if (p.agg_diameter < 1) fail(AMG_ERR_INVALID_ARG, "agg_diameter");
+  if (p.tile_rows < 64 || p.tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "tile_rows outside 64..1024");
+  if (p.coarse_max < 1 || p.max_levels < 1) fail(AMG_ERR_INVALID_ARG, "coarse_max/max_levels");
+  if (p.smoother != AMG_SMOOTHER_MCSGS && p.smoother != AMG_SMOOTHER_L1_JACOBI) fail(AMG_ERR_INVALID_ARG, "smoother");
+  if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
+}
+
+void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy& H) {
+  const double t0 = now_ms();
+  if (!A || !pp) fail(AMG_ERR_INVALID_ARG, "NULL argument");
+  H.p = *pp;
+  check_params(H.p);
+  H.flexible = H.p.flexible < 0 ? (H.p.vcycle_fp32 ? 1 : 0) : (H.p.flexible ? 1 : 0);
+  H.setup_stream = s;
+  if (A->n <= 0 || A->nnz < A->n || !A->rowptr || !A->colind || !A->vals)
+    fail(AMG_ERR_INVALID_ARG, "invalid CSR header (n, nnz or NULL arrays)");
+  const int fl = validate_csr(A->n, A->nnz, A->rowptr, A->colind, A->vals, H.p.check_symmetry, s);
+  if (fl & 1) fail(AMG_ERR_INVALID_ARG, "malformed CSR (row pointers, column order/range or non-finite value)");
+  if (fl & 2) fail(AMG_ERR_BAD_DIAGONAL, "missing or non-positive diagonal");
+  if (fl & 4) fail(AMG_ERR_NOT_SYMMETRIC, "matrix is not symmetric");
+
+  H.lev.clear();
+  H.lev.emplace_back();
+  {
+    Level& L0 = H.lev[0];
+    L0.n = A->n;
+    L0.nnz = A->nnz;
+    L0.rowptr = H.alloc<int>((size_t)A->n + 1, s);
+    L0.colind = H.alloc<int>((size_t)A->nnz, s);
+    L0.vals = H.alloc<double>((size_t)A->nnz, s);
+    AMG_HIP(hipMemcpyAsync(L0.rowptr, A->rowptr, ((size_t)A->n + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(L0.colind, A->colind, (size_t)A->nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(L0.vals, A->vals, (size_t)A->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  const amg_params& p = H.p;
+  for (;;) {
+    const int l = (int)H.lev.size() - 1;
+    {
+      Level& L = H.lev[l];
+      L.T = p.tile_rows;
+      L.ntiles = (L.n + L.T - 1) / L.T;
+      if (L.n <= p.coarse_max || l == p.max_levels - 1) break;
+    }
+    uint8_t *strong, *iso;
+    DBuf ts, ti;
+    const int n = H.lev[l].n, nnz = H.lev[l].nnz;
+    if (p.keep_setup_data) {
+      strong = H.alloc<uint8_t>((size_t)nnz, s);
+      iso = H.alloc<uint8_t>((size_t)n, s);
+      H.lev[l].strong = strong;
+      H.lev[l].iso = iso;
+    } else {
+      ts = DBuf((size_t)nnz, s);
+      ti = DBuf((size_t)n, s);
+      strong = ts.as<uint8_t>();
+      iso = ti.as<uint8_t>();
+    }
+    strength(H.lev[l], p.strength_threshold, p.isolated_threshold, strong, iso, s);
+    const int nc = aggregate(H, H.lev[l], strong, iso, p, s);
+    if ((double)nc > 0.9 * (double)n) {
+      H.lev[l].nc = 0;  // stalled: this level becomes the coarsest
+      break;
+    }
+    H.lev.emplace_back();
+    galerkin(H, H.lev[l], H.lev[l + 1], s);
+  }
+  const int Lc = (int)H.lev.size() - 1;
+  H.lev[Lc].nc = 0;
+  const bool f32 = p.vcycle_fp32 != 0;
+  for (int l = 0; l <= Lc; ++l) {
+    Level& L = H.lev[l];
+    colour(H, L, p.colour_seed + (uint32_t)l, s);
+    if (l == Lc) break;
+    if (f32) {
+      L.vals32 = H.alloc<float>((size_t)L.nnz, s);
+      cast_f32(L.vals, L.vals32, (size_t)L.nnz, s);
+    }
+    if (p.smoother == AMG_SMOOTHER_L1_JACOBI) {
+      if (f32) {
+        L.l1_32 = H.alloc<float>((size_t)L.n, s);
+        l1_diag(L, nullptr, L.l1_32, s);
+        L.t32 = H.alloc<float>((size_t)L.n, s);
+      } else {
+        L.l1 = H.alloc<double>((size_t)L.n, s);
+        l1_diag(L, L.l1, nullptr, s);
+        L.t64 = H.alloc<double>((size_t)L.n, s);
+      }
+    }
+    if (l > 0 || f32) {
+      if (f32) {
+        L.x32 = H.alloc<float>((size_t)L.n, s);
+        L.b32 = H.alloc<float>((size_t)L.n, s);
+      } else {
+        L.x64 = H.alloc<double>((size_t)L.n, s);
+        L.b64 = H.alloc<double>((size_t)L.n, s);
+      }
+    }
+  }
+  {
+    Level& C = H.lev[Lc];
+    if (C.n > 4096) fail(AMG_ERR_COARSENING_STALLED, "coarsest level has " + std::to_string(C.n) + " rows");
+    if (Lc > 0) {
+      if (f32) {
+        C.x32 = H.alloc<float>((size_t)C.n, s);
+        C.b32 = H.alloc<float>((size_t)C.n, s);
+      } else {
+        C.x64 = H.alloc<double>((size_t)C.n, s);
+        C.b64 = H.alloc<double>((size_t)C.n, s);
+      }
+    } else if (f32) {
+      C.x32 = H.alloc<float>((size_t)C.n, s);
+      C.b32 = H.alloc<float>((size_t)C.n, s);
+    }
+    coarse_factor(H, C, s);
+  }
+  const int n0 = H.lev[0].n;
+  H.r = H.alloc<double>((size_t)n0, s);
+  H.z = H.alloc<double>((size_t)n0, s);
+  H.pv = H.alloc<double>((size_t)n0, s);
+  H.q = H.alloc<double>((size_t)n0, s);
+  if (H.flexible) H.rold = H.alloc<double>((size_t)n0, s);
+  H.partial = H.alloc<double>(2 * (size_t)RED_BLOCKS, s);
+  H.scal = H.alloc<double>(S_COUNT, s);
+  AMG_HIP(hipHostMalloc((void**)&H.host_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+  AMG_HIP(hipStreamSynchronize(s));
+  H.setup_ms = now_ms() - t0;
+}
+
+void read_scal(Hierarchy& H, hipStream_t s) {
+  AMG_HIP(hipMemcpyAsync(H.host_scal, H.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+amg_status pcg_impl(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
+                    double* res_hist, double* iter_hist, hipStream_t s) {
+  const double t0 = now_ms();
+  Level& L0 = H.lev[0];
+  const int n = L0.n;
+  double* const r = H.r;
+  double* const z = H.z;
+  double* const p = H.pv;
+  double* const q = H.q;
+  double* const rold = H.flexible ? H.rold : nullptr;
+  double* const part = H.partial;
+  double* const scal = H.scal;
+  AMG_HIP(hipMemsetAsync(scal, 0, S_COUNT * sizeof(double), s));
+  residual64(L0, b, x, r, part, s);
+  finish(part, RED_BLOCKS, scal, S_R0, FIN_STORE, s);
+  if (iter_hist) AMG_HIP(hipMemcpyAsync(iter_hist, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  read_scal(H, s);
+  const double r0 = std::sqrt(H.host_scal[S_R0]);
+  if (res_hist) res_hist[0] = 1.0;
+  int it = 0;
+  amg_status st = AMG_ERR_NOT_CONVERGED;
+  double rel = r0 > 0.0 ? 1.0 : 0.0;
+  if (r0 == 0.0) {
+    st = AMG_OK;
+  } else {
+    precond_apply(H, r, z, s);
+    AMG_HIP(hipMemcpyAsync(p, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    dot_partial(n, r, z, part, s);
+    finish(part, RED_BLOCKS, scal, S_RHO, FIN_RHO_INIT, s);
+    for (int k = 1; k <= maxit; ++k) {
+      spmv64(L0, p, q, part, s, AMG_KIND_SPMV_F64);
+      finish(part, RED_BLOCKS, scal, S_PQ, FIN_ALPHA, s);
+      cg_update_xr(n, x, r, rold, p, q, scal, part, s);
+      finish(part, RED_BLOCKS, scal, S_RR, FIN_STORE, s);
+      read_scal(H, s);
+      if (H.host_scal[S_FLAG] != 0.0) {
+        st = AMG_ERR_BREAKDOWN;
+        break;
+      }
+      it = k;
+      rel = std::sqrt(H.host_scal[S_RR]) / r0;
+      if (res_hist) res_hist[k] = rel;
+      if (iter_hist)
+        AMG_HIP(hipMemcpyAsync(iter_hist + (size_t)k * n, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (rel <= rtol) {
+        st = AMG_OK;
+        break;
+      }
+      precond_apply(H, r, z, s);
+      cg_dots_rz(n, r, z, rold, part, s);
+      finish(part, RED_BLOCKS, scal, S_RZ, H.flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
+      cg_update_p(n, p, z, scal, s);
+    }
+  }
+  // true residual ||b - A x|| / ||b||
+  residual64(L0, b, x, q, part, s);
+  finish(part, RED_BLOCKS, scal, S_TMP, FIN_STORE, s);
+  read_scal(H, s);
+  const double rn = std::sqrt(H.host_scal[S_TMP]);
+  dot_partial(n, b, b, part, s);
+  finish(part, RED_BLOCKS, scal, S_TMP, FIN_STORE, s);
+  read_scal(H, s);
+  const double bn = std::sqrt(H.host_scal[S_TMP]);
+  if (info) {
+    info->iterations = it;
+    info->converged = st == AMG_OK ? 1 : 0;
+    info->levels = (int)H.lev.size();
+    info->rel_residual = rel;
+    info->true_rel_residual = bn > 0.0 ? rn / bn : 0.0;
+    info->setup_ms = H.setup_ms;
+    info->solve_ms = now_ms() - t0;
+  }
+  if (st == AMG_ERR_NOT_CONVERGED) set_error("maximum number of iterations reached");
+  if (st == AMG_ERR_BREAKDOWN) set_error("CG breakdown (p^T A p <= 0 or r^T z <= 0)");
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+amg_status amg_default_params(amg_params* p) {
+  if (!p) return AMG_ERR_INVALID_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->strength_threshold = 0.08;
+  p->isolated_threshold = 1e-5;
+  p->agg_min = 8;
+  p->agg_max = 12;
+  p->agg_diameter = 3;
+  p->omega = 1.6;
+  p->coarse_max = 500;
+  p->max_levels = 25;
+  p->tile_rows = 512;
+  p->smoother = AMG_SMOOTHER_MCSGS;
+  p->pre_sweeps = 1;
+  p->post_sweeps = 1;
+  p->vcycle_fp32 = 0;
+  p->flexible = -1;
+  p->colour_seed = 0;
+  p->check_symmetry = 1;
+  p->keep_setup_data = 0;
+  return AMG_OK;
+}
+
+amg_status amg_setup(const amg_csr* A, const amg_params* p, void* stream, amg_hierarchy** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return AMG_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  amg_hierarchy* h = nullptr;
+  try {
+    h = new amg_hierarchy();
+  } catch (...) {
+    set_error("host allocation failed");
+    return AMG_ERR_OUT_OF_MEMORY;
+  }
+  amg_status st = guarded([&] { setup_impl(A, p, S(stream), h->H); });
+  if (st != AMG_OK) {
+    (void)hipStreamSynchronize(S(stream));
+    h->H.release(S(stream));
+    (void)hipStreamSynchronize(S(stream));
+    delete h;
+    return st;
+  }
+  *out = h;
+  return AMG_OK;
+}
+
+amg_status amg_precond_apply(amg_hierarchy* h, const double* r, double* z, void* stream) {
+  if (!h || !r || !z || r == z) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  return guarded([&] { precond_apply(h->H, r, z, S(stream)); });
+}
+
+amg_status pcg_solve(amg_hierarchy* h, const double* b, double* x, double rtol, int32_t maxit, amg_solve_info* info,
+                     double* res_hist, double* iter_hist, void* stream) {
+  if (!h || !b || !x || maxit < 0 || !(rtol >= 0.0)) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  amg_status st = AMG_OK;
+  amg_status g = guarded([&] { st = pcg_impl(h->H, b, x, rtol, maxit, info, res_hist, iter_hist, S(stream)); });
+  return g != AMG_OK ? g : st;
+}
+
+void amg_free(amg_hierarchy* h) {
+  if (!h) return;
+  hipStream_t s = h->H.setup_stream;
+  (void)hipStreamSynchronize(s);
+  h->H.release(s);
+  (void)hipStreamSynchronize(s);
+  delete h;
+}
+
+const char* amg_status_string(amg_status s) {
+  switch (s) {
+    case AMG_OK: return "AMG_OK";
+    case AMG_ERR_INVALID_ARG: return "AMG_ERR_INVALID_ARG";
+    case AMG_ERR_BAD_DIAGONAL: return "AMG_ERR_BAD_DIAGONAL";
+    case AMG_ERR_NOT_SYMMETRIC: return "AMG_ERR_NOT_SYMMETRIC";
+    case AMG_ERR_NOT_SPD: return "AMG_ERR_NOT_SPD";
+    case AMG_ERR_COARSENING_STALLED: return "AMG_ERR_COARSENING_STALLED";
+    case AMG_ERR_OUT_OF_MEMORY: return "AMG_ERR_OUT_OF_MEMORY";
+    case AMG_ERR_BREAKDOWN: return "AMG_ERR_BREAKDOWN";
+    case AMG_ERR_NOT_CONVERGED: return "AMG_ERR_NOT_CONVERGED";
+    case AMG_ERR_HIP: return "AMG_ERR_HIP";
+    case AMG_ERR_UNSUPPORTED: return "AMG_ERR_UNSUPPORTED";
+  }
+  return "unknown status";
+}
+
+const char* amg_last_error(void) { return g_err.c_str(); }
+
+amg_status amg_set_allocator(amg_alloc_fn alloc, amg_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    set_error("allocator and free must both be set or both be NULL");
+    return AMG_ERR_INVALID_ARG;
+  }
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_ctx = ctx;
+  return AMG_OK;
+}
+
+amg_status amg_hierarchy_bytes(const amg_hierarchy* h, size_t* bytes) {
+  if (!h || !bytes) return AMG_ERR_INVALID_ARG;
+  *bytes = h->H.bytes;
+  return AMG_OK;
+}
+
+amg_status amg_num_levels(const amg_hierarchy* h, int32_t* levels) {
+  if (!h || !levels) return AMG_ERR_INVALID_ARG;
+  *levels = (int32_t)h->H.lev.size();
+  return AMG_OK;
+}
+
+amg_status amg_level_info(const amg_hierarchy* h, int32_t l, int32_t* n, int32_t* nnz, int32_t* ncolours,
+                          int32_t* n_next) {
+  if (!h || l < 0 || l >= (int32_t)h->H.lev.size()) {
+    set_error("level out of range");
+    return AMG_ERR_INVALID_ARG;
+  }
+  const Level& L = h->H.lev[l];
+  if (n) *n = L.n;
+  if (nnz) *nnz = L.nnz;
+  if (ncolours) *ncolours = L.ncol;
+  if (n_next) *n_next = L.nc;
+  return AMG_OK;
+}
+
+amg_status amg_copy_level(const amg_hierarchy* h, int32_t l, int32_t* agg, int32_t* colour, int32_t* rowptr,
+                          int32_t* colind, double* vals, uint8_t* strong, uint8_t* iso) {
+  if (!h || l < 0 || l >= (int32_t)h->H.lev.size()) {
+    set_error("level out of range");
+    return AMG_ERR_INVALID_ARG;
+  }
+  const Level& L = h->H.lev[l];
+  return guarded([&] {
+    AMG_HIP(hipDeviceSynchronize());
+    if (agg && L.agg && L.nc > 0) AMG_HIP(hipMemcpy(agg, L.agg, (size_t)L.n * sizeof(int), hipMemcpyDeviceToHost));
+    if (colour) AMG_HIP(hipMemcpy(colour, L.colour, (size_t)L.n * sizeof(int), hipMemcpyDeviceToHost));
+    if (rowptr) AMG_HIP(hipMemcpy(rowptr, L.rowptr, ((size_t)L.n + 1) * sizeof(int), hipMemcpyDeviceToHost));
+    if (colind) AMG_HIP(hipMemcpy(colind, L.colind, (size_t)L.nnz * sizeof(int), hipMemcpyDeviceToHost));
+    if (vals) AMG_HIP(hipMemcpy(vals, L.vals, (size_t)L.nnz * sizeof(double), hipMemcpyDeviceToHost));
+    if (strong && L.strong) AMG_HIP(hipMemcpy(strong, L.strong, (size_t)L.nnz, hipMemcpyDeviceToHost));
+    if (iso && L.iso) AMG_HIP(hipMemcpy(iso, L.iso, (size_t)L.n, hipMemcpyDeviceToHost));
+  });
+}
+
+amg_status amg_set_kernel_timing(int32_t enable) {
+  std::lock_guard<std::mutex> g(g_tmu);
+  g_timing = enable != 0;
+  return AMG_OK;
+}
+
+amg_status amg_get_kernel_timing(int32_t kind, double* ms, int64_t* launches, double* bytes) {
+  if (kind < 0 || kind >= AMG_KIND_COUNT) return AMG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(g_tmu);
+  drain_timing();
+  if (ms) *ms = g_ms[kind];
+  if (launches) *launches = g_launches[kind];
+  if (bytes) *bytes = g_bytes[kind];
+  return AMG_OK;
+}
+
+amg_status amg_reset_kernel_timing(void) {
+  std::lock_guard<std::mutex> g(g_tmu);
+  drain_timing();
+  for (int k = 0; k < AMG_KIND_COUNT; ++k) {
+    g_ms[k] = 0.0;
+    g_launches[k] = 0;
+    g_bytes[k] = 0.0;
+  }
+  return AMG_OK;
+}
+
+}  // extern "C"

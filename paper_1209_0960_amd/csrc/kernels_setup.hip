@@ -1,0 +1,1213 @@
+// Setup kernels of the aggregation AMG hierarchy for gfx950 (wave64).
+//
+// Integer outputs (strong flags, aggregates, colours, coarse sparsity) are
+// deterministic and independent of scheduling; the Galerkin values are ordered
+// sequential sums, so the whole setup is reproducible bit for bit.  Floating
+// point contraction is disabled in this file so that every FP64 operation of
+// the strength test is rounded once.
+#include <algorithm>
+#include <climits>
+
+#include "amg_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace amgx {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    int t = __shfl_up(v, d, WAVE);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+__device__ inline unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= (unsigned)__shfl_xor((int)v, o, WAVE);
+  return v;
+}
+
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ============================================================== scan
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ int block_excl_scan(int v, int* total) {
+  __shared__ int ws[SCAN_THREADS / WAVE];
+  const int lane = __lane_id(), w = threadIdx.x / WAVE;
+  int inc = wave_incl_scan(v);
+  if (lane == WAVE - 1) ws[w] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_THREADS / WAVE; ++i) {
+    int s = ws[i];
+    off += (i < w) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(const int* __restrict__ in, int n, int* __restrict__ bsum) {
+  const long long base = (long long)blockIdx.x * SCAN_TILE;
+  int s = 0;
+#pragma unroll
+  for (int r = 0; r < SCAN_ITEMS; ++r) {
+    long long i = base + (long long)r * SCAN_THREADS + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  int tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of nb block sums in place, single workgroup; bsum[nb] = total.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int* bsum, int nb) {
+  int carry = 0;
+  for (int base = 0; base < nb; base += SCAN_THREADS) {
+    int i = base + threadIdx.x;
+    int v = i < nb ? bsum[i] : 0;
+    int tot;
+    int ex = block_excl_scan(v, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(const int* __restrict__ in, int n,
+                                                             const int* __restrict__ bsum, int nb,
+                                                             int* __restrict__ out) {
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int r = 0; r < SCAN_ITEMS; ++r) {
+    long long i = base + r;
+    v[r] = i < n ? in[i] : 0;
+    s += v[r];
+  }
+  int tot;
+  int ex = block_excl_scan(s, &tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < SCAN_ITEMS; ++r) {
+    long long i = base + r;
+    if (i < n) out[i] = ex;
+    ex += v[r];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = bsum[nb];
+}
+
+// ============================================================== validation
+__global__ void k_validate_struct(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+                                  const double* __restrict__ v, int* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int f = 0;
+  const int b = rp[i], e = rp[i + 1];
+  if (i == 0 && b != 0) f |= 1;
+  if (i == n - 1 && e != nnz) f |= 1;
+  if (b < 0 || e < b || e > nnz) {
+    atomicOr(flags, 1);
+    return;
+  }
+  bool has_diag = false;
+  double d = 0.0;
+  for (int k = b; k < e; ++k) {
+    const int j = ci[k];
+    const double a = v[k];
+    if (j < 0 || j >= n) f |= 1;
+    if (k > b && ci[k - 1] >= j) f |= 1;
+    if (!__builtin_isfinite(a)) f |= 1;
+    if (j == i) {
+      has_diag = true;
+      d = a;
+    }
+  }
+  if (!has_diag || !(d > 0.0)) f |= 2;
+  if (f) atomicOr(flags, f);
+}
+
+__device__ inline int find_in_row(const int* __restrict__ rp, const int* __restrict__ ci, int row, int col) {
+  int lo = rp[row], hi = rp[row + 1] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int c = ci[mid];
+    if (c == col) return mid;
+    if (c < col)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+__global__ void k_validate_sym(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ v, int check, int* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    if (j == i) continue;
+    const int q = find_in_row(rp, ci, j, i);
+    if (q < 0 || (check && v[q] != v[k])) {
+      atomicOr(flags, 4);
+      return;
+    }
+  }
+}
+
+// ============================================================== strength
+// Sec. 2.1, eqs. (symmetric_strong1)/(symmetric_strong2) on in-tile edges:
+// w_E(i,j) = max(-a_ij, 0), w_V(i) = a_ii, s_ij = w_E(i,j) w_E(j,i) / (a_ii a_jj).
+__device__ inline double s_edge(const int* __restrict__ rp, const int* __restrict__ ci,
+                                const double* __restrict__ v, const double* __restrict__ d, int i, int j,
+                                double aij) {
+  const int q = find_in_row(rp, ci, j, i);
+  const double aji = q >= 0 ? v[q] : 0.0;
+  const double wij = (-aij > 0.0) ? -aij : 0.0;
+  const double wji = (-aji > 0.0) ? -aji : 0.0;
+  const double num = wij * wji;
+  const double den = d[i] * d[j];
+  return num / den;
+}
+
+__global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                       double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] == i) a = v[k];
+  d[i] = a;
+}
+
+__global__ void k_eta(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
+                      const double* __restrict__ v, const double* __restrict__ d, double* __restrict__ eta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int lo = (i / T) * T, hi = min(lo + T, n);
+  double e = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    if (j == i || j < lo || j >= hi) continue;
+    const double s = s_edge(rp, ci, v, d, i, j, v[k]);
+    if (s > e) e = s;
+  }
+  eta[i] = e;
+}
+
+__global__ void k_strong(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
+                         const double* __restrict__ v, const double* __restrict__ d, const double* __restrict__ eta,
+                         double delta, double beta, uint8_t* __restrict__ strong, uint8_t* __restrict__ iso) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int lo = (i / T) * T, hi = min(lo + T, n);
+  const double ei = eta[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    uint8_t f = 0;
+    if (j != i && j >= lo && j < hi) {
+      const double ej = eta[j];
+      const double m = ei < ej ? ei : ej;
+      const double s = s_edge(rp, ci, v, d, i, j, v[k]);
+      f = (s > delta * m) ? 1 : 0;
+    }
+    strong[k] = f;
+  }
+  iso[i] = (ei < beta) ? 1 : 0;
+}
+
+// ============================================================== aggregation
+// One wavefront per tile of T rows runs the greedy aggregation of Sec. 2.1
+// (Alg. 1 with Alg. 2 and Alg. 3, singleton merge, isolated phase) on the tile
+// subgraph (Alg. 4).  The tile graph lives in LDS as a local CSR of 16-bit
+// neighbour indices with the strong flag in bit 15.  Each selection step
+// evaluates all front candidates in parallel (one per lane) and picks the
+// winner with a butterfly reduction over a strict total order.
+constexpr unsigned F_ISO = 1, F_FRONT = 2;
+constexpr int AGG_MAX_T = 1024;
+constexpr int AGG_MAX_SLOTS = 32;
+
+struct AggLayout {
+  size_t lptr, key1, key2, adjf, madj, nbk, agg, nna, front, adjl, mem, slot, flag, ladj, total;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline AggLayout agg_layout(int T, int E) {
+  AggLayout L;
+  size_t o = 0;
+  L.lptr = o; o = align16(o + 4 * (size_t)(T + 1));
+  L.key1 = o; o = align16(o + 4 * (size_t)T);
+  L.key2 = o; o = align16(o + 4 * (size_t)T);
+  L.adjf = o; o = align16(o + 4 * (size_t)T);
+  L.madj = o; o = align16(o + 4 * (size_t)AGG_MAX_SLOTS);
+  L.nbk = o; o = align16(o + 2 * (size_t)T);
+  L.agg = o; o = align16(o + 2 * (size_t)T);
+  L.nna = o; o = align16(o + 2 * (size_t)T);
+  L.front = o; o = align16(o + 2 * (size_t)T);
+  L.adjl = o; o = align16(o + 2 * (size_t)T);
+  L.mem = o; o = align16(o + 2 * (size_t)AGG_MAX_SLOTS);
+  L.slot = o; o = align16(o + (size_t)T);
+  L.flag = o; o = align16(o + (size_t)T);
+  L.ladj = o; o = align16(o + 2 * (size_t)(E > 0 ? E : 1));
+  L.total = o;
+  return L;
+}
+
+struct AggSh {
+  int* lptr;
+  int* key1;
+  int* key2;
+  int* adjflag;
+  unsigned* madj;
+  short* nbk;
+  short* agg;
+  short* nna;
+  short* front;
+  short* adjl;
+  short* mem;
+  signed char* slot;
+  unsigned char* flag;
+  unsigned short* ladj;
+};
+
+// Per-aggregate state, uniform across the wave.
+struct AggState {
+  int asize;   // members of the current aggregate
+  int fcount;  // entries appended to the front list (N(a) n candidates)
+  int acount;  // entries appended to the adjacent-aggregate list
+};
+
+// Adds vertex c to the aggregate `id`: marks it, updates the unaggregated
+// neighbour counts, the member adjacency masks, the candidate front and the
+// set of adjacent aggregates.  Phase 1 fronts hold non-isolated vertices and
+// track every adjacent aggregate; the isolated phase fronts hold isolated
+// vertices and track only aggregates of phase 1 (ids < P1).
+__device__ void add_member(const AggSh& S, AggState& st, int c, int id, bool iso_phase, int P1) {
+  const int lane = __lane_id();
+  const int s = st.asize;
+  if (lane == 0) {
+    S.agg[c] = (short)id;
+    S.slot[c] = (signed char)s;
+    S.mem[s] = (short)c;
+    S.flag[c] &= (unsigned char)~F_FRONT;
+  }
+  __syncthreads();
+  const int b = S.lptr[c], e = S.lptr[c + 1];
+  unsigned bits = 0;
+  for (int base = b; base < e; base += WAVE) {
+    const int k = base + lane;
+    int j = 0, aj = 0;
+    bool appF = false, appA = false;
+    if (k < e) {
+      j = S.ladj[k] & 0x7FFF;
+      if (!iso_phase) S.nna[j] = (short)(S.nna[j] - 1);
+      aj = S.agg[j];
+      const unsigned char fj = S.flag[j];
+      if (aj == id) {
+        const int sj = S.slot[j];
+        bits |= 1u << sj;
+        S.madj[sj] |= 1u << s;
+      } else if (aj < 0) {
+        const bool elig = iso_phase ? (fj & F_ISO) != 0 : (fj & F_ISO) == 0;
+        if (elig && !(fj & F_FRONT)) {
+          S.flag[j] = (unsigned char)(fj | F_FRONT);
+          appF = true;
+        }
+      } else {
+        const bool track = iso_phase ? (aj < P1) : true;
+        if (track && atomicExch(&S.adjflag[aj], 1) == 0) appA = true;
+      }
+    }
+    const uint64_t mF = __ballot(appF);
+    if (appF) S.front[st.fcount + __popcll(mF & lanemask_lt())] = (short)j;
+    st.fcount += __popcll(mF);
+    const uint64_t mA = __ballot(appA);
+    if (appA) S.adjl[st.acount + __popcll(mA & lanemask_lt())] = (short)aj;
+    st.acount += __popcll(mA);
+  }
+  bits = wave_or(bits);
+  if (lane == 0) S.madj[s] = bits;
+  st.asize = s + 1;
+  __syncthreads();
+}
+
+__device__ void clear_aggregate(const AggSh& S, AggState& st) {
+  const int lane = __lane_id();
+  for (int p = lane; p < st.fcount; p += WAVE) S.flag[S.front[p]] &= (unsigned char)~F_FRONT;
+  for (int p = lane; p < st.acount; p += WAVE) S.adjflag[S.adjl[p]] = 0;
+  if (lane < st.asize) {
+    S.slot[S.mem[lane]] = -1;
+    S.madj[lane] = 0;
+  }
+  st.asize = st.fcount = st.acount = 0;
+  __syncthreads();
+}
+
+// Eccentricity test of a candidate within a+{c}: every member reachable in at
+// most dmax hops (paths through members only; c is the source).  Because every
+// earlier addition passed the same test, this equals diam(a+{c}) <= dmax.
+__device__ inline bool ecc_ok(const AggSh& S, unsigned mm, int asize, int dmax) {
+  const unsigned full = asize >= 32 ? 0xFFFFFFFFu : ((1u << asize) - 1u);
+  unsigned reach = mm, fr = mm;
+  for (int d = 1; d < dmax && reach != full; ++d) {
+    unsigned nx = 0, f = fr;
+    while (f) {
+      const int u = __builtin_ctz(f);
+      f &= f - 1;
+      nx |= S.madj[u];
+    }
+    fr = nx & ~reach;
+    reach |= nx;
+  }
+  return reach == full;
+}
+
+struct Cand {
+  int c2, c1, conn, nb, in_a, in_U;
+  unsigned mm;
+};
+
+// cons2/cons1 (two-/one-way strong links into a), connect(c,a), neighbors(c,a),
+// |N(c) n a|, |N(c) n U| and the member mask of candidate c.
+__device__ inline Cand evaluate(const AggSh& S, int c, int id) {
+  Cand r{0, 0, 0, 0, 0, 0, 0u};
+  const int b = S.lptr[c], e = S.lptr[c + 1];
+  for (int k = b; k < e; ++k) {
+    const unsigned w = S.ladj[k];
+    const int j = w & 0x7FFF;
+    const int stg = (int)(w >> 15);
+    const int aj = S.agg[j];
+    if (aj == id) {
+      r.mm |= 1u << S.slot[j];
+      int rev = 0;
+      const int jb = S.lptr[j], je = S.lptr[j + 1];
+      for (int q = jb; q < je; ++q) {
+        const unsigned wq = S.ladj[q];
+        if ((int)(wq & 0x7FFF) == c) {
+          rev = (int)(wq >> 15);
+          break;
+        }
+      }
+      r.c2 += stg & rev;
+      r.c1 += stg ^ rev;
+    } else {
+      if (stg) r.conn += (aj >= 0 && S.adjflag[aj]) ? 2 : 1;
+      const unsigned char fj = S.flag[j];
+      if (aj < 0 && !(fj & F_ISO)) {
+        ++r.in_U;
+        if (!(fj & F_FRONT)) ++r.nb;
+      }
+    }
+  }
+  r.in_a = __popc(r.mm);
+  return r;
+}
+
+// Strict total order of grow candidates with equal cons: larger
+// connect/|N| (exact cross multiplication), then larger neighbors, then
+// smaller index.  c < 0 marks "no candidate".
+__device__ inline bool better(int ca, int conna, int dega, int nba, int cb, int connb, int degb, int nbb) {
+  if (ca < 0) return false;
+  if (cb < 0) return true;
+  const long long l = (long long)conna * degb, r = (long long)connb * dega;
+  if (l != r) return l > r;
+  if (nba != nbb) return nba > nbb;
+  return ca < cb;
+}
+
+__global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const uint8_t* __restrict__ strong,
+                                                    const uint8_t* __restrict__ isov, int smin, int smax, int dmax,
+                                                    int Ecap, int* __restrict__ agg_local, int* __restrict__ tile_cnt,
+                                                    int* __restrict__ members, int* __restrict__ mstart) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const AggLayout Lo = agg_layout(T, Ecap);
+  AggSh S;
+  S.lptr = (int*)(sm + Lo.lptr);
+  S.key1 = (int*)(sm + Lo.key1);
+  S.key2 = (int*)(sm + Lo.key2);
+  S.adjflag = (int*)(sm + Lo.adjf);
+  S.madj = (unsigned*)(sm + Lo.madj);
+  S.nbk = (short*)(sm + Lo.nbk);
+  S.agg = (short*)(sm + Lo.agg);
+  S.nna = (short*)(sm + Lo.nna);
+  S.front = (short*)(sm + Lo.front);
+  S.adjl = (short*)(sm + Lo.adjl);
+  S.mem = (short*)(sm + Lo.mem);
+  S.slot = (signed char*)(sm + Lo.slot);
+  S.flag = (unsigned char*)(sm + Lo.flag);
+  S.ladj = (unsigned short*)(sm + Lo.ladj);
+
+  const int lane = __lane_id();
+  const int t = blockIdx.x;
+  const int lo = t * T;
+  const int nt = min(T, n - lo);
+
+  // ---- tile graph: local CSR of the in-tile off-diagonal entries
+  int carry = 0;
+  for (int base = 0; base < nt; base += WAVE) {
+    const int v = base + lane;
+    int cnt = 0;
+    if (v < nt) {
+      const int i = lo + v;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = ci[k];
+        cnt += (j != i && j >= lo && j < lo + nt) ? 1 : 0;
+      }
+    }
+    const int inc = wave_incl_scan(cnt);
+    if (v < nt) S.lptr[v] = carry + inc - cnt;
+    carry += __shfl(inc, WAVE - 1, WAVE);
+  }
+  if (lane == 0) S.lptr[nt] = carry;
+  __syncthreads();
+  int nonIso = 0;
+  for (int v = lane; v < nt; v += WAVE) {
+    const int i = lo + v;
+    int pos = S.lptr[v];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = ci[k];
+      if (j != i && j >= lo && j < lo + nt) S.ladj[pos++] = (unsigned short)((j - lo) | (strong[k] ? 0x8000 : 0));
+    }
+    const bool is = isov[i] != 0;
+    S.flag[v] = is ? F_ISO : 0;
+    S.agg[v] = -1;
+    S.nna[v] = (short)(pos - S.lptr[v]);
+    S.slot[v] = -1;
+    S.adjflag[v] = 0;
+    nonIso += is ? 0 : 1;
+  }
+  if (lane < AGG_MAX_SLOTS) S.madj[lane] = 0;
+  int nU = wave_sum(nonIso);
+  __syncthreads();
+
+  AggState st{0, 0, 0};
+  int id = 0;
+
+  // ---- phase 1: non-isolated vertices (Alg. 1)
+  int seed = INT_MAX;
+  if (nU > 0) {
+    int key = INT_MAX;
+    for (int v = lane; v < nt; v += WAVE)
+      if (!(S.flag[v] & F_ISO)) key = min(key, ((int)S.nna[v] << 16) | v);
+    seed = wave_min(key) & 0xFFFF;
+  }
+  while (nU > 0) {
+    add_member(S, st, seed, id, false, 0);
+    --nU;
+    // Grow (Alg. 2)
+    while (st.asize < smin) {
+      int lm2 = 0, lm1 = 0;
+      for (int base = 0; base < st.fcount; base += WAVE) {
+        const int p = base + lane;
+        if (p < st.fcount) {
+          const int c = S.front[p];
+          int k1 = -1;
+          if (S.agg[c] < 0) {
+            const Cand r = evaluate(S, c, id);
+            const int ok = ecc_ok(S, r.mm, st.asize, dmax) ? 1 : 0;
+            k1 = r.c2 | (r.c1 << 8) | (ok << 16);
+            S.key2[p] = r.conn | ((S.lptr[c + 1] - S.lptr[c]) << 16);
+            S.nbk[p] = (short)r.nb;
+            if (ok) {
+              lm2 = max(lm2, r.c2);
+              lm1 = max(lm1, r.c1);
+            }
+          }
+          S.key1[p] = k1;
+        }
+      }
+      const int m2 = wave_max(lm2), m1 = wave_max(lm1);
+      if (m2 == 0 && m1 == 0) break;
+      __syncthreads();
+      int bc = -1, bconn = 0, bdeg = 1, bnb = 0;
+      for (int base = 0; base < st.fcount; base += WAVE) {
+        const int p = base + lane;
+        if (p < st.fcount) {
+          const int k1 = S.key1[p];
+          if (k1 >= 0 && (k1 >> 16)) {
+            const int prim = m2 > 0 ? (k1 & 0xFF) : ((k1 >> 8) & 0xFF);
+            const int tgt = m2 > 0 ? m2 : m1;
+            if (prim == tgt) {
+              const int c = S.front[p];
+              const int k2 = S.key2[p];
+              const int conn = k2 & 0xFFFF, deg = k2 >> 16, nb = S.nbk[p];
+              if (better(c, conn, deg, nb, bc, bconn, bdeg, bnb)) {
+                bc = c;
+                bconn = conn;
+                bdeg = deg;
+                bnb = nb;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const int oc = __shfl_xor(bc, o, WAVE), oconn = __shfl_xor(bconn, o, WAVE);
+        const int odeg = __shfl_xor(bdeg, o, WAVE), onb = __shfl_xor(bnb, o, WAVE);
+        if (better(oc, oconn, odeg, onb, bc, bconn, bdeg, bnb)) {
+          bc = oc;
+          bconn = oconn;
+          bdeg = odeg;
+          bnb = onb;
+        }
+      }
+      __syncthreads();
+      if (bc < 0) break;
+      add_member(S, st, bc, id, false, 0);
+      --nU;
+    }
+    // Round (Alg. 3)
+    while (st.asize < smax) {
+      int best = INT_MAX;
+      for (int base = 0; base < st.fcount; base += WAVE) {
+        const int p = base + lane;
+        if (p < st.fcount) {
+          const int c = S.front[p];
+          if (S.agg[c] < 0) {
+            const Cand r = evaluate(S, c, id);
+            if ((r.c2 > 0 || r.c1 > 0) && r.in_a > r.in_U) best = min(best, c);
+          }
+        }
+      }
+      best = wave_min(best);
+      if (best == INT_MAX) break;
+      add_member(S, st, best, id, false, 0);
+      --nU;
+    }
+    // One-vertex aggregate: join the aggregate holding most strong neighbours.
+    bool merged = false;
+    if (st.asize == 1) {
+      const int v = S.mem[0];
+      const int b = S.lptr[v], e = S.lptr[v + 1];
+      int bk = INT_MAX, bcnt = 0;
+      for (int base = b; base < e; base += WAVE) {
+        const int k = base + lane;
+        if (k < e) {
+          const unsigned w = S.ladj[k];
+          const int aj = S.agg[w & 0x7FFF];
+          if ((w >> 15) && aj >= 0 && aj != id) {
+            int cnt = 0;
+            for (int q = b; q < e; ++q) {
+              const unsigned wq = S.ladj[q];
+              cnt += ((wq >> 15) && S.agg[wq & 0x7FFF] == aj) ? 1 : 0;
+            }
+            if (cnt > bcnt || (cnt == bcnt && aj < bk)) {
+              bcnt = cnt;
+              bk = aj;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const int ok = __shfl_xor(bk, o, WAVE), oc = __shfl_xor(bcnt, o, WAVE);
+        if (oc > bcnt || (oc == bcnt && ok < bk)) {
+          bcnt = oc;
+          bk = ok;
+        }
+      }
+      if (bcnt > 0) {
+        if (lane == 0) S.agg[v] = (short)bk;
+        merged = true;
+      }
+      __syncthreads();
+    }
+    if (!merged) ++id;
+    // Next seed: fewest unaggregated neighbours on the front, else over U.
+    if (nU > 0) {
+      int key = INT_MAX;
+      for (int p = lane; p < st.fcount; p += WAVE) {
+        const int c = S.front[p];
+        if (S.agg[c] < 0) key = min(key, ((int)S.nna[c] << 16) | c);
+      }
+      key = wave_min(key);
+      if (key == INT_MAX) {
+        for (int v = lane; v < nt; v += WAVE)
+          if (S.agg[v] < 0 && !(S.flag[v] & F_ISO)) key = min(key, ((int)S.nna[v] << 16) | v);
+        key = wave_min(key);
+      }
+      seed = key & 0xFFFF;
+    }
+    clear_aggregate(S, st);
+  }
+
+  // ---- phase 2: isolated vertices (GrowIsoAggregate reading)
+  const int P1 = id;
+  for (int base = 0; base < nt; base += WAVE) {
+    for (;;) {
+      const int v = base + lane;
+      const bool cand = v < nt && (S.flag[v] & F_ISO) && S.agg[v] < 0;
+      const uint64_t m = __ballot(cand);
+      if (!m) break;
+      const int s0 = base + (int)__builtin_ctzll(m);
+      const int myid = id++;
+      add_member(S, st, s0, myid, true, P1);
+      while (st.asize < smin) {
+        int best = INT_MAX;
+        for (int b2 = 0; b2 < st.fcount; b2 += WAVE) {
+          const int p = b2 + lane;
+          if (p < st.fcount) {
+            const int c = S.front[p];
+            if (S.agg[c] < 0) {
+              bool common = false;
+              unsigned mm = 0;
+              for (int k = S.lptr[c]; k < S.lptr[c + 1]; ++k) {
+                const int j = S.ladj[k] & 0x7FFF;
+                const int aj = S.agg[j];
+                if (aj == myid)
+                  mm |= 1u << S.slot[j];
+                else if (aj >= 0 && aj < P1 && S.adjflag[aj])
+                  common = true;
+              }
+              if (common && ecc_ok(S, mm, st.asize, dmax)) best = min(best, c);
+            }
+          }
+        }
+        best = wave_min(best);
+        if (best == INT_MAX) break;
+        add_member(S, st, best, myid, true, P1);
+      }
+      clear_aggregate(S, st);
+    }
+  }
+
+  // ---- outputs: local ids, count, member lists grouped by aggregate
+  __syncthreads();
+  for (int v = lane; v < nt; v += WAVE) agg_local[lo + v] = S.agg[v];
+  const int na = id;
+  if (lane == 0) tile_cnt[t] = na;
+  for (int k = lane; k < na; k += WAVE) S.key1[k] = 0;
+  __syncthreads();
+  for (int v = lane; v < nt; v += WAVE) atomicAdd(&S.key1[S.agg[v]], 1);
+  __syncthreads();
+  carry = 0;
+  for (int base = 0; base < na; base += WAVE) {
+    const int k = base + lane;
+    const int c = k < na ? S.key1[k] : 0;
+    const int inc = wave_incl_scan(c);
+    if (k < na) S.key2[k] = carry + inc - c;
+    carry += __shfl(inc, WAVE - 1, WAVE);
+  }
+  __syncthreads();
+  for (int k = lane; k < na; k += WAVE) {
+    int pos = S.key2[k];
+    mstart[lo + k] = pos;
+    for (int v = 0; v < nt; ++v)
+      if (S.agg[v] == k) members[lo + pos++] = lo + v;
+  }
+}
+
+__global__ void k_tile_nnz_max(int n, int T, int ntiles, const int* __restrict__ rp, int* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int lo = t * T, hi = min(lo + T, n);
+  atomicMax(out, rp[hi] - rp[lo]);
+}
+
+__global__ void k_agg_finalize(int n, int T, const int* __restrict__ agg_local, const int* __restrict__ tile_off,
+                               const int* __restrict__ tile_cnt, const int* __restrict__ mstart,
+                               int* __restrict__ agg, int* __restrict__ mptr, int nc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = i / T;
+  const int off = tile_off[t];
+  agg[i] = off + agg_local[i];
+  const int k = i - t * T;
+  if (k < tile_cnt[t]) mptr[off + k] = t * T + mstart[i];
+  if (i == 0) mptr[nc] = n;
+}
+
+// ============================================================== Galerkin
+// A_c(I,J) = sum over members i of a_I (ascending) and stored (i,j) in CSR
+// order with agg[j] = J of a_ij, summed sequentially from the first term.
+// One wavefront per coarse row: the row's terms are gathered in that order,
+// ranked by (J, position) (a stable counting sort), and equal-J runs summed.
+constexpr int GAL_CAP = 512;
+constexpr int GAL_WAVES = 4;
+
+__global__ void k_term_count(int nc, const int* __restrict__ mptr, const int* __restrict__ members,
+                             const int* __restrict__ rp, int* __restrict__ tcount, int* maxm) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int s = 0;
+  for (int p = mptr[I]; p < mptr[I + 1]; ++p) {
+    const int i = members[p];
+    s += rp[i + 1] - rp[i];
+  }
+  tcount[I] = s;
+  atomicMax(maxm, s);
+}
+
+template <typename IdxT>
+__device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr, const int* __restrict__ members,
+                             const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ va,
+                             const int* __restrict__ agg, int* J, double* V, IdxT* Sx, int* __restrict__ tcol,
+                             double* __restrict__ tval, int* __restrict__ ucount) {
+  const int lane = __lane_id();
+  int pos = 0;
+  for (int p = mptr[I]; p < mptr[I + 1]; ++p) {
+    const int i = members[p];
+    const int b = rp[i], e = rp[i + 1];
+    for (int k = b + lane; k < e; k += WAVE) {
+      J[pos + k - b] = agg[ci[k]];
+      V[pos + k - b] = va[k];
+    }
+    pos += e - b;
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < m; t += WAVE) {
+    const int Jt = J[t];
+    int r = 0;
+    for (int u = 0; u < m; ++u) {
+      const int Ju = J[u];
+      r += (Ju < Jt || (Ju == Jt && u < t)) ? 1 : 0;
+    }
+    Sx[r] = (IdxT)t;
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  int cnt = 0;
+  for (int base = 0; base < m; base += WAVE) {
+    const int r = base + lane;
+    bool head = false;
+    int Jr = 0;
+    if (r < m) {
+      Jr = J[Sx[r]];
+      head = (r == 0) || (J[Sx[r - 1]] != Jr);
+    }
+    const uint64_t hm = __ballot(head);
+    if (head) {
+      const int o = cnt + __popcll(hm & lanemask_lt());
+      double acc = V[Sx[r]];
+      for (int q = r + 1; q < m && J[Sx[q]] == Jr; ++q) acc = acc + V[Sx[q]];
+      tcol[tb + o] = Jr;
+      tval[tb + o] = acc;
+    }
+    cnt += __popcll(hm);
+  }
+  if (lane == 0) ucount[I] = cnt;
+}
+
+__global__ __launch_bounds__(GAL_WAVES* WAVE) void k_galerkin_rows(
+    int nc, const int* __restrict__ mptr, const int* __restrict__ members, const int* __restrict__ rp,
+    const int* __restrict__ ci, const double* __restrict__ va, const int* __restrict__ agg,
+    const int* __restrict__ toff, int* gJ, double* gV, int* gS, int* __restrict__ tcol, double* __restrict__ tval,
+    int* __restrict__ ucount) {
+  __shared__ int sJ[GAL_WAVES][GAL_CAP];
+  __shared__ double sV[GAL_WAVES][GAL_CAP];
+  __shared__ short sS[GAL_WAVES][GAL_CAP];
+  const int w = threadIdx.x / WAVE;
+  const int I = blockIdx.x * GAL_WAVES + w;
+  if (I >= nc) return;
+  const int tb = toff[I];
+  const int m = toff[I + 1] - tb;
+  if (m <= GAL_CAP)
+    galerkin_row<short>(I, m, tb, mptr, members, rp, ci, va, agg, sJ[w], sV[w], sS[w], tcol, tval, ucount);
+  else
+    galerkin_row<int>(I, m, tb, mptr, members, rp, ci, va, agg, gJ + tb, gV + tb, gS + tb, tcol, tval, ucount);
+}
+
+__global__ void k_compact(int nc, const int* __restrict__ toff, const int* __restrict__ crp,
+                          const int* __restrict__ tcol, const double* __restrict__ tval, int* __restrict__ ccol,
+                          double* __restrict__ cval) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int src = toff[I], dst = crp[I], cnt = crp[I + 1] - dst;
+  for (int q = 0; q < cnt; ++q) {
+    ccol[dst + q] = tcol[src + q];
+    cval[dst + q] = tval[src + q];
+  }
+}
+
+// ============================================================== colouring
+// Jones-Plassmann rounds: a row takes the smallest colour unused by its
+// neighbours of higher key once all of them are coloured.  key(i) =
+// (fmix32(i ^ seed), i), fmix32 being the MurmurHash3 32-bit finaliser.
+__device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+__device__ inline uint64_t ckey(int i, uint32_t s) {
+  return ((uint64_t)fmix32((uint32_t)i ^ s) << 32) | (uint32_t)i;
+}
+
+__global__ void k_fill(int n, int* p, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_colour_round(int n, const int* __restrict__ rp, const int* __restrict__ ci, uint32_t seed,
+                               int* colour, int* remaining, int* maxcol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || colour[i] >= 0) return;
+  const uint64_t ki = ckey(i, seed);
+  uint64_t mask = 0;
+  bool big = false;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    if (j == i || ckey(j, seed) < ki) continue;
+    const int cj = colour[j];
+    if (cj < 0) {
+      atomicAdd(remaining, 1);
+      return;
+    }
+    if (cj < 64)
+      mask |= 1ull << cj;
+    else
+      big = true;
+  }
+  int c;
+  if (!big && mask != ~0ull) {
+    c = (int)__builtin_ctzll(~mask);
+  } else {
+    c = 0;
+    for (;;) {
+      bool used = false;
+      for (int k = rp[i]; k < rp[i + 1] && !used; ++k) {
+        const int j = ci[k];
+        if (j != i && ckey(j, seed) > ki && colour[j] == c) used = true;
+      }
+      if (!used) break;
+      ++c;
+    }
+  }
+  colour[i] = c;
+  atomicMax(maxcol, c);
+}
+
+constexpr int CL_THREADS = 256;
+
+__global__ __launch_bounds__(CL_THREADS) void k_colour_hist(int n, const int* __restrict__ colour, int C,
+                                                            int nblk, int* __restrict__ bcnt) {
+  extern __shared__ int h[];
+  for (int c = threadIdx.x; c < C; c += CL_THREADS) h[c] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * CL_THREADS + threadIdx.x;
+  if (i < n) atomicAdd(&h[colour[i]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += CL_THREADS) bcnt[(size_t)c * nblk + blockIdx.x] = h[c];
+}
+
+__global__ __launch_bounds__(CL_THREADS) void k_colour_place(int n, const int* __restrict__ colour, int C, int nblk,
+                                                             const int* __restrict__ gofs, int* __restrict__ crows) {
+  extern __shared__ int wc[];  // [CL_THREADS/WAVE][C]
+  const int nw = CL_THREADS / WAVE;
+  for (int q = threadIdx.x; q < nw * C; q += CL_THREADS) wc[q] = 0;
+  __syncthreads();
+  const int lane = __lane_id(), w = threadIdx.x / WAVE;
+  const int i = blockIdx.x * CL_THREADS + threadIdx.x;
+  const bool valid = i < n;
+  const int c = valid ? colour[i] : -1;
+  uint64_t active = __ballot(valid);
+  int rank = 0;
+  while (active) {
+    const int leader = (int)__builtin_ctzll(active);
+    const int cl = __shfl(c, leader, WAVE);
+    const uint64_t m = __ballot(valid && c == cl);
+    if (valid && c == cl) rank = __popcll(m & lanemask_lt());
+    if (lane == 0) wc[w * C + cl] = __popcll(m);
+    active &= ~m;
+  }
+  __syncthreads();
+  if (!valid) return;
+  int off = 0;
+  for (int q = 0; q < w; ++q) off += wc[q * C + c];
+  crows[gofs[(size_t)c * nblk + blockIdx.x] + off + rank] = i;
+}
+
+__global__ void k_gather_cptr(int C, int nblk, const int* __restrict__ gofs, int n, int* __restrict__ cptr) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < C) cptr[c] = gofs[(size_t)c * nblk];
+  if (c == C) cptr[C] = n;
+}
+
+// ============================================================== casts etc.
+__global__ void k_cast(size_t n, const double* __restrict__ in, float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+__global__ void k_l1(int n, const int* __restrict__ rp, const double* __restrict__ v, double* __restrict__ o64,
+                     float* __restrict__ o32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) s = s + fabs(v[k]);
+  if (o64) o64[i] = s;
+  if (o32) o32[i] = (float)s;
+}
+
+// ============================================================== coarsest level
+__global__ void k_densify(int nL, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ D) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nL) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) D[(size_t)i * nL + ci[k]] = v[k];
+}
+
+// Right-looking dense Cholesky on the lower triangle, one workgroup.
+__global__ __launch_bounds__(1024) void k_cholesky(int n, double* D, int* fail) {
+  __shared__ double piv;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = D[(size_t)k * n + k];
+      if (!(d > 0.0)) {
+        *fail = 1;
+        piv = 1.0;
+      } else {
+        piv = sqrt(d);
+      }
+      D[(size_t)k * n + k] = piv;
+    }
+    __syncthreads();
+    const double p = piv;
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) D[(size_t)i * n + k] = D[(size_t)i * n + k] / p;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
+      if (j <= i) D[(size_t)i * n + j] = D[(size_t)i * n + j] - D[(size_t)i * n + k] * D[(size_t)j * n + k];
+    }
+    __syncthreads();
+  }
+}
+
+// W = L^{-1} column by column (lower triangular).
+__global__ void k_trinv(int n, const double* __restrict__ L, double* __restrict__ W) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int i = j; i < n; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int k = j; k < i; ++k) s = s - L[(size_t)i * n + k] * W[(size_t)k * n + j];
+    W[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+  }
+}
+
+// A^{-1} = W^T W, summed in ascending k from max(i,j): exactly symmetric.
+__global__ void k_wtw(int n, const double* __restrict__ W, double* __restrict__ Ainv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = max(i, j); k < n; ++k) s = s + W[(size_t)k * n + i] * W[(size_t)k * n + j];
+  Ainv[(size_t)j * n + i] = s;
+}
+
+template <typename T>
+T read1(const T* dptr, hipStream_t s) {
+  T v;
+  AMG_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+}  // namespace
+
+// ================================================================== host side
+void exclusive_scan(const int* in, int* out, int n, hipStream_t s) {
+  const int nb = std::max(1, cdiv(n, SCAN_TILE));
+  DBuf bs((size_t)(nb + 1) * sizeof(int), s);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, bs.as<int>());
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, bs.as<int>(), nb);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, bs.as<int>(), nb, out);
+  AMG_HIP(hipGetLastError());
+}
+
+int validate_csr(int n, int nnz, const int* rp, const int* ci, const double* v, int check_symmetry, hipStream_t s) {
+  DBuf f(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_validate_struct, dim3(cdiv(n, 256)), dim3(256), 0, s, n, nnz, rp, ci, v, f.as<int>());
+  AMG_HIP(hipGetLastError());
+  int flags = read1(f.as<int>(), s);
+  if (flags) return flags;
+  hipLaunchKernelGGL(k_validate_sym, dim3(cdiv(n, 256)), dim3(256), 0, s, n, rp, ci, v, check_symmetry, f.as<int>());
+  AMG_HIP(hipGetLastError());
+  return read1(f.as<int>(), s);
+}
+
+void strength(const Level& L, double delta, double beta, uint8_t* strong, uint8_t* iso, hipStream_t s) {
+  DBuf d((size_t)L.n * sizeof(double), s), eta((size_t)L.n * sizeof(double), s);
+  const int g = cdiv(L.n, 256);
+  hipLaunchKernelGGL(k_diag, dim3(g), dim3(256), 0, s, L.n, L.rowptr, L.colind, L.vals, d.as<double>());
+  hipLaunchKernelGGL(k_eta, dim3(g), dim3(256), 0, s, L.n, L.T, L.rowptr, L.colind, L.vals, d.as<double>(),
+                     eta.as<double>());
+  hipLaunchKernelGGL(k_strong, dim3(g), dim3(256), 0, s, L.n, L.T, L.rowptr, L.colind, L.vals, d.as<double>(),
+                     eta.as<double>(), delta, beta, strong, iso);
+  AMG_HIP(hipGetLastError());
+}
+
+int aggregate(Hierarchy& H, Level& L, const uint8_t* strong, const uint8_t* iso, const amg_params& p, hipStream_t s) {
+  const int n = L.n, T = L.T;
+  const int ntiles = cdiv(n, T);
+  L.ntiles = ntiles;
+  DBuf mx(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_tile_nnz_max, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, n, T, ntiles, L.rowptr, mx.as<int>());
+  AMG_HIP(hipGetLastError());
+  const int Ecap = read1(mx.as<int>(), s);
+  const AggLayout lay = agg_layout(T, Ecap);
+  if (lay.total > 160 * 1024)
+    fail(AMG_ERR_UNSUPPORTED, "aggregation tile graph exceeds LDS (" + std::to_string(lay.total) +
+                                  " bytes); use smaller tile_rows");
+  AMG_HIP(hipFuncSetAttribute((const void*)k_aggregate, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total));
+  DBuf agg_local((size_t)n * sizeof(int), s), tile_cnt((size_t)ntiles * sizeof(int), s),
+      mstart((size_t)n * sizeof(int), s);
+  int* members = H.alloc<int>((size_t)n, s);
+  hipLaunchKernelGGL(k_aggregate, dim3(ntiles), dim3(WAVE), lay.total, s, n, T, L.rowptr, L.colind, strong, iso,
+                     p.agg_min, p.agg_max, p.agg_diameter, Ecap, agg_local.as<int>(), tile_cnt.as<int>(), members,
+                     mstart.as<int>());
+  AMG_HIP(hipGetLastError());
+  int* tile_off = H.alloc<int>((size_t)ntiles + 1, s);
+  exclusive_scan(tile_cnt.as<int>(), tile_off, ntiles, s);
+  const int nc = read1(tile_off + ntiles, s);
+  int* agg = H.alloc<int>((size_t)n, s);
+  int* mptr = H.alloc<int>((size_t)nc + 1, s);
+  hipLaunchKernelGGL(k_agg_finalize, dim3(cdiv(n, 256)), dim3(256), 0, s, n, T, agg_local.as<int>(), tile_off,
+                     tile_cnt.as<int>(), mstart.as<int>(), agg, mptr, nc);
+  AMG_HIP(hipGetLastError());
+  L.members = members;
+  L.tile_off = tile_off;
+  L.agg = agg;
+  L.mptr = mptr;
+  L.nc = nc;
+  return nc;
+}
+
+void galerkin(Hierarchy& H, const Level& L, Level& C, hipStream_t s) {
+  const int nc = L.nc;
+  DBuf tcount((size_t)nc * sizeof(int), s), mx(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_term_count, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, L.mptr, L.members, L.rowptr,
+                     tcount.as<int>(), mx.as<int>());
+  DBuf toff((size_t)(nc + 1) * sizeof(int), s);
+  exclusive_scan(tcount.as<int>(), toff.as<int>(), nc, s);
+  const int maxm = read1(mx.as<int>(), s);
+  const int total = read1(toff.as<int>() + nc, s);
+  if (total != L.nnz) fail(AMG_ERR_HIP, "Galerkin term count mismatch");
+  DBuf tcol((size_t)total * sizeof(int), s), tval((size_t)total * sizeof(double), s),
+      ucount((size_t)nc * sizeof(int), s);
+  DBuf gJ, gV, gS;
+  if (maxm > GAL_CAP) {
+    gJ = DBuf((size_t)total * sizeof(int), s);
+    gV = DBuf((size_t)total * sizeof(double), s);
+    gS = DBuf((size_t)total * sizeof(int), s);
+  }
+  hipLaunchKernelGGL(k_galerkin_rows, dim3(cdiv(nc, GAL_WAVES)), dim3(GAL_WAVES * WAVE), 0, s, nc, L.mptr,
+                     L.members, L.rowptr, L.colind, L.vals, L.agg, toff.as<int>(), gJ.as<int>(), gV.as<double>(),
+                     gS.as<int>(), tcol.as<int>(), tval.as<double>(), ucount.as<int>());
+  AMG_HIP(hipGetLastError());
+  C.n = nc;
+  C.rowptr = H.alloc<int>((size_t)nc + 1, s);
+  exclusive_scan(ucount.as<int>(), C.rowptr, nc, s);
+  C.nnz = read1(C.rowptr + nc, s);
+  C.colind = H.alloc<int>((size_t)C.nnz, s);
+  C.vals = H.alloc<double>((size_t)C.nnz, s);
+  hipLaunchKernelGGL(k_compact, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, toff.as<int>(), C.rowptr, tcol.as<int>(),
+                     tval.as<double>(), C.colind, C.vals);
+  AMG_HIP(hipGetLastError());
+}
+
+void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
+  const int n = L.n;
+  L.colour = H.alloc<int>((size_t)n, s);
+  DBuf cnt(2 * sizeof(int), s);
+  const int g = cdiv(n, 256);
+  hipLaunchKernelGGL(k_fill, dim3(g), dim3(256), 0, s, n, L.colour, -1);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(int), s));
+  int rounds = 0;
+  for (;;) {
+    AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_colour_round, dim3(g), dim3(256), 0, s, n, L.rowptr, L.colind, seed, L.colour,
+                       cnt.as<int>(), cnt.as<int>() + 1);
+    AMG_HIP(hipGetLastError());
+    ++rounds;
+    if (read1(cnt.as<int>(), s) == 0) break;
+    if (rounds > 100000) fail(AMG_ERR_HIP, "colouring did not terminate");
+  }
+  const int C = read1(cnt.as<int>() + 1, s) + 1;
+  if (C > 4096) fail(AMG_ERR_UNSUPPORTED, "more than 4096 colours");
+  L.ncol = C;
+  const int nblk = cdiv(n, CL_THREADS);
+  DBuf bcnt((size_t)C * nblk * sizeof(int), s), gofs(((size_t)C * nblk + 1) * sizeof(int), s);
+  hipLaunchKernelGGL(k_colour_hist, dim3(nblk), dim3(CL_THREADS), C * sizeof(int), s, n, L.colour, C, nblk,
+                     bcnt.as<int>());
+  exclusive_scan(bcnt.as<int>(), gofs.as<int>(), C * nblk, s);
+  L.crows = H.alloc<int>((size_t)n, s);
+  hipLaunchKernelGGL(k_colour_place, dim3(nblk), dim3(CL_THREADS), (CL_THREADS / WAVE) * C * sizeof(int), s, n,
+                     L.colour, C, nblk, gofs.as<int>(), L.crows);
+  DBuf cp((size_t)(C + 1) * sizeof(int), s);
+  hipLaunchKernelGGL(k_gather_cptr, dim3(cdiv(C + 1, 256)), dim3(256), 0, s, C, nblk, gofs.as<int>(), n, cp.as<int>());
+  AMG_HIP(hipGetLastError());
+  L.cptr.assign(C + 1, 0);
+  AMG_HIP(hipMemcpyAsync(L.cptr.data(), cp.p, (C + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+void cast_f32(const double* in, float* out, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_cast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in, out);
+  AMG_HIP(hipGetLastError());
+}
+
+void l1_diag(const Level& L, double* o64, float* o32, hipStream_t s) {
+  hipLaunchKernelGGL(k_l1, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, L.rowptr, L.vals, o64, o32);
+  AMG_HIP(hipGetLastError());
+}
+
+void coarse_factor(Hierarchy& H, const Level& L, hipStream_t s) {
+  const int n = L.n;
+  H.nL = n;
+  const size_t nn = (size_t)n * n;
+  DBuf D(nn * sizeof(double), s), W(nn * sizeof(double), s), f(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(D.p, 0, nn * sizeof(double), s));
+  AMG_HIP(hipMemsetAsync(W.p, 0, nn * sizeof(double), s));
+  AMG_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_densify, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.rowptr, L.colind, L.vals, D.as<double>());
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, n, D.as<double>(), f.as<int>());
+  AMG_HIP(hipGetLastError());
+  if (read1(f.as<int>(), s)) fail(AMG_ERR_NOT_SPD, "coarsest-level Cholesky pivot <= 0");
+  hipLaunchKernelGGL(k_trinv, dim3(cdiv(n, 64)), dim3(64), 0, s, n, D.as<double>(), W.as<double>());
+  H.Ainv = H.alloc<double>(nn, s);
+  hipLaunchKernelGGL(k_wtw, dim3(cdiv(n, 64), n), dim3(64), 0, s, n, W.as<double>(), H.Ainv);
+  AMG_HIP(hipGetLastError());
+}
+
+}  // namespace amgx
