@@ -160,9 +160,11 @@ AMG_API amg_status amg_copy_level(const amg_hierarchy *h, int32_t l, int32_t *ag
                           int32_t *colind, double *vals, uint8_t *strong, uint8_t *iso);
 
 /* Per-kernel-class timing with HIP events recorded around each launch on the
- * launch stream (off by default; adds a small overhead when on).  kind is one
- * of the AMG_KIND_* values; *ms is the summed duration, *launches the count,
- * *bytes the summed algorithmic HBM bytes of those launches. */
+ * launch stream (off by default; adds a small overhead when on).
+ * amg_set_kernel_timing takes a bit mask of kinds (bit k enables kind k; 0
+ * disables).  kind is one of the AMG_KIND_* values; *ms is the summed
+ * duration, *launches the count, *bytes the summed algorithmic HBM bytes of
+ * those launches. */
 enum {
   AMG_KIND_SPMV_F64 = 0,      /* outer CG product q = A p                        */
   AMG_KIND_SWEEP = 1,         /* one colour pass of the level-0 smoother         */
@@ -172,7 +174,7 @@ enum {
   AMG_KIND_COARSE_LEVELS = 5, /* every launch of levels >= 1                     */
   AMG_KIND_COUNT = 6
 };
-AMG_API amg_status amg_set_kernel_timing(int32_t enable);
+AMG_API amg_status amg_set_kernel_timing(int32_t kind_mask);
 AMG_API amg_status amg_get_kernel_timing(int32_t kind, double *ms, int64_t *launches, double *bytes);
 AMG_API amg_status amg_reset_kernel_timing(void);
 

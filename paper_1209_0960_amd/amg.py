@@ -187,8 +187,17 @@ def set_allocator(alloc, free, ctx=None):
                                    C.cast(free, C.c_void_p) if free else None, ctx))
 
 
-def set_kernel_timing(enable: bool):
-    _check(lib().amg_set_kernel_timing(1 if enable else 0))
+def set_kernel_timing(kinds=True):
+    """kinds: True (all), False (none) or an iterable of KIND_* values."""
+    if kinds is True:
+        mask = -1
+    elif kinds is False or kinds is None:
+        mask = 0
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << k
+    _check(lib().amg_set_kernel_timing(mask))
 
 
 def reset_kernel_timing():
@@ -211,7 +220,10 @@ class Hierarchy:
 
     def close(self):
         if getattr(self, "h", None):
-            amg_free(self.h)
+            try:
+                amg_free(self.h)
+            except TypeError:  # interpreter shutdown: module globals already cleared
+                pass
             self.h = None
 
     def __del__(self):

@@ -76,14 +76,14 @@ struct TimingRec {
   hipEvent_t e0, e1;
 };
 static std::mutex g_tmu;
-static bool g_timing = false;
+static int g_timing = 0;  // bit mask of enabled kinds
 static std::vector<TimingRec> g_pending;
 static std::vector<hipEvent_t> g_event_pool;
 static double g_ms[AMG_KIND_COUNT];
 static int64_t g_launches[AMG_KIND_COUNT];
 static double g_bytes[AMG_KIND_COUNT];
 
-bool timing_on() { return g_timing; }
+bool timing_on() { return g_timing != 0; }
 
 static hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -97,7 +97,7 @@ static hipEvent_t take_event() {
 }
 
 KTimer::KTimer(int k, hipStream_t st, double b) : kind(k), s(st), bytes(b) {
-  if (!g_timing || k < 0) return;
+  if (k < 0 || !(g_timing & (1 << k))) return;
   std::lock_guard<std::mutex> g(g_tmu);
   e0 = take_event();
   e1 = take_event();
@@ -524,9 +524,9 @@ amg_status amg_copy_level(const amg_hierarchy* h, int32_t l, int32_t* agg, int32
   });
 }
 
-amg_status amg_set_kernel_timing(int32_t enable) {
+amg_status amg_set_kernel_timing(int32_t kind_mask) {
   std::lock_guard<std::mutex> g(g_tmu);
-  g_timing = enable != 0;
+  g_timing = kind_mask;
   return AMG_OK;
 }
 
