@@ -178,7 +178,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_gs_colour<float> (level-0 multicolour Gauss-Seidel pass)",
+            "kernel": "k_gs_sell<float> (one level-0 colour pass of the Gauss-Seidel smoother, SELL-64)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

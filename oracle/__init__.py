@@ -67,7 +67,7 @@ def lib():
         L.orc_galerkin.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, I32P, C.c_int, I32P, C.c_void_p,
                                    C.c_void_p]
         L.orc_colour.restype = C.c_int
-        L.orc_colour.argtypes = [C.c_int, C.c_int, I32P, I32P, C.c_uint32, I32P]
+        L.orc_colour.argtypes = [C.c_int, C.c_int, I32P, I32P, C.c_int, C.c_uint32, I32P]
         L.orc_fmix32.restype = C.c_uint32
         L.orc_fmix32.argtypes = [C.c_uint32]
         L.orc_cholesky.restype = C.c_int
@@ -156,11 +156,12 @@ def galerkin(rowptr, colind, vals, agg, nc):
     return cptr, ccol, cval
 
 
-def colour(rowptr, colind, seed=0):
+def colour(rowptr, colind, seed=0, tile_rows=512):
+    """Tile-ordered greedy colouring: colour per row and number of colours."""
     rp, ci, _ = _csr(rowptr, colind)
     n = rp.shape[0] - 1
     c = np.zeros(n, np.int32)
-    k = lib().orc_colour(n, ci.shape[0], rp, ci, seed & 0xFFFFFFFF, c)
+    k = lib().orc_colour(n, ci.shape[0], rp, ci, tile_rows, seed & 0xFFFFFFFF, c)
     return c, k
 
 

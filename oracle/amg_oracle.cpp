@@ -493,10 +493,13 @@ Csr galerkin(const Csr& A, const std::vector<int>& agg, int nc) {
 
 // ---------------------------------------------------------------------------
 // Multicolouring (not in the paper: the hot path replaces the hybrid smoother
-// by multicolour symmetric Gauss-Seidel).  key(i) = (fmix32(i xor s), i) with
-// fmix32 the 32-bit finaliser of MurmurHash3 (public domain) and s the colour
-// seed plus the level.  colour(i) = smallest c >= 0 that no stored off-diagonal
-// neighbour j with key(j) > key(i) has.  Rows are coloured in descending key.
+// by multicolour symmetric Gauss-Seidel).  Greedy first-fit colouring in a
+// fixed vertex order: the tiles (the same row ranges as the aggregation) are
+// taken in descending key (fmix32(t xor s), t), with fmix32 the 32-bit
+// finaliser of MurmurHash3 (public domain) and s the colour seed plus the
+// level; inside a tile the rows are taken in ascending order.  Each row gets
+// the smallest colour c >= 0 that none of its already coloured neighbours
+// (stored off-diagonals, any tile) has.
 uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;
   h *= 0x85ebca6bu;
@@ -506,29 +509,30 @@ uint32_t fmix32(uint32_t h) {
   return h;
 }
 
-uint64_t colour_key(int i, uint32_t s) {
-  return ((uint64_t)fmix32((uint32_t)i ^ s) << 32) | (uint32_t)i;
+uint64_t tile_key(int t, uint32_t s) {
+  return ((uint64_t)fmix32((uint32_t)t ^ s) << 32) | (uint32_t)t;
 }
 
-int colour_rows(const Csr& A, uint32_t s, std::vector<int>& colour) {
+int colour_rows(const Csr& A, int T, uint32_t s, std::vector<int>& colour) {
   const int n = A.n;
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::sort(order.begin(), order.end(),
-            [&](int a, int b) { return colour_key(a, s) > colour_key(b, s); });
+  const int ntiles = (n + T - 1) / T;
+  std::vector<int> tiles(ntiles);
+  for (int t = 0; t < ntiles; ++t) tiles[t] = t;
+  std::sort(tiles.begin(), tiles.end(), [&](int a, int b) { return tile_key(a, s) > tile_key(b, s); });
   colour.assign(n, -1);
   int ncol = 0;
-  for (int i : order) {
-    std::set<int> used;
-    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      int j = A.col[k];
-      if (j != i && colour_key(j, s) > colour_key(i, s)) used.insert(colour[j]);
+  for (int t : tiles)
+    for (int i = tile_lo(t, T); i < tile_hi(t, T, n); ++i) {
+      std::set<int> used;
+      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        int j = A.col[k];
+        if (j != i && colour[j] >= 0) used.insert(colour[j]);
+      }
+      int c = 0;
+      while (used.count(c)) ++c;
+      colour[i] = c;
+      ncol = std::max(ncol, c + 1);
     }
-    int c = 0;
-    while (used.count(c)) ++c;
-    colour[i] = c;
-    ncol = std::max(ncol, c + 1);
-  }
   return ncol;
 }
 
@@ -733,7 +737,7 @@ int validate(const Csr& A, int check_symmetry) {
 }
 
 void finish_level(Level& L, const Params& p, int l) {
-  L.ncol = colour_rows(L.A, p.colour_seed + (uint32_t)l, L.colour);
+  L.ncol = colour_rows(L.A, p.tile_rows, p.colour_seed + (uint32_t)l, L.colour);
   L.rows_of_colour.assign(L.ncol, {});
   for (int i = 0; i < L.A.n; ++i) L.rows_of_colour[L.colour[i]].push_back(i);
   L.val32.resize(L.A.nnz());
@@ -884,13 +888,13 @@ int orc_galerkin(int n, int nnz, const int* ptr, const int* col, const double* v
   return C.nnz();
 }
 
-int orc_colour(int n, int nnz, const int* ptr, const int* col, uint32_t seed, int* colour) {
+int orc_colour(int n, int nnz, const int* ptr, const int* col, int tile_rows, uint32_t seed, int* colour) {
   Csr A;
   A.n = n;
   A.ptr.assign(ptr, ptr + n + 1);
   A.col.assign(col, col + nnz);
   std::vector<int> c;
-  int k = colour_rows(A, seed, c);
+  int k = colour_rows(A, tile_rows, seed, c);
   std::memcpy(colour, c.data(), sizeof(int) * n);
   return k;
 }

@@ -2,6 +2,7 @@
 // preconditioner application, (flexible) preconditioned CG, introspection.
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -59,8 +60,20 @@ void dfree(void* p, hipStream_t s) {
   (void)hipFreeAsync(p, s);
 }
 
+void Hierarchy::free_one(void* ptr, hipStream_t s) {
+  if (!ptr) return;
+  for (size_t k = 0; k < owned.size(); ++k)
+    if (owned[k].first == ptr) {
+      bytes -= owned[k].second;
+      owned[k] = owned.back();
+      owned.pop_back();
+      dfree(ptr, s);
+      return;
+    }
+}
+
 void Hierarchy::release(hipStream_t s) {
-  for (void* p : owned) dfree(p, s);
+  for (auto& o : owned) dfree(o.first, s);
   owned.clear();
   if (host_scal) {
     (void)hipHostFree(host_scal);
@@ -228,25 +241,43 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   const int Lc = (int)H.lev.size() - 1;
   H.lev[Lc].nc = 0;
   const bool f32 = p.vcycle_fp32 != 0;
+  for (int l = 0; l <= Lc; ++l) colour(H, H.lev[l], p.colour_seed + (uint32_t)l, s);
+  // Relabel every level above the coarsest into colour order (the coarsest
+  // keeps its natural order for the dense solve).
+  for (int l = Lc - 1; l >= 0; --l) permute_level(H, l, l + 1 < Lc ? H.lev[l + 1].perm : nullptr, s);
   for (int l = 0; l <= Lc; ++l) {
     Level& L = H.lev[l];
-    colour(H, L, p.colour_seed + (uint32_t)l, s);
-    if (l == Lc) break;
-    if (f32) {
-      L.vals32 = H.alloc<float>((size_t)L.nnz, s);
-      cast_f32(L.vals, L.vals32, (size_t)L.nnz, s);
-    }
+    const double mean = (double)L.nnz / L.n;
+    L.sub = 4;
+    while (L.sub < 64 && L.sub < mean) L.sub *= 2;
+  }
+  for (int l = 0; l < Lc; ++l) {
+    Level& L = H.lev[l];
     if (p.smoother == AMG_SMOOTHER_L1_JACOBI) {
       if (f32) {
         L.l1_32 = H.alloc<float>((size_t)L.n, s);
         l1_diag(L, nullptr, L.l1_32, s);
-        L.t32 = H.alloc<float>((size_t)L.n, s);
       } else {
         L.l1 = H.alloc<double>((size_t)L.n, s);
         l1_diag(L, L.l1, nullptr, s);
-        L.t64 = H.alloc<double>((size_t)L.n, s);
       }
     }
+    build_sell(H, l, s);
+    if (f32) {
+      const size_t ent = (size_t)L.soff_h[L.nsl];
+      L.sval32 = H.alloc<float>(ent, s);
+      cast_f32(L.sval, L.sval32, ent, s);
+      L.dg32 = H.alloc<float>((size_t)L.n, s);
+      cast_f32(L.dg, L.dg32, (size_t)L.n, s);
+      if (l > 0) {  // level 0 keeps FP64 values for the outer CG product
+        H.free_one(L.sval, s);
+        L.sval = nullptr;
+      }
+    }
+    if (f32)
+      L.t32 = H.alloc<float>((size_t)L.n, s);
+    else
+      L.t64 = H.alloc<double>((size_t)L.n, s);
     if (l > 0 || f32) {
       if (f32) {
         L.x32 = H.alloc<float>((size_t)L.n, s);
@@ -260,7 +291,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   {
     Level& C = H.lev[Lc];
     if (C.n > 4096) fail(AMG_ERR_COARSENING_STALLED, "coarsest level has " + std::to_string(C.n) + " rows");
-    if (Lc > 0) {
+    if (Lc > 0 || f32) {
       if (f32) {
         C.x32 = H.alloc<float>((size_t)C.n, s);
         C.b32 = H.alloc<float>((size_t)C.n, s);
@@ -268,9 +299,6 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
         C.x64 = H.alloc<double>((size_t)C.n, s);
         C.b64 = H.alloc<double>((size_t)C.n, s);
       }
-    } else if (f32) {
-      C.x32 = H.alloc<float>((size_t)C.n, s);
-      C.b32 = H.alloc<float>((size_t)C.n, s);
     }
     coarse_factor(H, C, s);
   }
@@ -279,6 +307,8 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   H.z = H.alloc<double>((size_t)n0, s);
   H.pv = H.alloc<double>((size_t)n0, s);
   H.q = H.alloc<double>((size_t)n0, s);
+  H.bp = H.alloc<double>((size_t)n0, s);
+  H.xp = H.alloc<double>((size_t)n0, s);
   if (H.flexible) H.rold = H.alloc<double>((size_t)n0, s);
   H.partial = H.alloc<double>(2 * (size_t)RED_BLOCKS, s);
   H.scal = H.alloc<double>(S_COUNT, s);
@@ -292,11 +322,17 @@ void read_scal(Hierarchy& H, hipStream_t s) {
   AMG_HIP(hipStreamSynchronize(s));
 }
 
-amg_status pcg_impl(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
-                    double* res_hist, double* iter_hist, hipStream_t s) {
+amg_status pcg_impl(Hierarchy& H, const double* b_user, double* x_user, double rtol, int maxit,
+                    amg_solve_info* info, double* res_hist, double* iter_hist, hipStream_t s) {
   const double t0 = now_ms();
   Level& L0 = H.lev[0];
   const int n = L0.n;
+  // The iteration runs in the level-0 solve order.
+  const int* perm0 = L0.perm;
+  double* const b = H.bp;
+  double* const x = H.xp;
+  gather(n, perm0, b_user, b, s);
+  gather(n, perm0, x_user, x, s);
   double* const r = H.r;
   double* const z = H.z;
   double* const p = H.pv;
@@ -307,7 +343,7 @@ amg_status pcg_impl(Hierarchy& H, const double* b, double* x, double rtol, int m
   AMG_HIP(hipMemsetAsync(scal, 0, S_COUNT * sizeof(double), s));
   residual64(L0, b, x, r, part, s);
   finish(part, RED_BLOCKS, scal, S_R0, FIN_STORE, s);
-  if (iter_hist) AMG_HIP(hipMemcpyAsync(iter_hist, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (iter_hist) scatter(n, perm0, x, iter_hist, s);
   read_scal(H, s);
   const double r0 = std::sqrt(H.host_scal[S_R0]);
   if (res_hist) res_hist[0] = 1.0;
@@ -334,8 +370,7 @@ amg_status pcg_impl(Hierarchy& H, const double* b, double* x, double rtol, int m
       it = k;
       rel = std::sqrt(H.host_scal[S_RR]) / r0;
       if (res_hist) res_hist[k] = rel;
-      if (iter_hist)
-        AMG_HIP(hipMemcpyAsync(iter_hist + (size_t)k * n, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (iter_hist) scatter(n, perm0, x, iter_hist + (size_t)k * n, s);
       if (rel <= rtol) {
         st = AMG_OK;
         break;
@@ -346,6 +381,7 @@ amg_status pcg_impl(Hierarchy& H, const double* b, double* x, double rtol, int m
       cg_update_p(n, p, z, scal, s);
     }
   }
+  scatter(n, perm0, x, x_user, s);
   // true residual ||b - A x|| / ||b||
   residual64(L0, b, x, q, part, s);
   finish(part, RED_BLOCKS, scal, S_TMP, FIN_STORE, s);
@@ -426,7 +462,13 @@ amg_status amg_precond_apply(amg_hierarchy* h, const double* r, double* z, void*
     set_error("invalid argument");
     return AMG_ERR_INVALID_ARG;
   }
-  return guarded([&] { precond_apply(h->H, r, z, S(stream)); });
+  return guarded([&] {
+    Hierarchy& H = h->H;
+    const int n = H.lev[0].n;
+    gather(n, H.lev[0].perm, r, H.bp, S(stream));
+    precond_apply(H, H.bp, H.xp, S(stream));
+    scatter(n, H.lev[0].perm, H.xp, z, S(stream));
+  });
 }
 
 amg_status pcg_solve(amg_hierarchy* h, const double* b, double* x, double rtol, int32_t maxit, amg_solve_info* info,
@@ -511,16 +553,75 @@ amg_status amg_copy_level(const amg_hierarchy* h, int32_t l, int32_t* agg, int32
     set_error("level out of range");
     return AMG_ERR_INVALID_ARG;
   }
-  const Level& L = h->H.lev[l];
+  const Hierarchy& H = h->H;
+  const Level& L = H.lev[l];
   return guarded([&] {
     AMG_HIP(hipDeviceSynchronize());
-    if (agg && L.agg && L.nc > 0) AMG_HIP(hipMemcpy(agg, L.agg, (size_t)L.n * sizeof(int), hipMemcpyDeviceToHost));
-    if (colour) AMG_HIP(hipMemcpy(colour, L.colour, (size_t)L.n * sizeof(int), hipMemcpyDeviceToHost));
-    if (rowptr) AMG_HIP(hipMemcpy(rowptr, L.rowptr, ((size_t)L.n + 1) * sizeof(int), hipMemcpyDeviceToHost));
-    if (colind) AMG_HIP(hipMemcpy(colind, L.colind, (size_t)L.nnz * sizeof(int), hipMemcpyDeviceToHost));
-    if (vals) AMG_HIP(hipMemcpy(vals, L.vals, (size_t)L.nnz * sizeof(double), hipMemcpyDeviceToHost));
-    if (strong && L.strong) AMG_HIP(hipMemcpy(strong, L.strong, (size_t)L.nnz, hipMemcpyDeviceToHost));
-    if (iso && L.iso) AMG_HIP(hipMemcpy(iso, L.iso, (size_t)L.n, hipMemcpyDeviceToHost));
+    const int n = L.n, nnz = L.nnz;
+    if (strong && L.strong) AMG_HIP(hipMemcpy(strong, L.strong, (size_t)nnz, hipMemcpyDeviceToHost));
+    if (iso && L.iso) AMG_HIP(hipMemcpy(iso, L.iso, (size_t)n, hipMemcpyDeviceToHost));
+    if (!L.perm) {  // natural order (the coarsest level, or a one-level hierarchy)
+      if (agg && L.agg && L.nc > 0) AMG_HIP(hipMemcpy(agg, L.agg, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+      if (colour) AMG_HIP(hipMemcpy(colour, L.colour, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+      if (rowptr) AMG_HIP(hipMemcpy(rowptr, L.rowptr, ((size_t)n + 1) * sizeof(int), hipMemcpyDeviceToHost));
+      if (colind) AMG_HIP(hipMemcpy(colind, L.colind, (size_t)nnz * sizeof(int), hipMemcpyDeviceToHost));
+      if (vals) AMG_HIP(hipMemcpy(vals, L.vals, (size_t)nnz * sizeof(double), hipMemcpyDeviceToHost));
+      return;
+    }
+    // Solve order (SELL-64 + diagonal) -> natural-order CSR on the host.
+    std::vector<int> perm(n), pinv(n), srp(n + 1), scol(L.soff_h[L.nsl]);
+    std::vector<double> sval(L.soff_h[L.nsl]), dg(n);
+    AMG_HIP(hipMemcpy(perm.data(), L.perm, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+    AMG_HIP(hipMemcpy(srp.data(), L.rowptr, ((size_t)n + 1) * sizeof(int), hipMemcpyDeviceToHost));
+    AMG_HIP(hipMemcpy(scol.data(), L.scol, scol.size() * sizeof(int), hipMemcpyDeviceToHost));
+    if (L.sval) {
+      AMG_HIP(hipMemcpy(sval.data(), L.sval, sval.size() * sizeof(double), hipMemcpyDeviceToHost));
+    } else {  // FP32 levels above 0 keep only the FP32 copy: values are not recoverable exactly
+      std::vector<float> f(sval.size());
+      AMG_HIP(hipMemcpy(f.data(), L.sval32, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+      for (size_t q = 0; q < f.size(); ++q) sval[q] = f[q];
+    }
+    AMG_HIP(hipMemcpy(dg.data(), L.dg, (size_t)n * sizeof(double), hipMemcpyDeviceToHost));
+    for (int r = 0; r < n; ++r) pinv[perm[r]] = r;
+    std::vector<int> rp(n + 1, 0);
+    for (int i = 0; i < n; ++i) rp[i + 1] = rp[i] + (srp[pinv[i] + 1] - srp[pinv[i]]);
+    std::vector<std::pair<int, double>> row;
+    for (int sl = 0; sl < L.nsl; ++sl) {
+      const int w = (L.soff_h[sl + 1] - L.soff_h[sl]) / 64;
+      for (int r = L.srow_h[sl]; r < L.srow_h[sl + 1]; ++r) {
+        const int lane = r - L.srow_h[sl];
+        const int i = perm[r];
+        row.clear();
+        row.emplace_back(i, dg[r]);
+        for (int k = 0; k < srp[r + 1] - srp[r] - 1 && k < w; ++k) {
+          const size_t q = (size_t)L.soff_h[sl] + 64 * (size_t)k + lane;
+          row.emplace_back(perm[scol[q]], sval[q]);
+        }
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int, double>& a, const std::pair<int, double>& b) { return a.first < b.first; });
+        for (size_t q = 0; q < row.size(); ++q) {
+          if (colind) colind[rp[i] + q] = row[q].first;
+          if (vals) vals[rp[i] + q] = row[q].second;
+        }
+      }
+    }
+    if (rowptr) std::memcpy(rowptr, rp.data(), ((size_t)n + 1) * sizeof(int));
+    if (colour)
+      for (int c = 0; c < L.ncol; ++c)
+        for (int r = L.cptr[c]; r < L.cptr[c + 1]; ++r) colour[perm[r]] = c;
+    if (agg && L.nc > 0) {
+      std::vector<int> pagg(n), nperm;
+      AMG_HIP(hipMemcpy(pagg.data(), L.agg, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+      const Level& N = H.lev[l + 1];
+      if (N.perm) {
+        nperm.resize(N.n);
+        AMG_HIP(hipMemcpy(nperm.data(), N.perm, (size_t)N.n * sizeof(int), hipMemcpyDeviceToHost));
+      }
+      for (int i = 0; i < n; ++i) {
+        const int a = pagg[pinv[i]];
+        agg[i] = N.perm ? nperm[a] : a;
+      }
+    }
   });
 }
 

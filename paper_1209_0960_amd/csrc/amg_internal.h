@@ -78,11 +78,19 @@ struct KTimer {
 };
 
 // ------------------------------------------------------------------ hierarchy
+// A level of the hierarchy.  During construction the arrays are in the
+// level's natural row order (level 0: the caller's order; level l+1: coarse
+// rows numbered tile-major in aggregate creation order).  Once the hierarchy is
+// complete, every level except the coarsest is relabelled into colour order
+// (rows of colour 0 first, each colour in ascending natural order) and the
+// arrays below then hold that "solve order": perm[r] is the natural row of
+// solve row r.  The CSR entry order inside each row is unchanged.
 struct Level {
   int n = 0, nnz = 0;
   int T = 512, ntiles = 0;
   int nc = 0;  // rows of the next level (0 on the coarsest)
   int ncol = 0;
+  int sub = 8;  // lanes per row of the solve kernels (power of two >= mean row length, 4..64)
   // matrix
   int* rowptr = nullptr;
   int* colind = nullptr;
@@ -91,18 +99,34 @@ struct Level {
   double* l1 = nullptr;  // sum_j |a_ij| for l1-Jacobi
   float* l1_32 = nullptr;
   // aggregation (towards level l+1)
-  int* agg = nullptr;       // n
-  int* members = nullptr;   // n, grouped by coarse row, ascending rows
+  int* agg = nullptr;       // n: coarse row of each row
+  int* members = nullptr;   // n: rows grouped by coarse row, ascending natural order
   int* mptr = nullptr;      // nc+1
-  int* tile_off = nullptr;  // ntiles+1: first coarse row of each tile
+  int* tile_off = nullptr;  // ntiles+1: first coarse row of each tile (natural order only)
   // colouring
-  int* colour = nullptr;  // n
-  int* crows = nullptr;   // n: rows grouped by colour, ascending
-  std::vector<int> cptr;  // host, ncol+1
-  // optional setup data
+  int* colour = nullptr;  // n (natural order only)
+  int* crows = nullptr;   // n: rows grouped by colour, ascending (natural order only)
+  std::vector<int> cptr;  // host, ncol+1: colour c = solve rows [cptr[c], cptr[c+1])
+  int* perm = nullptr;    // n: natural row of each solve row (NULL: identity)
+  // Solve-phase matrix in SELL-64 form: slice s holds solve rows
+  // [srow[s], srow[s+1]) (at most 64, never across a colour boundary); its
+  // off-diagonal entries are stored column-major (entry k of lane t at
+  // soff[s] + 64 k + t), padded to the slice's longest row with (row, 0.0);
+  // the diagonal is kept apart.  sptr[c] = first slice of colour c.
+  int nsl = 0;
+  std::vector<int> sptr;  // host, ncol+1
+  int* srow = nullptr;    // nsl+1
+  std::vector<int> srow_h, soff_h;  // host copies (launch sizes, byte counts)
+  int* soff = nullptr;    // nsl+1
+  int* scol = nullptr;
+  double* sval = nullptr;
+  float* sval32 = nullptr;
+  double* dg = nullptr;
+  float* dg32 = nullptr;
+  // optional setup data (natural order)
   uint8_t* strong = nullptr;
   uint8_t* iso = nullptr;
-  // V-cycle work vectors (precision of the cycle); level 0 uses caller vectors
+  // V-cycle work vectors (precision of the cycle, solve order)
   double* x64 = nullptr;
   double* b64 = nullptr;
   double* t64 = nullptr;
@@ -119,20 +143,23 @@ struct Hierarchy {
   double* Ainv = nullptr;  // dense inverse of the coarsest matrix (FP64, symmetric)
   // CG work space
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *rold = nullptr;
+  double *bp = nullptr, *xp = nullptr;  // level-0 right-hand side / iterate in solve order
   double* partial = nullptr;  // reduction partials
   double* scal = nullptr;     // device scalars
   double* host_scal = nullptr;  // pinned
   double setup_ms = 0.0;
   size_t bytes = 0;
-  std::vector<void*> owned;
+  std::vector<std::pair<void*, size_t>> owned;
   hipStream_t setup_stream = nullptr;
 
+  // Frees one buffer obtained from alloc() (no-op for NULL).
+  void free_one(void* ptr, hipStream_t s);
   template <typename T>
   T* alloc(size_t count, hipStream_t s) {
     size_t b = count * sizeof(T);
     if (b == 0) b = sizeof(T);
     void* ptr = dalloc(b, s);
-    owned.push_back(ptr);
+    owned.emplace_back(ptr, b);
     bytes += b;
     return static_cast<T*>(ptr);
   }
@@ -172,6 +199,15 @@ void cast_f32(const double* in, float* out, size_t n, hipStream_t s);
 void l1_diag(const Level& L, double* out64, float* out32, hipStream_t s);
 // Dense FP64 factorisation of the coarsest level and its explicit inverse.
 void coarse_factor(Hierarchy& H, const Level& L, hipStream_t s);
+// Relabels level l into colour order (solve order); `next_perm` is the solve
+// order of level l+1 (NULL: identity, the coarsest level).  Frees the natural
+// order arrays that the solve does not need.
+void permute_level(Hierarchy& H, int l, const int* next_perm, hipStream_t s);
+// out[r] = in[perm[r]] (gather) and out[perm[r]] = in[r] (scatter); perm NULL: copy.
+void gather(int n, const int* perm, const double* in, double* out, hipStream_t s);
+// Builds the SELL-64 arrays of a level in solve order from its CSR and frees the CSR.
+void build_sell(Hierarchy& H, int l, hipStream_t s);
+void scatter(int n, const int* perm, const double* in, double* out, hipStream_t s);
 void exclusive_scan(const int* in, int* out, int n, hipStream_t s);  // out has n+1 entries
 
 // ------------------------------------------------------------------ solve kernels

@@ -409,18 +409,13 @@ __device__ inline Cand evaluate(const AggSh& S, int c, int id) {
     const int stg = (int)(w >> 15);
     const int aj = S.agg[j];
     if (aj == id) {
+      // The strong flags are symmetric: s_ij and s_ji are the same products
+      // (w_ij w_ji and a_ii a_jj commute) compared with the same
+      // delta*min(eta_i, eta_j), so the edge (j,c) is strong exactly when
+      // (c,j) is.  Every strong link is therefore two-way: cons2 counts
+      // them and cons1 is zero, without looking up the reverse entry.
       r.mm |= 1u << S.slot[j];
-      int rev = 0;
-      const int jb = S.lptr[j], je = S.lptr[j + 1];
-      for (int q = jb; q < je; ++q) {
-        const unsigned wq = S.ladj[q];
-        if ((int)(wq & 0x7FFF) == c) {
-          rev = (int)(wq >> 15);
-          break;
-        }
-      }
-      r.c2 += stg & rev;
-      r.c1 += stg ^ rev;
+      r.c2 += stg;
     } else {
       if (stg) r.conn += (aj >= 0 && S.adjflag[aj]) ? 2 : 1;
       const unsigned char fj = S.flag[j];
@@ -854,9 +849,15 @@ __global__ void k_compact(int nc, const int* __restrict__ toff, const int* __res
 }
 
 // ============================================================== colouring
-// Jones-Plassmann rounds: a row takes the smallest colour unused by its
-// neighbours of higher key once all of them are coloured.  key(i) =
-// (fmix32(i ^ seed), i), fmix32 being the MurmurHash3 32-bit finaliser.
+// Greedy first-fit colouring in a fixed order: tiles by descending key
+// (fmix32(t ^ seed), t) -- fmix32 being the MurmurHash3 32-bit finaliser --
+// and rows ascending inside a tile; each row takes the smallest colour that
+// none of its already coloured neighbours has.  In parallel, a tile is
+// coloured once every neighbour of its rows that lies in a tile of higher key
+// is coloured (such tiles precede it in the order; neighbours in tiles of
+// lower key wait for it), and inside the tile a row is coloured once all its
+// smaller in-tile neighbours are.  Either way a row sees exactly the neighbours
+// that precede it in the sequential order, so the result is that order's.
 __device__ inline uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;
   h *= 0x85ebca6bu;
@@ -865,8 +866,10 @@ __device__ inline uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;
   return h;
 }
-__device__ inline uint64_t ckey(int i, uint32_t s) {
-  return ((uint64_t)fmix32((uint32_t)i ^ s) << 32) | (uint32_t)i;
+
+__device__ inline bool tile_before(int ta, int tb, uint32_t seed) {  // ta precedes tb
+  const uint32_t ka = fmix32((uint32_t)ta ^ seed), kb = fmix32((uint32_t)tb ^ seed);
+  return ka > kb || (ka == kb && ta > tb);
 }
 
 __global__ void k_fill(int n, int* p, int v) {
@@ -874,43 +877,127 @@ __global__ void k_fill(int n, int* p, int v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_colour_round(int n, const int* __restrict__ rp, const int* __restrict__ ci, uint32_t seed,
-                               int* colour, int* remaining, int* maxcol) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || colour[i] >= 0) return;
-  const uint64_t ki = ckey(i, seed);
-  uint64_t mask = 0;
-  bool big = false;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const int j = ci[k];
-    if (j == i || ckey(j, seed) < ki) continue;
-    const int cj = colour[j];
-    if (cj < 0) {
-      atomicAdd(remaining, 1);
-      return;
-    }
-    if (cj < 64)
-      mask |= 1ull << cj;
-    else
-      big = true;
-  }
-  int c;
-  if (!big && mask != ~0ull) {
-    c = (int)__builtin_ctzll(~mask);
-  } else {
-    c = 0;
-    for (;;) {
-      bool used = false;
-      for (int k = rp[i]; k < rp[i + 1] && !used; ++k) {
+constexpr int COL_MAX_T = 1024;
+
+// Dynamic LDS of k_colour_tiles: lptr[T+1], col[T], mask[T] (64-bit), big[T],
+// adj[E] (local indices of the smaller in-tile neighbours).
+__host__ __device__ inline size_t col_smem(int T, int E) {
+  return align16(4 * (size_t)(T + 1)) + align16(4 * (size_t)T) + align16(8 * (size_t)T) + align16((size_t)T) +
+         align16(2 * (size_t)(E > 0 ? E : 1));
+}
+
+__global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, int Ecap, const int* __restrict__ work,
+                                                       int* __restrict__ next, int* next_cnt,
+                                                       const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       uint32_t seed, int* colour, int* maxcol) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  int* lptr = (int*)sm;
+  int* col = (int*)(sm + align16(4 * (size_t)(T + 1)));
+  uint64_t* mask = (uint64_t*)((unsigned char*)col + align16(4 * (size_t)T));
+  unsigned char* big = (unsigned char*)mask + align16(8 * (size_t)T);
+  unsigned short* adj = (unsigned short*)(big + align16((size_t)T));
+  const int lane = __lane_id();
+  const int t = work ? work[blockIdx.x] : (int)blockIdx.x;
+  const int lo = t * T, hi = min(lo + T, n), nt = hi - lo;
+  // Readiness, the colours already taken by off-tile neighbours, and the
+  // number of smaller in-tile neighbours of each row.
+  bool wait = false;
+  int carry = 0;
+  for (int base = 0; base < nt; base += WAVE) {
+    const int v = base + lane;
+    int cnt = 0;
+    if (v < nt && !wait) {
+      const int i = lo + v;
+      uint64_t m = 0;
+      unsigned char bg = 0;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
         const int j = ci[k];
-        if (j != i && ckey(j, seed) > ki && colour[j] == c) used = true;
+        if (j >= lo && j < hi) {
+          cnt += (j < i) ? 1 : 0;
+          continue;
+        }
+        const int cj = colour[j];
+        if (cj < 0) {
+          if (tile_before(j / T, t, seed)) {
+            wait = true;
+            break;
+          }
+        } else if (cj < 64) {
+          m |= 1ull << cj;
+        } else {
+          bg = 1;
+        }
       }
-      if (!used) break;
-      ++c;
+      mask[v] = m;
+      big[v] = bg;
     }
+    const int inc = wave_incl_scan(cnt);
+    if (v < nt) lptr[v] = carry + inc - cnt;
+    carry += __shfl(inc, WAVE - 1, WAVE);
   }
-  colour[i] = c;
-  atomicMax(maxcol, c);
+  if (__ballot(wait)) {
+    if (lane == 0) next[atomicAdd(next_cnt, 1)] = t;
+    return;
+  }
+  if (lane == 0) lptr[nt] = carry;
+  __syncthreads();
+  for (int v = lane; v < nt; v += WAVE) {
+    const int i = lo + v;
+    int pos = lptr[v];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = ci[k];
+      if (j >= lo && j < i) adj[pos++] = (unsigned short)(j - lo);
+    }
+    col[v] = -1;
+  }
+  __syncthreads();
+  int left = nt, cmax = -1;
+  while (left > 0) {
+    int done = 0;
+    for (int base = 0; base < nt; base += WAVE) {
+      const int v = base + lane;
+      if (v >= nt || col[v] >= 0) continue;
+      bool ready = true, bg = big[v] != 0;
+      uint64_t m = mask[v];
+      for (int q = lptr[v]; q < lptr[v + 1]; ++q) {
+        const int cj = col[adj[q]];
+        if (cj < 0) {
+          ready = false;
+          break;
+        }
+        if (cj < 64)
+          m |= 1ull << cj;
+        else
+          bg = true;
+      }
+      if (!ready) continue;
+      int c;
+      if (!bg && m != ~0ull) {
+        c = (int)__builtin_ctzll(~m);
+      } else {  // colours beyond 63 among the neighbours: search directly
+        const int i = lo + v;
+        c = 0;
+        for (;;) {
+          bool used = false;
+          for (int k = rp[i]; k < rp[i + 1] && !used; ++k) {
+            const int j = ci[k];
+            if (j == i || (j >= lo && j > i)) continue;
+            used = ((j >= lo && j < hi) ? col[j - lo] : colour[j]) == c;
+          }
+          if (!used) break;
+          ++c;
+        }
+      }
+      col[v] = c;
+      ++done;
+      cmax = max(cmax, c);
+    }
+    left -= wave_sum(done);
+    __syncthreads();
+  }
+  for (int v = lane; v < nt; v += WAVE) colour[lo + v] = col[v];
+  cmax = wave_max(cmax);
+  if (lane == 0) atomicMax(maxcol, cmax);
 }
 
 constexpr int CL_THREADS = 256;
@@ -1031,6 +1118,115 @@ __global__ void k_wtw(int n, const double* __restrict__ W, double* __restrict__ 
   Ainv[(size_t)j * n + i] = s;
 }
 
+// ============================================================== solve order
+__global__ void k_invperm(int n, const int* __restrict__ perm, int* __restrict__ pinv) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) pinv[perm[r]] = r;
+}
+
+__global__ void k_perm_rowlen(int n, const int* __restrict__ perm, const int* __restrict__ rp, int* __restrict__ len) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) {
+    const int i = perm[r];
+    len[r] = rp[i + 1] - rp[i];
+  }
+}
+
+// One wavefront per solve row: copy the row's entries (same order) with the
+// columns relabelled.
+__global__ __launch_bounds__(256) void k_perm_rows(int n, const int* __restrict__ perm, const int* __restrict__ pinv,
+                                                   const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double* __restrict__ v, const int* __restrict__ prp,
+                                                   int* __restrict__ pci, double* __restrict__ pv) {
+  const int r = blockIdx.x * 4 + threadIdx.x / WAVE;
+  if (r >= n) return;
+  const int i = perm[r];
+  const int b = rp[i], len = rp[i + 1] - b, d = prp[r];
+  for (int q = __lane_id(); q < len; q += WAVE) {
+    pci[d + q] = pinv[ci[b + q]];
+    pv[d + q] = v[b + q];
+  }
+}
+
+__global__ void k_perm_agg(int n, const int* __restrict__ perm, const int* __restrict__ agg,
+                           const int* __restrict__ next_pinv, int* __restrict__ pagg) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) {
+    const int a = agg[perm[r]];
+    pagg[r] = next_pinv ? next_pinv[a] : a;
+  }
+}
+
+__global__ void k_perm_mcount(int nc, const int* __restrict__ next_perm, const int* __restrict__ mptr,
+                              int* __restrict__ cnt) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) {
+    const int I = next_perm ? next_perm[c] : c;
+    cnt[c] = mptr[I + 1] - mptr[I];
+  }
+}
+
+__global__ void k_perm_members(int nc, const int* __restrict__ next_perm, const int* __restrict__ mptr,
+                               const int* __restrict__ members, const int* __restrict__ pinv,
+                               const int* __restrict__ pmptr, int* __restrict__ pmem) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) {
+    const int I = next_perm ? next_perm[c] : c;
+    const int b = mptr[I], len = mptr[I + 1] - b, d = pmptr[c];
+    for (int q = 0; q < len; ++q) pmem[d + q] = pinv[members[b + q]];
+  }
+}
+
+__global__ void k_gather(int n, const int* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = in[perm[r]];
+}
+
+__global__ void k_scatter(int n, const int* __restrict__ perm, const double* __restrict__ in,
+                          double* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[perm[r]] = in[r];
+}
+
+// ============================================================== SELL-64
+__global__ void k_sell_width(int nsl, const int* __restrict__ srow, const int* __restrict__ rp,
+                             int* __restrict__ w64) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nsl) return;
+  int w = 0;
+  for (int r = srow[sl]; r < srow[sl + 1]; ++r) w = max(w, rp[r + 1] - rp[r] - 1);
+  w64[sl] = 64 * w;
+}
+
+__global__ __launch_bounds__(256) void k_sell_fill(int nsl, const int* __restrict__ srow, const int* __restrict__ soff,
+                                                   const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double* __restrict__ v, int* __restrict__ scol,
+                                                   double* __restrict__ sval, double* __restrict__ dg) {
+  const int sl = blockIdx.x * 4 + threadIdx.x / WAVE;
+  if (sl >= nsl) return;
+  const int lane = __lane_id();
+  const int r0 = srow[sl], r = r0 + lane;
+  const bool valid = r < srow[sl + 1];
+  const int base = soff[sl], w = (soff[sl + 1] - base) / 64;
+  int k = 0;
+  if (valid) {
+    for (int q = rp[r]; q < rp[r + 1]; ++q) {
+      const int j = ci[q];
+      if (j == r) {
+        dg[r] = v[q];
+      } else {
+        scol[base + 64 * k + lane] = j;
+        sval[base + 64 * k + lane] = v[q];
+        ++k;
+      }
+    }
+  }
+  for (; k < w; ++k) {
+    scol[base + 64 * k + lane] = valid ? r : r0;
+    sval[base + 64 * k + lane] = 0.0;
+  }
+}
+
 template <typename T>
 T read1(const T* dptr, hipStream_t s) {
   T v;
@@ -1146,21 +1342,35 @@ void galerkin(Hierarchy& H, const Level& L, Level& C, hipStream_t s) {
 }
 
 void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
-  const int n = L.n;
+  const int n = L.n, T = L.T;
+  if (T > COL_MAX_T) fail(AMG_ERR_UNSUPPORTED, "tile_rows above 1024");
+  const int ntiles = cdiv(n, T);
   L.colour = H.alloc<int>((size_t)n, s);
-  DBuf cnt(2 * sizeof(int), s);
-  const int g = cdiv(n, 256);
-  hipLaunchKernelGGL(k_fill, dim3(g), dim3(256), 0, s, n, L.colour, -1);
-  AMG_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(int), s));
-  int rounds = 0;
-  for (;;) {
-    AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_colour_round, dim3(g), dim3(256), 0, s, n, L.rowptr, L.colind, seed, L.colour,
-                       cnt.as<int>(), cnt.as<int>() + 1);
+  DBuf cnt(4 * sizeof(int), s), w0((size_t)ntiles * sizeof(int), s), w1((size_t)ntiles * sizeof(int), s);
+  hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.colour, -1);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(int), s));
+  DBuf mx(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_tile_nnz_max, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, n, T, ntiles, L.rowptr, mx.as<int>());
+  const int Ecap = read1(mx.as<int>(), s);
+  const size_t shm = col_smem(T, Ecap);
+  if (shm > 160 * 1024) fail(AMG_ERR_UNSUPPORTED, "colouring tile exceeds LDS; use smaller tile_rows");
+  AMG_HIP(hipFuncSetAttribute((const void*)k_colour_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  int rounds = 0, remaining = ntiles;
+  const int* work = nullptr;
+  int* bufs[2] = {w0.as<int>(), w1.as<int>()};
+  while (remaining > 0) {
+    int* next = bufs[rounds & 1];
+    int* next_cnt = cnt.as<int>() + 2 + (rounds & 1);
+    AMG_HIP(hipMemsetAsync(next_cnt, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_colour_tiles, dim3(remaining), dim3(WAVE), shm, s, n, T, Ecap, work, next, next_cnt,
+                       L.rowptr, L.colind, seed, L.colour, cnt.as<int>() + 1);
     AMG_HIP(hipGetLastError());
     ++rounds;
-    if (read1(cnt.as<int>(), s) == 0) break;
-    if (rounds > 100000) fail(AMG_ERR_HIP, "colouring did not terminate");
+    const int left = read1(next_cnt, s);
+    if (left >= remaining) fail(AMG_ERR_HIP, "colouring made no progress");
+    remaining = left;
+    work = next;
   }
   const int C = read1(cnt.as<int>() + 1, s) + 1;
   if (C > 4096) fail(AMG_ERR_UNSUPPORTED, "more than 4096 colours");
@@ -1208,6 +1418,103 @@ void coarse_factor(Hierarchy& H, const Level& L, hipStream_t s) {
   H.Ainv = H.alloc<double>(nn, s);
   hipLaunchKernelGGL(k_wtw, dim3(cdiv(n, 64), n), dim3(64), 0, s, n, W.as<double>(), H.Ainv);
   AMG_HIP(hipGetLastError());
+}
+
+void gather(int n, const int* perm, const double* in, double* out, hipStream_t s) {
+  if (!perm) {
+    if (in != out) AMG_HIP(hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, in, out);
+  AMG_HIP(hipGetLastError());
+}
+
+void scatter(int n, const int* perm, const double* in, double* out, hipStream_t s) {
+  if (!perm) {
+    if (in != out) AMG_HIP(hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  hipLaunchKernelGGL(k_scatter, dim3(cdiv(n, 256)), dim3(256), 0, s, n, perm, in, out);
+  AMG_HIP(hipGetLastError());
+}
+
+void permute_level(Hierarchy& H, int l, const int* next_perm, hipStream_t s) {
+  Level& L = H.lev[l];
+  const int n = L.n, nnz = L.nnz, nc = L.nc;
+  const int g = cdiv(n, 256);
+  int* perm = L.crows;  // rows grouped by colour, ascending: the solve order
+  DBuf pinv((size_t)n * sizeof(int), s), len((size_t)n * sizeof(int), s);
+  hipLaunchKernelGGL(k_invperm, dim3(g), dim3(256), 0, s, n, perm, pinv.as<int>());
+  hipLaunchKernelGGL(k_perm_rowlen, dim3(g), dim3(256), 0, s, n, perm, L.rowptr, len.as<int>());
+  int* prp = H.alloc<int>((size_t)n + 1, s);
+  exclusive_scan(len.as<int>(), prp, n, s);
+  int* pci = H.alloc<int>((size_t)nnz, s);
+  double* pv = H.alloc<double>((size_t)nnz, s);
+  hipLaunchKernelGGL(k_perm_rows, dim3(cdiv(n, 4)), dim3(256), 0, s, n, perm, pinv.as<int>(), L.rowptr, L.colind,
+                     L.vals, prp, pci, pv);
+  DBuf npinv(next_perm ? (size_t)nc * sizeof(int) : 0, s);
+  if (next_perm)
+    hipLaunchKernelGGL(k_invperm, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, next_perm, npinv.as<int>());
+  int* pagg = H.alloc<int>((size_t)n, s);
+  hipLaunchKernelGGL(k_perm_agg, dim3(g), dim3(256), 0, s, n, perm, L.agg, npinv.as<int>(), pagg);
+  DBuf mc((size_t)nc * sizeof(int), s);
+  hipLaunchKernelGGL(k_perm_mcount, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, next_perm, L.mptr, mc.as<int>());
+  int* pmptr = H.alloc<int>((size_t)nc + 1, s);
+  exclusive_scan(mc.as<int>(), pmptr, nc, s);
+  int* pmem = H.alloc<int>((size_t)n, s);
+  hipLaunchKernelGGL(k_perm_members, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, next_perm, L.mptr, L.members,
+                     pinv.as<int>(), pmptr, pmem);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+  for (void* p : {(void*)L.rowptr, (void*)L.colind, (void*)L.vals, (void*)L.agg, (void*)L.members, (void*)L.mptr,
+                  (void*)L.tile_off, (void*)L.colour})
+    H.free_one(p, s);
+  L.rowptr = prp;
+  L.colind = pci;
+  L.vals = pv;
+  L.agg = pagg;
+  L.mptr = pmptr;
+  L.members = pmem;
+  L.tile_off = nullptr;
+  L.colour = nullptr;
+  L.perm = perm;
+  L.crows = nullptr;
+}
+
+void build_sell(Hierarchy& H, int l, hipStream_t s) {
+  Level& L = H.lev[l];
+  std::vector<int> srow_h;
+  L.sptr.assign(L.ncol + 1, 0);
+  for (int c = 0; c < L.ncol; ++c) {
+    L.sptr[c] = (int)srow_h.size();
+    for (int r = L.cptr[c]; r < L.cptr[c + 1]; r += 64) srow_h.push_back(r);
+  }
+  L.sptr[L.ncol] = (int)srow_h.size();
+  srow_h.push_back(L.n);
+  L.nsl = (int)srow_h.size() - 1;
+  L.srow = H.alloc<int>(srow_h.size(), s);
+  AMG_HIP(hipMemcpyAsync(L.srow, srow_h.data(), srow_h.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  DBuf w((size_t)L.nsl * sizeof(int), s);
+  hipLaunchKernelGGL(k_sell_width, dim3(cdiv(L.nsl, 256)), dim3(256), 0, s, L.nsl, L.srow, L.rowptr, w.as<int>());
+  L.soff = H.alloc<int>((size_t)L.nsl + 1, s);
+  exclusive_scan(w.as<int>(), L.soff, L.nsl, s);
+  L.srow_h = srow_h;
+  L.soff_h.assign(L.nsl + 1, 0);
+  AMG_HIP(hipMemcpyAsync(L.soff_h.data(), L.soff, ((size_t)L.nsl + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  const int tot = L.soff_h[L.nsl];
+  if (tot < 0) fail(AMG_ERR_UNSUPPORTED, "padded matrix exceeds 2^31 entries");
+  L.scol = H.alloc<int>((size_t)tot, s);
+  L.sval = H.alloc<double>((size_t)tot, s);
+  L.dg = H.alloc<double>((size_t)L.n, s);
+  hipLaunchKernelGGL(k_sell_fill, dim3(cdiv(L.nsl, 4)), dim3(256), 0, s, L.nsl, L.srow, L.soff, L.rowptr, L.colind,
+                     L.vals, L.scol, L.sval, L.dg);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+  H.free_one(L.colind, s);
+  H.free_one(L.vals, s);
+  L.colind = nullptr;
+  L.vals = nullptr;
 }
 
 }  // namespace amgx

@@ -81,14 +81,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_residual_dot(int n, const int* 
 }
 
 // ---------------------------------------------------------------- smoothers
-// Gauss-Seidel update of the rows of one colour: x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii.
+// Gauss-Seidel update of the rows of one colour, which occupy the contiguous
+// solve rows [lo, lo+cnt): x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii.
 template <typename V>
-__global__ void k_gs_colour(int cnt, const int* __restrict__ rows, const int* __restrict__ rp,
-                            const int* __restrict__ ci, const V* __restrict__ va, const V* __restrict__ b,
-                            V* __restrict__ x) {
+__global__ void k_gs_colour(int lo, int cnt, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const V* __restrict__ va, const V* __restrict__ b, V* __restrict__ x) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
-  const int i = rows[t];
+  const int i = lo + t;
   V acc = b[i], d = 1;
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
     const int j = ci[k];
@@ -117,33 +117,206 @@ __global__ void k_jacobi_update(int n, const V* __restrict__ t, const V* __restr
   if (i < n) x[i] += t[i] / d[i];
 }
 
-// ---------------------------------------------------------------- transfers
-// One workgroup per aggregation tile: residual of the tile's rows into LDS,
-// then b_c[I] = sum over the members of each aggregate I of the tile
-// (ascending rows).  Aggregates never cross tiles, so no atomics are needed.
+// ---------------------------------------------------------------- sub-wave rows
+// SUB consecutive lanes own one row: they read the row's entries as one
+// contiguous stream (a wavefront covers 64/SUB consecutive rows in one
+// coalesced load per entry block) and combine with a SUB-wide butterfly.
+template <int SUB, typename V>
+__device__ inline V group_sum(V v) {
+#pragma unroll
+  for (int o = SUB / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SUB);
+  return v;
+}
+
+// ---------------------------------------------------------------- SELL-64
+// One wavefront per slice of 64 solve rows: lane t owns row srow[s] + t and
+// reads its off-diagonal entry k at soff[s] + 64 k + t, so every load of the
+// matrix is one contiguous 64-wide access; padding entries are (row, 0).
 template <typename V>
-__global__ __launch_bounds__(256) void k_resid_restrict(int n, int T, const int* __restrict__ rp,
-                                                        const int* __restrict__ ci, const V* __restrict__ va,
-                                                        const V* __restrict__ b, const V* __restrict__ x,
-                                                        const int* __restrict__ tile_off,
-                                                        const int* __restrict__ mptr,
-                                                        const int* __restrict__ members, V* __restrict__ bc) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  V* rl = reinterpret_cast<V*>(smem);
-  const int t = blockIdx.x;
-  const int lo = t * T, hi = min(lo + T, n);
-  for (int v = threadIdx.x; v < hi - lo; v += blockDim.x) {
-    const int i = lo + v;
-    V acc = b[i];
-    for (int k = rp[i]; k < rp[i + 1]; ++k) acc -= va[k] * x[ci[k]];
-    rl[v] = acc;
+__device__ inline V sell_offdiag(const int* __restrict__ scol, const V* __restrict__ sval, int base, int w, int lane,
+                                 const V* __restrict__ x) {
+  const int* cp = scol + base + lane;
+  const V* vp = sval + base + lane;
+  V acc = 0;
+  int k = 0;
+  for (; k + 2 <= w; k += 2) {
+    const int j0 = cp[64 * k], j1 = cp[64 * (k + 1)];
+    const V a0 = vp[64 * k], a1 = vp[64 * (k + 1)];
+    acc += a0 * x[j0];
+    acc += a1 * x[j1];
   }
-  __syncthreads();
-  for (int I = tile_off[t] + threadIdx.x; I < tile_off[t + 1]; I += blockDim.x) {
-    V s = 0;
-    for (int p = mptr[I]; p < mptr[I + 1]; ++p) s += rl[members[p] - lo];
-    bc[I] = s;
+  if (k < w) acc += vp[64 * k] * x[cp[64 * k]];
+  return acc;
+}
+
+// Gauss-Seidel on the slices [s0, s0+ns) of one colour.
+template <typename V>
+__global__ __launch_bounds__(256) void k_gs_sell(int s0, int ns, const int* __restrict__ srow,
+                                                 const int* __restrict__ soff, const int* __restrict__ scol,
+                                                 const V* __restrict__ sval, const V* __restrict__ dg,
+                                                 const V* __restrict__ b, V* __restrict__ x) {
+  const int sl = s0 + (int)(blockIdx.x * 4 + threadIdx.x / WAVE);
+  if (sl >= s0 + ns) return;
+  const int lane = __lane_id();
+  const int r = srow[sl] + lane;
+  const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
+  const V acc = sell_offdiag<V>(scol, sval, base, w, lane, x);
+  if (r < srow[sl + 1]) x[r] = (b[r] - acc) / dg[r];
+}
+
+// t = b - A x over all slices.
+template <typename V>
+__global__ __launch_bounds__(256) void k_resid_sell(int nsl, const int* __restrict__ srow,
+                                                    const int* __restrict__ soff, const int* __restrict__ scol,
+                                                    const V* __restrict__ sval, const V* __restrict__ dg,
+                                                    const V* __restrict__ b, const V* __restrict__ x,
+                                                    V* __restrict__ t) {
+  const int sl = (int)(blockIdx.x * 4 + threadIdx.x / WAVE);
+  if (sl >= nsl) return;
+  const int lane = __lane_id();
+  const int r = srow[sl] + lane;
+  const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
+  const V acc = sell_offdiag<V>(scol, sval, base, w, lane, x);
+  if (r < srow[sl + 1]) t[r] = b[r] - (dg[r] * x[r] + acc);
+}
+
+// y = A x (FP64) with deterministic partial sums of x.y over a fixed grid.
+__global__ __launch_bounds__(RED_THREADS) void k_spmv_dot_sell(int nsl, const int* __restrict__ srow,
+                                                               const int* __restrict__ soff,
+                                                               const int* __restrict__ scol,
+                                                               const double* __restrict__ sval,
+                                                               const double* __restrict__ dg,
+                                                               const double* __restrict__ x, double* __restrict__ y,
+                                                               double* __restrict__ partial) {
+  const int lane = __lane_id();
+  const int wpb = RED_THREADS / WAVE;
+  double acc = 0.0;
+  for (int sl = blockIdx.x * wpb + threadIdx.x / WAVE; sl < nsl; sl += RED_BLOCKS * wpb) {
+    const int r = srow[sl] + lane;
+    const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
+    const double off = sell_offdiag<double>(scol, sval, base, w, lane, x);
+    if (r < srow[sl + 1]) {
+      const double xr = x[r];
+      const double yr = dg[r] * xr + off;
+      y[r] = yr;
+      acc += xr * yr;
+    }
   }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// r = b - A x (FP64) with deterministic partial sums of r.r.
+__global__ __launch_bounds__(RED_THREADS) void k_residual_dot_sell(int nsl, const int* __restrict__ srow,
+                                                                   const int* __restrict__ soff,
+                                                                   const int* __restrict__ scol,
+                                                                   const double* __restrict__ sval,
+                                                                   const double* __restrict__ dg,
+                                                                   const double* __restrict__ b,
+                                                                   const double* __restrict__ x,
+                                                                   double* __restrict__ r,
+                                                                   double* __restrict__ partial) {
+  const int lane = __lane_id();
+  const int wpb = RED_THREADS / WAVE;
+  double acc = 0.0;
+  for (int sl = blockIdx.x * wpb + threadIdx.x / WAVE; sl < nsl; sl += RED_BLOCKS * wpb) {
+    const int i = srow[sl] + lane;
+    const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
+    const double off = sell_offdiag<double>(scol, sval, base, w, lane, x);
+    if (i < srow[sl + 1]) {
+      const double ri = b[i] - (dg[i] * x[i] + off);
+      r[i] = ri;
+      acc += ri * ri;
+    }
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// y = A x with deterministic partial sums of x.y over a fixed grid.
+template <int SUB>
+__global__ __launch_bounds__(RED_THREADS) void k_spmv_dot_sub(int n, const int* __restrict__ rp,
+                                                              const int* __restrict__ ci,
+                                                              const double* __restrict__ va,
+                                                              const double* __restrict__ x, double* __restrict__ y,
+                                                              double* __restrict__ partial) {
+  const int sl = threadIdx.x % SUB;
+  const int gpb = RED_THREADS / SUB;
+  double acc = 0.0;
+  for (int i = blockIdx.x * gpb + threadIdx.x / SUB; i < n; i += RED_BLOCKS * gpb) {
+    double s = 0.0;
+    for (int k = rp[i] + sl; k < rp[i + 1]; k += SUB) s += va[k] * x[ci[k]];
+    s = group_sum<SUB>(s);
+    if (sl == 0) {
+      y[i] = s;
+      acc += x[i] * s;
+    }
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// r = b - A x with deterministic partial sums of r.r.
+template <int SUB>
+__global__ __launch_bounds__(RED_THREADS) void k_residual_dot_sub(int n, const int* __restrict__ rp,
+                                                                  const int* __restrict__ ci,
+                                                                  const double* __restrict__ va,
+                                                                  const double* __restrict__ b,
+                                                                  const double* __restrict__ x,
+                                                                  double* __restrict__ r, double* __restrict__ partial) {
+  const int sl = threadIdx.x % SUB;
+  const int gpb = RED_THREADS / SUB;
+  double acc = 0.0;
+  for (int i = blockIdx.x * gpb + threadIdx.x / SUB; i < n; i += RED_BLOCKS * gpb) {
+    double s = 0.0;
+    for (int k = rp[i] + sl; k < rp[i + 1]; k += SUB) s += va[k] * x[ci[k]];
+    s = group_sum<SUB>(s);
+    if (sl == 0) {
+      const double ri = b[i] - s;
+      r[i] = ri;
+      acc += ri * ri;
+    }
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// Dispatch on the lanes-per-row width chosen for a level.
+#define AMG_SUB_DISPATCH(SUBV, KERNEL_CALL) \
+  switch (SUBV) {                           \
+    case 4: {                               \
+      constexpr int SUB = 4;                \
+      KERNEL_CALL;                          \
+    } break;                                \
+    case 8: {                               \
+      constexpr int SUB = 8;                \
+      KERNEL_CALL;                          \
+    } break;                                \
+    case 16: {                              \
+      constexpr int SUB = 16;               \
+      KERNEL_CALL;                          \
+    } break;                                \
+    case 32: {                              \
+      constexpr int SUB = 32;               \
+      KERNEL_CALL;                          \
+    } break;                                \
+    default: {                              \
+      constexpr int SUB = 64;               \
+      KERNEL_CALL;                          \
+    } break;                                \
+  }
+
+// ---------------------------------------------------------------- transfers
+// b_c[I] = sum over the members of aggregate I (ascending natural order) of the
+// residual t computed by k_resid.
+template <typename V>
+__global__ void k_restrict(int nc, const int* __restrict__ mptr, const int* __restrict__ members,
+                           const V* __restrict__ t, V* __restrict__ bc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  V s = 0;
+  for (int p = mptr[I]; p < mptr[I + 1]; ++p) s += t[members[p]];
+  bc[I] = s;
 }
 
 template <typename V>
@@ -152,15 +325,19 @@ __global__ void k_prolong(int n, const int* __restrict__ agg, const V* __restric
   if (i < n) x[i] += omega * xc[agg[i]];
 }
 
-// x = A_L^{-1} b with the symmetric explicit inverse (column i read coalesced).
+// x = A_L^{-1} b with the explicit inverse: one wavefront per row, lanes over
+// the (contiguous) row, butterfly sum.
 template <typename Vin, typename Vout>
-__global__ void k_coarse_gemv(int n, const double* __restrict__ Ainv, const Vin* __restrict__ b,
-                              Vout* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_coarse_gemv(int n, const double* __restrict__ Ainv,
+                                                     const Vin* __restrict__ b, Vout* __restrict__ x) {
+  const int i = blockIdx.x * 4 + threadIdx.x / WAVE;
   if (i >= n) return;
+  const int lane = __lane_id();
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s += Ainv[(size_t)j * n + i] * (double)b[j];
-  x[i] = (Vout)s;
+  const double* row = Ainv + (size_t)i * n;
+  for (int j = lane; j < n; j += WAVE) s += row[j] * (double)b[j];
+  s = wave_sum_d(s);
+  if (lane == 0) x[i] = (Vout)s;
 }
 
 template <typename A, typename B>
@@ -273,6 +450,8 @@ template <typename V>
 struct LV;
 template <>
 struct LV<double> {
+  static const double* svals(const Level& L) { return L.sval; }
+  static const double* diag(const Level& L) { return L.dg; }
   static const double* vals(const Level& L) { return L.vals; }
   static double* x(Level& L) { return L.x64; }
   static double* b(Level& L) { return L.b64; }
@@ -281,6 +460,8 @@ struct LV<double> {
 };
 template <>
 struct LV<float> {
+  static const float* svals(const Level& L) { return L.sval32; }
+  static const float* diag(const Level& L) { return L.dg32; }
   static const float* vals(const Level& L) { return L.vals32; }
   static float* x(Level& L) { return L.x32; }
   static float* b(Level& L) { return L.b32; }
@@ -291,29 +472,37 @@ struct LV<float> {
 inline int kind_of(int l, int k) { return l == 0 ? k : AMG_KIND_COARSE_LEVELS; }
 
 template <typename V>
+double slice_bytes(const Level& L, int s0, int s1) {  // algorithmic bytes of a pass over slices [s0, s1)
+  const double vb = sizeof(V);
+  const double ent = (double)(L.soff_h[s1] - L.soff_h[s0]);
+  const double rows = (double)(L.srow_h[s1] - L.srow_h[s0]);
+  return ent * (4.0 + vb) + rows * 4.0 * vb + (s1 - s0) * 8.0;  // entries; b, diag, x read, x write; slice headers
+}
+
+template <typename V>
 void smooth(Hierarchy& H, int l, const V* b, V* x, hipStream_t s) {
   Level& L = H.lev[l];
-  const V* va = LV<V>::vals(L);
-  const double vb = sizeof(V);
-  const double nnz_row = (double)L.nnz / L.n;
+  const V* va = LV<V>::svals(L);
+  const V* dg = LV<V>::diag(L);
   if (H.p.smoother == AMG_SMOOTHER_MCSGS) {
     for (int dir = 0; dir < 2; ++dir)
       for (int q = 0; q < L.ncol; ++q) {
         const int c = dir == 0 ? q : L.ncol - 1 - q;
-        const int cnt = L.cptr[c + 1] - L.cptr[c];
-        if (!cnt) continue;
-        KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, cnt * ((4.0 + vb) * nnz_row + 8.0 + 3.0 * vb));
-        hipLaunchKernelGGL(k_gs_colour<V>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, L.crows + L.cptr[c],
-                           L.rowptr, L.colind, va, b, x);
+        const int s0 = L.sptr[c], ns = L.sptr[c + 1] - s0;
+        if (!ns) continue;
+        KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, slice_bytes<V>(L, s0, s0 + ns));
+        hipLaunchKernelGGL(k_gs_sell<V>, dim3(cdiv(ns, 4)), dim3(256), 0, s, s0, ns, L.srow, L.soff, L.scol, va, dg, b,
+                           x);
       }
   } else {
     V* t = LV<V>::t(L);
     {
-      KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, L.n * ((4.0 + vb) * nnz_row + 4.0 + 3.0 * vb));
-      hipLaunchKernelGGL(k_resid<V>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, L.rowptr, L.colind, va, b, x, t);
+      KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, slice_bytes<V>(L, 0, L.nsl));
+      hipLaunchKernelGGL(k_resid_sell<V>, dim3(cdiv(L.nsl, 4)), dim3(256), 0, s, L.nsl, L.srow, L.soff, L.scol, va, dg,
+                         b, x, t);
     }
     {
-      KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, L.n * 4.0 * vb);
+      KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, L.n * 4.0 * sizeof(V));
       hipLaunchKernelGGL(k_jacobi_update<V>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, t, LV<V>::l1(L), x);
     }
   }
@@ -328,7 +517,7 @@ void vcycle(Hierarchy& H, int l, const V* b, V* x, hipStream_t s) {
   Level& L = H.lev[l];
   if (l == Lc) {
     KTimer tm(kind_of(l, AMG_KIND_COARSE_LEVELS), s, 8.0 * H.nL * H.nL);
-    hipLaunchKernelGGL((k_coarse_gemv<V, V>), dim3(cdiv(H.nL, 64)), dim3(64), 0, s, H.nL, H.Ainv, b, x);
+    hipLaunchKernelGGL((k_coarse_gemv<V, V>), dim3(cdiv(H.nL, 4)), dim3(256), 0, s, H.nL, H.Ainv, b, x);
     AMG_HIP(hipGetLastError());
     return;
   }
@@ -337,10 +526,14 @@ void vcycle(Hierarchy& H, int l, const V* b, V* x, hipStream_t s) {
   for (int k = 0; k < H.p.pre_sweeps; ++k) smooth<V>(H, l, b, x, s);
   Level& C = H.lev[l + 1];
   {
-    KTimer tm(kind_of(l, AMG_KIND_RESTRICT), s,
-              (4.0 + vb) * L.nnz + L.n * (4.0 + 2 * vb + 4.0) + L.nc * (4.0 + vb) + 4.0 * L.ntiles);
-    hipLaunchKernelGGL(k_resid_restrict<V>, dim3(L.ntiles), dim3(256), (size_t)L.T * sizeof(V), s, L.n, L.T,
-                       L.rowptr, L.colind, LV<V>::vals(L), b, x, L.tile_off, L.mptr, L.members, LV<V>::b(C));
+    KTimer tm(kind_of(l, AMG_KIND_RESTRICT), s, slice_bytes<V>(L, 0, L.nsl));
+    hipLaunchKernelGGL(k_resid_sell<V>, dim3(cdiv(L.nsl, 4)), dim3(256), 0, s, L.nsl, L.srow, L.soff, L.scol,
+                       LV<V>::svals(L), LV<V>::diag(L), b, x, LV<V>::t(L));
+  }
+  {
+    KTimer tm(kind_of(l, AMG_KIND_RESTRICT), s, L.n * (4.0 + vb) + L.nc * (4.0 + vb));
+    hipLaunchKernelGGL(k_restrict<V>, dim3(cdiv(L.nc, 256)), dim3(256), 0, s, L.nc, L.mptr, L.members, LV<V>::t(L),
+                       LV<V>::b(C));
     AMG_HIP(hipGetLastError());
   }
   vcycle<V>(H, l + 1, LV<V>::b(C), LV<V>::x(C), s);
@@ -377,18 +570,27 @@ void precond_apply(Hierarchy& H, const double* r, double* z, hipStream_t s) {
 
 void spmv64(const Level& L, const double* x, double* y, double* partial, hipStream_t s, int kind) {
   KTimer tm(kind, s, 12.0 * L.nnz + 4.0 * (L.n + 1) + 16.0 * L.n);
-  if (partial)
-    hipLaunchKernelGGL(k_spmv_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.n, L.rowptr, L.colind, L.vals, x, y,
-                       partial);
-  else
+  if (!partial && L.scol) fail(AMG_ERR_HIP, "spmv64 on SELL level needs a partial buffer");
+  if (L.scol) {
+    hipLaunchKernelGGL(k_spmv_dot_sell, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.nsl, L.srow, L.soff, L.scol,
+                       L.sval, L.dg, x, y, partial);
+  } else if (partial) {
+    AMG_SUB_DISPATCH(L.sub, hipLaunchKernelGGL(k_spmv_dot_sub<SUB>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.n,
+                                               L.rowptr, L.colind, L.vals, x, y, partial));
+  } else
     hipLaunchKernelGGL(k_spmv<double>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, L.rowptr, L.colind, L.vals, x, y);
   AMG_HIP(hipGetLastError());
 }
 
 void residual64(const Level& L, const double* b, const double* x, double* r, double* partial, hipStream_t s) {
   KTimer tm(AMG_KIND_CG_VEC, s, 12.0 * L.nnz + 4.0 * (L.n + 1) + 24.0 * L.n);
-  hipLaunchKernelGGL(k_residual_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.n, L.rowptr, L.colind, L.vals, b, x,
-                     r, partial);
+  if (L.scol) {
+    hipLaunchKernelGGL(k_residual_dot_sell, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.nsl, L.srow, L.soff, L.scol,
+                       L.sval, L.dg, b, x, r, partial);
+  } else {
+    AMG_SUB_DISPATCH(L.sub, hipLaunchKernelGGL(k_residual_dot_sub<SUB>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.n,
+                                               L.rowptr, L.colind, L.vals, b, x, r, partial));
+  }
   AMG_HIP(hipGetLastError());
 }
 

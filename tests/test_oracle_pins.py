@@ -316,21 +316,43 @@ def test_galerkin_closed_form_aligned_cubes():
 
 # ----------------------------------------------------------------- colouring
 def test_colouring_proper_and_first_fit():
-    for s in (P.poisson(12), P.lognormal(10)):
-        c, k = O.colour(s.rowptr, s.colind, seed=3)
+    """Proper colouring; each row's colour is the smallest one missing among the
+    neighbours that precede it in the order (tiles by descending key, rows
+    ascending inside a tile), checked by brute force on the output."""
+    for s, T in ((P.poisson(12), 64), (P.lognormal(10), 128), (P.jump_cube(9), 100)):
+        c, k = O.colour(s.rowptr, s.colind, seed=3, tile_rows=T)
         rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
         off = rows != s.colind
         assert not np.any(c[rows[off]] == c[s.colind[off]])
         assert c.max() == k - 1
-        # first fit along descending keys: each colour below c(i) appears on a
-        # higher-key neighbour of i
-        h = np.array([O.fmix32(i ^ 3) for i in range(s.n)], dtype=np.uint64)
-        key = (h << np.uint64(32)) | np.arange(s.n, dtype=np.uint64)
+        nt = (s.n + T - 1) // T
+        tkey = [(O.fmix32(t ^ 3), t) for t in range(nt)]
+        order = sorted(range(nt), key=lambda t: tkey[t], reverse=True)
+        pos = np.empty(s.n, np.int64)
+        p = 0
+        for t in order:
+            for i in range(t * T, min((t + 1) * T, s.n)):
+                pos[i] = p
+                p += 1
         for i in range(s.n):
             nb = s.colind[s.rowptr[i]:s.rowptr[i + 1]]
-            nb = nb[(nb != i) & (key[nb] > key[i])]
-            assert set(range(c[i])) <= set(c[nb].tolist())
+            nb = nb[(nb != i) & (pos[nb] < pos[i])]
+            used = set(c[nb].tolist())
+            assert c[i] == min(set(range(len(nb) + 1)) - used)
 
+
+def test_colouring_is_parity_on_aligned_morton_tiles():
+    """7-point graph, edges multiples of 8, 512-row tiles (aligned 8^3 Morton
+    cubes): every cell except a tile's first has an in-tile neighbour earlier in
+    Morton order, the first cell of a tile has even coordinate sum, and
+    neighbours always have opposite parity, so the greedy colours are exactly
+    (x + y + z) mod 2 for any coefficients and any tile order."""
+    for s in (P.poisson(16), P.lognormal(16, seed=3), P.from_field(np.ones((8, 16, 24)))):
+        c, k = O.colour(s.rowptr, s.colind, seed=11, tile_rows=512)
+        nx, ny, nz = s.shape
+        z, y, x = np.unravel_index(s.order, (nz, ny, nx))
+        assert k == 2
+        assert np.array_equal(c, (x + y + z) % 2)
 
 def test_fmix32_known_properties():
     assert O.fmix32(0) == 0
@@ -341,7 +363,7 @@ def test_fmix32_known_properties():
 # ----------------------------------------------------------------- smoother
 def test_mcsgs_equals_textbook_sgs_on_colour_permuted_matrix():
     s = P.lognormal(8, seed=11)
-    c, k = O.colour(s.rowptr, s.colind, seed=0)
+    c, k = O.colour(s.rowptr, s.colind, seed=0, tile_rows=64)
     rng = np.random.default_rng(0)
     b = rng.standard_normal(s.n)
     x0 = rng.standard_normal(s.n)
