@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--cpu-sample-n", type=int, default=64)
+    ap.add_argument("--cpu-sample-n", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain-FP64 comparison solves")
     args = ap.parse_args()
