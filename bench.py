@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain-FP64 comparison solves")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of this "
@@ -98,6 +100,16 @@ def main():
     from paper_1209_0960_amd import problems as P
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "repeats": 3}), flush=True)
+        return
     A.lib()
     n = args.n
     t = time.perf_counter()
@@ -117,8 +129,6 @@ def main():
         _, r, _ = step(True)
         log(f"warmup {w}: setup {r.setup_ms:.1f} ms solve {r.solve_ms:.1f} ms it={r.iterations}")
 
-    A.set_kernel_timing([A.KIND_SWEEP])
-    A.reset_kernel_timing()
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,12 +137,19 @@ def main():
         infos.append(r)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    A.set_kernel_timing(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    sweep_ms, sweep_launches, sweep_bytes = A.kernel_timing(A.KIND_SWEEP)
     for r in infos:
         log(f"timed step: setup {r.setup_ms:.1f} ms solve {r.solve_ms:.1f} ms it={r.iterations} "
             f"true_rel_res={r.true_rel_residual:.2e}")
+    # Per-kernel HIP-event timing of the dominant kernel: one more step of the
+    # same workload with event timing on (iterations launched individually, the
+    # kernels are the ones the graph replays).
+    A.set_kernel_timing([A.KIND_SWEEP])
+    A.reset_kernel_timing()
+    _, rt, _ = step(True)
+    A.set_kernel_timing(False)
+    sweep_ms, sweep_launches, sweep_bytes = A.kernel_timing(A.KIND_SWEEP)
+    log(f"event-timed step: solve {rt.solve_ms:.1f} ms, {sweep_launches} sweep launches")
 
     extra = {}
     if not args.no_compare:
@@ -184,6 +201,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic,
+            "method": "HIP events on the launch stream around every level-0 colour pass of one extra step "
+                      "of the same workload after the timed steps",
             "launches": sweep_launches,
             "avg_launch_us": avg_launch_ms * 1e3,
             "algorithmic_bytes_per_launch": bytes_per_launch,

@@ -83,6 +83,7 @@ typedef struct amg_params {
   uint32_t colour_seed;      /* seed of the colouring priorities               [0]    */
   int32_t check_symmetry;    /* 1: reject A with a_ij != a_ji                  [1]    */
   int32_t keep_setup_data;   /* 1: keep strong/isolated flags for amg_copy_level [0]  */
+  int32_t use_graphs;        /* 1: pcg_solve replays each iteration as a HIP graph [1] */
 } amg_params;
 
 typedef struct amg_solve_info {
@@ -120,7 +121,10 @@ AMG_API amg_status amg_precond_apply(amg_hierarchy *h, const double *r, double *
  * for A x = b with x holding x0 on entry and the solution on return.  Stops
  * when ||r_k||_2 <= rtol ||r_0||_2 (recursive residual) or after maxit
  * iterations (then AMG_ERR_NOT_CONVERGED with x = last iterate and *info
- * filled).  Blocks until done.
+ * filled).  Blocks until done.  The iterations run on a stream owned by the
+ * hierarchy, ordered after the caller's earlier work on `stream`; with
+ * use_graphs each iteration is one replay of a captured HIP graph.  Calls on
+ * one hierarchy must not overlap.
  *   info      host, nullable
  *   res_hist  host, nullable, maxit+1 doubles: ||r_k||/||r_0||
  *   iter_hist device, nullable, n*(maxit+1) doubles: x_k for k = 0.. */
@@ -162,7 +166,8 @@ AMG_API amg_status amg_copy_level(const amg_hierarchy *h, int32_t l, int32_t *ag
 /* Per-kernel-class timing with HIP events recorded around each launch on the
  * launch stream (off by default; adds a small overhead when on).
  * amg_set_kernel_timing takes a bit mask of kinds (bit k enables kind k; 0
- * disables).  kind is one of the AMG_KIND_* values; *ms is the summed
+ * disables).  While timing is on, pcg_solve launches its iterations
+ * individually instead of replaying a graph.  kind is one of the AMG_KIND_* values; *ms is the summed
  * duration, *launches the count, *bytes the summed algorithmic HBM bytes of
  * those launches. */
 enum {

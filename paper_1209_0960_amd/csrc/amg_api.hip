@@ -73,8 +73,20 @@ void Hierarchy::free_one(void* ptr, hipStream_t s) {
 }
 
 void Hierarchy::release(hipStream_t s) {
+  if (iter_exec) {
+    (void)hipGraphExecDestroy(iter_exec);
+    iter_exec = nullptr;
+  }
   for (auto& o : owned) dfree(o.first, s);
   owned.clear();
+  if (ev_in) (void)hipEventDestroy(ev_in);
+  if (ev_out) (void)hipEventDestroy(ev_out);
+  ev_in = ev_out = nullptr;
+  if (work) {
+    (void)hipStreamSynchronize(work);
+    (void)hipStreamDestroy(work);
+    work = nullptr;
+  }
   if (host_scal) {
     (void)hipHostFree(host_scal);
     host_scal = nullptr;
@@ -83,12 +95,8 @@ void Hierarchy::release(hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ timing
-struct TimingRec {
-  int kind;
-  double bytes;
-  hipEvent_t e0, e1;
-};
 static std::mutex g_tmu;
+
 static int g_timing = 0;  // bit mask of enabled kinds
 static std::vector<TimingRec> g_pending;
 static std::vector<hipEvent_t> g_event_pool;
@@ -97,6 +105,7 @@ static int64_t g_launches[AMG_KIND_COUNT];
 static double g_bytes[AMG_KIND_COUNT];
 
 bool timing_on() { return g_timing != 0; }
+int g_timing_mask_for_graphs() { return g_timing; }
 
 static hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -119,8 +128,8 @@ KTimer::KTimer(int k, hipStream_t st, double b) : kind(k), s(st), bytes(b) {
 
 KTimer::~KTimer() {
   if (!e0) return;
-  std::lock_guard<std::mutex> g(g_tmu);
   (void)hipEventRecord(e1, s);
+  std::lock_guard<std::mutex> g(g_tmu);
   g_pending.push_back(TimingRec{kind, bytes, e0, e1});
 }
 
@@ -313,6 +322,9 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   H.partial = H.alloc<double>(2 * (size_t)RED_BLOCKS, s);
   H.scal = H.alloc<double>(S_COUNT, s);
   AMG_HIP(hipHostMalloc((void**)&H.host_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+  AMG_HIP(hipStreamCreateWithFlags(&H.work, hipStreamNonBlocking));
+  AMG_HIP(hipEventCreateWithFlags(&H.ev_in, hipEventDisableTiming));
+  AMG_HIP(hipEventCreateWithFlags(&H.ev_out, hipEventDisableTiming));
   AMG_HIP(hipStreamSynchronize(s));
   H.setup_ms = now_ms() - t0;
 }
@@ -322,17 +334,61 @@ void read_scal(Hierarchy& H, hipStream_t s) {
   AMG_HIP(hipStreamSynchronize(s));
 }
 
+// The part of a CG iteration after the convergence test of iteration k and
+// up to that of iteration k+1: z = M r, beta and the new direction, then
+// q = A p, alpha, the x/r update and ||r||^2.
+void iteration_body(Hierarchy& H, hipStream_t s) {
+  Level& L0 = H.lev[0];
+  const int n = L0.n;
+  double* const rold = H.flexible ? H.rold : nullptr;
+  precond_apply(H, H.r, H.z, s);
+  cg_dots_rz(n, H.r, H.z, rold, H.partial, s);
+  finish(H.partial, RED_BLOCKS, H.scal, S_RZ, H.flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
+  cg_update_p(n, H.pv, H.z, H.scal, s);
+  spmv64(L0, H.pv, H.q, H.partial, s, AMG_KIND_SPMV_F64);
+  finish(H.partial, RED_BLOCKS, H.scal, S_PQ, FIN_ALPHA, s);
+  cg_update_xr(n, H.xp, H.r, rold, H.pv, H.q, H.scal, H.partial, s);
+  finish(H.partial, RED_BLOCKS, H.scal, S_RR, FIN_STORE, s);
+}
+
+void run_iteration(Hierarchy& H, hipStream_t s) {
+  // Per-kernel event timing records events around individual launches, so it
+  // runs the iteration eagerly (the kernels are the same as in the graph).
+  const int mask = g_timing_mask_for_graphs();
+  if (!H.p.use_graphs || mask != 0) {
+    iteration_body(H, s);
+    return;
+  }
+  if (!H.iter_exec) {
+    hipGraph_t g = nullptr;
+    AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      iteration_body(H, s);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    AMG_HIP(hipStreamEndCapture(s, &g));
+    hipError_t e = hipGraphInstantiate(&H.iter_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    AMG_HIP(e);
+  }
+  AMG_HIP(hipGraphLaunch(H.iter_exec, s));
+}
+
 amg_status pcg_impl(Hierarchy& H, const double* b_user, double* x_user, double rtol, int maxit,
-                    amg_solve_info* info, double* res_hist, double* iter_hist, hipStream_t s) {
+                    amg_solve_info* info, double* res_hist, double* iter_hist, hipStream_t us) {
   const double t0 = now_ms();
   Level& L0 = H.lev[0];
   const int n = L0.n;
+  hipStream_t s = H.work;
+  AMG_HIP(hipEventRecord(H.ev_in, us));
+  AMG_HIP(hipStreamWaitEvent(s, H.ev_in, 0));
   // The iteration runs in the level-0 solve order.
   const int* perm0 = L0.perm;
   double* const b = H.bp;
   double* const x = H.xp;
-  gather(n, perm0, b_user, b, s);
-  gather(n, perm0, x_user, x, s);
   double* const r = H.r;
   double* const z = H.z;
   double* const p = H.pv;
@@ -340,6 +396,8 @@ amg_status pcg_impl(Hierarchy& H, const double* b_user, double* x_user, double r
   double* const rold = H.flexible ? H.rold : nullptr;
   double* const part = H.partial;
   double* const scal = H.scal;
+  gather(n, perm0, b_user, b, s);
+  gather(n, perm0, x_user, x, s);
   AMG_HIP(hipMemsetAsync(scal, 0, S_COUNT * sizeof(double), s));
   residual64(L0, b, x, r, part, s);
   finish(part, RED_BLOCKS, scal, S_R0, FIN_STORE, s);
@@ -352,17 +410,17 @@ amg_status pcg_impl(Hierarchy& H, const double* b_user, double* x_user, double r
   double rel = r0 > 0.0 ? 1.0 : 0.0;
   if (r0 == 0.0) {
     st = AMG_OK;
-  } else {
+  } else if (maxit > 0) {
     precond_apply(H, r, z, s);
     AMG_HIP(hipMemcpyAsync(p, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
     dot_partial(n, r, z, part, s);
     finish(part, RED_BLOCKS, scal, S_RHO, FIN_RHO_INIT, s);
-    for (int k = 1; k <= maxit; ++k) {
-      spmv64(L0, p, q, part, s, AMG_KIND_SPMV_F64);
-      finish(part, RED_BLOCKS, scal, S_PQ, FIN_ALPHA, s);
-      cg_update_xr(n, x, r, rold, p, q, scal, part, s);
-      finish(part, RED_BLOCKS, scal, S_RR, FIN_STORE, s);
-      read_scal(H, s);
+    spmv64(L0, p, q, part, s, AMG_KIND_SPMV_F64);
+    finish(part, RED_BLOCKS, scal, S_PQ, FIN_ALPHA, s);
+    cg_update_xr(n, x, r, rold, p, q, scal, part, s);
+    finish(part, RED_BLOCKS, scal, S_RR, FIN_STORE, s);
+    read_scal(H, s);
+    for (int k = 1;; ++k) {
       if (H.host_scal[S_FLAG] != 0.0) {
         st = AMG_ERR_BREAKDOWN;
         break;
@@ -375,10 +433,10 @@ amg_status pcg_impl(Hierarchy& H, const double* b_user, double* x_user, double r
         st = AMG_OK;
         break;
       }
-      precond_apply(H, r, z, s);
-      cg_dots_rz(n, r, z, rold, part, s);
-      finish(part, RED_BLOCKS, scal, S_RZ, H.flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
-      cg_update_p(n, p, z, scal, s);
+      if (k == maxit) break;
+      run_iteration(H, s);
+      read_scal(H, s);
+
     }
   }
   scatter(n, perm0, x, x_user, s);
@@ -391,6 +449,8 @@ amg_status pcg_impl(Hierarchy& H, const double* b_user, double* x_user, double r
   finish(part, RED_BLOCKS, scal, S_TMP, FIN_STORE, s);
   read_scal(H, s);
   const double bn = std::sqrt(H.host_scal[S_TMP]);
+  AMG_HIP(hipEventRecord(H.ev_out, s));
+  AMG_HIP(hipStreamWaitEvent(us, H.ev_out, 0));
   if (info) {
     info->iterations = it;
     info->converged = st == AMG_OK ? 1 : 0;
@@ -429,6 +489,7 @@ amg_status amg_default_params(amg_params* p) {
   p->colour_seed = 0;
   p->check_symmetry = 1;
   p->keep_setup_data = 0;
+  p->use_graphs = 1;
   return AMG_OK;
 }
 

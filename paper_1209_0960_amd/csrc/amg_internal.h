@@ -67,6 +67,12 @@ struct DBuf {
 // ------------------------------------------------------------------ timing
 enum { KIND_NONE = -1 };
 bool timing_on();
+struct TimingRec {
+  int kind;
+  double bytes;
+  hipEvent_t e0, e1;
+};
+int g_timing_mask_for_graphs();
 // Records an event pair around a launch when timing is enabled.
 struct KTimer {
   int kind;
@@ -148,6 +154,10 @@ struct Hierarchy {
   double* scal = nullptr;     // device scalars
   double* host_scal = nullptr;  // pinned
   double setup_ms = 0.0;
+  // solve stream and the captured CG iteration
+  hipStream_t work = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t iter_exec = nullptr;
   size_t bytes = 0;
   std::vector<std::pair<void*, size_t>> owned;
   hipStream_t setup_stream = nullptr;

@@ -250,15 +250,22 @@ __global__ void k_strong(int n, int T, const int* __restrict__ rp, const int* __
 // One wavefront per tile of T rows runs the greedy aggregation of Sec. 2.1
 // (Alg. 1 with Alg. 2 and Alg. 3, singleton merge, isolated phase) on the tile
 // subgraph (Alg. 4).  The tile graph lives in LDS as a local CSR of 16-bit
-// neighbour indices with the strong flag in bit 15.  Each selection step
-// evaluates all front candidates in parallel (one per lane) and picks the
-// winner with a butterfly reduction over a strict total order.
-constexpr unsigned F_ISO = 1, F_FRONT = 2;
+// neighbour indices with the strong flag in bit 15, and each vertex has one
+// packed 32-bit state word.  Each selection step scores all front candidates
+// in parallel (one per lane) and picks the winner with a butterfly reduction
+// over a strict total order.
 constexpr int AGG_MAX_T = 1024;
 constexpr int AGG_MAX_SLOTS = 32;
+// state word: bits 0-15 aggregate id (0xFFFF = none), 16-21 member slot of
+// the current aggregate (63 = none), bit 22 isolated, bit 23 on the front.
+constexpr unsigned ST_AGG = 0xFFFFu, ST_SLOT_SHIFT = 16, ST_SLOT_NONE = 63u << 16, ST_SLOT_MASK = 63u << 16;
+constexpr unsigned ST_ISO = 1u << 22, ST_FRONT = 1u << 23;
+
+__device__ inline int st_agg(unsigned w) { return (int)(short)(w & ST_AGG); }
+__device__ inline int st_slot(unsigned w) { return (int)((w >> ST_SLOT_SHIFT) & 63u); }
 
 struct AggLayout {
-  size_t lptr, key1, key2, adjf, madj, nbk, agg, nna, front, adjl, mem, slot, flag, ladj, total;
+  size_t lptr, st, key1, key2, adjf, madj, nbk, nna, front, adjl, mem, ladj, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -267,18 +274,16 @@ __host__ __device__ inline AggLayout agg_layout(int T, int E) {
   AggLayout L;
   size_t o = 0;
   L.lptr = o; o = align16(o + 4 * (size_t)(T + 1));
+  L.st = o; o = align16(o + 4 * (size_t)T);
   L.key1 = o; o = align16(o + 4 * (size_t)T);
   L.key2 = o; o = align16(o + 4 * (size_t)T);
   L.adjf = o; o = align16(o + 4 * (size_t)T);
   L.madj = o; o = align16(o + 4 * (size_t)AGG_MAX_SLOTS);
   L.nbk = o; o = align16(o + 2 * (size_t)T);
-  L.agg = o; o = align16(o + 2 * (size_t)T);
   L.nna = o; o = align16(o + 2 * (size_t)T);
   L.front = o; o = align16(o + 2 * (size_t)T);
   L.adjl = o; o = align16(o + 2 * (size_t)T);
   L.mem = o; o = align16(o + 2 * (size_t)AGG_MAX_SLOTS);
-  L.slot = o; o = align16(o + (size_t)T);
-  L.flag = o; o = align16(o + (size_t)T);
   L.ladj = o; o = align16(o + 2 * (size_t)(E > 0 ? E : 1));
   L.total = o;
   return L;
@@ -286,41 +291,37 @@ __host__ __device__ inline AggLayout agg_layout(int T, int E) {
 
 struct AggSh {
   int* lptr;
+  unsigned* st;
   int* key1;
   int* key2;
   int* adjflag;
   unsigned* madj;
   short* nbk;
-  short* agg;
   short* nna;
   short* front;
   short* adjl;
   short* mem;
-  signed char* slot;
-  unsigned char* flag;
   unsigned short* ladj;
 };
 
 // Per-aggregate state, uniform across the wave.
 struct AggState {
   int asize;   // members of the current aggregate
-  int fcount;  // entries appended to the front list (N(a) n candidates)
+  int fcount;  // entries appended to the front list (candidates in N(a))
   int acount;  // entries appended to the adjacent-aggregate list
 };
 
-// Adds vertex c to the aggregate `id`: marks it, updates the unaggregated
+// Adds vertex c to aggregate `id`: marks it, updates the unaggregated
 // neighbour counts, the member adjacency masks, the candidate front and the
 // set of adjacent aggregates.  Phase 1 fronts hold non-isolated vertices and
 // track every adjacent aggregate; the isolated phase fronts hold isolated
 // vertices and track only aggregates of phase 1 (ids < P1).
-__device__ void add_member(const AggSh& S, AggState& st, int c, int id, bool iso_phase, int P1) {
+__device__ void add_member(const AggSh& S, AggState& as, int c, int id, bool iso_phase, int P1) {
   const int lane = __lane_id();
-  const int s = st.asize;
+  const int s = as.asize;
   if (lane == 0) {
-    S.agg[c] = (short)id;
-    S.slot[c] = (signed char)s;
+    S.st[c] = (S.st[c] & ST_ISO) | ((unsigned)s << ST_SLOT_SHIFT) | ((unsigned)id & ST_AGG);
     S.mem[s] = (short)c;
-    S.flag[c] &= (unsigned char)~F_FRONT;
   }
   __syncthreads();
   const int b = S.lptr[c], e = S.lptr[c + 1];
@@ -332,16 +333,16 @@ __device__ void add_member(const AggSh& S, AggState& st, int c, int id, bool iso
     if (k < e) {
       j = S.ladj[k] & 0x7FFF;
       if (!iso_phase) S.nna[j] = (short)(S.nna[j] - 1);
-      aj = S.agg[j];
-      const unsigned char fj = S.flag[j];
+      const unsigned wj = S.st[j];
+      aj = st_agg(wj);
       if (aj == id) {
-        const int sj = S.slot[j];
+        const int sj = st_slot(wj);
         bits |= 1u << sj;
         S.madj[sj] |= 1u << s;
       } else if (aj < 0) {
-        const bool elig = iso_phase ? (fj & F_ISO) != 0 : (fj & F_ISO) == 0;
-        if (elig && !(fj & F_FRONT)) {
-          S.flag[j] = (unsigned char)(fj | F_FRONT);
+        const bool elig = iso_phase ? (wj & ST_ISO) != 0 : (wj & ST_ISO) == 0;
+        if (elig && !(wj & ST_FRONT)) {
+          S.st[j] = wj | ST_FRONT;
           appF = true;
         }
       } else {
@@ -350,27 +351,29 @@ __device__ void add_member(const AggSh& S, AggState& st, int c, int id, bool iso
       }
     }
     const uint64_t mF = __ballot(appF);
-    if (appF) S.front[st.fcount + __popcll(mF & lanemask_lt())] = (short)j;
-    st.fcount += __popcll(mF);
+    if (appF) S.front[as.fcount + __popcll(mF & lanemask_lt())] = (short)j;
+    as.fcount += __popcll(mF);
     const uint64_t mA = __ballot(appA);
-    if (appA) S.adjl[st.acount + __popcll(mA & lanemask_lt())] = (short)aj;
-    st.acount += __popcll(mA);
+    if (appA) S.adjl[as.acount + __popcll(mA & lanemask_lt())] = (short)aj;
+    as.acount += __popcll(mA);
   }
   bits = wave_or(bits);
   if (lane == 0) S.madj[s] = bits;
-  st.asize = s + 1;
+  as.asize = s + 1;
   __syncthreads();
 }
 
-__device__ void clear_aggregate(const AggSh& S, AggState& st) {
+__device__ void clear_aggregate(const AggSh& S, AggState& as) {
   const int lane = __lane_id();
-  for (int p = lane; p < st.fcount; p += WAVE) S.flag[S.front[p]] &= (unsigned char)~F_FRONT;
-  for (int p = lane; p < st.acount; p += WAVE) S.adjflag[S.adjl[p]] = 0;
-  if (lane < st.asize) {
-    S.slot[S.mem[lane]] = -1;
+  for (int p = lane; p < as.fcount; p += WAVE) S.st[S.front[p]] &= ~ST_FRONT;
+  for (int p = lane; p < as.acount; p += WAVE) S.adjflag[S.adjl[p]] = 0;
+  __syncthreads();
+  if (lane < as.asize) {
+    const int v = S.mem[lane];
+    S.st[v] = (S.st[v] & ~ST_SLOT_MASK) | ST_SLOT_NONE;
     S.madj[lane] = 0;
   }
-  st.asize = st.fcount = st.acount = 0;
+  as.asize = as.fcount = as.acount = 0;
   __syncthreads();
 }
 
@@ -393,43 +396,51 @@ __device__ inline bool ecc_ok(const AggSh& S, unsigned mm, int asize, int dmax) 
   return reach == full;
 }
 
-struct Cand {
-  int c2, c1, conn, nb, in_a, in_U;
+// First scoring pass of candidate c: cons2 (strong links into a), the member
+// mask, and |N(c) n U|.  The strong flags are symmetric: s_ij and s_ji are the
+// same products (w_ij w_ji and a_ii a_jj commute) compared with the same
+// delta*min(eta_i, eta_j), so every strong link is two-way, cons2 counts them
+// and cons1 is zero.
+struct ScoreA {
+  int c2, in_U;
   unsigned mm;
 };
-
-// cons2/cons1 (two-/one-way strong links into a), connect(c,a), neighbors(c,a),
-// |N(c) n a|, |N(c) n U| and the member mask of candidate c.
-__device__ inline Cand evaluate(const AggSh& S, int c, int id) {
-  Cand r{0, 0, 0, 0, 0, 0, 0u};
+__device__ inline ScoreA score_a(const AggSh& S, int c, int id) {
+  ScoreA r{0, 0, 0u};
   const int b = S.lptr[c], e = S.lptr[c + 1];
+#pragma unroll 2
   for (int k = b; k < e; ++k) {
     const unsigned w = S.ladj[k];
-    const int j = w & 0x7FFF;
-    const int stg = (int)(w >> 15);
-    const int aj = S.agg[j];
+    const unsigned wj = S.st[w & 0x7FFF];
+    const int aj = st_agg(wj);
     if (aj == id) {
-      // The strong flags are symmetric: s_ij and s_ji are the same products
-      // (w_ij w_ji and a_ii a_jj commute) compared with the same
-      // delta*min(eta_i, eta_j), so the edge (j,c) is strong exactly when
-      // (c,j) is.  Every strong link is therefore two-way: cons2 counts
-      // them and cons1 is zero, without looking up the reverse entry.
-      r.mm |= 1u << S.slot[j];
-      r.c2 += stg;
-    } else {
-      if (stg) r.conn += (aj >= 0 && S.adjflag[aj]) ? 2 : 1;
-      const unsigned char fj = S.flag[j];
-      if (aj < 0 && !(fj & F_ISO)) {
-        ++r.in_U;
-        if (!(fj & F_FRONT)) ++r.nb;
-      }
+      r.mm |= 1u << st_slot(wj);
+      r.c2 += (int)(w >> 15);
+    } else if (aj < 0 && !(wj & ST_ISO)) {
+      ++r.in_U;
     }
   }
-  r.in_a = __popc(r.mm);
   return r;
 }
 
-// Strict total order of grow candidates with equal cons: larger
+// Tie-break pass: connect(c,a) (strong neighbours outside a, weight 2 when in
+// an aggregate adjacent to a) and neighbors(c,a) = |(N(c) n U) \ N(a)|.
+__device__ inline void score_b(const AggSh& S, int c, int id, int& conn, int& nb) {
+  conn = 0;
+  nb = 0;
+  const int b = S.lptr[c], e = S.lptr[c + 1];
+#pragma unroll 2
+  for (int k = b; k < e; ++k) {
+    const unsigned w = S.ladj[k];
+    const unsigned wj = S.st[w & 0x7FFF];
+    const int aj = st_agg(wj);
+    if (aj == id) continue;
+    if (w >> 15) conn += (aj >= 0 && S.adjflag[aj]) ? 2 : 1;
+    if (aj < 0 && !(wj & (ST_ISO | ST_FRONT))) ++nb;
+  }
+}
+
+// Strict total order of grow candidates with equal cons2: larger
 // connect/|N| (exact cross multiplication), then larger neighbors, then
 // smaller index.  c < 0 marks "no candidate".
 __device__ inline bool better(int ca, int conna, int dega, int nba, int cb, int connb, int degb, int nbb) {
@@ -450,18 +461,16 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   const AggLayout Lo = agg_layout(T, Ecap);
   AggSh S;
   S.lptr = (int*)(sm + Lo.lptr);
+  S.st = (unsigned*)(sm + Lo.st);
   S.key1 = (int*)(sm + Lo.key1);
   S.key2 = (int*)(sm + Lo.key2);
   S.adjflag = (int*)(sm + Lo.adjf);
   S.madj = (unsigned*)(sm + Lo.madj);
   S.nbk = (short*)(sm + Lo.nbk);
-  S.agg = (short*)(sm + Lo.agg);
   S.nna = (short*)(sm + Lo.nna);
   S.front = (short*)(sm + Lo.front);
   S.adjl = (short*)(sm + Lo.adjl);
   S.mem = (short*)(sm + Lo.mem);
-  S.slot = (signed char*)(sm + Lo.slot);
-  S.flag = (unsigned char*)(sm + Lo.flag);
   S.ladj = (unsigned short*)(sm + Lo.ladj);
 
   const int lane = __lane_id();
@@ -496,10 +505,8 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
       if (j != i && j >= lo && j < lo + nt) S.ladj[pos++] = (unsigned short)((j - lo) | (strong[k] ? 0x8000 : 0));
     }
     const bool is = isov[i] != 0;
-    S.flag[v] = is ? F_ISO : 0;
-    S.agg[v] = -1;
+    S.st[v] = ST_AGG | ST_SLOT_NONE | (is ? ST_ISO : 0u);
     S.nna[v] = (short)(pos - S.lptr[v]);
-    S.slot[v] = -1;
     S.adjflag[v] = 0;
     nonIso += is ? 0 : 1;
   }
@@ -507,7 +514,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   int nU = wave_sum(nonIso);
   __syncthreads();
 
-  AggState st{0, 0, 0};
+  AggState as{0, 0, 0};
   int id = 0;
 
   // ---- phase 1: non-isolated vertices (Alg. 1)
@@ -515,56 +522,45 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   if (nU > 0) {
     int key = INT_MAX;
     for (int v = lane; v < nt; v += WAVE)
-      if (!(S.flag[v] & F_ISO)) key = min(key, ((int)S.nna[v] << 16) | v);
+      if (!(S.st[v] & ST_ISO)) key = min(key, ((int)S.nna[v] << 16) | v);
     seed = wave_min(key) & 0xFFFF;
   }
   while (nU > 0) {
-    add_member(S, st, seed, id, false, 0);
+    add_member(S, as, seed, id, false, 0);
     --nU;
     // Grow (Alg. 2)
-    while (st.asize < smin) {
-      int lm2 = 0, lm1 = 0;
-      for (int base = 0; base < st.fcount; base += WAVE) {
+    while (as.asize < smin) {
+      int lm2 = 0;
+      for (int base = 0; base < as.fcount; base += WAVE) {
         const int p = base + lane;
-        if (p < st.fcount) {
+        if (p < as.fcount) {
           const int c = S.front[p];
           int k1 = -1;
-          if (S.agg[c] < 0) {
-            const Cand r = evaluate(S, c, id);
-            const int ok = ecc_ok(S, r.mm, st.asize, dmax) ? 1 : 0;
-            k1 = r.c2 | (r.c1 << 8) | (ok << 16);
-            S.key2[p] = r.conn | ((S.lptr[c + 1] - S.lptr[c]) << 16);
-            S.nbk[p] = (short)r.nb;
-            if (ok) {
-              lm2 = max(lm2, r.c2);
-              lm1 = max(lm1, r.c1);
-            }
+          if (st_agg(S.st[c]) < 0) {
+            const ScoreA r = score_a(S, c, id);
+            const int ok = (r.c2 > 0 && ecc_ok(S, r.mm, as.asize, dmax)) ? 1 : 0;
+            k1 = ok ? r.c2 : 0;
+            if (ok) lm2 = max(lm2, r.c2);
           }
           S.key1[p] = k1;
         }
       }
-      const int m2 = wave_max(lm2), m1 = wave_max(lm1);
-      if (m2 == 0 && m1 == 0) break;
+      const int m2 = wave_max(lm2);
+      if (m2 == 0) break;
       __syncthreads();
       int bc = -1, bconn = 0, bdeg = 1, bnb = 0;
-      for (int base = 0; base < st.fcount; base += WAVE) {
+      for (int base = 0; base < as.fcount; base += WAVE) {
         const int p = base + lane;
-        if (p < st.fcount) {
-          const int k1 = S.key1[p];
-          if (k1 >= 0 && (k1 >> 16)) {
-            const int prim = m2 > 0 ? (k1 & 0xFF) : ((k1 >> 8) & 0xFF);
-            const int tgt = m2 > 0 ? m2 : m1;
-            if (prim == tgt) {
-              const int c = S.front[p];
-              const int k2 = S.key2[p];
-              const int conn = k2 & 0xFFFF, deg = k2 >> 16, nb = S.nbk[p];
-              if (better(c, conn, deg, nb, bc, bconn, bdeg, bnb)) {
-                bc = c;
-                bconn = conn;
-                bdeg = deg;
-                bnb = nb;
-              }
-            }
+        if (p < as.fcount && S.key1[p] == m2) {
+          const int c = S.front[p];
+          int conn, nb;
+          score_b(S, c, id, conn, nb);
+          const int deg = S.lptr[c + 1] - S.lptr[c];
+          if (better(c, conn, deg, nb, bc, bconn, bdeg, bnb)) {
+            bc = c;
+            bconn = conn;
+            bdeg = deg;
+            bnb = nb;
           }
         }
       }
@@ -581,30 +577,30 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
       }
       __syncthreads();
       if (bc < 0) break;
-      add_member(S, st, bc, id, false, 0);
+      add_member(S, as, bc, id, false, 0);
       --nU;
     }
     // Round (Alg. 3)
-    while (st.asize < smax) {
+    while (as.asize < smax) {
       int best = INT_MAX;
-      for (int base = 0; base < st.fcount; base += WAVE) {
+      for (int base = 0; base < as.fcount; base += WAVE) {
         const int p = base + lane;
-        if (p < st.fcount) {
+        if (p < as.fcount) {
           const int c = S.front[p];
-          if (S.agg[c] < 0) {
-            const Cand r = evaluate(S, c, id);
-            if ((r.c2 > 0 || r.c1 > 0) && r.in_a > r.in_U) best = min(best, c);
+          if (st_agg(S.st[c]) < 0) {
+            const ScoreA r = score_a(S, c, id);
+            if (r.c2 > 0 && __popc(r.mm) > r.in_U) best = min(best, c);
           }
         }
       }
       best = wave_min(best);
       if (best == INT_MAX) break;
-      add_member(S, st, best, id, false, 0);
+      add_member(S, as, best, id, false, 0);
       --nU;
     }
     // One-vertex aggregate: join the aggregate holding most strong neighbours.
     bool merged = false;
-    if (st.asize == 1) {
+    if (as.asize == 1) {
       const int v = S.mem[0];
       const int b = S.lptr[v], e = S.lptr[v + 1];
       int bk = INT_MAX, bcnt = 0;
@@ -612,12 +608,12 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
         const int k = base + lane;
         if (k < e) {
           const unsigned w = S.ladj[k];
-          const int aj = S.agg[w & 0x7FFF];
+          const int aj = st_agg(S.st[w & 0x7FFF]);
           if ((w >> 15) && aj >= 0 && aj != id) {
             int cnt = 0;
             for (int q = b; q < e; ++q) {
               const unsigned wq = S.ladj[q];
-              cnt += ((wq >> 15) && S.agg[wq & 0x7FFF] == aj) ? 1 : 0;
+              cnt += ((wq >> 15) && st_agg(S.st[wq & 0x7FFF]) == aj) ? 1 : 0;
             }
             if (cnt > bcnt || (cnt == bcnt && aj < bk)) {
               bcnt = cnt;
@@ -635,7 +631,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
         }
       }
       if (bcnt > 0) {
-        if (lane == 0) S.agg[v] = (short)bk;
+        if (lane == 0) S.st[v] = (S.st[v] & ~ST_AGG) | ((unsigned)bk & ST_AGG);
         merged = true;
       }
       __syncthreads();
@@ -644,19 +640,21 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
     // Next seed: fewest unaggregated neighbours on the front, else over U.
     if (nU > 0) {
       int key = INT_MAX;
-      for (int p = lane; p < st.fcount; p += WAVE) {
+      for (int p = lane; p < as.fcount; p += WAVE) {
         const int c = S.front[p];
-        if (S.agg[c] < 0) key = min(key, ((int)S.nna[c] << 16) | c);
+        if (st_agg(S.st[c]) < 0) key = min(key, ((int)S.nna[c] << 16) | c);
       }
       key = wave_min(key);
       if (key == INT_MAX) {
-        for (int v = lane; v < nt; v += WAVE)
-          if (S.agg[v] < 0 && !(S.flag[v] & F_ISO)) key = min(key, ((int)S.nna[v] << 16) | v);
+        for (int v = lane; v < nt; v += WAVE) {
+          const unsigned wv = S.st[v];
+          if (st_agg(wv) < 0 && !(wv & ST_ISO)) key = min(key, ((int)S.nna[v] << 16) | v);
+        }
         key = wave_min(key);
       }
       seed = key & 0xFFFF;
     }
-    clear_aggregate(S, st);
+    clear_aggregate(S, as);
   }
 
   // ---- phase 2: isolated vertices (GrowIsoAggregate reading)
@@ -664,49 +662,53 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   for (int base = 0; base < nt; base += WAVE) {
     for (;;) {
       const int v = base + lane;
-      const bool cand = v < nt && (S.flag[v] & F_ISO) && S.agg[v] < 0;
+      bool cand = false;
+      if (v < nt) {
+        const unsigned wv = S.st[v];
+        cand = (wv & ST_ISO) && st_agg(wv) < 0;
+      }
       const uint64_t m = __ballot(cand);
       if (!m) break;
       const int s0 = base + (int)__builtin_ctzll(m);
       const int myid = id++;
-      add_member(S, st, s0, myid, true, P1);
-      while (st.asize < smin) {
+      add_member(S, as, s0, myid, true, P1);
+      while (as.asize < smin) {
         int best = INT_MAX;
-        for (int b2 = 0; b2 < st.fcount; b2 += WAVE) {
+        for (int b2 = 0; b2 < as.fcount; b2 += WAVE) {
           const int p = b2 + lane;
-          if (p < st.fcount) {
+          if (p < as.fcount) {
             const int c = S.front[p];
-            if (S.agg[c] < 0) {
+            if (st_agg(S.st[c]) < 0) {
               bool common = false;
               unsigned mm = 0;
               for (int k = S.lptr[c]; k < S.lptr[c + 1]; ++k) {
-                const int j = S.ladj[k] & 0x7FFF;
-                const int aj = S.agg[j];
+                const unsigned wj = S.st[S.ladj[k] & 0x7FFF];
+                const int aj = st_agg(wj);
                 if (aj == myid)
-                  mm |= 1u << S.slot[j];
+                  mm |= 1u << st_slot(wj);
                 else if (aj >= 0 && aj < P1 && S.adjflag[aj])
                   common = true;
               }
-              if (common && ecc_ok(S, mm, st.asize, dmax)) best = min(best, c);
+              if (common && ecc_ok(S, mm, as.asize, dmax)) best = min(best, c);
             }
           }
         }
         best = wave_min(best);
         if (best == INT_MAX) break;
-        add_member(S, st, best, myid, true, P1);
+        add_member(S, as, best, myid, true, P1);
       }
-      clear_aggregate(S, st);
+      clear_aggregate(S, as);
     }
   }
 
   // ---- outputs: local ids, count, member lists grouped by aggregate
   __syncthreads();
-  for (int v = lane; v < nt; v += WAVE) agg_local[lo + v] = S.agg[v];
+  for (int v = lane; v < nt; v += WAVE) agg_local[lo + v] = st_agg(S.st[v]);
   const int na = id;
   if (lane == 0) tile_cnt[t] = na;
   for (int k = lane; k < na; k += WAVE) S.key1[k] = 0;
   __syncthreads();
-  for (int v = lane; v < nt; v += WAVE) atomicAdd(&S.key1[S.agg[v]], 1);
+  for (int v = lane; v < nt; v += WAVE) atomicAdd(&S.key1[st_agg(S.st[v])], 1);
   __syncthreads();
   carry = 0;
   for (int base = 0; base < na; base += WAVE) {
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
     int pos = S.key2[k];
     mstart[lo + k] = pos;
     for (int v = 0; v < nt; ++v)
-      if (S.agg[v] == k) members[lo + pos++] = lo + v;
+      if (st_agg(S.st[v]) == k) members[lo + pos++] = lo + v;
   }
 }
 
@@ -878,6 +880,76 @@ __global__ void k_fill(int n, int* p, int v) {
 }
 
 constexpr int COL_MAX_T = 1024;
+constexpr int TSET = 2048;  // LDS hash set of the neighbour tiles of one tile
+
+// Distinct neighbour tiles of each tile (tiles holding an off-tile neighbour of
+// one of its rows).  Count pass (adj == NULL): cnt[t] and pending[t] = number
+// of neighbour tiles that precede t.  Fill pass: adj[tptr[t] ...].
+__global__ __launch_bounds__(WAVE) void k_tile_nbrs(int n, int T, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, uint32_t seed,
+                                                    const int* __restrict__ tptr, int* __restrict__ adj,
+                                                    int* __restrict__ cnt, int* __restrict__ pending,
+                                                    int* overflow) {
+  __shared__ int hs[TSET];
+  const int lane = __lane_id();
+  const int t = blockIdx.x;
+  const int lo = t * T, hi = min(lo + T, n), nt = hi - lo;
+  for (int q = lane; q < TSET; q += WAVE) hs[q] = -1;
+  __syncthreads();
+  for (int v = lane; v < nt; v += WAVE) {
+    const int i = lo + v;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = ci[k];
+      if (j >= lo && j < hi) continue;
+      const int u = j / T;
+      int h = (int)(fmix32((uint32_t)u) & (TSET - 1));
+      for (int probe = 0;; ++probe) {
+        if (probe == TSET) {
+          atomicOr(overflow, 1);
+          break;
+        }
+        const int old = atomicCAS(&hs[h], -1, u);
+        if (old == -1 || old == u) break;
+        h = (h + 1) & (TSET - 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (!adj) {
+    int c = 0, pr = 0;
+    for (int q = lane; q < TSET; q += WAVE)
+      if (hs[q] >= 0) {
+        ++c;
+        pr += tile_before(hs[q], t, seed) ? 1 : 0;
+      }
+    c = wave_sum(c);
+    pr = wave_sum(pr);
+    if (lane == 0) {
+      cnt[t] = c;
+      pending[t] = pr;
+    }
+    return;
+  }
+  int pos = tptr[t];
+  for (int base = 0; base < TSET; base += WAVE) {
+    const int u = hs[base + lane];
+    const uint64_t m = __ballot(u >= 0);
+    if (u >= 0) adj[pos + __popcll(m & lanemask_lt())] = u;
+    pos += __popcll(m);
+  }
+}
+
+__global__ void k_ready0(int ntiles, const int* __restrict__ pending, int* __restrict__ list, int* cnt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ready = t < ntiles && pending[t] == 0;
+  const uint64_t m = __ballot(ready);
+  if (!m) return;
+  const int lane = __lane_id(), leader = (int)__builtin_ctzll(m);
+  int base = 0;
+  if (lane == leader) base = atomicAdd(cnt, __popcll(m));
+  base = __shfl(base, leader, WAVE);
+  if (ready) list[base + __popcll(m & lanemask_lt())] = t;
+}
 
 // Dynamic LDS of k_colour_tiles: lptr[T+1], col[T], mask[T] (64-bit), big[T],
 // adj[E] (local indices of the smaller in-tile neighbours).
@@ -886,10 +958,13 @@ __host__ __device__ inline size_t col_smem(int T, int E) {
          align16(2 * (size_t)(E > 0 ? E : 1));
 }
 
-__global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, int Ecap, const int* __restrict__ work,
+// Colours the tiles of `work` (all their preceding neighbour tiles are
+// finished), then releases the neighbour tiles they precede.
+__global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* __restrict__ work,
                                                        int* __restrict__ next, int* next_cnt,
                                                        const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       uint32_t seed, int* colour, int* maxcol) {
+                                                       const int* __restrict__ tptr, const int* __restrict__ tadj,
+                                                       int* pending, uint32_t seed, int* colour, int* maxcol) {
   extern __shared__ __align__(16) unsigned char sm[];
   int* lptr = (int*)sm;
   int* col = (int*)(sm + align16(4 * (size_t)(T + 1)));
@@ -897,16 +972,15 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, int Ecap, c
   unsigned char* big = (unsigned char*)mask + align16(8 * (size_t)T);
   unsigned short* adj = (unsigned short*)(big + align16((size_t)T));
   const int lane = __lane_id();
-  const int t = work ? work[blockIdx.x] : (int)blockIdx.x;
+  const int t = work[blockIdx.x];
   const int lo = t * T, hi = min(lo + T, n), nt = hi - lo;
-  // Readiness, the colours already taken by off-tile neighbours, and the
-  // number of smaller in-tile neighbours of each row.
-  bool wait = false;
+  // Colours already taken by off-tile neighbours (all in preceding tiles) and
+  // the smaller in-tile neighbours of each row.
   int carry = 0;
   for (int base = 0; base < nt; base += WAVE) {
     const int v = base + lane;
     int cnt = 0;
-    if (v < nt && !wait) {
+    if (v < nt) {
       const int i = lo + v;
       uint64_t m = 0;
       unsigned char bg = 0;
@@ -917,16 +991,10 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, int Ecap, c
           continue;
         }
         const int cj = colour[j];
-        if (cj < 0) {
-          if (tile_before(j / T, t, seed)) {
-            wait = true;
-            break;
-          }
-        } else if (cj < 64) {
-          m |= 1ull << cj;
-        } else {
+        if (cj >= 64)
           bg = 1;
-        }
+        else if (cj >= 0)
+          m |= 1ull << cj;
       }
       mask[v] = m;
       big[v] = bg;
@@ -934,10 +1002,6 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, int Ecap, c
     const int inc = wave_incl_scan(cnt);
     if (v < nt) lptr[v] = carry + inc - cnt;
     carry += __shfl(inc, WAVE - 1, WAVE);
-  }
-  if (__ballot(wait)) {
-    if (lane == 0) next[atomicAdd(next_cnt, 1)] = t;
-    return;
   }
   if (lane == 0) lptr[nt] = carry;
   __syncthreads();
@@ -951,53 +1015,66 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, int Ecap, c
     col[v] = -1;
   }
   __syncthreads();
-  int left = nt, cmax = -1;
-  while (left > 0) {
-    int done = 0;
-    for (int base = 0; base < nt; base += WAVE) {
-      const int v = base + lane;
-      if (v >= nt || col[v] >= 0) continue;
-      bool ready = true, bg = big[v] != 0;
-      uint64_t m = mask[v];
-      for (int q = lptr[v]; q < lptr[v + 1]; ++q) {
-        const int cj = col[adj[q]];
-        if (cj < 0) {
-          ready = false;
-          break;
-        }
-        if (cj < 64)
-          m |= 1ull << cj;
-        else
-          bg = true;
-      }
-      if (!ready) continue;
-      int c;
-      if (!bg && m != ~0ull) {
-        c = (int)__builtin_ctzll(~m);
-      } else {  // colours beyond 63 among the neighbours: search directly
-        const int i = lo + v;
-        c = 0;
-        for (;;) {
-          bool used = false;
-          for (int k = rp[i]; k < rp[i + 1] && !used; ++k) {
-            const int j = ci[k];
-            if (j == i || (j >= lo && j > i)) continue;
-            used = ((j >= lo && j < hi) ? col[j - lo] : colour[j]) == c;
-          }
-          if (!used) break;
-          ++c;
-        }
-      }
-      col[v] = c;
-      ++done;
-      cmax = max(cmax, c);
+  // Rows in ascending order; the lanes read one row's smaller in-tile
+  // neighbours together and OR their colours into the forbidden mask.
+  int cmax = -1;
+  for (int v = 0; v < nt; ++v) {
+    uint64_t m = 0;
+    bool bg = false;
+    for (int q = lptr[v] + lane; q < lptr[v + 1]; q += WAVE) {
+      const int cj = col[adj[q]];
+      if (cj < 64)
+        m |= 1ull << cj;
+      else
+        bg = true;
     }
-    left -= wave_sum(done);
+    unsigned lo32 = (unsigned)m, hi32 = (unsigned)(m >> 32);
+    lo32 = wave_or(lo32);
+    hi32 = wave_or(hi32);
+    m = ((uint64_t)hi32 << 32 | lo32) | mask[v];
+    bg = (__ballot(bg) != 0) || big[v] != 0;
+    int c;
+    if (!bg && m != ~0ull) {
+      c = (int)__builtin_ctzll(~m);
+    } else {  // colours beyond 63 among the neighbours: search directly
+      const int i = lo + v;
+      c = 0;
+      for (;;) {
+        bool used = false;
+        for (int k = rp[i] + lane; k < rp[i + 1]; k += WAVE) {
+          const int j = ci[k];
+          if (j == i || (j >= lo && j > i)) continue;
+          if (((j >= lo && j < hi) ? col[j - lo] : colour[j]) == c) used = true;
+        }
+        if (!__ballot(used)) break;
+        ++c;
+      }
+    }
+    if (lane == 0) col[v] = c;
+    cmax = max(cmax, c);
     __syncthreads();
   }
   for (int v = lane; v < nt; v += WAVE) colour[lo + v] = col[v];
   cmax = wave_max(cmax);
   if (lane == 0) atomicMax(maxcol, cmax);
+  __threadfence();
+  for (int q0 = tptr[t]; q0 < tptr[t + 1]; q0 += WAVE) {
+    const int q = q0 + lane;
+    bool rel = false;
+    int u = 0;
+    if (q < tptr[t + 1]) {
+      u = tadj[q];
+      if (tile_before(t, u, seed)) rel = atomicSub(&pending[u], 1) == 1;
+    }
+    const uint64_t m = __ballot(rel);
+    if (m) {
+      const int leader = (int)__builtin_ctzll(m);
+      int base = 0;
+      if (lane == leader) base = atomicAdd(next_cnt, __popcll(m));
+      base = __shfl(base, leader, WAVE);
+      if (rel) next[base + __popcll(m & lanemask_lt())] = u;
+    }
+  }
 }
 
 constexpr int CL_THREADS = 256;
@@ -1070,52 +1147,184 @@ __global__ void k_densify(int nL, const int* __restrict__ rp, const int* __restr
   for (int k = rp[i]; k < rp[i + 1]; ++k) D[(size_t)i * nL + ci[k]] = v[k];
 }
 
-// Right-looking dense Cholesky on the lower triangle, one workgroup.
-__global__ __launch_bounds__(1024) void k_cholesky(int n, double* D, int* fail) {
+// Blocked dense Cholesky A = L L^T and inverse A^-1 = L^-T L^-1 (FP64) with
+// 64x64 blocks.  D is row-major n x n; blocks past the edge are handled with
+// bounds checks (entries outside the matrix read as identity padding).
+constexpr int CB = 64;
+
+__device__ inline void load_block(const double* __restrict__ D, int n, int bi, int bj, double (*B)[CB + 1]) {
+  for (int q = threadIdx.x; q < CB * CB; q += blockDim.x) {
+    const int r = q / CB, c = q % CB, i = bi * CB + r, j = bj * CB + c;
+    B[r][c] = (i < n && j < n) ? D[(size_t)i * n + j] : (i == j ? 1.0 : 0.0);
+  }
+}
+__device__ inline void store_block(double* __restrict__ D, int n, int bi, int bj, double (*B)[CB + 1]) {
+  for (int q = threadIdx.x; q < CB * CB; q += blockDim.x) {
+    const int r = q / CB, c = q % CB, i = bi * CB + r, j = bj * CB + c;
+    if (i < n && j < n) D[(size_t)i * n + j] = B[r][c];
+  }
+}
+
+// Factor the diagonal block p in LDS (lower triangle).
+__global__ __launch_bounds__(256) void k_chol_diag(int n, int p, double* D, int* fail) {
+  __shared__ double B[CB][CB + 1];
   __shared__ double piv;
-  for (int k = 0; k < n; ++k) {
+  load_block(D, n, p, p, B);
+  __syncthreads();
+  for (int k = 0; k < CB; ++k) {
     if (threadIdx.x == 0) {
-      const double d = D[(size_t)k * n + k];
+      const double d = B[k][k];
       if (!(d > 0.0)) {
         *fail = 1;
         piv = 1.0;
       } else {
         piv = sqrt(d);
       }
-      D[(size_t)k * n + k] = piv;
+      B[k][k] = piv;
     }
     __syncthreads();
-    const double p = piv;
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) D[(size_t)i * n + k] = D[(size_t)i * n + k] / p;
+    for (int i = k + 1 + threadIdx.x; i < CB; i += blockDim.x) B[i][k] = B[i][k] / piv;
     __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
-      if (j <= i) D[(size_t)i * n + j] = D[(size_t)i * n + j] - D[(size_t)i * n + k] * D[(size_t)j * n + k];
+    for (int q = threadIdx.x; q < CB * CB; q += blockDim.x) {
+      const int i = q / CB, j = q % CB;
+      if (j > k && j <= i) B[i][j] = B[i][j] - B[i][k] * B[j][k];
     }
     __syncthreads();
   }
+  store_block(D, n, p, p, B);
 }
 
-// W = L^{-1} column by column (lower triangular).
-__global__ void k_trinv(int n, const double* __restrict__ L, double* __restrict__ W) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  for (int i = j; i < n; ++i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    for (int k = j; k < i; ++k) s = s - L[(size_t)i * n + k] * W[(size_t)k * n + j];
-    W[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+// Panel: L_ip = A_ip L_pp^{-T} for the block rows i > p (one workgroup each).
+__global__ __launch_bounds__(256) void k_chol_trsm(int n, int p, double* D) {
+  __shared__ double Lp[CB][CB + 1];
+  __shared__ double X[CB][CB + 1];
+  const int bi = p + 1 + blockIdx.x;
+  load_block(D, n, p, p, Lp);
+  load_block(D, n, bi, p, X);
+  __syncthreads();
+  if (threadIdx.x < CB) {
+    const int r = threadIdx.x;
+    for (int c = 0; c < CB; ++c) {
+      double v = X[r][c];
+      for (int k = 0; k < c; ++k) v = v - X[r][k] * Lp[c][k];
+      X[r][c] = v / Lp[c][c];
+    }
+  }
+  __syncthreads();
+  store_block(D, n, bi, p, X);
+}
+
+// Trailing update A_ij -= L_ip L_jp^T for p < j <= i (one workgroup per pair).
+__global__ __launch_bounds__(256) void k_chol_update(int n, int p, double* D) {
+  __shared__ double Li[CB][CB + 1];
+  __shared__ double Lj[CB][CB + 1];
+  const int m = gridDim.x;  // pairs are enumerated as (i, j) with i >= j over the trailing blocks
+  (void)m;
+  int q = blockIdx.x, bi = 0;
+  const int nt = (n + CB - 1) / CB - (p + 1);
+  while (q >= bi + 1) {
+    q -= bi + 1;
+    ++bi;
+  }
+  const int I = p + 1 + bi, J = p + 1 + q;
+  if (bi >= nt) return;
+  load_block(D, n, I, p, Li);
+  load_block(D, n, J, p, Lj);
+  __syncthreads();
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e / CB, c = e % CB, i = I * CB + r, j = J * CB + c;
+    if (i >= n || j >= n || (I == J && c > r)) continue;
+    double s = 0.0;
+    for (int k = 0; k < CB; ++k) s += Li[r][k] * Lj[c][k];
+    D[(size_t)i * n + j] -= s;
   }
 }
 
-// A^{-1} = W^T W, summed in ascending k from max(i,j): exactly symmetric.
-__global__ void k_wtw(int n, const double* __restrict__ W, double* __restrict__ Ainv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int k = max(i, j); k < n; ++k) s = s + W[(size_t)k * n + i] * W[(size_t)k * n + j];
-  Ainv[(size_t)j * n + i] = s;
+// W = L^{-1}: diagonal blocks W_ii = L_ii^{-1} (one workgroup each).
+__global__ __launch_bounds__(256) void k_trinv_diag(int n, const double* __restrict__ D, double* __restrict__ W) {
+  __shared__ double L[CB][CB + 1];
+  __shared__ double X[CB][CB + 1];
+  const int b = blockIdx.x;
+  load_block(D, n, b, b, L);
+  __syncthreads();
+  if (threadIdx.x < CB) {  // column c of the inverse by forward substitution
+    const int c = threadIdx.x;
+    for (int r = 0; r < CB; ++r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int k = c; k < r; ++k) v = v - L[r][k] * X[k][c];
+      X[r][c] = r < c ? 0.0 : v / L[r][r];
+    }
+  }
+  __syncthreads();
+  store_block(W, n, b, b, X);
+}
+
+// Block row i of W: W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj for j < i.
+__global__ __launch_bounds__(256) void k_trinv_row(int n, int bi, const double* __restrict__ D,
+                                                   double* __restrict__ W) {
+  __shared__ double A[CB][CB + 1];
+  __shared__ double Bm[CB][CB + 1];
+  __shared__ double S[CB][CB + 1];
+  const int bj = blockIdx.x;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) S[e / CB][e % CB] = 0.0;
+  for (int bk = bj; bk < bi; ++bk) {
+    __syncthreads();
+    load_block(D, n, bi, bk, A);
+    load_block(W, n, bk, bj, Bm);
+    __syncthreads();
+    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+      const int r = e / CB, c = e % CB;
+      double s = 0.0;
+      for (int k = 0; k < CB; ++k) s += A[r][k] * Bm[k][c];
+      S[r][c] += s;
+    }
+  }
+  __syncthreads();
+  load_block(W, n, bi, bi, A);
+  __syncthreads();
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e / CB, c = e % CB;
+    double s = 0.0;
+    for (int k = 0; k < CB; ++k) s += A[r][k] * S[k][c];
+    Bm[r][c] = -s;
+  }
+  __syncthreads();
+  store_block(W, n, bi, bj, Bm);
+}
+
+// A^-1 = W^T W: block (I, J), I >= J, sum over k >= I of W_kI^T W_kJ; written
+// to both (I, J) and (J, I) so the result is exactly symmetric.
+__global__ __launch_bounds__(256) void k_wtw_blocks(int n, const double* __restrict__ W, double* __restrict__ Ainv) {
+  __shared__ double Wi[CB][CB + 1];
+  __shared__ double Wj[CB][CB + 1];
+  int q = blockIdx.x, bi = 0;
+  while (q >= bi + 1) {
+    q -= bi + 1;
+    ++bi;
+  }
+  const int I = bi, J = q;
+  const int nb = (n + CB - 1) / CB;
+  double acc[CB * CB / 256];
+  for (int t = 0; t < CB * CB / 256; ++t) acc[t] = 0.0;
+  for (int bk = I; bk < nb; ++bk) {
+    __syncthreads();
+    load_block(W, n, bk, I, Wi);
+    load_block(W, n, bk, J, Wj);
+    __syncthreads();
+    for (int t = 0; t < CB * CB / 256; ++t) {
+      const int e = threadIdx.x + 256 * t, r = e / CB, c = e % CB;
+      double s = 0.0;
+      for (int k = 0; k < CB; ++k) s += Wi[k][r] * Wj[k][c];
+      acc[t] += s;
+    }
+  }
+  for (int t = 0; t < CB * CB / 256; ++t) {
+    const int e = threadIdx.x + 256 * t, r = e / CB, c = e % CB, i = I * CB + r, j = J * CB + c;
+    if (i < n && j < n && (I != J || c <= r)) {
+      Ainv[(size_t)i * n + j] = acc[t];
+      Ainv[(size_t)j * n + i] = acc[t];
+    }
+  }
 }
 
 // ============================================================== solve order
@@ -1347,8 +1556,20 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   const int ntiles = cdiv(n, T);
   L.colour = H.alloc<int>((size_t)n, s);
   DBuf cnt(4 * sizeof(int), s), w0((size_t)ntiles * sizeof(int), s), w1((size_t)ntiles * sizeof(int), s);
+  DBuf tcnt((size_t)ntiles * sizeof(int), s), pend((size_t)ntiles * sizeof(int), s),
+      tptr(((size_t)ntiles + 1) * sizeof(int), s);
   hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.colour, -1);
   AMG_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(int), s));
+  // tile graph
+  hipLaunchKernelGGL(k_tile_nbrs, dim3(ntiles), dim3(WAVE), 0, s, n, T, L.rowptr, L.colind, seed, nullptr, nullptr,
+                     tcnt.as<int>(), pend.as<int>(), cnt.as<int>());
+  exclusive_scan(tcnt.as<int>(), tptr.as<int>(), ntiles, s);
+  const int nadj = read1(tptr.as<int>() + ntiles, s);
+  DBuf tadj((size_t)std::max(nadj, 1) * sizeof(int), s);
+  hipLaunchKernelGGL(k_tile_nbrs, dim3(ntiles), dim3(WAVE), 0, s, n, T, L.rowptr, L.colind, seed, tptr.as<int>(),
+                     tadj.as<int>(), nullptr, nullptr, cnt.as<int>());
+  AMG_HIP(hipGetLastError());
+  if (read1(cnt.as<int>(), s)) fail(AMG_ERR_UNSUPPORTED, "a tile has more than 2048 neighbour tiles");
   DBuf mx(sizeof(int), s);
   AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_tile_nnz_max, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, n, T, ntiles, L.rowptr, mx.as<int>());
@@ -1356,22 +1577,25 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   const size_t shm = col_smem(T, Ecap);
   if (shm > 160 * 1024) fail(AMG_ERR_UNSUPPORTED, "colouring tile exceeds LDS; use smaller tile_rows");
   AMG_HIP(hipFuncSetAttribute((const void*)k_colour_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  int rounds = 0, remaining = ntiles;
-  const int* work = nullptr;
   int* bufs[2] = {w0.as<int>(), w1.as<int>()};
+  AMG_HIP(hipMemsetAsync(cnt.as<int>() + 2, 0, 2 * sizeof(int), s));
+  hipLaunchKernelGGL(k_ready0, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, ntiles, pend.as<int>(), bufs[1],
+                     cnt.as<int>() + 3);
+  int remaining = read1(cnt.as<int>() + 3, s), rounds = 0, coloured = 0;
+  const int* work = bufs[1];
   while (remaining > 0) {
     int* next = bufs[rounds & 1];
     int* next_cnt = cnt.as<int>() + 2 + (rounds & 1);
     AMG_HIP(hipMemsetAsync(next_cnt, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_colour_tiles, dim3(remaining), dim3(WAVE), shm, s, n, T, Ecap, work, next, next_cnt,
-                       L.rowptr, L.colind, seed, L.colour, cnt.as<int>() + 1);
+    hipLaunchKernelGGL(k_colour_tiles, dim3(remaining), dim3(WAVE), shm, s, n, T, work, next, next_cnt, L.rowptr,
+                       L.colind, tptr.as<int>(), tadj.as<int>(), pend.as<int>(), seed, L.colour, cnt.as<int>() + 1);
     AMG_HIP(hipGetLastError());
     ++rounds;
-    const int left = read1(next_cnt, s);
-    if (left >= remaining) fail(AMG_ERR_HIP, "colouring made no progress");
-    remaining = left;
+    coloured += remaining;
+    remaining = read1(next_cnt, s);
     work = next;
   }
+  if (coloured != ntiles) fail(AMG_ERR_HIP, "tile colouring did not reach every tile");
   const int C = read1(cnt.as<int>() + 1, s) + 1;
   if (C > 4096) fail(AMG_ERR_UNSUPPORTED, "more than 4096 colours");
   L.ncol = C;
@@ -1406,17 +1630,27 @@ void coarse_factor(Hierarchy& H, const Level& L, hipStream_t s) {
   const int n = L.n;
   H.nL = n;
   const size_t nn = (size_t)n * n;
+  const int nb = cdiv(n, CB);
   DBuf D(nn * sizeof(double), s), W(nn * sizeof(double), s), f(sizeof(int), s);
   AMG_HIP(hipMemsetAsync(D.p, 0, nn * sizeof(double), s));
   AMG_HIP(hipMemsetAsync(W.p, 0, nn * sizeof(double), s));
   AMG_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_densify, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.rowptr, L.colind, L.vals, D.as<double>());
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, n, D.as<double>(), f.as<int>());
+  for (int p = 0; p < nb; ++p) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, n, p, D.as<double>(), f.as<int>());
+    const int rest = nb - p - 1;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_chol_trsm, dim3(rest), dim3(256), 0, s, n, p, D.as<double>());
+      hipLaunchKernelGGL(k_chol_update, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, n, p, D.as<double>());
+    }
+  }
   AMG_HIP(hipGetLastError());
   if (read1(f.as<int>(), s)) fail(AMG_ERR_NOT_SPD, "coarsest-level Cholesky pivot <= 0");
-  hipLaunchKernelGGL(k_trinv, dim3(cdiv(n, 64)), dim3(64), 0, s, n, D.as<double>(), W.as<double>());
+  hipLaunchKernelGGL(k_trinv_diag, dim3(nb), dim3(256), 0, s, n, D.as<double>(), W.as<double>());
+  for (int bi = 1; bi < nb; ++bi)
+    hipLaunchKernelGGL(k_trinv_row, dim3(bi), dim3(256), 0, s, n, bi, D.as<double>(), W.as<double>());
   H.Ainv = H.alloc<double>(nn, s);
-  hipLaunchKernelGGL(k_wtw, dim3(cdiv(n, 64), n), dim3(64), 0, s, n, W.as<double>(), H.Ainv);
+  hipLaunchKernelGGL(k_wtw_blocks, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, n, W.as<double>(), H.Ainv);
   AMG_HIP(hipGetLastError());
 }
 

@@ -340,6 +340,12 @@ __global__ __launch_bounds__(256) void k_coarse_gemv(int n, const double* __rest
   if (lane == 0) x[i] = (Vout)s;
 }
 
+template <typename V>
+__global__ void k_zero(int n, V* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
 template <typename A, typename B>
 __global__ void k_convert(int n, const A* __restrict__ in, B* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -522,7 +528,7 @@ void vcycle(Hierarchy& H, int l, const V* b, V* x, hipStream_t s) {
     return;
   }
   const double vb = sizeof(V);
-  AMG_HIP(hipMemsetAsync(x, 0, (size_t)L.n * sizeof(V), s));
+  hipLaunchKernelGGL(k_zero<V>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, x);
   for (int k = 0; k < H.p.pre_sweeps; ++k) smooth<V>(H, l, b, x, s);
   Level& C = H.lev[l + 1];
   {

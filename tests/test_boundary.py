@@ -39,4 +39,24 @@ def test_params_struct_matches_header_defaults():
     assert (p.strength_threshold, p.isolated_threshold, p.agg_min, p.agg_max, p.agg_diameter) == (0.08, 1e-5, 8, 12, 3)
     assert (p.omega, p.coarse_max, p.max_levels, p.tile_rows) == (1.6, 500, 25, 512)
     assert (p.smoother, p.pre_sweeps, p.post_sweeps, p.vcycle_fp32, p.flexible) == (0, 1, 1, 0, -1)
-    assert ctypes.sizeof(A.Params) == 88
+    assert p.use_graphs == 1
+    assert ctypes.sizeof(A.Params) == 88  # 5 doubles + 12 int32 fields, 8-byte aligned
+
+
+def test_header_compiles_as_c_and_matches_ctypes_layout(tmp_path):
+    """The public header is plain C; the binding's structs have its layout."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "amg.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(amg_params), sizeof(amg_solve_info),'
+                   ' sizeof(amg_csr), offsetof(amg_params, use_graphs));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    sizes = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    from paper_1209_0960_amd import amg as A
+    assert sizes == [ctypes.sizeof(A.Params), ctypes.sizeof(A.SolveInfo), ctypes.sizeof(A.CSR),
+                     A.Params.use_graphs.offset]

@@ -1,0 +1,151 @@
+"""Parity at the benchmark sizes (128^3 and 256^3 lognormal systems) on outputs
+the oracle can compute piece by piece, plus properties that hold at any size.
+
+* strong / isolated flags of level 0: every entry against the oracle;
+* aggregates: sampled tiles aggregated by the oracle, compared with the GPU's
+  tile-local ids (global id minus the tile's first coarse id);
+* Galerkin rows of level 1 for the aggregates of sampled tiles, computed by the
+  oracle from its own aggregation of those tiles and their neighbour tiles;
+* colouring of level 0: the full oracle colouring (128^3) or the parity closed
+  form (256^3, aligned 8^3 Morton tiles);
+* the solve: true FP64 residual from an independent CPU product <= 1e-8 for
+  the mixed-precision and the FP64 path, and their solution difference.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import oracle as O
+from paper_1209_0960_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+T = 512
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1209_0960_amd import amg
+    amg.lib()
+    return amg
+
+
+_CACHE = {}
+
+
+def build(A, n):
+    if n not in _CACHE:
+        s = P.lognormal(n, seed=1)
+        rp, ci, v, b = A.to_device(s)
+        h = A.Hierarchy(rp, ci, v, keep_setup_data=1)
+        L0 = h.level(0)
+        L1 = h.level(1)
+        _CACHE[n] = (s, h, L0, L1, (rp, ci, v, b))
+    return _CACHE[n]
+
+
+def sample_tiles(ntiles, k, seed):
+    rng = np.random.default_rng(seed)
+    pick = set(rng.choice(ntiles, size=min(k, ntiles), replace=False).tolist())
+    pick.update({0, ntiles - 1})
+    return np.array(sorted(pick), np.int32)
+
+
+def tile_offsets(agg, n):
+    ntiles = (n + T - 1) // T
+    return np.array([agg[t * T:min((t + 1) * T, n)].min() for t in range(ntiles)] + [agg.max() + 1])
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_strength_all_rows(A, n):
+    s, h, L0, _, _ = build(A, n)
+    strong, iso = O.strength(s.rowptr, s.colind, s.vals, tile_rows=T)
+    assert np.array_equal(L0["strong"], strong)
+    assert np.array_equal(L0["iso"], iso)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_aggregates_sampled_tiles(A, n):
+    s, h, L0, _, _ = build(A, n)
+    tiles = sample_tiles((s.n + T - 1) // T, 40, seed=n)
+    loc, cnt = O.aggregate_tiles(s.rowptr, s.colind, L0["strong"], L0["iso"], tiles, tile_rows=T)
+    agg = L0["agg"]
+    offs = tile_offsets(agg, s.n)
+    for k, t in enumerate(tiles):
+        lo, hi = t * T, min((t + 1) * T, s.n)
+        assert offs[t + 1] - offs[t] == cnt[k], t
+        assert np.array_equal(agg[lo:hi] - offs[t], loc[lo:hi]), t
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_galerkin_rows_sampled(A, n):
+    """Level-1 rows of the aggregates of sampled tiles.  The oracle aggregates
+    each sampled tile and every tile holding a neighbour of its rows, forms the
+    coarse rows by its ordered sums, and names coarse columns (tile, local id);
+    the GPU row is mapped to the same names through its own tile offsets."""
+    s, h, L0, L1, _ = build(A, n)
+    ntiles = (s.n + T - 1) // T
+    agg = L0["agg"]
+    offs = tile_offsets(agg, s.n)
+    tiles = sample_tiles(ntiles, 6, seed=7 * n)
+    for t in tiles:
+        lo, hi = t * T, min((t + 1) * T, s.n)
+        cols = s.colind[s.rowptr[lo]:s.rowptr[hi]]
+        nbr_tiles = np.unique(cols // T).astype(np.int32)
+        loc, cnt = O.aggregate_tiles(s.rowptr, s.colind, L0["strong"], L0["iso"], nbr_tiles, tile_rows=T)
+        name = {}  # row -> (tile, local id) from the oracle
+        for i in range(lo, hi):
+            name[i] = (int(t), int(loc[i]))
+        for u in nbr_tiles:
+            for i in range(u * T, min((u + 1) * T, s.n)):
+                name[i] = (int(u), int(loc[i]))
+        # oracle coarse rows of tile t: ordered sums over members ascending, CSR order
+        rows = {}
+        for i in range(lo, hi):
+            I = name[i]
+            r = rows.setdefault(I, {})
+            for k in range(s.rowptr[i], s.rowptr[i + 1]):
+                J = name[int(s.colind[k])]
+                r[J] = r[J] + s.vals[k] if J in r else s.vals[k]
+        # GPU rows
+        for (tt, li), r in rows.items():
+            I = offs[tt] + li
+            a, b_ = L1["rowptr"][I], L1["rowptr"][I + 1]
+            gcols, gvals = L1["colind"][a:b_], L1["vals"][a:b_]
+            gt = np.searchsorted(offs, gcols, side="right") - 1
+            got = {(int(u), int(c - offs[u])): v for u, c, v in zip(gt, gcols, gvals)}
+            assert set(got) == set(r), (tt, li)
+            for J, val in r.items():
+                assert got[J] == val, (tt, li, J)
+
+
+def test_colouring_128_full(A):
+    s, h, L0, _, _ = build(A, 128)
+    c, k = O.colour(s.rowptr, s.colind, seed=0, tile_rows=T)
+    assert L0["ncolours"] == k and np.array_equal(L0["colour"], c)
+
+
+def test_colouring_256_parity_closed_form(A):
+    s, h, L0, _, _ = build(A, 256)
+    z, y, x = np.unravel_index(s.order, (256, 256, 256))
+    assert L0["ncolours"] == 2
+    assert np.array_equal(L0["colour"], ((x + y + z) % 2).astype(np.int32))
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_solve_true_residual_independent_product(A, n):
+    s, h, _, _, (rp, ci, v, b) = build(A, n)
+    M = sp.csr_matrix((s.vals, s.colind, s.rowptr), shape=(s.n, s.n))
+    sols = {}
+    for fp32 in (0, 1):
+        with A.Hierarchy(rp, ci, v, vcycle_fp32=fp32) as hh:
+            x, r = hh.solve(b, rtol=1e-8)
+            assert r.status == A.OK
+            xs = x.cpu().numpy()
+            res = np.linalg.norm(s.b - M @ xs) / np.linalg.norm(s.b)
+            assert res <= 1.01e-8, (fp32, res)
+            assert abs(res - r.true_rel_residual) <= 1e-3 * res + 1e-14
+            sols[fp32] = xs
+    d = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[0])
+    assert d <= 1e-6

@@ -209,3 +209,30 @@ def test_not_converged_keeps_last_iterate(A):
         o = O.Hierarchy(s.rowptr, s.colind, s.vals).pcg(s.b, rtol=1e-14, maxit=3)
         assert o["status"] == O.NOT_CONVERGED
         assert rel(x.cpu().numpy(), o["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_graph_replays_match_eager(A, fp32):
+    """Each CG iteration replayed from a captured HIP graph gives bit-identical
+    iterates to the eager launches, over repeated solves on one hierarchy with
+    eager work in between."""
+    s = system("hetero_24")
+    rp, ci, v, b = dev(s)
+    maxit = 100
+    runs = []
+    for graphs in (0, 1):
+        with A.Hierarchy(rp, ci, v, use_graphs=graphs, vcycle_fp32=fp32) as h:
+            hists = []
+            for rep in range(3):
+                hist = torch.zeros((maxit + 1) * s.n, dtype=torch.float64, device="cuda")
+                x, r = h.solve(b, maxit=maxit, iter_hist=hist)
+                assert r.status == A.OK
+                z = h.precond(b)  # eager work between replays
+                torch.cuda.synchronize()
+                hists.append((hist.cpu().numpy()[:(r.iterations + 1) * s.n], x.cpu().numpy(), z.cpu().numpy()))
+            runs.append(hists)
+    ref = runs[0][0]
+    for hists in runs:
+        for h in hists:
+            for a, c in zip(h, ref):
+                assert np.array_equal(a, c)
