@@ -122,17 +122,68 @@ AMG_API amg_status amg_precond_apply(amg_hierarchy *h, const double *r, double *
  * when ||r_k||_2 <= rtol ||r_0||_2 (recursive residual) or after maxit
  * iterations (then AMG_ERR_NOT_CONVERGED with x = last iterate and *info
  * filled).  Blocks until done.  The iterations run on a stream owned by the
- * hierarchy, ordered after the caller's earlier work on `stream`; with
- * use_graphs each iteration is one replay of a captured HIP graph.  Calls on
- * one hierarchy must not overlap.
+ * hierarchy's solve context (created on first use), ordered after the
+ * caller's earlier work on `stream`; with use_graphs each iteration from the
+ * second on is one replay of a captured HIP graph.  Calls on one hierarchy
+ * (pcg_solve, amg_precond_apply) must not overlap.
  *   info      host, nullable
  *   res_hist  host, nullable, maxit+1 doubles: ||r_k||/||r_0||
  *   iter_hist device, nullable, n*(maxit+1) doubles: x_k for k = 0.. */
 AMG_API amg_status pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
                      amg_solve_info *info, double *res_hist, double *iter_hist, void *stream);
 
-/* Releases everything the hierarchy owns.  NULL-safe. */
+/* Releases everything the hierarchy owns.  NULL-safe.  The hierarchy must not
+ * be part of a running batch entry (amg_batch_submit). */
 AMG_API void amg_free(amg_hierarchy *h);
+
+/* ---- many systems -------------------------------------------------------- */
+/* Builds the hierarchies of nsys independent systems A[0..nsys) with one
+ * parameter set (each system as in amg_setup).  The setups run concurrently
+ * (host threads, one stream each) and overlap on the device.  Blocks until
+ * all are complete.  out: host array of nsys handles; on failure every handle
+ * is NULL and the status is that of the first failing system. */
+AMG_API amg_status amg_setup_batched(const amg_csr *A, int32_t nsys, const amg_params *p, void *stream,
+                                     amg_hierarchy **out);
+
+/* Solves nsys systems with nrhs right-hand sides each (nrhs = 1, 2, 4 or 8)
+ * by (flexible) preconditioned CG as in pcg_solve, all of them advanced
+ * together: every step is one launch per kernel for all systems (the V-cycle
+ * level by level, the CG vector updates), so the matrix of a system is read
+ * once for its nrhs right-hand sides.  b[s] and x[s] are device arrays of
+ * nrhs * n_s doubles, right-hand side k at offset k * n_s; x[s] holds x0 on
+ * entry.  Each right-hand side stops at its own convergence (its iterate is
+ * then frozen); its result equals that of pcg_solve alone bit for bit when
+ * nrhs = 1 (and has the same arithmetic for any nrhs).  The hierarchies must
+ * share vcycle_fp32, smoother, sweeps and the CG variant.  info: host, nullable,
+ * nsys * nrhs records (system-major).  Returns AMG_OK if every right-hand side
+ * converged, else AMG_ERR_BREAKDOWN or AMG_ERR_NOT_CONVERGED.  Blocks. */
+AMG_API amg_status pcg_solve_batched(amg_hierarchy *const *h, int32_t nsys, int32_t nrhs, const double *const *b,
+                                     double *const *x, double rtol, int32_t maxit, amg_solve_info *info,
+                                     void *stream);
+
+/* ---- continuous batching ------------------------------------------------- */
+/* A batch holds up to max_entries running solves (entries) of nrhs
+ * right-hand sides each.  amg_batch_submit adds a solve of hierarchy h
+ * (vectors as in pcg_solve_batched, ordered after earlier work on `stream`);
+ * it joins the running ones at the next step.  amg_batch_step performs
+ * `iterations` CG iterations of every running entry; entries that finish are
+ * completed (true residual computed, x written) inside the step and reported
+ * by amg_batch_poll (tags, status, info: host, nrhs records per entry, up to
+ * cap entries, *count returned).  An entry's arithmetic does not depend on
+ * the other entries.  Submitting to a full batch returns AMG_ERR_INVALID_ARG.
+ * One host thread per batch. */
+typedef struct amg_batch amg_batch;
+AMG_API amg_status amg_batch_create(int32_t nrhs, int32_t max_entries, int32_t use_graphs, amg_batch **out);
+AMG_API amg_status amg_batch_submit(amg_batch *b, amg_hierarchy *h, const double *rhs, double *x, double rtol,
+                                    int32_t maxit, int64_t tag, void *stream);
+AMG_API amg_status amg_batch_step(amg_batch *b, int32_t iterations);
+AMG_API amg_status amg_batch_poll(amg_batch *b, int64_t *tags, amg_status *status, amg_solve_info *info,
+                                  int32_t cap, int32_t *count);
+/* Entries submitted and not yet polled-out as finished. */
+AMG_API amg_status amg_batch_active(const amg_batch *b, int32_t *active);
+/* Device bytes of the running entries' vectors. */
+AMG_API amg_status amg_batch_bytes(const amg_batch *b, size_t *bytes);
+AMG_API void amg_batch_free(amg_batch *b);
 
 /* ---- support ---------------------------------------------------------- */
 AMG_API const char *amg_status_string(amg_status s);
@@ -177,7 +228,8 @@ enum {
   AMG_KIND_PROLONG = 3,       /* level-0 prolongation                            */
   AMG_KIND_CG_VEC = 4,        /* CG vector updates and dot products              */
   AMG_KIND_COARSE_LEVELS = 5, /* every launch of levels >= 1                     */
-  AMG_KIND_COUNT = 6
+  AMG_KIND_OTHER = 6,         /* level-0 fills (iterate set to zero)             */
+  AMG_KIND_COUNT = 7
 };
 AMG_API amg_status amg_set_kernel_timing(int32_t kind_mask);
 AMG_API amg_status amg_get_kernel_timing(int32_t kind, double *ms, int64_t *launches, double *bytes);

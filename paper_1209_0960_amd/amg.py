@@ -26,7 +26,7 @@ ERR_INVALID_ARG, ERR_BAD_DIAGONAL, ERR_NOT_SYMMETRIC, ERR_NOT_SPD = 1, 2, 3, 4
 ERR_COARSENING_STALLED, ERR_OUT_OF_MEMORY, ERR_BREAKDOWN, ERR_NOT_CONVERGED = 5, 6, 7, 8
 ERR_HIP, ERR_UNSUPPORTED = 9, 10
 SMOOTHER_MCSGS, SMOOTHER_L1_JACOBI = 0, 1
-KIND_SPMV_F64, KIND_SWEEP, KIND_RESTRICT, KIND_PROLONG, KIND_CG_VEC, KIND_COARSE_LEVELS = range(6)
+KIND_SPMV_F64, KIND_SWEEP, KIND_RESTRICT, KIND_PROLONG, KIND_CG_VEC, KIND_COARSE_LEVELS, KIND_OTHER = range(7)
 
 
 class AMGError(RuntimeError):
@@ -101,6 +101,26 @@ def lib():
                                             C.POINTER(C.c_double)]
         L.amg_reset_kernel_timing.restype = st
         L.amg_reset_kernel_timing.argtypes = []
+        L.amg_setup_batched.restype = st
+        L.amg_setup_batched.argtypes = [C.POINTER(CSR), i32, C.POINTER(Params), vp, C.POINTER(vp)]
+        L.pcg_solve_batched.restype = st
+        L.pcg_solve_batched.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(vp), C.POINTER(vp), C.c_double, i32,
+                                        C.POINTER(SolveInfo), vp]
+        L.amg_batch_create.restype = st
+        L.amg_batch_create.argtypes = [i32, i32, i32, C.POINTER(vp)]
+        L.amg_batch_submit.restype = st
+        L.amg_batch_submit.argtypes = [vp, vp, vp, vp, C.c_double, i32, C.c_int64, vp]
+        L.amg_batch_step.restype = st
+        L.amg_batch_step.argtypes = [vp, i32]
+        L.amg_batch_poll.restype = st
+        L.amg_batch_poll.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(SolveInfo), i32,
+                                     C.POINTER(i32)]
+        L.amg_batch_active.restype = st
+        L.amg_batch_active.argtypes = [vp, C.POINTER(i32)]
+        L.amg_batch_bytes.restype = st
+        L.amg_batch_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.amg_batch_free.restype = None
+        L.amg_batch_free.argtypes = [vp]
         _LIB = L
     return _LIB
 
@@ -144,6 +164,96 @@ def amg_setup(rowptr: torch.Tensor, colind: torch.Tensor, vals: torch.Tensor, pa
     h = C.c_void_p()
     _check(lib().amg_setup(C.byref(A), C.byref(p), _stream(stream), C.byref(h)))
     return h
+
+
+def _csr(rowptr, colind, vals) -> CSR:
+    if rowptr.dtype != torch.int32 or colind.dtype != torch.int32 or vals.dtype != torch.float64:
+        raise TypeError("CSR must be int32/int32/float64")
+    return CSR(rowptr.numel() - 1, colind.numel(), _ptr(rowptr), _ptr(colind), _ptr(vals))
+
+
+def amg_setup_batched(systems, params: Params | None = None, stream=None) -> list:
+    """amg_setup_batched over a list of (rowptr, colind, vals) device tensors; returns the handles."""
+    arr = (CSR * len(systems))(*[_csr(*s) for s in systems])
+    out = (C.c_void_p * len(systems))()
+    p = params if params is not None else default_params()
+    _check(lib().amg_setup_batched(arr, len(systems), C.byref(p), _stream(stream), out))
+    return [C.c_void_p(h) for h in out]
+
+
+def pcg_solve_batched(handles, bs, xs, nrhs: int = 1, rtol: float = 1e-8, maxit: int = 1000, stream=None):
+    """pcg_solve_batched: bs[s], xs[s] hold nrhs * n_s values (right-hand side k
+    at k * n_s).  Returns (status, list of nsys lists of nrhs info dicts)."""
+    ns = len(handles)
+    hs = (C.c_void_p * ns)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    bp = (C.c_void_p * ns)(*[b.data_ptr() for b in bs])
+    xp = (C.c_void_p * ns)(*[x.data_ptr() for x in xs])
+    for t in list(bs) + list(xs):
+        _ptr(t)
+    info = (SolveInfo * (ns * nrhs))()
+    st = lib().pcg_solve_batched(hs, ns, nrhs, bp, xp, rtol, maxit, info, _stream(stream))
+    if st not in (OK, ERR_NOT_CONVERGED):
+        _check(st)
+    return st, [[_info_dict(info[s * nrhs + k]) for k in range(nrhs)] for s in range(ns)]
+
+
+def _info_dict(i: SolveInfo) -> dict:
+    return dict(iterations=i.iterations, converged=bool(i.converged), levels=i.levels, rel_residual=i.rel_residual,
+                true_rel_residual=i.true_rel_residual, setup_ms=i.setup_ms, solve_ms=i.solve_ms)
+
+
+class Batch:
+    """Continuous batching of CG solves (amg_batch_*): submit, step, poll."""
+
+    def __init__(self, nrhs: int = 1, max_entries: int = 64, use_graphs: bool = True):
+        self.nrhs = nrhs
+        self.b = C.c_void_p()
+        _check(lib().amg_batch_create(nrhs, max_entries, 1 if use_graphs else 0, C.byref(self.b)))
+
+    def submit(self, h, rhs: torch.Tensor, x: torch.Tensor, rtol=1e-8, maxit=1000, tag=0, stream=None):
+        hh = h.h if isinstance(h, Hierarchy) else h
+        _check(lib().amg_batch_submit(self.b, hh, _ptr(rhs), _ptr(x), rtol, maxit, tag, _stream(stream)))
+
+    def step(self, iterations: int = 1):
+        _check(lib().amg_batch_step(self.b, iterations))
+
+    def poll(self, cap: int = 256) -> list:
+        tags = (C.c_int64 * cap)()
+        sts = (C.c_int * cap)()
+        info = (SolveInfo * (cap * self.nrhs))()
+        cnt = C.c_int32()
+        _check(lib().amg_batch_poll(self.b, tags, sts, info, cap, C.byref(cnt)))
+        return [(tags[i], sts[i], [_info_dict(info[i * self.nrhs + k]) for k in range(self.nrhs)])
+                for i in range(cnt.value)]
+
+    @property
+    def active(self) -> int:
+        a = C.c_int32()
+        _check(lib().amg_batch_active(self.b, C.byref(a)))
+        return a.value
+
+    @property
+    def bytes(self) -> int:
+        v = C.c_size_t()
+        _check(lib().amg_batch_bytes(self.b, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            try:
+                lib().amg_batch_free(self.b)
+            except TypeError:
+                pass
+            self.b = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def amg_precond_apply(h, r: torch.Tensor, z: torch.Tensor, stream=None):
@@ -218,6 +328,18 @@ class Hierarchy:
         self.params = default_params(**params)
         self.n = rowptr.numel() - 1
         self.h = amg_setup(rowptr, colind, vals, self.params, stream)
+
+    @classmethod
+    def batched(cls, systems, stream=None, **params) -> list:
+        """amg_setup_batched over [(rowptr, colind, vals), ...]."""
+        p = default_params(**params)
+        hs = amg_setup_batched(systems, p, stream)
+        out = []
+        for (rp, _, _), h in zip(systems, hs):
+            o = cls.__new__(cls)
+            o.params, o.n, o.h = p, rp.numel() - 1, h
+            out.append(o)
+        return out
 
     def close(self):
         if getattr(self, "h", None):

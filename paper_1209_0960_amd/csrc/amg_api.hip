@@ -4,7 +4,9 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <thread>
 
 #include "amg_internal.h"
 
@@ -73,24 +75,12 @@ void Hierarchy::free_one(void* ptr, hipStream_t s) {
 }
 
 void Hierarchy::release(hipStream_t s) {
-  if (iter_exec) {
-    (void)hipGraphExecDestroy(iter_exec);
-    iter_exec = nullptr;
+  if (single) {  // its launch tables and graph refer to the arrays below
+    batch_destroy(single);
+    single = nullptr;
   }
   for (auto& o : owned) dfree(o.first, s);
   owned.clear();
-  if (ev_in) (void)hipEventDestroy(ev_in);
-  if (ev_out) (void)hipEventDestroy(ev_out);
-  ev_in = ev_out = nullptr;
-  if (work) {
-    (void)hipStreamSynchronize(work);
-    (void)hipStreamDestroy(work);
-    work = nullptr;
-  }
-  if (host_scal) {
-    (void)hipHostFree(host_scal);
-    host_scal = nullptr;
-  }
   bytes = 0;
 }
 
@@ -155,6 +145,10 @@ struct amg_hierarchy {
   Hierarchy H;
 };
 
+struct amg_batch {
+  Batch* B = nullptr;
+};
+
 namespace {
 
 template <typename F>
@@ -184,6 +178,7 @@ void check_params(const amg_params& p) {
   if (p.agg_diameter < 1) fail(AMG_ERR_INVALID_ARG, "agg_diameter");
   if (p.tile_rows < 64 || p.tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "tile_rows outside 64..1024");
   if (p.coarse_max < 1 || p.max_levels < 1) fail(AMG_ERR_INVALID_ARG, "coarse_max/max_levels");
+  if (p.max_levels > MAX_LEVELS) fail(AMG_ERR_UNSUPPORTED, "max_levels above 32");
   if (p.smoother != AMG_SMOOTHER_MCSGS && p.smoother != AMG_SMOOTHER_L1_JACOBI) fail(AMG_ERR_INVALID_ARG, "smoother");
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
 }
@@ -283,186 +278,14 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
         L.sval = nullptr;
       }
     }
-    if (f32)
-      L.t32 = H.alloc<float>((size_t)L.n, s);
-    else
-      L.t64 = H.alloc<double>((size_t)L.n, s);
-    if (l > 0 || f32) {
-      if (f32) {
-        L.x32 = H.alloc<float>((size_t)L.n, s);
-        L.b32 = H.alloc<float>((size_t)L.n, s);
-      } else {
-        L.x64 = H.alloc<double>((size_t)L.n, s);
-        L.b64 = H.alloc<double>((size_t)L.n, s);
-      }
-    }
   }
   {
     Level& C = H.lev[Lc];
     if (C.n > 4096) fail(AMG_ERR_COARSENING_STALLED, "coarsest level has " + std::to_string(C.n) + " rows");
-    if (Lc > 0 || f32) {
-      if (f32) {
-        C.x32 = H.alloc<float>((size_t)C.n, s);
-        C.b32 = H.alloc<float>((size_t)C.n, s);
-      } else {
-        C.x64 = H.alloc<double>((size_t)C.n, s);
-        C.b64 = H.alloc<double>((size_t)C.n, s);
-      }
-    }
     coarse_factor(H, C, s);
   }
-  const int n0 = H.lev[0].n;
-  H.r = H.alloc<double>((size_t)n0, s);
-  H.z = H.alloc<double>((size_t)n0, s);
-  H.pv = H.alloc<double>((size_t)n0, s);
-  H.q = H.alloc<double>((size_t)n0, s);
-  H.bp = H.alloc<double>((size_t)n0, s);
-  H.xp = H.alloc<double>((size_t)n0, s);
-  if (H.flexible) H.rold = H.alloc<double>((size_t)n0, s);
-  H.partial = H.alloc<double>(2 * (size_t)RED_BLOCKS, s);
-  H.scal = H.alloc<double>(S_COUNT, s);
-  AMG_HIP(hipHostMalloc((void**)&H.host_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
-  AMG_HIP(hipStreamCreateWithFlags(&H.work, hipStreamNonBlocking));
-  AMG_HIP(hipEventCreateWithFlags(&H.ev_in, hipEventDisableTiming));
-  AMG_HIP(hipEventCreateWithFlags(&H.ev_out, hipEventDisableTiming));
   AMG_HIP(hipStreamSynchronize(s));
   H.setup_ms = now_ms() - t0;
-}
-
-void read_scal(Hierarchy& H, hipStream_t s) {
-  AMG_HIP(hipMemcpyAsync(H.host_scal, H.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
-}
-
-// The part of a CG iteration after the convergence test of iteration k and
-// up to that of iteration k+1: z = M r, beta and the new direction, then
-// q = A p, alpha, the x/r update and ||r||^2.
-void iteration_body(Hierarchy& H, hipStream_t s) {
-  Level& L0 = H.lev[0];
-  const int n = L0.n;
-  double* const rold = H.flexible ? H.rold : nullptr;
-  precond_apply(H, H.r, H.z, s);
-  cg_dots_rz(n, H.r, H.z, rold, H.partial, s);
-  finish(H.partial, RED_BLOCKS, H.scal, S_RZ, H.flexible ? FIN_BETA_FCG : FIN_BETA_PCG, s);
-  cg_update_p(n, H.pv, H.z, H.scal, s);
-  spmv64(L0, H.pv, H.q, H.partial, s, AMG_KIND_SPMV_F64);
-  finish(H.partial, RED_BLOCKS, H.scal, S_PQ, FIN_ALPHA, s);
-  cg_update_xr(n, H.xp, H.r, rold, H.pv, H.q, H.scal, H.partial, s);
-  finish(H.partial, RED_BLOCKS, H.scal, S_RR, FIN_STORE, s);
-}
-
-void run_iteration(Hierarchy& H, hipStream_t s) {
-  // Per-kernel event timing records events around individual launches, so it
-  // runs the iteration eagerly (the kernels are the same as in the graph).
-  const int mask = g_timing_mask_for_graphs();
-  if (!H.p.use_graphs || mask != 0) {
-    iteration_body(H, s);
-    return;
-  }
-  if (!H.iter_exec) {
-    hipGraph_t g = nullptr;
-    AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    try {
-      iteration_body(H, s);
-    } catch (...) {
-      (void)hipStreamEndCapture(s, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    AMG_HIP(hipStreamEndCapture(s, &g));
-    hipError_t e = hipGraphInstantiate(&H.iter_exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    AMG_HIP(e);
-  }
-  AMG_HIP(hipGraphLaunch(H.iter_exec, s));
-}
-
-amg_status pcg_impl(Hierarchy& H, const double* b_user, double* x_user, double rtol, int maxit,
-                    amg_solve_info* info, double* res_hist, double* iter_hist, hipStream_t us) {
-  const double t0 = now_ms();
-  Level& L0 = H.lev[0];
-  const int n = L0.n;
-  hipStream_t s = H.work;
-  AMG_HIP(hipEventRecord(H.ev_in, us));
-  AMG_HIP(hipStreamWaitEvent(s, H.ev_in, 0));
-  // The iteration runs in the level-0 solve order.
-  const int* perm0 = L0.perm;
-  double* const b = H.bp;
-  double* const x = H.xp;
-  double* const r = H.r;
-  double* const z = H.z;
-  double* const p = H.pv;
-  double* const q = H.q;
-  double* const rold = H.flexible ? H.rold : nullptr;
-  double* const part = H.partial;
-  double* const scal = H.scal;
-  gather(n, perm0, b_user, b, s);
-  gather(n, perm0, x_user, x, s);
-  AMG_HIP(hipMemsetAsync(scal, 0, S_COUNT * sizeof(double), s));
-  residual64(L0, b, x, r, part, s);
-  finish(part, RED_BLOCKS, scal, S_R0, FIN_STORE, s);
-  if (iter_hist) scatter(n, perm0, x, iter_hist, s);
-  read_scal(H, s);
-  const double r0 = std::sqrt(H.host_scal[S_R0]);
-  if (res_hist) res_hist[0] = 1.0;
-  int it = 0;
-  amg_status st = AMG_ERR_NOT_CONVERGED;
-  double rel = r0 > 0.0 ? 1.0 : 0.0;
-  if (r0 == 0.0) {
-    st = AMG_OK;
-  } else if (maxit > 0) {
-    precond_apply(H, r, z, s);
-    AMG_HIP(hipMemcpyAsync(p, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    dot_partial(n, r, z, part, s);
-    finish(part, RED_BLOCKS, scal, S_RHO, FIN_RHO_INIT, s);
-    spmv64(L0, p, q, part, s, AMG_KIND_SPMV_F64);
-    finish(part, RED_BLOCKS, scal, S_PQ, FIN_ALPHA, s);
-    cg_update_xr(n, x, r, rold, p, q, scal, part, s);
-    finish(part, RED_BLOCKS, scal, S_RR, FIN_STORE, s);
-    read_scal(H, s);
-    for (int k = 1;; ++k) {
-      if (H.host_scal[S_FLAG] != 0.0) {
-        st = AMG_ERR_BREAKDOWN;
-        break;
-      }
-      it = k;
-      rel = std::sqrt(H.host_scal[S_RR]) / r0;
-      if (res_hist) res_hist[k] = rel;
-      if (iter_hist) scatter(n, perm0, x, iter_hist + (size_t)k * n, s);
-      if (rel <= rtol) {
-        st = AMG_OK;
-        break;
-      }
-      if (k == maxit) break;
-      run_iteration(H, s);
-      read_scal(H, s);
-
-    }
-  }
-  scatter(n, perm0, x, x_user, s);
-  // true residual ||b - A x|| / ||b||
-  residual64(L0, b, x, q, part, s);
-  finish(part, RED_BLOCKS, scal, S_TMP, FIN_STORE, s);
-  read_scal(H, s);
-  const double rn = std::sqrt(H.host_scal[S_TMP]);
-  dot_partial(n, b, b, part, s);
-  finish(part, RED_BLOCKS, scal, S_TMP, FIN_STORE, s);
-  read_scal(H, s);
-  const double bn = std::sqrt(H.host_scal[S_TMP]);
-  AMG_HIP(hipEventRecord(H.ev_out, s));
-  AMG_HIP(hipStreamWaitEvent(us, H.ev_out, 0));
-  if (info) {
-    info->iterations = it;
-    info->converged = st == AMG_OK ? 1 : 0;
-    info->levels = (int)H.lev.size();
-    info->rel_residual = rel;
-    info->true_rel_residual = bn > 0.0 ? rn / bn : 0.0;
-    info->setup_ms = H.setup_ms;
-    info->solve_ms = now_ms() - t0;
-  }
-  if (st == AMG_ERR_NOT_CONVERGED) set_error("maximum number of iterations reached");
-  if (st == AMG_ERR_BREAKDOWN) set_error("CG breakdown (p^T A p <= 0 or r^T z <= 0)");
-  return st;
 }
 
 }  // namespace
@@ -523,13 +346,7 @@ amg_status amg_precond_apply(amg_hierarchy* h, const double* r, double* z, void*
     set_error("invalid argument");
     return AMG_ERR_INVALID_ARG;
   }
-  return guarded([&] {
-    Hierarchy& H = h->H;
-    const int n = H.lev[0].n;
-    gather(n, H.lev[0].perm, r, H.bp, S(stream));
-    precond_apply(H, H.bp, H.xp, S(stream));
-    scatter(n, H.lev[0].perm, H.xp, z, S(stream));
-  });
+  return guarded([&] { precond_run(h->H, r, z, S(stream)); });
 }
 
 amg_status pcg_solve(amg_hierarchy* h, const double* b, double* x, double rtol, int32_t maxit, amg_solve_info* info,
@@ -539,7 +356,7 @@ amg_status pcg_solve(amg_hierarchy* h, const double* b, double* x, double rtol, 
     return AMG_ERR_INVALID_ARG;
   }
   amg_status st = AMG_OK;
-  amg_status g = guarded([&] { st = pcg_impl(h->H, b, x, rtol, maxit, info, res_hist, iter_hist, S(stream)); });
+  amg_status g = guarded([&] { st = pcg_run(h->H, b, x, rtol, maxit, info, res_hist, iter_hist, S(stream)); });
   return g != AMG_OK ? g : st;
 }
 
@@ -684,6 +501,148 @@ amg_status amg_copy_level(const amg_hierarchy* h, int32_t l, int32_t* agg, int32
       }
     }
   });
+}
+
+amg_status amg_setup_batched(const amg_csr* A, int32_t nsys, const amg_params* p, void* stream,
+                             amg_hierarchy** out) {
+  if (!out || !A || !p || nsys < 1) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  for (int i = 0; i < nsys; ++i) out[i] = nullptr;
+  // Setups are independent and end in host synchronisations (level sizes,
+  // colour counts), so several run at once, each from its own host thread on
+  // its own stream; their kernels overlap on the device.
+  hipStream_t us = S(stream);
+  if (hipStreamSynchronize(us) != hipSuccess) {
+    set_error("caller stream failed");
+    return AMG_ERR_HIP;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int nthreads = std::max(1, std::min<int>(nsys, 8));
+  std::atomic<int> next{0};
+  std::vector<amg_status> st(nsys, AMG_OK);
+  std::vector<std::string> msg(nsys);
+  auto worker = [&]() {
+    (void)hipSetDevice(dev);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    for (int i = next++; i < nsys; i = next++) {
+      if (!s) {
+        st[i] = AMG_ERR_HIP;
+        msg[i] = "stream creation failed";
+        continue;
+      }
+      st[i] = amg_setup(&A[i], p, s, &out[i]);
+      if (st[i] != AMG_OK) msg[i] = amg_last_error();
+      if (out[i]) out[i]->H.setup_stream = us;
+    }
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(worker);
+  } catch (...) {
+  }
+  worker();
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < nsys; ++i)
+    if (st[i] != AMG_OK) {
+      for (int j = 0; j < nsys; ++j) {
+        amg_free(out[j]);
+        out[j] = nullptr;
+      }
+      set_error("system " + std::to_string(i) + ": " + msg[i]);
+      return st[i];
+    }
+  return AMG_OK;
+}
+
+amg_status pcg_solve_batched(amg_hierarchy* const* h, int32_t nsys, int32_t nrhs, const double* const* b,
+                             double* const* x, double rtol, int32_t maxit, amg_solve_info* info, void* stream) {
+  if (!h || !b || !x || nsys < 1 || maxit < 0 || !(rtol >= 0.0)) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  std::vector<Hierarchy*> hs(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    if (!h[i] || !b[i] || !x[i]) {
+      set_error("NULL hierarchy or vector for system " + std::to_string(i));
+      return AMG_ERR_INVALID_ARG;
+    }
+    hs[i] = &h[i]->H;
+  }
+  amg_status st = AMG_OK;
+  amg_status g = guarded([&] { st = pcg_batched_run(hs.data(), nsys, nrhs, b, x, rtol, maxit, info, S(stream)); });
+  return g != AMG_OK ? g : st;
+}
+
+amg_status amg_batch_create(int32_t nrhs, int32_t max_entries, int32_t use_graphs, amg_batch** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return AMG_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  amg_batch* b = nullptr;
+  amg_status st = guarded([&] {
+    b = new amg_batch();
+    b->B = batch_new(nrhs, max_entries, use_graphs);
+  });
+  if (st != AMG_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return AMG_OK;
+}
+
+amg_status amg_batch_submit(amg_batch* b, amg_hierarchy* h, const double* rhs, double* x, double rtol,
+                            int32_t maxit, int64_t tag, void* stream) {
+  if (!b || !h || !rhs || !x || maxit < 0 || !(rtol >= 0.0)) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  return guarded([&] { (void)batch_submit(*b->B, h->H, rhs, x, rtol, maxit, tag, S(stream)); });
+}
+
+amg_status amg_batch_step(amg_batch* b, int32_t iterations) {
+  if (!b || iterations < 0) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  return guarded([&] { batch_step(*b->B, iterations); });
+}
+
+amg_status amg_batch_poll(amg_batch* b, int64_t* tags, amg_status* status, amg_solve_info* info, int32_t cap,
+                          int32_t* count) {
+  if (!b || !count || cap < 0) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  *count = batch_poll(*b->B, tags, status, info, cap);
+  return AMG_OK;
+}
+
+amg_status amg_batch_active(const amg_batch* b, int32_t* active) {
+  if (!b || !active) return AMG_ERR_INVALID_ARG;
+  *active = batch_active(*b->B);
+  return AMG_OK;
+}
+
+amg_status amg_batch_bytes(const amg_batch* b, size_t* bytes) {
+  if (!b || !bytes) return AMG_ERR_INVALID_ARG;
+  *bytes = batch_entry_bytes(*b->B);
+  return AMG_OK;
+}
+
+void amg_batch_free(amg_batch* b) {
+  if (!b) return;
+  batch_destroy(b->B);
+  delete b;
 }
 
 amg_status amg_set_kernel_timing(int32_t kind_mask) {

@@ -132,14 +132,9 @@ struct Level {
   // optional setup data (natural order)
   uint8_t* strong = nullptr;
   uint8_t* iso = nullptr;
-  // V-cycle work vectors (precision of the cycle, solve order)
-  double* x64 = nullptr;
-  double* b64 = nullptr;
-  double* t64 = nullptr;
-  float* x32 = nullptr;
-  float* b32 = nullptr;
-  float* t32 = nullptr;
 };
+
+struct Batch;
 
 struct Hierarchy {
   amg_params p{};
@@ -147,17 +142,10 @@ struct Hierarchy {
   std::vector<Level> lev;
   int nL = 0;
   double* Ainv = nullptr;  // dense inverse of the coarsest matrix (FP64, symmetric)
-  // CG work space
-  double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *rold = nullptr;
-  double *bp = nullptr, *xp = nullptr;  // level-0 right-hand side / iterate in solve order
-  double* partial = nullptr;  // reduction partials
-  double* scal = nullptr;     // device scalars
-  double* host_scal = nullptr;  // pinned
   double setup_ms = 0.0;
-  // solve stream and the captured CG iteration
-  hipStream_t work = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  hipGraphExec_t iter_exec = nullptr;
+  // Solve context of pcg_solve / amg_precond_apply (one entry, one right-hand
+  // side), created on first use and released with the hierarchy.
+  Batch* single = nullptr;
   size_t bytes = 0;
   std::vector<std::pair<void*, size_t>> owned;
   hipStream_t setup_stream = nullptr;
@@ -176,23 +164,28 @@ struct Hierarchy {
   void release(hipStream_t s);
 };
 
-// Slots of the device scalar block used by the CG kernels.
+// Slots of the per-right-hand-side scalar block used by the CG kernels.
 enum {
-  S_RHO = 0,
-  S_PQ,
+  S_RHO = 0,  // r.z of the current direction
+  S_PQ,       // p.A p
   S_ALPHA,
-  S_RR,
+  S_RR,       // r.r after the update
   S_RZ,
-  S_ZDR,
+  S_ZDR,      // z.(r - r_old) (flexible CG)
   S_BETA,
-  S_FLAG,  // 1.0 = breakdown
-  S_R0,
-  S_TMP,
+  S_FLAG,     // 1.0 = breakdown (p.A p <= 0 or r.z <= 0): updates stop
+  S_R0,       // r_0.r_0
+  S_TMP,      // ||b - A x||^2 at the end
+  S_TMP2,     // ||b||^2 at the end
+  S_NEWP,     // 1.0 until the first direction is formed (p = z, beta unused)
   S_COUNT = 16
 };
 
-constexpr int RED_BLOCKS = 1024;  // fixed number of partial sums of every dot product
+constexpr int RED_BLOCKS = 1024;  // upper bound on the partial sums of one dot product
 constexpr int RED_THREADS = 256;
+constexpr int MAX_LEVELS = 32;
+constexpr int MAX_RHS = 8;
+constexpr int CTL_INTS = 16;  // per entry: [0] active, [1 + k] right-hand side k finished
 
 // ------------------------------------------------------------------ setup kernels
 // Validation: returns bit flags 1 = invalid structure/value, 2 = bad diagonal,
@@ -220,22 +213,99 @@ void build_sell(Hierarchy& H, int l, hipStream_t s);
 void scatter(int n, const int* perm, const double* in, double* out, hipStream_t s);
 void exclusive_scan(const int* in, int* out, int n, hipStream_t s);  // out has n+1 entries
 
-// ------------------------------------------------------------------ solve kernels
-template <typename V>
-void vcycle(Hierarchy& H, int l, const V* b, V* x, hipStream_t s);
-void precond_apply(Hierarchy& H, const double* r, double* z, hipStream_t s);
-// y = A x (FP64) for level 0, fused partial of dot(x, y) when `partial` is set.
-void spmv64(const Level& L, const double* x, double* y, double* partial, hipStream_t s, int kind);
-void residual64(const Level& L, const double* b, const double* x, double* r, double* partial, hipStream_t s);
+// ------------------------------------------------------------------ solve engine
+// Every solve-phase launch is table driven: block b of a launch reads
+// tab[b] = {d, lo, hi, part} and works on units [lo, hi) (rows, slices or
+// coarse rows, by kernel) of descriptor D[d], one (entry, level) pair of a
+// batch; reductions write their block sum to partial index `part` of the
+// entry.  The split of an entry's units into blocks depends on that entry
+// alone, so its arithmetic is the same in every batch it runs in.
+struct Item {
+  int d, lo, hi, part;
+};
 
-// CG vector kernels: each writes RED_BLOCKS partial sums, reduced by finish_*.
-void cg_update_xr(int n, double* x, double* r, double* rold, const double* p, const double* q,
-                  const double* scal, double* partial, hipStream_t s);
-void cg_dots_rz(int n, const double* r, const double* z, const double* rold, double* partial, hipStream_t s);
-void cg_update_p(int n, double* p, const double* z, const double* scal, hipStream_t s);
-void dot_partial(int n, const double* a, const double* b, double* partial, hipStream_t s);
-// Reduces `nparts` partial sums into scal[slot]; op selects the scalar update.
-enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_RHO_INIT };
-void finish(double* partial, int nparts, double* scal, int slot, int op, hipStream_t s);
+// Device descriptor of one level of one batch entry.  Matrix arrays belong to
+// the hierarchy, vectors to the entry (right-hand sides interleaved: value k
+// of row i at i * R + k, rows in solve order).
+struct BDesc {
+  const int *srow, *soff, *scol;
+  const double *sval64, *dg64, *l164;
+  const float *sval32, *dg32, *l132;
+  const int *rowptr, *colind;  // CSR (one-level hierarchies only)
+  const double* vals;
+  const int *mptr, *members, *agg;  // transfer to level l+1
+  const double* Ainv;               // coarsest level: dense inverse (nL x nL)
+  void *x, *b, *t;                  // this level's iterate, right-hand side, residual
+  void *xc, *bc;                    // level l+1's iterate and right-hand side
+  double *r, *z, *p, *q, *rold, *xs, *bs;  // level-0 CG vectors
+  double* partial;                  // [2][RED_BLOCKS][R]
+  double* scal;                     // [R][S_COUNT]
+  const int* ctl;                   // [CTL_INTS]
+  int active;                       // 0: the entry is finished (table launches skip it)
+  int n, nc, nsl, nL;
+  double omega;
+};
+
+// Kernel selectors of a launch.
+enum {
+  OP_ZERO = 0,   // x = 0 (rows)
+  OP_GS,         // Gauss-Seidel on the slices of one colour
+  OP_RESID,      // t = b - A x (slices)
+  OP_JACOBI,     // x += t / l1 (rows)
+  OP_RESTRICT,   // b_c = P^T t (coarse rows)
+  OP_PROLONG,    // x += omega P x_c (rows)
+  OP_COARSE,     // x = A_L^{-1} b (rows of the coarsest level, 4 per block)
+  OP_R2B,        // FP32 cycle: b_0 = (float) r
+  OP_X2Z,        // FP32 cycle: z = (double) x_0
+  OP_DOTS_RZ,    // partials of r.z and z.(r - r_old)
+  OP_UPDATE_P,   // p = z + beta p
+  OP_SPMV_DOT,   // q = A p, partials of p.q (SELL slices)
+  OP_SPMV_DOT_CSR,   // same on a CSR level 0 (aux = lanes per row)
+  OP_UPDATE_XR,  // x += alpha p, r -= alpha q, partials of r.r
+  OP_RESID_DOT,  // out = b - A x, partials of out.out (aux = 0: out = r, 1: out = q)
+  OP_RESID_DOT_CSR,  // same on a CSR level 0 (aux2 = lanes per row)
+  OP_DOT_BB,     // partials of b.b
+  OP_VZERO_ROLD, // r_old = 0 (rows)
+  OP_FINISH,     // per entry: reduce partials, scalar update (aux = FIN_*, aux2 = slot)
+};
+enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
+
+struct Launch {
+  int op = 0, level = 0, aux = 0, aux2 = 0;
+  size_t off = 0;  // first item in the plan's table
+  int nblk = 0;
+  int kind = KIND_NONE;
+  double bytes = 0.0;  // algorithmic HBM bytes
+  // Plans of one entry launch without a table: descriptor direct.d passed by
+  // value, units [direct.lo, direct.hi) in pieces of direct.part per block.
+  bool use_direct = false;
+  Item direct{};
+};
+
+// Enqueues launches[i] for i in [first, last) with tables at `tab`.
+// Dh: host copy of the descriptors (direct launches pass one by value).
+void issue_launches(const std::vector<Launch>& L, size_t first, size_t last, const Item* tab, const BDesc* D,
+                    const BDesc* Dh, int R, int fp32, hipStream_t s);
+// out = in permuted and interleaved: out[r * R + k] = in[k * n + perm[r]]
+// (gather) and its inverse (scatter); perm NULL: identity.
+void gather_rhs(int n, int R, const int* perm, const double* in, double* out, hipStream_t s);
+void scatter_rhs(int n, int R, const int* perm, const double* in, double* out, hipStream_t s);
+
+void batch_destroy(Batch* B);
+// pcg_solve / amg_precond_apply / pcg_solve_batched on the engine.
+amg_status pcg_run(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
+                   double* res_hist, double* iter_hist, hipStream_t us);
+void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us);
+amg_status pcg_batched_run(Hierarchy* const* hs, int nsys, int nrhs, const double* const* b, double* const* x,
+                           double rtol, int maxit, amg_solve_info* info, hipStream_t us);
+// Continuous batching: entries are submitted and retired between steps.
+Batch* batch_new(int R, int cap, int use_graphs);
+int batch_submit(Batch& B, Hierarchy& H, const double* b, double* x, double rtol, int maxit, int64_t tag,
+                 hipStream_t us);
+void batch_step(Batch& B, int iterations);
+int batch_active(const Batch& B);
+int batch_poll(Batch& B, int64_t* tags, amg_status* status, amg_solve_info* info, int cap);
+size_t batch_entry_bytes(const Batch& B);
+
 
 }  // namespace amgx

@@ -1,0 +1,941 @@
+// Solve engine: one or many CG solves (entries) advanced together, one CG
+// iteration of every active entry per step.  A step is a fixed list of
+// table-driven launches (the V-cycle of Sec. 2 level by level over all
+// entries, then the CG vector updates), built once per set of entries and
+// replayed as a HIP graph while the set is unchanged.  Entries join (after a
+// prologue that forms r_0) and leave (after the true residual and the copy of
+// x back to the caller) between steps, which gives pcg_solve (one entry),
+// pcg_solve_batched (all entries start together) and the continuous-batching
+// interface amg_batch_* the same code and the same per-entry arithmetic.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "amg_internal.h"
+
+namespace amgx {
+
+namespace {
+
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int ROW_CH = 1024;     // rows per block of the row-wise kernels
+constexpr int RESTRICT_CH = 256; // coarse rows per block of the restriction
+constexpr int SLICES_PB = 4;     // slices per block of the sweep / residual kernels
+
+// Number of partial sums of a reduction over n rows (or slices): depends on
+// the entry alone.
+int red_blocks_rows(int n) { return std::min(RED_BLOCKS, std::max(1, cdiv(n, 2048))); }
+int red_blocks_slices(int nsl) { return std::min(RED_BLOCKS, std::max(1, cdiv(nsl, 8))); }
+
+}  // namespace
+
+// Device vectors of one entry (right-hand sides interleaved, solve order).
+struct Ctx {
+  std::vector<std::pair<void*, size_t>> owned;
+  size_t bytes = 0;
+  std::vector<void*> x, b, t;  // per level, precision of the cycle
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rold = nullptr, *xs = nullptr, *bs = nullptr;
+  double* partial = nullptr;
+  void* alloc(size_t bytes_, hipStream_t s) {
+    void* ptr = dalloc(bytes_, s);
+    owned.emplace_back(ptr, bytes_);
+    bytes += bytes_;
+    return ptr;
+  }
+  void release(hipStream_t s) {
+    for (auto& o : owned) dfree(o.first, s);
+    owned.clear();
+    bytes = 0;
+    x.clear();
+    b.clear();
+    t.clear();
+  }
+};
+
+struct Result {
+  int64_t tag = 0;
+  amg_status status = AMG_OK;
+  amg_solve_info info[MAX_RHS];
+};
+
+struct Entry {
+  bool used = false;       // holds a solve (running or awaiting finalisation)
+  bool complete = false;   // every right-hand side finished
+  Hierarchy* bound = nullptr;  // hierarchy whose vectors and descriptors the slot holds
+  Ctx ctx;
+  const double* b_user = nullptr;
+  double* x_user = nullptr;
+  double rtol = 0.0;
+  int maxit = 0;
+  int64_t tag = 0;
+  bool started = false;
+  double r0[MAX_RHS], rel[MAX_RHS];
+  int it[MAX_RHS];
+  amg_status st[MAX_RHS];
+  bool done[MAX_RHS];
+  double* res_hist = nullptr;   // host, R = 1 only
+  double* iter_hist = nullptr;  // device, R = 1 only
+  double t0 = 0.0;
+};
+
+struct Plan {
+  std::vector<Launch> L;
+  size_t precond_end = 0;  // launches [0, precond_end) form the V-cycle
+  Item* tab_d = nullptr;
+  size_t cap = 0;
+  hipGraphExec_t exec = nullptr;
+  int runs = 0;
+  std::vector<int> slots;
+  double rows = 0.0;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    runs = 0;
+  }
+};
+
+struct Batch {
+  int R = 1, cap = 0, use_graphs = 1;
+  bool single = false;  // the per-hierarchy context of pcg_solve / amg_precond_apply
+  int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0;
+  hipStream_t work = nullptr;
+  hipEvent_t ev = nullptr;
+  BDesc* desc_d = nullptr;
+  std::vector<BDesc> desc_h;
+  double* scal_d = nullptr;
+  double* scal_h = nullptr;  // pinned
+  int* ctl_d = nullptr;
+  int* ctl_h = nullptr;  // pinned
+  std::vector<Entry> ent;
+  std::vector<int> pending;  // slots awaiting their prologue
+  std::vector<Result> results;
+  Plan iter, tmp;
+  bool dirty = true;
+
+  size_t scal_count() const { return (size_t)cap * R * S_COUNT; }
+  double* scal_of(int slot) const { return scal_d + (size_t)slot * R * S_COUNT; }
+  const double* scal_h_of(int slot) const { return scal_h + (size_t)slot * R * S_COUNT; }
+  int desc_index(int slot, int l) const { return slot * MAX_LEVELS + l; }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ set-up of a batch
+void batch_init(Batch& B, int R, int cap, int use_graphs) {
+  if (R != 1 && R != 2 && R != 4 && R != 8) fail(AMG_ERR_UNSUPPORTED, "right-hand sides per entry must be 1, 2, 4 or 8");
+  if (cap < 1) fail(AMG_ERR_INVALID_ARG, "batch capacity must be positive");
+  B.R = R;
+  B.cap = cap;
+  B.use_graphs = use_graphs;
+  B.ent.resize(cap);
+  AMG_HIP(hipStreamCreateWithFlags(&B.work, hipStreamNonBlocking));
+  AMG_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
+  B.desc_h.assign((size_t)cap * MAX_LEVELS, BDesc{});
+  B.desc_d = static_cast<BDesc*>(dalloc(B.desc_h.size() * sizeof(BDesc), B.work));
+  B.scal_d = static_cast<double*>(dalloc(B.scal_count() * sizeof(double), B.work));
+  B.ctl_d = static_cast<int*>(dalloc((size_t)cap * CTL_INTS * sizeof(int), B.work));
+  AMG_HIP(hipHostMalloc((void**)&B.scal_h, B.scal_count() * sizeof(double), hipHostMallocDefault));
+  AMG_HIP(hipHostMalloc((void**)&B.ctl_h, (size_t)cap * CTL_INTS * sizeof(int), hipHostMallocDefault));
+  std::memset(B.ctl_h, 0, (size_t)cap * CTL_INTS * sizeof(int));
+  AMG_HIP(hipMemsetAsync(B.ctl_d, 0, (size_t)cap * CTL_INTS * sizeof(int), B.work));
+  AMG_HIP(hipMemsetAsync(B.scal_d, 0, B.scal_count() * sizeof(double), B.work));
+}
+
+void check_uniform(Batch& B, const Hierarchy& H) {
+  const int fp32 = H.p.vcycle_fp32 ? 1 : 0;
+  if (B.fp32 < 0) {
+    B.fp32 = fp32;
+    B.smoother = H.p.smoother;
+    B.pre = H.p.pre_sweeps;
+    B.post = H.p.post_sweeps;
+    B.flexible = H.flexible;
+    return;
+  }
+  if (B.fp32 != fp32 || B.smoother != H.p.smoother || B.pre != H.p.pre_sweeps || B.post != H.p.post_sweeps ||
+      B.flexible != H.flexible)
+    fail(AMG_ERR_INVALID_ARG,
+         "hierarchies of one batch must share vcycle_fp32, smoother, pre/post sweeps and the CG variant");
+}
+
+// Allocates the vectors of `slot` for hierarchy H and writes its descriptors.
+void bind_slot(Batch& B, int slot, Hierarchy& H) {
+  Entry& E = B.ent[slot];
+  hipStream_t s = B.work;
+  E.ctx.release(s);
+  E.bound = nullptr;
+  const int R = B.R;
+  const int Lc = (int)H.lev.size() - 1;
+  if (Lc >= MAX_LEVELS) fail(AMG_ERR_UNSUPPORTED, "too many levels");
+  const size_t vb = B.fp32 ? 4 : 8;
+  Ctx& C = E.ctx;
+  const size_t n0 = (size_t)H.lev[0].n;
+  auto vec64 = [&](size_t n) { return static_cast<double*>(C.alloc(n * R * sizeof(double), s)); };
+  C.r = vec64(n0);
+  C.z = vec64(n0);
+  C.p = vec64(n0);
+  C.q = vec64(n0);
+  C.xs = vec64(n0);
+  C.bs = vec64(n0);
+  C.rold = H.flexible ? vec64(n0) : nullptr;
+  C.partial = static_cast<double*>(C.alloc(2 * (size_t)RED_BLOCKS * R * sizeof(double), s));
+  C.x.assign(Lc + 1, nullptr);
+  C.b.assign(Lc + 1, nullptr);
+  C.t.assign(Lc + 1, nullptr);
+  for (int l = 0; l <= Lc; ++l) {
+    const size_t n = (size_t)H.lev[l].n;
+    if (l == 0 && !B.fp32) {  // the FP64 cycle works on r and z directly
+      C.b[0] = C.r;
+      C.x[0] = C.z;
+    } else {
+      C.x[l] = C.alloc(n * R * vb, s);
+      C.b[l] = C.alloc(n * R * vb, s);
+    }
+    if (l < Lc) C.t[l] = C.alloc(n * R * vb, s);
+  }
+  for (int l = 0; l < MAX_LEVELS; ++l) {
+    BDesc& d = B.desc_h[B.desc_index(slot, l)];
+    d = BDesc{};
+    if (l > Lc) continue;
+    const Level& L = H.lev[l];
+    d.srow = L.srow;
+    d.soff = L.soff;
+    d.scol = L.scol;
+    d.sval64 = L.sval;
+    d.dg64 = L.dg;
+    d.l164 = L.l1;
+    d.sval32 = L.sval32;
+    d.dg32 = L.dg32;
+    d.l132 = L.l1_32;
+    d.rowptr = L.rowptr;
+    d.colind = L.colind;
+    d.vals = L.vals;
+    if (l < Lc) {
+      d.mptr = L.mptr;
+      d.members = L.members;
+      d.agg = L.agg;
+      d.xc = C.x[l + 1];
+      d.bc = C.b[l + 1];
+    } else {
+      d.Ainv = H.Ainv;
+    }
+    d.x = C.x[l];
+    d.b = C.b[l];
+    d.t = C.t[l];
+    d.r = C.r;
+    d.z = C.z;
+    d.p = C.p;
+    d.q = C.q;
+    d.rold = C.rold;
+    d.xs = C.xs;
+    d.bs = C.bs;
+    d.partial = C.partial;
+    d.scal = B.scal_of(slot);
+    d.ctl = B.ctl_d + (size_t)slot * CTL_INTS;
+    d.active = 0;
+    d.n = L.n;
+    d.nc = L.nc;
+    d.nsl = L.nsl;
+    d.nL = H.nL;
+    d.omega = H.p.omega;
+  }
+  AMG_HIP(hipMemcpyAsync(B.desc_d + B.desc_index(slot, 0), &B.desc_h[B.desc_index(slot, 0)],
+                         MAX_LEVELS * sizeof(BDesc), hipMemcpyHostToDevice, s));
+  E.bound = &H;
+  B.dirty = true;
+}
+
+// Marks the entry of `slot` active or finished in its descriptors.
+void set_active(Batch& B, int slot, int v, hipStream_t s) {
+  for (int l = 0; l < MAX_LEVELS; ++l) B.desc_h[B.desc_index(slot, l)].active = v;
+  AMG_HIP(hipMemcpyAsync(B.desc_d + B.desc_index(slot, 0), &B.desc_h[B.desc_index(slot, 0)],
+                         MAX_LEVELS * sizeof(BDesc), hipMemcpyHostToDevice, s));
+}
+
+void upload_ctl(Batch& B, hipStream_t s) {
+  AMG_HIP(hipMemcpyAsync(B.ctl_d, B.ctl_h, (size_t)B.cap * CTL_INTS * sizeof(int), hipMemcpyHostToDevice, s));
+}
+
+// ------------------------------------------------------------------ launch lists
+// Collects the launches of a program and their tables.  Every launch is a
+// list of segments, one per entry, each a regular split of a unit range; a
+// plan of a single entry launches its (single-segment) launches directly.
+struct Builder {
+  const Batch& B;
+  const bool single;
+  std::vector<Item> items;
+  std::vector<Launch> L;
+  Launch cur;
+  int segs = 0;
+  Builder(const Batch& b, bool single_entry) : B(b), single(single_entry) {}
+  void begin(int op, int level, int kind, int aux = 0, int aux2 = 0) {
+    cur = Launch{};
+    cur.op = op;
+    cur.level = level;
+    cur.kind = kind;
+    cur.aux = aux;
+    cur.aux2 = aux2;
+    cur.off = items.size();
+    segs = 0;
+  }
+  void add(int d, int lo, int hi, int part, double bytes) {
+    items.push_back(Item{d, lo, hi, part});
+    cur.bytes += bytes;
+  }
+  void segment(int d, int lo0, int hi, int ch) {
+    if (segs++ == 0) cur.direct = Item{d, lo0, hi, ch};
+  }
+  void end() {
+    cur.nblk = (int)(items.size() - cur.off);
+    cur.use_direct = single && segs == 1;
+    if (cur.nblk > 0) L.push_back(cur);
+  }
+  // Fixed-size pieces of [lo0, hi).
+  void pieces(int d, int lo0, int hi, int ch, double bytes_per_unit) {
+    if (lo0 >= hi) return;
+    segment(d, lo0, hi, ch);
+    for (int lo = lo0; lo < hi; lo += ch) {
+      const int h = std::min(hi, lo + ch);
+      add(d, lo, h, 0, bytes_per_unit * (h - lo));
+    }
+  }
+  void pieces(int d, int n, int ch, double bytes_per_unit) { pieces(d, 0, n, ch, bytes_per_unit); }
+  // nb contiguous chunks of [0, n), partial index = chunk index; returns nb.
+  int chunks(int d, int n, int nb, double bytes_per_unit) {
+    const int ch = cdiv(n, nb);
+    segment(d, 0, n, ch);
+    for (int i = 0; i < nb; ++i) {
+      const int lo = std::min(n, i * ch), hi = std::min(n, lo + ch);
+      add(d, lo, hi, i, bytes_per_unit * (hi - lo));
+    }
+    return nb;
+  }
+  // One item for entry d whose lo carries a partial count (finish kernels).
+  void one(int d, int np) {
+    segment(d, np, np, 0);
+    add(d, np, np, 0, 0.0);
+  }
+};
+
+inline const Hierarchy& hier(const Batch& B, int slot) { return *B.ent[slot].bound; }
+inline int coarsest(const Batch& B, int slot) { return (int)hier(B, slot).lev.size() - 1; }
+inline bool sell0(const Batch& B, int slot) { return hier(B, slot).lev[0].scol != nullptr; }
+
+int kind_at(int l, int k) { return l == 0 ? k : AMG_KIND_COARSE_LEVELS; }
+
+// Algorithmic bytes of one pass over slices [s0, s1) of level L: matrix once,
+// diagonal, and R x (b read, x read, x written) per row.
+double pass_bytes(const Level& L, int s0, int s1, int R, double vb) {
+  const double ent = (double)(L.soff_h[s1] - L.soff_h[s0]);
+  const double rows = (double)(L.srow_h[s1] - L.srow_h[s0]);
+  return ent * (4.0 + vb) + rows * (vb + 3.0 * R * vb) + (s1 - s0) * 8.0;
+}
+
+void add_slices(Builder& b, const Batch& B, int slot, int l, int s0, int s1) {
+  if (s0 >= s1) return;
+  const Level& L = hier(B, slot).lev[l];
+  const double vb = B.fp32 ? 4 : 8;
+  const int d = B.desc_index(slot, l);
+  b.segment(d, s0, s1, SLICES_PB);
+  for (int lo = s0; lo < s1; lo += SLICES_PB) {
+    const int hi = std::min(s1, lo + SLICES_PB);
+    b.add(d, lo, hi, 0, pass_bytes(L, lo, hi, B.R, vb));
+  }
+}
+
+void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l) {
+  const double vb = B.fp32 ? 4 : 8;
+  if (B.smoother == AMG_SMOOTHER_MCSGS) {
+    int maxcol = 0;
+    for (int e : E) maxcol = std::max(maxcol, hier(B, e).lev[l].ncol);
+    for (int dir = 0; dir < 2; ++dir)
+      for (int q = 0; q < maxcol; ++q) {
+        b.begin(OP_GS, l, kind_at(l, AMG_KIND_SWEEP));
+        for (int e : E) {
+          const Level& L = hier(B, e).lev[l];
+          if (q >= L.ncol) continue;
+          const int c = dir == 0 ? q : L.ncol - 1 - q;
+          add_slices(b, B, e, l, L.sptr[c], L.sptr[c + 1]);
+        }
+        b.end();
+      }
+  } else {
+    b.begin(OP_RESID, l, kind_at(l, AMG_KIND_SWEEP));
+    for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
+    b.end();
+    b.begin(OP_JACOBI, l, kind_at(l, AMG_KIND_SWEEP));
+    for (int e : E) b.pieces(B.desc_index(e, l), hier(B, e).lev[l].n, ROW_CH, vb + 3.0 * B.R * vb);
+    b.end();
+  }
+}
+
+// z = M r for every entry of S (Sec. 2: V-cycle), level by level over the
+// entries that have the level; all coarsest solves in one launch.
+void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
+  const double vb = B.fp32 ? 4 : 8;
+  const int R = B.R;
+  int maxLc = 0;
+  for (int e : S) maxLc = std::max(maxLc, coarsest(B, e));
+  if (B.fp32) {
+    b.begin(OP_R2B, 0, AMG_KIND_CG_VEC);
+    for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 12.0 * R);
+    b.end();
+  }
+  std::vector<std::vector<int>> below(maxLc);
+  for (int l = 0; l < maxLc; ++l)
+    for (int e : S)
+      if (coarsest(B, e) > l) below[l].push_back(e);
+  for (int l = 0; l < maxLc; ++l) {
+    const std::vector<int>& E = below[l];
+    b.begin(OP_ZERO, l, l == 0 ? AMG_KIND_OTHER : AMG_KIND_COARSE_LEVELS);
+    for (int e : E) b.pieces(B.desc_index(e, l), hier(B, e).lev[l].n, ROW_CH, R * vb);
+    b.end();
+    for (int k = 0; k < B.pre; ++k) build_smooth(b, B, E, l);
+    b.begin(OP_RESID, l, kind_at(l, AMG_KIND_RESTRICT));
+    for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
+    b.end();
+    b.begin(OP_RESTRICT, l, kind_at(l, AMG_KIND_RESTRICT));
+    for (int e : E) {
+      const Level& L = hier(B, e).lev[l];
+      // members and fine residual once, coarse pointers and result once
+      const double per_coarse = (double)L.n / std::max(1, L.nc) * (4.0 + R * vb) + 4.0 + R * vb;
+      b.pieces(B.desc_index(e, l), L.nc, RESTRICT_CH, per_coarse);
+    }
+    b.end();
+  }
+  b.begin(OP_COARSE, maxLc, AMG_KIND_COARSE_LEVELS);
+  for (int e : S) {
+    const Hierarchy& H = hier(B, e);
+    b.pieces(B.desc_index(e, coarsest(B, e)), H.nL, 4, 8.0 * H.nL + 2.0 * R * vb);
+  }
+  b.end();
+  for (int l = maxLc - 1; l >= 0; --l) {
+    const std::vector<int>& E = below[l];
+    b.begin(OP_PROLONG, l, kind_at(l, AMG_KIND_PROLONG));
+    for (int e : E) {
+      const Level& L = hier(B, e).lev[l];
+      const double per_row = 4.0 + 2.0 * R * vb + R * vb * (double)L.nc / L.n;
+      b.pieces(B.desc_index(e, l), L.n, ROW_CH, per_row);
+    }
+    b.end();
+    for (int k = 0; k < B.post; ++k) build_smooth(b, B, E, l);
+  }
+  if (B.fp32) {
+    b.begin(OP_X2Z, 0, AMG_KIND_CG_VEC);
+    for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 12.0 * R);
+    b.end();
+  }
+}
+
+// out = b - A x with partials (which: 0 -> r, 1 -> q); returns per-slot partial counts.
+std::vector<int> build_resid_dot(Builder& b, const Batch& B, const std::vector<int>& S, int which, int kind) {
+  std::vector<int> np(S.size());
+  const int R = B.R;
+  b.begin(OP_RESID_DOT, 0, kind, which);
+  for (size_t i = 0; i < S.size(); ++i) {
+    const int e = S[i];
+    if (!sell0(B, e)) continue;
+    const Level& L = hier(B, e).lev[0];
+    const double per_slice = ((double)L.soff_h[L.nsl] * 12.0 + (double)L.n * (8.0 + 24.0 * R)) / L.nsl + 8.0;
+    np[i] = b.chunks(B.desc_index(e, 0), L.nsl, red_blocks_slices(L.nsl), per_slice);
+  }
+  b.end();
+  for (int sub = 4; sub <= 64; sub *= 2) {
+    b.begin(OP_RESID_DOT_CSR, 0, kind, which, sub);
+    for (size_t i = 0; i < S.size(); ++i) {
+      const int e = S[i];
+      const Level& L = hier(B, e).lev[0];
+      if (sell0(B, e) || L.sub != sub) continue;
+      const double per_row = (double)L.nnz / L.n * 12.0 + 4.0 + 24.0 * R;
+      np[i] = b.chunks(B.desc_index(e, 0), L.n, red_blocks_rows(L.n), per_row);
+    }
+    b.end();
+  }
+  return np;
+}
+
+void build_finish(Builder& b, const Batch& B, const std::vector<int>& S, const std::vector<int>& np, int op,
+                  int slot_ = 0) {
+  b.begin(OP_FINISH, 0, KIND_NONE, op, slot_);
+  for (size_t i = 0; i < S.size(); ++i) b.one(B.desc_index(S[i], 0), np[i]);
+  b.end();
+}
+
+// One CG iteration (Sec. 2): z = M r, beta, p, q = A p, alpha, x and r, ||r||^2.
+void build_iter(Builder& b, const Batch& B, const std::vector<int>& S, size_t* precond_end) {
+  const int R = B.R;
+  build_precond(b, B, S);
+  *precond_end = b.L.size();
+  std::vector<int> nr(S.size());
+  b.begin(OP_DOTS_RZ, 0, AMG_KIND_CG_VEC);
+  for (size_t i = 0; i < S.size(); ++i) {
+    const int n = hier(B, S[i]).lev[0].n;
+    nr[i] = b.chunks(B.desc_index(S[i], 0), n, red_blocks_rows(n), (B.flexible ? 24.0 : 16.0) * R);
+  }
+  b.end();
+  build_finish(b, B, S, nr, B.flexible ? FIN_BETA_FCG : FIN_BETA_PCG);
+  b.begin(OP_UPDATE_P, 0, AMG_KIND_CG_VEC);
+  for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 24.0 * R);
+  b.end();
+  std::vector<int> ns(S.size());
+  b.begin(OP_SPMV_DOT, 0, AMG_KIND_SPMV_F64);
+  for (size_t i = 0; i < S.size(); ++i) {
+    const int e = S[i];
+    if (!sell0(B, e)) continue;
+    const Level& L = hier(B, e).lev[0];
+    const double per_slice = ((double)L.soff_h[L.nsl] * 12.0 + (double)L.n * (8.0 + 16.0 * R)) / L.nsl + 8.0;
+    ns[i] = b.chunks(B.desc_index(e, 0), L.nsl, red_blocks_slices(L.nsl), per_slice);
+  }
+  b.end();
+  for (int sub = 4; sub <= 64; sub *= 2) {
+    b.begin(OP_SPMV_DOT_CSR, 0, AMG_KIND_SPMV_F64, sub);
+    for (size_t i = 0; i < S.size(); ++i) {
+      const int e = S[i];
+      const Level& L = hier(B, e).lev[0];
+      if (sell0(B, e) || L.sub != sub) continue;
+      const double per_row = (double)L.nnz / L.n * 12.0 + 4.0 + 16.0 * R;
+      ns[i] = b.chunks(B.desc_index(e, 0), L.n, red_blocks_rows(L.n), per_row);
+    }
+    b.end();
+  }
+  build_finish(b, B, S, ns, FIN_ALPHA);
+  b.begin(OP_UPDATE_XR, 0, AMG_KIND_CG_VEC);
+  for (size_t i = 0; i < S.size(); ++i) {
+    const int n = hier(B, S[i]).lev[0].n;
+    nr[i] = b.chunks(B.desc_index(S[i], 0), n, red_blocks_rows(n), (B.flexible ? 56.0 : 48.0) * R);
+  }
+  b.end();
+  build_finish(b, B, S, nr, FIN_STORE, S_RR);
+}
+
+// r = b - A x, ||r_0||^2 and the CG scalars of a starting entry.
+void build_prologue(Builder& b, const Batch& B, const std::vector<int>& S) {
+  if (B.flexible) {
+    b.begin(OP_VZERO_ROLD, 0, AMG_KIND_CG_VEC);
+    for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 8.0 * B.R);
+    b.end();
+  }
+  const std::vector<int> np = build_resid_dot(b, B, S, 0, AMG_KIND_CG_VEC);
+  build_finish(b, B, S, np, FIN_INIT);
+}
+
+// ||b - A x||^2 and ||b||^2 of finishing entries.
+void build_final(Builder& b, const Batch& B, const std::vector<int>& S) {
+  const std::vector<int> np = build_resid_dot(b, B, S, 1, AMG_KIND_CG_VEC);
+  build_finish(b, B, S, np, FIN_STORE, S_TMP);
+  std::vector<int> nb(S.size());
+  b.begin(OP_DOT_BB, 0, AMG_KIND_CG_VEC);
+  for (size_t i = 0; i < S.size(); ++i) {
+    const int n = hier(B, S[i]).lev[0].n;
+    nb[i] = b.chunks(B.desc_index(S[i], 0), n, red_blocks_rows(n), 8.0 * B.R);
+  }
+  b.end();
+  build_finish(b, B, S, nb, FIN_STORE, S_TMP2);
+}
+
+void upload_plan(Plan& P, Builder& b, hipStream_t s) {
+  P.drop_graph();
+  P.L = std::move(b.L);
+  if (b.items.size() > P.cap) {
+    if (P.tab_d) dfree(P.tab_d, s);
+    P.cap = std::max(b.items.size(), (size_t)1024);
+    P.tab_d = static_cast<Item*>(dalloc(P.cap * sizeof(Item), s));
+  }
+  if (!b.items.empty())
+    AMG_HIP(hipMemcpyAsync(P.tab_d, b.items.data(), b.items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+}
+
+void run_plan(Batch& B, Plan& P, hipStream_t s, bool graph) {
+  if (!graph || !B.use_graphs || g_timing_mask_for_graphs() != 0) {
+    issue_launches(P.L, 0, P.L.size(), P.tab_d, B.desc_d, B.desc_h.data(), B.R, B.fp32, s);
+    return;
+  }
+  if (!P.exec) {
+    hipGraph_t g = nullptr;
+    AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      issue_launches(P.L, 0, P.L.size(), P.tab_d, B.desc_d, B.desc_h.data(), B.R, B.fp32, s);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    AMG_HIP(hipStreamEndCapture(s, &g));
+    hipError_t e = hipGraphInstantiate(&P.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    AMG_HIP(e);
+  }
+  AMG_HIP(hipGraphLaunch(P.exec, s));
+}
+
+void read_scal(Batch& B) {
+  AMG_HIP(hipMemcpyAsync(B.scal_h, B.scal_d, B.scal_count() * sizeof(double), hipMemcpyDeviceToHost, B.work));
+  AMG_HIP(hipStreamSynchronize(B.work));
+}
+
+// ------------------------------------------------------------------ entry life cycle
+void start_entry(Batch& B, int slot, Hierarchy& H, const double* b, double* x, double rtol, int maxit, int64_t tag,
+                 double* res_hist, double* iter_hist, hipStream_t us) {
+  check_uniform(B, H);
+  Entry& E = B.ent[slot];
+  if (E.bound != &H) bind_slot(B, slot, H);
+  hipStream_t s = B.work;
+  E.used = true;
+  E.complete = false;
+  E.started = false;
+  E.b_user = b;
+  E.x_user = x;
+  E.rtol = rtol;
+  E.maxit = maxit;
+  E.tag = tag;
+  E.res_hist = res_hist;
+  E.iter_hist = iter_hist;
+  for (int k = 0; k < MAX_RHS; ++k) {
+    E.r0[k] = 0.0;
+    E.rel[k] = 1.0;
+    E.it[k] = 0;
+    E.st[k] = AMG_ERR_NOT_CONVERGED;
+    E.done[k] = false;
+  }
+  int* c = B.ctl_h + (size_t)slot * CTL_INTS;
+  std::memset(c, 0, CTL_INTS * sizeof(int));
+  c[0] = 1;
+  for (int k = 0; k < B.R; ++k) c[1 + k] = maxit == 0 ? 1 : 0;
+  AMG_HIP(hipEventRecord(B.ev, us));
+  AMG_HIP(hipStreamWaitEvent(s, B.ev, 0));
+  AMG_HIP(hipMemsetAsync(B.scal_of(slot), 0, (size_t)B.R * S_COUNT * sizeof(double), s));
+  upload_ctl(B, s);
+  set_active(B, slot, 1, s);
+  const Level& L0 = H.lev[0];
+  gather_rhs(L0.n, B.R, L0.perm, b, E.ctx.bs, s);
+  gather_rhs(L0.n, B.R, L0.perm, x, E.ctx.xs, s);
+  if (iter_hist) scatter_rhs(L0.n, 1, L0.perm, E.ctx.xs, iter_hist, s);
+  if (res_hist) res_hist[0] = 1.0;
+  if (std::find(B.iter.slots.begin(), B.iter.slots.end(), slot) == B.iter.slots.end()) B.dirty = true;
+  B.pending.push_back(slot);
+  E.t0 = now_ms();
+}
+
+// True residual, copy-out and result record of the finishing slots.
+void finalise(Batch& B, const std::vector<int>& S) {
+  if (S.empty()) return;
+  hipStream_t s = B.work;
+  Builder b(B, S.size() == 1);
+  build_final(b, B, S);
+  upload_plan(B.tmp, b, s);
+  run_plan(B, B.tmp, s, false);
+  for (int e : S) {
+    const Entry& E = B.ent[e];
+    const Level& L0 = E.bound->lev[0];
+    scatter_rhs(L0.n, B.R, L0.perm, E.ctx.xs, E.x_user, s);
+  }
+  read_scal(B);
+  const double t = now_ms();
+  for (int e : S) {
+    Entry& E = B.ent[e];
+    Result res;
+    res.tag = E.tag;
+    res.status = AMG_OK;
+    for (int k = 0; k < B.R; ++k) {
+      const double* sc = B.scal_h_of(e) + k * S_COUNT;
+      const double rn = std::sqrt(sc[S_TMP]), bn = std::sqrt(sc[S_TMP2]);
+      amg_solve_info& in = res.info[k];
+      in.iterations = E.it[k];
+      in.converged = E.st[k] == AMG_OK ? 1 : 0;
+      in.levels = (int)E.bound->lev.size();
+      in.rel_residual = E.rel[k];
+      in.true_rel_residual = bn > 0.0 ? rn / bn : 0.0;
+      in.setup_ms = E.bound->setup_ms;
+      in.solve_ms = t - E.t0;
+      if (E.st[k] == AMG_ERR_BREAKDOWN)
+        res.status = AMG_ERR_BREAKDOWN;
+      else if (E.st[k] != AMG_OK && res.status == AMG_OK)
+        res.status = E.st[k];
+    }
+    B.results.push_back(res);
+    B.ctl_h[(size_t)e * CTL_INTS] = 0;
+    set_active(B, e, 0, s);
+    E.used = false;
+    E.complete = false;
+    if (!B.single) {  // a batch slot gives its memory back; the single context keeps it
+      E.ctx.release(s);
+      E.bound = nullptr;
+    }
+  }
+  upload_ctl(B, s);
+}
+
+void finish_rhs(Entry& E, int k, amg_status st, int* c) {
+  E.done[k] = true;
+  E.st[k] = st;
+  c[1 + k] = 1;
+}
+
+// One CG iteration of every active entry.
+void step(Batch& B) {
+  hipStream_t s = B.work;
+  if (!B.pending.empty()) {
+    Builder b(B, B.pending.size() == 1);
+    build_prologue(b, B, B.pending);
+    upload_plan(B.tmp, b, s);
+    run_plan(B, B.tmp, s, false);
+    B.pending.clear();
+  }
+  std::vector<int> act;
+  double act_rows = 0.0;
+  for (int e = 0; e < B.cap; ++e)
+    if (B.ent[e].used && !B.ent[e].complete) {
+      act.push_back(e);
+      act_rows += B.ent[e].bound->lev[0].n;
+    }
+  if (act.empty()) return;
+  bool rebuild = B.dirty || B.iter.L.empty() || act_rows < 0.7 * B.iter.rows;
+  if (!rebuild)
+    for (int e : act)
+      if (std::find(B.iter.slots.begin(), B.iter.slots.end(), e) == B.iter.slots.end()) rebuild = true;
+  if (rebuild) {
+    Builder b(B, act.size() == 1);
+    build_iter(b, B, act, &B.iter.precond_end);
+    const size_t pe = B.iter.precond_end;
+    upload_plan(B.iter, b, s);
+    B.iter.precond_end = pe;
+    B.iter.slots = act;
+    B.iter.rows = act_rows;
+    B.dirty = false;
+  }
+  run_plan(B, B.iter, s, B.iter.runs >= 1);
+  B.iter.runs++;
+  read_scal(B);
+  std::vector<int> fin;
+  bool ctl_changed = false;
+  for (int e : act) {
+    Entry& E = B.ent[e];
+    int* c = B.ctl_h + (size_t)e * CTL_INTS;
+    const double* sc0 = B.scal_h_of(e);
+    bool all = true;
+    for (int k = 0; k < B.R; ++k) {
+      if (E.done[k]) continue;
+      const double* sc = sc0 + k * S_COUNT;
+      if (!E.started) {
+        E.r0[k] = std::sqrt(sc[S_R0]);
+        if (E.r0[k] == 0.0) {
+          E.rel[k] = 0.0;
+          finish_rhs(E, k, AMG_OK, c);
+          ctl_changed = true;
+          continue;
+        }
+        if (E.maxit == 0) {
+          finish_rhs(E, k, AMG_ERR_NOT_CONVERGED, c);
+          continue;
+        }
+      }
+      if (sc[S_FLAG] != 0.0) {
+        finish_rhs(E, k, AMG_ERR_BREAKDOWN, c);
+        ctl_changed = true;
+        continue;
+      }
+      E.it[k] += 1;
+      E.rel[k] = std::sqrt(sc[S_RR]) / E.r0[k];
+      if (E.res_hist) E.res_hist[E.it[k]] = E.rel[k];
+      if (E.rel[k] <= E.rtol) {
+        finish_rhs(E, k, AMG_OK, c);
+        ctl_changed = true;
+      } else if (E.it[k] >= E.maxit) {
+        finish_rhs(E, k, AMG_ERR_NOT_CONVERGED, c);
+        ctl_changed = true;
+      }
+    }
+    E.started = true;
+    if (E.iter_hist) {
+      const Level& L0 = E.bound->lev[0];
+      scatter_rhs(L0.n, 1, L0.perm, E.ctx.xs, E.iter_hist + (size_t)E.it[0] * L0.n, s);
+    }
+    for (int k = 0; k < B.R; ++k) all = all && E.done[k];
+    if (all) {
+      E.complete = true;
+      fin.push_back(e);
+    }
+  }
+  if (!fin.empty())
+    finalise(B, fin);
+  else if (ctl_changed)
+    upload_ctl(B, s);
+}
+
+void batch_release(Batch& B) {
+  if (B.work) (void)hipStreamSynchronize(B.work);
+  hipStream_t s = B.work;
+  B.iter.drop_graph();
+  B.tmp.drop_graph();
+  for (auto& E : B.ent) E.ctx.release(s);
+  if (B.iter.tab_d) dfree(B.iter.tab_d, s);
+  if (B.tmp.tab_d) dfree(B.tmp.tab_d, s);
+  if (B.desc_d) dfree(B.desc_d, s);
+  if (B.scal_d) dfree(B.scal_d, s);
+  if (B.ctl_d) dfree(B.ctl_d, s);
+  B.iter.tab_d = B.tmp.tab_d = nullptr;
+  B.desc_d = nullptr;
+  B.scal_d = nullptr;
+  B.ctl_d = nullptr;
+  if (s) (void)hipStreamSynchronize(s);
+  if (B.scal_h) (void)hipHostFree(B.scal_h);
+  if (B.ctl_h) (void)hipHostFree(B.ctl_h);
+  B.scal_h = nullptr;
+  B.ctl_h = nullptr;
+  if (B.ev) (void)hipEventDestroy(B.ev);
+  B.ev = nullptr;
+  if (s) (void)hipStreamDestroy(s);
+  B.work = nullptr;
+}
+
+Batch& single_of(Hierarchy& H) {
+  if (!H.single) {
+    Batch* B = new Batch();
+    B->single = true;
+    try {
+      batch_init(*B, 1, 1, H.p.use_graphs);
+      check_uniform(*B, H);
+      bind_slot(*B, 0, H);
+    } catch (...) {
+      batch_release(*B);
+      delete B;
+      throw;
+    }
+    H.single = B;
+  }
+  return *H.single;
+}
+
+}  // namespace
+
+void batch_destroy(Batch* B) {
+  if (!B) return;
+  batch_release(*B);
+  delete B;
+}
+
+// ------------------------------------------------------------------ entry points
+amg_status pcg_run(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
+                   double* res_hist, double* iter_hist, hipStream_t us) {
+  Batch& B = single_of(H);
+  B.results.clear();
+  B.pending.clear();
+  start_entry(B, 0, H, b, x, rtol, maxit, 0, res_hist, iter_hist, us);
+  while (B.results.empty()) step(B);
+  const Result res = B.results.back();
+  B.results.clear();
+  AMG_HIP(hipEventRecord(B.ev, B.work));
+  AMG_HIP(hipStreamWaitEvent(us, B.ev, 0));
+  if (info) *info = res.info[0];
+  if (res.status == AMG_ERR_NOT_CONVERGED) set_error("maximum number of iterations reached");
+  if (res.status == AMG_ERR_BREAKDOWN) set_error("CG breakdown (p^T A p <= 0 or r^T z <= 0)");
+  return res.status;
+}
+
+void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us) {
+  Batch& B = single_of(H);
+  hipStream_t s = B.work;
+  if (B.dirty || B.iter.L.empty() || B.iter.slots != std::vector<int>{0}) {
+    Builder b(B, true);
+    build_iter(b, B, {0}, &B.iter.precond_end);
+    const size_t pe = B.iter.precond_end;
+    upload_plan(B.iter, b, s);
+    B.iter.precond_end = pe;
+    B.iter.slots = {0};
+    B.iter.rows = H.lev[0].n;
+    B.dirty = false;
+  }
+  AMG_HIP(hipStreamSynchronize(s));  // descriptors and tables are written on the work stream
+  const Level& L0 = H.lev[0];
+  const Entry& E = B.ent[0];
+  gather_rhs(L0.n, 1, L0.perm, r, E.ctx.r, us);
+  issue_launches(B.iter.L, 0, B.iter.precond_end, B.iter.tab_d, B.desc_d, B.desc_h.data(), 1, B.fp32, us);
+  scatter_rhs(L0.n, 1, L0.perm, E.ctx.z, z, us);
+}
+
+amg_status pcg_batched_run(Hierarchy* const* hs, int nsys, int nrhs, const double* const* b, double* const* x,
+                           double rtol, int maxit, amg_solve_info* info, hipStream_t us) {
+  Batch B;
+  amg_status worst = AMG_OK;
+  try {
+    batch_init(B, nrhs, nsys, hs[0]->p.use_graphs);
+    for (int i = 0; i < nsys; ++i) start_entry(B, i, *hs[i], b[i], x[i], rtol, maxit, i, nullptr, nullptr, us);
+    while ((int)B.results.size() < nsys) step(B);
+    for (const Result& r : B.results) {
+      if (info)
+        for (int k = 0; k < nrhs; ++k) info[(size_t)r.tag * nrhs + k] = r.info[k];
+      if (r.status == AMG_ERR_BREAKDOWN)
+        worst = AMG_ERR_BREAKDOWN;
+      else if (r.status != AMG_OK && worst == AMG_OK)
+        worst = r.status;
+    }
+    AMG_HIP(hipEventRecord(B.ev, B.work));
+    AMG_HIP(hipStreamWaitEvent(us, B.ev, 0));
+  } catch (...) {
+    batch_release(B);
+    throw;
+  }
+  batch_release(B);
+  if (worst == AMG_ERR_NOT_CONVERGED) set_error("maximum number of iterations reached for some system");
+  if (worst == AMG_ERR_BREAKDOWN) set_error("CG breakdown in some system");
+  return worst;
+}
+
+// ------------------------------------------------------------------ continuous batching
+Batch* batch_new(int R, int cap, int use_graphs) {
+  Batch* B = new Batch();
+  try {
+    batch_init(*B, R, cap, use_graphs);
+  } catch (...) {
+    batch_release(*B);
+    delete B;
+    throw;
+  }
+  return B;
+}
+
+int batch_submit(Batch& B, Hierarchy& H, const double* b, double* x, double rtol, int maxit, int64_t tag,
+                 hipStream_t us) {
+  int slot = -1;
+  for (int e = 0; e < B.cap && slot < 0; ++e)
+    if (!B.ent[e].used) slot = e;
+  if (slot < 0) fail(AMG_ERR_INVALID_ARG, "batch is full");
+  start_entry(B, slot, H, b, x, rtol, maxit, tag, nullptr, nullptr, us);
+  return slot;
+}
+
+void batch_step(Batch& B, int iterations) {
+  for (int i = 0; i < iterations; ++i) step(B);
+}
+
+int batch_active(const Batch& B) {
+  int a = 0;
+  for (const Entry& E : B.ent) a += E.used ? 1 : 0;
+  return a;
+}
+
+int batch_poll(Batch& B, int64_t* tags, amg_status* status, amg_solve_info* info, int cap) {
+  const int n = std::min<int>(cap, (int)B.results.size());
+  for (int i = 0; i < n; ++i) {
+    const Result& r = B.results[i];
+    if (tags) tags[i] = r.tag;
+    if (status) status[i] = r.status;
+    if (info)
+      for (int k = 0; k < B.R; ++k) info[(size_t)i * B.R + k] = r.info[k];
+  }
+  B.results.erase(B.results.begin(), B.results.begin() + n);
+  return n;
+}
+
+size_t batch_entry_bytes(const Batch& B) {
+  size_t s = 0;
+  for (const Entry& E : B.ent) s += E.ctx.bytes;
+  return s;
+}
+
+}  // namespace amgx

@@ -1,9 +1,16 @@
-// Solve-phase kernels for gfx950: CSR products, multicolour Gauss-Seidel and
-// l1-Jacobi sweeps, fused residual + restriction per aggregation tile,
-// prolongation with the over-correction factor, the coarsest-level product
-// with the explicit inverse, and the CG vector kernels.  All reductions use a
-// fixed number of partial sums and a fixed tree, so results are reproducible
-// run to run and independent of other work on the device.
+// Solve-phase kernels for gfx950, table driven (see Item / BDesc): SELL-64
+// multicolour Gauss-Seidel and l1-Jacobi sweeps, residual, restriction by
+// aggregate member lists, prolongation with the over-correction factor, the
+// coarsest-level product with the explicit inverse, the FP64 outer product
+// and the CG vector kernels.  Each kernel handles R right-hand sides at once
+// (interleaved vectors): a lane owns one row and keeps R accumulators, so the
+// matrix is read once for all of them and the arithmetic of right-hand side
+// k is the same for every R.  Contraction is off and every multiply-add is an
+// explicit fma, so the code generated for different R rounds identically.
+// Reductions: each block writes one partial sum per right-hand side; the
+// per-entry finish kernel adds an entry's partials in a fixed order.
+#pragma clang fp contract(off)
+
 #include "amg_internal.h"
 
 namespace amgx {
@@ -11,8 +18,37 @@ namespace amgx {
 namespace {
 
 constexpr int WAVE = 64;
+constexpr int NT = 256;  // threads of every solve kernel
 
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+__device__ inline float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double madd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// R consecutive values as one vector access.
+template <typename V, int R>
+__device__ inline void ldv(const V* p, V (&o)[R]) {
+  if constexpr (R == 1) {
+    o[0] = p[0];
+  } else {
+    typedef V vt __attribute__((ext_vector_type(R)));
+    const vt t = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = t[k];
+  }
+}
+template <typename V, int R>
+__device__ inline void stv(V* p, const V (&o)[R]) {
+  if constexpr (R == 1) {
+    p[0] = o[0];
+  } else {
+    typedef V vt __attribute__((ext_vector_type(R)));
+    vt t;
+#pragma unroll
+    for (int k = 0; k < R; ++k) t[k] = o[k];
+    *reinterpret_cast<vt*>(p) = t;
+  }
+}
 
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
@@ -20,613 +56,785 @@ __device__ inline double wave_sum_d(double v) {
   return v;
 }
 
-// Deterministic block sum (RED_THREADS threads): per-wave butterfly, then the
-// wave sums in wave order.
-__device__ inline double block_sum(double v) {
-  __shared__ double ws[RED_THREADS / WAVE];
-  v = wave_sum_d(v);
+// Deterministic block sums of R values (valid in thread 0): per-wave
+// butterfly, then the wave sums in wave order.
+template <int R>
+__device__ inline void block_sums(double (&v)[R]) {
+  __shared__ double ws[NT / WAVE][R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = wave_sum_d(v[k]);
   const int w = threadIdx.x / WAVE;
-  if (__lane_id() == 0) ws[w] = v;
+  if (__lane_id() == 0)
+#pragma unroll
+    for (int k = 0; k < R; ++k) ws[w][k] = v[k];
   __syncthreads();
-  double s = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < RED_THREADS / WAVE; ++i) s += ws[i];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < NT / WAVE; ++i) s += ws[i][k];
+      v[k] = s;
+    }
   __syncthreads();
-  return s;
 }
 
-// ---------------------------------------------------------------- products
+template <int R>
+__device__ inline void write_partials(const BDesc& d, int set, int part, const double (&v)[R]) {
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < R; ++k) d.partial[((size_t)set * RED_BLOCKS + part) * R + k] = v[k];
+}
+
+// Right-hand side k of the entry takes no more CG updates (finished or broken down).
+__device__ inline bool frozen(const BDesc& d, int k) {
+  return d.ctl[1 + k] != 0 || d.scal[k * S_COUNT + S_FLAG] != 0.0;
+}
+
 template <typename V>
-__global__ void k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const V* __restrict__ va,
-                       const V* __restrict__ x, V* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  V s = 0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) s += va[k] * x[ci[k]];
-  y[i] = s;
+struct Mat;
+template <>
+struct Mat<double> {
+  __device__ static const double* sval(const BDesc& d) { return d.sval64; }
+  __device__ static const double* dg(const BDesc& d) { return d.dg64; }
+  __device__ static const double* l1(const BDesc& d) { return d.l164; }
+};
+template <>
+struct Mat<float> {
+  __device__ static const float* sval(const BDesc& d) { return d.sval32; }
+  __device__ static const float* dg(const BDesc& d) { return d.dg32; }
+  __device__ static const float* l1(const BDesc& d) { return d.l132; }
+};
+
+// Work item of this block.  Table launches read it from tab[blockIdx.x] and
+// the descriptor from D (an inactive entry -- finished, awaiting removal from
+// the batch -- returns at once); direct launches (a plan of one entry) get the
+// descriptor by value and split [base.lo, base.hi) into pieces of base.part
+// units per block, the same split the table would hold.
+__device__ inline Item direct_item(const Item& base) {
+  Item it;
+  it.d = base.d;
+  it.lo = base.lo + (int)blockIdx.x * base.part;
+  it.hi = min(base.hi, it.lo + base.part);
+  it.part = (int)blockIdx.x;
+  return it;
 }
 
-// y = A x with partial sums of x.y (grid-stride over a fixed grid).
-__global__ __launch_bounds__(RED_THREADS) void k_spmv_dot(int n, const int* __restrict__ rp,
-                                                          const int* __restrict__ ci, const double* __restrict__ va,
-                                                          const double* __restrict__ x, double* __restrict__ y,
-                                                          double* __restrict__ partial) {
-  double acc = 0.0;
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
-    double s = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) s += va[k] * x[ci[k]];
-    y[i] = s;
-    acc += x[i] * s;
+#define AMG_KARGS const Item *__restrict__ tab, const BDesc *__restrict__ D, const BDesc dv, const Item base
+#define AMG_BODY(BODY, ...)            \
+  if constexpr (DIRECT) {              \
+    const Item it = direct_item(base); \
+    BODY(it, dv, ##__VA_ARGS__);       \
+  } else {                             \
+    const Item it = tab[blockIdx.x];   \
+    const BDesc& d = D[it.d];          \
+    if (d.active == 0) return;         \
+    BODY(it, d, ##__VA_ARGS__);        \
   }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
 
-// r = b - A x with partial sums of r.r.
-__global__ __launch_bounds__(RED_THREADS) void k_residual_dot(int n, const int* __restrict__ rp,
-                                                              const int* __restrict__ ci,
-                                                              const double* __restrict__ va,
-                                                              const double* __restrict__ b,
-                                                              const double* __restrict__ x, double* __restrict__ r,
-                                                              double* __restrict__ partial) {
-  double acc = 0.0;
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
-    double s = b[i];
-    for (int k = rp[i]; k < rp[i + 1]; ++k) s -= va[k] * x[ci[k]];
-    r[i] = s;
-    acc += s * s;
+// ---------------------------------------------------------------- SELL-64
+// Lane t of the wavefront owning slice s reads its off-diagonal entry e at
+// soff[s] + 64 e + t: every matrix load is one contiguous 64-wide access;
+// padding entries are (row, 0).
+template <typename V, int R>
+__device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __restrict__ sval, int base, int w,
+                                    int lane, const V* x, V (&acc)[R]) {
+  const int* cp = scol + base + lane;
+  const V* vp = sval + base + lane;
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0;
+  int e = 0;
+  for (; e + 2 <= w; e += 2) {
+    const int j0 = cp[64 * e], j1 = cp[64 * (e + 1)];
+    const V a0 = vp[64 * e], a1 = vp[64 * (e + 1)];
+    V x0[R], x1[R];
+    ldv<V, R>(x + (size_t)j0 * R, x0);
+    ldv<V, R>(x + (size_t)j1 * R, x1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = madd(a0, x0[k], acc[k]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = madd(a1, x1[k], acc[k]);
   }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-// ---------------------------------------------------------------- smoothers
-// Gauss-Seidel update of the rows of one colour, which occupy the contiguous
-// solve rows [lo, lo+cnt): x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii.
-template <typename V>
-__global__ void k_gs_colour(int lo, int cnt, const int* __restrict__ rp, const int* __restrict__ ci,
-                            const V* __restrict__ va, const V* __restrict__ b, V* __restrict__ x) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  const int i = lo + t;
-  V acc = b[i], d = 1;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const int j = ci[k];
-    const V a = va[k];
-    if (j == i)
-      d = a;
-    else
-      acc -= a * x[j];
+  if (e < w) {
+    const int j0 = cp[64 * e];
+    const V a0 = vp[64 * e];
+    V x0[R];
+    ldv<V, R>(x + (size_t)j0 * R, x0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = madd(a0, x0[k], acc[k]);
   }
-  x[i] = acc / d;
 }
 
-template <typename V>
-__global__ void k_resid(int n, const int* __restrict__ rp, const int* __restrict__ ci, const V* __restrict__ va,
-                        const V* __restrict__ b, const V* __restrict__ x, V* __restrict__ t) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  V acc = b[i];
-  for (int k = rp[i]; k < rp[i + 1]; ++k) acc -= va[k] * x[ci[k]];
-  t[i] = acc;
+// Gauss-Seidel update of the slices [lo, hi) (one per wavefront) of one
+// colour: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.  Rows of one colour do
+// not couple, so the in-place update is race free.
+template <typename V, int R>
+__device__ __forceinline__ void kb_gs_body(const Item& it, const BDesc& d) {
+  const int sl = it.lo + (int)(threadIdx.x / WAVE);
+  if (sl >= it.hi) return;
+  const int lane = __lane_id();
+  const int r = d.srow[sl] + lane;
+  const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
+  V* x = static_cast<V*>(d.x);
+  V acc[R];
+  sell_offdiag<V, R>(d.scol, Mat<V>::sval(d), base, w, lane, x, acc);
+  if (r < d.srow[sl + 1]) {
+    V bb[R], o[R];
+    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+    const V dg = Mat<V>::dg(d)[r];
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = (bb[k] - acc[k]) / dg;
+    stv<V, R>(x + (size_t)r * R, o);
+  }
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_gs(AMG_KARGS) {
+  AMG_BODY((kb_gs_body<V, R>))
 }
 
-template <typename V>
-__global__ void k_jacobi_update(int n, const V* __restrict__ t, const V* __restrict__ d, V* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] += t[i] / d[i];
+// t = b - A x on the slices [lo, hi).
+template <typename V, int R>
+__device__ __forceinline__ void kb_resid_body(const Item& it, const BDesc& d) {
+  const int sl = it.lo + (int)(threadIdx.x / WAVE);
+  if (sl >= it.hi) return;
+  const int lane = __lane_id();
+  const int r = d.srow[sl] + lane;
+  const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
+  const V* x = static_cast<const V*>(d.x);
+  V acc[R];
+  sell_offdiag<V, R>(d.scol, Mat<V>::sval(d), base, w, lane, x, acc);
+  if (r < d.srow[sl + 1]) {
+    V bb[R], xr[R], o[R];
+    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+    ldv<V, R>(x + (size_t)r * R, xr);
+    const V dg = Mat<V>::dg(d)[r];
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = bb[k] - madd(dg, xr[k], acc[k]);
+    stv<V, R>(static_cast<V*>(d.t) + (size_t)r * R, o);
+  }
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_resid(AMG_KARGS) {
+  AMG_BODY((kb_resid_body<V, R>))
 }
 
-// ---------------------------------------------------------------- sub-wave rows
-// SUB consecutive lanes own one row: they read the row's entries as one
-// contiguous stream (a wavefront covers 64/SUB consecutive rows in one
-// coalesced load per entry block) and combine with a SUB-wide butterfly.
-template <int SUB, typename V>
-__device__ inline V group_sum(V v) {
+template <typename V, int R>
+__device__ __forceinline__ void kb_zero_body(const Item& it, const BDesc& d) {
+  V* x = static_cast<V*>(d.x);
+  V z[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) z[k] = 0;
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) stv<V, R>(x + (size_t)i * R, z);
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_zero(AMG_KARGS) {
+  AMG_BODY((kb_zero_body<V, R>))
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void kb_jacobi_body(const Item& it, const BDesc& d) {
+  V* x = static_cast<V*>(d.x);
+  const V* t = static_cast<const V*>(d.t);
+  const V* l1 = Mat<V>::l1(d);
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    V xv[R], tv[R];
+    ldv<V, R>(x + (size_t)i * R, xv);
+    ldv<V, R>(t + (size_t)i * R, tv);
+    const V di = l1[i];
+#pragma unroll
+    for (int k = 0; k < R; ++k) xv[k] = xv[k] + tv[k] / di;
+    stv<V, R>(x + (size_t)i * R, xv);
+  }
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_jacobi(AMG_KARGS) {
+  AMG_BODY((kb_jacobi_body<V, R>))
+}
+
+// b_c[I] = sum of t over the members of aggregate I (ascending), coarse rows [lo, hi).
+template <typename V, int R>
+__device__ __forceinline__ void kb_restrict_body(const Item& it, const BDesc& d) {
+  const int I = it.lo + (int)threadIdx.x;
+  if (I >= it.hi) return;
+  const V* t = static_cast<const V*>(d.t);
+  V s[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) s[k] = 0;
+  for (int p = d.mptr[I]; p < d.mptr[I + 1]; ++p) {
+    V tv[R];
+    ldv<V, R>(t + (size_t)d.members[p] * R, tv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) s[k] += tv[k];
+  }
+  stv<V, R>(static_cast<V*>(d.bc) + (size_t)I * R, s);
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_restrict(AMG_KARGS) {
+  AMG_BODY((kb_restrict_body<V, R>))
+}
+
+// x_i += omega x_c[agg_i], rows [lo, hi).
+template <typename V, int R>
+__device__ __forceinline__ void kb_prolong_body(const Item& it, const BDesc& d) {
+  V* x = static_cast<V*>(d.x);
+  const V* xc = static_cast<const V*>(d.xc);
+  const V om = (V)d.omega;
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    V xv[R], cv[R];
+    ldv<V, R>(x + (size_t)i * R, xv);
+    ldv<V, R>(xc + (size_t)d.agg[i] * R, cv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) xv[k] = madd(om, cv[k], xv[k]);
+    stv<V, R>(x + (size_t)i * R, xv);
+  }
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_prolong(AMG_KARGS) {
+  AMG_BODY((kb_prolong_body<V, R>))
+}
+
+// x = A_L^{-1} b on the coarsest level: one wavefront per row (rows
+// [lo, hi), at most 4), lanes over the contiguous row, FP64 accumulation.
+template <typename V, int R>
+__device__ __forceinline__ void kb_coarse_body(const Item& it, const BDesc& d) {
+  const int i = it.lo + (int)(threadIdx.x / WAVE);
+  if (i >= it.hi) return;
+  const int lane = __lane_id(), n = d.nL;
+  const V* b = static_cast<const V*>(d.b);
+  const double* row = d.Ainv + (size_t)i * n;
+  double s[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) s[k] = 0.0;
+  for (int j = lane; j < n; j += WAVE) {
+    const double a = row[j];
+    V bv[R];
+    ldv<V, R>(b + (size_t)j * R, bv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) s[k] = madd(a, (double)bv[k], s[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) s[k] = wave_sum_d(s[k]);
+  if (lane == 0) {
+    V o[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = (V)s[k];
+    stv<V, R>(static_cast<V*>(d.x) + (size_t)i * R, o);
+  }
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_coarse(AMG_KARGS) {
+  AMG_BODY((kb_coarse_body<V, R>))
+}
+
+// FP32 cycle: level-0 right-hand side = (float) r; z = (double) x.
+template <int R>
+__device__ __forceinline__ void kb_r2b_body(const Item& it, const BDesc& d) {
+  float* b = static_cast<float*>(d.b);
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    double rv[R];
+    float o[R];
+    ldv<double, R>(d.r + (size_t)i * R, rv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = (float)rv[k];
+    stv<float, R>(b + (size_t)i * R, o);
+  }
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_r2b(AMG_KARGS) {
+  AMG_BODY((kb_r2b_body<R>))
+}
+
+template <int R>
+__device__ __forceinline__ void kb_x2z_body(const Item& it, const BDesc& d) {
+  const float* x = static_cast<const float*>(d.x);
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    float xv[R];
+    double o[R];
+    ldv<float, R>(x + (size_t)i * R, xv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = (double)xv[k];
+    stv<double, R>(d.z + (size_t)i * R, o);
+  }
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_x2z(AMG_KARGS) {
+  AMG_BODY((kb_x2z_body<R>))
+}
+
+// ---------------------------------------------------------------- CG vectors
+// Partials of r.z and (flexible) z.(r - r_old) over the rows [lo, hi).
+template <int R>
+__device__ __forceinline__ void kb_dots_rz_body(const Item& it, const BDesc& d) {
+  double a[R], c[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) a[k] = c[k] = 0.0;
+  const bool flex = d.rold != nullptr;
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    double rv[R], zv[R];
+    ldv<double, R>(d.r + (size_t)i * R, rv);
+    ldv<double, R>(d.z + (size_t)i * R, zv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) a[k] = madd(rv[k], zv[k], a[k]);
+    if (flex) {
+      double ov[R];
+      ldv<double, R>(d.rold + (size_t)i * R, ov);
+#pragma unroll
+      for (int k = 0; k < R; ++k) c[k] = madd(zv[k], rv[k] - ov[k], c[k]);
+    }
+  }
+  block_sums<R>(a);
+  block_sums<R>(c);
+  write_partials<R>(d, 0, it.part, a);
+  write_partials<R>(d, 1, it.part, c);
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_dots_rz(AMG_KARGS) {
+  AMG_BODY((kb_dots_rz_body<R>))
+}
+
+// p = z (first direction) or p = z + beta p, rows [lo, hi).
+template <int R>
+__device__ __forceinline__ void kb_update_p_body(const Item& it, const BDesc& d) {
+  bool skip[R], first[R];
+  double beta[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    skip[k] = frozen(d, k);
+    first[k] = d.scal[k * S_COUNT + S_NEWP] != 0.0;
+    beta[k] = d.scal[k * S_COUNT + S_BETA];
+  }
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    double pv[R], zv[R];
+    ldv<double, R>(d.p + (size_t)i * R, pv);
+    ldv<double, R>(d.z + (size_t)i * R, zv);
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      if (!skip[k]) pv[k] = first[k] ? zv[k] : madd(beta[k], pv[k], zv[k]);
+    stv<double, R>(d.p + (size_t)i * R, pv);
+  }
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_update_p(AMG_KARGS) {
+  AMG_BODY((kb_update_p_body<R>))
+}
+
+// q = A p (FP64, SELL slices [lo, hi), wavefront w takes lo + w, lo + w + 4, ...)
+// with partials of p.q.
+template <int R>
+__device__ __forceinline__ void kb_spmv_dot_body(const Item& it, const BDesc& d) {
+  const int lane = __lane_id();
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  for (int sl = it.lo + (int)(threadIdx.x / WAVE); sl < it.hi; sl += NT / WAVE) {
+    const int r = d.srow[sl] + lane;
+    const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
+    double off[R];
+    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.p, off);
+    if (r < d.srow[sl + 1]) {
+      double pr[R], y[R];
+      ldv<double, R>(d.p + (size_t)r * R, pr);
+      const double dg = d.dg64[r];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        y[k] = madd(dg, pr[k], off[k]);
+        acc[k] = madd(pr[k], y[k], acc[k]);
+      }
+      stv<double, R>(d.q + (size_t)r * R, y);
+    }
+  }
+  block_sums<R>(acc);
+  write_partials<R>(d, 0, it.part, acc);
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_spmv_dot(AMG_KARGS) {
+  AMG_BODY((kb_spmv_dot_body<R>))
+}
+
+// out = b - A x (FP64, SELL) with partials of out.out; out is r (which = 0)
+// or q (which = 1), b and x the entry's right-hand side and iterate.
+template <int R>
+__device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d, int which) {
+  const int lane = __lane_id();
+  double* out = which ? d.q : d.r;
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  for (int sl = it.lo + (int)(threadIdx.x / WAVE); sl < it.hi; sl += NT / WAVE) {
+    const int r = d.srow[sl] + lane;
+    const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
+    double off[R];
+    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.xs, off);
+    if (r < d.srow[sl + 1]) {
+      double xr[R], br[R], o[R];
+      ldv<double, R>(d.xs + (size_t)r * R, xr);
+      ldv<double, R>(d.bs + (size_t)r * R, br);
+      const double dg = d.dg64[r];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        o[k] = br[k] - madd(dg, xr[k], off[k]);
+        acc[k] = madd(o[k], o[k], acc[k]);
+      }
+      stv<double, R>(out + (size_t)r * R, o);
+    }
+  }
+  block_sums<R>(acc);
+  write_partials<R>(d, 0, it.part, acc);
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_resid_dot(AMG_KARGS, int which) {
+  AMG_BODY((kb_resid_dot_body<R>), which)
+}
+
+// CSR level 0 (one-level hierarchies): SUB lanes per row read the row as one
+// contiguous stream and combine with a SUB-wide butterfly.
+template <int SUB>
+__device__ inline double group_sum(double v) {
 #pragma unroll
   for (int o = SUB / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SUB);
   return v;
 }
 
-// ---------------------------------------------------------------- SELL-64
-// One wavefront per slice of 64 solve rows: lane t owns row srow[s] + t and
-// reads its off-diagonal entry k at soff[s] + 64 k + t, so every load of the
-// matrix is one contiguous 64-wide access; padding entries are (row, 0).
-template <typename V>
-__device__ inline V sell_offdiag(const int* __restrict__ scol, const V* __restrict__ sval, int base, int w, int lane,
-                                 const V* __restrict__ x) {
-  const int* cp = scol + base + lane;
-  const V* vp = sval + base + lane;
-  V acc = 0;
-  int k = 0;
-  for (; k + 2 <= w; k += 2) {
-    const int j0 = cp[64 * k], j1 = cp[64 * (k + 1)];
-    const V a0 = vp[64 * k], a1 = vp[64 * (k + 1)];
-    acc += a0 * x[j0];
-    acc += a1 * x[j1];
+template <int R, int SUB>
+__device__ inline void csr_row(const BDesc& d, int i, int sl, const double* x, double (&s)[R]) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) s[k] = 0.0;
+  for (int e = d.rowptr[i] + sl; e < d.rowptr[i + 1]; e += SUB) {
+    const double a = d.vals[e];
+    double xv[R];
+    ldv<double, R>(x + (size_t)d.colind[e] * R, xv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) s[k] = madd(a, xv[k], s[k]);
   }
-  if (k < w) acc += vp[64 * k] * x[cp[64 * k]];
-  return acc;
+#pragma unroll
+  for (int k = 0; k < R; ++k) s[k] = group_sum<SUB>(s[k]);
 }
 
-// Gauss-Seidel on the slices [s0, s0+ns) of one colour.
-template <typename V>
-__global__ __launch_bounds__(256) void k_gs_sell(int s0, int ns, const int* __restrict__ srow,
-                                                 const int* __restrict__ soff, const int* __restrict__ scol,
-                                                 const V* __restrict__ sval, const V* __restrict__ dg,
-                                                 const V* __restrict__ b, V* __restrict__ x) {
-  const int sl = s0 + (int)(blockIdx.x * 4 + threadIdx.x / WAVE);
-  if (sl >= s0 + ns) return;
-  const int lane = __lane_id();
-  const int r = srow[sl] + lane;
-  const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
-  const V acc = sell_offdiag<V>(scol, sval, base, w, lane, x);
-  if (r < srow[sl + 1]) x[r] = (b[r] - acc) / dg[r];
-}
-
-// t = b - A x over all slices.
-template <typename V>
-__global__ __launch_bounds__(256) void k_resid_sell(int nsl, const int* __restrict__ srow,
-                                                    const int* __restrict__ soff, const int* __restrict__ scol,
-                                                    const V* __restrict__ sval, const V* __restrict__ dg,
-                                                    const V* __restrict__ b, const V* __restrict__ x,
-                                                    V* __restrict__ t) {
-  const int sl = (int)(blockIdx.x * 4 + threadIdx.x / WAVE);
-  if (sl >= nsl) return;
-  const int lane = __lane_id();
-  const int r = srow[sl] + lane;
-  const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
-  const V acc = sell_offdiag<V>(scol, sval, base, w, lane, x);
-  if (r < srow[sl + 1]) t[r] = b[r] - (dg[r] * x[r] + acc);
-}
-
-// y = A x (FP64) with deterministic partial sums of x.y over a fixed grid.
-__global__ __launch_bounds__(RED_THREADS) void k_spmv_dot_sell(int nsl, const int* __restrict__ srow,
-                                                               const int* __restrict__ soff,
-                                                               const int* __restrict__ scol,
-                                                               const double* __restrict__ sval,
-                                                               const double* __restrict__ dg,
-                                                               const double* __restrict__ x, double* __restrict__ y,
-                                                               double* __restrict__ partial) {
-  const int lane = __lane_id();
-  const int wpb = RED_THREADS / WAVE;
-  double acc = 0.0;
-  for (int sl = blockIdx.x * wpb + threadIdx.x / WAVE; sl < nsl; sl += RED_BLOCKS * wpb) {
-    const int r = srow[sl] + lane;
-    const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
-    const double off = sell_offdiag<double>(scol, sval, base, w, lane, x);
-    if (r < srow[sl + 1]) {
-      const double xr = x[r];
-      const double yr = dg[r] * xr + off;
-      y[r] = yr;
-      acc += xr * yr;
-    }
-  }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-// r = b - A x (FP64) with deterministic partial sums of r.r.
-__global__ __launch_bounds__(RED_THREADS) void k_residual_dot_sell(int nsl, const int* __restrict__ srow,
-                                                                   const int* __restrict__ soff,
-                                                                   const int* __restrict__ scol,
-                                                                   const double* __restrict__ sval,
-                                                                   const double* __restrict__ dg,
-                                                                   const double* __restrict__ b,
-                                                                   const double* __restrict__ x,
-                                                                   double* __restrict__ r,
-                                                                   double* __restrict__ partial) {
-  const int lane = __lane_id();
-  const int wpb = RED_THREADS / WAVE;
-  double acc = 0.0;
-  for (int sl = blockIdx.x * wpb + threadIdx.x / WAVE; sl < nsl; sl += RED_BLOCKS * wpb) {
-    const int i = srow[sl] + lane;
-    const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
-    const double off = sell_offdiag<double>(scol, sval, base, w, lane, x);
-    if (i < srow[sl + 1]) {
-      const double ri = b[i] - (dg[i] * x[i] + off);
-      r[i] = ri;
-      acc += ri * ri;
-    }
-  }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-// y = A x with deterministic partial sums of x.y over a fixed grid.
-template <int SUB>
-__global__ __launch_bounds__(RED_THREADS) void k_spmv_dot_sub(int n, const int* __restrict__ rp,
-                                                              const int* __restrict__ ci,
-                                                              const double* __restrict__ va,
-                                                              const double* __restrict__ x, double* __restrict__ y,
-                                                              double* __restrict__ partial) {
+template <int R, int SUB>
+__device__ __forceinline__ void kb_spmv_dot_csr_body(const Item& it, const BDesc& d) {
   const int sl = threadIdx.x % SUB;
-  const int gpb = RED_THREADS / SUB;
-  double acc = 0.0;
-  for (int i = blockIdx.x * gpb + threadIdx.x / SUB; i < n; i += RED_BLOCKS * gpb) {
-    double s = 0.0;
-    for (int k = rp[i] + sl; k < rp[i + 1]; k += SUB) s += va[k] * x[ci[k]];
-    s = group_sum<SUB>(s);
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  for (int i = it.lo + (int)threadIdx.x / SUB; i < it.hi; i += NT / SUB) {
+    double s[R];
+    csr_row<R, SUB>(d, i, sl, d.p, s);
     if (sl == 0) {
-      y[i] = s;
-      acc += x[i] * s;
+      double pr[R];
+      ldv<double, R>(d.p + (size_t)i * R, pr);
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc[k] = madd(pr[k], s[k], acc[k]);
+      stv<double, R>(d.q + (size_t)i * R, s);
     }
   }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  block_sums<R>(acc);
+  write_partials<R>(d, 0, it.part, acc);
+}
+template <int R, int SUB, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_spmv_dot_csr(AMG_KARGS) {
+  AMG_BODY((kb_spmv_dot_csr_body<R, SUB>))
 }
 
-// r = b - A x with deterministic partial sums of r.r.
-template <int SUB>
-__global__ __launch_bounds__(RED_THREADS) void k_residual_dot_sub(int n, const int* __restrict__ rp,
-                                                                  const int* __restrict__ ci,
-                                                                  const double* __restrict__ va,
-                                                                  const double* __restrict__ b,
-                                                                  const double* __restrict__ x,
-                                                                  double* __restrict__ r, double* __restrict__ partial) {
+template <int R, int SUB>
+__device__ __forceinline__ void kb_resid_dot_csr_body(const Item& it, const BDesc& d, int which) {
   const int sl = threadIdx.x % SUB;
-  const int gpb = RED_THREADS / SUB;
-  double acc = 0.0;
-  for (int i = blockIdx.x * gpb + threadIdx.x / SUB; i < n; i += RED_BLOCKS * gpb) {
-    double s = 0.0;
-    for (int k = rp[i] + sl; k < rp[i + 1]; k += SUB) s += va[k] * x[ci[k]];
-    s = group_sum<SUB>(s);
+  double* out = which ? d.q : d.r;
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  for (int i = it.lo + (int)threadIdx.x / SUB; i < it.hi; i += NT / SUB) {
+    double s[R];
+    csr_row<R, SUB>(d, i, sl, d.xs, s);
     if (sl == 0) {
-      const double ri = b[i] - s;
-      r[i] = ri;
-      acc += ri * ri;
+      double br[R], o[R];
+      ldv<double, R>(d.bs + (size_t)i * R, br);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        o[k] = br[k] - s[k];
+        acc[k] = madd(o[k], o[k], acc[k]);
+      }
+      stv<double, R>(out + (size_t)i * R, o);
     }
   }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  block_sums<R>(acc);
+  write_partials<R>(d, 0, it.part, acc);
+}
+template <int R, int SUB, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_resid_dot_csr(AMG_KARGS, int which) {
+  AMG_BODY((kb_resid_dot_csr_body<R, SUB>), which)
 }
 
-// Dispatch on the lanes-per-row width chosen for a level.
-#define AMG_SUB_DISPATCH(SUBV, KERNEL_CALL) \
-  switch (SUBV) {                           \
-    case 4: {                               \
-      constexpr int SUB = 4;                \
-      KERNEL_CALL;                          \
-    } break;                                \
-    case 8: {                               \
-      constexpr int SUB = 8;                \
-      KERNEL_CALL;                          \
-    } break;                                \
-    case 16: {                              \
-      constexpr int SUB = 16;               \
-      KERNEL_CALL;                          \
-    } break;                                \
-    case 32: {                              \
-      constexpr int SUB = 32;               \
-      KERNEL_CALL;                          \
-    } break;                                \
-    default: {                              \
-      constexpr int SUB = 64;               \
-      KERNEL_CALL;                          \
-    } break;                                \
+// x += alpha p; r_old = r (flexible); r -= alpha q; partials of r.r, rows
+// [lo, hi).  A frozen right-hand side keeps x, r and r_old.
+template <int R>
+__device__ __forceinline__ void kb_update_xr_body(const Item& it, const BDesc& d) {
+  bool skip[R], anyskip = false;
+  double alpha[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    skip[k] = frozen(d, k);
+    anyskip |= skip[k];
+    alpha[k] = d.scal[k * S_COUNT + S_ALPHA];
   }
-
-// ---------------------------------------------------------------- transfers
-// b_c[I] = sum over the members of aggregate I (ascending natural order) of the
-// residual t computed by k_resid.
-template <typename V>
-__global__ void k_restrict(int nc, const int* __restrict__ mptr, const int* __restrict__ members,
-                           const V* __restrict__ t, V* __restrict__ bc) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  V s = 0;
-  for (int p = mptr[I]; p < mptr[I + 1]; ++p) s += t[members[p]];
-  bc[I] = s;
-}
-
-template <typename V>
-__global__ void k_prolong(int n, const int* __restrict__ agg, const V* __restrict__ xc, V* __restrict__ x, V omega) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] += omega * xc[agg[i]];
-}
-
-// x = A_L^{-1} b with the explicit inverse: one wavefront per row, lanes over
-// the (contiguous) row, butterfly sum.
-template <typename Vin, typename Vout>
-__global__ __launch_bounds__(256) void k_coarse_gemv(int n, const double* __restrict__ Ainv,
-                                                     const Vin* __restrict__ b, Vout* __restrict__ x) {
-  const int i = blockIdx.x * 4 + threadIdx.x / WAVE;
-  if (i >= n) return;
-  const int lane = __lane_id();
-  double s = 0.0;
-  const double* row = Ainv + (size_t)i * n;
-  for (int j = lane; j < n; j += WAVE) s += row[j] * (double)b[j];
-  s = wave_sum_d(s);
-  if (lane == 0) x[i] = (Vout)s;
-}
-
-template <typename V>
-__global__ void k_zero(int n, V* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = 0;
-}
-
-template <typename A, typename B>
-__global__ void k_convert(int n, const A* __restrict__ in, B* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (B)in[i];
-}
-
-// ---------------------------------------------------------------- CG vectors
-// x += alpha p; r_old = r (flexible); r -= alpha q; partial sums of r.r.
-// A set breakdown flag turns the update into a no-op.
-__global__ __launch_bounds__(RED_THREADS) void k_cg_update_xr(int n, double* __restrict__ x, double* __restrict__ r,
-                                                              double* __restrict__ rold,
-                                                              const double* __restrict__ p,
-                                                              const double* __restrict__ q,
-                                                              const double* __restrict__ scal,
-                                                              double* __restrict__ partial) {
-  const bool skip = scal[S_FLAG] != 0.0;
-  const double alpha = scal[S_ALPHA];
-  double acc = 0.0;
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
-    double ri = r[i];
-    if (!skip) {
-      x[i] += alpha * p[i];
-      if (rold) rold[i] = ri;
-      ri -= alpha * q[i];
-      r[i] = ri;
+  const bool flex = d.rold != nullptr;
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    double xv[R], rv[R], pv[R], qv[R], ov[R];
+    ldv<double, R>(d.xs + (size_t)i * R, xv);
+    ldv<double, R>(d.r + (size_t)i * R, rv);
+    ldv<double, R>(d.p + (size_t)i * R, pv);
+    ldv<double, R>(d.q + (size_t)i * R, qv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      ov[k] = rv[k];
+      if (!skip[k]) {
+        xv[k] = madd(alpha[k], pv[k], xv[k]);
+        rv[k] = madd(-alpha[k], qv[k], rv[k]);
+      }
+      acc[k] = madd(rv[k], rv[k], acc[k]);
     }
-    acc += ri * ri;
+    stv<double, R>(d.xs + (size_t)i * R, xv);
+    stv<double, R>(d.r + (size_t)i * R, rv);
+    if (flex) {
+      if (anyskip) {
+        double keep[R];
+        ldv<double, R>(d.rold + (size_t)i * R, keep);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          if (!skip[k]) keep[k] = ov[k];
+        stv<double, R>(d.rold + (size_t)i * R, keep);
+      } else {
+        stv<double, R>(d.rold + (size_t)i * R, ov);
+      }
+    }
   }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  block_sums<R>(acc);
+  write_partials<R>(d, 0, it.part, acc);
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_update_xr(AMG_KARGS) {
+  AMG_BODY((kb_update_xr_body<R>))
 }
 
-// partial sums of r.z and (flexible) z.(r - r_old) into partial[0..B) and [B..2B).
-__global__ __launch_bounds__(RED_THREADS) void k_cg_dots_rz(int n, const double* __restrict__ r,
-                                                            const double* __restrict__ z,
-                                                            const double* __restrict__ rold,
-                                                            double* __restrict__ partial) {
-  double a = 0.0, c = 0.0;
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
-    const double zi = z[i], ri = r[i];
-    a += ri * zi;
-    if (rold) c += zi * (ri - rold[i]);
+template <int R>
+__device__ __forceinline__ void kb_dot_bb_body(const Item& it, const BDesc& d) {
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+    double bv[R];
+    ldv<double, R>(d.bs + (size_t)i * R, bv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = madd(bv[k], bv[k], acc[k]);
   }
-  const double ta = block_sum(a);
-  const double tc = block_sum(c);
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x] = ta;
-    partial[RED_BLOCKS + blockIdx.x] = tc;
-  }
+  block_sums<R>(acc);
+  write_partials<R>(d, 0, it.part, acc);
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_dot_bb(AMG_KARGS) {
+  AMG_BODY((kb_dot_bb_body<R>))
 }
 
-__global__ void k_cg_update_p(int n, double* __restrict__ p, const double* __restrict__ z,
-                              const double* __restrict__ scal) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || scal[S_FLAG] != 0.0) return;
-  p[i] = z[i] + scal[S_BETA] * p[i];
+template <int R>
+__device__ __forceinline__ void kb_vzero_rold_body(const Item& it, const BDesc& d) {
+  double z[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) z[k] = 0.0;
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) stv<double, R>(d.rold + (size_t)i * R, z);
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_vzero_rold(AMG_KARGS) {
+  AMG_BODY((kb_vzero_rold_body<R>))
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_dot(int n, const double* __restrict__ a,
-                                                     const double* __restrict__ b, double* __restrict__ partial) {
-  double acc = 0.0;
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) acc += a[i] * b[i];
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(RED_THREADS) void k_finish(const double* __restrict__ partial, int nparts,
-                                                        double* __restrict__ scal, int slot, int op) {
-  double a = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += RED_THREADS) {
-    a += partial[i];
-    if (op == FIN_BETA_FCG) c += partial[RED_BLOCKS + i];
+// One block per entry: sums the entry's it.lo partials per right-hand side in
+// index order (fixed tree) and applies the scalar step `op`.
+template <int R>
+__device__ __forceinline__ void kb_finish_body(const Item& it, const BDesc& d, int op, int slot) {
+  const int nparts = it.lo;
+  double a[R], c[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) a[k] = c[k] = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      a[k] += d.partial[(size_t)i * R + k];
+      if (op == FIN_BETA_FCG) c[k] += d.partial[((size_t)RED_BLOCKS + i) * R + k];
+    }
   }
-  a = block_sum(a);
-  c = block_sum(c);
+  block_sums<R>(a);
+  block_sums<R>(c);
   if (threadIdx.x != 0) return;
-  switch (op) {
-    case FIN_STORE:
-      scal[slot] = a;
-      break;
-    case FIN_ALPHA:
-      scal[S_PQ] = a;
-      if (!(a > 0.0)) scal[S_FLAG] = 1.0;
-      scal[S_ALPHA] = scal[S_RHO] / a;
-      break;
-    case FIN_RHO_INIT:
-      scal[S_RHO] = a;
-      if (!(a > 0.0)) scal[S_FLAG] = 1.0;
-      break;
-    case FIN_BETA_PCG:
-    case FIN_BETA_FCG: {
-      scal[S_RZ] = a;
-      scal[S_ZDR] = c;
-      if (!(a > 0.0)) {
-        scal[S_FLAG] = 1.0;
+  for (int k = 0; k < R; ++k) {
+    double* sc = d.scal + k * S_COUNT;
+    switch (op) {
+      case FIN_STORE:
+        sc[slot] = a[k];
+        break;
+      case FIN_INIT:
+        sc[S_R0] = a[k];
+        sc[S_RR] = a[k];
+        sc[S_NEWP] = 1.0;
+        sc[S_FLAG] = 0.0;
+        break;
+      case FIN_ALPHA:
+        if (d.ctl[1 + k] != 0) break;
+        sc[S_PQ] = a[k];
+        if (!(a[k] > 0.0)) sc[S_FLAG] = 1.0;
+        sc[S_ALPHA] = sc[S_RHO] / a[k];
+        sc[S_NEWP] = 0.0;
+        break;
+      case FIN_BETA_PCG:
+      case FIN_BETA_FCG: {
+        if (d.ctl[1 + k] != 0) break;
+        sc[S_RZ] = a[k];
+        sc[S_ZDR] = c[k];
+        if (!(a[k] > 0.0)) sc[S_FLAG] = 1.0;
+        if (sc[S_NEWP] != 0.0)
+          sc[S_BETA] = 0.0;
+        else if (a[k] > 0.0)
+          sc[S_BETA] = (op == FIN_BETA_FCG ? c[k] : a[k]) / sc[S_RHO];
+        sc[S_RHO] = a[k];
         break;
       }
-      const double rho = scal[S_RHO];
-      scal[S_BETA] = (op == FIN_BETA_FCG ? c : a) / rho;
-      scal[S_RHO] = a;
+    }
+  }
+}
+template <int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_finish(AMG_KARGS, int op, int slot) {
+  AMG_BODY((kb_finish_body<R>), op, slot)
+}
+
+// ---------------------------------------------------------------- user vectors
+// out[r * R + k] = in[k * n + perm[r]]
+__global__ void k_gather_rhs(int n, int R, const int* __restrict__ perm, const double* __restrict__ in,
+                             double* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * R) return;
+  const int r = (int)(e / R), k = (int)(e % R);
+  out[e] = in[(size_t)k * n + (perm ? perm[r] : r)];
+}
+
+__global__ void k_scatter_rhs(int n, int R, const int* __restrict__ perm, const double* __restrict__ in,
+                              double* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * R) return;
+  const int r = (int)(e / R), k = (int)(e % R);
+  out[(size_t)k * n + (perm ? perm[r] : r)] = in[e];
+}
+
+#define AMG_SUB_DISPATCH(SUBV, CALL) \
+  switch (SUBV) {                    \
+    case 4: {                        \
+      constexpr int SUB = 4;         \
+      CALL;                          \
+    } break;                         \
+    case 8: {                        \
+      constexpr int SUB = 8;         \
+      CALL;                          \
+    } break;                         \
+    case 16: {                       \
+      constexpr int SUB = 16;        \
+      CALL;                          \
+    } break;                         \
+    case 32: {                       \
+      constexpr int SUB = 32;        \
+      CALL;                          \
+    } break;                         \
+    default: {                       \
+      constexpr int SUB = 64;        \
+      CALL;                          \
+    } break;                         \
+  }
+
+#define AMG_STRIP(...) __VA_ARGS__
+// Launches the direct or the table variant of kernel KNAME<TARGS..., DIRECT>.
+#define AMG_LAUNCH(KNAME, TARGS, ...)                                                                  \
+  do {                                                                                                 \
+    if (L.use_direct)                                                                                  \
+      hipLaunchKernelGGL((KNAME<AMG_STRIP TARGS, true>), g, b, 0, s, nullptr, nullptr, Dh[L.direct.d], \
+                         L.direct, ##__VA_ARGS__);                                                     \
+    else                                                                                               \
+      hipLaunchKernelGGL((KNAME<AMG_STRIP TARGS, false>), g, b, 0, s, t, D, BDesc{}, Item{}, ##__VA_ARGS__); \
+  } while (0)
+
+template <typename V, int R>
+void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, hipStream_t s) {
+  const dim3 g(L.nblk), b(NT);
+  switch (L.op) {
+    case OP_ZERO: AMG_LAUNCH(kb_zero, (V, R)); break;
+    case OP_GS: AMG_LAUNCH(kb_gs, (V, R)); break;
+    case OP_RESID: AMG_LAUNCH(kb_resid, (V, R)); break;
+    case OP_JACOBI: AMG_LAUNCH(kb_jacobi, (V, R)); break;
+    case OP_RESTRICT: AMG_LAUNCH(kb_restrict, (V, R)); break;
+    case OP_PROLONG: AMG_LAUNCH(kb_prolong, (V, R)); break;
+    case OP_COARSE: AMG_LAUNCH(kb_coarse, (V, R)); break;
+    default: fail(AMG_ERR_HIP, "unknown cycle launch");
+  }
+}
+
+template <int R>
+void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, int fp32, hipStream_t s) {
+  const dim3 g(L.nblk), b(NT);
+  switch (L.op) {
+    case OP_ZERO:
+    case OP_GS:
+    case OP_RESID:
+    case OP_JACOBI:
+    case OP_RESTRICT:
+    case OP_PROLONG:
+    case OP_COARSE:
+      if (fp32)
+        launch_cycle_op<float, R>(L, t, D, Dh, s);
+      else
+        launch_cycle_op<double, R>(L, t, D, Dh, s);
       break;
-    }
+    case OP_R2B: AMG_LAUNCH(kb_r2b, (R)); break;
+    case OP_X2Z: AMG_LAUNCH(kb_x2z, (R)); break;
+    case OP_DOTS_RZ: AMG_LAUNCH(kb_dots_rz, (R)); break;
+    case OP_UPDATE_P: AMG_LAUNCH(kb_update_p, (R)); break;
+    case OP_SPMV_DOT: AMG_LAUNCH(kb_spmv_dot, (R)); break;
+    case OP_SPMV_DOT_CSR: AMG_SUB_DISPATCH(L.aux, AMG_LAUNCH(kb_spmv_dot_csr, (R, SUB))); break;
+    case OP_UPDATE_XR: AMG_LAUNCH(kb_update_xr, (R)); break;
+    case OP_RESID_DOT: AMG_LAUNCH(kb_resid_dot, (R), L.aux); break;
+    case OP_RESID_DOT_CSR: AMG_SUB_DISPATCH(L.aux2, AMG_LAUNCH(kb_resid_dot_csr, (R, SUB), L.aux)); break;
+    case OP_DOT_BB: AMG_LAUNCH(kb_dot_bb, (R)); break;
+    case OP_VZERO_ROLD: AMG_LAUNCH(kb_vzero_rold, (R)); break;
+    case OP_FINISH: AMG_LAUNCH(kb_finish, (R), L.aux, L.aux2); break;
+    default: fail(AMG_ERR_HIP, "unknown launch");
   }
-}
-
-// ---------------------------------------------------------------- level access
-template <typename V>
-struct LV;
-template <>
-struct LV<double> {
-  static const double* svals(const Level& L) { return L.sval; }
-  static const double* diag(const Level& L) { return L.dg; }
-  static const double* vals(const Level& L) { return L.vals; }
-  static double* x(Level& L) { return L.x64; }
-  static double* b(Level& L) { return L.b64; }
-  static double* t(Level& L) { return L.t64; }
-  static const double* l1(const Level& L) { return L.l1; }
-};
-template <>
-struct LV<float> {
-  static const float* svals(const Level& L) { return L.sval32; }
-  static const float* diag(const Level& L) { return L.dg32; }
-  static const float* vals(const Level& L) { return L.vals32; }
-  static float* x(Level& L) { return L.x32; }
-  static float* b(Level& L) { return L.b32; }
-  static float* t(Level& L) { return L.t32; }
-  static const float* l1(const Level& L) { return L.l1_32; }
-};
-
-inline int kind_of(int l, int k) { return l == 0 ? k : AMG_KIND_COARSE_LEVELS; }
-
-template <typename V>
-double slice_bytes(const Level& L, int s0, int s1) {  // algorithmic bytes of a pass over slices [s0, s1)
-  const double vb = sizeof(V);
-  const double ent = (double)(L.soff_h[s1] - L.soff_h[s0]);
-  const double rows = (double)(L.srow_h[s1] - L.srow_h[s0]);
-  return ent * (4.0 + vb) + rows * 4.0 * vb + (s1 - s0) * 8.0;  // entries; b, diag, x read, x write; slice headers
-}
-
-template <typename V>
-void smooth(Hierarchy& H, int l, const V* b, V* x, hipStream_t s) {
-  Level& L = H.lev[l];
-  const V* va = LV<V>::svals(L);
-  const V* dg = LV<V>::diag(L);
-  if (H.p.smoother == AMG_SMOOTHER_MCSGS) {
-    for (int dir = 0; dir < 2; ++dir)
-      for (int q = 0; q < L.ncol; ++q) {
-        const int c = dir == 0 ? q : L.ncol - 1 - q;
-        const int s0 = L.sptr[c], ns = L.sptr[c + 1] - s0;
-        if (!ns) continue;
-        KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, slice_bytes<V>(L, s0, s0 + ns));
-        hipLaunchKernelGGL(k_gs_sell<V>, dim3(cdiv(ns, 4)), dim3(256), 0, s, s0, ns, L.srow, L.soff, L.scol, va, dg, b,
-                           x);
-      }
-  } else {
-    V* t = LV<V>::t(L);
-    {
-      KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, slice_bytes<V>(L, 0, L.nsl));
-      hipLaunchKernelGGL(k_resid_sell<V>, dim3(cdiv(L.nsl, 4)), dim3(256), 0, s, L.nsl, L.srow, L.soff, L.scol, va, dg,
-                         b, x, t);
-    }
-    {
-      KTimer tm(kind_of(l, AMG_KIND_SWEEP), s, L.n * 4.0 * sizeof(V));
-      hipLaunchKernelGGL(k_jacobi_update<V>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, t, LV<V>::l1(L), x);
-    }
-  }
-  AMG_HIP(hipGetLastError());
 }
 
 }  // namespace
 
-template <typename V>
-void vcycle(Hierarchy& H, int l, const V* b, V* x, hipStream_t s) {
-  const int Lc = (int)H.lev.size() - 1;
-  Level& L = H.lev[l];
-  if (l == Lc) {
-    KTimer tm(kind_of(l, AMG_KIND_COARSE_LEVELS), s, 8.0 * H.nL * H.nL);
-    hipLaunchKernelGGL((k_coarse_gemv<V, V>), dim3(cdiv(H.nL, 4)), dim3(256), 0, s, H.nL, H.Ainv, b, x);
-    AMG_HIP(hipGetLastError());
-    return;
-  }
-  const double vb = sizeof(V);
-  hipLaunchKernelGGL(k_zero<V>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, x);
-  for (int k = 0; k < H.p.pre_sweeps; ++k) smooth<V>(H, l, b, x, s);
-  Level& C = H.lev[l + 1];
-  {
-    KTimer tm(kind_of(l, AMG_KIND_RESTRICT), s, slice_bytes<V>(L, 0, L.nsl));
-    hipLaunchKernelGGL(k_resid_sell<V>, dim3(cdiv(L.nsl, 4)), dim3(256), 0, s, L.nsl, L.srow, L.soff, L.scol,
-                       LV<V>::svals(L), LV<V>::diag(L), b, x, LV<V>::t(L));
-  }
-  {
-    KTimer tm(kind_of(l, AMG_KIND_RESTRICT), s, L.n * (4.0 + vb) + L.nc * (4.0 + vb));
-    hipLaunchKernelGGL(k_restrict<V>, dim3(cdiv(L.nc, 256)), dim3(256), 0, s, L.nc, L.mptr, L.members, LV<V>::t(L),
-                       LV<V>::b(C));
-    AMG_HIP(hipGetLastError());
-  }
-  vcycle<V>(H, l + 1, LV<V>::b(C), LV<V>::x(C), s);
-  {
-    KTimer tm(kind_of(l, AMG_KIND_PROLONG), s, L.n * (4.0 + 2 * vb) + L.nc * vb);
-    hipLaunchKernelGGL(k_prolong<V>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, L.agg, LV<V>::x(C), x,
-                       (V)H.p.omega);
-    AMG_HIP(hipGetLastError());
-  }
-  for (int k = 0; k < H.p.post_sweeps; ++k) smooth<V>(H, l, b, x, s);
-}
-
-template void vcycle<double>(Hierarchy&, int, const double*, double*, hipStream_t);
-template void vcycle<float>(Hierarchy&, int, const float*, float*, hipStream_t);
-
-void precond_apply(Hierarchy& H, const double* r, double* z, hipStream_t s) {
-  if (!H.p.vcycle_fp32) {
-    vcycle<double>(H, 0, r, z, s);
-    return;
-  }
-  Level& L = H.lev[0];
-  const int n = L.n;
-  {
-    KTimer tm(AMG_KIND_CG_VEC, s, 12.0 * n);
-    hipLaunchKernelGGL((k_convert<double, float>), dim3(cdiv(n, 256)), dim3(256), 0, s, n, r, L.b32);
-  }
-  vcycle<float>(H, 0, L.b32, L.x32, s);
-  {
-    KTimer tm(AMG_KIND_CG_VEC, s, 12.0 * n);
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.x32, z);
+void issue_launches(const std::vector<Launch>& Ls, size_t first, size_t last, const Item* tab, const BDesc* D,
+                    const BDesc* Dh, int R, int fp32, hipStream_t s) {
+  for (size_t i = first; i < last; ++i) {
+    const Launch& L = Ls[i];
+    if (L.nblk <= 0) continue;
+    KTimer tm(L.kind, s, L.bytes);
+    const Item* t = tab + L.off;
+    switch (R) {
+      case 1: launch_r<1>(L, t, D, Dh, fp32, s); break;
+      case 2: launch_r<2>(L, t, D, Dh, fp32, s); break;
+      case 4: launch_r<4>(L, t, D, Dh, fp32, s); break;
+      case 8: launch_r<8>(L, t, D, Dh, fp32, s); break;
+      default: fail(AMG_ERR_UNSUPPORTED, "right-hand sides per entry must be 1, 2, 4 or 8");
+    }
   }
   AMG_HIP(hipGetLastError());
 }
 
-void spmv64(const Level& L, const double* x, double* y, double* partial, hipStream_t s, int kind) {
-  KTimer tm(kind, s, 12.0 * L.nnz + 4.0 * (L.n + 1) + 16.0 * L.n);
-  if (!partial && L.scol) fail(AMG_ERR_HIP, "spmv64 on SELL level needs a partial buffer");
-  if (L.scol) {
-    hipLaunchKernelGGL(k_spmv_dot_sell, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.nsl, L.srow, L.soff, L.scol,
-                       L.sval, L.dg, x, y, partial);
-  } else if (partial) {
-    AMG_SUB_DISPATCH(L.sub, hipLaunchKernelGGL(k_spmv_dot_sub<SUB>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.n,
-                                               L.rowptr, L.colind, L.vals, x, y, partial));
-  } else
-    hipLaunchKernelGGL(k_spmv<double>, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.n, L.rowptr, L.colind, L.vals, x, y);
+void gather_rhs(int n, int R, const int* perm, const double* in, double* out, hipStream_t s) {
+  const long long e = (long long)n * R;
+  hipLaunchKernelGGL(k_gather_rhs, dim3(cdiv(e, 256)), dim3(256), 0, s, n, R, perm, in, out);
   AMG_HIP(hipGetLastError());
 }
 
-void residual64(const Level& L, const double* b, const double* x, double* r, double* partial, hipStream_t s) {
-  KTimer tm(AMG_KIND_CG_VEC, s, 12.0 * L.nnz + 4.0 * (L.n + 1) + 24.0 * L.n);
-  if (L.scol) {
-    hipLaunchKernelGGL(k_residual_dot_sell, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.nsl, L.srow, L.soff, L.scol,
-                       L.sval, L.dg, b, x, r, partial);
-  } else {
-    AMG_SUB_DISPATCH(L.sub, hipLaunchKernelGGL(k_residual_dot_sub<SUB>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, L.n,
-                                               L.rowptr, L.colind, L.vals, b, x, r, partial));
-  }
-  AMG_HIP(hipGetLastError());
-}
-
-void cg_update_xr(int n, double* x, double* r, double* rold, const double* p, const double* q, const double* scal,
-                  double* partial, hipStream_t s) {
-  KTimer tm(AMG_KIND_CG_VEC, s, (rold ? 56.0 : 48.0) * n);
-  hipLaunchKernelGGL(k_cg_update_xr, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, n, x, r, rold, p, q, scal, partial);
-  AMG_HIP(hipGetLastError());
-}
-
-void cg_dots_rz(int n, const double* r, const double* z, const double* rold, double* partial, hipStream_t s) {
-  KTimer tm(AMG_KIND_CG_VEC, s, (rold ? 24.0 : 16.0) * n);
-  hipLaunchKernelGGL(k_cg_dots_rz, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, n, r, z, rold, partial);
-  AMG_HIP(hipGetLastError());
-}
-
-void cg_update_p(int n, double* p, const double* z, const double* scal, hipStream_t s) {
-  KTimer tm(AMG_KIND_CG_VEC, s, 24.0 * n);
-  hipLaunchKernelGGL(k_cg_update_p, dim3(cdiv(n, 256)), dim3(256), 0, s, n, p, z, scal);
-  AMG_HIP(hipGetLastError());
-}
-
-void dot_partial(int n, const double* a, const double* b, double* partial, hipStream_t s) {
-  KTimer tm(AMG_KIND_CG_VEC, s, 16.0 * n);
-  hipLaunchKernelGGL(k_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, n, a, b, partial);
-  AMG_HIP(hipGetLastError());
-}
-
-void finish(double* partial, int nparts, double* scal, int slot, int op, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(RED_THREADS), 0, s, partial, nparts, scal, slot, op);
+void scatter_rhs(int n, int R, const int* perm, const double* in, double* out, hipStream_t s) {
+  const long long e = (long long)n * R;
+  hipLaunchKernelGGL(k_scatter_rhs, dim3(cdiv(e, 256)), dim3(256), 0, s, n, R, perm, in, out);
   AMG_HIP(hipGetLastError());
 }
 
