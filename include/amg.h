@@ -199,6 +199,15 @@ AMG_API amg_status amg_set_allocator(amg_alloc_fn alloc, amg_free_fn free_fn, vo
 /* Device bytes held by the hierarchy. */
 AMG_API amg_status amg_hierarchy_bytes(const amg_hierarchy *h, size_t *bytes);
 
+/* Device memory estimate (upper estimate for 7-point-like operators with
+ * aggregates of 8-12 rows; grows with coarse-level fill for denser
+ * matrices) for a hierarchy of an n x n matrix with nnz entries under
+ * parameters p: peak during amg_setup, held by the hierarchy afterwards, and
+ * held by one solve with nrhs right-hand sides (each output nullable).  No
+ * device work; used for admission by memory footprint. */
+AMG_API amg_status amg_estimate_bytes(int32_t n, int32_t nnz, const amg_params *p, int32_t nrhs,
+                                      size_t *setup_peak, size_t *hierarchy, size_t *context);
+
 /* Number of levels (level 0 is the input matrix). */
 AMG_API amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels);
 

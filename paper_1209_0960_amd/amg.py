@@ -106,6 +106,8 @@ def lib():
         L.pcg_solve_batched.restype = st
         L.pcg_solve_batched.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(vp), C.POINTER(vp), C.c_double, i32,
                                         C.POINTER(SolveInfo), vp]
+        L.amg_estimate_bytes.restype = st
+        L.amg_estimate_bytes.argtypes = [i32, i32, C.POINTER(Params), i32] + [C.POINTER(C.c_size_t)] * 3
         L.amg_batch_create.restype = st
         L.amg_batch_create.argtypes = [i32, i32, i32, C.POINTER(vp)]
         L.amg_batch_submit.restype = st
@@ -195,6 +197,14 @@ def pcg_solve_batched(handles, bs, xs, nrhs: int = 1, rtol: float = 1e-8, maxit:
     if st not in (OK, ERR_NOT_CONVERGED):
         _check(st)
     return st, [[_info_dict(info[s * nrhs + k]) for k in range(nrhs)] for s in range(ns)]
+
+
+def estimate_bytes(n: int, nnz: int, params: Params | None = None, nrhs: int = 1) -> dict:
+    """amg_estimate_bytes: dict(setup_peak, hierarchy, context) in bytes."""
+    p = params if params is not None else default_params()
+    a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    _check(lib().amg_estimate_bytes(n, nnz, C.byref(p), nrhs, C.byref(a), C.byref(b), C.byref(c)))
+    return dict(setup_peak=a.value, hierarchy=b.value, context=c.value)
 
 
 def _info_dict(i: SolveInfo) -> dict:

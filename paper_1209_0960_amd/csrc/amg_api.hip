@@ -645,6 +645,36 @@ void amg_batch_free(amg_batch* b) {
   delete b;
 }
 
+amg_status amg_estimate_bytes(int32_t n, int32_t nnz, const amg_params* p, int32_t nrhs, size_t* setup_peak,
+                              size_t* hierarchy, size_t* context) {
+  if (n <= 0 || nnz < n || !p || nrhs < 1) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  const double N = n, Z = nnz;
+  const bool f32 = p->vcycle_fp32 != 0;
+  const bool flex = p->flexible < 0 ? f32 : p->flexible != 0;
+  const double vb = f32 ? 4.0 : 8.0;
+  // Level 0 in solve order: SELL-64 off-diagonals (column + FP64 value, + FP32
+  // copy), diagonal(s), permutation, row pointers, aggregate map and members.
+  const double lev0 = f32 ? 16.0 * Z + 12.0 * N : 12.0 * Z + 16.0 * N;
+  // Coarser levels and slice padding stay below 35% of level 0 for aggregates
+  // of 8-12 rows; the dense coarsest inverse and its factorisation workspace.
+  const double cm = std::min<double>(std::max(p->coarse_max, 1), 4096);
+  const double dense = 3.0 * 8.0 * cm * cm;
+  const double hier = 1.35 * lev0 + dense;
+  // Setup holds the input copy, strength flags, aggregation and Galerkin
+  // temporaries and the relabelled copies of a level at once.
+  const double peak = std::max(36.0 * Z + 8.0 * N, hier) + dense;
+  // Per solve: CG vectors (x, b, r, z, p, q, and r_old for flexible CG) and the
+  // cycle's x, b, t on every level (levels below 0 add at most 20%).
+  const double ctx = nrhs * N * (8.0 * (6 + (flex ? 1 : 0)) + 3.6 * vb) + 2.0 * RED_BLOCKS * nrhs * 8.0 + 65536.0;
+  if (setup_peak) *setup_peak = (size_t)peak;
+  if (hierarchy) *hierarchy = (size_t)hier;
+  if (context) *context = (size_t)ctx;
+  return AMG_OK;
+}
+
 amg_status amg_set_kernel_timing(int32_t kind_mask) {
   std::lock_guard<std::mutex> g(g_tmu);
   g_timing = kind_mask;

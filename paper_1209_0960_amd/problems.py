@@ -251,3 +251,149 @@ def batched_systems(count: int = 64, seed: int = 3, edges=(16, 24, 32, 48, 64),
 def nnz_7pt(nx: int, ny: int, nz: int) -> int:
     """Stored entries of the 7-point operator with eliminated Dirichlet boundaries."""
     return nx * ny * nz + 2 * ((nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1))
+
+
+# ---------------------------------------------------------------- device generation
+# The same discretisation with torch tensor operations, for workloads too large
+# to generate on the host (a request stream).  ccfv7_torch(K) on a float64
+# tensor returns exactly the arrays of ccfv7(K.numpy()) (same face formulas and
+# summation order, same Morton order), on K's device.
+
+def morton_order_torch(nx: int, ny: int, nz: int, device) -> "torch.Tensor":
+    import torch
+    z, y, x = torch.meshgrid(torch.arange(nz, device=device), torch.arange(ny, device=device),
+                             torch.arange(nx, device=device), indexing="ij")
+    x = x.reshape(-1); y = y.reshape(-1); z = z.reshape(-1)
+    code = torch.zeros_like(x)
+    bits = max(1, int(math.ceil(math.log2(max(nx, ny, nz, 2)))))
+    for b in range(bits):
+        code |= ((x >> b) & 1) << (3 * b)
+        code |= ((y >> b) & 1) << (3 * b + 1)
+        code |= ((z >> b) & 1) << (3 * b + 2)
+    return torch.argsort(code, stable=True)
+
+
+def ccfv7_torch(K) -> tuple:
+    """Device twin of ccfv7: (rowptr int32, colind int32, vals float64, order int64)."""
+    import torch
+    K = K.to(torch.float64).contiguous()
+    nz, ny, nx = K.shape
+    n = nx * ny * nz
+    dev = K.device
+
+    def harm(a, b):
+        return 2.0 * a * b / (a + b)
+
+    txm = torch.empty_like(K); txp = torch.empty_like(K)
+    tym = torch.empty_like(K); typ = torch.empty_like(K)
+    tzm = torch.empty_like(K); tzp = torch.empty_like(K)
+    fx = harm(K[:, :, :-1], K[:, :, 1:])
+    txp[:, :, :-1] = fx; txp[:, :, -1] = 2.0 * K[:, :, -1]
+    txm[:, :, 1:] = fx; txm[:, :, 0] = 2.0 * K[:, :, 0]
+    fy = harm(K[:, :-1, :], K[:, 1:, :])
+    typ[:, :-1, :] = fy; typ[:, -1, :] = 2.0 * K[:, -1, :]
+    tym[:, 1:, :] = fy; tym[:, 0, :] = 2.0 * K[:, 0, :]
+    fz = harm(K[:-1, :, :], K[1:, :, :])
+    tzp[:-1, :, :] = fz; tzp[-1, :, :] = 2.0 * K[-1, :, :]
+    tzm[1:, :, :] = fz; tzm[0, :, :] = 2.0 * K[0, :, :]
+    del fx, fy, fz
+    diag = txm + txp
+    diag += tym
+    diag += typ
+    diag += tzm
+    diag += tzp
+    order = morton_order_torch(nx, ny, nz, dev)
+    inv = torch.empty(n, dtype=torch.int64, device=dev)
+    inv[order] = torch.arange(n, dtype=torch.int64, device=dev)
+    x = order % nx
+    y = (order // nx) % ny
+    z = order // (nx * ny)
+    cols = torch.full((n, 7), n, dtype=torch.int64, device=dev)
+    vals = torch.zeros((n, 7), dtype=torch.float64, device=dev)
+    cols[:, 0] = torch.arange(n, dtype=torch.int64, device=dev)
+    vals[:, 0] = diag.reshape(-1)[order]
+    del diag
+    slot = 1
+    for s, coord, ext, tm, tp in ((1, x, nx, txm, txp), (nx, y, ny, tym, typ), (nx * ny, z, nz, tzm, tzp)):
+        lo = coord > 0
+        cols[lo, slot] = inv[order[lo] - s]
+        vals[lo, slot] = -tm.reshape(-1)[order[lo]]
+        slot += 1
+        hi = coord < ext - 1
+        cols[hi, slot] = inv[order[hi] + s]
+        vals[hi, slot] = -tp.reshape(-1)[order[hi]]
+        slot += 1
+    del x, y, z, inv, txm, txp, tym, typ, tzm, tzp
+    cols, perm = torch.sort(cols, dim=1, stable=True)
+    vals = torch.gather(vals, 1, perm)
+    del perm
+    valid = cols < n
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    rowptr[1:] = torch.cumsum(valid.sum(dim=1), 0)
+    colind = cols[valid].to(torch.int32)
+    v = vals[valid].contiguous()
+    return rowptr.to(torch.int32), colind, v, order
+
+
+def lognormal_torch(edge: int, sigma2: float, generator, window: int = 2, divisor: float = math.sqrt(8.0),
+                    nrhs: int = 1):
+    """Lognormal K (g ~ N(0,1) on (edge+window-1)^3, window sum / divisor,
+    K = exp(sigma g')) and nrhs right-hand sides U[-1,1], drawn on the
+    generator's device in that order; returns (rowptr, colind, vals, b) with b
+    of shape (nrhs, edge^3) in row order."""
+    import torch
+    dev = generator.device
+    n = edge
+    m = n + window - 1
+    g = torch.randn((m, m, m), generator=generator, device=dev, dtype=torch.float64)
+    gs = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    for dz in range(window):
+        for dy in range(window):
+            for dx in range(window):
+                gs += g[dz:dz + n, dy:dy + n, dx:dx + n]
+    del g
+    gs /= divisor
+    K = torch.exp(math.sqrt(sigma2) * gs)
+    del gs
+    rp, ci, v, order = ccfv7_torch(K)
+    del K
+    b = rhs_torch(order, generator, nrhs)
+    return rp, ci, v, b
+
+
+def rhs_torch(order, generator, nrhs: int = 1):
+    """nrhs right-hand sides U[-1,1] drawn in lexicographic cell order, returned in row order."""
+    import torch
+    n = order.numel()
+    b = torch.rand((nrhs, n), generator=generator, device=order.device, dtype=torch.float64) * 2.0 - 1.0
+    return b[:, order].contiguous()
+
+
+def serving_trace(rate: float = 200.0, seconds: float = 60.0, seed: int = 4, edges=(32, 256),
+                  sigma2=(0.0, 4.0), reuse: float = 0.3) -> list:
+    """Request stream: Poisson arrivals (exponential gaps of mean 1/rate) until
+    `seconds`; per request, in this order: edge ~ U{edges}, sigma^2 ~ U[sigma2],
+    reuse ~ Bernoulli(reuse) and, when reusing, a target drawn uniformly from
+    the earlier requests that introduced a new matrix (the request then solves
+    that matrix with a new right-hand side).  Request i draws its own field
+    and right-hand side from the stream seeded by SeedSequence([seed, i])."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out, news = [], []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        i = len(out)
+        edge = int(rng.integers(edges[0], edges[1] + 1))
+        s2 = float(rng.uniform(sigma2[0], sigma2[1]))
+        hit = bool(rng.random() < reuse)
+        if hit and news:
+            j = news[int(rng.integers(len(news)))]
+            edge, s2, matrix = out[j]["edge"], out[j]["sigma2"], j
+        else:
+            matrix = i
+            news.append(i)
+        seed_i = int(np.random.SeedSequence([seed, i]).generate_state(1)[0])
+        out.append(dict(id=i, t=t, edge=edge, sigma2=s2, matrix=matrix, seed=seed_i))
+    return out
