@@ -9,6 +9,11 @@ permeability K = exp(2 g') with g' a 2x2x2 box-filtered N(0,1) field
 (seed 1), 7-point cell-centred finite volumes with harmonic faces, RHS
 uniform[-1,1], x0 = 0.  Inputs are resident in HBM before timing starts.
 
+Two more sections go into the same line: "batched" (64 uneven systems with 4
+right-hand sides each, amg_setup_batched + pcg_solve_batched against a loop
+of single solves) and "serving" (a request stream served with continuous
+batching against serial plain-FP64 solves, with p50/p99 latency).
+
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 import argparse
@@ -76,6 +81,106 @@ def cpu_baseline(sample_n: int, full_n: int):
     }
 
 
+def batched_section(A, P, nsys: int, nrhs: int = 4, seed: int = 3):
+    """64 uneven lognormal systems x 4 right-hand sides: amg_setup_batched +
+    pcg_solve_batched against a loop of amg_setup + pcg_solve per system and
+    right-hand side (same parameters: FP32 V-cycle, FP64 flexible CG)."""
+    import torch
+
+    t = time.perf_counter()
+    systems = P.batched_systems(nsys, seed=seed, nrhs=nrhs)
+    gen = time.perf_counter() - t
+    dev = [(torch.from_numpy(s.rowptr).cuda(), torch.from_numpy(s.colind).cuda(), torch.from_numpy(s.vals).cuda(),
+            torch.from_numpy(s.b.reshape(-1)).cuda()) for s in systems]
+    rows = sum(s.n for s in systems)
+
+    def batched():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hs = A.Hierarchy.batched([d[:3] for d in dev], vcycle_fp32=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xs = [torch.zeros_like(d[3]) for d in dev]
+        st, infos = A.pcg_solve_batched([h.h for h in hs], [d[3] for d in dev], xs, nrhs=nrhs, rtol=1e-8,
+                                        maxit=500)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for h in hs:
+            h.close()
+        return t1 - t0, t2 - t1, st, [i for inf in infos for i in inf]
+
+    def loop():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ts = 0.0
+        infos = []
+        for d, s in zip(dev, systems):
+            a = time.perf_counter()
+            h = A.Hierarchy(*d[:3], vcycle_fp32=1)
+            ts += time.perf_counter() - a
+            n = s.n
+            for k in range(nrhs):
+                x, r = h.solve(d[3][k * n:(k + 1) * n].contiguous(), rtol=1e-8, maxit=500)
+                infos.append(r)
+            h.close()
+        torch.cuda.synchronize()
+        return ts, time.perf_counter() - t0 - ts, infos
+
+    batched()  # warm-up (allocator pool, code objects)
+    bs, bv, st, binf = batched()
+    ls, lv, linf = loop()
+    its = [i["iterations"] for i in binf]
+    return {
+        "workload": f"{nsys} lognormal systems, edges from {{16,24,32,48,64}} (seed {seed}), sigma^2=2, 4^3 box "
+                    f"filter, {nrhs} right-hand sides each; FP32 V-cycle in FP64 flexible CG to 1e-8",
+        "unknowns": rows, "solves": nsys * nrhs, "generation_s": gen,
+        "batched_ms": (bs + bv) * 1e3, "batched_setup_ms": bs * 1e3, "batched_solve_ms": bv * 1e3,
+        "loop_ms": (ls + lv) * 1e3, "loop_setup_ms": ls * 1e3, "loop_solve_ms": lv * 1e3,
+        "speedup_batched_vs_loop": (ls + lv) / (bs + bv),
+        "unknown_rhs_per_s_batched": rows * nrhs / (bs + bv),
+        "iterations_max": max(its), "iterations_mean": float(sum(its)) / len(its),
+        "all_converged": st == A.OK and all(i["converged"] for i in binf) and all(r.converged for r in linf),
+        "worst_true_rel_residual": max(i["true_rel_residual"] for i in binf),
+    }
+
+
+def serving_section(A, P, seconds: float, rate: float):
+    """Request stream (Poisson arrivals at `rate` for `seconds`, edges U{32..256},
+    sigma^2 U[0,4], 30% reuse; fields generated on the device): continuous
+    batching (FP32 V-cycle, flexible CG) against serial plain-FP64 solves."""
+    import torch
+    from paper_1209_0960_amd import serve as S
+
+    trace = P.serving_trace(rate=rate, seconds=seconds, seed=4)
+    reqs, gen_s = S.requests_from_trace(trace)
+    srv = S.Server(cap_bytes=200e9, max_entries=32, setup_workers=2, vcycle_fp32=1)
+    try:
+        recs = srv.run(reqs)
+        stats = dict(srv.stats)
+    finally:
+        srv.close()
+    base, bstats, _ = S.serve_serial(reqs, vcycle_fp32=0)
+    unknowns = sum(r.n for r in recs)
+    del reqs
+    torch.cuda.empty_cache()
+    sm, sb = S.summarise(recs, **stats), S.summarise(base, **bstats)
+    ok = all(r.status == A.OK for r in recs) and all(r.status == A.OK for r in base)
+    return {
+        "workload": f"{len(trace)} requests: Poisson arrivals at {rate:g}/s over {seconds:g} s (seed 4), edge U{{32..256}}, "
+                    f"sigma^2 U[0,4], 30% reuse of a resident matrix with a new right-hand side, rtol 1e-8",
+        "unknowns": unknowns, "generation_s": gen_s, "all_converged": ok,
+        "served": {"solves_per_s": sm.solves_per_s, "p50_ms": sm.p50_ms, "p99_ms": sm.p99_ms,
+                   "makespan_s": sm.makespan_s, "hits": sm.hits, "setups": sm.setups, "evictions": sm.evictions,
+                   "max_running": sm.max_running, "peak_reserved_bytes": sm.peak_reserved_bytes,
+                   "policy": "continuous batching (32 slots), FP32 V-cycle + FP64 flexible CG, admission by "
+                             "estimated HBM footprint under 200 GB, LRU hierarchy cache"},
+        "serial_fp64": {"solves_per_s": sb.solves_per_s, "p50_ms": sb.p50_ms, "p99_ms": sb.p99_ms,
+                        "makespan_s": sb.makespan_s, "hits": sb.hits, "setups": sb.setups},
+        "throughput_ratio": sm.solves_per_s / sb.solves_per_s,
+        "p99_ratio": sb.p99_ms / sm.p99_ms,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +190,9 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain-FP64 comparison solves")
+    ap.add_argument("--batched-systems", type=int, default=64, help="systems of the batched section (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="length of the request stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (per s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -195,7 +303,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_gs_sell<float> (one level-0 colour pass of the Gauss-Seidel smoother, SELL-64)",
+            "kernel": "kb_gs<float, 1, direct> (one level-0 colour pass of the Gauss-Seidel smoother, SELL-64)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -209,6 +317,16 @@ def main():
         },
     }
     out["config"].update(extra)
+    if args.batched_systems > 0:
+        log("batched section ...")
+        out["batched"] = batched_section(A, P, args.batched_systems)
+        log(f"batched: {out['batched']['batched_ms']:.0f} ms vs loop {out['batched']['loop_ms']:.0f} ms")
+    if args.serve_seconds > 0:
+        log("serving section ...")
+        out["serving"] = serving_section(A, P, args.serve_seconds, args.serve_rate)
+        log(f"serving: {out['serving']['served']['solves_per_s']:.1f} solves/s p99 "
+            f"{out['serving']['served']['p99_ms']:.0f} ms vs serial {out['serving']['serial_fp64']['solves_per_s']:.1f}"
+            f" solves/s p99 {out['serving']['serial_fp64']['p99_ms']:.0f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, n)

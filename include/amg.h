@@ -84,6 +84,8 @@ typedef struct amg_params {
   int32_t check_symmetry;    /* 1: reject A with a_ij != a_ji                  [1]    */
   int32_t keep_setup_data;   /* 1: keep strong/isolated flags for amg_copy_level [0]  */
   int32_t use_graphs;        /* 1: pcg_solve replays each iteration as a HIP graph [1] */
+  int32_t tail_rows;         /* levels with at most this many rows (and all    [0]
+                                coarser ones) are cycled by one workgroup per solve */
 } amg_params;
 
 typedef struct amg_solve_info {

@@ -181,6 +181,7 @@ void check_params(const amg_params& p) {
   if (p.max_levels > MAX_LEVELS) fail(AMG_ERR_UNSUPPORTED, "max_levels above 32");
   if (p.smoother != AMG_SMOOTHER_MCSGS && p.smoother != AMG_SMOOTHER_L1_JACOBI) fail(AMG_ERR_INVALID_ARG, "smoother");
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
+  if (p.tail_rows < 0) fail(AMG_ERR_INVALID_ARG, "tail_rows");
 }
 
 void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy& H) {
@@ -267,6 +268,8 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
       }
     }
     build_sell(H, l, s);
+    L.sptr_d = H.alloc<int>(L.sptr.size(), s);
+    AMG_HIP(hipMemcpyAsync(L.sptr_d, L.sptr.data(), L.sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
     if (f32) {
       const size_t ent = (size_t)L.soff_h[L.nsl];
       L.sval32 = H.alloc<float>(ent, s);
@@ -313,6 +316,7 @@ amg_status amg_default_params(amg_params* p) {
   p->check_symmetry = 1;
   p->keep_setup_data = 0;
   p->use_graphs = 1;
+  p->tail_rows = 0;
   return AMG_OK;
 }
 

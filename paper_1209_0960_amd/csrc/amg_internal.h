@@ -121,6 +121,7 @@ struct Level {
   // the diagonal is kept apart.  sptr[c] = first slice of colour c.
   int nsl = 0;
   std::vector<int> sptr;  // host, ncol+1
+  int* sptr_d = nullptr;  // device copy of sptr
   int* srow = nullptr;    // nsl+1
   std::vector<int> srow_h, soff_h;  // host copies (launch sizes, byte counts)
   int* soff = nullptr;    // nsl+1
@@ -240,6 +241,8 @@ struct BDesc {
   double *r, *z, *p, *q, *rold, *xs, *bs;  // level-0 CG vectors
   double* partial;                  // [2][RED_BLOCKS][R]
   double* scal;                     // [R][S_COUNT]
+  const int* sptr;                  // ncol+1: first slice of each colour
+  int ncol;
   const int* ctl;                   // [CTL_INTS]
   int active;                       // 0: the entry is finished (table launches skip it)
   int n, nc, nsl, nL;
@@ -255,6 +258,7 @@ enum {
   OP_RESTRICT,   // b_c = P^T t (coarse rows)
   OP_PROLONG,    // x += omega P x_c (rows)
   OP_COARSE,     // x = A_L^{-1} b (rows of the coarsest level, 4 per block)
+  OP_TAIL,       // V-cycle of levels lt..L of one entry in one workgroup (coarsest: x = A_L^{-1} b)
   OP_R2B,        // FP32 cycle: b_0 = (float) r
   OP_X2Z,        // FP32 cycle: z = (double) x_0
   OP_DOTS_RZ,    // partials of r.z and z.(r - r_old)

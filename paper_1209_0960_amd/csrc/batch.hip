@@ -35,26 +35,33 @@ int red_blocks_slices(int nsl) { return std::min(RED_BLOCKS, std::max(1, cdiv(ns
 
 }  // namespace
 
-// Device vectors of one entry (right-hand sides interleaved, solve order).
+// Device vectors of one entry (right-hand sides interleaved, solve order),
+// carved from one allocation.
 struct Ctx {
-  std::vector<std::pair<void*, size_t>> owned;
+  void* block = nullptr;
   size_t bytes = 0;
   std::vector<void*> x, b, t;  // per level, precision of the cycle
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rold = nullptr, *xs = nullptr, *bs = nullptr;
   double* partial = nullptr;
-  void* alloc(size_t bytes_, hipStream_t s) {
-    void* ptr = dalloc(bytes_, s);
-    owned.emplace_back(ptr, bytes_);
-    bytes += bytes_;
-    return ptr;
-  }
   void release(hipStream_t s) {
-    for (auto& o : owned) dfree(o.first, s);
-    owned.clear();
+    if (block) dfree(block, s);
+    block = nullptr;
     bytes = 0;
     x.clear();
     b.clear();
     t.clear();
+  }
+};
+
+// Two-pass carving: the first pass sums aligned sizes, the second hands out
+// pointers into the block.
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  void* take(size_t n) {
+    void* p = base ? base + off : nullptr;
+    off += (n + 255) & ~(size_t)255;
+    return p;
   }
 };
 
@@ -103,11 +110,15 @@ struct Plan {
 struct Batch {
   int R = 1, cap = 0, use_graphs = 1;
   bool single = false;  // the per-hierarchy context of pcg_solve / amg_precond_apply
+  // All entries start together and are completed at the end (pcg_solve_batched):
+  // finished entries are only switched off, the launch plan is kept.
+  bool deferred = false;
   int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0;
   hipStream_t work = nullptr;
   hipEvent_t ev = nullptr;
   BDesc* desc_d = nullptr;
-  std::vector<BDesc> desc_h;
+  BDesc* desc_h = nullptr;  // pinned host copy, uploaded whole when dirty
+  bool desc_dirty = false, ctl_dirty = false;
   double* scal_d = nullptr;
   double* scal_h = nullptr;  // pinned
   int* ctl_d = nullptr;
@@ -136,8 +147,9 @@ void batch_init(Batch& B, int R, int cap, int use_graphs) {
   B.ent.resize(cap);
   AMG_HIP(hipStreamCreateWithFlags(&B.work, hipStreamNonBlocking));
   AMG_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
-  B.desc_h.assign((size_t)cap * MAX_LEVELS, BDesc{});
-  B.desc_d = static_cast<BDesc*>(dalloc(B.desc_h.size() * sizeof(BDesc), B.work));
+  AMG_HIP(hipHostMalloc((void**)&B.desc_h, (size_t)cap * MAX_LEVELS * sizeof(BDesc), hipHostMallocDefault));
+  for (size_t i = 0; i < (size_t)cap * MAX_LEVELS; ++i) B.desc_h[i] = BDesc{};
+  B.desc_d = static_cast<BDesc*>(dalloc((size_t)cap * MAX_LEVELS * sizeof(BDesc), B.work));
   B.scal_d = static_cast<double*>(dalloc(B.scal_count() * sizeof(double), B.work));
   B.ctl_d = static_cast<int*>(dalloc((size_t)cap * CTL_INTS * sizeof(int), B.work));
   AMG_HIP(hipHostMalloc((void**)&B.scal_h, B.scal_count() * sizeof(double), hipHostMallocDefault));
@@ -175,29 +187,38 @@ void bind_slot(Batch& B, int slot, Hierarchy& H) {
   const size_t vb = B.fp32 ? 4 : 8;
   Ctx& C = E.ctx;
   const size_t n0 = (size_t)H.lev[0].n;
-  auto vec64 = [&](size_t n) { return static_cast<double*>(C.alloc(n * R * sizeof(double), s)); };
-  C.r = vec64(n0);
-  C.z = vec64(n0);
-  C.p = vec64(n0);
-  C.q = vec64(n0);
-  C.xs = vec64(n0);
-  C.bs = vec64(n0);
-  C.rold = H.flexible ? vec64(n0) : nullptr;
-  C.partial = static_cast<double*>(C.alloc(2 * (size_t)RED_BLOCKS * R * sizeof(double), s));
-  C.x.assign(Lc + 1, nullptr);
-  C.b.assign(Lc + 1, nullptr);
-  C.t.assign(Lc + 1, nullptr);
-  for (int l = 0; l <= Lc; ++l) {
-    const size_t n = (size_t)H.lev[l].n;
-    if (l == 0 && !B.fp32) {  // the FP64 cycle works on r and z directly
-      C.b[0] = C.r;
-      C.x[0] = C.z;
-    } else {
-      C.x[l] = C.alloc(n * R * vb, s);
-      C.b[l] = C.alloc(n * R * vb, s);
+  auto carve = [&](Carver& cv) {
+    auto vec64 = [&](size_t n) { return static_cast<double*>(cv.take(n * R * sizeof(double))); };
+    C.r = vec64(n0);
+    C.z = vec64(n0);
+    C.p = vec64(n0);
+    C.q = vec64(n0);
+    C.xs = vec64(n0);
+    C.bs = vec64(n0);
+    C.rold = H.flexible ? vec64(n0) : nullptr;
+    C.partial = static_cast<double*>(cv.take(2 * (size_t)RED_BLOCKS * R * sizeof(double)));
+    C.x.assign(Lc + 1, nullptr);
+    C.b.assign(Lc + 1, nullptr);
+    C.t.assign(Lc + 1, nullptr);
+    for (int l = 0; l <= Lc; ++l) {
+      const size_t n = (size_t)H.lev[l].n;
+      if (l == 0 && !B.fp32) {  // the FP64 cycle works on r and z directly
+        C.b[0] = C.r;
+        C.x[0] = C.z;
+      } else {
+        C.x[l] = cv.take(n * R * vb);
+        C.b[l] = cv.take(n * R * vb);
+      }
+      if (l < Lc) C.t[l] = cv.take(n * R * vb);
     }
-    if (l < Lc) C.t[l] = C.alloc(n * R * vb, s);
-  }
+  };
+  Carver sizing;
+  carve(sizing);
+  C.block = dalloc(sizing.off, s);
+  C.bytes = sizing.off;
+  Carver cv;
+  cv.base = static_cast<char*>(C.block);
+  carve(cv);
   for (int l = 0; l < MAX_LEVELS; ++l) {
     BDesc& d = B.desc_h[B.desc_index(slot, l)];
     d = BDesc{};
@@ -238,27 +259,42 @@ void bind_slot(Batch& B, int slot, Hierarchy& H) {
     d.scal = B.scal_of(slot);
     d.ctl = B.ctl_d + (size_t)slot * CTL_INTS;
     d.active = 0;
+    d.sptr = L.sptr_d;
+    d.ncol = L.ncol;
     d.n = L.n;
     d.nc = L.nc;
     d.nsl = L.nsl;
     d.nL = H.nL;
     d.omega = H.p.omega;
   }
-  AMG_HIP(hipMemcpyAsync(B.desc_d + B.desc_index(slot, 0), &B.desc_h[B.desc_index(slot, 0)],
-                         MAX_LEVELS * sizeof(BDesc), hipMemcpyHostToDevice, s));
+  B.desc_dirty = true;
   E.bound = &H;
   B.dirty = true;
 }
 
 // Marks the entry of `slot` active or finished in its descriptors.
 void set_active(Batch& B, int slot, int v, hipStream_t s) {
+  (void)s;
   for (int l = 0; l < MAX_LEVELS; ++l) B.desc_h[B.desc_index(slot, l)].active = v;
-  AMG_HIP(hipMemcpyAsync(B.desc_d + B.desc_index(slot, 0), &B.desc_h[B.desc_index(slot, 0)],
-                         MAX_LEVELS * sizeof(BDesc), hipMemcpyHostToDevice, s));
+  B.desc_dirty = true;
 }
 
 void upload_ctl(Batch& B, hipStream_t s) {
-  AMG_HIP(hipMemcpyAsync(B.ctl_d, B.ctl_h, (size_t)B.cap * CTL_INTS * sizeof(int), hipMemcpyHostToDevice, s));
+  (void)s;
+  B.ctl_dirty = true;
+}
+
+// Uploads the host copies changed since the last launch sequence (pinned
+// memory, one copy each).  The host changes them only between
+// synchronisations, and every change is followed by a flush before the next
+// launch on the stream, so the device sees the latest state.
+void flush(Batch& B, hipStream_t s) {
+  if (B.desc_dirty)
+    AMG_HIP(hipMemcpyAsync(B.desc_d, B.desc_h, (size_t)B.cap * MAX_LEVELS * sizeof(BDesc), hipMemcpyHostToDevice,
+                           s));
+  if (B.ctl_dirty)
+    AMG_HIP(hipMemcpyAsync(B.ctl_d, B.ctl_h, (size_t)B.cap * CTL_INTS * sizeof(int), hipMemcpyHostToDevice, s));
+  B.desc_dirty = B.ctl_dirty = false;
 }
 
 // ------------------------------------------------------------------ launch lists
@@ -325,6 +361,15 @@ struct Builder {
 inline const Hierarchy& hier(const Batch& B, int slot) { return *B.ent[slot].bound; }
 inline int coarsest(const Batch& B, int slot) { return (int)hier(B, slot).lev.size() - 1; }
 inline bool sell0(const Batch& B, int slot) { return hier(B, slot).lev[0].scol != nullptr; }
+// First level cycled by the single-workgroup tail: the first with at most
+// tail_rows rows (the coarsest if none).
+inline int tail_start(const Batch& B, int slot) {
+  const Hierarchy& H = hier(B, slot);
+  const int Lc = (int)H.lev.size() - 1;
+  for (int l = 0; l < Lc; ++l)
+    if (H.lev[l].n <= H.p.tail_rows) return l;
+  return Lc;
+}
 
 int kind_at(int l, int k) { return l == 0 ? k : AMG_KIND_COARSE_LEVELS; }
 
@@ -379,8 +424,8 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l) 
 void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
   const double vb = B.fp32 ? 4 : 8;
   const int R = B.R;
-  int maxLc = 0;
-  for (int e : S) maxLc = std::max(maxLc, coarsest(B, e));
+  int maxLc = 0;  // deepest level cycled by separate launches
+  for (int e : S) maxLc = std::max(maxLc, tail_start(B, e));
   if (B.fp32) {
     b.begin(OP_R2B, 0, AMG_KIND_CG_VEC);
     for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 12.0 * R);
@@ -389,7 +434,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
   std::vector<std::vector<int>> below(maxLc);
   for (int l = 0; l < maxLc; ++l)
     for (int e : S)
-      if (coarsest(B, e) > l) below[l].push_back(e);
+      if (tail_start(B, e) > l) below[l].push_back(e);
   for (int l = 0; l < maxLc; ++l) {
     const std::vector<int>& E = below[l];
     b.begin(OP_ZERO, l, l == 0 ? AMG_KIND_OTHER : AMG_KIND_COARSE_LEVELS);
@@ -408,10 +453,29 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
     }
     b.end();
   }
+  // Entries whose tail is the coarsest level alone: the dense solve spread
+  // over many workgroups; the others: one workgroup per entry.
   b.begin(OP_COARSE, maxLc, AMG_KIND_COARSE_LEVELS);
   for (int e : S) {
     const Hierarchy& H = hier(B, e);
-    b.pieces(B.desc_index(e, coarsest(B, e)), H.nL, 4, 8.0 * H.nL + 2.0 * R * vb);
+    if (tail_start(B, e) == coarsest(B, e))
+      b.pieces(B.desc_index(e, coarsest(B, e)), H.nL, 4, 8.0 * H.nL + 2.0 * R * vb);
+  }
+  b.end();
+  b.begin(OP_TAIL, maxLc, AMG_KIND_COARSE_LEVELS, B.smoother, (B.pre << 8) | B.post);
+  for (int e : S) {
+    const Hierarchy& H = hier(B, e);
+    const int lt = tail_start(B, e), lc = coarsest(B, e);
+    if (lt == lc) continue;
+    double bytes = 8.0 * H.nL * H.nL + 2.0 * R * vb * H.nL;
+    for (int l = lt; l < lc; ++l) {
+      const Level& L = H.lev[l];
+      const double pass = pass_bytes(L, 0, L.nsl, R, vb);
+      bytes += (2.0 * (B.pre + B.post) + 1.0) * pass + L.n * (8.0 + 4.0 * R * vb);
+    }
+    const int d = B.desc_index(e, lt);
+    b.segment(d, lt, lc, 0);
+    b.add(d, lt, lc, 0, bytes);
   }
   b.end();
   for (int l = maxLc - 1; l >= 0; --l) {
@@ -551,15 +615,16 @@ void upload_plan(Plan& P, Builder& b, hipStream_t s) {
 }
 
 void run_plan(Batch& B, Plan& P, hipStream_t s, bool graph) {
+  flush(B, s);
   if (!graph || !B.use_graphs || g_timing_mask_for_graphs() != 0) {
-    issue_launches(P.L, 0, P.L.size(), P.tab_d, B.desc_d, B.desc_h.data(), B.R, B.fp32, s);
+    issue_launches(P.L, 0, P.L.size(), P.tab_d, B.desc_d, B.desc_h, B.R, B.fp32, s);
     return;
   }
   if (!P.exec) {
     hipGraph_t g = nullptr;
     AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
-      issue_launches(P.L, 0, P.L.size(), P.tab_d, B.desc_d, B.desc_h.data(), B.R, B.fp32, s);
+      issue_launches(P.L, 0, P.L.size(), P.tab_d, B.desc_d, B.desc_h, B.R, B.fp32, s);
     } catch (...) {
       (void)hipStreamEndCapture(s, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -694,7 +759,7 @@ void step(Batch& B) {
       act_rows += B.ent[e].bound->lev[0].n;
     }
   if (act.empty()) return;
-  bool rebuild = B.dirty || B.iter.L.empty() || act_rows < 0.7 * B.iter.rows;
+  bool rebuild = B.dirty || B.iter.L.empty() || (!B.deferred && act_rows < 0.7 * B.iter.rows);
   if (!rebuild)
     for (int e : act)
       if (std::find(B.iter.slots.begin(), B.iter.slots.end(), e) == B.iter.slots.end()) rebuild = true;
@@ -761,10 +826,12 @@ void step(Batch& B) {
       fin.push_back(e);
     }
   }
-  if (!fin.empty())
+  if (!fin.empty() && !B.deferred) {
     finalise(B, fin);
-  else if (ctl_changed)
-    upload_ctl(B, s);
+  } else {
+    for (int e : fin) set_active(B, e, 0, s);
+    if (ctl_changed) upload_ctl(B, s);
+  }
 }
 
 void batch_release(Batch& B) {
@@ -783,6 +850,8 @@ void batch_release(Batch& B) {
   B.scal_d = nullptr;
   B.ctl_d = nullptr;
   if (s) (void)hipStreamSynchronize(s);
+  if (B.desc_h) (void)hipHostFree(B.desc_h);
+  B.desc_h = nullptr;
   if (B.scal_h) (void)hipHostFree(B.scal_h);
   if (B.ctl_h) (void)hipHostFree(B.ctl_h);
   B.scal_h = nullptr;
@@ -851,10 +920,11 @@ void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us) {
     B.dirty = false;
   }
   AMG_HIP(hipStreamSynchronize(s));  // descriptors and tables are written on the work stream
+  flush(B, us);
   const Level& L0 = H.lev[0];
   const Entry& E = B.ent[0];
   gather_rhs(L0.n, 1, L0.perm, r, E.ctx.r, us);
-  issue_launches(B.iter.L, 0, B.iter.precond_end, B.iter.tab_d, B.desc_d, B.desc_h.data(), 1, B.fp32, us);
+  issue_launches(B.iter.L, 0, B.iter.precond_end, B.iter.tab_d, B.desc_d, B.desc_h, 1, B.fp32, us);
   scatter_rhs(L0.n, 1, L0.perm, E.ctx.z, z, us);
 }
 
@@ -864,8 +934,20 @@ amg_status pcg_batched_run(Hierarchy* const* hs, int nsys, int nrhs, const doubl
   amg_status worst = AMG_OK;
   try {
     batch_init(B, nrhs, nsys, hs[0]->p.use_graphs);
+    B.deferred = true;
     for (int i = 0; i < nsys; ++i) start_entry(B, i, *hs[i], b[i], x[i], rtol, maxit, i, nullptr, nullptr, us);
-    while ((int)B.results.size() < nsys) step(B);
+    auto running = [&] {
+      for (const Entry& E : B.ent)
+        if (E.used && !E.complete) return true;
+      return false;
+    };
+    while (running()) step(B);
+    std::vector<int> all(nsys);
+    for (int i = 0; i < nsys; ++i) {
+      all[i] = i;
+      set_active(B, i, 1, B.work);
+    }
+    finalise(B, all);
     for (const Result& r : B.results) {
       if (info)
         for (int k = 0; k < nrhs; ++k) info[(size_t)r.tag * nrhs + k] = r.info[k];

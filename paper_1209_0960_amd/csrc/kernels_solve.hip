@@ -223,7 +223,7 @@ __device__ __forceinline__ void kb_zero_body(const Item& it, const BDesc& d) {
   V z[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) z[k] = 0;
-  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) stv<V, R>(x + (size_t)i * R, z);
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += (int)blockDim.x) stv<V, R>(x + (size_t)i * R, z);
 }
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_zero(AMG_KARGS) {
@@ -235,7 +235,7 @@ __device__ __forceinline__ void kb_jacobi_body(const Item& it, const BDesc& d) {
   V* x = static_cast<V*>(d.x);
   const V* t = static_cast<const V*>(d.t);
   const V* l1 = Mat<V>::l1(d);
-  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += (int)blockDim.x) {
     V xv[R], tv[R];
     ldv<V, R>(x + (size_t)i * R, xv);
     ldv<V, R>(t + (size_t)i * R, tv);
@@ -278,7 +278,7 @@ __device__ __forceinline__ void kb_prolong_body(const Item& it, const BDesc& d) 
   V* x = static_cast<V*>(d.x);
   const V* xc = static_cast<const V*>(d.xc);
   const V om = (V)d.omega;
-  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
+  for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += (int)blockDim.x) {
     V xv[R], cv[R];
     ldv<V, R>(x + (size_t)i * R, xv);
     ldv<V, R>(xc + (size_t)d.agg[i] * R, cv);
@@ -323,6 +323,75 @@ __device__ __forceinline__ void kb_coarse_body(const Item& it, const BDesc& d) {
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_coarse(AMG_KARGS) {
   AMG_BODY((kb_coarse_body<V, R>))
+}
+
+// ---------------------------------------------------------------- coarse tail
+// The V-cycle below level lt of one entry in one workgroup (TAIL_NT threads):
+// levels lt..lc-1 and the coarsest solve, passes separated by workgroup
+// barriers instead of kernel launches.  Every pass applies the same per-row
+// bodies as the launches of the larger levels (one wavefront per slice, one
+// thread per row), so the result does not depend on where the tail starts.
+constexpr int TAIL_NT = 1024;
+
+template <typename V, int R>
+__device__ inline void tail_slices(const BDesc& d, int s0, int s1, bool gs) {
+  const int nw = (int)blockDim.x / WAVE;
+  for (int lo = s0; lo < s1; lo += nw) {
+    const Item it{0, lo, min(s1, lo + nw), 0};
+    if (gs)
+      kb_gs_body<V, R>(it, d);
+    else
+      kb_resid_body<V, R>(it, d);
+  }
+  __syncthreads();
+}
+
+template <typename V, int R>
+__device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps) {
+  for (int k = 0; k < sweeps; ++k) {
+    if (smoother == AMG_SMOOTHER_MCSGS) {
+      for (int dir = 0; dir < 2; ++dir)
+        for (int q = 0; q < d.ncol; ++q) {
+          const int c = dir == 0 ? q : d.ncol - 1 - q;
+          tail_slices<V, R>(d, d.sptr[c], d.sptr[c + 1], true);
+        }
+    } else {
+      tail_slices<V, R>(d, 0, d.nsl, false);
+      kb_jacobi_body<V, R>(Item{0, 0, d.n, 0}, d);
+      __syncthreads();
+    }
+  }
+}
+
+// it.d: descriptor of level lt (level l at D[it.d + l - lt]); it.lo = lt, it.hi = lc.
+template <typename V, int R>
+__global__ __launch_bounds__(TAIL_NT) void kb_tail(const Item* __restrict__ tab, const BDesc* __restrict__ D,
+                                                    const Item base, int smoother, int pre, int post, int direct) {
+  const Item it = direct ? base : tab[blockIdx.x];
+  const BDesc* dl = D + it.d;
+  if (!direct && dl->active == 0) return;
+  const int lt = it.lo, lc = it.hi;
+  const int nt = (int)blockDim.x, nw = nt / WAVE;
+  for (int l = lt; l < lc; ++l) {
+    const BDesc& d = dl[l - lt];
+    kb_zero_body<V, R>(Item{0, 0, d.n, 0}, d);
+    __syncthreads();
+    tail_smooth<V, R>(d, smoother, pre);
+    tail_slices<V, R>(d, 0, d.nsl, false);
+    for (int lo = 0; lo < d.nc; lo += nt) kb_restrict_body<V, R>(Item{0, lo, min(d.nc, lo + nt), 0}, d);
+    __syncthreads();
+  }
+  {
+    const BDesc& c = dl[lc - lt];
+    for (int lo = 0; lo < c.nL; lo += nw) kb_coarse_body<V, R>(Item{0, lo, min(c.nL, lo + nw), 0}, c);
+    __syncthreads();
+  }
+  for (int l = lc - 1; l >= lt; --l) {
+    const BDesc& d = dl[l - lt];
+    kb_prolong_body<V, R>(Item{0, 0, d.n, 0}, d);
+    __syncthreads();
+    tail_smooth<V, R>(d, smoother, post);
+  }
 }
 
 // FP32 cycle: level-0 right-hand side = (float) r; z = (double) x.
@@ -770,6 +839,14 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
     case OP_RESTRICT: AMG_LAUNCH(kb_restrict, (V, R)); break;
     case OP_PROLONG: AMG_LAUNCH(kb_prolong, (V, R)); break;
     case OP_COARSE: AMG_LAUNCH(kb_coarse, (V, R)); break;
+    case OP_TAIL:
+      if (L.use_direct)
+        hipLaunchKernelGGL((kb_tail<V, R>), dim3(1), dim3(TAIL_NT), 0, s, nullptr, D, L.direct, L.aux, L.aux2 >> 8,
+                           L.aux2 & 255, 1);
+      else
+        hipLaunchKernelGGL((kb_tail<V, R>), dim3(L.nblk), dim3(TAIL_NT), 0, s, t, D, Item{}, L.aux, L.aux2 >> 8,
+                           L.aux2 & 255, 0);
+      break;
     default: fail(AMG_ERR_HIP, "unknown cycle launch");
   }
 }
@@ -785,6 +862,7 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
     case OP_RESTRICT:
     case OP_PROLONG:
     case OP_COARSE:
+    case OP_TAIL:
       if (fp32)
         launch_cycle_op<float, R>(L, t, D, Dh, s);
       else

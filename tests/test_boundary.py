@@ -40,7 +40,8 @@ def test_params_struct_matches_header_defaults():
     assert (p.omega, p.coarse_max, p.max_levels, p.tile_rows) == (1.6, 500, 25, 512)
     assert (p.smoother, p.pre_sweeps, p.post_sweeps, p.vcycle_fp32, p.flexible) == (0, 1, 1, 0, -1)
     assert p.use_graphs == 1
-    assert ctypes.sizeof(A.Params) == 88  # 5 doubles + 12 int32 fields, 8-byte aligned
+    assert p.tail_rows == 0
+    assert ctypes.sizeof(A.Params) == 96  # 3 doubles + 15 int32 fields, 8-byte aligned
 
 
 def test_header_compiles_as_c_and_matches_ctypes_layout(tmp_path):
