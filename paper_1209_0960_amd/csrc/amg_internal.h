@@ -107,7 +107,8 @@ struct Level {
   // aggregation (towards level l+1)
   int* agg = nullptr;       // n: coarse row of each row
   int* members = nullptr;   // n: rows grouped by coarse row, ascending natural order
-  int* mptr = nullptr;      // nc+1
+  int* mptr = nullptr;      // nc+1 (natural coarse order)
+  int* cinv = nullptr;      // nc: coarse solve row of each natural coarse row (NULL: identity)
   int* tile_off = nullptr;  // ntiles+1: first coarse row of each tile (natural order only)
   // colouring
   int* colour = nullptr;  // n (natural order only)
@@ -235,6 +236,7 @@ struct BDesc {
   const int *rowptr, *colind;  // CSR (one-level hierarchies only)
   const double* vals;
   const int *mptr, *members, *agg;  // transfer to level l+1
+  const int* cinv;                  // natural -> solve order of level l+1 (NULL: identity)
   const double* Ainv;               // coarsest level: dense inverse (nL x nL)
   void *x, *b, *t;                  // this level's iterate, right-hand side, residual
   void *xc, *bc;                    // level l+1's iterate and right-hand side

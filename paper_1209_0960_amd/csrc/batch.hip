@@ -240,6 +240,7 @@ void bind_slot(Batch& B, int slot, Hierarchy& H) {
       d.mptr = L.mptr;
       d.members = L.members;
       d.agg = L.agg;
+      d.cinv = L.cinv;
       d.xc = C.x[l + 1];
       d.bc = C.b[l + 1];
     } else {

@@ -265,7 +265,7 @@ __device__ inline int st_agg(unsigned w) { return (int)(short)(w & ST_AGG); }
 __device__ inline int st_slot(unsigned w) { return (int)((w >> ST_SLOT_SHIFT) & 63u); }
 
 struct AggLayout {
-  size_t lptr, st, key1, key2, adjf, madj, nbk, nna, front, adjl, mem, ladj, total;
+  size_t lptr, st, key1, adjb, madj, nna, front, adjl, mem, ladj, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -275,11 +275,9 @@ __host__ __device__ inline AggLayout agg_layout(int T, int E) {
   size_t o = 0;
   L.lptr = o; o = align16(o + 4 * (size_t)(T + 1));
   L.st = o; o = align16(o + 4 * (size_t)T);
-  L.key1 = o; o = align16(o + 4 * (size_t)T);
-  L.key2 = o; o = align16(o + 4 * (size_t)T);
-  L.adjf = o; o = align16(o + 4 * (size_t)T);
+  L.key1 = o; o = align16(o + 2 * (size_t)T);
+  L.adjb = o; o = align16(o + 4 * (size_t)((T + 31) / 32));
   L.madj = o; o = align16(o + 4 * (size_t)AGG_MAX_SLOTS);
-  L.nbk = o; o = align16(o + 2 * (size_t)T);
   L.nna = o; o = align16(o + 2 * (size_t)T);
   L.front = o; o = align16(o + 2 * (size_t)T);
   L.adjl = o; o = align16(o + 2 * (size_t)T);
@@ -292,11 +290,9 @@ __host__ __device__ inline AggLayout agg_layout(int T, int E) {
 struct AggSh {
   int* lptr;
   unsigned* st;
-  int* key1;
-  int* key2;
-  int* adjflag;
+  short* key1;       // grow score per front position
+  unsigned* adjbits; // bit a: aggregate a is adjacent to the current aggregate
   unsigned* madj;
-  short* nbk;
   short* nna;
   short* front;
   short* adjl;
@@ -347,7 +343,8 @@ __device__ void add_member(const AggSh& S, AggState& as, int c, int id, bool iso
         }
       } else {
         const bool track = iso_phase ? (aj < P1) : true;
-        if (track && atomicExch(&S.adjflag[aj], 1) == 0) appA = true;
+        const unsigned bit = 1u << (aj & 31);
+        if (track && (atomicOr(&S.adjbits[aj >> 5], bit) & bit) == 0) appA = true;
       }
     }
     const uint64_t mF = __ballot(appF);
@@ -366,7 +363,10 @@ __device__ void add_member(const AggSh& S, AggState& as, int c, int id, bool iso
 __device__ void clear_aggregate(const AggSh& S, AggState& as) {
   const int lane = __lane_id();
   for (int p = lane; p < as.fcount; p += WAVE) S.st[S.front[p]] &= ~ST_FRONT;
-  for (int p = lane; p < as.acount; p += WAVE) S.adjflag[S.adjl[p]] = 0;
+  for (int p = lane; p < as.acount; p += WAVE) {
+    const int a = S.adjl[p];
+    atomicAnd(&S.adjbits[a >> 5], ~(1u << (a & 31)));
+  }
   __syncthreads();
   if (lane < as.asize) {
     const int v = S.mem[lane];
@@ -435,7 +435,7 @@ __device__ inline void score_b(const AggSh& S, int c, int id, int& conn, int& nb
     const unsigned wj = S.st[w & 0x7FFF];
     const int aj = st_agg(wj);
     if (aj == id) continue;
-    if (w >> 15) conn += (aj >= 0 && S.adjflag[aj]) ? 2 : 1;
+    if (w >> 15) conn += (aj >= 0 && ((S.adjbits[aj >> 5] >> (aj & 31)) & 1u)) ? 2 : 1;
     if (aj < 0 && !(wj & (ST_ISO | ST_FRONT))) ++nb;
   }
 }
@@ -462,11 +462,9 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   AggSh S;
   S.lptr = (int*)(sm + Lo.lptr);
   S.st = (unsigned*)(sm + Lo.st);
-  S.key1 = (int*)(sm + Lo.key1);
-  S.key2 = (int*)(sm + Lo.key2);
-  S.adjflag = (int*)(sm + Lo.adjf);
+  S.key1 = (short*)(sm + Lo.key1);
+  S.adjbits = (unsigned*)(sm + Lo.adjb);
   S.madj = (unsigned*)(sm + Lo.madj);
-  S.nbk = (short*)(sm + Lo.nbk);
   S.nna = (short*)(sm + Lo.nna);
   S.front = (short*)(sm + Lo.front);
   S.adjl = (short*)(sm + Lo.adjl);
@@ -507,9 +505,9 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
     const bool is = isov[i] != 0;
     S.st[v] = ST_AGG | ST_SLOT_NONE | (is ? ST_ISO : 0u);
     S.nna[v] = (short)(pos - S.lptr[v]);
-    S.adjflag[v] = 0;
     nonIso += is ? 0 : 1;
   }
+  for (int w = lane; w < (T + 31) / 32; w += WAVE) S.adjbits[w] = 0;
   if (lane < AGG_MAX_SLOTS) S.madj[lane] = 0;
   int nU = wave_sum(nonIso);
   __syncthreads();
@@ -542,7 +540,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
             k1 = ok ? r.c2 : 0;
             if (ok) lm2 = max(lm2, r.c2);
           }
-          S.key1[p] = k1;
+          S.key1[p] = (short)k1;
         }
       }
       const int m2 = wave_max(lm2);
@@ -686,7 +684,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
                 const int aj = st_agg(wj);
                 if (aj == myid)
                   mm |= 1u << st_slot(wj);
-                else if (aj >= 0 && aj < P1 && S.adjflag[aj])
+                else if (aj >= 0 && aj < P1 && ((S.adjbits[aj >> 5] >> (aj & 31)) & 1u))
                   common = true;
               }
               if (common && ecc_ok(S, mm, as.asize, dmax)) best = min(best, c);
@@ -701,30 +699,45 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
     }
   }
 
-  // ---- outputs: local ids, count, member lists grouped by aggregate
+  // ---- outputs: local ids, count, member lists grouped by aggregate (rows
+  // ascending inside each).  The adjacency is no longer needed: lptr holds the
+  // per-aggregate counters, front the rank of each row inside its aggregate.
   __syncthreads();
   for (int v = lane; v < nt; v += WAVE) agg_local[lo + v] = st_agg(S.st[v]);
   const int na = id;
   if (lane == 0) tile_cnt[t] = na;
-  for (int k = lane; k < na; k += WAVE) S.key1[k] = 0;
+  int* cnt = S.lptr;
+  for (int k = lane; k < na; k += WAVE) cnt[k] = 0;
   __syncthreads();
-  for (int v = lane; v < nt; v += WAVE) atomicAdd(&S.key1[st_agg(S.st[v])], 1);
-  __syncthreads();
+  for (int base = 0; base < nt; base += WAVE) {
+    const int v = base + lane;
+    const int k = v < nt ? st_agg(S.st[v]) : -1;
+    uint64_t left = __ballot(v < nt);
+    while (left) {
+      const int leader = (int)__builtin_ctzll(left);
+      const int kl = __shfl(k, leader, WAVE);
+      const uint64_t m = __ballot(k == kl) & left;
+      const int c0 = cnt[kl];
+      if (k == kl && ((m >> lane) & 1ull)) S.front[v] = (short)(c0 + __popcll(m & lanemask_lt()));
+      __syncthreads();
+      if (lane == leader) cnt[kl] = c0 + __popcll(m);
+      __syncthreads();
+      left &= ~m;
+    }
+  }
   carry = 0;
   for (int base = 0; base < na; base += WAVE) {
     const int k = base + lane;
-    const int c = k < na ? S.key1[k] : 0;
+    const int c = k < na ? cnt[k] : 0;
     const int inc = wave_incl_scan(c);
-    if (k < na) S.key2[k] = carry + inc - c;
+    if (k < na) {
+      cnt[k] = carry + inc - c;
+      mstart[lo + k] = carry + inc - c;
+    }
     carry += __shfl(inc, WAVE - 1, WAVE);
   }
   __syncthreads();
-  for (int k = lane; k < na; k += WAVE) {
-    int pos = S.key2[k];
-    mstart[lo + k] = pos;
-    for (int v = 0; v < nt; ++v)
-      if (st_agg(S.st[v]) == k) members[lo + pos++] = lo + v;
-  }
+  for (int v = lane; v < nt; v += WAVE) members[lo + cnt[st_agg(S.st[v])] + S.front[v]] = lo + v;
 }
 
 __global__ void k_tile_nnz_max(int n, int T, int ntiles, const int* __restrict__ rp, int* out) {
@@ -1686,29 +1699,28 @@ void permute_level(Hierarchy& H, int l, const int* next_perm, hipStream_t s) {
   double* pv = H.alloc<double>((size_t)nnz, s);
   hipLaunchKernelGGL(k_perm_rows, dim3(cdiv(n, 4)), dim3(256), 0, s, n, perm, pinv.as<int>(), L.rowptr, L.colind,
                      L.vals, prp, pci, pv);
-  DBuf npinv(next_perm ? (size_t)nc * sizeof(int) : 0, s);
-  if (next_perm)
-    hipLaunchKernelGGL(k_invperm, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, next_perm, npinv.as<int>());
+  // Coarse solve index of each natural coarse row (NULL: the next level is the
+  // coarsest and keeps its natural order).
+  int* npinv = next_perm ? H.alloc<int>((size_t)nc, s) : nullptr;
+  if (next_perm) hipLaunchKernelGGL(k_invperm, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, next_perm, npinv);
   int* pagg = H.alloc<int>((size_t)n, s);
-  hipLaunchKernelGGL(k_perm_agg, dim3(g), dim3(256), 0, s, n, perm, L.agg, npinv.as<int>(), pagg);
-  DBuf mc((size_t)nc * sizeof(int), s);
-  hipLaunchKernelGGL(k_perm_mcount, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, next_perm, L.mptr, mc.as<int>());
-  int* pmptr = H.alloc<int>((size_t)nc + 1, s);
-  exclusive_scan(mc.as<int>(), pmptr, nc, s);
+  hipLaunchKernelGGL(k_perm_agg, dim3(g), dim3(256), 0, s, n, perm, L.agg, npinv, pagg);
+  // Member lists stay in natural coarse order (the restriction walks
+  // neighbouring aggregates together); members become fine solve rows.
   int* pmem = H.alloc<int>((size_t)n, s);
-  hipLaunchKernelGGL(k_perm_members, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, next_perm, L.mptr, L.members,
-                     pinv.as<int>(), pmptr, pmem);
+  hipLaunchKernelGGL(k_perm_members, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, nullptr, L.mptr, L.members,
+                     pinv.as<int>(), L.mptr, pmem);
   AMG_HIP(hipGetLastError());
   AMG_HIP(hipStreamSynchronize(s));
-  for (void* p : {(void*)L.rowptr, (void*)L.colind, (void*)L.vals, (void*)L.agg, (void*)L.members, (void*)L.mptr,
+  for (void* p : {(void*)L.rowptr, (void*)L.colind, (void*)L.vals, (void*)L.agg, (void*)L.members,
                   (void*)L.tile_off, (void*)L.colour})
     H.free_one(p, s);
   L.rowptr = prp;
   L.colind = pci;
   L.vals = pv;
   L.agg = pagg;
-  L.mptr = pmptr;
   L.members = pmem;
+  L.cinv = npinv;
   L.tile_off = nullptr;
   L.colour = nullptr;
   L.perm = perm;

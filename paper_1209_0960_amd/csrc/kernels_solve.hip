@@ -250,7 +250,9 @@ __global__ __launch_bounds__(NT) void kb_jacobi(AMG_KARGS) {
   AMG_BODY((kb_jacobi_body<V, R>))
 }
 
-// b_c[I] = sum of t over the members of aggregate I (ascending), coarse rows [lo, hi).
+// b_c[I] = sum of t over the members of aggregate I (ascending), coarse rows
+// [lo, hi) in natural coarse order (neighbouring threads gather neighbouring
+// fine rows); the sum goes to I's solve row.
 template <typename V, int R>
 __device__ __forceinline__ void kb_restrict_body(const Item& it, const BDesc& d) {
   const int I = it.lo + (int)threadIdx.x;
@@ -265,7 +267,7 @@ __device__ __forceinline__ void kb_restrict_body(const Item& it, const BDesc& d)
 #pragma unroll
     for (int k = 0; k < R; ++k) s[k] += tv[k];
   }
-  stv<V, R>(static_cast<V*>(d.bc) + (size_t)I * R, s);
+  stv<V, R>(static_cast<V*>(d.bc) + (size_t)(d.cinv ? d.cinv[I] : I) * R, s);
 }
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_restrict(AMG_KARGS) {
