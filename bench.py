@@ -9,10 +9,12 @@ permeability K = exp(2 g') with g' a 2x2x2 box-filtered N(0,1) field
 (seed 1), 7-point cell-centred finite volumes with harmonic faces, RHS
 uniform[-1,1], x0 = 0.  Inputs are resident in HBM before timing starts.
 
-Two more sections go into the same line: "batched" (64 uneven systems with 4
-right-hand sides each, amg_setup_batched + pcg_solve_batched against a loop
-of single solves) and "serving" (a request stream served with continuous
-batching against serial plain-FP64 solves, with p50/p99 latency).
+Three more sections go into the same line: "large" (layered 512^3, per-kernel
+GB/s and the FP64 solution error against a 1e-12 reference), "batched" (64
+uneven systems with 4 right-hand sides each, amg_setup_batched +
+pcg_solve_batched against a loop of single solves) and "serving" (a request
+stream served with continuous batching against serial plain-FP64 solves, with
+p50/p99 latency).
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -181,6 +183,67 @@ def serving_section(A, P, seconds: float, rate: float):
     }
 
 
+def large_section(A, P, n: int = 512, seed: int = 2):
+    """Layered 512^3 (contrast ~1e6): FP64 operator, FP32 hierarchy and
+    smoother in flexible CG to 1e-8; per-kernel-class GB/s from HIP events of
+    one more solve; FP64 solution error against a plain-FP64 PCG solve to
+    1e-12 on the same GPU.  The field and right-hand side are drawn on the
+    host (default_rng(seed)), the operator is assembled on the device."""
+    import torch
+
+    t = time.perf_counter()
+    K, b_lex, _ = P.layered_field_and_rhs(n, seed)
+    Kt = torch.from_numpy(K).cuda()
+    del K
+    rp, ci, v, order = P.ccfv7_torch(Kt)
+    del Kt
+    b = torch.from_numpy(b_lex).cuda()[order].contiguous()
+    del b_lex, order
+    torch.cuda.synchronize()
+    gen = time.perf_counter() - t
+    out = {"workload": f"layered K {n}^3 (u_z ~ U[-3,3] per 4-cell z-layer times lognormal sigma=1, seed {seed}), "
+                       "FP32 V-cycle in FP64 flexible CG to 1e-8",
+           "unknowns": rp.numel() - 1, "nnz": ci.numel(), "generation_s": gen}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = A.Hierarchy(rp, ci, v, vcycle_fp32=1)
+    x, r = h.solve(b, rtol=1e-8, maxit=500)
+    torch.cuda.synchronize()
+    out.update(time_to_1e8_ms=(time.perf_counter() - t0) * 1e3, setup_ms=r.setup_ms, solve_ms=r.solve_ms,
+               iterations=r.iterations, levels=h.levels, true_rel_residual=r.true_rel_residual,
+               hierarchy_bytes=h.bytes)
+    A.set_kernel_timing(True)
+    A.reset_kernel_timing()
+    h.solve(b, rtol=1e-8, maxit=500)
+    A.set_kernel_timing(False)
+    names = {A.KIND_SPMV_F64: "spmv_f64_level0", A.KIND_SWEEP: "gs_colour_pass_level0",
+             A.KIND_RESTRICT: "residual_restrict_level0", A.KIND_PROLONG: "prolong_level0",
+             A.KIND_CG_VEC: "cg_vectors", A.KIND_COARSE_LEVELS: "levels_1_and_below", A.KIND_OTHER: "fills_level0"}
+    out["kernel_gbs"] = {}
+    for k, nm in names.items():
+        ms, cnt, by = A.kernel_timing(k)
+        if cnt:
+            out["kernel_gbs"][nm] = {"GB/s": by / (ms * 1e-3) / 1e9, "launches": cnt, "ms": ms}
+    h.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h64 = A.Hierarchy(rp, ci, v, vcycle_fp32=0)
+    x64, r64 = h64.solve(b, rtol=1e-8, maxit=500)
+    torch.cuda.synchronize()
+    out["plain_fp64"] = {"time_to_1e8_ms": (time.perf_counter() - t0) * 1e3, "iterations": r64.iterations}
+    xr, rr = h64.solve(b, rtol=1e-12, maxit=1000, raise_on_error=False)
+    h64.close()
+    nr = float(torch.linalg.norm(xr))
+    out["fp64_solution_error_mixed"] = float(torch.linalg.norm(x - xr)) / nr
+    out["fp64_solution_error_plain"] = float(torch.linalg.norm(x64 - xr)) / nr
+    out["reference"] = {"rtol": 1e-12, "iterations": rr.iterations, "status": int(rr.status),
+                        "true_rel_residual": rr.true_rel_residual}
+    out["speedup_mixed_vs_plain_fp64"] = out["plain_fp64"]["time_to_1e8_ms"] / out["time_to_1e8_ms"]
+    del rp, ci, v, b, x, x64, xr
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +256,7 @@ def main():
     ap.add_argument("--batched-systems", type=int, default=64, help="systems of the batched section (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="length of the request stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (per s)")
+    ap.add_argument("--large-n", type=int, default=512, help="edge of the layered large section (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -317,6 +381,11 @@ def main():
         },
     }
     out["config"].update(extra)
+    if args.large_n > 0:
+        log(f"large section (layered {args.large_n}^3) ...")
+        out["large"] = large_section(A, P, args.large_n)
+        log(f"large: {out['large']['time_to_1e8_ms']:.0f} ms, {out['large']['iterations']} iterations, "
+            f"FP64 error {out['large']['fp64_solution_error_mixed']:.2e}")
     if args.batched_systems > 0:
         log("batched section ...")
         out["batched"] = batched_section(A, P, args.batched_systems)

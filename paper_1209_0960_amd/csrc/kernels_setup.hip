@@ -1356,17 +1356,22 @@ __global__ void k_perm_rowlen(int n, const int* __restrict__ perm, const int* __
 
 // One wavefront per solve row: copy the row's entries (same order) with the
 // columns relabelled.
-__global__ __launch_bounds__(256) void k_perm_rows(int n, const int* __restrict__ perm, const int* __restrict__ pinv,
-                                                   const int* __restrict__ rp, const int* __restrict__ ci,
-                                                   const double* __restrict__ v, const int* __restrict__ prp,
-                                                   int* __restrict__ pci, double* __restrict__ pv) {
-  const int r = blockIdx.x * 4 + threadIdx.x / WAVE;
-  if (r >= n) return;
-  const int i = perm[r];
-  const int b = rp[i], len = rp[i + 1] - b, d = prp[r];
-  for (int q = __lane_id(); q < len; q += WAVE) {
-    pci[d + q] = pinv[ci[b + q]];
-    pv[d + q] = v[b + q];
+// `sub` consecutive threads (a power of two <= 64) copy one row; grid-stride
+// over rows, so the grid stays within the dispatch limits at any n.
+__global__ __launch_bounds__(256) void k_perm_rows(int n, int sub, const int* __restrict__ perm,
+                                                   const int* __restrict__ pinv, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const double* __restrict__ v,
+                                                   const int* __restrict__ prp, int* __restrict__ pci,
+                                                   double* __restrict__ pv) {
+  const int per = 256 / sub;
+  const int q0 = (int)threadIdx.x % sub;
+  for (long long r = (long long)blockIdx.x * per + threadIdx.x / sub; r < n; r += (long long)gridDim.x * per) {
+    const int i = perm[r];
+    const int b = rp[i], len = rp[i + 1] - b, d = prp[r];
+    for (int q = q0; q < len; q += sub) {
+      pci[d + q] = pinv[ci[b + q]];
+      pv[d + q] = v[b + q];
+    }
   }
 }
 
@@ -1697,7 +1702,10 @@ void permute_level(Hierarchy& H, int l, const int* next_perm, hipStream_t s) {
   exclusive_scan(len.as<int>(), prp, n, s);
   int* pci = H.alloc<int>((size_t)nnz, s);
   double* pv = H.alloc<double>((size_t)nnz, s);
-  hipLaunchKernelGGL(k_perm_rows, dim3(cdiv(n, 4)), dim3(256), 0, s, n, perm, pinv.as<int>(), L.rowptr, L.colind,
+  int sub = 4;
+  while (sub < 64 && (long long)sub * n < 2LL * nnz) sub *= 2;  // about the mean row length
+  hipLaunchKernelGGL(k_perm_rows, dim3(std::min(cdiv(n, 256 / sub), 1 << 20)), dim3(256), 0, s, n, sub, perm,
+                     pinv.as<int>(), L.rowptr, L.colind,
                      L.vals, prp, pci, pv);
   // Coarse solve index of each natural coarse row (NULL: the next level is the
   // coarsest and keeps its natural order).

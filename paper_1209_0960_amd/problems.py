@@ -397,3 +397,27 @@ def serving_trace(rate: float = 200.0, seconds: float = 60.0, seed: int = 4, edg
         seed_i = int(np.random.SeedSequence([seed, i]).generate_state(1)[0])
         out.append(dict(id=i, t=t, edge=edge, sigma2=s2, matrix=matrix, seed=seed_i))
     return out
+
+
+# ---------------------------------------------------------------- large layered workload
+def layered_field_and_rhs(n: int, seed: int = 2):
+    """Layered field K[z, y, x] (field_layered recipe) and b_lex ~ U[-1,1] in
+    lexicographic order, drawn in that order from default_rng(seed); returns
+    (K, b_lex, rng) with rng positioned after the draws."""
+    rng = np.random.default_rng(seed)
+    K = field_layered(rng, n)
+    b_lex = rng.uniform(-1.0, 1.0, n * n * n)
+    return K, b_lex, rng
+
+
+def layered_subsampled(n_full: int = 512, seed: int = 2) -> CSRSystem:
+    """The (n_full/2)^3 system of the field sampled at even cells,
+    K_sub[k, j, i] = K[2k, 2j, 2i], with its own b drawn from the same
+    generator after the full-size field and right-hand side."""
+    K, _, rng = layered_field_and_rhs(n_full, seed)
+    Ks = np.ascontiguousarray(K[::2, ::2, ::2])
+    del K
+    rowptr, colind, vals, order = ccfv7(Ks)
+    m = n_full // 2
+    b = rng.uniform(-1.0, 1.0, m * m * m)[order]
+    return CSRSystem(rowptr, colind, vals, np.ascontiguousarray(b), (m, m, m), order)

@@ -9,8 +9,14 @@ the oracle can compute piece by piece, plus properties that hold at any size.
 * colouring of level 0: the full oracle colouring (128^3) or the parity closed
   form (256^3, aligned 8^3 Morton tiles);
 * the solve: true FP64 residual from an independent CPU product <= 1e-8 for
-  the mixed-precision and the FP64 path, and their solution difference.
+  the mixed-precision and the FP64 path, and their solution difference;
+* the 256^3 system sampled from the 512^3 layered field against the oracle's
+  stored hierarchy fingerprint and solution samples.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -43,6 +49,10 @@ def build(A, n):
         L1 = h.level(1)
         _CACHE[n] = (s, h, L0, L1, (rp, ci, v, b))
     return _CACHE[n]
+
+
+def sha(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
 def sample_tiles(ntiles, k, seed):
@@ -149,3 +159,35 @@ def test_solve_true_residual_independent_product(A, n):
             sols[fp32] = xs
     d = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[0])
     assert d <= 1e-6
+
+
+GOLD_SUB256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "layered_sub256.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD_SUB256), reason="golden file not written yet "
+                    "(tests/golden/make_layered_sub256.py)")
+def test_layered_sub256_matches_oracle_golden(A):
+    """The 256^3 system sampled from the 512^3 layered field (contrast ~1e6):
+    every level bit-exact with the oracle's hierarchy (SHA-256 of the natural
+    order arrays written by tests/golden/make_layered_sub256.py), FP64 PCG
+    iterations within one and sampled solution values within 1e-9."""
+    g = json.load(open(GOLD_SUB256))
+    s = P.layered_subsampled(512, seed=2)
+    assert (s.n, s.nnz) == (g["n"], g["nnz"])
+    rp, ci, v, b = A.to_device(s)
+    with A.Hierarchy(rp, ci, v, vcycle_fp32=0) as h:
+        assert h.levels == len(g["levels"])
+        for l, gl in enumerate(g["levels"]):
+            L = h.level(l)
+            assert (L["n"], L["nnz"], L["ncolours"]) == (gl["n"], gl["nnz"], gl["ncolours"]), l
+            if gl["agg_sha256"] is not None:
+                assert sha(L["agg"].astype(np.int32)) == gl["agg_sha256"], l
+            assert sha(L["colour"].astype(np.int32)) == gl["colour_sha256"], l
+            assert sha(L["rowptr"].astype(np.int32)) == gl["rowptr_sha256"], l
+            assert sha(L["colind"].astype(np.int32)) == gl["colind_sha256"], l
+            assert sha(L["vals"].astype(np.float64)) == gl["vals_sha256"], l
+        x, r = h.solve(b, rtol=1e-8)
+    assert r.status == A.OK and abs(r.iterations - g["iterations"]) <= 1
+    xs = x.cpu().numpy()[np.asarray(g["sample_rows"])]
+    ref = np.asarray(g["x_sample"])
+    assert np.max(np.abs(xs - ref)) <= 1e-9 * np.max(np.abs(ref))
