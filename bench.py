@@ -84,10 +84,14 @@ def cpu_baseline(sample_n: int, full_n: int):
 
 
 def batched_section(A, P, nsys: int, nrhs: int = 4, seed: int = 3):
-    """64 uneven lognormal systems x 4 right-hand sides: amg_setup_batched +
-    pcg_solve_batched against a loop of amg_setup + pcg_solve per system and
-    right-hand side (same parameters: FP32 V-cycle, FP64 flexible CG)."""
+    """64 uneven lognormal systems x 4 right-hand sides, FP32 V-cycle in FP64
+    flexible CG to 1e-8: amg_setup_batched + pcg_solve_batched with the
+    autotuned tile / cycle / right-hand-side-interleave variants (tuning timed
+    apart), the same with default parameters, and a loop of amg_setup +
+    pcg_solve per system and right-hand side (default parameters)."""
     import torch
+
+    from paper_1209_0960_amd import autotune as AT
 
     t = time.perf_counter()
     systems = P.batched_systems(nsys, seed=seed, nrhs=nrhs)
@@ -95,21 +99,7 @@ def batched_section(A, P, nsys: int, nrhs: int = 4, seed: int = 3):
     dev = [(torch.from_numpy(s.rowptr).cuda(), torch.from_numpy(s.colind).cuda(), torch.from_numpy(s.vals).cuda(),
             torch.from_numpy(s.b.reshape(-1)).cuda()) for s in systems]
     rows = sum(s.n for s in systems)
-
-    def batched():
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hs = A.Hierarchy.batched([d[:3] for d in dev], vcycle_fp32=1)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        xs = [torch.zeros_like(d[3]) for d in dev]
-        st, infos = A.pcg_solve_batched([h.h for h in hs], [d[3] for d in dev], xs, nrhs=nrhs, rtol=1e-8,
-                                        maxit=500)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for h in hs:
-            h.close()
-        return t1 - t0, t2 - t1, st, [i for inf in infos for i in inf]
+    common = {"vcycle_fp32": 1}
 
     def loop():
         torch.cuda.synchronize()
@@ -118,7 +108,7 @@ def batched_section(A, P, nsys: int, nrhs: int = 4, seed: int = 3):
         infos = []
         for d, s in zip(dev, systems):
             a = time.perf_counter()
-            h = A.Hierarchy(*d[:3], vcycle_fp32=1)
+            h = A.Hierarchy(*d[:3], **common)
             ts += time.perf_counter() - a
             n = s.n
             for k in range(nrhs):
@@ -128,21 +118,32 @@ def batched_section(A, P, nsys: int, nrhs: int = 4, seed: int = 3):
         torch.cuda.synchronize()
         return ts, time.perf_counter() - t0 - ts, infos
 
-    batched()  # warm-up (allocator pool, code objects)
-    bs, bv, st, binf = batched()
+    AT.run_batched(dev, lambda i: {}, nrhs, nrhs, **common)  # warm-up (allocator pool, code objects)
+    table = AT.tune(dev, nrhs, **common)
+    ts, tv, tinf, tst, _ = AT.run_batched(dev, AT.params_from(table, dev), nrhs, table["R"], **common)
+    ds, dv, dinf, dst, _ = AT.run_batched(dev, lambda i: {}, nrhs, nrhs, **common)
     ls, lv, linf = loop()
-    its = [i["iterations"] for i in binf]
+    its = [i["iterations"] for inf in tinf for i in inf]
+    classes = {str(k): v for k, v in table.items() if isinstance(k, int)}
     return {
         "workload": f"{nsys} lognormal systems, edges from {{16,24,32,48,64}} (seed {seed}), sigma^2=2, 4^3 box "
                     f"filter, {nrhs} right-hand sides each; FP32 V-cycle in FP64 flexible CG to 1e-8",
         "unknowns": rows, "solves": nsys * nrhs, "generation_s": gen,
-        "batched_ms": (bs + bv) * 1e3, "batched_setup_ms": bs * 1e3, "batched_solve_ms": bv * 1e3,
+        "batched_ms": (ts + tv) * 1e3, "batched_setup_ms": ts * 1e3, "batched_solve_ms": tv * 1e3,
+        "batched_default_ms": (ds + dv) * 1e3, "batched_default_setup_ms": ds * 1e3,
+        "batched_default_solve_ms": dv * 1e3,
         "loop_ms": (ls + lv) * 1e3, "loop_setup_ms": ls * 1e3, "loop_solve_ms": lv * 1e3,
-        "speedup_batched_vs_loop": (ls + lv) / (bs + bv),
-        "unknown_rhs_per_s_batched": rows * nrhs / (bs + bv),
+        "speedup_batched_vs_loop": (ls + lv) / (ts + tv),
+        "unknown_rhs_per_s_batched": rows * nrhs / (ts + tv),
+        "autotune": {"per_class_rows": classes, "rhs_interleave": table["R"],
+                     "rhs_interleave_ms": {str(k): v for k, v in table["R_ms"].items()},
+                     "tuning_s": table["tuning_s"],
+                     "variants": "tile_rows in {256,512,1024} x tail_rows in {0,8192} per size class; "
+                                 "right-hand sides per entry in {4,2,1}"},
         "iterations_max": max(its), "iterations_mean": float(sum(its)) / len(its),
-        "all_converged": st == A.OK and all(i["converged"] for i in binf) and all(r.converged for r in linf),
-        "worst_true_rel_residual": max(i["true_rel_residual"] for i in binf),
+        "all_converged": tst == A.OK and dst == A.OK and all(i["converged"] for inf in tinf for i in inf)
+                         and all(r.converged for r in linf),
+        "worst_true_rel_residual": max(i["true_rel_residual"] for inf in tinf for i in inf),
     }
 
 
