@@ -20,6 +20,23 @@ constexpr int WAVE = 64;
 
 __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
+// Calls f(k, j) for the stored entries k of row i (column j), loading them in
+// chunks of 8 whose loads are issued together.  The per-tile kernels walk
+// their rows one per lane of a single wavefront, where entry-by-entry loads
+// would be a chain of dependent memory round trips.
+template <typename F>
+__device__ __forceinline__ void for_entries(const int* __restrict__ rp, const int* __restrict__ ci, int i, F f) {
+  const int b = rp[i], e = rp[i + 1];
+  for (int k0 = b; k0 < e; k0 += 8) {
+    int jj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) jj[q] = k0 + q < e ? ci[k0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (jj[q] >= 0) f(k0 + q, jj[q]);
+  }
+}
+
 __device__ inline int wave_incl_scan(int v) {
   const int lane = __lane_id();
 #pragma unroll
@@ -260,12 +277,15 @@ constexpr int AGG_MAX_SLOTS = 32;
 // the current aggregate (63 = none), bit 22 isolated, bit 23 on the front.
 constexpr unsigned ST_AGG = 0xFFFFu, ST_SLOT_SHIFT = 16, ST_SLOT_NONE = 63u << 16, ST_SLOT_MASK = 63u << 16;
 constexpr unsigned ST_ISO = 1u << 22, ST_FRONT = 1u << 23;
+// bits 24-29 of a front vertex: its strong links into the current aggregate
+// (cons2), kept up to date as members are added.
+constexpr unsigned ST_C2_SHIFT = 24, ST_C2_MASK = 63u << 24;
 
 __device__ inline int st_agg(unsigned w) { return (int)(short)(w & ST_AGG); }
 __device__ inline int st_slot(unsigned w) { return (int)((w >> ST_SLOT_SHIFT) & 63u); }
 
 struct AggLayout {
-  size_t lptr, st, key1, adjb, madj, nna, front, adjl, mem, ladj, total;
+  size_t lptr, st, cmm, key1, adjb, madj, nna, front, adjl, mem, ladj, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -275,6 +295,7 @@ __host__ __device__ inline AggLayout agg_layout(int T, int E) {
   size_t o = 0;
   L.lptr = o; o = align16(o + 4 * (size_t)(T + 1));
   L.st = o; o = align16(o + 4 * (size_t)T);
+  L.cmm = o; o = align16(o + 4 * (size_t)T);
   L.key1 = o; o = align16(o + 2 * (size_t)T);
   L.adjb = o; o = align16(o + 4 * (size_t)((T + 31) / 32));
   L.madj = o; o = align16(o + 4 * (size_t)AGG_MAX_SLOTS);
@@ -290,6 +311,7 @@ __host__ __device__ inline AggLayout agg_layout(int T, int E) {
 struct AggSh {
   int* lptr;
   unsigned* st;
+  unsigned* cmm;     // front vertex: mask of the member slots it is adjacent to
   short* key1;       // grow score per front position
   unsigned* adjbits; // bit a: aggregate a is adjacent to the current aggregate
   unsigned* madj;
@@ -337,9 +359,12 @@ __device__ void add_member(const AggSh& S, AggState& as, int c, int id, bool iso
         S.madj[sj] |= 1u << s;
       } else if (aj < 0) {
         const bool elig = iso_phase ? (wj & ST_ISO) != 0 : (wj & ST_ISO) == 0;
-        if (elig && !(wj & ST_FRONT)) {
-          S.st[j] = wj | ST_FRONT;
-          appF = true;
+        if (elig) {
+          // on the front: one more member slot adjacent, one more strong link
+          // (strong flags are symmetric, so c's flag for j is j's for c)
+          S.st[j] = (wj | ST_FRONT) + ((S.ladj[k] >> 15) << ST_C2_SHIFT);
+          S.cmm[j] |= 1u << s;
+          appF = !(wj & ST_FRONT);
         }
       } else {
         const bool track = iso_phase ? (aj < P1) : true;
@@ -362,7 +387,11 @@ __device__ void add_member(const AggSh& S, AggState& as, int c, int id, bool iso
 
 __device__ void clear_aggregate(const AggSh& S, AggState& as) {
   const int lane = __lane_id();
-  for (int p = lane; p < as.fcount; p += WAVE) S.st[S.front[p]] &= ~ST_FRONT;
+  for (int p = lane; p < as.fcount; p += WAVE) {
+    const int c = S.front[p];
+    S.st[c] &= ~(ST_FRONT | ST_C2_MASK);
+    S.cmm[c] = 0;
+  }
   for (int p = lane; p < as.acount; p += WAVE) {
     const int a = S.adjl[p];
     atomicAnd(&S.adjbits[a >> 5], ~(1u << (a & 31)));
@@ -462,6 +491,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   AggSh S;
   S.lptr = (int*)(sm + Lo.lptr);
   S.st = (unsigned*)(sm + Lo.st);
+  S.cmm = (unsigned*)(sm + Lo.cmm);
   S.key1 = (short*)(sm + Lo.key1);
   S.adjbits = (unsigned*)(sm + Lo.adjb);
   S.madj = (unsigned*)(sm + Lo.madj);
@@ -483,10 +513,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
     int cnt = 0;
     if (v < nt) {
       const int i = lo + v;
-      for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = ci[k];
-        cnt += (j != i && j >= lo && j < lo + nt) ? 1 : 0;
-      }
+      for_entries(rp, ci, i, [&](int, int j) { cnt += (j != i && j >= lo && j < lo + nt) ? 1 : 0; });
     }
     const int inc = wave_incl_scan(cnt);
     if (v < nt) S.lptr[v] = carry + inc - cnt;
@@ -498,12 +525,12 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   for (int v = lane; v < nt; v += WAVE) {
     const int i = lo + v;
     int pos = S.lptr[v];
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      const int j = ci[k];
+    for_entries(rp, ci, i, [&](int k, int j) {
       if (j != i && j >= lo && j < lo + nt) S.ladj[pos++] = (unsigned short)((j - lo) | (strong[k] ? 0x8000 : 0));
-    }
+    });
     const bool is = isov[i] != 0;
     S.st[v] = ST_AGG | ST_SLOT_NONE | (is ? ST_ISO : 0u);
+    S.cmm[v] = 0;
     S.nna[v] = (short)(pos - S.lptr[v]);
     nonIso += is ? 0 : 1;
   }
@@ -534,11 +561,12 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
         if (p < as.fcount) {
           const int c = S.front[p];
           int k1 = -1;
-          if (st_agg(S.st[c]) < 0) {
-            const ScoreA r = score_a(S, c, id);
-            const int ok = (r.c2 > 0 && ecc_ok(S, r.mm, as.asize, dmax)) ? 1 : 0;
-            k1 = ok ? r.c2 : 0;
-            if (ok) lm2 = max(lm2, r.c2);
+          const unsigned wc = S.st[c];
+          if (st_agg(wc) < 0) {
+            const int c2 = (int)((wc & ST_C2_MASK) >> ST_C2_SHIFT);
+            const int ok = (c2 > 0 && ecc_ok(S, S.cmm[c], as.asize, dmax)) ? 1 : 0;
+            k1 = ok ? c2 : 0;
+            if (ok) lm2 = max(lm2, c2);
           }
           S.key1[p] = (short)k1;
         }
@@ -911,9 +939,8 @@ __global__ __launch_bounds__(WAVE) void k_tile_nbrs(int n, int T, const int* __r
   __syncthreads();
   for (int v = lane; v < nt; v += WAVE) {
     const int i = lo + v;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      const int j = ci[k];
-      if (j >= lo && j < hi) continue;
+    for_entries(rp, ci, i, [&](int, int j) {
+      if (j >= lo && j < hi) return;
       const int u = j / T;
       int h = (int)(fmix32((uint32_t)u) & (TSET - 1));
       for (int probe = 0;; ++probe) {
@@ -925,7 +952,7 @@ __global__ __launch_bounds__(WAVE) void k_tile_nbrs(int n, int T, const int* __r
         if (old == -1 || old == u) break;
         h = (h + 1) & (TSET - 1);
       }
-    }
+    });
   }
   __syncthreads();
   if (!adj) {
@@ -997,18 +1024,17 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
       const int i = lo + v;
       uint64_t m = 0;
       unsigned char bg = 0;
-      for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = ci[k];
+      for_entries(rp, ci, i, [&](int, int j) {
         if (j >= lo && j < hi) {
           cnt += (j < i) ? 1 : 0;
-          continue;
+          return;
         }
         const int cj = colour[j];
         if (cj >= 64)
           bg = 1;
         else if (cj >= 0)
           m |= 1ull << cj;
-      }
+      });
       mask[v] = m;
       big[v] = bg;
     }
@@ -1021,17 +1047,56 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
   for (int v = lane; v < nt; v += WAVE) {
     const int i = lo + v;
     int pos = lptr[v];
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      const int j = ci[k];
+    for_entries(rp, ci, i, [&](int, int j) {
       if (j >= lo && j < i) adj[pos++] = (unsigned short)(j - lo);
-    }
+    });
     col[v] = -1;
+  }
+  __syncthreads();
+  // First-fit colour of a row depends only on the colours of its smaller
+  // neighbours, so rows whose smaller in-tile neighbours are all coloured can
+  // be coloured at once: wavefront rounds (one lane per row) while the rate
+  // would finish the tile in a few dozen rounds, then rows in ascending order
+  // for the rest of a long chain.  Both give the sequential first-fit colouring.
+  int cmax = -1;
+  int first = 0;  // every row below `first` is coloured
+  int total = 0;  // rows coloured by the rounds
+  for (int round = 0; round < 64; ++round) {
+    int made = 0;
+    for (int v = first + lane; v < nt; v += WAVE) {
+      if (col[v] >= 0) continue;
+      uint64_t m = mask[v];
+      bool ready = true, bg = big[v] != 0;
+      for (int q = lptr[v]; q < lptr[v + 1]; ++q) {
+        const int cj = col[adj[q]];
+        if (cj < 0) {
+          ready = false;
+          break;
+        }
+        if (cj < 64)
+          m |= 1ull << cj;
+        else
+          bg = true;
+      }
+      if (!ready || bg || m == ~0ull) continue;  // colours beyond 63: left to the ordered pass
+      const int c = (int)__builtin_ctzll(~m);
+      col[v] = c;
+      cmax = max(cmax, c);
+      ++made;
+    }
+    __syncthreads();
+    made = wave_sum(made);
+    total += made;
+    while (first < nt && col[first] >= 0) ++first;
+    if (first >= nt || made == 0) break;
+    // A long dependency chain (few rows per round) is faster row by row.
+    if (round >= 7 && (long long)(nt - total) * (round + 1) > 40LL * total) break;
   }
   __syncthreads();
   // Rows in ascending order; the lanes read one row's smaller in-tile
   // neighbours together and OR their colours into the forbidden mask.
-  int cmax = -1;
-  for (int v = 0; v < nt; ++v) {
+  for (int v = first; v < nt; ++v) {
+    if (col[v] >= 0) continue;
     uint64_t m = 0;
     bool bg = false;
     for (int q = lptr[v] + lane; q < lptr[v + 1]; q += WAVE) {
@@ -1070,7 +1135,7 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
   for (int v = lane; v < nt; v += WAVE) colour[lo + v] = col[v];
   cmax = wave_max(cmax);
   if (lane == 0) atomicMax(maxcol, cmax);
-  __threadfence();
+  // Released tiles are coloured by the next launch, which sees these colours.
   for (int q0 = tptr[t]; q0 < tptr[t + 1]; q0 += WAVE) {
     const int q = q0 + lane;
     bool rel = false;
