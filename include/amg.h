@@ -86,6 +86,7 @@ typedef struct amg_params {
   int32_t use_graphs;        /* 1: pcg_solve replays each iteration as a HIP graph [1] */
   int32_t tail_rows;         /* levels with at most this many rows (and all    [0]
                                 coarser ones) are cycled by one workgroup per solve */
+  int32_t colour_tile_rows;  /* rows per tile of the colouring order (64..1024) [128] */
 } amg_params;
 
 typedef struct amg_solve_info {

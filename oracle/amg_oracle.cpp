@@ -580,6 +580,7 @@ struct Params {
   int smoother, pre, post, fp32, flexible;
   uint32_t colour_seed;
   int check_symmetry;
+  int colour_tile_rows;  // rows per tile of the colouring order
 };
 
 enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1 };
@@ -737,7 +738,7 @@ int validate(const Csr& A, int check_symmetry) {
 }
 
 void finish_level(Level& L, const Params& p, int l) {
-  L.ncol = colour_rows(L.A, p.tile_rows, p.colour_seed + (uint32_t)l, L.colour);
+  L.ncol = colour_rows(L.A, p.colour_tile_rows, p.colour_seed + (uint32_t)l, L.colour);
   L.rows_of_colour.assign(L.ncol, {});
   for (int i = 0; i < L.A.n; ++i) L.rows_of_colour[L.colour[i]].push_back(i);
   L.val32.resize(L.A.nnz());
@@ -806,6 +807,7 @@ struct orc_params {
   int smoother, pre_sweeps, post_sweeps, vcycle_fp32, flexible;
   uint32_t colour_seed;
   int check_symmetry;
+  int colour_tile_rows;
 };
 
 static Params to_params(const orc_params* q) {
@@ -826,6 +828,7 @@ static Params to_params(const orc_params* q) {
   p.flexible = q->flexible < 0 ? q->vcycle_fp32 : q->flexible;
   p.colour_seed = q->colour_seed;
   p.check_symmetry = q->check_symmetry;
+  p.colour_tile_rows = q->colour_tile_rows;
   return p;
 }
 

@@ -182,6 +182,7 @@ void check_params(const amg_params& p) {
   if (p.smoother != AMG_SMOOTHER_MCSGS && p.smoother != AMG_SMOOTHER_L1_JACOBI) fail(AMG_ERR_INVALID_ARG, "smoother");
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
   if (p.tail_rows < 0) fail(AMG_ERR_INVALID_ARG, "tail_rows");
+  if (p.colour_tile_rows < 64 || p.colour_tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows outside 64..1024");
 }
 
 void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy& H) {
@@ -317,6 +318,7 @@ amg_status amg_default_params(amg_params* p) {
   p->keep_setup_data = 0;
   p->use_graphs = 1;
   p->tail_rows = 0;
+  p->colour_tile_rows = 128;
   return AMG_OK;
 }
 

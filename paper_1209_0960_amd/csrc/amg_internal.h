@@ -183,7 +183,7 @@ enum {
   S_COUNT = 16
 };
 
-constexpr int RED_BLOCKS = 1024;  // upper bound on the partial sums of one dot product
+constexpr int RED_BLOCKS = 8192;  // upper bound on the partial sums of one dot product
 constexpr int RED_THREADS = 256;
 constexpr int MAX_LEVELS = 32;
 constexpr int MAX_RHS = 8;

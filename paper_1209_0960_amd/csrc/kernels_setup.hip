@@ -1634,8 +1634,8 @@ void galerkin(Hierarchy& H, const Level& L, Level& C, hipStream_t s) {
 }
 
 void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
-  const int n = L.n, T = L.T;
-  if (T > COL_MAX_T) fail(AMG_ERR_UNSUPPORTED, "tile_rows above 1024");
+  const int n = L.n, T = H.p.colour_tile_rows;
+  if (T > COL_MAX_T) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows above 1024");
   const int ntiles = cdiv(n, T);
   L.colour = H.alloc<int>((size_t)n, s);
   DBuf cnt(4 * sizeof(int), s), w0((size_t)ntiles * sizeof(int), s), w1((size_t)ntiles * sizeof(int), s);

@@ -143,6 +143,25 @@ __device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __res
 #pragma unroll
   for (int k = 0; k < R; ++k) acc[k] = 0;
   int e = 0;
+  if constexpr (R * sizeof(V) <= 8) {
+    // Long rows (coarse levels): chunks of 8 entries with all their loads,
+    // then all their gathers, in flight together; same summation order.
+    for (; w > 8 && e + 8 <= w; e += 8) {
+      int j[8];
+      V a[8], xv[8][R];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        j[q] = cp[64 * (e + q)];
+        a[q] = vp[64 * (e + q)];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ldv<V, R>(x + (size_t)j[q] * R, xv[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = madd(a[q], xv[q][k], acc[k]);
+    }
+  }
   for (; e + 2 <= w; e += 2) {
     const int j0 = cp[64 * e], j1 = cp[64 * (e + 1)];
     const V a0 = vp[64 * e], a1 = vp[64 * (e + 1)];

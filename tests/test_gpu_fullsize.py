@@ -132,7 +132,7 @@ def test_galerkin_rows_sampled(A, n):
 
 def test_colouring_128_full(A):
     s, h, L0, _, _ = build(A, 128)
-    c, k = O.colour(s.rowptr, s.colind, seed=0, tile_rows=T)
+    c, k = O.colour(s.rowptr, s.colind, seed=0, tile_rows=128)  # colour_tile_rows default
     assert L0["ncolours"] == k and np.array_equal(L0["colour"], c)
 
 
