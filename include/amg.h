@@ -192,9 +192,13 @@ AMG_API void amg_batch_free(amg_batch *b);
 AMG_API const char *amg_status_string(amg_status s);
 AMG_API const char *amg_last_error(void);
 
-/* Device allocator used for all library memory (default: stream-ordered
- * hipMallocAsync/hipFreeAsync).  alloc returns NULL on failure.  Passing
- * NULL for both restores the default.  Not thread-safe with running setups. */
+/* Device allocator used for all library memory.  Default: a cache of
+ * hipMalloc blocks (freed blocks are reused best fit; reuse from another
+ * stream waits for an event recorded when the block was freed; idle blocks
+ * return to the device only when a hipMalloc fails).  alloc returns NULL on
+ * failure.  Passing NULL for both restores the default.  Change it only while
+ * no hierarchy, batch or solve allocated by the other allocator exists and
+ * no call is running. */
 typedef void *(*amg_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*amg_free_fn)(void *ptr, void *stream, void *ctx);
 AMG_API amg_status amg_set_allocator(amg_alloc_fn alloc, amg_free_fn free_fn, void *ctx);

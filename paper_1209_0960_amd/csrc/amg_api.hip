@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cstring>
 #include <atomic>
+#include <map>
+#include <unordered_map>
 #include <mutex>
 #include <thread>
 
@@ -24,7 +26,52 @@ void fail(amg_status st, const std::string& msg) {
 static amg_alloc_fn g_alloc = nullptr;
 static amg_free_fn g_free = nullptr;
 static void* g_ctx = nullptr;
-static std::once_flag g_pool_once;
+
+// Default allocator: a cache of hipMalloc blocks.  A freed block keeps an
+// event recorded on the freeing stream; reusing it from another stream first
+// makes that stream wait for the event, so every reuse is ordered after the
+// block's last use.  Blocks are rounded (256 B below 1 MiB, 2 MiB above) and
+// reused best fit within 25% + 2 MiB of the request; they are returned to the
+// device only when a hipMalloc fails (then every idle block is released and
+// the allocation retried).  The stream-ordered runtime pool was measured at
+// milliseconds of runtime calls per hierarchy; this keeps setup and release
+// to a map lookup per buffer once warm.
+namespace {
+struct CBlock {
+  void* p;
+  hipStream_t s;
+  hipEvent_t ev;
+};
+std::mutex g_cmu;
+std::multimap<std::pair<int, size_t>, CBlock> g_cache;  // (device, bytes) -> idle block
+std::unordered_map<void*, std::pair<int, size_t>> g_live;  // live block -> (device, bytes)
+std::vector<hipEvent_t> g_cev;
+
+size_t round_bytes(size_t b) {
+  const size_t MB2 = (size_t)2 << 20;
+  return b < ((size_t)1 << 20) ? (b + 255) & ~(size_t)255 : (b + MB2 - 1) / MB2 * MB2;
+}
+
+void release_idle(int dev) {
+  std::vector<CBlock> drop;
+  {
+    std::lock_guard<std::mutex> g(g_cmu);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+      if (it->first.first == dev) {
+        drop.push_back(it->second);
+        it = g_cache.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (auto& c : drop) {
+    (void)hipEventSynchronize(c.ev);
+    (void)hipFree(c.p);
+    (void)hipEventDestroy(c.ev);
+  }
+}
+}  // namespace
 
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 16;
@@ -33,23 +80,41 @@ void* dalloc(size_t bytes, hipStream_t s) {
     if (!p) fail(AMG_ERR_OUT_OF_MEMORY, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
     return p;
   }
-  std::call_once(g_pool_once, [] {
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-      hipMemPool_t pool;
-      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-      }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t need = round_bytes(bytes);
+  CBlock hit{nullptr, nullptr, nullptr};
+  size_t got = 0;
+  {
+    std::lock_guard<std::mutex> g(g_cmu);
+    auto it = g_cache.lower_bound({dev, need});
+    if (it != g_cache.end() && it->first.first == dev && it->first.second <= need + need / 4 + ((size_t)2 << 20)) {
+      hit = it->second;
+      got = it->first.second;
+      g_cache.erase(it);
+      g_live[hit.p] = {dev, got};
     }
-  });
+  }
+  if (hit.p) {
+    if (hit.s != s) AMG_HIP(hipStreamWaitEvent(s, hit.ev, 0));
+    std::lock_guard<std::mutex> g(g_cmu);
+    g_cev.push_back(hit.ev);
+    return hit.p;
+  }
   void* p = nullptr;
-  hipError_t e = hipMallocAsync(&p, bytes, s);
+  hipError_t e = hipMalloc(&p, need);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    release_idle(dev);
+    e = hipMalloc(&p, need);
+  }
   if (e != hipSuccess || !p) {
     (void)hipGetLastError();
     fail(e == hipErrorOutOfMemory ? AMG_ERR_OUT_OF_MEMORY : AMG_ERR_HIP,
-         std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+         std::string("hipMalloc(") + std::to_string(need) + "): " + hipGetErrorString(e));
   }
+  std::lock_guard<std::mutex> g(g_cmu);
+  g_live[p] = {dev, need};
   return p;
 }
 
@@ -59,7 +124,28 @@ void dfree(void* p, hipStream_t s) {
     g_free(p, (void*)s, g_ctx);
     return;
   }
-  (void)hipFreeAsync(p, s);
+  hipEvent_t ev = nullptr;
+  std::pair<int, size_t> key;
+  {
+    std::lock_guard<std::mutex> g(g_cmu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;  // not ours
+    key = it->second;
+    g_live.erase(it);
+    if (!g_cev.empty()) {
+      ev = g_cev.back();
+      g_cev.pop_back();
+    }
+  }
+  if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p);
+    return;
+  }
+  (void)hipEventRecord(ev, s);
+  std::lock_guard<std::mutex> g(g_cmu);
+  g_cache.insert({key, CBlock{p, s, ev}});
 }
 
 void Hierarchy::free_one(void* ptr, hipStream_t s) {

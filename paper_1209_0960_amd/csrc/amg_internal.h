@@ -31,7 +31,7 @@ struct Failure {
 [[noreturn]] void fail(amg_status st, const std::string& msg);
 
 // ------------------------------------------------------------------ memory
-// Device allocation through the user hook or stream-ordered hipMallocAsync.
+// Device allocation through the user hook or the library's block cache.
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "amg_internal.h"
 
@@ -35,6 +36,86 @@ constexpr int SLICES_PB = 4;     // slices per block of the sweep / residual ker
 // slices per wavefront), so they get more blocks.
 int red_blocks_rows(int n) { return std::min(1024, std::max(1, cdiv(n, 2048))); }
 int red_blocks_slices(int nsl) { return std::min(RED_BLOCKS, std::max(1, cdiv(nsl, 32))); }
+
+// Process-wide reuse of pinned host buffers, streams and events: creating and
+// destroying them costs milliseconds of runtime calls per solve context.
+std::mutex g_pool_mu;
+std::vector<std::pair<size_t, void*>> g_pinned;  // (bytes, pointer), free
+std::vector<std::pair<int, hipStream_t>> g_streams;  // (device, stream), free
+std::vector<std::pair<int, hipEvent_t>> g_events;
+
+void* pinned_take(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    size_t best = SIZE_MAX;
+    for (size_t i = 0; i < g_pinned.size(); ++i)
+      if (g_pinned[i].first >= bytes && g_pinned[i].first <= 4 * bytes + 65536 &&
+          (best == SIZE_MAX || g_pinned[i].first < g_pinned[best].first))
+        best = i;
+    if (best != SIZE_MAX) {
+      void* p = g_pinned[best].second;
+      g_pinned[best] = g_pinned.back();
+      g_pinned.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  AMG_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+  return p;
+}
+void pinned_give(void* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  g_pinned.emplace_back(bytes, p);
+}
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+hipStream_t stream_take() {
+  const int dev = current_device();
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    for (size_t i = 0; i < g_streams.size(); ++i)
+      if (g_streams[i].first == dev) {
+        hipStream_t st = g_streams[i].second;
+        g_streams[i] = g_streams.back();
+        g_streams.pop_back();
+        return st;
+      }
+  }
+  hipStream_t st = nullptr;
+  AMG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  return st;
+}
+void stream_give(hipStream_t st) {
+  if (!st) return;
+  (void)hipStreamSynchronize(st);
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  g_streams.emplace_back(current_device(), st);
+}
+hipEvent_t event_take() {
+  const int dev = current_device();
+  {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    for (size_t i = 0; i < g_events.size(); ++i)
+      if (g_events[i].first == dev) {
+        hipEvent_t e = g_events[i].second;
+        g_events[i] = g_events.back();
+        g_events.pop_back();
+        return e;
+      }
+  }
+  hipEvent_t e = nullptr;
+  AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return e;
+}
+void event_give(hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> g(g_pool_mu);
+  g_events.emplace_back(current_device(), e);
+}
 
 }  // namespace
 
@@ -148,15 +229,15 @@ void batch_init(Batch& B, int R, int cap, int use_graphs) {
   B.cap = cap;
   B.use_graphs = use_graphs;
   B.ent.resize(cap);
-  AMG_HIP(hipStreamCreateWithFlags(&B.work, hipStreamNonBlocking));
-  AMG_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
-  AMG_HIP(hipHostMalloc((void**)&B.desc_h, (size_t)cap * MAX_LEVELS * sizeof(BDesc), hipHostMallocDefault));
+  B.work = stream_take();
+  B.ev = event_take();
+  B.desc_h = static_cast<BDesc*>(pinned_take((size_t)cap * MAX_LEVELS * sizeof(BDesc)));
   for (size_t i = 0; i < (size_t)cap * MAX_LEVELS; ++i) B.desc_h[i] = BDesc{};
   B.desc_d = static_cast<BDesc*>(dalloc((size_t)cap * MAX_LEVELS * sizeof(BDesc), B.work));
   B.scal_d = static_cast<double*>(dalloc(B.scal_count() * sizeof(double), B.work));
   B.ctl_d = static_cast<int*>(dalloc((size_t)cap * CTL_INTS * sizeof(int), B.work));
-  AMG_HIP(hipHostMalloc((void**)&B.scal_h, B.scal_count() * sizeof(double), hipHostMallocDefault));
-  AMG_HIP(hipHostMalloc((void**)&B.ctl_h, (size_t)cap * CTL_INTS * sizeof(int), hipHostMallocDefault));
+  B.scal_h = static_cast<double*>(pinned_take(B.scal_count() * sizeof(double)));
+  B.ctl_h = static_cast<int*>(pinned_take((size_t)cap * CTL_INTS * sizeof(int)));
   std::memset(B.ctl_h, 0, (size_t)cap * CTL_INTS * sizeof(int));
   AMG_HIP(hipMemsetAsync(B.ctl_d, 0, (size_t)cap * CTL_INTS * sizeof(int), B.work));
   AMG_HIP(hipMemsetAsync(B.scal_d, 0, B.scal_count() * sizeof(double), B.work));
@@ -854,15 +935,15 @@ void batch_release(Batch& B) {
   B.scal_d = nullptr;
   B.ctl_d = nullptr;
   if (s) (void)hipStreamSynchronize(s);
-  if (B.desc_h) (void)hipHostFree(B.desc_h);
+  pinned_give(B.desc_h, (size_t)B.cap * MAX_LEVELS * sizeof(BDesc));
   B.desc_h = nullptr;
-  if (B.scal_h) (void)hipHostFree(B.scal_h);
-  if (B.ctl_h) (void)hipHostFree(B.ctl_h);
+  pinned_give(B.scal_h, B.scal_count() * sizeof(double));
+  pinned_give(B.ctl_h, (size_t)B.cap * CTL_INTS * sizeof(int));
   B.scal_h = nullptr;
   B.ctl_h = nullptr;
-  if (B.ev) (void)hipEventDestroy(B.ev);
+  event_give(B.ev);
   B.ev = nullptr;
-  if (s) (void)hipStreamDestroy(s);
+  stream_give(s);
   B.work = nullptr;
 }
 
