@@ -193,9 +193,11 @@ AMG_API const char *amg_status_string(amg_status s);
 AMG_API const char *amg_last_error(void);
 
 /* Device allocator used for all library memory.  Default: a cache of
- * hipMalloc blocks (freed blocks are reused best fit; reuse from another
- * stream waits for an event recorded when the block was freed; idle blocks
- * return to the device only when a hipMalloc fails).  alloc returns NULL on
+ * hipMalloc blocks (freed blocks are reused best fit, by the stream that
+ * freed them, or by any stream once the library has synchronised that stream
+ * after the free; idle blocks return to the device only when a hipMalloc
+ * fails).
+ * alloc returns NULL on
  * failure.  Passing NULL for both restores the default.  Change it only while
  * no hierarchy, batch or solve allocated by the other allocator exists and
  * no call is running. */
@@ -244,7 +246,8 @@ enum {
   AMG_KIND_PROLONG = 3,       /* level-0 prolongation                            */
   AMG_KIND_CG_VEC = 4,        /* CG vector updates and dot products              */
   AMG_KIND_COARSE_LEVELS = 5, /* every launch of levels >= 1                     */
-  AMG_KIND_OTHER = 6,         /* level-0 fills (iterate set to zero)             */
+  AMG_KIND_OTHER = 6,         /* level-0 fills and the smoother's first pass     *
+                               * from a zero iterate (x = b / diag)             */
   AMG_KIND_COUNT = 7
 };
 AMG_API amg_status amg_set_kernel_timing(int32_t kind_mask);

@@ -27,51 +27,114 @@ static amg_alloc_fn g_alloc = nullptr;
 static amg_free_fn g_free = nullptr;
 static void* g_ctx = nullptr;
 
-// Default allocator: a cache of hipMalloc blocks.  A freed block keeps an
-// event recorded on the freeing stream; reusing it from another stream first
-// makes that stream wait for the event, so every reuse is ordered after the
-// block's last use.  Blocks are rounded (256 B below 1 MiB, 2 MiB above) and
-// reused best fit within 25% + 2 MiB of the request; they are returned to the
-// device only when a hipMalloc fails (then every idle block is released and
+// Default allocator: a cache of hipMalloc blocks.  A freed block is kept for
+// the stream that freed it, whose order puts any reuse after the block's last
+// use; once the library has synchronised that stream after the free, the
+// block is idle and any stream may take it.  No stream waits on an event of
+// another stream, which may be under graph capture meanwhile.  Blocks are
+// rounded (256 B below 1 MiB, 2 MiB above) and reused best fit within 25% +
+// 2 MiB of the request; they return to the device only when a hipMalloc fails
+// (then the calling stream is synchronised, every idle block is released and
 // the allocation retried).  The stream-ordered runtime pool was measured at
 // milliseconds of runtime calls per hierarchy; this keeps setup and release
 // to a map lookup per buffer once warm.
 namespace {
-struct CBlock {
+constexpr uintptr_t ANY_STREAM = ~(uintptr_t)0;
+struct CKey {
+  int dev;
+  uintptr_t s;  // freeing stream, or ANY_STREAM once idle
+  size_t bytes;
+  bool operator<(const CKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (s != o.s) return s < o.s;
+    return bytes < o.bytes;
+  }
+};
+struct CVal {
   void* p;
-  hipStream_t s;
-  hipEvent_t ev;
+  unsigned long long gen;  // order of the free
 };
 std::mutex g_cmu;
-std::multimap<std::pair<int, size_t>, CBlock> g_cache;  // (device, bytes) -> idle block
+std::multimap<CKey, CVal> g_cache;
 std::unordered_map<void*, std::pair<int, size_t>> g_live;  // live block -> (device, bytes)
-std::vector<hipEvent_t> g_cev;
+unsigned long long g_gen = 0;
 
 size_t round_bytes(size_t b) {
   const size_t MB2 = (size_t)2 << 20;
   return b < ((size_t)1 << 20) ? (b + 255) & ~(size_t)255 : (b + MB2 - 1) / MB2 * MB2;
 }
 
-void release_idle(int dev) {
-  std::vector<CBlock> drop;
-  {
-    std::lock_guard<std::mutex> g(g_cmu);
-    for (auto it = g_cache.begin(); it != g_cache.end();) {
-      if (it->first.first == dev) {
-        drop.push_back(it->second);
-        it = g_cache.erase(it);
-      } else {
-        ++it;
-      }
+// The cache's runtime calls (hipMalloc, hipFree) concern only memory that no
+// stream uses.  Other threads may be capturing graphs meanwhile; the relaxed
+// interaction mode keeps these calls from invalidating those captures.
+struct RelaxedCapture {
+  hipStreamCaptureMode m = hipStreamCaptureModeRelaxed;
+  RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&m); }
+  ~RelaxedCapture() { (void)hipThreadExchangeStreamCaptureMode(&m); }
+};
+
+// Takes the smallest fitting block kept for (dev, s); the lock is held.
+void* take_block(int dev, uintptr_t s, size_t need) {
+  const size_t limit = need + need / 4 + ((size_t)2 << 20);
+  auto it = g_cache.lower_bound(CKey{dev, s, need});
+  if (it == g_cache.end() || it->first.dev != dev || it->first.s != s || it->first.bytes > limit) return nullptr;
+  void* p = it->second.p;
+  g_live[p] = {dev, it->first.bytes};
+  g_cache.erase(it);
+  return p;
+}
+
+// Blocks freed on s up to free number `gen` become idle (s has been
+// synchronised after those frees).
+void promote(hipStream_t s, unsigned long long gen) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(g_cmu);
+  auto it = g_cache.lower_bound(CKey{dev, (uintptr_t)s, 0});
+  while (it != g_cache.end() && it->first.dev == dev && it->first.s == (uintptr_t)s) {
+    if (it->second.gen <= gen) {
+      g_cache.insert({CKey{dev, ANY_STREAM, it->first.bytes}, it->second});
+      it = g_cache.erase(it);
+    } else {
+      ++it;
     }
   }
-  for (auto& c : drop) {
-    (void)hipEventSynchronize(c.ev);
-    (void)hipFree(c.p);
-    (void)hipEventDestroy(c.ev);
+}
+
+unsigned long long free_count() {
+  std::lock_guard<std::mutex> g(g_cmu);
+  return g_gen;
+}
+
+void release_idle(int dev, hipStream_t s) {
+  const unsigned long long gen = free_count();
+  if (hipStreamSynchronize(s) == hipSuccess) promote(s, gen);
+  (void)hipGetLastError();
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(g_cmu);
+    auto it = g_cache.lower_bound(CKey{dev, ANY_STREAM, 0});
+    while (it != g_cache.end() && it->first.dev == dev && it->first.s == ANY_STREAM) {
+      drop.push_back(it->second.p);
+      it = g_cache.erase(it);
+    }
   }
+  for (void* p : drop) (void)hipFree(p);
 }
 }  // namespace
+
+hipError_t sync_stream_nothrow(hipStream_t s) {
+  const unsigned long long gen = free_count();
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) promote(s, gen);
+  return e;
+}
+
+void sync_stream(hipStream_t s) {
+  const unsigned long long gen = free_count();
+  AMG_HIP(hipStreamSynchronize(s));
+  promote(s, gen);
+}
 
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 16;
@@ -83,29 +146,18 @@ void* dalloc(size_t bytes, hipStream_t s) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   const size_t need = round_bytes(bytes);
-  CBlock hit{nullptr, nullptr, nullptr};
-  size_t got = 0;
   {
     std::lock_guard<std::mutex> g(g_cmu);
-    auto it = g_cache.lower_bound({dev, need});
-    if (it != g_cache.end() && it->first.first == dev && it->first.second <= need + need / 4 + ((size_t)2 << 20)) {
-      hit = it->second;
-      got = it->first.second;
-      g_cache.erase(it);
-      g_live[hit.p] = {dev, got};
-    }
+    void* p = take_block(dev, (uintptr_t)s, need);
+    if (!p) p = take_block(dev, ANY_STREAM, need);
+    if (p) return p;
   }
-  if (hit.p) {
-    if (hit.s != s) AMG_HIP(hipStreamWaitEvent(s, hit.ev, 0));
-    std::lock_guard<std::mutex> g(g_cmu);
-    g_cev.push_back(hit.ev);
-    return hit.p;
-  }
+  RelaxedCapture relaxed;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, need);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
-    release_idle(dev);
+    release_idle(dev, s);
     e = hipMalloc(&p, need);
   }
   if (e != hipSuccess || !p) {
@@ -124,28 +176,12 @@ void dfree(void* p, hipStream_t s) {
     g_free(p, (void*)s, g_ctx);
     return;
   }
-  hipEvent_t ev = nullptr;
-  std::pair<int, size_t> key;
-  {
-    std::lock_guard<std::mutex> g(g_cmu);
-    auto it = g_live.find(p);
-    if (it == g_live.end()) return;  // not ours
-    key = it->second;
-    g_live.erase(it);
-    if (!g_cev.empty()) {
-      ev = g_cev.back();
-      g_cev.pop_back();
-    }
-  }
-  if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(p);
-    return;
-  }
-  (void)hipEventRecord(ev, s);
   std::lock_guard<std::mutex> g(g_cmu);
-  g_cache.insert({key, CBlock{p, s, ev}});
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;  // not ours
+  const CKey key{it->second.first, (uintptr_t)s, it->second.second};
+  g_live.erase(it);
+  g_cache.insert({key, CVal{p, ++g_gen}});
 }
 
 void Hierarchy::free_one(void* ptr, hipStream_t s) {
@@ -374,7 +410,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     if (C.n > 4096) fail(AMG_ERR_COARSENING_STALLED, "coarsest level has " + std::to_string(C.n) + " rows");
     coarse_factor(H, C, s);
   }
-  AMG_HIP(hipStreamSynchronize(s));
+  sync_stream(s);
   H.setup_ms = now_ms() - t0;
 }
 
@@ -423,9 +459,9 @@ amg_status amg_setup(const amg_csr* A, const amg_params* p, void* stream, amg_hi
   }
   amg_status st = guarded([&] { setup_impl(A, p, S(stream), h->H); });
   if (st != AMG_OK) {
-    (void)hipStreamSynchronize(S(stream));
+    (void)sync_stream_nothrow(S(stream));
     h->H.release(S(stream));
-    (void)hipStreamSynchronize(S(stream));
+    (void)sync_stream_nothrow(S(stream));
     delete h;
     return st;
   }
@@ -455,9 +491,9 @@ amg_status pcg_solve(amg_hierarchy* h, const double* b, double* x, double rtol, 
 void amg_free(amg_hierarchy* h) {
   if (!h) return;
   hipStream_t s = h->H.setup_stream;
-  (void)hipStreamSynchronize(s);
+  (void)sync_stream_nothrow(s);
   h->H.release(s);
-  (void)hipStreamSynchronize(s);
+  (void)sync_stream_nothrow(s);
   delete h;
 }
 
@@ -606,7 +642,7 @@ amg_status amg_setup_batched(const amg_csr* A, int32_t nsys, const amg_params* p
   // colour counts), so several run at once, each from its own host thread on
   // its own stream; their kernels overlap on the device.
   hipStream_t us = S(stream);
-  if (hipStreamSynchronize(us) != hipSuccess) {
+  if (sync_stream_nothrow(us) != hipSuccess) {
     set_error("caller stream failed");
     return AMG_ERR_HIP;
   }
@@ -631,7 +667,7 @@ amg_status amg_setup_batched(const amg_csr* A, int32_t nsys, const amg_params* p
       if (out[i]) out[i]->H.setup_stream = us;
     }
     if (s) {
-      (void)hipStreamSynchronize(s);
+      (void)sync_stream_nothrow(s);
       (void)hipStreamDestroy(s);
     }
   };

@@ -34,6 +34,10 @@ struct Failure {
 // Device allocation through the user hook or the library's block cache.
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
+// Synchronise a stream; blocks the library freed on it before the call become
+// reusable from any stream.
+void sync_stream(hipStream_t s);
+hipError_t sync_stream_nothrow(hipStream_t s);
 
 // RAII owner of a temporary device buffer.
 struct DBuf {
@@ -273,6 +277,7 @@ enum {
   OP_DOT_BB,     // partials of b.b
   OP_VZERO_ROLD, // r_old = 0 (rows)
   OP_FINISH,     // per entry: reduce partials, scalar update (aux = FIN_*, aux2 = slot)
+  OP_GS0,        // first Gauss-Seidel pass from x = 0: x = b / diag on the slices of one colour
 };
 enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
 

@@ -91,7 +91,7 @@ hipStream_t stream_take() {
 }
 void stream_give(hipStream_t st) {
   if (!st) return;
-  (void)hipStreamSynchronize(st);
+  (void)sync_stream_nothrow(st);
   std::lock_guard<std::mutex> g(g_pool_mu);
   g_streams.emplace_back(current_device(), st);
 }
@@ -478,29 +478,70 @@ void add_slices(Builder& b, const Batch& B, int slot, int l, int s0, int s1) {
   }
 }
 
-void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l) {
+// Colours of the passes of `sweeps` symmetric multicolour Gauss-Seidel sweeps
+// (forward, then backward over the colours).  A pass on the colour updated by
+// the pass before is left out: rows of one colour depend only on the other
+// colours, so it would recompute the same values.
+std::vector<int> sgs_passes(int ncol, int sweeps) {
+  std::vector<int> q;
+  for (int k = 0; k < sweeps; ++k) {
+    for (int c = 0; c < ncol; ++c)
+      if (q.empty() || q.back() != c) q.push_back(c);
+    for (int c = ncol - 1; c >= 0; --c)
+      if (q.empty() || q.back() != c) q.push_back(c);
+  }
+  return q;
+}
+
+// Algorithmic bytes of a pass from x = 0 over slices [s0, s1): diagonal, and
+// R x (b read, x written) per row.
+double pass0_bytes(const Level& L, int s0, int s1, int R, double vb) {
+  const double rows = (double)(L.srow_h[s1] - L.srow_h[s0]);
+  return rows * (vb + 2.0 * R * vb) + (s1 - s0) * 8.0;
+}
+
+// `sweeps` smoothing steps on level l; from_zero: the iterate is zero before.
+void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, int sweeps, bool from_zero) {
   const double vb = B.fp32 ? 4 : 8;
   if (B.smoother == AMG_SMOOTHER_MCSGS) {
-    int maxcol = 0;
-    for (int e : E) maxcol = std::max(maxcol, hier(B, e).lev[l].ncol);
-    for (int dir = 0; dir < 2; ++dir)
-      for (int q = 0; q < maxcol; ++q) {
-        b.begin(OP_GS, l, kind_at(l, AMG_KIND_SWEEP));
-        for (int e : E) {
-          const Level& L = hier(B, e).lev[l];
-          if (q >= L.ncol) continue;
-          const int c = dir == 0 ? q : L.ncol - 1 - q;
+    std::vector<std::vector<int>> seq(E.size());
+    size_t len = 0;
+    for (size_t i = 0; i < E.size(); ++i) {
+      seq[i] = sgs_passes(hier(B, E[i]).lev[l].ncol, sweeps);
+      len = std::max(len, seq[i].size());
+    }
+    for (size_t j = 0; j < len; ++j) {
+      const bool zero = from_zero && j == 0;
+      b.begin(zero ? OP_GS0 : OP_GS, l, kind_at(l, zero ? AMG_KIND_OTHER : AMG_KIND_SWEEP));
+      for (size_t i = 0; i < E.size(); ++i) {
+        if (j >= seq[i].size()) continue;
+        const int e = E[i];
+        const Level& L = hier(B, e).lev[l];
+        const int c = seq[i][j];
+        if (!zero) {
           add_slices(b, B, e, l, L.sptr[c], L.sptr[c + 1]);
+          continue;
         }
-        b.end();
+        const int s0 = L.sptr[c], s1 = L.sptr[c + 1];
+        if (s0 >= s1) continue;
+        const int d = B.desc_index(e, l);
+        b.segment(d, s0, s1, SLICES_PB);
+        for (int lo = s0; lo < s1; lo += SLICES_PB) {
+          const int hi = std::min(s1, lo + SLICES_PB);
+          b.add(d, lo, hi, 0, pass0_bytes(L, lo, hi, B.R, vb));
+        }
       }
+      b.end();
+    }
   } else {
-    b.begin(OP_RESID, l, kind_at(l, AMG_KIND_SWEEP));
-    for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
-    b.end();
-    b.begin(OP_JACOBI, l, kind_at(l, AMG_KIND_SWEEP));
-    for (int e : E) b.pieces(B.desc_index(e, l), hier(B, e).lev[l].n, ROW_CH, vb + 3.0 * B.R * vb);
-    b.end();
+    for (int k = 0; k < sweeps; ++k) {
+      b.begin(OP_RESID, l, kind_at(l, AMG_KIND_SWEEP));
+      for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
+      b.end();
+      b.begin(OP_JACOBI, l, kind_at(l, AMG_KIND_SWEEP));
+      for (int e : E) b.pieces(B.desc_index(e, l), hier(B, e).lev[l].n, ROW_CH, vb + 3.0 * B.R * vb);
+      b.end();
+    }
   }
 }
 
@@ -525,7 +566,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
     b.begin(OP_ZERO, l, l == 0 ? AMG_KIND_OTHER : AMG_KIND_COARSE_LEVELS);
     for (int e : E) b.pieces(B.desc_index(e, l), hier(B, e).lev[l].n, ROW_CH, R * vb);
     b.end();
-    for (int k = 0; k < B.pre; ++k) build_smooth(b, B, E, l);
+    build_smooth(b, B, E, l, B.pre, true);
     b.begin(OP_RESID, l, kind_at(l, AMG_KIND_RESTRICT));
     for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
     b.end();
@@ -556,7 +597,11 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
     for (int l = lt; l < lc; ++l) {
       const Level& L = H.lev[l];
       const double pass = pass_bytes(L, 0, L.nsl, R, vb);
-      bytes += (2.0 * (B.pre + B.post) + 1.0) * pass + L.n * (8.0 + 4.0 * R * vb);
+      const double sweeps = B.smoother == AMG_SMOOTHER_MCSGS
+                                ? (double)(sgs_passes(L.ncol, B.pre).size() + sgs_passes(L.ncol, B.post).size()) /
+                                      std::max(1, L.ncol)
+                                : 2.0 * (B.pre + B.post);
+      bytes += (sweeps + 1.0) * pass + L.n * (8.0 + 4.0 * R * vb);
     }
     const int d = B.desc_index(e, lt);
     b.segment(d, lt, lc, 0);
@@ -572,7 +617,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
       b.pieces(B.desc_index(e, l), L.n, ROW_CH, per_row);
     }
     b.end();
-    for (int k = 0; k < B.post; ++k) build_smooth(b, B, E, l);
+    build_smooth(b, B, E, l, B.post, false);
   }
   if (B.fp32) {
     b.begin(OP_X2Z, 0, AMG_KIND_CG_VEC);
@@ -725,7 +770,7 @@ void run_plan(Batch& B, Plan& P, hipStream_t s, bool graph) {
 
 void read_scal(Batch& B) {
   AMG_HIP(hipMemcpyAsync(B.scal_h, B.scal_d, B.scal_count() * sizeof(double), hipMemcpyDeviceToHost, B.work));
-  AMG_HIP(hipStreamSynchronize(B.work));
+  sync_stream(B.work);
 }
 
 // ------------------------------------------------------------------ entry life cycle
@@ -920,7 +965,7 @@ void step(Batch& B) {
 }
 
 void batch_release(Batch& B) {
-  if (B.work) (void)hipStreamSynchronize(B.work);
+  if (B.work) (void)sync_stream_nothrow(B.work);
   hipStream_t s = B.work;
   B.iter.drop_graph();
   B.tmp.drop_graph();
@@ -934,7 +979,7 @@ void batch_release(Batch& B) {
   B.desc_d = nullptr;
   B.scal_d = nullptr;
   B.ctl_d = nullptr;
-  if (s) (void)hipStreamSynchronize(s);
+  if (s) (void)sync_stream_nothrow(s);
   pinned_give(B.desc_h, (size_t)B.cap * MAX_LEVELS * sizeof(BDesc));
   B.desc_h = nullptr;
   pinned_give(B.scal_h, B.scal_count() * sizeof(double));
@@ -1004,7 +1049,7 @@ void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us) {
     B.iter.rows = H.lev[0].n;
     B.dirty = false;
   }
-  AMG_HIP(hipStreamSynchronize(s));  // descriptors and tables are written on the work stream
+  sync_stream(s);  // descriptors and tables are written on the work stream
   flush(B, us);
   const Level& L0 = H.lev[0];
   const Entry& E = B.ent[0];

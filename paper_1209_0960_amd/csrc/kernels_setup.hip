@@ -47,25 +47,56 @@ __device__ inline int wave_incl_scan(int v) {
   return v;
 }
 
+// Wave reductions with DPP: two quad permutations and two row rotations give
+// every lane its 16-lane row's result, then the four rows are combined from
+// lanes 15, 31, 47 and 63.  Called with all 64 lanes active; the result is
+// wave-uniform.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <typename Op>
+__device__ __forceinline__ unsigned wave_reduce(unsigned v, Op op) {
+  v = op(v, dpp_u32<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = op(v, dpp_u32<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = op(v, dpp_u32<0x124>(v));  // row_ror:4
+  v = op(v, dpp_u32<0x128>(v));  // row_ror:8
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 15), b = (unsigned)__builtin_amdgcn_readlane((int)v, 31);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 47), d = (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+  return op(op(a, b), op(c, d));
+}
 __device__ inline int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
+  return (int)wave_reduce((unsigned)v, [](unsigned x, unsigned y) { return x + y; });
 }
 __device__ inline int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
-  return v;
+  return (int)wave_reduce((unsigned)v, [](unsigned x, unsigned y) { return (unsigned)max((int)x, (int)y); });
 }
 __device__ inline int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
-  return v;
+  return (int)wave_reduce((unsigned)v, [](unsigned x, unsigned y) { return (unsigned)min((int)x, (int)y); });
 }
 __device__ inline unsigned wave_or(unsigned v) {
+  return wave_reduce(v, [](unsigned x, unsigned y) { return x | y; });
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v) {
+  const unsigned lo = dpp_u32<CTRL>((unsigned)v), hi = dpp_u32<CTRL>((unsigned)(v >> 32));
+  const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+  return o > v ? o : v;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+  v = dpp_max_u64<0xB1>(v);
+  v = dpp_max_u64<0x4E>(v);
+  v = dpp_max_u64<0x124>(v);
+  v = dpp_max_u64<0x128>(v);
+  unsigned long long r = 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= (unsigned)__shfl_xor((int)v, o, WAVE);
-  return v;
+  for (int l = 15; l < WAVE; l += 16) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    const unsigned long long x = ((unsigned long long)hi << 32) | lo;
+    r = x > r ? x : r;
+  }
+  return r;
 }
 
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -285,7 +316,7 @@ __device__ inline int st_agg(unsigned w) { return (int)(short)(w & ST_AGG); }
 __device__ inline int st_slot(unsigned w) { return (int)((w >> ST_SLOT_SHIFT) & 63u); }
 
 struct AggLayout {
-  size_t lptr, st, cmm, key1, adjb, madj, nna, front, adjl, mem, ladj, total;
+  size_t lptr, st, cmm, niso, adjb, madj, nna, front, adjl, mem, ladj, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -296,7 +327,7 @@ __host__ __device__ inline AggLayout agg_layout(int T, int E) {
   L.lptr = o; o = align16(o + 4 * (size_t)(T + 1));
   L.st = o; o = align16(o + 4 * (size_t)T);
   L.cmm = o; o = align16(o + 4 * (size_t)T);
-  L.key1 = o; o = align16(o + 2 * (size_t)T);
+  L.niso = o; o = align16(o + 2 * (size_t)T);
   L.adjb = o; o = align16(o + 4 * (size_t)((T + 31) / 32));
   L.madj = o; o = align16(o + 4 * (size_t)AGG_MAX_SLOTS);
   L.nna = o; o = align16(o + 2 * (size_t)T);
@@ -312,7 +343,7 @@ struct AggSh {
   int* lptr;
   unsigned* st;
   unsigned* cmm;     // front vertex: mask of the member slots it is adjacent to
-  short* key1;       // grow score per front position
+  short* niso;       // isolated in-tile neighbours per vertex
   unsigned* adjbits; // bit a: aggregate a is adjacent to the current aggregate
   unsigned* madj;
   short* nna;
@@ -425,48 +456,46 @@ __device__ inline bool ecc_ok(const AggSh& S, unsigned mm, int asize, int dmax) 
   return reach == full;
 }
 
-// First scoring pass of candidate c: cons2 (strong links into a), the member
-// mask, and |N(c) n U|.  The strong flags are symmetric: s_ij and s_ji are the
-// same products (w_ij w_ji and a_ii a_jj commute) compared with the same
-// delta*min(eta_i, eta_j), so every strong link is two-way, cons2 counts them
-// and cons1 is zero.
-struct ScoreA {
-  int c2, in_U;
-  unsigned mm;
-};
-__device__ inline ScoreA score_a(const AggSh& S, int c, int id) {
-  ScoreA r{0, 0, 0u};
-  const int b = S.lptr[c], e = S.lptr[c + 1];
-#pragma unroll 2
-  for (int k = b; k < e; ++k) {
-    const unsigned w = S.ladj[k];
-    const unsigned wj = S.st[w & 0x7FFF];
-    const int aj = st_agg(wj);
-    if (aj == id) {
-      r.mm |= 1u << st_slot(wj);
-      r.c2 += (int)(w >> 15);
-    } else if (aj < 0 && !(wj & ST_ISO)) {
-      ++r.in_U;
-    }
-  }
-  return r;
-}
-
-// Tie-break pass: connect(c,a) (strong neighbours outside a, weight 2 when in
-// an aggregate adjacent to a) and neighbors(c,a) = |(N(c) n U) \ N(a)|.
+// Scores of a candidate c from state kept up to date by add_member.  The
+// strong flags are symmetric: s_ij and s_ji are the same products (w_ij w_ji
+// and a_ii a_jj commute) compared with the same delta*min(eta_i, eta_j), so
+// every strong link is two-way: cons2 (strong links into a) is the count in
+// c's status word and cons1 is zero.  The sparsity pattern is symmetric
+// (checked at setup), so the member mask of c is cmm[c], and in phase 1
+// |N(c) n U| is the unaggregated neighbour count nna[c] less the isolated
+// neighbours niso[c] (isolated vertices are all unaggregated then).
+// Tie-break scores: connect(c,a) (strong neighbours outside a, weight 2 when
+// in an aggregate adjacent to a) and neighbors(c,a) = |(N(c) n U) \ N(a)|.
+// Entries are read in chunks of 8 so that their loads are in flight together.
 __device__ inline void score_b(const AggSh& S, int c, int id, int& conn, int& nb) {
   conn = 0;
   nb = 0;
   const int b = S.lptr[c], e = S.lptr[c + 1];
-#pragma unroll 2
-  for (int k = b; k < e; ++k) {
-    const unsigned w = S.ladj[k];
-    const unsigned wj = S.st[w & 0x7FFF];
-    const int aj = st_agg(wj);
-    if (aj == id) continue;
-    if (w >> 15) conn += (aj >= 0 && ((S.adjbits[aj >> 5] >> (aj & 31)) & 1u)) ? 2 : 1;
-    if (aj < 0 && !(wj & (ST_ISO | ST_FRONT))) ++nb;
+  for (int k0 = b; k0 < e; k0 += 8) {
+    unsigned w[8], wj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = k0 + q < e ? S.ladj[k0 + q] : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) wj[q] = k0 + q < e ? S.st[w[q] & 0x7FFF] : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (k0 + q >= e) break;
+      const int aj = st_agg(wj[q]);
+      if (aj == id) continue;
+      if (w[q] >> 15) conn += (aj >= 0 && ((S.adjbits[aj >> 5] >> (aj & 31)) & 1u)) ? 2 : 1;
+      if (aj < 0 && !(wj[q] & (ST_ISO | ST_FRONT))) ++nb;
+    }
   }
+}
+
+// Grow key of an admissible candidate: the lexicographic order (cons2,
+// connect/|N|, neighbors, -index) as one unsigned integer.  |N| <= T-1 < 2^10
+// and connect <= 2|N|, so floor(connect * 2^20 / |N|) orders the ratios
+// exactly (two distinct ratios differ by at least 2^-20) and fits 22 bits.
+__device__ inline unsigned long long grow_key(int c2, int conn, int deg, int nb, int c) {
+  const unsigned r = ((unsigned)conn << 20) / (unsigned)deg;
+  return ((unsigned long long)c2 << 58) | ((unsigned long long)r << 22) | ((unsigned long long)nb << 11) |
+         (unsigned long long)(2047 - c);
 }
 
 // Strict total order of grow candidates with equal cons2: larger
@@ -492,7 +521,7 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   S.lptr = (int*)(sm + Lo.lptr);
   S.st = (unsigned*)(sm + Lo.st);
   S.cmm = (unsigned*)(sm + Lo.cmm);
-  S.key1 = (short*)(sm + Lo.key1);
+  S.niso = (short*)(sm + Lo.niso);
   S.adjbits = (unsigned*)(sm + Lo.adjb);
   S.madj = (unsigned*)(sm + Lo.madj);
   S.nna = (short*)(sm + Lo.nna);
@@ -538,6 +567,12 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   if (lane < AGG_MAX_SLOTS) S.madj[lane] = 0;
   int nU = wave_sum(nonIso);
   __syncthreads();
+  for (int v = lane; v < nt; v += WAVE) {
+    int c = 0;
+    for (int k = S.lptr[v]; k < S.lptr[v + 1]; ++k) c += (S.st[S.ladj[k] & 0x7FFF] & ST_ISO) ? 1 : 0;
+    S.niso[v] = (short)c;
+  }
+  __syncthreads();
 
   AggState as{0, 0, 0};
   int id = 0;
@@ -553,70 +588,42 @@ __global__ __launch_bounds__(WAVE) void k_aggregate(int n, int T, const int* __r
   while (nU > 0) {
     add_member(S, as, seed, id, false, 0);
     --nU;
-    // Grow (Alg. 2)
+    // Grow (Alg. 2): among the unaggregated front candidates with cons2 > 0
+    // whose addition keeps the diameter within dmax, the one with the largest
+    // cons2, ties broken by connect/|N|, then neighbors, then the smaller
+    // index: the maximum grow key.
     while (as.asize < smin) {
-      int lm2 = 0;
+      unsigned long long key = 0;
       for (int base = 0; base < as.fcount; base += WAVE) {
         const int p = base + lane;
         if (p < as.fcount) {
           const int c = S.front[p];
-          int k1 = -1;
           const unsigned wc = S.st[c];
-          if (st_agg(wc) < 0) {
-            const int c2 = (int)((wc & ST_C2_MASK) >> ST_C2_SHIFT);
-            const int ok = (c2 > 0 && ecc_ok(S, S.cmm[c], as.asize, dmax)) ? 1 : 0;
-            k1 = ok ? c2 : 0;
-            if (ok) lm2 = max(lm2, c2);
-          }
-          S.key1[p] = (short)k1;
-        }
-      }
-      const int m2 = wave_max(lm2);
-      if (m2 == 0) break;
-      __syncthreads();
-      int bc = -1, bconn = 0, bdeg = 1, bnb = 0;
-      for (int base = 0; base < as.fcount; base += WAVE) {
-        const int p = base + lane;
-        if (p < as.fcount && S.key1[p] == m2) {
-          const int c = S.front[p];
-          int conn, nb;
-          score_b(S, c, id, conn, nb);
-          const int deg = S.lptr[c + 1] - S.lptr[c];
-          if (better(c, conn, deg, nb, bc, bconn, bdeg, bnb)) {
-            bc = c;
-            bconn = conn;
-            bdeg = deg;
-            bnb = nb;
+          const int c2 = (int)((wc & ST_C2_MASK) >> ST_C2_SHIFT);
+          if (st_agg(wc) < 0 && c2 > 0 && ecc_ok(S, S.cmm[c], as.asize, dmax)) {
+            int conn, nb;
+            score_b(S, c, id, conn, nb);
+            const unsigned long long k = grow_key(c2, conn, S.lptr[c + 1] - S.lptr[c], nb, c);
+            key = k > key ? k : key;
           }
         }
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const int oc = __shfl_xor(bc, o, WAVE), oconn = __shfl_xor(bconn, o, WAVE);
-        const int odeg = __shfl_xor(bdeg, o, WAVE), onb = __shfl_xor(bnb, o, WAVE);
-        if (better(oc, oconn, odeg, onb, bc, bconn, bdeg, bnb)) {
-          bc = oc;
-          bconn = oconn;
-          bdeg = odeg;
-          bnb = onb;
-        }
-      }
-      __syncthreads();
-      if (bc < 0) break;
-      add_member(S, as, bc, id, false, 0);
+      key = wave_max_u64(key);
+      if (key == 0) break;
+      add_member(S, as, 2047 - (int)(key & 2047), id, false, 0);
       --nU;
     }
-    // Round (Alg. 3)
+    // Round (Alg. 3): the smallest candidate with cons2 > 0 adjacent to more
+    // members than unaggregated non-isolated vertices.
     while (as.asize < smax) {
       int best = INT_MAX;
       for (int base = 0; base < as.fcount; base += WAVE) {
         const int p = base + lane;
         if (p < as.fcount) {
           const int c = S.front[p];
-          if (st_agg(S.st[c]) < 0) {
-            const ScoreA r = score_a(S, c, id);
-            if (r.c2 > 0 && __popc(r.mm) > r.in_U) best = min(best, c);
-          }
+          const unsigned wc = S.st[c];
+          if (st_agg(wc) < 0 && (wc & ST_C2_MASK) != 0 && __popc(S.cmm[c]) > S.nna[c] - S.niso[c])
+            best = min(best, c);
         }
       }
       best = wave_min(best);
@@ -1523,7 +1530,7 @@ template <typename T>
 T read1(const T* dptr, hipStream_t s) {
   T v;
   AMG_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  sync_stream(s);
   return v;
 }
 
@@ -1695,7 +1702,7 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   AMG_HIP(hipGetLastError());
   L.cptr.assign(C + 1, 0);
   AMG_HIP(hipMemcpyAsync(L.cptr.data(), cp.p, (C + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  sync_stream(s);
 }
 
 void cast_f32(const double* in, float* out, size_t n, hipStream_t s) {
@@ -1784,7 +1791,7 @@ void permute_level(Hierarchy& H, int l, const int* next_perm, hipStream_t s) {
   hipLaunchKernelGGL(k_perm_members, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, nullptr, L.mptr, L.members,
                      pinv.as<int>(), L.mptr, pmem);
   AMG_HIP(hipGetLastError());
-  AMG_HIP(hipStreamSynchronize(s));
+  sync_stream(s);
   for (void* p : {(void*)L.rowptr, (void*)L.colind, (void*)L.vals, (void*)L.agg, (void*)L.members,
                   (void*)L.tile_off, (void*)L.colour})
     H.free_one(p, s);
@@ -1820,7 +1827,7 @@ void build_sell(Hierarchy& H, int l, hipStream_t s) {
   L.srow_h = srow_h;
   L.soff_h.assign(L.nsl + 1, 0);
   AMG_HIP(hipMemcpyAsync(L.soff_h.data(), L.soff, ((size_t)L.nsl + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  sync_stream(s);
   const int tot = L.soff_h[L.nsl];
   if (tot < 0) fail(AMG_ERR_UNSUPPORTED, "padded matrix exceeds 2^31 entries");
   L.scol = H.alloc<int>((size_t)tot, s);
@@ -1829,7 +1836,7 @@ void build_sell(Hierarchy& H, int l, hipStream_t s) {
   hipLaunchKernelGGL(k_sell_fill, dim3(cdiv(L.nsl, 4)), dim3(256), 0, s, L.nsl, L.srow, L.soff, L.rowptr, L.colind,
                      L.vals, L.scol, L.sval, L.dg);
   AMG_HIP(hipGetLastError());
-  AMG_HIP(hipStreamSynchronize(s));
+  sync_stream(s);
   H.free_one(L.colind, s);
   H.free_one(L.vals, s);
   L.colind = nullptr;

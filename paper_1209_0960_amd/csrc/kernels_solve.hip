@@ -210,6 +210,28 @@ __global__ __launch_bounds__(NT) void kb_gs(AMG_KARGS) {
   AMG_BODY((kb_gs_body<V, R>))
 }
 
+// The first Gauss-Seidel pass from x = 0: every off-diagonal product is a
+// zero, the sum stays +0 and the update is b_i / a_ii, so the pass reads no
+// matrix entries and gives the same values bit for bit.
+template <typename V, int R>
+__device__ __forceinline__ void kb_gs0_body(const Item& it, const BDesc& d) {
+  const int sl = it.lo + (int)(threadIdx.x / WAVE);
+  if (sl >= it.hi) return;
+  const int r = d.srow[sl] + __lane_id();
+  if (r < d.srow[sl + 1]) {
+    V bb[R], o[R];
+    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+    const V dg = Mat<V>::dg(d)[r];
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = bb[k] / dg;
+    stv<V, R>(static_cast<V*>(d.x) + (size_t)r * R, o);
+  }
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_gs0(AMG_KARGS) {
+  AMG_BODY((kb_gs0_body<V, R>))
+}
+
 // t = b - A x on the slices [lo, hi).
 template <typename V, int R>
 __device__ __forceinline__ void kb_resid_body(const Item& it, const BDesc& d) {
@@ -369,11 +391,14 @@ __device__ inline void tail_slices(const BDesc& d, int s0, int s1, bool gs) {
 
 template <typename V, int R>
 __device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps) {
+  int prev = -1;  // a pass on the colour just updated would repeat its values
   for (int k = 0; k < sweeps; ++k) {
     if (smoother == AMG_SMOOTHER_MCSGS) {
       for (int dir = 0; dir < 2; ++dir)
         for (int q = 0; q < d.ncol; ++q) {
           const int c = dir == 0 ? q : d.ncol - 1 - q;
+          if (c == prev) continue;
+          prev = c;
           tail_slices<V, R>(d, d.sptr[c], d.sptr[c + 1], true);
         }
     } else {
@@ -855,6 +880,7 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
   switch (L.op) {
     case OP_ZERO: AMG_LAUNCH(kb_zero, (V, R)); break;
     case OP_GS: AMG_LAUNCH(kb_gs, (V, R)); break;
+    case OP_GS0: AMG_LAUNCH(kb_gs0, (V, R)); break;
     case OP_RESID: AMG_LAUNCH(kb_resid, (V, R)); break;
     case OP_JACOBI: AMG_LAUNCH(kb_jacobi, (V, R)); break;
     case OP_RESTRICT: AMG_LAUNCH(kb_restrict, (V, R)); break;
@@ -878,6 +904,7 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
   switch (L.op) {
     case OP_ZERO:
     case OP_GS:
+    case OP_GS0:
     case OP_RESID:
     case OP_JACOBI:
     case OP_RESTRICT:
