@@ -74,7 +74,7 @@ typedef struct amg_params {
   double omega;              /* over-correction of the coarse correction       [1.6]  */
   int32_t coarse_max;        /* stop coarsening at <= this many rows           [500]  */
   int32_t max_levels;        /*                                                [25]   */
-  int32_t tile_rows;         /* rows per decoupled aggregation tile (64..1024) [512]  */
+  int32_t tile_rows;         /* rows per decoupled aggregation tile (64..1024) [128]  */
   int32_t smoother;          /* AMG_SMOOTHER_MCSGS or AMG_SMOOTHER_L1_JACOBI   [MCSGS]*/
   int32_t pre_sweeps;        /* symmetric GS steps (fwd+bwd) or Jacobi sweeps  [1]    */
   int32_t post_sweeps;       /*                                                [1]    */

@@ -37,7 +37,7 @@ class Params(C.Structure):
 
 def default_params(**kw) -> Params:
     p = Params(strength_threshold=0.08, isolated_threshold=1e-5, agg_min=8, agg_max=12,
-               agg_diameter=3, omega=1.6, coarse_max=500, max_levels=25, tile_rows=512,
+               agg_diameter=3, omega=1.6, coarse_max=500, max_levels=25, tile_rows=128,
                smoother=0, pre_sweeps=1, post_sweeps=1, vcycle_fp32=0, flexible=-1,
                colour_seed=0, check_symmetry=1, colour_tile_rows=128)
     for k, v in kw.items():
@@ -108,7 +108,7 @@ def validate(rowptr, colind, vals, check_symmetry=True) -> int:
     return lib().orc_validate(rp.shape[0] - 1, ci.shape[0], rp, ci, v, int(check_symmetry))
 
 
-def strength(rowptr, colind, vals, tile_rows=512, delta=0.08, beta=1e-5):
+def strength(rowptr, colind, vals, tile_rows=128, delta=0.08, beta=1e-5):
     """Strong flag per stored entry and isolated flag per row (Sec. 2.1)."""
     rp, ci, v = _csr(rowptr, colind, vals)
     n, nnz = rp.shape[0] - 1, ci.shape[0]
@@ -118,7 +118,7 @@ def strength(rowptr, colind, vals, tile_rows=512, delta=0.08, beta=1e-5):
     return strong, iso
 
 
-def aggregate(rowptr, colind, strong, iso, tile_rows=512, smin=8, smax=12, dmax=3):
+def aggregate(rowptr, colind, strong, iso, tile_rows=128, smin=8, smax=12, dmax=3):
     """Global aggregate id per row, number of aggregates, per-tile counts (Alg. 1-4)."""
     rp, ci, _ = _csr(rowptr, colind)
     n, nnz = rp.shape[0] - 1, ci.shape[0]
@@ -129,7 +129,7 @@ def aggregate(rowptr, colind, strong, iso, tile_rows=512, smin=8, smax=12, dmax=
     return agg, nc, tc
 
 
-def aggregate_tiles(rowptr, colind, strong, iso, tiles, tile_rows=512, smin=8, smax=12, dmax=3):
+def aggregate_tiles(rowptr, colind, strong, iso, tiles, tile_rows=128, smin=8, smax=12, dmax=3):
     """Tile-local aggregate ids for the rows of the given tiles (others -1) and their counts."""
     rp, ci, _ = _csr(rowptr, colind)
     n, nnz = rp.shape[0] - 1, ci.shape[0]
@@ -156,7 +156,7 @@ def galerkin(rowptr, colind, vals, agg, nc):
     return cptr, ccol, cval
 
 
-def colour(rowptr, colind, seed=0, tile_rows=512):
+def colour(rowptr, colind, seed=0, tile_rows=128):
     """Tile-ordered greedy colouring: colour per row and number of colours."""
     rp, ci, _ = _csr(rowptr, colind)
     n = rp.shape[0] - 1

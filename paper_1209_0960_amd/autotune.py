@@ -26,7 +26,7 @@ import torch
 
 from . import amg as A
 
-TILES = (256, 512, 1024)
+TILES = (64, 128, 256, 512)
 TAILS = (0, 8192)
 RHS = (4, 2, 1)
 

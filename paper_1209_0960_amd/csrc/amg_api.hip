@@ -429,7 +429,7 @@ amg_status amg_default_params(amg_params* p) {
   p->omega = 1.6;
   p->coarse_max = 500;
   p->max_levels = 25;
-  p->tile_rows = 512;
+  p->tile_rows = 128;
   p->smoother = AMG_SMOOTHER_MCSGS;
   p->pre_sweeps = 1;
   p->post_sweeps = 1;

@@ -264,7 +264,7 @@ enum {
   OP_RESTRICT,   // b_c = P^T t (coarse rows)
   OP_PROLONG,    // x += omega P x_c (rows)
   OP_COARSE,     // x = A_L^{-1} b (rows of the coarsest level, 4 per block)
-  OP_TAIL,       // V-cycle of levels lt..L of one entry in one workgroup (coarsest: x = A_L^{-1} b)
+  OP_TAIL,       // down-leg of levels lt..L-1 of one entry in one workgroup (zero, pre-smooth, restrict)
   OP_R2B,        // FP32 cycle: b_0 = (float) r
   OP_X2Z,        // FP32 cycle: z = (double) x_0
   OP_DOTS_RZ,    // partials of r.z and z.(r - r_old)
@@ -278,6 +278,7 @@ enum {
   OP_VZERO_ROLD, // r_old = 0 (rows)
   OP_FINISH,     // per entry: reduce partials, scalar update (aux = FIN_*, aux2 = slot)
   OP_GS0,        // first Gauss-Seidel pass from x = 0: x = b / diag on the slices of one colour
+  OP_TAIL_UP,    // up-leg of levels L-1..lt of one entry in one workgroup (prolong, post-smooth)
 };
 enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
 

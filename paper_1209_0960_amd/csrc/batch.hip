@@ -211,6 +211,7 @@ struct Batch {
   std::vector<int> pending;  // slots awaiting their prologue
   std::vector<Result> results;
   Plan iter, tmp;
+  Plan papply;  // the preconditioner alone (amg_precond_apply)
   bool dirty = true;
 
   size_t scal_count() const { return (size_t)cap * R * S_COUNT; }
@@ -546,13 +547,15 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
 }
 
 // z = M r for every entry of S (Sec. 2: V-cycle), level by level over the
-// entries that have the level; all coarsest solves in one launch.
-void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
+// entries that have the level; all coarsest solves in one launch.  convert:
+// FP32 cycle with r -> b_0 and x_0 -> z conversions of its own (the CG
+// iteration writes b_0 where r is produced and reads x_0 as z).
+void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool convert) {
   const double vb = B.fp32 ? 4 : 8;
   const int R = B.R;
   int maxLc = 0;  // deepest level cycled by separate launches
   for (int e : S) maxLc = std::max(maxLc, tail_start(B, e));
-  if (B.fp32) {
+  if (B.fp32 && convert) {
     b.begin(OP_R2B, 0, AMG_KIND_CG_VEC);
     for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 12.0 * R);
     b.end();
@@ -579,35 +582,40 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
     }
     b.end();
   }
-  // Entries whose tail is the coarsest level alone: the dense solve spread
-  // over many workgroups; the others: one workgroup per entry.
+  // Levels from tail_start down: one workgroup per entry (down-leg, then
+  // up-leg); the coarsest solves of all entries in between, spread over many
+  // workgroups.
+  auto tail_leg = [&](int op, bool up) {
+    b.begin(op, maxLc, AMG_KIND_COARSE_LEVELS, B.smoother, (B.pre << 8) | B.post);
+    for (int e : S) {
+      const Hierarchy& H = hier(B, e);
+      const int lt = tail_start(B, e), lc = coarsest(B, e);
+      if (lt == lc) continue;
+      double bytes = 0.0;
+      for (int l = lt; l < lc; ++l) {
+        const Level& L = H.lev[l];
+        const double pass = pass_bytes(L, 0, L.nsl, R, vb);
+        const int k = up ? B.post : B.pre;
+        const double sweeps = B.smoother == AMG_SMOOTHER_MCSGS
+                                  ? (double)sgs_passes(L.ncol, k).size() / std::max(1, L.ncol)
+                                  : 2.0 * k;
+        bytes += up ? sweeps * pass + L.n * (4.0 + 2.0 * R * vb)
+                    : (sweeps + 1.0) * pass + L.n * (4.0 + 2.0 * R * vb);
+      }
+      const int d = B.desc_index(e, lt);
+      b.segment(d, lt, lc, 0);
+      b.add(d, lt, lc, 0, bytes);
+    }
+    b.end();
+  };
+  tail_leg(OP_TAIL, false);
   b.begin(OP_COARSE, maxLc, AMG_KIND_COARSE_LEVELS);
   for (int e : S) {
     const Hierarchy& H = hier(B, e);
-    if (tail_start(B, e) == coarsest(B, e))
-      b.pieces(B.desc_index(e, coarsest(B, e)), H.nL, 4, 8.0 * H.nL + 2.0 * R * vb);
+    b.pieces(B.desc_index(e, coarsest(B, e)), H.nL, 4, 8.0 * H.nL + 2.0 * R * vb);
   }
   b.end();
-  b.begin(OP_TAIL, maxLc, AMG_KIND_COARSE_LEVELS, B.smoother, (B.pre << 8) | B.post);
-  for (int e : S) {
-    const Hierarchy& H = hier(B, e);
-    const int lt = tail_start(B, e), lc = coarsest(B, e);
-    if (lt == lc) continue;
-    double bytes = 8.0 * H.nL * H.nL + 2.0 * R * vb * H.nL;
-    for (int l = lt; l < lc; ++l) {
-      const Level& L = H.lev[l];
-      const double pass = pass_bytes(L, 0, L.nsl, R, vb);
-      const double sweeps = B.smoother == AMG_SMOOTHER_MCSGS
-                                ? (double)(sgs_passes(L.ncol, B.pre).size() + sgs_passes(L.ncol, B.post).size()) /
-                                      std::max(1, L.ncol)
-                                : 2.0 * (B.pre + B.post);
-      bytes += (sweeps + 1.0) * pass + L.n * (8.0 + 4.0 * R * vb);
-    }
-    const int d = B.desc_index(e, lt);
-    b.segment(d, lt, lc, 0);
-    b.add(d, lt, lc, 0, bytes);
-  }
-  b.end();
+  tail_leg(OP_TAIL_UP, true);
   for (int l = maxLc - 1; l >= 0; --l) {
     const std::vector<int>& E = below[l];
     b.begin(OP_PROLONG, l, kind_at(l, AMG_KIND_PROLONG));
@@ -619,7 +627,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S) {
     b.end();
     build_smooth(b, B, E, l, B.post, false);
   }
-  if (B.fp32) {
+  if (B.fp32 && convert) {
     b.begin(OP_X2Z, 0, AMG_KIND_CG_VEC);
     for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 12.0 * R);
     b.end();
@@ -663,18 +671,19 @@ void build_finish(Builder& b, const Batch& B, const std::vector<int>& S, const s
 // One CG iteration (Sec. 2): z = M r, beta, p, q = A p, alpha, x and r, ||r||^2.
 void build_iter(Builder& b, const Batch& B, const std::vector<int>& S, size_t* precond_end) {
   const int R = B.R;
-  build_precond(b, B, S);
+  const double zb = B.fp32 ? 4.0 : 8.0;  // bytes per value of z (read as the FP32 x_0)
+  build_precond(b, B, S, false);
   *precond_end = b.L.size();
   std::vector<int> nr(S.size());
-  b.begin(OP_DOTS_RZ, 0, AMG_KIND_CG_VEC);
+  b.begin(OP_DOTS_RZ, 0, AMG_KIND_CG_VEC, B.fp32);
   for (size_t i = 0; i < S.size(); ++i) {
     const int n = hier(B, S[i]).lev[0].n;
-    nr[i] = b.chunks(B.desc_index(S[i], 0), n, red_blocks_rows(n), (B.flexible ? 24.0 : 16.0) * R);
+    nr[i] = b.chunks(B.desc_index(S[i], 0), n, red_blocks_rows(n), (zb + (B.flexible ? 16.0 : 8.0)) * R);
   }
   b.end();
   build_finish(b, B, S, nr, B.flexible ? FIN_BETA_FCG : FIN_BETA_PCG);
-  b.begin(OP_UPDATE_P, 0, AMG_KIND_CG_VEC);
-  for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 24.0 * R);
+  b.begin(OP_UPDATE_P, 0, AMG_KIND_CG_VEC, B.fp32);
+  for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, (zb + 16.0) * R);
   b.end();
   std::vector<int> ns(S.size());
   b.begin(OP_SPMV_DOT, 0, AMG_KIND_SPMV_F64);
@@ -698,10 +707,11 @@ void build_iter(Builder& b, const Batch& B, const std::vector<int>& S, size_t* p
     b.end();
   }
   build_finish(b, B, S, ns, FIN_ALPHA);
-  b.begin(OP_UPDATE_XR, 0, AMG_KIND_CG_VEC);
+  b.begin(OP_UPDATE_XR, 0, AMG_KIND_CG_VEC, B.fp32);
   for (size_t i = 0; i < S.size(); ++i) {
     const int n = hier(B, S[i]).lev[0].n;
-    nr[i] = b.chunks(B.desc_index(S[i], 0), n, red_blocks_rows(n), (B.flexible ? 56.0 : 48.0) * R);
+    nr[i] = b.chunks(B.desc_index(S[i], 0), n, red_blocks_rows(n),
+                     ((B.flexible ? 56.0 : 48.0) + (B.fp32 ? 4.0 : 0.0)) * R);
   }
   b.end();
   build_finish(b, B, S, nr, FIN_STORE, S_RR);
@@ -714,7 +724,8 @@ void build_prologue(Builder& b, const Batch& B, const std::vector<int>& S) {
     for (int e : S) b.pieces(B.desc_index(e, 0), hier(B, e).lev[0].n, ROW_CH, 8.0 * B.R);
     b.end();
   }
-  const std::vector<int> np = build_resid_dot(b, B, S, 0, AMG_KIND_CG_VEC);
+  // r = b - A x, and in the FP32 cycle also its right-hand side (float) r
+  const std::vector<int> np = build_resid_dot(b, B, S, B.fp32 ? 2 : 0, AMG_KIND_CG_VEC);
   build_finish(b, B, S, np, FIN_INIT);
 }
 
@@ -972,6 +983,8 @@ void batch_release(Batch& B) {
   for (auto& E : B.ent) E.ctx.release(s);
   if (B.iter.tab_d) dfree(B.iter.tab_d, s);
   if (B.tmp.tab_d) dfree(B.tmp.tab_d, s);
+  if (B.papply.tab_d) dfree(B.papply.tab_d, s);
+  B.papply.tab_d = nullptr;
   if (B.desc_d) dfree(B.desc_d, s);
   if (B.scal_d) dfree(B.scal_d, s);
   if (B.ctl_d) dfree(B.ctl_d, s);
@@ -1039,22 +1052,17 @@ amg_status pcg_run(Hierarchy& H, const double* b, double* x, double rtol, int ma
 void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us) {
   Batch& B = single_of(H);
   hipStream_t s = B.work;
-  if (B.dirty || B.iter.L.empty() || B.iter.slots != std::vector<int>{0}) {
+  if (B.papply.L.empty()) {
     Builder b(B, true);
-    build_iter(b, B, {0}, &B.iter.precond_end);
-    const size_t pe = B.iter.precond_end;
-    upload_plan(B.iter, b, s);
-    B.iter.precond_end = pe;
-    B.iter.slots = {0};
-    B.iter.rows = H.lev[0].n;
-    B.dirty = false;
+    build_precond(b, B, {0}, true);
+    upload_plan(B.papply, b, s);
   }
   sync_stream(s);  // descriptors and tables are written on the work stream
   flush(B, us);
   const Level& L0 = H.lev[0];
   const Entry& E = B.ent[0];
   gather_rhs(L0.n, 1, L0.perm, r, E.ctx.r, us);
-  issue_launches(B.iter.L, 0, B.iter.precond_end, B.iter.tab_d, B.desc_d, B.desc_h, 1, B.fp32, us);
+  issue_launches(B.papply.L, 0, B.papply.L.size(), B.papply.tab_d, B.desc_d, B.desc_h, 1, B.fp32, us);
   scatter_rhs(L0.n, 1, L0.perm, E.ctx.z, z, us);
 }
 

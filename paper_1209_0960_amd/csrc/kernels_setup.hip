@@ -822,15 +822,40 @@ __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr,
                              const int* __restrict__ agg, int* J, double* V, IdxT* Sx, int* __restrict__ tcol,
                              double* __restrict__ tval, int* __restrict__ ucount) {
   const int lane = __lane_id();
+  // Terms in member order, CSR order inside a member: lane q takes member q,
+  // finds its first term by a scan of the row lengths and copies its entries
+  // with their loads in flight together.
+  const int p0 = mptr[I], nm = mptr[I + 1] - p0;
   int pos = 0;
-  for (int p = mptr[I]; p < mptr[I + 1]; ++p) {
-    const int i = members[p];
-    const int b = rp[i], e = rp[i + 1];
-    for (int k = b + lane; k < e; k += WAVE) {
-      J[pos + k - b] = agg[ci[k]];
-      V[pos + k - b] = va[k];
+  for (int base = 0; base < nm; base += WAVE) {
+    const int q = base + lane;
+    int b = 0, len = 0;
+    if (q < nm) {
+      const int i = members[p0 + q];
+      b = rp[i];
+      len = rp[i + 1] - b;
     }
-    pos += e - b;
+    const int inc = wave_incl_scan(len);
+    const int off = pos + inc - len;
+    for (int k0 = 0; k0 < len; k0 += 8) {
+      int cc[8];
+      double vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        cc[u] = k0 + u < len ? ci[b + k0 + u] : 0;
+        vv[u] = k0 + u < len ? va[b + k0 + u] : 0.0;
+      }
+      int aa[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) aa[u] = k0 + u < len ? agg[cc[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < len) {
+          J[off + k0 + u] = aa[u];
+          V[off + k0 + u] = vv[u];
+        }
+    }
+    pos += __shfl(inc, WAVE - 1, WAVE);
   }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
@@ -1008,7 +1033,6 @@ __host__ __device__ inline size_t col_smem(int T, int E) {
 // Colours the tiles of `work` (all their preceding neighbour tiles are
 // finished), then releases the neighbour tiles they precede.
 __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* __restrict__ work,
-                                                       int* __restrict__ next, int* next_cnt,
                                                        const int* __restrict__ rp, const int* __restrict__ ci,
                                                        const int* __restrict__ tptr, const int* __restrict__ tadj,
                                                        int* pending, uint32_t seed, int* colour, int* maxcol) {
@@ -1074,7 +1098,7 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
       if (col[v] >= 0) continue;
       uint64_t m = mask[v];
       bool ready = true, bg = big[v] != 0;
-      for (int q = lptr[v]; q < lptr[v + 1]; ++q) {
+      for (int q = lptr[v]; q < lptr[v + 1]; ++q) {  // stops at the first uncoloured one
         const int cj = col[adj[q]];
         if (cj < 0) {
           ready = false;
@@ -1142,24 +1166,14 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
   for (int v = lane; v < nt; v += WAVE) colour[lo + v] = col[v];
   cmax = wave_max(cmax);
   if (lane == 0) atomicMax(maxcol, cmax);
-  // Released tiles are coloured by the next launch, which sees these colours.
-  for (int q0 = tptr[t]; q0 < tptr[t + 1]; q0 += WAVE) {
-    const int q = q0 + lane;
-    bool rel = false;
-    int u = 0;
-    if (q < tptr[t + 1]) {
-      u = tadj[q];
-      if (tile_before(t, u, seed)) rel = atomicSub(&pending[u], 1) == 1;
-    }
-    const uint64_t m = __ballot(rel);
-    if (m) {
-      const int leader = (int)__builtin_ctzll(m);
-      int base = 0;
-      if (lane == leader) base = atomicAdd(next_cnt, __popcll(m));
-      base = __shfl(base, leader, WAVE);
-      if (rel) next[base + __popcll(m & lanemask_lt())] = u;
-    }
+  // Tiles after this one wait for one neighbour less; k_ready0 lists those
+  // that reach zero for the next launch, which sees these colours.  This tile
+  // is marked done (-1): no tile before it is left to decrement it.
+  for (int q = tptr[t] + lane; q < tptr[t + 1]; q += WAVE) {
+    const int u = tadj[q];
+    if (tile_before(t, u, seed)) atomicSub(&pending[u], 1);
   }
+  if (lane == 0) pending[t] = -1;
 }
 
 constexpr int CL_THREADS = 256;
@@ -1645,7 +1659,7 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   if (T > COL_MAX_T) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows above 1024");
   const int ntiles = cdiv(n, T);
   L.colour = H.alloc<int>((size_t)n, s);
-  DBuf cnt(4 * sizeof(int), s), w0((size_t)ntiles * sizeof(int), s), w1((size_t)ntiles * sizeof(int), s);
+  DBuf cnt(4 * sizeof(int), s), w0((size_t)ntiles * sizeof(int), s);
   DBuf tcnt((size_t)ntiles * sizeof(int), s), pend((size_t)ntiles * sizeof(int), s),
       tptr(((size_t)ntiles + 1) * sizeof(int), s);
   hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.colour, -1);
@@ -1667,23 +1681,20 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   const size_t shm = col_smem(T, Ecap);
   if (shm > 160 * 1024) fail(AMG_ERR_UNSUPPORTED, "colouring tile exceeds LDS; use smaller tile_rows");
   AMG_HIP(hipFuncSetAttribute((const void*)k_colour_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  int* bufs[2] = {w0.as<int>(), w1.as<int>()};
-  AMG_HIP(hipMemsetAsync(cnt.as<int>() + 2, 0, 2 * sizeof(int), s));
-  hipLaunchKernelGGL(k_ready0, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, ntiles, pend.as<int>(), bufs[1],
-                     cnt.as<int>() + 3);
-  int remaining = read1(cnt.as<int>() + 3, s), rounds = 0, coloured = 0;
-  const int* work = bufs[1];
-  while (remaining > 0) {
-    int* next = bufs[rounds & 1];
-    int* next_cnt = cnt.as<int>() + 2 + (rounds & 1);
-    AMG_HIP(hipMemsetAsync(next_cnt, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_colour_tiles, dim3(remaining), dim3(WAVE), shm, s, n, T, work, next, next_cnt, L.rowptr,
-                       L.colind, tptr.as<int>(), tadj.as<int>(), pend.as<int>(), seed, L.colour, cnt.as<int>() + 1);
+  // Rounds: colour the listed tiles, then list the tiles whose neighbours
+  // before them are all done (ballot compaction, one atomic per wavefront).
+  int* list = w0.as<int>();
+  int* lcnt = cnt.as<int>() + 2;
+  int remaining = 0, coloured = 0;
+  for (;;) {
+    AMG_HIP(hipMemsetAsync(lcnt, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_ready0, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, ntiles, pend.as<int>(), list, lcnt);
+    remaining = read1(lcnt, s);
+    if (remaining == 0) break;
+    hipLaunchKernelGGL(k_colour_tiles, dim3(remaining), dim3(WAVE), shm, s, n, T, list, L.rowptr, L.colind,
+                       tptr.as<int>(), tadj.as<int>(), pend.as<int>(), seed, L.colour, cnt.as<int>() + 1);
     AMG_HIP(hipGetLastError());
-    ++rounds;
     coloured += remaining;
-    remaining = read1(next_cnt, s);
-    work = next;
   }
   if (coloured != ntiles) fail(AMG_ERR_HIP, "tile colouring did not reach every tile");
   const int C = read1(cnt.as<int>() + 1, s) + 1;

@@ -376,21 +376,25 @@ __global__ __launch_bounds__(NT) void kb_coarse(AMG_KARGS) {
 // thread per row), so the result does not depend on where the tail starts.
 constexpr int TAIL_NT = 1024;
 
+// op: 0 residual, 1 Gauss-Seidel pass, 2 Gauss-Seidel pass from x = 0.
 template <typename V, int R>
-__device__ inline void tail_slices(const BDesc& d, int s0, int s1, bool gs) {
+__device__ inline void tail_slices(const BDesc& d, int s0, int s1, int op) {
   const int nw = (int)blockDim.x / WAVE;
   for (int lo = s0; lo < s1; lo += nw) {
     const Item it{0, lo, min(s1, lo + nw), 0};
-    if (gs)
+    if (op == 1)
       kb_gs_body<V, R>(it, d);
+    else if (op == 2)
+      kb_gs0_body<V, R>(it, d);
     else
       kb_resid_body<V, R>(it, d);
   }
   __syncthreads();
 }
 
+// The colour passes of the separate launches, in the same order.
 template <typename V, int R>
-__device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps) {
+__device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps, bool from_zero) {
   int prev = -1;  // a pass on the colour just updated would repeat its values
   for (int k = 0; k < sweeps; ++k) {
     if (smoother == AMG_SMOOTHER_MCSGS) {
@@ -398,45 +402,48 @@ __device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps) {
         for (int q = 0; q < d.ncol; ++q) {
           const int c = dir == 0 ? q : d.ncol - 1 - q;
           if (c == prev) continue;
+          tail_slices<V, R>(d, d.sptr[c], d.sptr[c + 1], from_zero && prev < 0 ? 2 : 1);
           prev = c;
-          tail_slices<V, R>(d, d.sptr[c], d.sptr[c + 1], true);
         }
     } else {
-      tail_slices<V, R>(d, 0, d.nsl, false);
+      tail_slices<V, R>(d, 0, d.nsl, 0);
       kb_jacobi_body<V, R>(Item{0, 0, d.n, 0}, d);
       __syncthreads();
     }
   }
 }
 
+// Levels lt..lc-1 of one entry by one workgroup, where launches would be
+// latency bound: the down-leg (up = 0: x = 0, pre-smoothing, residual,
+// restriction) or the up-leg (up = 1: prolongation, post-smoothing).  The
+// coarsest solve between them is a separate many-block launch.
 // it.d: descriptor of level lt (level l at D[it.d + l - lt]); it.lo = lt, it.hi = lc.
 template <typename V, int R>
 __global__ __launch_bounds__(TAIL_NT) void kb_tail(const Item* __restrict__ tab, const BDesc* __restrict__ D,
-                                                    const Item base, int smoother, int pre, int post, int direct) {
+                                                    const Item base, int smoother, int pre, int post, int direct,
+                                                    int up) {
   const Item it = direct ? base : tab[blockIdx.x];
   const BDesc* dl = D + it.d;
   if (!direct && dl->active == 0) return;
   const int lt = it.lo, lc = it.hi;
-  const int nt = (int)blockDim.x, nw = nt / WAVE;
-  for (int l = lt; l < lc; ++l) {
-    const BDesc& d = dl[l - lt];
-    kb_zero_body<V, R>(Item{0, 0, d.n, 0}, d);
-    __syncthreads();
-    tail_smooth<V, R>(d, smoother, pre);
-    tail_slices<V, R>(d, 0, d.nsl, false);
-    for (int lo = 0; lo < d.nc; lo += nt) kb_restrict_body<V, R>(Item{0, lo, min(d.nc, lo + nt), 0}, d);
-    __syncthreads();
-  }
-  {
-    const BDesc& c = dl[lc - lt];
-    for (int lo = 0; lo < c.nL; lo += nw) kb_coarse_body<V, R>(Item{0, lo, min(c.nL, lo + nw), 0}, c);
-    __syncthreads();
-  }
-  for (int l = lc - 1; l >= lt; --l) {
-    const BDesc& d = dl[l - lt];
-    kb_prolong_body<V, R>(Item{0, 0, d.n, 0}, d);
-    __syncthreads();
-    tail_smooth<V, R>(d, smoother, post);
+  const int nt = (int)blockDim.x;
+  if (!up) {
+    for (int l = lt; l < lc; ++l) {
+      const BDesc& d = dl[l - lt];
+      kb_zero_body<V, R>(Item{0, 0, d.n, 0}, d);
+      __syncthreads();
+      tail_smooth<V, R>(d, smoother, pre, true);
+      tail_slices<V, R>(d, 0, d.nsl, 0);
+      for (int lo = 0; lo < d.nc; lo += nt) kb_restrict_body<V, R>(Item{0, lo, min(d.nc, lo + nt), 0}, d);
+      __syncthreads();
+    }
+  } else {
+    for (int l = lc - 1; l >= lt; --l) {
+      const BDesc& d = dl[l - lt];
+      kb_prolong_body<V, R>(Item{0, 0, d.n, 0}, d);
+      __syncthreads();
+      tail_smooth<V, R>(d, smoother, post, false);
+    }
   }
 }
 
@@ -476,9 +483,33 @@ __global__ __launch_bounds__(NT) void kb_x2z(AMG_KARGS) {
 }
 
 // ---------------------------------------------------------------- CG vectors
+// zx: z is the FP32 level-0 iterate of the cycle, widened here (exactly), so
+// the FP64 z is never stored during the iterations.
+template <int R>
+__device__ inline void load_z(const BDesc& d, int i, int zx, double (&zv)[R]) {
+  if (zx) {
+    float xv[R];
+    ldv<float, R>(static_cast<const float*>(d.x) + (size_t)i * R, xv);
+#pragma unroll
+    for (int k = 0; k < R; ++k) zv[k] = (double)xv[k];
+  } else {
+    ldv<double, R>(d.z + (size_t)i * R, zv);
+  }
+}
+
+// b32: the FP32 right-hand side of the cycle's level 0 is (float) r, written
+// where r is produced, so the next cycle needs no separate conversion.
+template <int R>
+__device__ inline void store_b32(const BDesc& d, int i, const double (&rv)[R]) {
+  float o[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) o[k] = (float)rv[k];
+  stv<float, R>(static_cast<float*>(d.b) + (size_t)i * R, o);
+}
+
 // Partials of r.z and (flexible) z.(r - r_old) over the rows [lo, hi).
 template <int R>
-__device__ __forceinline__ void kb_dots_rz_body(const Item& it, const BDesc& d) {
+__device__ __forceinline__ void kb_dots_rz_body(const Item& it, const BDesc& d, int zx) {
   double a[R], c[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) a[k] = c[k] = 0.0;
@@ -486,7 +517,7 @@ __device__ __forceinline__ void kb_dots_rz_body(const Item& it, const BDesc& d) 
   for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
     double rv[R], zv[R];
     ldv<double, R>(d.r + (size_t)i * R, rv);
-    ldv<double, R>(d.z + (size_t)i * R, zv);
+    load_z<R>(d, i, zx, zv);
 #pragma unroll
     for (int k = 0; k < R; ++k) a[k] = madd(rv[k], zv[k], a[k]);
     if (flex) {
@@ -502,13 +533,13 @@ __device__ __forceinline__ void kb_dots_rz_body(const Item& it, const BDesc& d) 
   write_partials<R>(d, 1, it.part, c);
 }
 template <int R, bool DIRECT>
-__global__ __launch_bounds__(NT) void kb_dots_rz(AMG_KARGS) {
-  AMG_BODY((kb_dots_rz_body<R>))
+__global__ __launch_bounds__(NT) void kb_dots_rz(AMG_KARGS, int zx) {
+  AMG_BODY((kb_dots_rz_body<R>), zx)
 }
 
 // p = z (first direction) or p = z + beta p, rows [lo, hi).
 template <int R>
-__device__ __forceinline__ void kb_update_p_body(const Item& it, const BDesc& d) {
+__device__ __forceinline__ void kb_update_p_body(const Item& it, const BDesc& d, int zx) {
   bool skip[R], first[R];
   double beta[R];
 #pragma unroll
@@ -520,7 +551,7 @@ __device__ __forceinline__ void kb_update_p_body(const Item& it, const BDesc& d)
   for (int i = it.lo + (int)threadIdx.x; i < it.hi; i += NT) {
     double pv[R], zv[R];
     ldv<double, R>(d.p + (size_t)i * R, pv);
-    ldv<double, R>(d.z + (size_t)i * R, zv);
+    load_z<R>(d, i, zx, zv);
 #pragma unroll
     for (int k = 0; k < R; ++k)
       if (!skip[k]) pv[k] = first[k] ? zv[k] : madd(beta[k], pv[k], zv[k]);
@@ -528,8 +559,8 @@ __device__ __forceinline__ void kb_update_p_body(const Item& it, const BDesc& d)
   }
 }
 template <int R, bool DIRECT>
-__global__ __launch_bounds__(NT) void kb_update_p(AMG_KARGS) {
-  AMG_BODY((kb_update_p_body<R>))
+__global__ __launch_bounds__(NT) void kb_update_p(AMG_KARGS, int zx) {
+  AMG_BODY((kb_update_p_body<R>), zx)
 }
 
 // q = A p (FP64, SELL slices [lo, hi), wavefront w takes lo + w, lo + w + 4, ...)
@@ -570,7 +601,8 @@ __global__ __launch_bounds__(NT) void kb_spmv_dot(AMG_KARGS) {
 template <int R>
 __device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d, int which) {
   const int lane = __lane_id();
-  double* out = which ? d.q : d.r;
+  const bool b32 = (which & 2) != 0;
+  double* out = (which & 1) ? d.q : d.r;
   double acc[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) acc[k] = 0.0;
@@ -590,6 +622,7 @@ __device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d
         acc[k] = madd(o[k], o[k], acc[k]);
       }
       stv<double, R>(out + (size_t)r * R, o);
+      if (b32) store_b32<R>(d, r, o);
     }
   }
   block_sums<R>(acc);
@@ -652,7 +685,8 @@ __global__ __launch_bounds__(NT) void kb_spmv_dot_csr(AMG_KARGS) {
 template <int R, int SUB>
 __device__ __forceinline__ void kb_resid_dot_csr_body(const Item& it, const BDesc& d, int which) {
   const int sl = threadIdx.x % SUB;
-  double* out = which ? d.q : d.r;
+  const bool b32 = (which & 2) != 0;
+  double* out = (which & 1) ? d.q : d.r;
   double acc[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) acc[k] = 0.0;
@@ -668,6 +702,7 @@ __device__ __forceinline__ void kb_resid_dot_csr_body(const Item& it, const BDes
         acc[k] = madd(o[k], o[k], acc[k]);
       }
       stv<double, R>(out + (size_t)i * R, o);
+      if (b32) store_b32<R>(d, i, o);
     }
   }
   block_sums<R>(acc);
@@ -681,7 +716,7 @@ __global__ __launch_bounds__(NT) void kb_resid_dot_csr(AMG_KARGS, int which) {
 // x += alpha p; r_old = r (flexible); r -= alpha q; partials of r.r, rows
 // [lo, hi).  A frozen right-hand side keeps x, r and r_old.
 template <int R>
-__device__ __forceinline__ void kb_update_xr_body(const Item& it, const BDesc& d) {
+__device__ __forceinline__ void kb_update_xr_body(const Item& it, const BDesc& d, int b32) {
   bool skip[R], anyskip = false;
   double alpha[R];
 #pragma unroll
@@ -711,6 +746,7 @@ __device__ __forceinline__ void kb_update_xr_body(const Item& it, const BDesc& d
     }
     stv<double, R>(d.xs + (size_t)i * R, xv);
     stv<double, R>(d.r + (size_t)i * R, rv);
+    if (b32) store_b32<R>(d, i, rv);
     if (flex) {
       if (anyskip) {
         double keep[R];
@@ -728,8 +764,8 @@ __device__ __forceinline__ void kb_update_xr_body(const Item& it, const BDesc& d
   write_partials<R>(d, 0, it.part, acc);
 }
 template <int R, bool DIRECT>
-__global__ __launch_bounds__(NT) void kb_update_xr(AMG_KARGS) {
-  AMG_BODY((kb_update_xr_body<R>))
+__global__ __launch_bounds__(NT) void kb_update_xr(AMG_KARGS, int b32) {
+  AMG_BODY((kb_update_xr_body<R>), b32)
 }
 
 template <int R>
@@ -887,13 +923,15 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
     case OP_PROLONG: AMG_LAUNCH(kb_prolong, (V, R)); break;
     case OP_COARSE: AMG_LAUNCH(kb_coarse, (V, R)); break;
     case OP_TAIL:
+    case OP_TAIL_UP: {
+      const int up = L.op == OP_TAIL_UP ? 1 : 0;
       if (L.use_direct)
         hipLaunchKernelGGL((kb_tail<V, R>), dim3(1), dim3(TAIL_NT), 0, s, nullptr, D, L.direct, L.aux, L.aux2 >> 8,
-                           L.aux2 & 255, 1);
+                           L.aux2 & 255, 1, up);
       else
         hipLaunchKernelGGL((kb_tail<V, R>), dim3(L.nblk), dim3(TAIL_NT), 0, s, t, D, Item{}, L.aux, L.aux2 >> 8,
-                           L.aux2 & 255, 0);
-      break;
+                           L.aux2 & 255, 0, up);
+    } break;
     default: fail(AMG_ERR_HIP, "unknown cycle launch");
   }
 }
@@ -911,6 +949,7 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
     case OP_PROLONG:
     case OP_COARSE:
     case OP_TAIL:
+    case OP_TAIL_UP:
       if (fp32)
         launch_cycle_op<float, R>(L, t, D, Dh, s);
       else
@@ -918,11 +957,11 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
       break;
     case OP_R2B: AMG_LAUNCH(kb_r2b, (R)); break;
     case OP_X2Z: AMG_LAUNCH(kb_x2z, (R)); break;
-    case OP_DOTS_RZ: AMG_LAUNCH(kb_dots_rz, (R)); break;
-    case OP_UPDATE_P: AMG_LAUNCH(kb_update_p, (R)); break;
+    case OP_DOTS_RZ: AMG_LAUNCH(kb_dots_rz, (R), L.aux); break;
+    case OP_UPDATE_P: AMG_LAUNCH(kb_update_p, (R), L.aux); break;
     case OP_SPMV_DOT: AMG_LAUNCH(kb_spmv_dot, (R)); break;
     case OP_SPMV_DOT_CSR: AMG_SUB_DISPATCH(L.aux, AMG_LAUNCH(kb_spmv_dot_csr, (R, SUB))); break;
-    case OP_UPDATE_XR: AMG_LAUNCH(kb_update_xr, (R)); break;
+    case OP_UPDATE_XR: AMG_LAUNCH(kb_update_xr, (R), L.aux); break;
     case OP_RESID_DOT: AMG_LAUNCH(kb_resid_dot, (R), L.aux); break;
     case OP_RESID_DOT_CSR: AMG_SUB_DISPATCH(L.aux2, AMG_LAUNCH(kb_resid_dot_csr, (R, SUB), L.aux)); break;
     case OP_DOT_BB: AMG_LAUNCH(kb_dot_bb, (R)); break;

@@ -37,7 +37,7 @@ def test_params_struct_matches_header_defaults():
     from paper_1209_0960_amd import amg as A
     p = A.default_params()
     assert (p.strength_threshold, p.isolated_threshold, p.agg_min, p.agg_max, p.agg_diameter) == (0.08, 1e-5, 8, 12, 3)
-    assert (p.omega, p.coarse_max, p.max_levels, p.tile_rows) == (1.6, 500, 25, 512)
+    assert (p.omega, p.coarse_max, p.max_levels, p.tile_rows) == (1.6, 500, 25, 128)
     assert (p.smoother, p.pre_sweeps, p.post_sweeps, p.vcycle_fp32, p.flexible) == (0, 1, 1, 0, -1)
     assert p.use_graphs == 1
     assert p.tail_rows == 0

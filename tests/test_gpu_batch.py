@@ -174,3 +174,38 @@ def test_precond_after_solve_matches_fresh(A):
         z2 = h.precond(r)
         torch.cuda.synchronize()
         assert torch.equal(z1, z2)
+
+
+@pytest.mark.parametrize("fp32", [1, 0])
+def test_tail_bit_identical(A, fp32):
+    """Levels cycled by one workgroup per entry (tail_rows: below that many
+    rows; the coarsest solve stays a many-block launch) give the same bits as
+    one launch per step: single solves, preconditioner applications, and
+    batches with four right-hand sides per system."""
+    d = dev(systems(4, seed=5))
+    ref = None
+    for tail in (0, 600, 1 << 30):
+        hs = [A.Hierarchy(rp, ci, v, vcycle_fp32=fp32, tail_rows=tail) for rp, ci, v, _ in d]
+        try:
+            out = []
+            for h, (*_, B) in zip(hs, d):
+                b = B[0].contiguous()
+                x, r = alone(A, h, b)
+                out.append((r.iterations, x.cpu().numpy(), h.precond(b).cpu().numpy()))
+            bs = [B.reshape(-1).clone() for *_, B in d]
+            xs = [torch.zeros_like(b) for b in bs]
+            st, infos = A.pcg_solve_batched([h.h for h in hs], bs, xs, nrhs=4, rtol=1e-8, maxit=200)
+            assert st == A.OK
+            out.append(([i["iterations"] for inf in infos for i in inf], [x.cpu().numpy() for x in xs]))
+        finally:
+            for h in hs:
+                h.close()
+        if ref is None:
+            ref = out
+            continue
+        for k, (a, c) in enumerate(zip(ref[:-1], out[:-1])):
+            assert a[0] == c[0], (tail, k)
+            assert np.array_equal(a[1], c[1]) and np.array_equal(a[2], c[2]), (tail, k)
+        assert ref[-1][0] == out[-1][0], tail
+        for a, c in zip(ref[-1][1], out[-1][1]):
+            assert np.array_equal(a, c), tail

@@ -27,7 +27,7 @@ from paper_1209_0960_amd import problems as P
 
 pytestmark = pytest.mark.gpu
 
-T = 512
+T = 128  # tile_rows default
 
 
 @pytest.fixture(scope="module")
