@@ -800,7 +800,7 @@ __global__ void k_agg_finalize(int n, int T, const int* __restrict__ agg_local, 
 // order with agg[j] = J of a_ij, summed sequentially from the first term.
 // One wavefront per coarse row: the row's terms are gathered in that order,
 // ranked by (J, position) (a stable counting sort), and equal-J runs summed.
-constexpr int GAL_CAP = 512;
+constexpr int GAL_CAP = 256;
 constexpr int GAL_WAVES = 4;
 
 __global__ void k_term_count(int nc, const int* __restrict__ mptr, const int* __restrict__ members,
@@ -859,10 +859,19 @@ __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr,
   }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
+  // Rank of term t among the terms ordered by (J, position): a stable
+  // counting sort, reading 8 terms per step with their loads in flight together.
   for (int t = lane; t < m; t += WAVE) {
     const int Jt = J[t];
-    int r = 0;
-    for (int u = 0; u < m; ++u) {
+    int r = 0, u = 0;
+    for (; u + 8 <= m; u += 8) {
+      int Ju[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) Ju[k] = J[u + k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) r += (Ju[k] < Jt || (Ju[k] == Jt && u + k < t)) ? 1 : 0;
+    }
+    for (; u < m; ++u) {
       const int Ju = J[u];
       r += (Ju < Jt || (Ju == Jt && u < t)) ? 1 : 0;
     }
@@ -870,6 +879,9 @@ __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr,
   }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
+  // Equal-J runs in rank order, each summed sequentially from its first term
+  // by the run's head; the run's end inside this chunk of 64 ranks comes from
+  // the ballot of heads, so its loads are independent of the additions.
   int cnt = 0;
   for (int base = 0; base < m; base += WAVE) {
     const int r = base + lane;
@@ -882,8 +894,13 @@ __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr,
     const uint64_t hm = __ballot(head);
     if (head) {
       const int o = cnt + __popcll(hm & lanemask_lt());
+      const uint64_t after = lane == WAVE - 1 ? 0ull : (hm >> (lane + 1));
+      const int end = after ? r + 1 + (int)__builtin_ctzll(after) : min(m, base + WAVE);
       double acc = V[Sx[r]];
-      for (int q = r + 1; q < m && J[Sx[q]] == Jr; ++q) acc = acc + V[Sx[q]];
+#pragma unroll 4
+      for (int q = r + 1; q < end; ++q) acc = acc + V[Sx[q]];
+      if (!after)  // the run may go on in the next chunk
+        for (int q = end; q < m && J[Sx[q]] == Jr; ++q) acc = acc + V[Sx[q]];
       tcol[tb + o] = Jr;
       tval[tb + o] = acc;
     }
@@ -1024,10 +1041,10 @@ __global__ void k_ready0(int ntiles, const int* __restrict__ pending, int* __res
 }
 
 // Dynamic LDS of k_colour_tiles: lptr[T+1], col[T], mask[T] (64-bit), big[T],
-// adj[E] (local indices of the smaller in-tile neighbours).
+// qcur[T], adj[E] (local indices of the smaller in-tile neighbours).
 __host__ __device__ inline size_t col_smem(int T, int E) {
   return align16(4 * (size_t)(T + 1)) + align16(4 * (size_t)T) + align16(8 * (size_t)T) + align16((size_t)T) +
-         align16(2 * (size_t)(E > 0 ? E : 1));
+         align16(4 * (size_t)T) + align16(2 * (size_t)(E > 0 ? E : 1));
 }
 
 // Colours the tiles of `work` (all their preceding neighbour tiles are
@@ -1041,7 +1058,8 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
   int* col = (int*)(sm + align16(4 * (size_t)(T + 1)));
   uint64_t* mask = (uint64_t*)((unsigned char*)col + align16(4 * (size_t)T));
   unsigned char* big = (unsigned char*)mask + align16(8 * (size_t)T);
-  unsigned short* adj = (unsigned short*)(big + align16((size_t)T));
+  int* qcur = (int*)(big + align16((size_t)T));  // first smaller neighbour not yet seen coloured
+  unsigned short* adj = (unsigned short*)((unsigned char*)qcur + align16(4 * (size_t)T));
   const int lane = __lane_id();
   const int t = work[blockIdx.x];
   const int lo = t * T, hi = min(lo + T, n), nt = hi - lo;
@@ -1078,6 +1096,7 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
   for (int v = lane; v < nt; v += WAVE) {
     const int i = lo + v;
     int pos = lptr[v];
+    qcur[v] = pos;
     for_entries(rp, ci, i, [&](int, int j) {
       if (j >= lo && j < i) adj[pos++] = (unsigned short)(j - lo);
     });
@@ -1089,6 +1108,8 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
   // be coloured at once: wavefront rounds (one lane per row) while the rate
   // would finish the tile in a few dozen rounds, then rows in ascending order
   // for the rest of a long chain.  Both give the sequential first-fit colouring.
+  // Colours never change once set, so a waiting row keeps where its scan
+  // stopped (qcur) and the colours seen so far (OR-ed into mask, big).
   int cmax = -1;
   int first = 0;  // every row below `first` is coloured
   int total = 0;  // rows coloured by the rounds
@@ -1098,7 +1119,8 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
       if (col[v] >= 0) continue;
       uint64_t m = mask[v];
       bool ready = true, bg = big[v] != 0;
-      for (int q = lptr[v]; q < lptr[v + 1]; ++q) {  // stops at the first uncoloured one
+      int q = qcur[v];
+      for (const int qe = lptr[v + 1]; q < qe; ++q) {  // stops at the first uncoloured one
         const int cj = col[adj[q]];
         if (cj < 0) {
           ready = false;
@@ -1109,7 +1131,13 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
         else
           bg = true;
       }
-      if (!ready || bg || m == ~0ull) continue;  // colours beyond 63: left to the ordered pass
+      if (!ready) {
+        qcur[v] = q;
+        mask[v] = m;
+        big[v] = bg ? 1 : 0;
+        continue;
+      }
+      if (bg || m == ~0ull) continue;  // colours beyond 63: left to the ordered pass
       const int c = (int)__builtin_ctzll(~m);
       col[v] = c;
       cmax = max(cmax, c);
@@ -1118,7 +1146,16 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
     __syncthreads();
     made = wave_sum(made);
     total += made;
-    while (first < nt && col[first] >= 0) ++first;
+    while (first < nt) {  // first uncoloured row, 64 rows per step
+      const int v = first + lane;
+      const uint64_t done = __ballot(v >= nt || col[v] >= 0);
+      if (done != ~0ull) {
+        first += (int)__builtin_ctzll(~done);
+        break;
+      }
+      first += WAVE;
+    }
+    first = min(first, nt);
     if (first >= nt || made == 0) break;
     // A long dependency chain (few rows per round) is faster row by row.
     if (round >= 7 && (long long)(nt - total) * (round + 1) > 40LL * total) break;
