@@ -279,6 +279,7 @@ enum {
   OP_FINISH,     // per entry: reduce partials, scalar update (aux = FIN_*, aux2 = slot)
   OP_GS0,        // first Gauss-Seidel pass from x = 0: x = b / diag on the slices of one colour
   OP_TAIL_UP,    // up-leg of levels L-1..lt of one entry in one workgroup (prolong, post-smooth)
+  OP_GS_RESID,   // Gauss-Seidel pass that also writes the residual of its rows
 };
 enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
 

@@ -467,7 +467,8 @@ double pass_bytes(const Level& L, int s0, int s1, int R, double vb) {
   return ent * (4.0 + vb) + rows * (vb + 3.0 * R * vb) + (s1 - s0) * 8.0;
 }
 
-void add_slices(Builder& b, const Batch& B, int slot, int l, int s0, int s1) {
+// extra_writes: further R-vectors written per row (the residual variant: 1).
+void add_slices(Builder& b, const Batch& B, int slot, int l, int s0, int s1, double extra_writes = 0.0) {
   if (s0 >= s1) return;
   const Level& L = hier(B, slot).lev[l];
   const double vb = B.fp32 ? 4 : 8;
@@ -475,7 +476,8 @@ void add_slices(Builder& b, const Batch& B, int slot, int l, int s0, int s1) {
   b.segment(d, s0, s1, SLICES_PB);
   for (int lo = s0; lo < s1; lo += SLICES_PB) {
     const int hi = std::min(s1, lo + SLICES_PB);
-    b.add(d, lo, hi, 0, pass_bytes(L, lo, hi, B.R, vb));
+    const double rows = (double)(L.srow_h[hi] - L.srow_h[lo]);
+    b.add(d, lo, hi, 0, pass_bytes(L, lo, hi, B.R, vb) + extra_writes * rows * B.R * vb);
   }
 }
 
@@ -501,7 +503,18 @@ double pass0_bytes(const Level& L, int s0, int s1, int R, double vb) {
   return rows * (vb + 2.0 * R * vb) + (s1 - s0) * 8.0;
 }
 
-// `sweeps` smoothing steps on level l; from_zero: the iterate is zero before.
+// Multicolour smoothing of entry e's level l starts and ends on colour 0 and
+// takes more than one pass: the zero fill and the prolongation can skip the
+// colour-0 rows (their values are written by the first pass before any read),
+// and the last pre-smoothing pass writes the residual of its rows.
+bool colour0_shortcuts(const Batch& B, int e, int l) {
+  return B.smoother == AMG_SMOOTHER_MCSGS && hier(B, e).lev[l].ncol >= 2;
+}
+// First row after colour 0 (solve order).
+int colour0_rows(const Level& L) { return L.srow_h[L.sptr[1]]; }
+
+// `sweeps` smoothing steps on level l; from_zero: the iterate is zero before,
+// and (pre-smoothing) each entry's last pass also writes its residual rows.
 void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, int sweeps, bool from_zero) {
   const double vb = B.fp32 ? 4 : 8;
   if (B.smoother == AMG_SMOOTHER_MCSGS) {
@@ -513,9 +526,25 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
     }
     for (size_t j = 0; j < len; ++j) {
       const bool zero = from_zero && j == 0;
+      // entries whose last pre-smoothing pass this is: the residual variant
+      auto last = [&](size_t i) {
+        return from_zero && !zero && j + 1 == seq[i].size() && colour0_shortcuts(B, E[i], l);
+      };
+      bool any_last = false;
+      for (size_t i = 0; i < E.size(); ++i) any_last = any_last || (j < seq[i].size() && last(i));
+      if (any_last) {
+        b.begin(OP_GS_RESID, l, kind_at(l, AMG_KIND_RESTRICT));
+        for (size_t i = 0; i < E.size(); ++i) {
+          if (j >= seq[i].size() || !last(i)) continue;
+          const Level& L = hier(B, E[i]).lev[l];
+          const int c = seq[i][j];
+          add_slices(b, B, E[i], l, L.sptr[c], L.sptr[c + 1], 1.0);
+        }
+        b.end();
+      }
       b.begin(zero ? OP_GS0 : OP_GS, l, kind_at(l, zero ? AMG_KIND_OTHER : AMG_KIND_SWEEP));
       for (size_t i = 0; i < E.size(); ++i) {
-        if (j >= seq[i].size()) continue;
+        if (j >= seq[i].size() || last(i)) continue;
         const int e = E[i];
         const Level& L = hier(B, e).lev[l];
         const int c = seq[i][j];
@@ -567,11 +596,18 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool c
   for (int l = 0; l < maxLc; ++l) {
     const std::vector<int>& E = below[l];
     b.begin(OP_ZERO, l, l == 0 ? AMG_KIND_OTHER : AMG_KIND_COARSE_LEVELS);
-    for (int e : E) b.pieces(B.desc_index(e, l), hier(B, e).lev[l].n, ROW_CH, R * vb);
+    for (int e : E) {
+      const Level& L = hier(B, e).lev[l];
+      const int r0 = B.pre > 0 && colour0_shortcuts(B, e, l) ? colour0_rows(L) : 0;
+      b.pieces(B.desc_index(e, l), r0, L.n, ROW_CH, R * vb);
+    }
     b.end();
     build_smooth(b, B, E, l, B.pre, true);
     b.begin(OP_RESID, l, kind_at(l, AMG_KIND_RESTRICT));
-    for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
+    for (int e : E) {
+      const Level& L = hier(B, e).lev[l];
+      add_slices(b, B, e, l, B.pre > 0 && colour0_shortcuts(B, e, l) ? L.sptr[1] : 0, L.nsl);
+    }
     b.end();
     b.begin(OP_RESTRICT, l, kind_at(l, AMG_KIND_RESTRICT));
     for (int e : E) {
@@ -622,7 +658,8 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool c
     for (int e : E) {
       const Level& L = hier(B, e).lev[l];
       const double per_row = 4.0 + 2.0 * R * vb + R * vb * (double)L.nc / L.n;
-      b.pieces(B.desc_index(e, l), L.n, ROW_CH, per_row);
+      const int r0 = B.post > 0 && colour0_shortcuts(B, e, l) ? colour0_rows(L) : 0;
+      b.pieces(B.desc_index(e, l), r0, L.n, ROW_CH, per_row);
     }
     b.end();
     build_smooth(b, B, E, l, B.post, false);

@@ -185,8 +185,10 @@ __device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __res
 
 // Gauss-Seidel update of the slices [lo, hi) (one per wavefront) of one
 // colour: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.  Rows of one colour do
-// not couple, so the in-place update is race free.
-template <typename V, int R>
+// not couple, so the in-place update is race free.  RES (the last pass before
+// the residual): also t_i = b_i - (a_ii x_i + sum), from the same sum, which
+// is what the residual kernel would compute for these rows.
+template <typename V, int R, bool RES = false>
 __device__ __forceinline__ void kb_gs_body(const Item& it, const BDesc& d) {
   const int sl = it.lo + (int)(threadIdx.x / WAVE);
   if (sl >= it.hi) return;
@@ -203,11 +205,21 @@ __device__ __forceinline__ void kb_gs_body(const Item& it, const BDesc& d) {
 #pragma unroll
     for (int k = 0; k < R; ++k) o[k] = (bb[k] - acc[k]) / dg;
     stv<V, R>(x + (size_t)r * R, o);
+    if constexpr (RES) {
+      V t[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) t[k] = bb[k] - madd(dg, o[k], acc[k]);
+      stv<V, R>(static_cast<V*>(d.t) + (size_t)r * R, t);
+    }
   }
 }
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_gs(AMG_KARGS) {
   AMG_BODY((kb_gs_body<V, R>))
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_gsr(AMG_KARGS) {
+  AMG_BODY((kb_gs_body<V, R, true>))
 }
 
 // The first Gauss-Seidel pass from x = 0: every off-diagonal product is a
@@ -917,6 +929,7 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
     case OP_ZERO: AMG_LAUNCH(kb_zero, (V, R)); break;
     case OP_GS: AMG_LAUNCH(kb_gs, (V, R)); break;
     case OP_GS0: AMG_LAUNCH(kb_gs0, (V, R)); break;
+    case OP_GS_RESID: AMG_LAUNCH(kb_gsr, (V, R)); break;
     case OP_RESID: AMG_LAUNCH(kb_resid, (V, R)); break;
     case OP_JACOBI: AMG_LAUNCH(kb_jacobi, (V, R)); break;
     case OP_RESTRICT: AMG_LAUNCH(kb_restrict, (V, R)); break;
@@ -943,6 +956,7 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
     case OP_ZERO:
     case OP_GS:
     case OP_GS0:
+    case OP_GS_RESID:
     case OP_RESID:
     case OP_JACOBI:
     case OP_RESTRICT:
