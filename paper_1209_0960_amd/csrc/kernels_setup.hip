@@ -1049,10 +1049,9 @@ __host__ __device__ inline size_t col_smem(int T, int E) {
 
 // Colours the tiles of `work` (all their preceding neighbour tiles are
 // finished), then releases the neighbour tiles they precede.
-__global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* __restrict__ work,
-                                                       const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const int* __restrict__ tptr, const int* __restrict__ tadj,
-                                                       int* pending, uint32_t seed, int* colour, int* maxcol) {
+__device__ void colour_tile(int t, int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const int* __restrict__ tptr, const int* __restrict__ tadj, int* pending, uint32_t seed,
+                            int* colour, int* maxcol) {
   extern __shared__ __align__(16) unsigned char sm[];
   int* lptr = (int*)sm;
   int* col = (int*)(sm + align16(4 * (size_t)(T + 1)));
@@ -1061,7 +1060,6 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
   int* qcur = (int*)(big + align16((size_t)T));  // first smaller neighbour not yet seen coloured
   unsigned short* adj = (unsigned short*)((unsigned char*)qcur + align16(4 * (size_t)T));
   const int lane = __lane_id();
-  const int t = work[blockIdx.x];
   const int lo = t * T, hi = min(lo + T, n), nt = hi - lo;
   // Colours already taken by off-tile neighbours (all in preceding tiles) and
   // the smaller in-tile neighbours of each row.
@@ -1211,6 +1209,27 @@ __global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* 
     if (tile_before(t, u, seed)) atomicSub(&pending[u], 1);
   }
   if (lane == 0) pending[t] = -1;
+  __syncthreads();  // the next tile of this block reuses the shared arrays
+}
+
+// The tiles of work[0, *count) (all their preceding neighbour tiles are
+// finished), block b taking entries b, b + gridDim.x, ...: the grid does not
+// depend on the count, so rounds are enqueued without a host round trip.
+__global__ __launch_bounds__(WAVE) void k_colour_tiles(int n, int T, const int* __restrict__ work,
+                                                       const int* __restrict__ count, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, const int* __restrict__ tptr,
+                                                       const int* __restrict__ tadj, int* pending, uint32_t seed,
+                                                       int* colour, int* maxcol) {
+  const int c = *count;
+  for (int w = blockIdx.x; w < c; w += gridDim.x)
+    colour_tile(work[w], n, T, rp, ci, tptr, tadj, pending, seed, colour, maxcol);
+}
+
+// Number of tiles not yet coloured (pending != -1), added to *out.
+__global__ void k_count_pending(int ntiles, const int* __restrict__ pending, int* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t m = __ballot(t < ntiles && pending[t] != -1);
+  if (m && __lane_id() == (int)__builtin_ctzll(m)) atomicAdd(out, __popcll(m));
 }
 
 constexpr int CL_THREADS = 256;
@@ -1718,22 +1737,28 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   const size_t shm = col_smem(T, Ecap);
   if (shm > 160 * 1024) fail(AMG_ERR_UNSUPPORTED, "colouring tile exceeds LDS; use smaller tile_rows");
   AMG_HIP(hipFuncSetAttribute((const void*)k_colour_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  // Rounds: colour the listed tiles, then list the tiles whose neighbours
-  // before them are all done (ballot compaction, one atomic per wavefront).
+  // Rounds: list the tiles whose neighbours before them are all done (ballot
+  // compaction, one atomic per wavefront), then colour them.  Rounds are
+  // enqueued 8 at a time; the host then checks whether any tile is left.
+  // Every round colours at least one tile while any is left (the tile order
+  // is acyclic), so ntiles rounds always suffice.
   int* list = w0.as<int>();
   int* lcnt = cnt.as<int>() + 2;
-  int remaining = 0, coloured = 0;
-  for (;;) {
-    AMG_HIP(hipMemsetAsync(lcnt, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_ready0, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, ntiles, pend.as<int>(), list, lcnt);
-    remaining = read1(lcnt, s);
-    if (remaining == 0) break;
-    hipLaunchKernelGGL(k_colour_tiles, dim3(remaining), dim3(WAVE), shm, s, n, T, list, L.rowptr, L.colind,
-                       tptr.as<int>(), tadj.as<int>(), pend.as<int>(), seed, L.colour, cnt.as<int>() + 1);
+  const int grid = std::min(ntiles, 8192);
+  for (int done = 0; done < ntiles;) {
+    for (int k = 0; k < 8; ++k) {
+      AMG_HIP(hipMemsetAsync(lcnt, 0, sizeof(int), s));
+      hipLaunchKernelGGL(k_ready0, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, ntiles, pend.as<int>(), list, lcnt);
+      hipLaunchKernelGGL(k_colour_tiles, dim3(grid), dim3(WAVE), shm, s, n, T, list, lcnt, L.rowptr, L.colind,
+                         tptr.as<int>(), tadj.as<int>(), pend.as<int>(), seed, L.colour, cnt.as<int>() + 1);
+    }
     AMG_HIP(hipGetLastError());
-    coloured += remaining;
+    done += 8;
+    AMG_HIP(hipMemsetAsync(lcnt, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_count_pending, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, ntiles, pend.as<int>(), lcnt);
+    if (read1(lcnt, s) == 0) break;
+    if (done >= ntiles) fail(AMG_ERR_HIP, "tile colouring did not reach every tile");
   }
-  if (coloured != ntiles) fail(AMG_ERR_HIP, "tile colouring did not reach every tile");
   const int C = read1(cnt.as<int>() + 1, s) + 1;
   if (C > 4096) fail(AMG_ERR_UNSUPPORTED, "more than 4096 colours");
   L.ncol = C;
