@@ -357,7 +357,9 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
       strong = ts.as<uint8_t>();
       iso = ti.as<uint8_t>();
     }
-    strength(H.lev[l], p.strength_threshold, p.isolated_threshold, strong, iso, s);
+    // level 0's values were checked exactly symmetric; Galerkin sums of a
+    // coarse level need not be (their terms are added in different orders)
+    strength(H.lev[l], p.strength_threshold, p.isolated_threshold, strong, iso, l == 0 && p.check_symmetry != 0, s);
     const int nc = aggregate(H, H.lev[l], strong, iso, p, s);
     if ((double)nc > 0.9 * (double)n) {
       H.lev[l].nc = 0;  // stalled: this level becomes the coarsest

@@ -198,7 +198,8 @@ constexpr int CTL_INTS = 16;  // per entry: [0] active, [1 + k] right-hand side 
 // 4 = not symmetric.
 int validate_csr(int n, int nnz, const int* rp, const int* ci, const double* v, int check_symmetry,
                  hipStream_t s);
-void strength(const Level& L, double delta, double beta, uint8_t* strong, uint8_t* iso, hipStream_t s);
+// sym: the level's values are known to be exactly symmetric.
+void strength(const Level& L, double delta, double beta, uint8_t* strong, uint8_t* iso, bool sym, hipStream_t s);
 // Returns the number of coarse rows; fills agg, members, mptr, tile_off.
 int aggregate(Hierarchy& H, Level& L, const uint8_t* strong, const uint8_t* iso, const amg_params& p, hipStream_t s);
 // Galerkin product; returns the coarse level's CSR arrays allocated in H.

@@ -236,11 +236,16 @@ __global__ void k_validate_sym(int n, const int* __restrict__ rp, const int* __r
 // ============================================================== strength
 // Sec. 2.1, eqs. (symmetric_strong1)/(symmetric_strong2) on in-tile edges:
 // w_E(i,j) = max(-a_ij, 0), w_V(i) = a_ii, s_ij = w_E(i,j) w_E(j,i) / (a_ii a_jj).
+// sym: the values are known to be exactly symmetric (checked at setup), so
+// a_ji is a_ij and the transposed entry need not be looked up.
 __device__ inline double s_edge(const int* __restrict__ rp, const int* __restrict__ ci,
                                 const double* __restrict__ v, const double* __restrict__ d, int i, int j,
-                                double aij) {
-  const int q = find_in_row(rp, ci, j, i);
-  const double aji = q >= 0 ? v[q] : 0.0;
+                                double aij, bool sym) {
+  double aji = aij;
+  if (!sym) {
+    const int q = find_in_row(rp, ci, j, i);
+    aji = q >= 0 ? v[q] : 0.0;
+  }
   const double wij = (-aij > 0.0) ? -aij : 0.0;
   const double wji = (-aji > 0.0) ? -aji : 0.0;
   const double num = wij * wji;
@@ -248,50 +253,58 @@ __device__ inline double s_edge(const int* __restrict__ rp, const int* __restric
   return num / den;
 }
 
-__global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
-                       double* __restrict__ d) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// The strength kernels give each row STR_SUB consecutive lanes, which take
+// its entries in turn, so a row's entries are read by neighbouring lanes.
+constexpr int STR_SUB = 8;
+
+__global__ __launch_bounds__(256) void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const double* __restrict__ v, double* __restrict__ d) {
+  const int i = blockIdx.x * (256 / STR_SUB) + (int)threadIdx.x / STR_SUB, q0 = (int)threadIdx.x % STR_SUB;
   if (i >= n) return;
-  double a = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k)
-    if (ci[k] == i) a = v[k];
-  d[i] = a;
+  for (int k = rp[i] + q0; k < rp[i + 1]; k += STR_SUB)
+    if (ci[k] == i) d[i] = v[k];
 }
 
-__global__ void k_eta(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
-                      const double* __restrict__ v, const double* __restrict__ d, double* __restrict__ eta) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int lo = (i / T) * T, hi = min(lo + T, n);
+__global__ __launch_bounds__(256) void k_eta(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
+                                             const double* __restrict__ v, const double* __restrict__ d,
+                                             double* __restrict__ eta, int sym) {
+  const int i = blockIdx.x * (256 / STR_SUB) + (int)threadIdx.x / STR_SUB, q0 = (int)threadIdx.x % STR_SUB;
+  const bool row = i < n;
   double e = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const int j = ci[k];
-    if (j == i || j < lo || j >= hi) continue;
-    const double s = s_edge(rp, ci, v, d, i, j, v[k]);
-    if (s > e) e = s;
+  if (row) {
+    const int lo = (i / T) * T, hi = min(lo + T, n);
+    for (int k = rp[i] + q0; k < rp[i + 1]; k += STR_SUB) {
+      const int j = ci[k];
+      if (j == i || j < lo || j >= hi) continue;
+      const double s = s_edge(rp, ci, v, d, i, j, v[k], sym != 0);
+      if (s > e) e = s;
+    }
   }
-  eta[i] = e;
+#pragma unroll
+  for (int o = STR_SUB / 2; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, STR_SUB));
+  if (row && q0 == 0) eta[i] = e;
 }
 
-__global__ void k_strong(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
-                         const double* __restrict__ v, const double* __restrict__ d, const double* __restrict__ eta,
-                         double delta, double beta, uint8_t* __restrict__ strong, uint8_t* __restrict__ iso) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_strong(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const double* __restrict__ v, const double* __restrict__ d,
+                                                const double* __restrict__ eta, double delta, double beta,
+                                                uint8_t* __restrict__ strong, uint8_t* __restrict__ iso, int sym) {
+  const int i = blockIdx.x * (256 / STR_SUB) + (int)threadIdx.x / STR_SUB, q0 = (int)threadIdx.x % STR_SUB;
   if (i >= n) return;
   const int lo = (i / T) * T, hi = min(lo + T, n);
   const double ei = eta[i];
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+  for (int k = rp[i] + q0; k < rp[i + 1]; k += STR_SUB) {
     const int j = ci[k];
     uint8_t f = 0;
     if (j != i && j >= lo && j < hi) {
       const double ej = eta[j];
       const double m = ei < ej ? ei : ej;
-      const double s = s_edge(rp, ci, v, d, i, j, v[k]);
+      const double s = s_edge(rp, ci, v, d, i, j, v[k], sym != 0);
       f = (s > delta * m) ? 1 : 0;
     }
     strong[k] = f;
   }
-  iso[i] = (ei < beta) ? 1 : 0;
+  if (q0 == 0) iso[i] = (ei < beta) ? 1 : 0;
 }
 
 // ============================================================== aggregation
@@ -928,13 +941,14 @@ __global__ __launch_bounds__(GAL_WAVES* WAVE) void k_galerkin_rows(
     galerkin_row<int>(I, m, tb, mptr, members, rp, ci, va, agg, gJ + tb, gV + tb, gS + tb, tcol, tval, ucount);
 }
 
-__global__ void k_compact(int nc, const int* __restrict__ toff, const int* __restrict__ crp,
-                          const int* __restrict__ tcol, const double* __restrict__ tval, int* __restrict__ ccol,
-                          double* __restrict__ cval) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+// 16 lanes per coarse row, so the copies are contiguous across lanes.
+__global__ __launch_bounds__(256) void k_compact(int nc, const int* __restrict__ toff, const int* __restrict__ crp,
+                                                 const int* __restrict__ tcol, const double* __restrict__ tval,
+                                                 int* __restrict__ ccol, double* __restrict__ cval) {
+  const int I = blockIdx.x * 16 + (int)threadIdx.x / 16, q0 = (int)threadIdx.x % 16;
   if (I >= nc) return;
   const int src = toff[I], dst = crp[I], cnt = crp[I + 1] - dst;
-  for (int q = 0; q < cnt; ++q) {
+  for (int q = q0; q < cnt; q += 16) {
     ccol[dst + q] = tcol[src + q];
     cval[dst + q] = tval[src + q];
   }
@@ -1628,14 +1642,15 @@ int validate_csr(int n, int nnz, const int* rp, const int* ci, const double* v, 
   return read1(f.as<int>(), s);
 }
 
-void strength(const Level& L, double delta, double beta, uint8_t* strong, uint8_t* iso, hipStream_t s) {
+void strength(const Level& L, double delta, double beta, uint8_t* strong, uint8_t* iso, bool sym, hipStream_t s) {
   DBuf d((size_t)L.n * sizeof(double), s), eta((size_t)L.n * sizeof(double), s);
-  const int g = cdiv(L.n, 256);
+  const int g = cdiv(L.n, 256 / STR_SUB);
+  AMG_HIP(hipMemsetAsync(d.p, 0, (size_t)L.n * sizeof(double), s));  // rows without a stored diagonal
   hipLaunchKernelGGL(k_diag, dim3(g), dim3(256), 0, s, L.n, L.rowptr, L.colind, L.vals, d.as<double>());
   hipLaunchKernelGGL(k_eta, dim3(g), dim3(256), 0, s, L.n, L.T, L.rowptr, L.colind, L.vals, d.as<double>(),
-                     eta.as<double>());
+                     eta.as<double>(), sym ? 1 : 0);
   hipLaunchKernelGGL(k_strong, dim3(g), dim3(256), 0, s, L.n, L.T, L.rowptr, L.colind, L.vals, d.as<double>(),
-                     eta.as<double>(), delta, beta, strong, iso);
+                     eta.as<double>(), delta, beta, strong, iso, sym ? 1 : 0);
   AMG_HIP(hipGetLastError());
 }
 
@@ -1705,7 +1720,7 @@ void galerkin(Hierarchy& H, const Level& L, Level& C, hipStream_t s) {
   C.nnz = read1(C.rowptr + nc, s);
   C.colind = H.alloc<int>((size_t)C.nnz, s);
   C.vals = H.alloc<double>((size_t)C.nnz, s);
-  hipLaunchKernelGGL(k_compact, dim3(cdiv(nc, 256)), dim3(256), 0, s, nc, toff.as<int>(), C.rowptr, tcol.as<int>(),
+  hipLaunchKernelGGL(k_compact, dim3(cdiv(nc, 16)), dim3(256), 0, s, nc, toff.as<int>(), C.rowptr, tcol.as<int>(),
                      tval.as<double>(), C.colind, C.vals);
   AMG_HIP(hipGetLastError());
 }
