@@ -218,11 +218,12 @@ __device__ inline int find_in_row(const int* __restrict__ rp, const int* __restr
   return -1;
 }
 
-__global__ void k_validate_sym(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                               const double* __restrict__ v, int check, int* flags) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// 8 lanes per row, taking its entries in turn.
+__global__ __launch_bounds__(256) void k_validate_sym(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      const double* __restrict__ v, int check, int* flags) {
+  const int i = blockIdx.x * 32 + (int)threadIdx.x / 8, q0 = (int)threadIdx.x % 8;
   if (i >= n) return;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+  for (int k = rp[i] + q0; k < rp[i + 1]; k += 8) {
     const int j = ci[k];
     if (j == i) continue;
     const int q = find_in_row(rp, ci, j, i);
@@ -1581,25 +1582,44 @@ __global__ void k_sell_width(int nsl, const int* __restrict__ srow, const int* _
   w64[sl] = 64 * w;
 }
 
+// One wavefront per slice.  The slice's rows are consecutive in the
+// (colour-ordered) CSR, so their entries are one contiguous range: it is
+// staged through shared memory with contiguous loads when it has at most
+// SF_CAP entries, and each lane then scans its row there.
+constexpr int SF_CAP = 512;
 __global__ __launch_bounds__(256) void k_sell_fill(int nsl, const int* __restrict__ srow, const int* __restrict__ soff,
                                                    const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const double* __restrict__ v, int* __restrict__ scol,
                                                    double* __restrict__ sval, double* __restrict__ dg) {
-  const int sl = blockIdx.x * 4 + threadIdx.x / WAVE;
+  __shared__ int sc[4][SF_CAP];
+  __shared__ double sv[4][SF_CAP];
+  const int wv = (int)threadIdx.x / WAVE;
+  const int sl = blockIdx.x * 4 + wv;
   if (sl >= nsl) return;
   const int lane = __lane_id();
-  const int r0 = srow[sl], r = r0 + lane;
-  const bool valid = r < srow[sl + 1];
+  const int r0 = srow[sl], r1 = srow[sl + 1], r = r0 + lane;
+  const bool valid = r < r1;
   const int base = soff[sl], w = (soff[sl + 1] - base) / 64;
+  const int e0 = rp[r0], ne = rp[r1] - e0;
+  const bool staged = ne <= SF_CAP;
+  if (staged) {
+    for (int k = lane; k < ne; k += WAVE) {
+      sc[wv][k] = ci[e0 + k];
+      sv[wv][k] = v[e0 + k];
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+  }
   int k = 0;
   if (valid) {
     for (int q = rp[r]; q < rp[r + 1]; ++q) {
-      const int j = ci[q];
+      const int j = staged ? sc[wv][q - e0] : ci[q];
+      const double a = staged ? sv[wv][q - e0] : v[q];
       if (j == r) {
-        dg[r] = v[q];
+        dg[r] = a;
       } else {
         scol[base + 64 * k + lane] = j;
-        sval[base + 64 * k + lane] = v[q];
+        sval[base + 64 * k + lane] = a;
         ++k;
       }
     }
@@ -1637,7 +1657,7 @@ int validate_csr(int n, int nnz, const int* rp, const int* ci, const double* v, 
   AMG_HIP(hipGetLastError());
   int flags = read1(f.as<int>(), s);
   if (flags) return flags;
-  hipLaunchKernelGGL(k_validate_sym, dim3(cdiv(n, 256)), dim3(256), 0, s, n, rp, ci, v, check_symmetry, f.as<int>());
+  hipLaunchKernelGGL(k_validate_sym, dim3(cdiv(n, 32)), dim3(256), 0, s, n, rp, ci, v, check_symmetry, f.as<int>());
   AMG_HIP(hipGetLastError());
   return read1(f.as<int>(), s);
 }
