@@ -176,16 +176,23 @@ def test_precond_after_solve_matches_fresh(A):
         assert torch.equal(z1, z2)
 
 
-@pytest.mark.parametrize("fp32", [1, 0])
-def test_tail_bit_identical(A, fp32):
+@pytest.mark.parametrize("fp32,pre,post,smoother", [(1, 1, 1, 0), (0, 1, 1, 0), (1, 2, 2, 0), (1, 0, 1, 0),
+                                                    (1, 1, 0, 0), (1, 1, 1, 1)])
+def test_tail_bit_identical(A, fp32, pre, post, smoother):
     """Levels cycled by one workgroup per entry (tail_rows: below that many
     rows; the coarsest solve stays a many-block launch) give the same bits as
     one launch per step: single solves, preconditioner applications, and
-    batches with four right-hand sides per system."""
+    batches with four right-hand sides per system.  The tail fills, forms the
+    residual and prolongs every row, so this also checks the launch path's
+    shortcuts (colour-0 rows skipped, residual from the last pre-smoothing
+    pass) for several sweep counts and both smoothers."""
     d = dev(systems(4, seed=5))
     ref = None
+    kw = dict(vcycle_fp32=fp32, pre_sweeps=pre, post_sweeps=post, smoother=smoother)
+    if pre + post == 0 or (fp32 == 0 and smoother == 1):
+        pytest.skip("not a symmetric positive definite preconditioner")
     for tail in (0, 600, 1 << 30):
-        hs = [A.Hierarchy(rp, ci, v, vcycle_fp32=fp32, tail_rows=tail) for rp, ci, v, _ in d]
+        hs = [A.Hierarchy(rp, ci, v, tail_rows=tail, **kw) for rp, ci, v, _ in d]
         try:
             out = []
             for h, (*_, B) in zip(hs, d):
