@@ -83,7 +83,9 @@ typedef struct amg_params {
   uint32_t colour_seed;      /* seed of the colouring priorities               [0]    */
   int32_t check_symmetry;    /* 1: reject A with a_ij != a_ji                  [1]    */
   int32_t keep_setup_data;   /* 1: keep strong/isolated flags for amg_copy_level [0]  */
-  int32_t use_graphs;        /* 1: pcg_solve replays each iteration as a HIP graph [1] */
+  int32_t use_graphs;        /* 1: pcg_solve replays each iteration as a HIP   [1]
+                                graph (systems below 1.5M rows x right-hand sides;
+                                larger ones launch directly, which is as fast) */
   int32_t tail_rows;         /* levels with at most this many rows (and all    [0]
                                 coarser ones) are cycled by one workgroup per solve */
   int32_t colour_tile_rows;  /* rows per tile of the colouring order (64..1024) [128] */
@@ -126,8 +128,9 @@ AMG_API amg_status amg_precond_apply(amg_hierarchy *h, const double *r, double *
  * iterations (then AMG_ERR_NOT_CONVERGED with x = last iterate and *info
  * filled).  Blocks until done.  The iterations run on a stream owned by the
  * hierarchy's solve context (created on first use), ordered after the
- * caller's earlier work on `stream`; with use_graphs each iteration from the
- * second on is one replay of a captured HIP graph.  Calls on one hierarchy
+ * caller's earlier work on `stream`; with use_graphs (and below 1.5M rows)
+ * each iteration from the second on is one replay of a captured HIP graph.
+ * Calls on one hierarchy
  * (pcg_solve, amg_precond_apply) must not overlap.
  *   info      host, nullable
  *   res_hist  host, nullable, maxit+1 doubles: ||r_k||/||r_0||

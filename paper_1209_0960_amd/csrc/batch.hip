@@ -792,9 +792,15 @@ void upload_plan(Plan& P, Builder& b, hipStream_t s) {
     AMG_HIP(hipMemcpyAsync(P.tab_d, b.items.data(), b.items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
 }
 
+// Plans over at least this many rows x right-hand sides are launched
+// directly: their kernels outlast the host's launch calls, so a graph only
+// adds its capture and instantiation (measured on lognormal systems: graphs
+// 9% faster at 96^3, launches 5% faster at 128^3 and equal at 256^3).
+constexpr double GRAPH_MAX_ROWS = 1.5e6;
+
 void run_plan(Batch& B, Plan& P, hipStream_t s, bool graph) {
   flush(B, s);
-  if (!graph || !B.use_graphs || g_timing_mask_for_graphs() != 0) {
+  if (!graph || !B.use_graphs || g_timing_mask_for_graphs() != 0 || P.rows * B.R >= GRAPH_MAX_ROWS) {
     issue_launches(P.L, 0, P.L.size(), P.tab_d, B.desc_d, B.desc_h, B.R, B.fp32, s);
     return;
   }
