@@ -7,6 +7,7 @@
 // the strength test is rounded once.
 #include <algorithm>
 #include <climits>
+#include <initializer_list>
 
 #include "amg_internal.h"
 
@@ -1638,6 +1639,12 @@ T read1(const T* dptr, hipStream_t s) {
   return v;
 }
 
+// Several device ints with one host round trip.
+void read_ints(hipStream_t s, std::initializer_list<std::pair<int*, const int*>> dst_src) {
+  for (const auto& d : dst_src) AMG_HIP(hipMemcpyAsync(d.first, d.second, sizeof(int), hipMemcpyDeviceToHost, s));
+  sync_stream(s);
+}
+
 }  // namespace
 
 // ================================================================== host side
@@ -1719,8 +1726,8 @@ void galerkin(Hierarchy& H, const Level& L, Level& C, hipStream_t s) {
                      tcount.as<int>(), mx.as<int>());
   DBuf toff((size_t)(nc + 1) * sizeof(int), s);
   exclusive_scan(tcount.as<int>(), toff.as<int>(), nc, s);
-  const int maxm = read1(mx.as<int>(), s);
-  const int total = read1(toff.as<int>() + nc, s);
+  int maxm = 0, total = 0;
+  read_ints(s, {{&maxm, mx.as<int>()}, {&total, toff.as<int>() + nc}});
   if (total != L.nnz) fail(AMG_ERR_HIP, "Galerkin term count mismatch");
   DBuf tcol((size_t)total * sizeof(int), s), tval((size_t)total * sizeof(double), s),
       ucount((size_t)nc * sizeof(int), s);
@@ -1759,16 +1766,18 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   hipLaunchKernelGGL(k_tile_nbrs, dim3(ntiles), dim3(WAVE), 0, s, n, T, L.rowptr, L.colind, seed, nullptr, nullptr,
                      tcnt.as<int>(), pend.as<int>(), cnt.as<int>());
   exclusive_scan(tcnt.as<int>(), tptr.as<int>(), ntiles, s);
-  const int nadj = read1(tptr.as<int>() + ntiles, s);
+  DBuf mx(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_tile_nnz_max, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, n, T, ntiles, L.rowptr, mx.as<int>());
+  // neighbour-tile entries, the hash-set overflow flag of the counting pass
+  // (the listing pass hashes the same keys) and the largest tile's entries
+  int nadj = 0, overflow = 0, Ecap = 0;
+  read_ints(s, {{&nadj, tptr.as<int>() + ntiles}, {&overflow, cnt.as<int>()}, {&Ecap, mx.as<int>()}});
+  if (overflow) fail(AMG_ERR_UNSUPPORTED, "a tile has more than 2048 neighbour tiles");
   DBuf tadj((size_t)std::max(nadj, 1) * sizeof(int), s);
   hipLaunchKernelGGL(k_tile_nbrs, dim3(ntiles), dim3(WAVE), 0, s, n, T, L.rowptr, L.colind, seed, tptr.as<int>(),
                      tadj.as<int>(), nullptr, nullptr, cnt.as<int>());
   AMG_HIP(hipGetLastError());
-  if (read1(cnt.as<int>(), s)) fail(AMG_ERR_UNSUPPORTED, "a tile has more than 2048 neighbour tiles");
-  DBuf mx(sizeof(int), s);
-  AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_tile_nnz_max, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, n, T, ntiles, L.rowptr, mx.as<int>());
-  const int Ecap = read1(mx.as<int>(), s);
   const size_t shm = col_smem(T, Ecap);
   if (shm > 160 * 1024) fail(AMG_ERR_UNSUPPORTED, "colouring tile exceeds LDS; use smaller tile_rows");
   AMG_HIP(hipFuncSetAttribute((const void*)k_colour_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
