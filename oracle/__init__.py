@@ -92,6 +92,13 @@ def lib():
         L.orc_pcg.restype = C.c_int
         L.orc_pcg.argtypes = [C.c_void_p, F64P, F64P, C.c_double, C.c_int, C.POINTER(C.c_int), C.c_void_p,
                               C.c_void_p, C.POINTER(C.c_double)]
+        L.orc_bicgstab.restype = C.c_int
+        L.orc_bicgstab.argtypes = [C.c_void_p, F64P, F64P, C.c_double, C.c_int, C.POINTER(C.c_int),
+                                   C.POINTER(C.c_int), C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+        L.orc_bicgstab_plain.restype = C.c_int
+        L.orc_bicgstab_plain.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, F64P, F64P, C.c_double, C.c_int,
+                                         C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_double)]
         _LIB = L
     return _LIB
 
@@ -273,3 +280,36 @@ class Hierarchy:
         if hist is not None:
             out["iterates"] = hist[:(k + 1) * n].reshape(k + 1, n)
         return out
+
+    def bicgstab(self, b, x0=None, rtol=1e-8, maxit=1000, keep_iterates=False):
+        """BiCGSTAB preconditioned by one V-cycle (Sec. 5); see _bicgstab_result."""
+        def call(x, res, hist, it, half, tr):
+            return lib().orc_bicgstab(self._h, np.ascontiguousarray(b, np.float64), x, rtol, maxit, C.byref(it),
+                                      C.byref(half), res, hist, C.byref(tr))
+        return _bicgstab_result(call, self.n, x0, maxit, keep_iterates)
+
+
+def _bicgstab_result(call, n, x0, maxit, keep_iterates):
+    """Runs an oracle BiCGSTAB; iterations k stopped in (half = 1: at the half
+    step, x = x_{k-1} + alpha M p), res_hist[0..k], iterates x_0..x_k."""
+    x = np.zeros(n) if x0 is None else np.array(x0, np.float64)
+    res = np.zeros(maxit + 1, np.float64)
+    hist = np.zeros((maxit + 1) * n, np.float64) if keep_iterates else None
+    it, half, tr = C.c_int(0), C.c_int(0), C.c_double(0.0)
+    st = call(x, res.ctypes.data, None if hist is None else hist.ctypes.data, it, half, tr)
+    k = it.value
+    out = dict(status=st, x=x, iterations=k, half=half.value, res_hist=res[:k + 1], true_rel_residual=tr.value)
+    if hist is not None:
+        out["iterates"] = hist[:(k + 1) * n].reshape(k + 1, n)
+    return out
+
+
+def bicgstab_plain(rowptr, colind, vals, b, x0=None, rtol=1e-8, maxit=1000, keep_iterates=False):
+    """Unpreconditioned BiCGSTAB on any square CSR matrix (the iteration alone)."""
+    rp, ci, v = _csr(rowptr, colind, vals)
+    n = rp.shape[0] - 1
+
+    def call(x, res, hist, it, half, tr):
+        return lib().orc_bicgstab_plain(n, ci.shape[0], rp, ci, v, np.ascontiguousarray(b, np.float64), x, rtol,
+                                        maxit, C.byref(it), C.byref(half), res, hist, C.byref(tr))
+    return _bicgstab_result(call, n, x0, maxit, keep_iterates)

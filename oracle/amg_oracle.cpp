@@ -1,4 +1,5 @@
 // Plain, slow CPU oracle of the non-smoothed aggregation AMG preconditioned CG
+// and BiCGSTAB
 // (Blatt, Ippisch, Bastian: "A Massively Parallel Algebraic Multigrid
 // Preconditioner based on Aggregation for Elliptic Problems with
 // Heterogeneous Coefficients").
@@ -1026,6 +1027,114 @@ int orc_pcg(void* h, const double* b, double* x, double rtol, int maxit, int* it
     rho = rz;
   }
   return finish(ORC_NOT_CONVERGED);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Preconditioned BiCGSTAB (van der Vorst, SIAM J. Sci. Stat. Comput. 13, 1992),
+// the outer solver of the paper's experiments (Sec. 5; it applies the
+// preconditioner twice per iteration).  Right preconditioning: M is applied to
+// the search directions p and s, so r stays the residual b - A x of the
+// iterate and the stopping test ||r||^2 <= (rtol ||r_0||)^2 is on it.  The
+// test is made twice per iteration, on s (x then holds x + alpha M p) and on
+// r.  res_hist[k] and iter_hist[k] hold the residual norm ratio and the
+// iterate where iteration k stopped (at s for a half-step exit; *half = 1).
+// Breakdown: r~.v = 0, t.t = 0, omega = 0, or r~.r = 0 before convergence,
+// or any of them not finite.  Parity pins: iterates equal to those of a
+// library BiCGSTAB with the same preconditioner; exact preconditioner ->
+// convergence at the first half step; recurrence residual equal to the
+// residual of the iterate; a hand-built breakdown.
+template <typename Prec>
+int bicgstab(const Csr& A, const Prec& M, const double* b, double* x, double rtol, int maxit, int* iters,
+             int* half, double* res_hist, double* iter_hist, double* true_rel) {
+  const int n = A.n;
+  std::vector<double> r(n), rt(n), p(n), ph(n), v(n), s(n), sh(n), t(n), d(n);
+  spmv(A, x, t.data());
+  for (int i = 0; i < n; ++i) r[i] = b[i] - t[i];
+  const double rr0 = dot(n, r.data(), r.data());
+  const double r0 = std::sqrt(rr0);
+  const double tol2 = (rtol * r0) * (rtol * r0);
+  if (res_hist) res_hist[0] = 1.0;
+  if (iter_hist) std::memcpy(iter_hist, x, sizeof(double) * n);
+  *iters = 0;
+  *half = 0;
+  auto finish = [&](int st) {
+    spmv(A, x, t.data());
+    for (int i = 0; i < n; ++i) d[i] = b[i] - t[i];
+    const double bn = std::sqrt(dot(n, b, b));
+    *true_rel = bn > 0.0 ? std::sqrt(dot(n, d.data(), d.data())) / bn : 0.0;
+    return st;
+  };
+  auto record = [&](int k, double nrm2) {
+    *iters = k;
+    if (res_hist) res_hist[k] = std::sqrt(nrm2) / r0;
+    if (iter_hist) std::memcpy(iter_hist + (size_t)k * n, x, sizeof(double) * n);
+  };
+  if (r0 == 0.0) return finish(ORC_OK);
+  rt = r;  // shadow residual r~ = r_0
+  p = r;
+  double rho = rr0;  // r~ . r_0
+  for (int k = 1; k <= maxit; ++k) {
+    M(p.data(), ph.data());
+    spmv(A, ph.data(), v.data());
+    const double rv = dot(n, rt.data(), v.data());
+    if (!(rv != 0.0) || !std::isfinite(rv)) return finish(ORC_BREAKDOWN);
+    const double alpha = rho / rv;
+    for (int i = 0; i < n; ++i) {
+      s[i] = r[i] - alpha * v[i];
+      x[i] = x[i] + alpha * ph[i];
+    }
+    const double ss = dot(n, s.data(), s.data());
+    if (ss <= tol2) {
+      *half = 1;
+      record(k, ss);
+      return finish(ORC_OK);
+    }
+    M(s.data(), sh.data());
+    spmv(A, sh.data(), t.data());
+    const double ts = dot(n, t.data(), s.data());
+    const double tt = dot(n, t.data(), t.data());
+    if (!(tt > 0.0) || !std::isfinite(tt)) return finish(ORC_BREAKDOWN);
+    const double omega = ts / tt;
+    if (!(omega != 0.0) || !std::isfinite(omega)) return finish(ORC_BREAKDOWN);
+    for (int i = 0; i < n; ++i) {
+      x[i] = x[i] + omega * sh[i];
+      r[i] = s[i] - omega * t[i];
+    }
+    const double rr = dot(n, r.data(), r.data());
+    record(k, rr);
+    if (rr <= tol2) return finish(ORC_OK);
+    const double rho_new = dot(n, rt.data(), r.data());
+    if (!(rho_new != 0.0) || !std::isfinite(rho_new)) return finish(ORC_BREAKDOWN);
+    const double beta = (rho_new / rho) * (alpha / omega);
+    for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+    rho = rho_new;
+  }
+  return finish(ORC_NOT_CONVERGED);
+}
+
+}  // namespace
+
+extern "C" {
+
+// BiCGSTAB preconditioned by one V-cycle of hierarchy h (x0 given in x).
+int orc_bicgstab(void* h, const double* b, double* x, double rtol, int maxit, int* iters, int* half,
+                 double* res_hist, double* iter_hist, double* true_rel) {
+  const Hier& H = *(const Hier*)h;
+  auto M = [&](const double* in, double* out) { precond(H, in, out); };
+  return bicgstab(H.lev[0].A, M, b, x, rtol, maxit, iters, half, res_hist, iter_hist, true_rel);
+}
+
+// Unpreconditioned BiCGSTAB (M = I) on any CSR matrix (square, not
+// necessarily symmetric), for the checks of the iteration itself.
+int orc_bicgstab_plain(int n, int nnz, const int* ptr, const int* col, const double* val, const double* b,
+                       double* x, double rtol, int maxit, int* iters, int* half, double* res_hist,
+                       double* iter_hist, double* true_rel) {
+  const Csr A = make_csr(n, nnz, ptr, col, val);
+  auto M = [&](const double* in, double* out) { std::memcpy(out, in, sizeof(double) * A.n); };
+  return bicgstab(A, M, b, x, rtol, maxit, iters, half, res_hist, iter_hist, true_rel);
 }
 
 }  // extern "C"

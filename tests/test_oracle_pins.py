@@ -535,3 +535,92 @@ def test_fcg_directions_stay_conjugate_with_asymmetric_cycle():
 
     assert conj(1) <= 1e-8
     assert conj(0) >= 1e-3
+
+
+# ----------------------------------------------------------------- BiCGSTAB (Sec. 5)
+def _scipy_bicgstab_iterates(A, b, M, k):
+    """x_1..x_k of scipy's BiCGSTAB (the same van der Vorst recurrences)."""
+    import scipy.sparse.linalg as sla_
+
+    xs = []
+    sla_.bicgstab(A, b, x0=np.zeros(b.shape[0]), rtol=0.0, atol=0.0, maxiter=k, M=M,
+                  callback=lambda x: xs.append(x.copy()))
+    return np.array(xs)
+
+
+def test_bicgstab_iterates_match_library_with_vcycle():
+    """Oracle BiCGSTAB preconditioned by its own V-cycle: every iterate equals
+    the library BiCGSTAB's with the V-cycle as its preconditioner."""
+    import scipy.sparse.linalg as sla_
+
+    s = P.lognormal(12, seed=6)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60)
+    assert H.levels >= 2
+    A = sp.csr_matrix((s.vals, s.colind, s.rowptr), shape=(s.n, s.n))
+    M = sla_.LinearOperator((s.n, s.n), matvec=lambda r: H.vcycle(np.ravel(r)))
+    k = 4
+    out = H.bicgstab(s.b, rtol=1e-14, maxit=k, keep_iterates=True)
+    assert out["status"] == O.NOT_CONVERGED and out["iterations"] == k and out["half"] == 0
+    ref = _scipy_bicgstab_iterates(A, s.b, M, k)
+    scale = np.abs(ref[-1]).max()
+    assert np.abs(out["iterates"][1:] - ref).max() <= 1e-10 * scale
+
+
+def test_bicgstab_plain_iterates_match_library_nonsymmetric():
+    """M = I on a non-symmetric convection-diffusion matrix (upwind), where
+    BiCGSTAB differs from CG: iterates equal the library's."""
+    n = 40
+    main = np.full(n, 2.5)
+    A = sp.diags([main, np.full(n - 1, -1.5), np.full(n - 1, -0.5)], [0, -1, 1], format="csr")
+    A.sort_indices()
+    b = np.random.default_rng(3).uniform(-1, 1, n)
+    k = 6
+    out = O.bicgstab_plain(A.indptr, A.indices, A.data, b, rtol=1e-15, maxit=k, keep_iterates=True)
+    assert out["iterations"] == k
+    ref = _scipy_bicgstab_iterates(A, b, None, k)
+    assert np.abs(out["iterates"][1:] - ref).max() <= 1e-10 * np.abs(ref[-1]).max()
+
+
+def test_bicgstab_exact_preconditioner_stops_at_first_half_step():
+    """One-level hierarchy: M = A^-1, so M p = A^-1 r_0, v = r_0, alpha = 1,
+    s = 0 and x = A^-1 b after the first half step."""
+    s = P.lognormal(6, seed=4)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals)
+    assert H.levels == 1
+    out = H.bicgstab(s.b, rtol=1e-10)
+    assert out["status"] == O.OK and out["iterations"] == 1 and out["half"] == 1
+    A = dense(s.rowptr, s.colind, s.vals)
+    assert np.abs(A @ out["x"] - s.b).max() <= 1e-12 * np.abs(s.b).max()
+
+
+def test_bicgstab_recurrence_residual_is_true_residual():
+    """The recurrences keep r_k = b - A x_k: the recorded residual history
+    equals the residual norms of the recorded iterates; the solve meets rtol."""
+    s = P.lognormal(12, seed=8)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60)
+    out = H.bicgstab(s.b, rtol=1e-8, keep_iterates=True)
+    assert out["status"] == O.OK
+    A = sp.csr_matrix((s.vals, s.colind, s.rowptr), shape=(s.n, s.n))
+    r0 = np.linalg.norm(s.b)
+    true = np.array([np.linalg.norm(s.b - A @ x) / r0 for x in out["iterates"]])
+    assert np.abs(true - out["res_hist"]).max() <= 1e-9
+    assert out["res_hist"][-1] <= 1e-8 and out["res_hist"][:-1].min() > 1e-8
+    assert out["true_rel_residual"] <= 1.01e-8
+    x = np.linalg.solve(dense(s.rowptr, s.colind, s.vals), s.b)
+    kappa = np.linalg.cond(dense(s.rowptr, s.colind, s.vals))
+    assert np.linalg.norm(out["x"] - x) / np.linalg.norm(x) <= kappa * 1e-8
+
+
+def test_bicgstab_breakdown_and_trivial_cases():
+    """r~.v = 0 at the first step (A = [[0,1],[1,0]], b = e_0, M = I) is a
+    breakdown that keeps x_0; b = 0 converges at once; maxit = 0 does not."""
+    A = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 0.0]]))
+    out = O.bicgstab_plain(A.indptr, A.indices, A.data, np.array([1.0, 0.0]))
+    assert out["status"] == O.BREAKDOWN and out["iterations"] == 0
+    assert np.array_equal(out["x"], np.zeros(2))
+    s = P.poisson(4)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals)
+    z = H.bicgstab(np.zeros(s.n))
+    assert z["status"] == O.OK and z["iterations"] == 0 and not z["x"].any()
+    m = H.bicgstab(s.b, maxit=0)
+    assert m["status"] == O.NOT_CONVERGED and m["iterations"] == 0
