@@ -131,12 +131,29 @@ AMG_API amg_status amg_precond_apply(amg_hierarchy *h, const double *r, double *
  * caller's earlier work on `stream`; with use_graphs (and below 1.5M rows)
  * each iteration from the second on is one replay of a captured HIP graph.
  * Calls on one hierarchy
- * (pcg_solve, amg_precond_apply) must not overlap.
+ * (pcg_solve, bicgstab_solve, amg_precond_apply) must not overlap.
  *   info      host, nullable
  *   res_hist  host, nullable, maxit+1 doubles: ||r_k||/||r_0||
  *   iter_hist device, nullable, n*(maxit+1) doubles: x_k for k = 0.. */
 AMG_API amg_status pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
                      amg_solve_info *info, double *res_hist, double *iter_hist, void *stream);
+
+/* BiCGSTAB (van der Vorst 1992), the outer solver of the paper's experiments
+ * (Sec. 5, which applies the preconditioner twice per iteration), right-
+ * preconditioned by one V-cycle of h for each of the two directions p and s.
+ * x holds x0 on entry and the solution on return.  Vectors, errors, streams
+ * and blocking as in pcg_solve (one iteration per host round trip; no graph).
+ * The stop test ||.||_2^2 <= (rtol ||r_0||_2)^2 is made on s (half step: x =
+ * x_{k-1} + alpha M p, *half_step = 1) and on r_k; info->iterations is the
+ * iteration k it stopped in.  AMG_ERR_BREAKDOWN when r~.v, t.t, omega or r~.r
+ * is zero or not finite before convergence (x = the iterate at that point).
+ *   half_step host, nullable
+ *   res_hist  host, nullable, maxit+1 doubles: ||r_k||/||r_0|| (||s_k||/||r_0||
+ *             for a half-step exit)
+ *   iter_hist device, nullable, n*(maxit+1) doubles: x_k for k = 0.. */
+AMG_API amg_status bicgstab_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+                                  amg_solve_info *info, int32_t *half_step, double *res_hist, double *iter_hist,
+                                  void *stream);
 
 /* Releases everything the hierarchy owns.  NULL-safe.  The hierarchy must not
  * be part of a running batch entry (amg_batch_submit). */

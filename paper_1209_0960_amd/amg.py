@@ -79,6 +79,9 @@ def lib():
         L.amg_precond_apply.argtypes = [vp, vp, vp, vp]
         L.pcg_solve.restype = st
         L.pcg_solve.argtypes = [vp, vp, vp, C.c_double, i32, C.POINTER(SolveInfo), vp, vp, vp]
+        L.bicgstab_solve.restype = st
+        L.bicgstab_solve.argtypes = [vp, vp, vp, C.c_double, i32, C.POINTER(SolveInfo), C.POINTER(i32), vp, vp,
+                                     vp]
         L.amg_free.restype = None
         L.amg_free.argtypes = [vp]
         L.amg_status_string.restype = C.c_char_p
@@ -282,6 +285,7 @@ class SolveResult:
     setup_ms: float
     solve_ms: float
     res_hist: np.ndarray
+    half_step: int = 0  # BiCGSTAB: stopped at the half step of the last iteration
 
 
 def pcg_solve(h, b: torch.Tensor, x: torch.Tensor, rtol: float = 1e-8, maxit: int = 1000,
@@ -296,6 +300,21 @@ def pcg_solve(h, b: torch.Tensor, x: torch.Tensor, rtol: float = 1e-8, maxit: in
     k = info.iterations
     return SolveResult(st, k, bool(info.converged), info.levels, info.rel_residual, info.true_rel_residual,
                        info.setup_ms, info.solve_ms, res[:k + 1].copy())
+
+
+def bicgstab_solve(h, b: torch.Tensor, x: torch.Tensor, rtol: float = 1e-8, maxit: int = 1000,
+                   iter_hist: torch.Tensor | None = None, stream=None, raise_on_error: bool = True):
+    """bicgstab_solve: x holds x0 on entry and the solution on return."""
+    info = SolveInfo()
+    half = C.c_int32(0)
+    res = np.zeros(maxit + 1, np.float64)
+    st = lib().bicgstab_solve(h, _ptr(b), _ptr(x), rtol, maxit, C.byref(info), C.byref(half),
+                              res.ctypes.data_as(C.c_void_p), _ptr(iter_hist), _stream(stream))
+    if st not in (OK, ERR_NOT_CONVERGED) and raise_on_error:
+        _check(st)
+    k = info.iterations
+    return SolveResult(st, k, bool(info.converged), info.levels, info.rel_residual, info.true_rel_residual,
+                       info.setup_ms, info.solve_ms, res[:k + 1].copy(), half.value)
 
 
 def amg_free(h):
@@ -414,9 +433,14 @@ class Hierarchy:
         return z
 
     def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, rtol=1e-8, maxit=1000, iter_hist=None,
-              stream=None, raise_on_error=True) -> tuple:
+              stream=None, raise_on_error=True, method="cg") -> tuple:
+        """method "cg": pcg_solve; "bicgstab": bicgstab_solve."""
         if x is None:
             x = torch.zeros_like(b)
+        if method == "bicgstab":
+            return x, bicgstab_solve(self.h, b, x, rtol, maxit, iter_hist, stream, raise_on_error)
+        if method != "cg":
+            raise ValueError(f"unknown method {method!r}")
         r = pcg_solve(self.h, b, x, rtol, maxit, iter_hist, stream, raise_on_error)
         return x, r
 

@@ -490,6 +490,19 @@ amg_status pcg_solve(amg_hierarchy* h, const double* b, double* x, double rtol, 
   return g != AMG_OK ? g : st;
 }
 
+amg_status bicgstab_solve(amg_hierarchy* h, const double* b, double* x, double rtol, int32_t maxit,
+                          amg_solve_info* info, int32_t* half_step, double* res_hist, double* iter_hist,
+                          void* stream) {
+  if (!h || !b || !x || maxit < 0 || !(rtol >= 0.0)) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  amg_status st = AMG_OK;
+  amg_status g = guarded(
+      [&] { st = bicgstab_run(h->H, b, x, rtol, maxit, info, half_step, res_hist, iter_hist, S(stream)); });
+  return g != AMG_OK ? g : st;
+}
+
 void amg_free(amg_hierarchy* h) {
   if (!h) return;
   hipStream_t s = h->H.setup_stream;

@@ -187,6 +187,24 @@ enum {
   S_COUNT = 16
 };
 
+// Scalars of a BiCGSTAB solve (device, one right-hand side).
+enum {
+  BS_RHO = 0,  // r~.r of the current direction
+  BS_ALPHA,
+  BS_OMEGA,
+  BS_BETA,
+  BS_SS,       // s.s of the half step
+  BS_RR,       // r.r after the update
+  BS_RR0,      // r_0.r_0
+  BS_FLAG,     // 1.0 = breakdown: updates stop
+  BS_HALF,     // 1.0 = converged at the half step (x = x + alpha M p): updates stop
+  BS_TMP,      // ||b - A x||^2 at the end
+  BS_TMP2,     // ||b||^2 at the end
+  BS_COUNT = 16
+};
+// Finish operations of the BiCGSTAB reductions (kk_bcg_finish).
+enum { BF_INIT = 0, BF_ALPHA, BF_S, BF_OMEGA, BF_BETA, BF_TRUE, BF_BB };
+
 constexpr int RED_BLOCKS = 8192;  // upper bound on the partial sums of one dot product
 constexpr int RED_THREADS = 256;
 constexpr int MAX_LEVELS = 32;
@@ -305,11 +323,34 @@ void issue_launches(const std::vector<Launch>& L, size_t first, size_t last, con
 void gather_rhs(int n, int R, const int* perm, const double* in, double* out, hipStream_t s);
 void scatter_rhs(int n, int R, const int* perm, const double* in, double* out, hipStream_t s);
 
+// BiCGSTAB level-0 kernels (one right-hand side, FP64, solve order).  Each
+// reduction leaves two partial sums per block in part[2 * block + {0, 1}];
+// bcg_finish sums them in block order.  Returns the number of blocks.
+// y = A x, or y = c - A x (c non-NULL); partials (w.y, y.y), w nullable.
+// sub: lanes per CSR row; bytes: algorithmic bytes (kernel timing).
+int bcg_spmv(const BDesc& d0, int sub, const double* x, const double* c, double* y, const double* w, double* part,
+             double bytes, hipStream_t s);
+// s = r - alpha v, x += alpha ph; partials (0, s.s).
+int bcg_half(int n, const double* r, const double* v, const double* ph, double* x, double* sv, const double* sc,
+             double* part, hipStream_t s);
+// x += omega sh, r = s - omega t; partials (r~.r, r.r).
+int bcg_full(int n, const double* sv, const double* t, const double* sh, const double* rt, double* x, double* r,
+             const double* sc, double* part, hipStream_t s);
+// p = r + beta (p - omega v), also into pin; init: p = pin = rt = r.
+void bcg_dir(int n, const double* r, const double* v, double* p, double* pin, double* rt, const double* sc,
+             int init, hipStream_t s);
+// partials (0, u.u)
+int bcg_norm2(int n, const double* u, double* part, hipStream_t s);
+void bcg_finish(int op, int nb, const double* part, double* sc, double tol2, hipStream_t s);
+
 void batch_destroy(Batch* B);
 // pcg_solve / amg_precond_apply / pcg_solve_batched on the engine.
 amg_status pcg_run(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
                    double* res_hist, double* iter_hist, hipStream_t us);
 void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us);
+// bicgstab_solve (Sec. 5: BiCGSTAB with the V-cycle applied twice per iteration).
+amg_status bicgstab_run(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
+                        int* half_step, double* res_hist, double* iter_hist, hipStream_t us);
 amg_status pcg_batched_run(Hierarchy* const* hs, int nsys, int nrhs, const double* const* b, double* const* x,
                            double rtol, int maxit, amg_solve_info* info, hipStream_t us);
 // Continuous batching: entries are submitted and retired between steps.

@@ -1109,6 +1109,130 @@ void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us) {
   scatter_rhs(L0.n, 1, L0.perm, E.ctx.z, z, us);
 }
 
+// BiCGSTAB (van der Vorst; the outer solver of Sec. 5) with right
+// preconditioning by the V-cycle of the hierarchy's solve context, in FP64 on
+// level-0 vectors in solve order.  The preconditioner reads the context's r
+// and writes its z; the direction p and then s are written into r, the
+// products M p and M s are consumed from z before the next application.  The
+// scalars stay on the device (the finish kernels compute alpha, omega, beta
+// and the stop flags); the host reads them once per iteration.
+amg_status bicgstab_run(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
+                        int* half_step, double* res_hist, double* iter_hist, hipStream_t us) {
+  Batch& B = single_of(H);
+  hipStream_t s = B.work;
+  const double t0 = now_ms();
+  if (B.papply.L.empty()) {
+    Builder bl(B, true);
+    build_precond(bl, B, {0}, true);
+    upload_plan(B.papply, bl, s);
+  }
+  const Level& L0 = H.lev[0];
+  const int n = L0.n;
+  const Ctx& C = B.ent[0].ctx;
+  const BDesc d0 = B.desc_h[B.desc_index(0, 0)];
+  AMG_HIP(hipEventRecord(B.ev, us));
+  AMG_HIP(hipStreamWaitEvent(s, B.ev, 0));
+  flush(B, s);
+  // r, r~, p, v, t, the partial sums and the scalars
+  Carver sizing;
+  for (int k = 0; k < 5; ++k) sizing.take((size_t)n * sizeof(double));
+  sizing.take(2 * (size_t)RED_BLOCKS * sizeof(double));
+  sizing.take(BS_COUNT * sizeof(double));
+  struct Owned {
+    void* blk = nullptr;
+    double* host = nullptr;
+    hipStream_t s;
+    ~Owned() {
+      if (blk) dfree(blk, s);
+      pinned_give(host, BS_COUNT * sizeof(double));
+    }
+  } own;
+  own.s = s;
+  own.blk = dalloc(sizing.off, s);
+  own.host = static_cast<double*>(pinned_take(BS_COUNT * sizeof(double)));
+  Carver cv;
+  cv.base = static_cast<char*>(own.blk);
+  auto vec = [&] { return static_cast<double*>(cv.take((size_t)n * sizeof(double))); };
+  double *r = vec(), *rt = vec(), *p = vec(), *v = vec(), *t = vec();
+  double* part = static_cast<double*>(cv.take(2 * (size_t)RED_BLOCKS * sizeof(double)));
+  double* sc = static_cast<double*>(cv.take(BS_COUNT * sizeof(double)));
+  double* sh = own.host;
+  // algorithmic bytes of y = A x (+ c read, + w read)
+  const double mat = L0.scol ? (double)L0.soff_h[L0.nsl] * 12.0 + 8.0 * n : (double)L0.nnz * 12.0 + 4.0 * (n + 1);
+  auto spmv = [&](const double* xin, const double* c, double* y, const double* w) {
+    return bcg_spmv(d0, L0.sub, xin, c, y, w, part, mat + n * (16.0 + (c ? 8.0 : 0.0) + (w ? 8.0 : 0.0)), s);
+  };
+  auto precond = [&] { issue_launches(B.papply.L, 0, B.papply.L.size(), B.papply.tab_d, B.desc_d, B.desc_h, 1, B.fp32, s); };
+  auto read = [&] {
+    AMG_HIP(hipMemcpyAsync(sh, sc, BS_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    sync_stream(s);
+  };
+  gather_rhs(n, 1, L0.perm, b, C.bs, s);
+  gather_rhs(n, 1, L0.perm, x, C.xs, s);
+  if (iter_hist) scatter_rhs(n, 1, L0.perm, C.xs, iter_hist, s);
+  if (res_hist) res_hist[0] = 1.0;
+  int nb = spmv(C.xs, C.bs, r, nullptr);
+  bcg_finish(BF_INIT, nb, part, sc, 0.0, s);
+  bcg_dir(n, r, v, p, C.r, rt, sc, 1, s);
+  read();
+  const double r0 = std::sqrt(sh[BS_RR0]);
+  const double tol2 = (rtol * r0) * (rtol * r0);
+  amg_status st = AMG_ERR_NOT_CONVERGED;
+  int it = 0, half = 0;
+  double rel = r0 == 0.0 ? 0.0 : 1.0;
+  if (r0 == 0.0) st = AMG_OK;
+  for (int k = 1; st == AMG_ERR_NOT_CONVERGED && k <= maxit; ++k) {
+    precond();  // z = M p
+    nb = spmv(C.z, nullptr, v, rt);
+    bcg_finish(BF_ALPHA, nb, part, sc, tol2, s);
+    nb = bcg_half(n, r, v, C.z, C.xs, C.r, sc, part, s);
+    bcg_finish(BF_S, nb, part, sc, tol2, s);
+    precond();  // z = M s
+    nb = spmv(C.z, nullptr, t, C.r);
+    bcg_finish(BF_OMEGA, nb, part, sc, tol2, s);
+    nb = bcg_full(n, C.r, t, C.z, rt, C.xs, r, sc, part, s);
+    bcg_finish(BF_BETA, nb, part, sc, tol2, s);
+    bcg_dir(n, r, v, p, C.r, rt, sc, 0, s);
+    read();
+    if (sh[BS_FLAG] != 0.0) {
+      st = AMG_ERR_BREAKDOWN;
+      break;
+    }
+    it = k;
+    if (iter_hist) scatter_rhs(n, 1, L0.perm, C.xs, iter_hist + (size_t)k * n, s);
+    if (sh[BS_HALF] != 0.0) {
+      half = 1;
+      rel = std::sqrt(sh[BS_SS]) / r0;
+      st = AMG_OK;
+    } else {
+      rel = std::sqrt(sh[BS_RR]) / r0;
+      if (sh[BS_RR] <= tol2) st = AMG_OK;
+    }
+    if (res_hist) res_hist[k] = rel;
+  }
+  nb = spmv(C.xs, C.bs, t, nullptr);
+  bcg_finish(BF_TRUE, nb, part, sc, 0.0, s);
+  nb = bcg_norm2(n, C.bs, part, s);
+  bcg_finish(BF_BB, nb, part, sc, 0.0, s);
+  scatter_rhs(n, 1, L0.perm, C.xs, x, s);
+  read();
+  if (info) {
+    info->iterations = it;
+    info->converged = st == AMG_OK ? 1 : 0;
+    info->levels = (int)H.lev.size();
+    info->rel_residual = rel;
+    info->true_rel_residual = sh[BS_TMP2] > 0.0 ? std::sqrt(sh[BS_TMP]) / std::sqrt(sh[BS_TMP2]) : 0.0;
+    info->setup_ms = H.setup_ms;
+    info->solve_ms = now_ms() - t0;
+  }
+  if (half_step) *half_step = half;
+  AMG_HIP(hipEventRecord(B.ev, s));
+  AMG_HIP(hipStreamWaitEvent(us, B.ev, 0));
+  if (st == AMG_ERR_NOT_CONVERGED) set_error("maximum number of iterations reached");
+  if (st == AMG_ERR_BREAKDOWN) set_error("BiCGSTAB breakdown (r~.v, t.t, omega or r~.r zero or not finite)");
+  return st;
+}
+
 amg_status pcg_batched_run(Hierarchy* const* hs, int nsys, int nrhs, const double* const* b, double* const* x,
                            double rtol, int maxit, amg_solve_info* info, hipStream_t us) {
   Batch B;

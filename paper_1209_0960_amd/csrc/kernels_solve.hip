@@ -1005,6 +1005,250 @@ void issue_launches(const std::vector<Launch>& Ls, size_t first, size_t last, co
   AMG_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- BiCGSTAB
+// Level-0 kernels of the BiCGSTAB iteration (Sec. 5), one right-hand side in
+// FP64 and solve order.  A reduction splits its rows (or slices) into nb fixed
+// chunks, one per block, and leaves two partial sums per block; the finish
+// kernel adds them in block order, so results do not depend on scheduling.
+// The scalars (BS_*) stay on the device: a block reads them once, and an
+// update kernel does nothing after a breakdown or a half-step exit.
+namespace {
+
+__device__ inline void bcg_partials(double* part, double a0, double a1) {
+  double a[2] = {a0, a1};
+  block_sums<2>(a);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a[0];
+    part[2 * blockIdx.x + 1] = a[1];
+  }
+}
+
+// y = A x (SELL-64 slices [lo, lo + ch) of the block), or c - A x.
+__global__ __launch_bounds__(NT) void kk_spmv_sell(const BDesc d, int ch, const double* __restrict__ x,
+                                                   const double* __restrict__ c, double* __restrict__ y,
+                                                   const double* __restrict__ w, double* __restrict__ part) {
+  const int lo = (int)blockIdx.x * ch, hi = min(d.nsl, lo + ch);
+  const int lane = __lane_id();
+  double wy = 0.0, yy = 0.0;
+  for (int sl = lo + (int)(threadIdx.x / WAVE); sl < hi; sl += NT / WAVE) {
+    const int r = d.srow[sl] + lane;
+    const int base = d.soff[sl], wd = (d.soff[sl + 1] - base) >> 6;
+    double off[1];
+    sell_offdiag<double, 1>(d.scol, d.sval64, base, wd, lane, x, off);
+    if (r < d.srow[sl + 1]) {
+      double v = madd(d.dg64[r], x[r], off[0]);
+      if (c) v = c[r] - v;
+      y[r] = v;
+      if (w) wy = madd(w[r], v, wy);
+      yy = madd(v, v, yy);
+    }
+  }
+  bcg_partials(part, wy, yy);
+}
+
+// The same over CSR rows [lo, lo + ch), SUB lanes per row.
+template <int SUB>
+__global__ __launch_bounds__(NT) void kk_spmv_csr(const BDesc d, int ch, const double* __restrict__ x,
+                                                  const double* __restrict__ c, double* __restrict__ y,
+                                                  const double* __restrict__ w, double* __restrict__ part) {
+  const int lo = (int)blockIdx.x * ch, hi = min(d.n, lo + ch);
+  const int sl = threadIdx.x % SUB;
+  double wy = 0.0, yy = 0.0;
+  for (int i = lo + (int)threadIdx.x / SUB; i < hi; i += NT / SUB) {
+    double sum[1];
+    csr_row<1, SUB>(d, i, sl, x, sum);
+    if (sl == 0) {
+      const double v = c ? c[i] - sum[0] : sum[0];
+      y[i] = v;
+      if (w) wy = madd(w[i], v, wy);
+      yy = madd(v, v, yy);
+    }
+  }
+  bcg_partials(part, wy, yy);
+}
+
+__device__ inline bool bcg_stopped(const double* sc) { return sc[BS_FLAG] != 0.0 || sc[BS_HALF] != 0.0; }
+
+__global__ __launch_bounds__(NT) void kk_bcg_half(int n, int ch, const double* __restrict__ r,
+                                                  const double* __restrict__ v, const double* __restrict__ ph,
+                                                  double* __restrict__ x, double* __restrict__ sv,
+                                                  const double* __restrict__ sc, double* __restrict__ part) {
+  if (bcg_stopped(sc)) return;
+  const double alpha = sc[BS_ALPHA];
+  const int lo = (int)blockIdx.x * ch, hi = min(n, lo + ch);
+  double ss = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += NT) {
+    const double si = madd(-alpha, v[i], r[i]);
+    sv[i] = si;
+    x[i] = madd(alpha, ph[i], x[i]);
+    ss = madd(si, si, ss);
+  }
+  bcg_partials(part, 0.0, ss);
+}
+
+__global__ __launch_bounds__(NT) void kk_bcg_full(int n, int ch, const double* __restrict__ sv,
+                                                  const double* __restrict__ t, const double* __restrict__ sh,
+                                                  const double* __restrict__ rt, double* __restrict__ x,
+                                                  double* __restrict__ r, const double* __restrict__ sc,
+                                                  double* __restrict__ part) {
+  if (bcg_stopped(sc)) return;
+  const double omega = sc[BS_OMEGA];
+  const int lo = (int)blockIdx.x * ch, hi = min(n, lo + ch);
+  double tr = 0.0, rr = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += NT) {
+    x[i] = madd(omega, sh[i], x[i]);
+    const double ri = madd(-omega, t[i], sv[i]);
+    r[i] = ri;
+    tr = madd(rt[i], ri, tr);
+    rr = madd(ri, ri, rr);
+  }
+  bcg_partials(part, tr, rr);
+}
+
+__global__ __launch_bounds__(NT) void kk_bcg_dir(int n, const double* __restrict__ r, const double* __restrict__ v,
+                                                 double* __restrict__ p, double* __restrict__ pin,
+                                                 double* __restrict__ rt, const double* __restrict__ sc,
+                                                 int init) {
+  const int i = (int)blockIdx.x * NT + (int)threadIdx.x;
+  if (i >= n) return;
+  if (init) {
+    const double ri = r[i];
+    p[i] = ri;
+    pin[i] = ri;
+    rt[i] = ri;
+    return;
+  }
+  if (bcg_stopped(sc)) return;
+  const double pi = madd(sc[BS_BETA], madd(-sc[BS_OMEGA], v[i], p[i]), r[i]);
+  p[i] = pi;
+  pin[i] = pi;
+}
+
+__global__ __launch_bounds__(NT) void kk_norm2(int n, int ch, const double* __restrict__ u,
+                                               double* __restrict__ part) {
+  const int lo = (int)blockIdx.x * ch, hi = min(n, lo + ch);
+  double uu = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += NT) uu = madd(u[i], u[i], uu);
+  bcg_partials(part, 0.0, uu);
+}
+
+__device__ inline bool is_finite_d(double v) { return v - v == 0.0; }
+
+// One block: sums the partials in block order, then the scalar step of `op`.
+// Convergence is tested as in the oracle: ||.||^2 <= tol2 = (rtol ||r_0||)^2.
+__global__ __launch_bounds__(NT) void kk_bcg_finish(int op, int nb, const double* __restrict__ part,
+                                                    double* __restrict__ sc, double tol2) {
+  double a0 = 0.0, a1 = 0.0;
+  for (int i = (int)threadIdx.x; i < nb; i += NT) {
+    a0 += part[2 * i];
+    a1 += part[2 * i + 1];
+  }
+  double a[2] = {a0, a1};
+  block_sums<2>(a);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case BF_INIT:  // r_0 = b - A x_0; r~ = r_0, so rho = r_0.r_0
+      for (int k = 0; k < BS_COUNT; ++k) sc[k] = 0.0;
+      sc[BS_RR0] = sc[BS_RR] = sc[BS_RHO] = a[1];
+      break;
+    case BF_ALPHA:
+      if (bcg_stopped(sc)) break;
+      if (!(a[0] != 0.0) || !is_finite_d(a[0]))
+        sc[BS_FLAG] = 1.0;
+      else
+        sc[BS_ALPHA] = sc[BS_RHO] / a[0];
+      break;
+    case BF_S:
+      if (bcg_stopped(sc)) break;
+      sc[BS_SS] = a[1];
+      if (a[1] <= tol2) sc[BS_HALF] = 1.0;
+      break;
+    case BF_OMEGA: {
+      if (bcg_stopped(sc)) break;
+      const double om = a[0] / a[1];
+      if (!(a[1] > 0.0) || !is_finite_d(a[1]) || !(om != 0.0) || !is_finite_d(om))
+        sc[BS_FLAG] = 1.0;
+      else
+        sc[BS_OMEGA] = om;
+    } break;
+    case BF_BETA:
+      if (bcg_stopped(sc)) break;
+      sc[BS_RR] = a[1];
+      if (a[1] <= tol2) break;  // converged: the host stops
+      if (!(a[0] != 0.0) || !is_finite_d(a[0])) {
+        sc[BS_FLAG] = 1.0;
+      } else {
+        sc[BS_BETA] = (a[0] / sc[BS_RHO]) * (sc[BS_ALPHA] / sc[BS_OMEGA]);
+        sc[BS_RHO] = a[0];
+      }
+      break;
+    case BF_TRUE: sc[BS_TMP] = a[1]; break;
+    default: sc[BS_TMP2] = a[1]; break;
+  }
+}
+
+int bcg_row_blocks(int n) { return std::min(1024, std::max(1, cdiv(n, 2048))); }
+
+}  // namespace
+
+int bcg_spmv(const BDesc& d0, int sub, const double* x, const double* c, double* y, const double* w, double* part,
+             double bytes, hipStream_t s) {
+  int nb;
+  if (d0.scol) {
+    nb = std::min(RED_BLOCKS, std::max(1, cdiv(d0.nsl, 32)));
+    const int ch = cdiv(d0.nsl, nb);
+    KTimer tm(AMG_KIND_SPMV_F64, s, bytes);
+    hipLaunchKernelGGL(kk_spmv_sell, dim3(nb), dim3(NT), 0, s, d0, ch, x, c, y, w, part);
+  } else {
+    nb = bcg_row_blocks(d0.n);
+    const int ch = cdiv(d0.n, nb);
+    KTimer tm(AMG_KIND_SPMV_F64, s, bytes);
+    AMG_SUB_DISPATCH(sub, hipLaunchKernelGGL((kk_spmv_csr<SUB>), dim3(nb), dim3(NT), 0, s, d0, ch, x, c, y, w,
+                                                part));
+  }
+  AMG_HIP(hipGetLastError());
+  return nb;
+}
+
+int bcg_half(int n, const double* r, const double* v, const double* ph, double* x, double* sv, const double* sc,
+             double* part, hipStream_t s) {
+  const int nb = bcg_row_blocks(n);
+  KTimer tm(AMG_KIND_CG_VEC, s, 48.0 * n);
+  hipLaunchKernelGGL(kk_bcg_half, dim3(nb), dim3(NT), 0, s, n, cdiv(n, nb), r, v, ph, x, sv, sc, part);
+  AMG_HIP(hipGetLastError());
+  return nb;
+}
+
+int bcg_full(int n, const double* sv, const double* t, const double* sh, const double* rt, double* x, double* r,
+             const double* sc, double* part, hipStream_t s) {
+  const int nb = bcg_row_blocks(n);
+  KTimer tm(AMG_KIND_CG_VEC, s, 56.0 * n);
+  hipLaunchKernelGGL(kk_bcg_full, dim3(nb), dim3(NT), 0, s, n, cdiv(n, nb), sv, t, sh, rt, x, r, sc, part);
+  AMG_HIP(hipGetLastError());
+  return nb;
+}
+
+void bcg_dir(int n, const double* r, const double* v, double* p, double* pin, double* rt, const double* sc,
+             int init, hipStream_t s) {
+  KTimer tm(AMG_KIND_CG_VEC, s, init ? 32.0 * n : 40.0 * n);
+  hipLaunchKernelGGL(kk_bcg_dir, dim3(cdiv(n, NT)), dim3(NT), 0, s, n, r, v, p, pin, rt, sc, init);
+  AMG_HIP(hipGetLastError());
+}
+
+int bcg_norm2(int n, const double* u, double* part, hipStream_t s) {
+  const int nb = bcg_row_blocks(n);
+  KTimer tm(AMG_KIND_CG_VEC, s, 8.0 * n);
+  hipLaunchKernelGGL(kk_norm2, dim3(nb), dim3(NT), 0, s, n, cdiv(n, nb), u, part);
+  AMG_HIP(hipGetLastError());
+  return nb;
+}
+
+void bcg_finish(int op, int nb, const double* part, double* sc, double tol2, hipStream_t s) {
+  KTimer tm(AMG_KIND_CG_VEC, s, 16.0 * nb);
+  hipLaunchKernelGGL(kk_bcg_finish, dim3(1), dim3(NT), 0, s, op, nb, part, sc, tol2);
+  AMG_HIP(hipGetLastError());
+}
+
 void gather_rhs(int n, int R, const int* perm, const double* in, double* out, hipStream_t s) {
   const long long e = (long long)n * R;
   hipLaunchKernelGGL(k_gather_rhs, dim3(cdiv(e, 256)), dim3(256), 0, s, n, R, perm, in, out);

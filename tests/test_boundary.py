@@ -18,7 +18,7 @@ def declared():
 
 def test_header_declares_the_four_calls():
     names = declared()
-    for fn in ("amg_setup", "amg_precond_apply", "pcg_solve", "amg_free"):
+    for fn in ("amg_setup", "amg_precond_apply", "pcg_solve", "bicgstab_solve", "amg_free"):
         assert fn in names
 
 
