@@ -74,6 +74,8 @@ def lib():
         L.orc_cholesky.argtypes = [C.c_int, F64P, F64P]
         L.orc_mcsgs.restype = None
         L.orc_mcsgs.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, I32P, C.c_int, F64P, F64P]
+        L.orc_hybrid_sgs.restype = None
+        L.orc_hybrid_sgs.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, C.c_int, F64P, F64P]
         L.orc_setup.restype = C.c_void_p
         L.orc_setup.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, C.POINTER(Params), C.POINTER(C.c_int)]
         L.orc_free.restype = None
@@ -189,6 +191,14 @@ def mcsgs(rowptr, colind, vals, col, ncol, b, x):
     x = np.ascontiguousarray(x, np.float64).copy()
     lib().orc_mcsgs(rp.shape[0] - 1, ci.shape[0], rp, ci, v, np.ascontiguousarray(col, np.int32), ncol,
                     np.ascontiguousarray(b, np.float64), x)
+    return x
+
+
+def hybrid_sgs(rowptr, colind, vals, tile_rows, b, x):
+    """One hybrid SGS step (block-Jacobi over tiles of tile_rows rows, SGS inside)."""
+    rp, ci, v = _csr(rowptr, colind, vals)
+    x = np.ascontiguousarray(x, np.float64).copy()
+    lib().orc_hybrid_sgs(rp.shape[0] - 1, ci.shape[0], rp, ci, v, tile_rows, np.ascontiguousarray(b, np.float64), x)
     return x
 
 

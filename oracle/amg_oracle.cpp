@@ -584,7 +584,7 @@ struct Params {
   int colour_tile_rows;  // rows per tile of the colouring order
 };
 
-enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1 };
+enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1, SMOOTH_HYBRID = 2 };
 
 struct Level {
   Csr A;
@@ -627,6 +627,42 @@ void gs_row(const Csr& A, const V* val, int i, const V* b, V* x) {
   x[i] = acc / d;
 }
 
+// One hybrid symmetric Gauss-Seidel step (Sec. 3.2, parallel smoothers):
+// block-Jacobi over the tiles [tT, min((t+1)T, n)), and inside each tile one
+// sequential Gauss-Seidel step, a forward then a backward sweep over its rows.
+// Couplings to other tiles use the iterate from before the step (the defect
+// is formed once, before any tile changes); couplings inside the tile use the
+// current values.  Row update: acc = b_i - (couplings to other tiles, CSR
+// order) - (couplings inside the tile except a_ii, CSR order); x_i = acc/a_ii.
+// Parity pin: x + M^-1 (b - A x) with M = (D + L_B) D^-1 (D + U_B), L_B and
+// U_B the strict triangles of the tile-block-diagonal part of A.
+template <typename V>
+void hybrid_sgs(const Csr& A, const V* val, int T, const V* b, V* x) {
+  const int n = A.n;
+  const std::vector<V> xold(x, x + n);
+  auto row = [&](int i, int lo, int hi) {
+    V acc = b[i];
+    V d = 0;
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int j = A.col[k];
+      if (j < lo || j >= hi) acc = acc - val[k] * xold[j];
+    }
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int j = A.col[k];
+      if (j == i)
+        d = val[k];
+      else if (j >= lo && j < hi)
+        acc = acc - val[k] * x[j];
+    }
+    x[i] = acc / d;
+  };
+  for (int lo = 0; lo < n; lo += T) {
+    const int hi = std::min(n, lo + T);
+    for (int i = lo; i < hi; ++i) row(i, lo, hi);
+    for (int i = hi - 1; i >= lo; --i) row(i, lo, hi);
+  }
+}
+
 template <typename V>
 const V* level_vals(const Level& L);
 template <>
@@ -643,6 +679,8 @@ void smooth(const Hier& H, int l, const V* b, V* x) {
       for (int i : L.rows_of_colour[c]) gs_row<V>(L.A, val, i, b, x);
     for (int c = L.ncol - 1; c >= 0; --c)  // backward sweep
       for (int i : L.rows_of_colour[c]) gs_row<V>(L.A, val, i, b, x);
+  } else if (H.p.smoother == SMOOTH_HYBRID) {
+    hybrid_sgs<V>(L.A, val, H.p.tile_rows, b, x);
   } else {
     // l1-Jacobi (Baker, Falgout, Kolev, Yang 2011, pointwise): x += (b - A x) / d
     const int n = L.A.n;
@@ -739,7 +777,12 @@ int validate(const Csr& A, int check_symmetry) {
 }
 
 void finish_level(Level& L, const Params& p, int l) {
-  L.ncol = colour_rows(L.A, p.colour_tile_rows, p.colour_seed + (uint32_t)l, L.colour);
+  if (p.smoother == SMOOTH_HYBRID) {  // no multicolouring: one colour, natural order
+    L.colour.assign(L.A.n, 0);
+    L.ncol = 1;
+  } else {
+    L.ncol = colour_rows(L.A, p.colour_tile_rows, p.colour_seed + (uint32_t)l, L.colour);
+  }
   L.rows_of_colour.assign(L.ncol, {});
   for (int i = 0; i < L.A.n; ++i) L.rows_of_colour[L.colour[i]].push_back(i);
   L.val32.resize(L.A.nnz());
@@ -922,6 +965,13 @@ void orc_mcsgs(int n, int nnz, const int* ptr, const int* col, const double* val
     for (int i : rows[c]) gs_row<double>(A, A.val.data(), i, b, x);
   for (int c = ncol - 1; c >= 0; --c)
     for (int i : rows[c]) gs_row<double>(A, A.val.data(), i, b, x);
+}
+
+// One hybrid SGS step with tiles of T rows on x in place.
+void orc_hybrid_sgs(int n, int nnz, const int* ptr, const int* col, const double* val, int T, const double* b,
+                    double* x) {
+  Csr A = make_csr(n, nnz, ptr, col, val);
+  hybrid_sgs<double>(A, A.val.data(), T, b, x);
 }
 
 void* orc_setup(int n, int nnz, const int* ptr, const int* col, const double* val, const orc_params* q,

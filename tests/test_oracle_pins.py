@@ -383,6 +383,40 @@ def test_mcsgs_equals_textbook_sgs_on_colour_permuted_matrix():
     assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("T", [1, 7, 64, 1000])
+def test_hybrid_sgs_closed_form(T):
+    """Hybrid SGS (Sec. 3.2) is x + M^-1 (b - A x) with M = (D + L_B) D^-1 (D + U_B),
+    L_B / U_B the strict triangles of A's tile-block-diagonal part: T = 1 gives
+    one Jacobi step, T >= n the textbook sequential SGS, T = 7 ragged tiles."""
+    s = P.lognormal(6, seed=12)
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(s.n)
+    x0 = rng.standard_normal(s.n)
+    x = O.hybrid_sgs(s.rowptr, s.colind, s.vals, T, b, x0)
+    A = dense(s.rowptr, s.colind, s.vals)
+    tile = np.arange(s.n) // T
+    Ab = np.where(tile[:, None] == tile[None, :], A, 0.0)
+    D = np.diag(np.diag(A))
+    M = (D + np.tril(Ab, -1)) @ np.diag(1.0 / np.diag(A)) @ (D + np.triu(Ab, 1))
+    ref = x0 + np.linalg.solve(M, b - A @ x0)
+    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+    if T == 1:
+        assert np.abs(x - (x0 + (b - A @ x0) / np.diag(A))).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_hybrid_hierarchy_has_one_colour_and_smooths():
+    """With the hybrid smoother no level is coloured (one colour, natural
+    order); the V-cycle is a convergent preconditioner for PCG and BiCGSTAB."""
+    s = P.lognormal(12, seed=3)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, smoother=2)
+    assert H.levels >= 2
+    for l in range(H.levels):
+        L = H.level(l)
+        assert L.ncol == 1 and not L.colour.any()
+    for out in (H.pcg(s.b), H.bicgstab(s.b)):
+        assert out["status"] == O.OK and out["true_rel_residual"] <= 1.01e-8
+
+
 # ----------------------------------------------------------------- Cholesky
 def test_cholesky_matches_library_and_rejects_indefinite():
     rng = np.random.default_rng(1)
@@ -414,7 +448,7 @@ def test_single_level_vcycle_is_exact_inverse():
 
 
 @pytest.mark.parametrize("omega", [1.0, 1.6])
-@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("smoother", [0, 1, 2])
 def test_two_grid_operator_spd_and_contracting(omega, smoother):
     """Two-level V-cycle B: symmetric positive definite; E = I - B A has rho < 1."""
     s = P.lognormal(8, seed=2)
