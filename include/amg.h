@@ -62,7 +62,11 @@ typedef struct amg_csr {
   const double *vals;     /* device, nnz                                      */
 } amg_csr;
 
-enum { AMG_SMOOTHER_MCSGS = 0, AMG_SMOOTHER_L1_JACOBI = 1 };
+/* Smoothers: multicolour symmetric Gauss-Seidel over the whole level;
+ * l1-Jacobi; the paper's hybrid symmetric Gauss-Seidel (Sec. 3.2: block-
+ * Jacobi over the tiles of tile_rows rows, one sequential forward + backward
+ * Gauss-Seidel sweep inside each tile, levels kept in natural order). */
+enum { AMG_SMOOTHER_MCSGS = 0, AMG_SMOOTHER_L1_JACOBI = 1, AMG_SMOOTHER_HYBRID_SGS = 2 };
 
 /* Parameters.  Defaults from amg_default_params() in brackets. */
 typedef struct amg_params {
@@ -75,7 +79,7 @@ typedef struct amg_params {
   int32_t coarse_max;        /* stop coarsening at <= this many rows           [500]  */
   int32_t max_levels;        /*                                                [25]   */
   int32_t tile_rows;         /* rows per decoupled aggregation tile (64..1024) [128]  */
-  int32_t smoother;          /* AMG_SMOOTHER_MCSGS or AMG_SMOOTHER_L1_JACOBI   [MCSGS]*/
+  int32_t smoother;          /* AMG_SMOOTHER_*                                 [MCSGS]*/
   int32_t pre_sweeps;        /* symmetric GS steps (fwd+bwd) or Jacobi sweeps  [1]    */
   int32_t post_sweeps;       /*                                                [1]    */
   int32_t vcycle_fp32;       /* 1: V-cycle in FP32 on levels 0..L-1            [0]    */

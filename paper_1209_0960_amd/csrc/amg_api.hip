@@ -301,7 +301,9 @@ void check_params(const amg_params& p) {
   if (p.tile_rows < 64 || p.tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "tile_rows outside 64..1024");
   if (p.coarse_max < 1 || p.max_levels < 1) fail(AMG_ERR_INVALID_ARG, "coarse_max/max_levels");
   if (p.max_levels > MAX_LEVELS) fail(AMG_ERR_UNSUPPORTED, "max_levels above 32");
-  if (p.smoother != AMG_SMOOTHER_MCSGS && p.smoother != AMG_SMOOTHER_L1_JACOBI) fail(AMG_ERR_INVALID_ARG, "smoother");
+  if (p.smoother != AMG_SMOOTHER_MCSGS && p.smoother != AMG_SMOOTHER_L1_JACOBI &&
+      p.smoother != AMG_SMOOTHER_HYBRID_SGS)
+    fail(AMG_ERR_INVALID_ARG, "smoother");
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
   if (p.tail_rows < 0) fail(AMG_ERR_INVALID_ARG, "tail_rows");
   if (p.colour_tile_rows < 64 || p.colour_tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows outside 64..1024");
@@ -371,7 +373,13 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   const int Lc = (int)H.lev.size() - 1;
   H.lev[Lc].nc = 0;
   const bool f32 = p.vcycle_fp32 != 0;
-  for (int l = 0; l <= Lc; ++l) colour(H, H.lev[l], p.colour_seed + (uint32_t)l, s);
+  const bool hybrid = p.smoother == AMG_SMOOTHER_HYBRID_SGS;
+  for (int l = 0; l <= Lc; ++l) {
+    if (hybrid)
+      colour_single(H, H.lev[l], s);
+    else
+      colour(H, H.lev[l], p.colour_seed + (uint32_t)l, s);
+  }
   // Relabel every level above the coarsest into colour order (the coarsest
   // keeps its natural order for the dense solve).
   for (int l = Lc - 1; l >= 0; --l) permute_level(H, l, l + 1 < Lc ? H.lev[l + 1].perm : nullptr, s);
@@ -393,6 +401,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
       }
     }
     build_sell(H, l, s);
+    if (hybrid) hybrid_steps(H, L, p.tile_rows, s);
     L.sptr_d = H.alloc<int>(L.sptr.size(), s);
     AMG_HIP(hipMemcpyAsync(L.sptr_d, L.sptr.data(), L.sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
     if (f32) {

@@ -135,6 +135,10 @@ struct Level {
   float* sval32 = nullptr;
   double* dg = nullptr;
   float* dg32 = nullptr;
+  // hybrid smoother (natural order, slices of 64 consecutive rows)
+  unsigned short* hsf = nullptr;  // n: forward wavefront step inside the tile
+  unsigned short* hsb = nullptr;  // n: backward wavefront step
+  int hdf = 0, hdb = 0;           // largest steps
   // optional setup data (natural order)
   uint8_t* strong = nullptr;
   uint8_t* iso = nullptr;
@@ -223,6 +227,11 @@ int aggregate(Hierarchy& H, Level& L, const uint8_t* strong, const uint8_t* iso,
 // Galerkin product; returns the coarse level's CSR arrays allocated in H.
 void galerkin(Hierarchy& H, const Level& L, Level& C, hipStream_t s);
 void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s);
+// One colour, natural order (the hybrid smoother needs no colouring).
+void colour_single(Hierarchy& H, Level& L, hipStream_t s);
+// Wavefront steps of the in-tile sweeps of the hybrid smoother (after
+// build_sell; the level has one colour).
+void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s);
 void cast_f32(const double* in, float* out, size_t n, hipStream_t s);
 void l1_diag(const Level& L, double* out64, float* out32, hipStream_t s);
 // Dense FP64 factorisation of the coarsest level and its explicit inverse.
@@ -268,6 +277,10 @@ struct BDesc {
   double* scal;                     // [R][S_COUNT]
   const int* sptr;                  // ncol+1: first slice of each colour
   int ncol;
+  // hybrid smoother: wavefront step of each row in the forward / backward
+  // sweep inside its tile of T rows, and the largest step of each sweep
+  const unsigned short *hsf, *hsb;
+  int T, hdf, hdb;
   const int* ctl;                   // [CTL_INTS]
   int active;                       // 0: the entry is finished (table launches skip it)
   int n, nc, nsl, nL;
@@ -299,6 +312,8 @@ enum {
   OP_GS0,        // first Gauss-Seidel pass from x = 0: x = b / diag on the slices of one colour
   OP_TAIL_UP,    // up-leg of levels L-1..lt of one entry in one workgroup (prolong, post-smooth)
   OP_GS_RESID,   // Gauss-Seidel pass that also writes the residual of its rows
+  OP_RESID_OFF,  // hybrid smoother: t = b - (couplings to other tiles) x (slices)
+  OP_HSGS,       // hybrid smoother: in-tile forward + backward sweeps (tiles; aux = 1: from b, x = 0)
 };
 enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
 

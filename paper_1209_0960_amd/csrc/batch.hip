@@ -197,7 +197,7 @@ struct Batch {
   // All entries start together and are completed at the end (pcg_solve_batched):
   // finished entries are only switched off, the launch plan is kept.
   bool deferred = false;
-  int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0;
+  int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0, tile_rows = 0;
   hipStream_t work = nullptr;
   hipEvent_t ev = nullptr;
   BDesc* desc_d = nullptr;
@@ -252,12 +252,15 @@ void check_uniform(Batch& B, const Hierarchy& H) {
     B.pre = H.p.pre_sweeps;
     B.post = H.p.post_sweeps;
     B.flexible = H.flexible;
+    B.tile_rows = H.p.tile_rows;
     return;
   }
   if (B.fp32 != fp32 || B.smoother != H.p.smoother || B.pre != H.p.pre_sweeps || B.post != H.p.post_sweeps ||
       B.flexible != H.flexible)
     fail(AMG_ERR_INVALID_ARG,
          "hierarchies of one batch must share vcycle_fp32, smoother, pre/post sweeps and the CG variant");
+  if (B.smoother == AMG_SMOOTHER_HYBRID_SGS && B.tile_rows != H.p.tile_rows)
+    fail(AMG_ERR_INVALID_ARG, "hierarchies of one batch with the hybrid smoother must share tile_rows");
 }
 
 // Allocates the vectors of `slot` for hierarchy H and writes its descriptors.
@@ -347,6 +350,11 @@ void bind_slot(Batch& B, int slot, Hierarchy& H) {
     d.active = 0;
     d.sptr = L.sptr_d;
     d.ncol = L.ncol;
+    d.hsf = L.hsf;
+    d.hsb = L.hsb;
+    d.T = L.T;
+    d.hdf = L.hdf;
+    d.hdb = L.hdb;
     d.n = L.n;
     d.nc = L.nc;
     d.nsl = L.nsl;
@@ -563,6 +571,26 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
       }
       b.end();
     }
+  } else if (B.smoother == AMG_SMOOTHER_HYBRID_SGS) {
+    // per step: t = b - (couplings to other tiles) x, then the in-tile sweeps
+    // (from x = 0: src = b, no residual pass)
+    for (int k = 0; k < sweeps; ++k) {
+      const bool zero = from_zero && k == 0;
+      if (!zero) {
+        b.begin(OP_RESID_OFF, l, kind_at(l, AMG_KIND_SWEEP));
+        for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
+        b.end();
+      }
+      b.begin(OP_HSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0);
+      for (int e : E) {
+        const Level& L = hier(B, e).lev[l];
+        // entries read by both sweeps, the source twice, x read and written
+        const double per_tile = (double)L.soff_h[L.nsl] / L.n * L.T * 2.0 * (4.0 + vb) +
+                                L.T * (4.0 + vb + 2.0 * B.R * vb + (zero ? 1.0 : 2.0) * B.R * vb);
+        b.pieces(B.desc_index(e, l), 0, cdiv(L.n, L.T), 1, per_tile);
+      }
+      b.end();
+    }
   } else {
     for (int k = 0; k < sweeps; ++k) {
       b.begin(OP_RESID, l, kind_at(l, AMG_KIND_SWEEP));
@@ -597,6 +625,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool c
     const std::vector<int>& E = below[l];
     b.begin(OP_ZERO, l, l == 0 ? AMG_KIND_OTHER : AMG_KIND_COARSE_LEVELS);
     for (int e : E) {
+      if (B.smoother == AMG_SMOOTHER_HYBRID_SGS && B.pre > 0) continue;  // the first step writes every row
       const Level& L = hier(B, e).lev[l];
       const int r0 = B.pre > 0 && colour0_shortcuts(B, e, l) ? colour0_rows(L) : 0;
       b.pieces(B.desc_index(e, l), r0, L.n, ROW_CH, R * vb);

@@ -1822,6 +1822,95 @@ void colour(Hierarchy& H, Level& L, uint32_t seed, hipStream_t s) {
   sync_stream(s);
 }
 
+// ---------------------------------------------------------------- hybrid smoother
+__global__ void k_iota(int n, int* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+void colour_single(Hierarchy& H, Level& L, hipStream_t s) {
+  const int n = L.n;
+  L.colour = H.alloc<int>((size_t)n, s);
+  L.crows = H.alloc<int>((size_t)n, s);
+  hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.colour, 0);
+  hipLaunchKernelGGL(k_iota, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.crows);
+  AMG_HIP(hipGetLastError());
+  L.ncol = 1;
+  L.cptr = {0, n};
+}
+
+constexpr int HS_MAX_T = 1024;
+
+// Wavefront steps of the sequential Gauss-Seidel sweeps inside one tile (one
+// wavefront per tile, rows in natural order, SELL slices of 64 consecutive
+// rows).  Forward: step(i) = 1 + the largest step of the rows j < i of the
+// tile coupled to i (a_ij or a_ji stored), 0 without any; backward the same
+// with j > i.  A row's step exceeds those of all its earlier-swept couplings,
+// so updating the rows step by step reproduces the sequential sweep.  Found by
+// monotone relaxation from 0 (each row pulls from its own entries and pushes
+// to the rows its entries name); it stops at the fixed point, reached after
+// at most nt rounds (a longest path has fewer than nt edges).
+__global__ __launch_bounds__(64) void k_hybrid_steps(int n, int T, const int* __restrict__ soff,
+                                                     const int* __restrict__ scol, unsigned short* __restrict__ sf,
+                                                     unsigned short* __restrict__ sb, int* __restrict__ mx) {
+  __shared__ int st[HS_MAX_T];
+  const int lo = (int)blockIdx.x * T, hi = min(n, lo + T), nt = hi - lo;
+  const int lane = (int)threadIdx.x;
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int q = lane; q < nt; q += 64) st[q] = 0;
+    __syncthreads();
+    bool conv = false;
+    for (int round = 0; round <= nt && !conv; ++round) {
+      bool ch = false;
+      for (int q = lane; q < nt; q += 64) {
+        const int i = lo + q, sl = i >> 6, t = i & 63;
+        const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
+        int m = st[q];
+        for (int k = 0; k < w; ++k) {
+          const int j = scol[base + 64 * k + t];
+          if (j >= lo && j < hi && (dir == 0 ? j < i : j > i)) m = max(m, st[j - lo] + 1);
+        }
+        if (m > st[q]) {
+          st[q] = m;
+          ch = true;
+        }
+        for (int k = 0; k < w; ++k) {
+          const int j = scol[base + 64 * k + t];
+          if (j >= lo && j < hi && (dir == 0 ? j > i : j < i) && atomicMax(&st[j - lo], m + 1) < m + 1) ch = true;
+        }
+      }
+      __syncthreads();
+      conv = __ballot(ch) == 0;
+    }
+    if (!conv) atomicOr(mx + 2, 1);
+    int dmax = 0;
+    for (int q = lane; q < nt; q += 64) {
+      (dir == 0 ? sf : sb)[lo + q] = (unsigned short)st[q];
+      dmax = max(dmax, st[q]);
+    }
+    dmax = wave_max(dmax);
+    if (lane == 0) atomicMax(mx + dir, dmax);
+    __syncthreads();
+  }
+}
+
+void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s) {
+  if (T > HS_MAX_T) fail(AMG_ERR_UNSUPPORTED, "the hybrid smoother takes tiles of at most 1024 rows");
+  if (L.ncol != 1) fail(AMG_ERR_INVALID_ARG, "hybrid smoother level must have one colour");
+  for (int q = 0; q < L.nsl; ++q)
+    if (L.srow_h[q] != 64 * q) fail(AMG_ERR_HIP, "hybrid smoother expects slices of 64 consecutive rows");
+  const int n = L.n, ntiles = cdiv(n, T);
+  L.hsf = H.alloc<unsigned short>((size_t)n, s);
+  L.hsb = H.alloc<unsigned short>((size_t)n, s);
+  DBuf mx(4 * sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, 4 * sizeof(int), s));
+  hipLaunchKernelGGL(k_hybrid_steps, dim3(ntiles), dim3(64), 0, s, n, T, L.soff, L.scol, L.hsf, L.hsb, mx.as<int>());
+  AMG_HIP(hipGetLastError());
+  int bad = 0;
+  read_ints(s, {{&L.hdf, mx.as<int>()}, {&L.hdb, mx.as<int>() + 1}, {&bad, mx.as<int>() + 2}});
+  if (bad) fail(AMG_ERR_HIP, "hybrid smoother step relaxation did not converge");
+}
+
 void cast_f32(const double* in, float* out, size_t n, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(k_cast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in, out);

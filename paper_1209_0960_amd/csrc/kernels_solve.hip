@@ -270,6 +270,112 @@ __global__ __launch_bounds__(NT) void kb_resid(AMG_KARGS) {
   AMG_BODY((kb_resid_body<V, R>))
 }
 
+// ---------------------------------------------------------------- hybrid smoother
+// Hybrid symmetric Gauss-Seidel (Sec. 3.2): block-Jacobi over the tiles of T
+// rows of a level in natural order, one forward and one backward sequential
+// Gauss-Seidel sweep inside each tile.  A step first forms, for every row,
+// t_i = b_i - sum over the couplings to other tiles of a_ij x_j (the iterate
+// from before the step); the in-tile sweeps then use t and the tile's own
+// current values only, so tiles never read each other's updates.
+
+// t = b - (couplings to other tiles) x on the slices [lo, hi).  Padding
+// entries name their own row and fall inside the tile.
+template <typename V, int R>
+__device__ __forceinline__ void kb_resid_off_body(const Item& it, const BDesc& d) {
+  const int sl = it.lo + (int)(threadIdx.x / WAVE);
+  if (sl >= it.hi) return;
+  const int lane = __lane_id();
+  const int r = d.srow[sl] + lane;
+  if (r >= d.srow[sl + 1]) return;
+  const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
+  const int lo = r - r % d.T, hi = lo + d.T;
+  const V* x = static_cast<const V*>(d.x);
+  const V* sv = Mat<V>::sval(d);
+  V acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0;
+  for (int e = 0; e < w; ++e) {
+    const int j = d.scol[base + 64 * e + lane];
+    if (j < lo || j >= hi) {
+      const V a = sv[base + 64 * e + lane];
+      V xv[R];
+      ldv<V, R>(x + (size_t)j * R, xv);
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc[k] = madd(a, xv[k], acc[k]);
+    }
+  }
+  V bb[R], o[R];
+  ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+#pragma unroll
+  for (int k = 0; k < R; ++k) o[k] = bb[k] - acc[k];
+  stv<V, R>(static_cast<V*>(d.t) + (size_t)r * R, o);
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_resid_off(AMG_KARGS) {
+  AMG_BODY((kb_resid_off_body<V, R>))
+}
+
+// The forward then the backward sweep over rows [lo, hi) of one tile by the
+// lanes of one wavefront: x_i = (src_i - sum over in-tile j != i of a_ij x_j)
+// / a_ii, rows of one wavefront step together (their couplings lie in earlier
+// steps of the sweep, whose values are final, or in later ones, not yet
+// touched), steps separated by sync().  xt[(i - lo) * R + k] is the tile's
+// iterate (LDS copy or the level's vector itself).  Every caller runs the
+// same number of steps, so sync() may be a workgroup barrier.
+template <typename V, int R, typename Sync>
+__device__ inline void hybrid_tile(const BDesc& d, int lo, int hi, const V* __restrict__ src, V* xt, int lane,
+                                   Sync sync) {
+  const V* sv = Mat<V>::sval(d);
+  const V* dg = Mat<V>::dg(d);
+  for (int dir = 0; dir < 2; ++dir) {
+    const unsigned short* st = dir == 0 ? d.hsf : d.hsb;
+    const int depth = dir == 0 ? d.hdf : d.hdb;
+    for (int step = 0; step <= depth; ++step) {
+      for (int i = lo + lane; i < hi; i += WAVE) {
+        if (st[i] != step) continue;
+        const int t = i & 63, base = d.soff[i >> 6], w = (d.soff[(i >> 6) + 1] - base) >> 6;
+        V acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = 0;
+        for (int e = 0; e < w; ++e) {
+          const int j = d.scol[base + 64 * e + t];
+          if (j >= lo && j < hi && j != i) {
+            const V a = sv[base + 64 * e + t];
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] = madd(a, xt[(size_t)(j - lo) * R + k], acc[k]);
+          }
+        }
+        V sr[R];
+        ldv<V, R>(src + (size_t)i * R, sr);
+        const V di = dg[i];
+#pragma unroll
+        for (int k = 0; k < R; ++k) xt[(size_t)(i - lo) * R + k] = (sr[k] - acc[k]) / di;
+      }
+      sync();
+    }
+  }
+}
+
+// One tile per block of one wavefront (it.lo = tile), its iterate staged in
+// LDS (T * R values).  from_b: the iterate before the step is zero, src = b.
+template <typename V, int R>
+__device__ __forceinline__ void kb_hsgs_body(const Item& it, const BDesc& d, int from_b) {
+  extern __shared__ double hs_lds[];
+  V* xt = reinterpret_cast<V*>(hs_lds);
+  const int lo = it.lo * d.T, hi = min(d.n, lo + d.T);
+  const int lane = (int)threadIdx.x;
+  V* x = static_cast<V*>(d.x);
+  const int m = (hi - lo) * R;
+  for (int q = lane; q < m; q += WAVE) xt[q] = from_b ? (V)0 : x[(size_t)lo * R + q];
+  __syncthreads();
+  hybrid_tile<V, R>(d, lo, hi, static_cast<const V*>(from_b ? d.b : d.t), xt, lane, [] { __syncthreads(); });
+  for (int q = lane; q < m; q += WAVE) x[(size_t)lo * R + q] = xt[q];
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(WAVE) void kb_hsgs(AMG_KARGS, int from_b) {
+  AMG_BODY((kb_hsgs_body<V, R>), from_b)
+}
+
 template <typename V, int R>
 __device__ __forceinline__ void kb_zero_body(const Item& it, const BDesc& d) {
   V* x = static_cast<V*>(d.x);
@@ -388,7 +494,8 @@ __global__ __launch_bounds__(NT) void kb_coarse(AMG_KARGS) {
 // thread per row), so the result does not depend on where the tail starts.
 constexpr int TAIL_NT = 1024;
 
-// op: 0 residual, 1 Gauss-Seidel pass, 2 Gauss-Seidel pass from x = 0.
+// op: 0 residual, 1 Gauss-Seidel pass, 2 Gauss-Seidel pass from x = 0,
+// 3 residual of the couplings to other tiles (hybrid smoother).
 template <typename V, int R>
 __device__ inline void tail_slices(const BDesc& d, int s0, int s1, int op) {
   const int nw = (int)blockDim.x / WAVE;
@@ -398,6 +505,8 @@ __device__ inline void tail_slices(const BDesc& d, int s0, int s1, int op) {
       kb_gs_body<V, R>(it, d);
     else if (op == 2)
       kb_gs0_body<V, R>(it, d);
+    else if (op == 3)
+      kb_resid_off_body<V, R>(it, d);
     else
       kb_resid_body<V, R>(it, d);
   }
@@ -417,6 +526,19 @@ __device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps, boo
           tail_slices<V, R>(d, d.sptr[c], d.sptr[c + 1], from_zero && prev < 0 ? 2 : 1);
           prev = c;
         }
+    } else if (smoother == AMG_SMOOTHER_HYBRID_SGS) {
+      // wavefronts take tiles; the sweeps work on the level's vector in
+      // place (tiles only read their own rows), steps separated by barriers
+      const bool zero = from_zero && k == 0;
+      if (!zero) tail_slices<V, R>(d, 0, d.nsl, 3);
+      const int nw = (int)blockDim.x / WAVE, wv = (int)threadIdx.x / WAVE;
+      const int ntl = (d.n + d.T - 1) / d.T;
+      const V* src = static_cast<const V*>(zero ? d.b : d.t);
+      for (int t0 = 0; t0 < ntl; t0 += nw) {
+        const int lo = min(d.n, (t0 + wv) * d.T), hi = min(d.n, lo + d.T);
+        hybrid_tile<V, R>(d, lo, hi, src, static_cast<V*>(d.x) + (size_t)lo * R, __lane_id(),
+                          [] { __syncthreads(); });
+      }
     } else {
       tail_slices<V, R>(d, 0, d.nsl, 0);
       kb_jacobi_body<V, R>(Item{0, 0, d.n, 0}, d);
@@ -931,6 +1053,16 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
     case OP_GS0: AMG_LAUNCH(kb_gs0, (V, R)); break;
     case OP_GS_RESID: AMG_LAUNCH(kb_gsr, (V, R)); break;
     case OP_RESID: AMG_LAUNCH(kb_resid, (V, R)); break;
+    case OP_RESID_OFF: AMG_LAUNCH(kb_resid_off, (V, R)); break;
+    case OP_HSGS: {
+      // one wavefront per tile, the tile's iterate in LDS
+      const dim3 bw(WAVE);
+      const size_t lds = (size_t)Dh[L.direct.d].T * R * sizeof(V);
+      if (L.use_direct)
+        hipLaunchKernelGGL((kb_hsgs<V, R, true>), g, bw, lds, s, nullptr, nullptr, Dh[L.direct.d], L.direct, L.aux);
+      else
+        hipLaunchKernelGGL((kb_hsgs<V, R, false>), g, bw, lds, s, t, D, BDesc{}, Item{}, L.aux);
+    } break;
     case OP_JACOBI: AMG_LAUNCH(kb_jacobi, (V, R)); break;
     case OP_RESTRICT: AMG_LAUNCH(kb_restrict, (V, R)); break;
     case OP_PROLONG: AMG_LAUNCH(kb_prolong, (V, R)); break;
@@ -958,6 +1090,8 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
     case OP_GS0:
     case OP_GS_RESID:
     case OP_RESID:
+    case OP_RESID_OFF:
+    case OP_HSGS:
     case OP_JACOBI:
     case OP_RESTRICT:
     case OP_PROLONG:

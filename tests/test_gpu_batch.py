@@ -177,7 +177,8 @@ def test_precond_after_solve_matches_fresh(A):
 
 
 @pytest.mark.parametrize("fp32,pre,post,smoother", [(1, 1, 1, 0), (0, 1, 1, 0), (1, 2, 2, 0), (1, 0, 1, 0),
-                                                    (1, 1, 0, 0), (1, 1, 1, 1)])
+                                                    (1, 1, 0, 0), (1, 1, 1, 1), (1, 1, 1, 2), (0, 1, 1, 2),
+                                                    (1, 2, 2, 2), (1, 0, 1, 2)])
 def test_tail_bit_identical(A, fp32, pre, post, smoother):
     """Levels cycled by one workgroup per entry (tail_rows: below that many
     rows; the coarsest solve stays a many-block launch) give the same bits as
@@ -185,7 +186,7 @@ def test_tail_bit_identical(A, fp32, pre, post, smoother):
     batches with four right-hand sides per system.  The tail fills, forms the
     residual and prolongs every row, so this also checks the launch path's
     shortcuts (colour-0 rows skipped, residual from the last pre-smoothing
-    pass) for several sweep counts and both smoothers."""
+    pass) for several sweep counts and every smoother."""
     d = dev(systems(4, seed=5))
     ref = None
     kw = dict(vcycle_fp32=fp32, pre_sweeps=pre, post_sweeps=post, smoother=smoother)

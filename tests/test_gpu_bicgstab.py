@@ -156,3 +156,43 @@ def test_bicgstab_fullsize_128_true_residual(A):
             print(f"128^3 fp32={fp32}: {r.iterations} iterations, half {r.half_step}, true residual {res:.3e}")
             assert res <= 1.5e-8
             assert abs(res - r.true_rel_residual) <= 1e-3 * res + 1e-14
+
+
+@pytest.mark.parametrize("name", ["hetero_24", "jump_20", "box_13x17x11"])
+@pytest.mark.parametrize("T", [128, 200])
+def test_bicgstab_hybrid_sgs_fp64_iterates(A, name, T):
+    """The paper's own configuration (Sec. 5): BiCGSTAB with one V-cycle of
+    hybrid symmetric Gauss-Seidel smoothing (block-Jacobi over tiles of T
+    rows, ragged when T = 200), iterates against the oracle's."""
+    s = system(name)
+    rp, ci, v, b = A.to_device(s)
+    maxit = 100
+    with A.Hierarchy(rp, ci, v, smoother=2, tile_rows=T) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, smoother=2, tile_rows=T)
+        hist = torch.zeros((maxit + 1) * s.n, dtype=torch.float64, device="cuda")
+        x, r = hg.solve(b, rtol=1e-8, maxit=maxit, iter_hist=hist, method="bicgstab")
+        o = ho.bicgstab(s.b, rtol=1e-8, maxit=maxit, keep_iterates=True)
+        assert r.status == A.OK and o["status"] == O.OK
+        assert abs(r.iterations - o["iterations"]) <= 1
+        k = min(r.iterations, o["iterations"])
+        H = hist.cpu().numpy().reshape(maxit + 1, s.n)
+        worst = max(rel(H[it], o["iterates"][it]) for it in range(1, k + 1))
+        print(f"{name} T={T}: {r.iterations} iterations (oracle {o['iterations']}), max iterate difference "
+              f"{worst:.2e}")
+        assert worst <= 1e-10
+        assert true_res(s, x.cpu().numpy()) <= 1.01e-8
+
+
+def test_hybrid_sgs_fp32_vcycle_and_cg(A):
+    s = system("hetero_24")
+    rp, ci, v, b = A.to_device(s)
+    with A.Hierarchy(rp, ci, v, smoother=2, vcycle_fp32=1) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, smoother=2, vcycle_fp32=1)
+        z = hg.precond(b)
+        torch.cuda.synchronize()
+        assert rel(z.cpu().numpy(), ho.vcycle(s.b)) <= 1e-5
+        for method, oracle_run in (("cg", ho.pcg), ("bicgstab", ho.bicgstab)):
+            x, r = hg.solve(b, rtol=1e-8, method=method)
+            o = oracle_run(s.b, rtol=1e-8)
+            assert r.status == A.OK and abs(r.iterations - o["iterations"]) <= 2, method
+            assert true_res(s, x.cpu().numpy()) <= 1.5e-8

@@ -72,7 +72,8 @@ def test_setup_bit_exact(A, name):
 
 
 @pytest.mark.parametrize("params", [dict(tile_rows=64), dict(tile_rows=1000, agg_min=4, agg_max=6, agg_diameter=2),
-                                    dict(strength_threshold=0.25, colour_seed=7)])
+                                    dict(strength_threshold=0.25, colour_seed=7), dict(smoother=2),
+                                    dict(smoother=2, tile_rows=200)])
 def test_setup_bit_exact_other_parameters(A, params):
     s = system("hetero_24")
     rp, ci, v, b = dev(s)
@@ -86,7 +87,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("smoother", [0, 1, 2])
 def test_vcycle_fp64_parity(A, name, smoother):
     s = system(name)
     rp, ci, v, b = dev(s)
