@@ -139,6 +139,7 @@ struct Level {
   unsigned short* hsf = nullptr;  // n: forward wavefront step inside the tile
   unsigned short* hsb = nullptr;  // n: backward wavefront step
   int hdf = 0, hdb = 0;           // largest steps
+  int hw = 0;                     // most in-tile couplings of a row
   // optional setup data (natural order)
   uint8_t* strong = nullptr;
   uint8_t* iso = nullptr;
@@ -280,7 +281,7 @@ struct BDesc {
   // hybrid smoother: wavefront step of each row in the forward / backward
   // sweep inside its tile of T rows, and the largest step of each sweep
   const unsigned short *hsf, *hsb;
-  int T, hdf, hdb;
+  int T, hdf, hdb, hw;
   const int* ctl;                   // [CTL_INTS]
   int active;                       // 0: the entry is finished (table launches skip it)
   int n, nc, nsl, nL;

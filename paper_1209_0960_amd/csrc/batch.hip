@@ -355,6 +355,7 @@ void bind_slot(Batch& B, int slot, Hierarchy& H) {
     d.T = L.T;
     d.hdf = L.hdf;
     d.hdb = L.hdb;
+    d.hw = L.hw;
     d.n = L.n;
     d.nc = L.nc;
     d.nsl = L.nsl;
@@ -581,7 +582,9 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
         for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
         b.end();
       }
-      b.begin(OP_HSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0);
+      int W = 0;  // LDS layout of the launch: the most in-tile couplings of a row over its entries
+      for (int e : E) W = std::max(W, hier(B, e).lev[l].hw);
+      b.begin(OP_HSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0, W);
       for (int e : E) {
         const Level& L = hier(B, e).lev[l];
         // entries read by both sweeps, the source twice, x read and written

@@ -1883,6 +1883,21 @@ __global__ __launch_bounds__(64) void k_hybrid_steps(int n, int T, const int* __
       conv = __ballot(ch) == 0;
     }
     if (!conv) atomicOr(mx + 2, 1);
+    if (dir == 0) {  // the most in-tile couplings of a row (LDS layout of the sweeps)
+      int cmax = 0;
+      for (int q = lane; q < nt; q += 64) {
+        const int i = lo + q, sl = i >> 6, t = i & 63;
+        const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
+        int c = 0;
+        for (int k = 0; k < w; ++k) {
+          const int j = scol[base + 64 * k + t];
+          c += (j >= lo && j < hi && j != i) ? 1 : 0;
+        }
+        cmax = max(cmax, c);
+      }
+      cmax = wave_max(cmax);
+      if (lane == 0) atomicMax(mx + 3, cmax);
+    }
     int dmax = 0;
     for (int q = lane; q < nt; q += 64) {
       (dir == 0 ? sf : sb)[lo + q] = (unsigned short)st[q];
@@ -1907,7 +1922,7 @@ void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s) {
   hipLaunchKernelGGL(k_hybrid_steps, dim3(ntiles), dim3(64), 0, s, n, T, L.soff, L.scol, L.hsf, L.hsb, mx.as<int>());
   AMG_HIP(hipGetLastError());
   int bad = 0;
-  read_ints(s, {{&L.hdf, mx.as<int>()}, {&L.hdb, mx.as<int>() + 1}, {&bad, mx.as<int>() + 2}});
+  read_ints(s, {{&L.hdf, mx.as<int>()}, {&L.hdb, mx.as<int>() + 1}, {&bad, mx.as<int>() + 2}, {&L.hw, mx.as<int>() + 3}});
   if (bad) fail(AMG_ERR_HIP, "hybrid smoother step relaxation did not converge");
 }
 

@@ -376,6 +376,120 @@ __global__ __launch_bounds__(WAVE) void kb_hsgs(AMG_KARGS, int from_b) {
   AMG_BODY((kb_hsgs_body<V, R>), from_b)
 }
 
+// LDS bytes of the staged sweep of a tile of T rows with at most W in-tile
+// couplings per row.
+template <typename V>
+__host__ __device__ inline size_t hsgs_lds_bytes(int T, int W, int R) {
+  return (size_t)T * (2 * R + 1 + W) * sizeof(V) + (size_t)T * (W + 3) * sizeof(unsigned short);
+}
+
+// The same sweeps with everything a step reads staged in LDS first: the
+// tile's iterate and source, its diagonal, the wavefront steps, and each row's
+// in-tile couplings (local column, value; SELL entry order, as in
+// hybrid_tile, so the sums and the results are the same).  A step then reads
+// LDS only.
+template <typename V, int R>
+__device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d, int from_b, int W) {
+  extern __shared__ double hs_lds[];
+  const int T = d.T;
+  V* xt = reinterpret_cast<V*>(hs_lds);
+  V* sr = xt + (size_t)T * R;
+  V* dl = sr + (size_t)T * R;
+  V* ev = dl + T;
+  unsigned short* ec = reinterpret_cast<unsigned short*>(ev + (size_t)T * W);
+  unsigned short* cn = ec + (size_t)T * W;
+  unsigned short* stf = cn + T;
+  unsigned short* stb = stf + T;
+  const int lo = it.lo * T, hi = min(d.n, lo + T), nt = hi - lo;
+  const int lane = (int)threadIdx.x;
+  V* x = static_cast<V*>(d.x);
+  const V* src = static_cast<const V*>(from_b ? d.b : d.t);
+  const V* sv = Mat<V>::sval(d);
+  const V* dg = Mat<V>::dg(d);
+  for (int q = lane; q < nt; q += WAVE) {
+    const int i = lo + q, t = i & 63, base = d.soff[i >> 6], w = (d.soff[(i >> 6) + 1] - base) >> 6;
+    int c = 0;
+    for (int e = 0; e < w; ++e) {
+      const int j = d.scol[base + 64 * e + t];
+      if (j >= lo && j < hi && j != i) {
+        ec[(size_t)q * W + c] = (unsigned short)(j - lo);
+        ev[(size_t)q * W + c] = sv[base + 64 * e + t];
+        ++c;
+      }
+    }
+    cn[q] = (unsigned short)c;
+    stf[q] = d.hsf[i];
+    stb[q] = d.hsb[i];
+    dl[q] = dg[i];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      sr[(size_t)q * R + k] = src[(size_t)i * R + k];
+      xt[(size_t)q * R + k] = from_b ? (V)0 : x[(size_t)i * R + k];
+    }
+  }
+  // this tile's deepest steps (the sweeps stop there)
+  int df = 0, db = 0;
+  for (int q = lane; q < nt; q += WAVE) {
+    df = max(df, (int)stf[q]);
+    db = max(db, (int)stb[q]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    df = max(df, __shfl_xor(df, o, WAVE));
+    db = max(db, __shfl_xor(db, o, WAVE));
+  }
+  __syncthreads();
+  for (int dir = 0; dir < 2; ++dir) {
+    const unsigned short* st = dir == 0 ? stf : stb;
+    const int depth = dir == 0 ? df : db;
+    for (int step = 0; step <= depth; ++step) {
+      for (int q = lane; q < nt; q += WAVE) {
+        if (st[q] != step) continue;
+        V acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = 0;
+        const int c = cn[q];
+        const V* evq = ev + (size_t)q * W;
+        const unsigned short* ecq = ec + (size_t)q * W;
+        int e = 0;
+        // chunks of 8 couplings: their loads, then their gathers, in flight
+        // together; the sum keeps the entry order
+        for (; e + 8 <= c; e += 8) {
+          V a[8], xv[8][R];
+          int j[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            a[u] = evq[e + u];
+            j[u] = ecq[e + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int k = 0; k < R; ++k) xv[u][k] = xt[(size_t)j[u] * R + k];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] = madd(a[u], xv[u][k], acc[k]);
+        }
+        for (; e < c; ++e) {
+          const V a = evq[e];
+          const int j = ecq[e];
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] = madd(a, xt[(size_t)j * R + k], acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) xt[(size_t)q * R + k] = (sr[(size_t)q * R + k] - acc[k]) / dl[q];
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = lane; q < nt * R; q += WAVE) x[(size_t)lo * R + q] = xt[q];
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(WAVE) void kb_hsgs_lds(AMG_KARGS, int from_b, int W) {
+  AMG_BODY((kb_hsgs_lds_body<V, R>), from_b, W)
+}
+
 template <typename V, int R>
 __device__ __forceinline__ void kb_zero_body(const Item& it, const BDesc& d) {
   V* x = static_cast<V*>(d.x);
@@ -1055,9 +1169,21 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
     case OP_RESID: AMG_LAUNCH(kb_resid, (V, R)); break;
     case OP_RESID_OFF: AMG_LAUNCH(kb_resid_off, (V, R)); break;
     case OP_HSGS: {
-      // one wavefront per tile, the tile's iterate in LDS
+      // one wavefront per tile: everything staged in LDS when it fits in
+      // 64 KiB (aux2 = the most in-tile couplings of a row), else the
+      // iterate alone
       const dim3 bw(WAVE);
-      const size_t lds = (size_t)Dh[L.direct.d].T * R * sizeof(V);
+      const int T = Dh[L.direct.d].T;
+      const size_t full = hsgs_lds_bytes<V>(T, L.aux2, R);
+      if (full <= 65536) {
+        if (L.use_direct)
+          hipLaunchKernelGGL((kb_hsgs_lds<V, R, true>), g, bw, full, s, nullptr, nullptr, Dh[L.direct.d], L.direct,
+                             L.aux, L.aux2);
+        else
+          hipLaunchKernelGGL((kb_hsgs_lds<V, R, false>), g, bw, full, s, t, D, BDesc{}, Item{}, L.aux, L.aux2);
+        break;
+      }
+      const size_t lds = (size_t)T * R * sizeof(V);
       if (L.use_direct)
         hipLaunchKernelGGL((kb_hsgs<V, R, true>), g, bw, lds, s, nullptr, nullptr, Dh[L.direct.d], L.direct, L.aux);
       else
