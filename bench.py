@@ -368,6 +368,30 @@ def main():
             log(f"{key}: {ms:.1f} ms (setup {rb.setup_ms:.1f}, solve {rb.solve_ms:.1f}), "
                 f"it={rb.iterations} half={rb.half_step} true_rel_res={rb.true_rel_residual:.2e}")
         extra["paper_solver"] = bic
+        # Iteration counts on the paper's Laplace problem (K = 1), the
+        # setting of its Table 1 (80^3 on one process: 5 levels, It = 8) and
+        # Table 4 (256^3 on one process: It = 6), BiCGSTAB with both smoothers.
+        lap = {}
+        for m in (80, 256):
+            sl = P.poisson(m)
+            lrp, lci, lv, lb = A.to_device(sl)
+            for smoother in (0, 2):
+                torch.cuda.synchronize()
+                q0 = time.perf_counter()
+                h = A.Hierarchy(lrp, lci, lv, smoother=smoother)
+                _, rl = h.solve(lb, rtol=1e-8, method="bicgstab")
+                lev = h.levels
+                h.close()
+                torch.cuda.synchronize()
+                lap[f"{m}^3_{'hybrid_sgs' if smoother == 2 else 'mcsgs'}"] = {
+                    "levels": lev, "iterations": rl.iterations, "half_step_exit": bool(rl.half_step),
+                    "time_to_1e8_ms": (time.perf_counter() - q0) * 1e3, "setup_ms": rl.setup_ms,
+                    "solve_ms": rl.solve_ms, "true_rel_residual": rl.true_rel_residual}
+            del lrp, lci, lv, lb
+        lap["paper_one_process"] = {"80^3": {"levels": 5, "iterations": 8}, "256^3": {"iterations": 6}}
+        log("laplace: " + ", ".join(f"{k} it={v['iterations']} lev={v['levels']}" for k, v in lap.items()
+                                    if "levels" in v and "iterations" in v and k != "paper_one_process"))
+        bic["laplace_bicgstab_fp64_vcycle"] = lap
 
     avg_launch_ms = sweep_ms / max(sweep_launches, 1)
     bytes_per_launch = sweep_bytes / max(sweep_launches, 1)
