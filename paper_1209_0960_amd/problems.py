@@ -226,6 +226,40 @@ def jump_cube(n: int, seed: int = 5) -> CSRSystem:
     return CSRSystem(rowptr, colind, vals, _rhs(rng, order), (n, n, n), order)
 
 
+def manufactured_exact(x, y, z) -> np.ndarray:
+    """u = exp(-|x|^2) of the manufactured Poisson problem."""
+    return np.exp(-(x * x + y * y + z * z))
+
+
+def manufactured(n: int) -> tuple:
+    """The Poisson problem with a known solution of the paper's helics3a runs
+    (Sec. 5): -Laplace u = f in (0,1)^3, u = g on the boundary.  The printed
+    pair is inconsistent (for u = exp(|x|), -Laplace u = -(1 + 2/|x|) exp(|x|)),
+    so the consistent pair u = exp(-|x|^2), f = (6 - 4|x|^2) exp(-|x|^2) is
+    used, with g = u.  K = 1 gives the matrix of `poisson`; with the dropped
+    factor h, row i reads sum_faces t (u_i - u_j) = h^2 f(x_i) + 2 g(c) summed
+    over the centres c of its boundary faces (Dirichlet data at distance h/2).
+    Returns (system, exact u at the cell centres in row order); the
+    discrete solution converges to it as O(h^2)."""
+    h = 1.0 / n
+    K = field_constant(n, (n, n, n))
+    rowptr, colind, vals, order = ccfv7(K)
+    c = (np.arange(n) + 0.5) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    r2 = X * X + Y * Y + Z * Z
+    b = h * h * (6.0 - 4.0 * r2) * np.exp(-r2)
+    # one term per boundary face (corner and edge cells have several)
+    b[:, :, 0] += 2.0 * manufactured_exact(0.0, Y[:, :, 0], Z[:, :, 0])
+    b[:, :, -1] += 2.0 * manufactured_exact(1.0, Y[:, :, -1], Z[:, :, -1])
+    b[:, 0, :] += 2.0 * manufactured_exact(X[:, 0, :], 0.0, Z[:, 0, :])
+    b[:, -1, :] += 2.0 * manufactured_exact(X[:, -1, :], 1.0, Z[:, -1, :])
+    b[0, :, :] += 2.0 * manufactured_exact(X[0, :, :], Y[0, :, :], 0.0)
+    b[-1, :, :] += 2.0 * manufactured_exact(X[-1, :, :], Y[-1, :, :], 1.0)
+    u = manufactured_exact(X, Y, Z)
+    sysm = CSRSystem(rowptr, colind, vals, np.ascontiguousarray(b.ravel()[order]), (n, n, n), order)
+    return sysm, np.ascontiguousarray(u.ravel()[order])
+
+
 def from_field(K: np.ndarray, seed: int = 0) -> CSRSystem:
     nz, ny, nx = K.shape
     rowptr, colind, vals, order = ccfv7(K)
