@@ -25,7 +25,7 @@ STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID_ARG", 2: "AMG_ERR_BAD_DIAGONAL", 3: "
 ERR_INVALID_ARG, ERR_BAD_DIAGONAL, ERR_NOT_SYMMETRIC, ERR_NOT_SPD = 1, 2, 3, 4
 ERR_COARSENING_STALLED, ERR_OUT_OF_MEMORY, ERR_BREAKDOWN, ERR_NOT_CONVERGED = 5, 6, 7, 8
 ERR_HIP, ERR_UNSUPPORTED = 9, 10
-SMOOTHER_MCSGS, SMOOTHER_L1_JACOBI = 0, 1
+SMOOTHER_MCSGS, SMOOTHER_L1_JACOBI, SMOOTHER_HYBRID_SGS = 0, 1, 2
 KIND_SPMV_F64, KIND_SWEEP, KIND_RESTRICT, KIND_PROLONG, KIND_CG_VEC, KIND_COARSE_LEVELS, KIND_OTHER = range(7)
 
 
