@@ -392,6 +392,34 @@ def main():
         log("laplace: " + ", ".join(f"{k} it={v['iterations']} lev={v['levels']}" for k, v in lap.items()
                                     if "levels" in v and "iterations" in v and k != "paper_one_process"))
         bic["laplace_bicgstab_fp64_vcycle"] = lap
+        # The paper's other workloads at its one-process sizes: the
+        # manufactured Poisson problem at 190^3 (Table 3: 5 levels, It = 8;
+        # solution error against exp(-|x|^2)) and the jump-coefficient cube at
+        # 80^3 (Table 6: 5 levels, It = 9).
+        wl = {}
+        sm, um = P.manufactured(190)
+        sj = P.jump_cube(80)
+        for name, sysw in (("manufactured_190^3", sm), ("jump_cube_80^3", sj)):
+            wrp, wci, wv, wb = A.to_device(sysw)
+            for smoother in (0, 2):
+                torch.cuda.synchronize()
+                q0 = time.perf_counter()
+                h = A.Hierarchy(wrp, wci, wv, smoother=smoother)
+                xw, rw = h.solve(wb, rtol=1e-8, method="bicgstab")
+                lev = h.levels
+                h.close()
+                torch.cuda.synchronize()
+                rec = {"levels": lev, "iterations": rw.iterations, "time_to_1e8_ms": (time.perf_counter() - q0) * 1e3,
+                       "setup_ms": rw.setup_ms, "solve_ms": rw.solve_ms, "true_rel_residual": rw.true_rel_residual}
+                if sysw is sm:
+                    rec["max_error_vs_exact"] = float((xw.cpu() - torch.from_numpy(um)).abs().max())
+                wl[f"{name}_{'hybrid_sgs' if smoother == 2 else 'mcsgs'}"] = rec
+            del wrp, wci, wv, wb
+        wl["paper_one_process"] = {"manufactured_190^3": {"levels": 5, "iterations": 8},
+                                   "jump_cube_80^3": {"levels": 5, "iterations": 9}}
+        log("workloads: " + ", ".join(f"{k} it={v['iterations']} lev={v['levels']}" for k, v in wl.items()
+                                      if k != "paper_one_process"))
+        bic["paper_workloads_bicgstab_fp64_vcycle"] = wl
 
     avg_launch_ms = sweep_ms / max(sweep_launches, 1)
     bytes_per_launch = sweep_bytes / max(sweep_launches, 1)

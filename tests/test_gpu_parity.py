@@ -237,3 +237,18 @@ def test_graph_replays_match_eager(A, fp32):
         for h in hists:
             for a, c in zip(h, ref):
                 assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_vcycle_hybrid_large_tiles(A, fp32):
+    """Hybrid smoother with 1024-row tiles: a tile's couplings no longer fit
+    the 64 KiB LDS staging (coarse levels, and level 0 in FP64), so those
+    sweeps run with the iterate alone in LDS; FP32 level 0 still stages
+    everything.  Both paths against the oracle."""
+    s = system("hetero_24")
+    rp, ci, v, b = dev(s)
+    with A.Hierarchy(rp, ci, v, smoother=2, tile_rows=1024, vcycle_fp32=fp32) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, smoother=2, tile_rows=1024, vcycle_fp32=fp32)
+        z = hg.precond(b)
+        torch.cuda.synchronize()
+        assert rel(z.cpu().numpy(), ho.vcycle(s.b)) <= (1e-5 if fp32 else 1e-12)
