@@ -147,6 +147,9 @@ AMG_API amg_status pcg_solve(amg_hierarchy *h, const double *b, double *x, doubl
  * preconditioned by one V-cycle of h for each of the two directions p and s.
  * x holds x0 on entry and the solution on return.  Vectors, errors, streams
  * and blocking as in pcg_solve (one iteration per host round trip; no graph).
+ * Each call takes 5 n + 16 K doubles of device memory through the allocator
+ * (r, r~, p, v, t, partial sums) beyond the solve context's vectors and
+ * returns them before it returns.
  * The stop test ||.||_2^2 <= (rtol ||r_0||_2)^2 is made on s (half step: x =
  * x_{k-1} + alpha M p, *half_step = 1) and on r_k; info->iterations is the
  * iteration k it stopped in.  AMG_ERR_BREAKDOWN when r~.v, t.t, omega or r~.r

@@ -809,7 +809,9 @@ amg_status amg_estimate_bytes(int32_t n, int32_t nnz, const amg_params* p, int32
   const double vb = f32 ? 4.0 : 8.0;
   // Level 0 in solve order: SELL-64 off-diagonals (column + FP64 value, + FP32
   // copy), diagonal(s), permutation, row pointers, aggregate map and members.
-  const double lev0 = f32 ? 16.0 * Z + 12.0 * N : 12.0 * Z + 16.0 * N;
+  // The hybrid smoother adds two 16-bit wavefront steps per row.
+  const double lev0 = (f32 ? 16.0 * Z + 12.0 * N : 12.0 * Z + 16.0 * N) +
+                      (p->smoother == AMG_SMOOTHER_HYBRID_SGS ? 4.0 * N : 0.0);
   // Coarser levels and slice padding stay below 35% of level 0 for aggregates
   // of 8-12 rows; the dense coarsest inverse and its factorisation workspace.
   const double cm = std::min<double>(std::max(p->coarse_max, 1), 4096);
