@@ -201,7 +201,7 @@ enum {
   BS_SS,       // s.s of the half step
   BS_RR,       // r.r after the update
   BS_RR0,      // r_0.r_0
-  BS_FLAG,     // 1.0 = breakdown: updates stop
+  BS_FLAG,     // breakdown, updates stop: 1 at alpha, 2 at omega, 3 at beta (x = x_k)
   BS_HALF,     // 1.0 = converged at the half step (x = x + alpha M p): updates stop
   BS_TMP,      // ||b - A x||^2 at the end
   BS_TMP2,     // ||b||^2 at the end

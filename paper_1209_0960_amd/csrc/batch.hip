@@ -1226,7 +1226,9 @@ amg_status bicgstab_run(Hierarchy& H, const double* b, double* x, double rtol, i
     bcg_finish(BF_BETA, nb, part, sc, tol2, s);
     bcg_dir(n, r, v, p, C.r, rt, sc, 0, s);
     read();
-    if (sh[BS_FLAG] != 0.0) {
+    // a breakdown at beta comes after iteration k is complete (as in the
+    // oracle, it counts and is recorded); earlier ones leave it uncounted
+    if (sh[BS_FLAG] != 0.0 && sh[BS_FLAG] != 3.0) {
       st = AMG_ERR_BREAKDOWN;
       break;
     }
@@ -1238,7 +1240,10 @@ amg_status bicgstab_run(Hierarchy& H, const double* b, double* x, double rtol, i
       st = AMG_OK;
     } else {
       rel = std::sqrt(sh[BS_RR]) / r0;
-      if (sh[BS_RR] <= tol2) st = AMG_OK;
+      if (sh[BS_RR] <= tol2)
+        st = AMG_OK;
+      else if (sh[BS_FLAG] != 0.0)
+        st = AMG_ERR_BREAKDOWN;
     }
     if (res_hist) res_hist[k] = rel;
   }

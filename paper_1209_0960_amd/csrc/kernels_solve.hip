@@ -1414,7 +1414,7 @@ __global__ __launch_bounds__(NT) void kk_bcg_finish(int op, int nb, const double
     case BF_ALPHA:
       if (bcg_stopped(sc)) break;
       if (!(a[0] != 0.0) || !is_finite_d(a[0]))
-        sc[BS_FLAG] = 1.0;
+        sc[BS_FLAG] = 1.0;  // x unchanged
       else
         sc[BS_ALPHA] = sc[BS_RHO] / a[0];
       break;
@@ -1427,7 +1427,7 @@ __global__ __launch_bounds__(NT) void kk_bcg_finish(int op, int nb, const double
       if (bcg_stopped(sc)) break;
       const double om = a[0] / a[1];
       if (!(a[1] > 0.0) || !is_finite_d(a[1]) || !(om != 0.0) || !is_finite_d(om))
-        sc[BS_FLAG] = 1.0;
+        sc[BS_FLAG] = 2.0;  // x holds the half step
       else
         sc[BS_OMEGA] = om;
     } break;
@@ -1436,7 +1436,7 @@ __global__ __launch_bounds__(NT) void kk_bcg_finish(int op, int nb, const double
       sc[BS_RR] = a[1];
       if (a[1] <= tol2) break;  // converged: the host stops
       if (!(a[0] != 0.0) || !is_finite_d(a[0])) {
-        sc[BS_FLAG] = 1.0;
+        sc[BS_FLAG] = 3.0;  // after the full iteration
       } else {
         sc[BS_BETA] = (a[0] / sc[BS_RHO]) * (sc[BS_ALPHA] / sc[BS_OMEGA]);
         sc[BS_RHO] = a[0];
