@@ -147,6 +147,10 @@ AMG_API amg_status pcg_solve(amg_hierarchy *h, const double *b, double *x, doubl
  * preconditioned by one V-cycle of h for each of the two directions p and s.
  * x holds x0 on entry and the solution on return.  Vectors, errors, streams
  * and blocking as in pcg_solve (one iteration per host round trip; no graph).
+ * BiCGSTAB assumes a fixed preconditioner: with vcycle_fp32 the cycle's
+ * rounding makes it vary slightly, and the iteration can stall just above a
+ * tight rtol (observed near 2.5e-8 for 1e-8 on one 256^3 system); the FP64
+ * cycle, or flexible CG for the FP32 cycle, avoids that.
  * Each call takes 5 n + 16 K doubles of device memory through the allocator
  * (r, r~, p, v, t, partial sums) beyond the solve context's vectors and
  * returns them before it returns.
