@@ -31,10 +31,11 @@ constexpr int SLICES_PB = 4;     // slices per block of the sweep / residual ker
 
 // Number of partial sums of a reduction over n rows (or slices): depends on
 // the entry alone.
-// Row reductions stream (threads stride over rows, 64 per thread at most);
+// Row reductions stream (threads stride over rows; 4096 blocks keep enough
+// waves in flight at 256^3, more measured no faster);
 // slice reductions are chains of dependent loads per wavefront (at most 8
 // slices per wavefront), so they get more blocks.
-int red_blocks_rows(int n) { return std::min(1024, std::max(1, cdiv(n, 2048))); }
+int red_blocks_rows(int n) { return std::min(4096, std::max(1, cdiv(n, 2048))); }
 int red_blocks_slices(int nsl) { return std::min(RED_BLOCKS, std::max(1, cdiv(nsl, 32))); }
 
 // Process-wide reuse of pinned host buffers, streams and events: creating and
