@@ -61,3 +61,22 @@ def test_header_compiles_as_c_and_matches_ctypes_layout(tmp_path):
     from paper_1209_0960_amd import amg as A
     assert sizes == [ctypes.sizeof(A.Params), ctypes.sizeof(A.SolveInfo), ctypes.sizeof(A.CSR),
                      A.Params.use_graphs.offset]
+
+
+def test_bicgstab_and_hybrid_host_checks():
+    """Host-only paths of the new calls: bicgstab_solve rejects a NULL
+    hierarchy and bad arguments before touching the device; the footprint
+    estimate counts the hybrid smoother's per-row steps."""
+    if not os.path.exists(LIB):
+        pytest.skip("HIP library not built")
+    from paper_1209_0960_amd import amg as A
+    L = A.lib()
+    assert L.bicgstab_solve(None, None, None, 1e-8, 10, None, None, None, None, None) == A.ERR_INVALID_ARG
+    p = A.default_params()
+    sizes = []
+    for smoother in (A.SMOOTHER_MCSGS, A.SMOOTHER_HYBRID_SGS):
+        p.smoother = smoother
+        hier = ctypes.c_size_t(0)
+        assert L.amg_estimate_bytes(1000000, 7000000, ctypes.byref(p), 1, None, ctypes.byref(hier), None) == A.OK
+        sizes.append(hier.value)
+    assert sizes[1] > sizes[0]
