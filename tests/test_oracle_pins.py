@@ -540,15 +540,16 @@ def test_validate_error_paths():
     assert O.validate(s.rowptr, s.colind, v) == O.INVALID
 
 
-def test_fp32_vcycle_close_to_fp64():
+@pytest.mark.parametrize("smoother", [0, 2])
+def test_fp32_vcycle_close_to_fp64(smoother):
     s = P.lognormal(12, seed=9)
-    H64 = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60)
-    H32 = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, vcycle_fp32=1)
+    H64 = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, smoother=smoother)
+    H32 = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60, vcycle_fp32=1, smoother=smoother)
     z64 = H64.vcycle(s.b)
     z32 = H32.vcycle(s.b)
     assert np.abs(z32 - z64).max() <= 1e-4 * np.abs(z64).max()
-    out = H32.pcg(s.b)
-    assert out["status"] == O.OK and out["true_rel_residual"] <= 1.5e-8
+    for out in (H32.pcg(s.b), H32.bicgstab(s.b)):
+        assert out["status"] == O.OK and out["true_rel_residual"] <= 1.5e-8
 
 
 def test_fcg_directions_stay_conjugate_with_asymmetric_cycle():
