@@ -9,14 +9,18 @@ permeability K = exp(2 g') with g' a 2x2x2 box-filtered N(0,1) field
 (seed 1), 7-point cell-centred finite volumes with harmonic faces, RHS
 uniform[-1,1], x0 = 0.  Inputs are resident in HBM before timing starts.
 
-Three more sections go into the same line: "large" (layered 512^3, per-kernel
-GB/s and the FP64 solution error against a 1e-12 reference), "batched" (64
+More sections go into the same line: "paper_solver" in config (BiCGSTAB,
+the paper's Krylov method, with multicolour and hybrid SGS on the same system;
+BiCGSTAB iteration counts on the paper's Laplace, manufactured Poisson and
+jump-coefficient problems beside its published counts), "large" (layered
+512^3, per-kernel GB/s and the FP64 solution error against a 1e-12
+reference), "batched" (64
 uneven systems with 4 right-hand sides each, amg_setup_batched +
 pcg_solve_batched against a loop of single solves) and "serving" (a request
 stream served with continuous batching against serial plain-FP64 solves, with
 p50/p99 latency).
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
 import argparse
 import hashlib
@@ -264,8 +268,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of this "
-              "build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
