@@ -252,3 +252,32 @@ def test_vcycle_hybrid_large_tiles(A, fp32):
         z = hg.precond(b)
         torch.cuda.synchronize()
         assert rel(z.cpu().numpy(), ho.vcycle(s.b)) <= (1e-5 if fp32 else 1e-12)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_user_stream_ordering_is_exact(A, fp32):
+    """Calls run after the caller's earlier work on its stream and leave their
+    results ready on it: a right-hand side still being produced on a busy side
+    stream is waited for, and the solution is consumed there at once.
+    Doubling b is exact in floating point, so x(2b) = 2 x(b) bit for bit (CG,
+    BiCGSTAB, the preconditioner)."""
+    s = system("hetero_24")
+    rp, ci, v, b = dev(s)
+    busy = torch.ones(1 << 24, device="cuda", dtype=torch.float64)
+    side = torch.cuda.Stream()
+    with A.Hierarchy(rp, ci, v, vcycle_fp32=fp32) as h:
+        refs = {m: h.solve(b, method=m)[0] for m in ("cg", "bicgstab")}
+        zref = h.precond(b)
+        torch.cuda.synchronize()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for m in ("cg", "bicgstab"):
+                for _ in range(20):
+                    busy.mul_(1.0)  # work ahead of the right-hand side on this stream
+                x2, _ = h.solve(b * 2.0, method=m)
+                assert torch.equal(x2 * 0.5, refs[m]), m
+            for _ in range(20):
+                busy.mul_(1.0)
+            z2 = h.precond(b * 2.0) * 0.5
+        side.synchronize()
+        assert torch.equal(z2, zref)
