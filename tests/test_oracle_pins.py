@@ -659,3 +659,22 @@ def test_bicgstab_breakdown_and_trivial_cases():
     assert z["status"] == O.OK and z["iterations"] == 0 and not z["x"].any()
     m = H.bicgstab(s.b, maxit=0)
     assert m["status"] == O.NOT_CONVERGED and m["iterations"] == 0
+
+
+def test_setup_invariant_under_scaling_by_two():
+    """Strength compares ratios of products (eqs. (symmetric_strong1),
+    (symmetric_strong2)) and aggregation uses only the resulting flags, so
+    scaling A by 2 (exact in floating point) leaves every flag, aggregate,
+    colour and pattern unchanged and doubles every Galerkin value exactly."""
+    s = P.lognormal(12, seed=4)
+    H1 = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=60)
+    H2 = O.Hierarchy(s.rowptr, s.colind, 2.0 * s.vals, coarse_max=60)
+    assert H1.levels == H2.levels >= 2
+    for l in range(H1.levels):
+        a, c = H1.level(l), H2.level(l)
+        assert np.array_equal(a.rowptr, c.rowptr) and np.array_equal(a.colind, c.colind)
+        assert np.array_equal(2.0 * a.vals, c.vals)
+        assert a.ncol == c.ncol and np.array_equal(a.colour, c.colour)
+        if l < H1.levels - 1:
+            assert np.array_equal(a.strong, c.strong) and np.array_equal(a.iso, c.iso)
+            assert np.array_equal(a.agg, c.agg)
