@@ -439,6 +439,52 @@ __device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d,
     db = max(db, __shfl_xor(db, o, WAVE));
   }
   __syncthreads();
+  if (T <= 2 * WAVE && W <= 8) {
+    // Small tiles with few couplings (the finest levels): each lane keeps its
+    // two rows' couplings, steps, source and diagonal in registers, so a step
+    // is one round of LDS gathers; same entry order and arithmetic.
+    int cq[2], sfq[2], sbq[2];
+    V aq[2][8], sq[2][R], dq[2];
+    int jq[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = lane + h * WAVE;
+      const bool on = q < nt;
+      cq[h] = on ? (int)cn[q] : 0;
+      sfq[h] = on ? (int)stf[q] : -1;
+      sbq[h] = on ? (int)stb[q] : -1;
+      dq[h] = on ? dl[q] : (V)1;
+#pragma unroll
+      for (int k = 0; k < R; ++k) sq[h][k] = on ? sr[(size_t)q * R + k] : (V)0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool e = u < cq[h];
+        aq[h][u] = e ? ev[(size_t)q * W + u] : (V)0;
+        jq[h][u] = e ? (int)ec[(size_t)q * W + u] : 0;
+      }
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+      const int depth = dir == 0 ? df : db;
+      for (int step = 0; step <= depth; ++step) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if ((dir == 0 ? sfq[h] : sbq[h]) != step) continue;
+          const int q = lane + h * WAVE;
+          V acc[R];
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] = 0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (u < cq[h])
+#pragma unroll
+              for (int k = 0; k < R; ++k) acc[k] = madd(aq[h][u], xt[(size_t)jq[h][u] * R + k], acc[k]);
+#pragma unroll
+          for (int k = 0; k < R; ++k) xt[(size_t)q * R + k] = (sq[h][k] - acc[k]) / dq[h];
+        }
+        __syncthreads();
+      }
+    }
+  } else
   for (int dir = 0; dir < 2; ++dir) {
     const unsigned short* st = dir == 0 ? stf : stb;
     const int depth = dir == 0 ? df : db;
