@@ -91,6 +91,8 @@ def lib():
         L.orc_coarse_factor.argtypes = [C.c_void_p, F64P]
         L.orc_vcycle.restype = None
         L.orc_vcycle.argtypes = [C.c_void_p, F64P, F64P]
+        L.orc_smooth.restype = None
+        L.orc_smooth.argtypes = [C.c_void_p, C.c_int, C.c_int, F64P, F64P]
         L.orc_pcg.restype = C.c_int
         L.orc_pcg.argtypes = [C.c_void_p, F64P, F64P, C.c_double, C.c_int, C.POINTER(C.c_int), C.c_void_p,
                               C.c_void_p, C.POINTER(C.c_double)]
@@ -275,6 +277,12 @@ class Hierarchy:
         z = np.zeros(self.n, np.float64)
         lib().orc_vcycle(self._h, np.ascontiguousarray(r, np.float64), z)
         return z
+
+    def smooth(self, l: int, b: np.ndarray, x: np.ndarray, fp32: bool = False) -> np.ndarray:
+        """One application of level l's smoother to a copy of x."""
+        x = np.ascontiguousarray(x, np.float64).copy()
+        lib().orc_smooth(self._h, l, int(fp32), np.ascontiguousarray(b, np.float64), x)
+        return x
 
     def pcg(self, b, x0=None, rtol=1e-8, maxit=1000, keep_iterates=False):
         n = self.n

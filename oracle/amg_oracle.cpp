@@ -1022,6 +1022,26 @@ void orc_coarse_factor(void* h, double* L) {
 
 void orc_vcycle(void* h, const double* r, double* z) { precond(*(Hier*)h, r, z); }
 
+// One application of level l's smoother (one symmetric Gauss-Seidel step, one
+// l1-Jacobi sweep or one hybrid step, as the hierarchy's parameters select) to
+// x in place, in FP64 (fp32 = 0) or with the level's FP32 values (fp32 = 1:
+// b and x are rounded to float first and the result widened back).
+void orc_smooth(void* h, int l, int fp32, const double* b, double* x) {
+  const Hier& H = *(const Hier*)h;
+  const int n = H.lev[l].A.n;
+  if (fp32) {
+    std::vector<float> bf(n), xf(n);
+    for (int i = 0; i < n; ++i) {
+      bf[i] = (float)b[i];
+      xf[i] = (float)x[i];
+    }
+    smooth<float>(H, l, bf.data(), xf.data());
+    for (int i = 0; i < n; ++i) x[i] = (double)xf[i];
+  } else {
+    smooth<double>(H, l, b, x);
+  }
+}
+
 // Preconditioned CG (x0 given in x) or flexible CG (Polak-Ribiere beta).
 // res_hist[k] = ||r_k|| / ||r_0||; iter_hist (n*(maxit+1), nullable) = x_k.
 int orc_pcg(void* h, const double* b, double* x, double rtol, int maxit, int* iters, double* res_hist,
