@@ -166,8 +166,10 @@ AMG_API amg_status bicgstab_solve(amg_hierarchy *h, const double *b, double *x, 
                                   amg_solve_info *info, int32_t *half_step, double *res_hist, double *iter_hist,
                                   void *stream);
 
-/* Releases everything the hierarchy owns.  NULL-safe.  The hierarchy must not
- * be part of a running batch entry (amg_batch_submit). */
+/* Releases everything the hierarchy owns.  NULL-safe.  Waits until the last
+ * amg_precond_apply on the hierarchy has finished on its stream before any
+ * memory is handed back.  The hierarchy must not be part of a running batch
+ * entry (amg_batch_submit). */
 AMG_API void amg_free(amg_hierarchy *h);
 
 /* ---- many systems -------------------------------------------------------- */

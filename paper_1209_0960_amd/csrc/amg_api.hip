@@ -197,6 +197,11 @@ void Hierarchy::free_one(void* ptr, hipStream_t s) {
 }
 
 void Hierarchy::release(hipStream_t s) {
+  if (apply_done) {  // the last preconditioner application may still read the arrays below
+    (void)hipEventSynchronize(apply_done);
+    (void)hipEventDestroy(apply_done);
+    apply_done = nullptr;
+  }
   if (single) {  // its launch tables and graph refer to the arrays below
     batch_destroy(single);
     single = nullptr;

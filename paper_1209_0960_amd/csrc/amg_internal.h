@@ -160,6 +160,10 @@ struct Hierarchy {
   size_t bytes = 0;
   std::vector<std::pair<void*, size_t>> owned;
   hipStream_t setup_stream = nullptr;
+  // Recorded on the caller's stream after each amg_precond_apply (which runs
+  // there, asynchronously); release() waits for it before any buffer returns
+  // to the allocator.
+  hipEvent_t apply_done = nullptr;
 
   // Frees one buffer obtained from alloc() (no-op for NULL).
   void free_one(void* ptr, hipStream_t s);

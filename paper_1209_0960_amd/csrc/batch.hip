@@ -1140,6 +1140,8 @@ void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us) {
   gather_rhs(L0.n, 1, L0.perm, r, E.ctx.r, us);
   issue_launches(B.papply.L, 0, B.papply.L.size(), B.papply.tab_d, B.desc_d, B.desc_h, 1, B.fp32, us);
   scatter_rhs(L0.n, 1, L0.perm, E.ctx.z, z, us);
+  if (!H.apply_done) AMG_HIP(hipEventCreateWithFlags(&H.apply_done, hipEventDisableTiming));
+  AMG_HIP(hipEventRecord(H.apply_done, us));
 }
 
 // BiCGSTAB (van der Vorst; the outer solver of Sec. 5) with right
