@@ -126,6 +126,23 @@ AMG_API amg_status amg_setup(const amg_csr *A, const amg_params *p, void *stream
  * Asynchronous: returns after enqueueing. */
 AMG_API amg_status amg_precond_apply(amg_hierarchy *h, const double *r, double *z, void *stream);
 
+/* amg_precond_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same launches and the same result bit for bit, with the
+ * V-cycle's vectors (level-0 r and z in solve order; per level the iterate,
+ * right-hand side and residual, in the cycle's precision) taken from a fixed
+ * file-scope array of 64 MiB per device instead of the allocator.  No device
+ * memory is allocated or freed by the call.  A hierarchy whose vectors need
+ * more than 64 MiB (about 27 B per level-0 row in FP64, 30 B with the FP32
+ * cycle: up to about 2.2 M rows) or that uses the one-workgroup tail
+ * (tail_rows > 0) is rejected with AMG_ERR_UNSUPPORTED before any work is
+ * enqueued.  Every call on one device shares that device's array, which
+ * keeps the last call's contents (every value a cycle reads is written by it
+ * first): calls that overlap on one device, on any streams, race and must be
+ * ordered by the caller.  Asynchronous on `stream`; the caller synchronises
+ * that stream before amg_free of the hierarchy. */
+AMG_API amg_status amg_precond_apply_noalloc(amg_hierarchy *h, const double *r, double *z, void *stream);
+
 /* Preconditioned CG (flexible CG if the hierarchy was built with flexible=1)
  * for A x = b with x holding x0 on entry and the solution on return.  Stops
  * when ||r_k||_2 <= rtol ||r_0||_2 (recursive residual) or after maxit

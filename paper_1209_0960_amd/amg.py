@@ -77,6 +77,8 @@ def lib():
         L.amg_setup.argtypes = [C.POINTER(CSR), C.POINTER(Params), vp, C.POINTER(vp)]
         L.amg_precond_apply.restype = st
         L.amg_precond_apply.argtypes = [vp, vp, vp, vp]
+        L.amg_precond_apply_noalloc.restype = st
+        L.amg_precond_apply_noalloc.argtypes = [vp, vp, vp, vp]
         L.pcg_solve.restype = st
         L.pcg_solve.argtypes = [vp, vp, vp, C.c_double, i32, C.POINTER(SolveInfo), vp, vp, vp]
         L.bicgstab_solve.restype = st
@@ -272,6 +274,10 @@ class Batch:
 
 def amg_precond_apply(h, r: torch.Tensor, z: torch.Tensor, stream=None):
     _check(lib().amg_precond_apply(h, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def amg_precond_apply_noalloc(h, r: torch.Tensor, z: torch.Tensor, stream=None):
+    _check(lib().amg_precond_apply_noalloc(h, _ptr(r), _ptr(z), _stream(stream)))
 
 
 @dataclass

@@ -493,6 +493,14 @@ amg_status amg_precond_apply(amg_hierarchy* h, const double* r, double* z, void*
   return guarded([&] { precond_run(h->H, r, z, S(stream)); });
 }
 
+amg_status amg_precond_apply_noalloc(amg_hierarchy* h, const double* r, double* z, void* stream) {
+  if (!h || !r || !z || r == z) {
+    set_error("invalid argument");
+    return AMG_ERR_INVALID_ARG;
+  }
+  return guarded([&] { precond_noalloc_run(h->H, r, z, S(stream)); });
+}
+
 amg_status pcg_solve(amg_hierarchy* h, const double* b, double* x, double rtol, int32_t maxit, amg_solve_info* info,
                      double* res_hist, double* iter_hist, void* stream) {
   if (!h || !b || !x || maxit < 0 || !(rtol >= 0.0)) {

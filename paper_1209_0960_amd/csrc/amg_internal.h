@@ -368,6 +368,11 @@ void batch_destroy(Batch* B);
 amg_status pcg_run(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
                    double* res_hist, double* iter_hist, hipStream_t us);
 void precond_run(Hierarchy& H, const double* r, double* z, hipStream_t us);
+// The same V-cycle with its vectors in the library's fixed per-device scratch
+// array (no allocation); fails with AMG_ERR_UNSUPPORTED when they do not fit.
+void precond_noalloc_run(Hierarchy& H, const double* r, double* z, hipStream_t us);
+size_t precond_noalloc_bytes(const Hierarchy& H);
+size_t precond_noalloc_capacity();
 // bicgstab_solve (Sec. 5: BiCGSTAB with the V-cycle applied twice per iteration).
 amg_status bicgstab_run(Hierarchy& H, const double* b, double* x, double rtol, int maxit, amg_solve_info* info,
                         int* half_step, double* res_hist, double* iter_hist, hipStream_t us);

@@ -264,6 +264,46 @@ void check_uniform(Batch& B, const Hierarchy& H) {
     fail(AMG_ERR_INVALID_ARG, "hierarchies of one batch with the hybrid smoother must share tile_rows");
 }
 
+// The fields of a level's descriptor that come from the hierarchy (matrix,
+// transfer, smoother and coarsest-solve data); the vectors are the caller's.
+void level_desc(BDesc& d, const Hierarchy& H, int l) {
+  const int Lc = (int)H.lev.size() - 1;
+  const Level& L = H.lev[l];
+  d.srow = L.srow;
+  d.soff = L.soff;
+  d.scol = L.scol;
+  d.sval64 = L.sval;
+  d.dg64 = L.dg;
+  d.l164 = L.l1;
+  d.sval32 = L.sval32;
+  d.dg32 = L.dg32;
+  d.l132 = L.l1_32;
+  d.rowptr = L.rowptr;
+  d.colind = L.colind;
+  d.vals = L.vals;
+  if (l < Lc) {
+    d.mptr = L.mptr;
+    d.members = L.members;
+    d.agg = L.agg;
+    d.cinv = L.cinv;
+  } else {
+    d.Ainv = H.Ainv;
+  }
+  d.sptr = L.sptr_d;
+  d.ncol = L.ncol;
+  d.hsf = L.hsf;
+  d.hsb = L.hsb;
+  d.T = L.T;
+  d.hdf = L.hdf;
+  d.hdb = L.hdb;
+  d.hw = L.hw;
+  d.n = L.n;
+  d.nc = L.nc;
+  d.nsl = L.nsl;
+  d.nL = H.nL;
+  d.omega = H.p.omega;
+}
+
 // Allocates the vectors of `slot` for hierarchy H and writes its descriptors.
 void bind_slot(Batch& B, int slot, Hierarchy& H) {
   Entry& E = B.ent[slot];
@@ -312,28 +352,10 @@ void bind_slot(Batch& B, int slot, Hierarchy& H) {
     BDesc& d = B.desc_h[B.desc_index(slot, l)];
     d = BDesc{};
     if (l > Lc) continue;
-    const Level& L = H.lev[l];
-    d.srow = L.srow;
-    d.soff = L.soff;
-    d.scol = L.scol;
-    d.sval64 = L.sval;
-    d.dg64 = L.dg;
-    d.l164 = L.l1;
-    d.sval32 = L.sval32;
-    d.dg32 = L.dg32;
-    d.l132 = L.l1_32;
-    d.rowptr = L.rowptr;
-    d.colind = L.colind;
-    d.vals = L.vals;
+    level_desc(d, H, l);
     if (l < Lc) {
-      d.mptr = L.mptr;
-      d.members = L.members;
-      d.agg = L.agg;
-      d.cinv = L.cinv;
       d.xc = C.x[l + 1];
       d.bc = C.b[l + 1];
-    } else {
-      d.Ainv = H.Ainv;
     }
     d.x = C.x[l];
     d.b = C.b[l];
@@ -349,19 +371,6 @@ void bind_slot(Batch& B, int slot, Hierarchy& H) {
     d.scal = B.scal_of(slot);
     d.ctl = B.ctl_d + (size_t)slot * CTL_INTS;
     d.active = 0;
-    d.sptr = L.sptr_d;
-    d.ncol = L.ncol;
-    d.hsf = L.hsf;
-    d.hsb = L.hsb;
-    d.T = L.T;
-    d.hdf = L.hdf;
-    d.hdb = L.hdb;
-    d.hw = L.hw;
-    d.n = L.n;
-    d.nc = L.nc;
-    d.nsl = L.nsl;
-    d.nL = H.nL;
-    d.omega = H.p.omega;
   }
   B.desc_dirty = true;
   E.bound = &H;
@@ -1363,6 +1372,121 @@ size_t batch_entry_bytes(const Batch& B) {
   size_t s = 0;
   for (const Entry& E : B.ent) s += E.ctx.bytes;
   return s;
+}
+
+// ------------------------------------------------------------------ fixed scratch
+// amg_precond_apply_noalloc takes the V-cycle's vectors (level-0 r and z in
+// solve order; per level the iterate, right-hand side and residual) from this
+// file-scope array instead of the allocator.  Each device that the library
+// runs on holds its own copy until the process ends.  In host code `scratch`
+// is only the host-side name of the symbol: its device address comes from
+// hipGetSymbolAddress, once per device (with that device current), and only
+// that address is handed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device: device address of `scratch`
+
+void* scratch_device_ptr() {
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    AMG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(AMG_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// The vectors of one V-cycle application, laid out as in a solve context of
+// one right-hand side (the FP64 cycle works on r and z directly at level 0).
+struct CycleVecs {
+  double *r = nullptr, *z = nullptr;
+  void *x[MAX_LEVELS] = {}, *b[MAX_LEVELS] = {}, *t[MAX_LEVELS] = {};
+};
+
+void carve_cycle(const Hierarchy& H, bool fp32, Carver& cv, CycleVecs& v) {
+  const int Lc = (int)H.lev.size() - 1;
+  const size_t vb = fp32 ? 4 : 8;
+  const size_t n0 = (size_t)H.lev[0].n;
+  v.r = static_cast<double*>(cv.take(n0 * sizeof(double)));
+  v.z = static_cast<double*>(cv.take(n0 * sizeof(double)));
+  for (int l = 0; l <= Lc; ++l) {
+    const size_t n = (size_t)H.lev[l].n;
+    if (l == 0 && !fp32) {
+      v.b[0] = v.r;
+      v.x[0] = v.z;
+    } else {
+      v.x[l] = cv.take(n * vb);
+      v.b[l] = cv.take(n * vb);
+    }
+    v.t[l] = l < Lc ? cv.take(n * vb) : nullptr;
+  }
+}
+}  // namespace
+
+size_t precond_noalloc_bytes(const Hierarchy& H) {
+  Carver sizing;
+  CycleVecs v;
+  carve_cycle(H, H.p.vcycle_fp32 != 0, sizing, v);
+  return sizing.off;
+}
+
+size_t precond_noalloc_capacity() { return NOALLOC_SCRATCH_BYTES; }
+
+void precond_noalloc_run(Hierarchy& H, const double* r, double* z, hipStream_t us) {
+  const int Lc = (int)H.lev.size() - 1;
+  if (Lc >= MAX_LEVELS) fail(AMG_ERR_UNSUPPORTED, "too many levels");
+  const size_t need = precond_noalloc_bytes(H);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    fail(AMG_ERR_UNSUPPORTED, "the V-cycle of this hierarchy needs " + std::to_string(need) +
+                                  " bytes of vectors, more than the fixed scratch array of " +
+                                  std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes");
+  // A host-side description of a one-entry batch: it only feeds the launch
+  // builder (no device memory, stream or event of its own).
+  Batch B;
+  B.R = 1;
+  B.cap = 1;
+  B.single = true;
+  B.ent.resize(1);
+  B.ent[0].bound = &H;
+  check_uniform(B, H);
+  if (tail_start(B, 0) != Lc)
+    fail(AMG_ERR_UNSUPPORTED, "amg_precond_apply_noalloc does not run the one-workgroup tail (tail_rows > 0)");
+  Carver cv;
+  cv.base = static_cast<char*>(scratch_device_ptr());
+  CycleVecs v;
+  carve_cycle(H, B.fp32 != 0, cv, v);
+  BDesc desc[MAX_LEVELS];
+  for (int l = 0; l <= Lc; ++l) {
+    BDesc& d = desc[l];
+    d = BDesc{};
+    level_desc(d, H, l);
+    d.x = v.x[l];
+    d.b = v.b[l];
+    d.t = v.t[l];
+    if (l < Lc) {
+      d.xc = v.x[l + 1];
+      d.bc = v.b[l + 1];
+    }
+    d.r = v.r;
+    d.z = v.z;
+    d.active = 1;
+  }
+  Builder bl(B, true);
+  build_precond(bl, B, {0}, true);
+  for (const Launch& L : bl.L)
+    if (!L.use_direct || L.op == OP_TAIL || L.op == OP_TAIL_UP)
+      fail(AMG_ERR_UNSUPPORTED, "launch without a by-value descriptor in the fixed-scratch V-cycle");
+  const Level& L0 = H.lev[0];
+  gather_rhs(L0.n, 1, L0.perm, r, v.r, us);
+  issue_launches(bl.L, 0, bl.L.size(), nullptr, nullptr, desc, 1, B.fp32, us);
+  scatter_rhs(L0.n, 1, L0.perm, v.z, z, us);
 }
 
 }  // namespace amgx

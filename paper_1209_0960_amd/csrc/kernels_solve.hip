@@ -1299,7 +1299,7 @@ void issue_launches(const std::vector<Launch>& Ls, size_t first, size_t last, co
     const Launch& L = Ls[i];
     if (L.nblk <= 0) continue;
     KTimer tm(L.kind, s, L.bytes);
-    const Item* t = tab + L.off;
+    const Item* t = L.use_direct ? nullptr : tab + L.off;  // direct launches take no table
     switch (R) {
       case 1: launch_r<1>(L, t, D, Dh, fp32, s); break;
       case 2: launch_r<2>(L, t, D, Dh, fp32, s); break;

@@ -1,0 +1,103 @@
+"""amg_precond_apply_noalloc: the V-cycle with its vectors in the library's
+fixed per-device scratch array.  Through the C ABI it must give the same
+result as amg_precond_apply bit for bit (the same kernels and arithmetic),
+on consecutive calls with a smaller system second (the array keeps the last
+call's contents), allocate nothing, and reject systems whose vectors do not
+fit the array.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1209_0960_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1209_0960_amd import amg
+    amg.lib()
+    return amg
+
+
+def dev(s):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (s.rowptr, s.colind, s.vals, s.b)]
+
+
+@pytest.mark.parametrize("fp32,smoother", [(0, 0), (1, 0), (0, 1), (1, 2), (0, 2)])
+def test_noalloc_equals_precond_apply(A, fp32, smoother):
+    big, small = P.lognormal(40, seed=6), P.lognormal(24, seed=7)
+    hs = []
+    try:
+        for s in (big, small):
+            rp, ci, v, b = dev(s)
+            hs.append((A.Hierarchy(rp, ci, v, vcycle_fp32=fp32, smoother=smoother), b))
+        # two calls in a row, the smaller system second, then the larger again
+        for h, b in (hs[0], hs[1], hs[0]):
+            z_ref = h.precond(b)
+            z = torch.full_like(b, float("nan"))
+            A.amg_precond_apply_noalloc(h.h, b, z)
+            torch.cuda.synchronize()
+            assert torch.equal(z, z_ref), (fp32, smoother, h.n)
+    finally:
+        for h, _ in hs:
+            h.close()
+
+
+def test_noalloc_allocates_nothing(A):
+    """With an allocator hook installed, the noalloc call makes no allocation
+    and leaves torch's allocated bytes unchanged; the regular call builds its
+    solve context through the hook."""
+    calls = {"alloc": 0, "free": 0}
+
+    def alloc(size, stream, ctx):
+        calls["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(size, 0, stream or 0)
+
+    def free(ptr, stream, ctx):
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    fa, ff = A.ALLOC_FN(alloc), A.FREE_FN(free)
+    A.set_allocator(fa, ff)
+    try:
+        s = P.lognormal(32, seed=8)
+        rp, ci, v, b = dev(s)
+        with A.Hierarchy(rp, ci, v) as h:
+            z = torch.empty_like(b)
+            torch.cuda.synchronize()
+            before = (dict(calls), torch.cuda.memory_allocated())
+            for _ in range(3):
+                A.amg_precond_apply_noalloc(h.h, b, z)
+            torch.cuda.synchronize()
+            assert (dict(calls), torch.cuda.memory_allocated()) == before
+            z_ref = h.precond(b)
+            torch.cuda.synchronize()
+            assert calls["alloc"] > before[0]["alloc"]
+            assert torch.equal(z, z_ref)
+    finally:
+        A.set_allocator(None, None)
+
+
+def test_noalloc_rejects_what_does_not_fit(A):
+    """About 2.6 M rows in FP64 need more than the 64 MiB array; a hierarchy
+    with the one-workgroup tail is not run either.  Both are refused before
+    any work is enqueued (the output stays untouched)."""
+    s = P.lognormal(138, seed=9)
+    rp, ci, v, b = dev(s)
+    with A.Hierarchy(rp, ci, v) as h:
+        z = torch.full_like(b, 7.0)
+        with pytest.raises(A.AMGError) as e:
+            A.amg_precond_apply_noalloc(h.h, b, z)
+        assert e.value.status == A.ERR_UNSUPPORTED and "scratch" in str(e.value)
+        torch.cuda.synchronize()
+        assert bool((z == 7.0).all())
+    del rp, ci, v, b, z
+    s = P.lognormal(16, seed=9)
+    rp, ci, v, b = dev(s)
+    with A.Hierarchy(rp, ci, v, tail_rows=1000) as h:
+        z = torch.zeros_like(b)
+        with pytest.raises(A.AMGError) as e:
+            A.amg_precond_apply_noalloc(h.h, b, z)
+        assert e.value.status == A.ERR_UNSUPPORTED
