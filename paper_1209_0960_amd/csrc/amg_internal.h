@@ -289,6 +289,7 @@ struct BDesc {
   const int* ctl;                   // [CTL_INTS]
   int active;                       // 0: the entry is finished (table launches skip it)
   int n, nc, nsl, nL;
+  int nt;                           // 1: SELL entries larger than the last-level cache (streaming loads)
   double omega;
 };
 

@@ -302,6 +302,9 @@ void level_desc(BDesc& d, const Hierarchy& H, int l) {
   d.nsl = L.nsl;
   d.nL = H.nL;
   d.omega = H.p.omega;
+  // entries of at least 8 B each (FP32 value and column) beyond the 256 MB
+  // last-level cache: every pass streams them from HBM
+  d.nt = (L.scol && (double)L.soff_h[L.nsl] * 8.0 > 256.0 * (1 << 20)) ? 1 : 0;
 }
 
 // Allocates the vectors of `slot` for hierarchy H and writes its descriptors.

@@ -135,9 +135,25 @@ __device__ inline Item direct_item(const Item& base) {
 // Lane t of the wavefront owning slice s reads its off-diagonal entry e at
 // soff[s] + 64 e + t: every matrix load is one contiguous 64-wide access;
 // padding entries are (row, 0).
-template <typename V, int R>
-__device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __restrict__ sval, int base, int w,
-                                    int lane, const V* x, V (&acc)[R]) {
+// Matrix entries of a level larger than the last-level cache are loaded with
+// the non-temporal hint (nt): they are read once per pass and would otherwise
+// push the gathered iterate values out of L2.  Smaller levels keep the
+// ordinary loads, since their entries are re-read from the cache by the next
+// passes.
+// (A run-time choice between the two loads of one address is folded into
+// one plain load by the compiler, so the choice is a template parameter and
+// callers branch on the level's flag around whole loops.)
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <typename V, int R, bool NT>
+__device__ inline void sell_offdiag_t(const int* __restrict__ scol, const V* __restrict__ sval, int base, int w,
+                                      int lane, const V* x, V (&acc)[R]) {
   const int* cp = scol + base + lane;
   const V* vp = sval + base + lane;
 #pragma unroll
@@ -151,8 +167,8 @@ __device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __res
       V a[8], xv[8][R];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        j[q] = cp[64 * (e + q)];
-        a[q] = vp[64 * (e + q)];
+        j[q] = ld_stream<NT>(cp + 64 * (e + q));
+        a[q] = ld_stream<NT>(vp + 64 * (e + q));
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) ldv<V, R>(x + (size_t)j[q] * R, xv[q]);
@@ -163,8 +179,8 @@ __device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __res
     }
   }
   for (; e + 2 <= w; e += 2) {
-    const int j0 = cp[64 * e], j1 = cp[64 * (e + 1)];
-    const V a0 = vp[64 * e], a1 = vp[64 * (e + 1)];
+    const int j0 = ld_stream<NT>(cp + 64 * e), j1 = ld_stream<NT>(cp + 64 * (e + 1));
+    const V a0 = ld_stream<NT>(vp + 64 * e), a1 = ld_stream<NT>(vp + 64 * (e + 1));
     V x0[R], x1[R];
     ldv<V, R>(x + (size_t)j0 * R, x0);
     ldv<V, R>(x + (size_t)j1 * R, x1);
@@ -174,8 +190,8 @@ __device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __res
     for (int k = 0; k < R; ++k) acc[k] = madd(a1, x1[k], acc[k]);
   }
   if (e < w) {
-    const int j0 = cp[64 * e];
-    const V a0 = vp[64 * e];
+    const int j0 = ld_stream<NT>(cp + 64 * e);
+    const V a0 = ld_stream<NT>(vp + 64 * e);
     V x0[R];
     ldv<V, R>(x + (size_t)j0 * R, x0);
 #pragma unroll
@@ -183,13 +199,22 @@ __device__ inline void sell_offdiag(const int* __restrict__ scol, const V* __res
   }
 }
 
+template <typename V, int R>
+__device__ __forceinline__ void sell_offdiag(const int* __restrict__ scol, const V* __restrict__ sval, int base,
+                                             int w, int lane, const V* x, V (&acc)[R], bool nt) {
+  if (nt)
+    sell_offdiag_t<V, R, true>(scol, sval, base, w, lane, x, acc);
+  else
+    sell_offdiag_t<V, R, false>(scol, sval, base, w, lane, x, acc);
+}
+
 // Gauss-Seidel update of the slices [lo, hi) (one per wavefront) of one
 // colour: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.  Rows of one colour do
 // not couple, so the in-place update is race free.  RES (the last pass before
 // the residual): also t_i = b_i - (a_ii x_i + sum), from the same sum, which
 // is what the residual kernel would compute for these rows.
-template <typename V, int R, bool RES = false>
-__device__ __forceinline__ void kb_gs_body(const Item& it, const BDesc& d) {
+template <typename V, int R, bool RES, bool NT>
+__device__ __forceinline__ void kb_gs_body_t(const Item& it, const BDesc& d) {
   const int sl = it.lo + (int)(threadIdx.x / WAVE);
   if (sl >= it.hi) return;
   const int lane = __lane_id();
@@ -197,11 +222,14 @@ __device__ __forceinline__ void kb_gs_body(const Item& it, const BDesc& d) {
   const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
   V* x = static_cast<V*>(d.x);
   V acc[R];
-  sell_offdiag<V, R>(d.scol, Mat<V>::sval(d), base, w, lane, x, acc);
+  sell_offdiag_t<V, R, NT>(d.scol, Mat<V>::sval(d), base, w, lane, x, acc);
   if (r < d.srow[sl + 1]) {
     V bb[R], o[R];
-    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
-    const V dg = Mat<V>::dg(d)[r];
+    if constexpr (R == 1)
+      bb[0] = ld_stream<NT>(static_cast<const V*>(d.b) + r);
+    else
+      ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+    const V dg = ld_stream<NT>(Mat<V>::dg(d) + r);
 #pragma unroll
     for (int k = 0; k < R; ++k) o[k] = (bb[k] - acc[k]) / dg;
     stv<V, R>(x + (size_t)r * R, o);
@@ -212,6 +240,13 @@ __device__ __forceinline__ void kb_gs_body(const Item& it, const BDesc& d) {
       stv<V, R>(static_cast<V*>(d.t) + (size_t)r * R, t);
     }
   }
+}
+template <typename V, int R, bool RES = false>
+__device__ __forceinline__ void kb_gs_body(const Item& it, const BDesc& d) {
+  if (d.nt)
+    kb_gs_body_t<V, R, RES, true>(it, d);
+  else
+    kb_gs_body_t<V, R, RES, false>(it, d);
 }
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_gs(AMG_KARGS) {
@@ -245,8 +280,8 @@ __global__ __launch_bounds__(NT) void kb_gs0(AMG_KARGS) {
 }
 
 // t = b - A x on the slices [lo, hi).
-template <typename V, int R>
-__device__ __forceinline__ void kb_resid_body(const Item& it, const BDesc& d) {
+template <typename V, int R, bool NT>
+__device__ __forceinline__ void kb_resid_body_t(const Item& it, const BDesc& d) {
   const int sl = it.lo + (int)(threadIdx.x / WAVE);
   if (sl >= it.hi) return;
   const int lane = __lane_id();
@@ -254,16 +289,26 @@ __device__ __forceinline__ void kb_resid_body(const Item& it, const BDesc& d) {
   const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
   const V* x = static_cast<const V*>(d.x);
   V acc[R];
-  sell_offdiag<V, R>(d.scol, Mat<V>::sval(d), base, w, lane, x, acc);
+  sell_offdiag_t<V, R, NT>(d.scol, Mat<V>::sval(d), base, w, lane, x, acc);
   if (r < d.srow[sl + 1]) {
     V bb[R], xr[R], o[R];
-    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+    if constexpr (R == 1)
+      bb[0] = ld_stream<NT>(static_cast<const V*>(d.b) + r);
+    else
+      ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
     ldv<V, R>(x + (size_t)r * R, xr);
-    const V dg = Mat<V>::dg(d)[r];
+    const V dg = ld_stream<NT>(Mat<V>::dg(d) + r);
 #pragma unroll
     for (int k = 0; k < R; ++k) o[k] = bb[k] - madd(dg, xr[k], acc[k]);
     stv<V, R>(static_cast<V*>(d.t) + (size_t)r * R, o);
   }
+}
+template <typename V, int R>
+__device__ __forceinline__ void kb_resid_body(const Item& it, const BDesc& d) {
+  if (d.nt)
+    kb_resid_body_t<V, R, true>(it, d);
+  else
+    kb_resid_body_t<V, R, false>(it, d);
 }
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_resid(AMG_KARGS) {
@@ -869,7 +914,7 @@ __device__ __forceinline__ void kb_spmv_dot_body(const Item& it, const BDesc& d)
     const int r = d.srow[sl] + lane;
     const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
     double off[R];
-    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.p, off);
+    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.p, off, d.nt != 0);
     if (r < d.srow[sl + 1]) {
       double pr[R], y[R];
       ldv<double, R>(d.p + (size_t)r * R, pr);
@@ -904,7 +949,7 @@ __device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d
     const int r = d.srow[sl] + lane;
     const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
     double off[R];
-    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.xs, off);
+    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.xs, off, d.nt != 0);
     if (r < d.srow[sl + 1]) {
       double xr[R], br[R], o[R];
       ldv<double, R>(d.xs + (size_t)r * R, xr);
@@ -1340,7 +1385,7 @@ __global__ __launch_bounds__(NT) void kk_spmv_sell(const BDesc d, int ch, const 
     const int r = d.srow[sl] + lane;
     const int base = d.soff[sl], wd = (d.soff[sl + 1] - base) >> 6;
     double off[1];
-    sell_offdiag<double, 1>(d.scol, d.sval64, base, wd, lane, x, off);
+    sell_offdiag<double, 1>(d.scol, d.sval64, base, wd, lane, x, off, d.nt != 0);
     if (r < d.srow[sl + 1]) {
       double v = madd(d.dg64[r], x[r], off[0]);
       if (c) v = c[r] - v;
