@@ -32,14 +32,15 @@ class Params(C.Structure):
                 ("omega", C.c_double), ("coarse_max", C.c_int), ("max_levels", C.c_int),
                 ("tile_rows", C.c_int), ("smoother", C.c_int), ("pre_sweeps", C.c_int),
                 ("post_sweeps", C.c_int), ("vcycle_fp32", C.c_int), ("flexible", C.c_int),
-                ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int), ("colour_tile_rows", C.c_int)]
+                ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int), ("colour_tile_rows", C.c_int),
+                ("block_size", C.c_int)]
 
 
 def default_params(**kw) -> Params:
     p = Params(strength_threshold=0.08, isolated_threshold=1e-5, agg_min=8, agg_max=12,
                agg_diameter=3, omega=1.6, coarse_max=500, max_levels=25, tile_rows=128,
                smoother=0, pre_sweeps=1, post_sweeps=1, vcycle_fp32=0, flexible=-1,
-               colour_seed=0, check_symmetry=1, colour_tile_rows=128)
+               colour_seed=0, check_symmetry=1, colour_tile_rows=128, block_size=1)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -258,8 +259,9 @@ class Hierarchy:
         rp = np.zeros(n + 1, np.int32)
         ci = np.zeros(nnz, np.int32)
         v = np.zeros(nnz, np.float64)
-        strong = None if last else np.zeros(nnz, np.uint8)
-        iso = None if last else np.zeros(n, np.uint8)
+        bs = max(1, int(self.params.block_size))
+        strong = None if last else np.zeros(nnz // (bs * bs), np.uint8)  # node graph when bs > 1
+        iso = None if last else np.zeros(n // bs, np.uint8)
 
         def p(a):
             return None if a is None else a.ctypes.data

@@ -582,6 +582,7 @@ struct Params {
   uint32_t colour_seed;
   int check_symmetry;
   int colour_tile_rows;  // rows per tile of the colouring order
+  int block_size;        // unknowns per node (point-based AMG for systems); 1: scalar
 };
 
 enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1, SMOOTH_HYBRID = 2 };
@@ -596,7 +597,127 @@ struct Level {
   int ncol = 0;
   std::vector<std::vector<int>> rows_of_colour;  // ascending rows per colour
   std::vector<double> l1;                        // sum_j |a_ij|
+  // point-based levels (block size bs > 1): inverse of every node's diagonal
+  // block, row-major bs x bs per node, in FP64 and rounded to FP32
+  std::vector<double> dinv;
+  std::vector<float> dinv32;
+  std::vector<std::vector<int>> nodes_of_colour;  // ascending nodes per colour
 };
+
+// ---------------------------------------------------------------------------
+// Point-based AMG for systems (Sec. 4.2, with the block weights of Sec. 2.1).
+// A level whose unknowns come in nodes of bs components is kept in scalar form:
+// node i owns rows i*bs .. i*bs+bs-1, and every stored block A_ij is stored in
+// full (its bs rows hold the bs columns j*bs .. j*bs+bs-1 side by side, in
+// ascending column order).  The coarsening graph is the node graph with the
+// row-sum norms of the blocks as weights: w_E((i,j)) = ||A_ij||_inf,
+// w_V(i) = ||A_ii||_inf; strength, aggregation and colouring run on it and
+// every decision holds for all bs unknowns of a node.  The prolongation is
+// P (x) I_bs, so the Galerkin block (I,J) is the sum of the blocks A_ij over
+// i in a_I, j in a_J (the scalar product P^T A P of the expanded P).
+
+// Node graph with the block weights in the places the scalar criterion reads
+// them: off-diagonal entry -||A_ij||_inf (so w_E = max(-a, 0) = the norm) and
+// diagonal ||A_ii||_inf.
+Csr node_weights(const Csr& A, int bs) {
+  Csr S;
+  S.n = A.n / bs;
+  S.ptr.assign(S.n + 1, 0);
+  for (int i = 0; i < S.n; ++i) {
+    const int r0 = i * bs;
+    const int nblk = (A.ptr[r0 + 1] - A.ptr[r0]) / bs;
+    for (int q = 0; q < nblk; ++q) {
+      const int J = A.col[A.ptr[r0] + q * bs] / bs;
+      double nrm = 0.0;
+      for (int c = 0; c < bs; ++c) {
+        double rs = 0.0;
+        for (int d = 0; d < bs; ++d) rs = rs + std::fabs(A.val[A.ptr[r0 + c] + q * bs + d]);
+        nrm = std::max(nrm, rs);
+      }
+      S.col.push_back(J);
+      S.val.push_back(J == i ? nrm : -nrm);
+    }
+    S.ptr[i + 1] = (int)S.col.size();
+  }
+  return S;
+}
+
+// Every node's rows have one pattern of whole blocks, the diagonal block
+// included.
+bool block_structure_ok(const Csr& A, int bs) {
+  if (bs < 1 || A.n % bs) return false;
+  for (int i = 0; i < A.n / bs; ++i) {
+    const int r0 = i * bs, len = A.ptr[r0 + 1] - A.ptr[r0];
+    if (len % bs) return false;
+    bool diag = false;
+    for (int c = 0; c < bs; ++c) {
+      if (A.ptr[r0 + c + 1] - A.ptr[r0 + c] != len) return false;
+      for (int q = 0; q < len / bs; ++q) {
+        const int J = A.col[A.ptr[r0] + q * bs] / bs;
+        for (int d = 0; d < bs; ++d)
+          if (A.col[A.ptr[r0 + c] + q * bs + d] != J * bs + d) return false;
+        if (J == i) diag = true;
+      }
+    }
+    if (!diag) return false;
+  }
+  return true;
+}
+
+// Gauss-Jordan inverse with partial pivoting (largest magnitude, first on
+// ties) of a bs x bs row-major block; false if a pivot is zero.
+bool invert_block(int bs, const double* a, double* inv) {
+  std::vector<double> m(a, a + bs * bs), e(bs * bs, 0.0);
+  for (int c = 0; c < bs; ++c) e[c * bs + c] = 1.0;
+  for (int c = 0; c < bs; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < bs; ++r)
+      if (std::fabs(m[r * bs + c]) > std::fabs(m[piv * bs + c])) piv = r;
+    if (m[piv * bs + c] == 0.0) return false;
+    if (piv != c)
+      for (int k = 0; k < bs; ++k) {
+        std::swap(m[c * bs + k], m[piv * bs + k]);
+        std::swap(e[c * bs + k], e[piv * bs + k]);
+      }
+    const double p = m[c * bs + c];
+    for (int k = 0; k < bs; ++k) {
+      m[c * bs + k] = m[c * bs + k] / p;
+      e[c * bs + k] = e[c * bs + k] / p;
+    }
+    for (int r = 0; r < bs; ++r) {
+      if (r == c) continue;
+      const double f = m[r * bs + c];
+      for (int k = 0; k < bs; ++k) {
+        m[r * bs + k] = m[r * bs + k] - f * m[c * bs + k];
+        e[r * bs + k] = e[r * bs + k] - f * e[c * bs + k];
+      }
+    }
+  }
+  std::copy(e.begin(), e.end(), inv);
+  return true;
+}
+
+// Block Gauss-Seidel update of node i (the smoother becomes a block smoother,
+// Sec. 4.2): t_c = b_(i,c) - sum over the entries of row (i,c) outside the
+// node's own block (CSR order) of a x; x_(i,c) = sum_d Dinv_i[c][d] t_d.
+template <typename V>
+void block_gs_node(const Csr& A, const V* val, const V* dinv, int bs, int i, const V* b, V* x) {
+  V t[16];
+  for (int c = 0; c < bs; ++c) {
+    const int r = i * bs + c;
+    V acc = b[r];
+    for (int k = A.ptr[r]; k < A.ptr[r + 1]; ++k) {
+      const int j = A.col[k];
+      if (j / bs != i) acc = acc - val[k] * x[j];
+    }
+    t[c] = acc;
+  }
+  for (int c = 0; c < bs; ++c) {
+    V s = 0;
+    for (int d = 0; d < bs; ++d) s = s + dinv[(size_t)i * bs * bs + c * bs + d] * t[d];
+    x[i * bs + c] = s;
+  }
+}
 
 struct Hier {
   Params p;
@@ -671,9 +792,25 @@ template <>
 const float* level_vals<float>(const Level& L) { return L.val32.data(); }
 
 template <typename V>
+const V* level_dinv(const Level& L);
+template <>
+const double* level_dinv<double>(const Level& L) { return L.dinv.data(); }
+template <>
+const float* level_dinv<float>(const Level& L) { return L.dinv32.data(); }
+
+template <typename V>
 void smooth(const Hier& H, int l, const V* b, V* x) {
   const Level& L = H.lev[l];
   const V* val = level_vals<V>(L);
+  const int bs = H.p.block_size;
+  if (bs > 1) {  // multicolour block symmetric Gauss-Seidel over the nodes
+    const V* dinv = level_dinv<V>(L);
+    for (int c = 0; c < L.ncol; ++c)
+      for (int i : L.nodes_of_colour[c]) block_gs_node<V>(L.A, val, dinv, bs, i, b, x);
+    for (int c = L.ncol - 1; c >= 0; --c)
+      for (int i : L.nodes_of_colour[c]) block_gs_node<V>(L.A, val, dinv, bs, i, b, x);
+    return;
+  }
   if (H.p.smoother == SMOOTH_MCSGS) {
     for (int c = 0; c < L.ncol; ++c)  // forward sweep
       for (int i : L.rows_of_colour[c]) gs_row<V>(L.A, val, i, b, x);
@@ -776,8 +913,29 @@ int validate(const Csr& A, int check_symmetry) {
   return ORC_OK;
 }
 
-void finish_level(Level& L, const Params& p, int l) {
-  if (p.smoother == SMOOTH_HYBRID) {  // no multicolouring: one colour, natural order
+bool finish_level(Level& L, const Params& p, int l) {
+  const int bs = p.block_size;
+  if (bs > 1) {  // colours of the node graph, each node's unknowns share its colour
+    const Csr S = node_weights(L.A, bs);
+    std::vector<int> nc;
+    L.ncol = colour_rows(S, p.colour_tile_rows, p.colour_seed + (uint32_t)l, nc);
+    L.colour.assign(L.A.n, 0);
+    L.nodes_of_colour.assign(L.ncol, {});
+    for (int i = 0; i < S.n; ++i) {
+      L.nodes_of_colour[nc[i]].push_back(i);
+      for (int c = 0; c < bs; ++c) L.colour[i * bs + c] = nc[i];
+    }
+    L.dinv.assign((size_t)S.n * bs * bs, 0.0);
+    std::vector<double> blk(bs * bs);
+    for (int i = 0; i < S.n; ++i) {
+      for (int c = 0; c < bs; ++c)
+        for (int k = L.A.ptr[i * bs + c]; k < L.A.ptr[i * bs + c + 1]; ++k)
+          if (L.A.col[k] / bs == i) blk[c * bs + L.A.col[k] % bs] = L.A.val[k];
+      if (!invert_block(bs, blk.data(), &L.dinv[(size_t)i * bs * bs])) return false;
+    }
+    L.dinv32.resize(L.dinv.size());
+    for (size_t k = 0; k < L.dinv.size(); ++k) L.dinv32[k] = (float)L.dinv[k];
+  } else if (p.smoother == SMOOTH_HYBRID) {  // no multicolouring: one colour, natural order
     L.colour.assign(L.A.n, 0);
     L.ncol = 1;
   } else {
@@ -793,10 +951,13 @@ void finish_level(Level& L, const Params& p, int l) {
     for (int k = L.A.ptr[i]; k < L.A.ptr[i + 1]; ++k) s = s + std::fabs(L.A.val[k]);
     L.l1[i] = s;
   }
+  return true;
 }
 
 int build(Hier& H, const Csr& A0) {
   const Params& p = H.p;
+  const int bs = p.block_size;
+  if (bs > 1 && (bs > 16 || p.smoother != SMOOTH_MCSGS || !block_structure_ok(A0, bs))) return ORC_INVALID;
   int st = validate(A0, p.check_symmetry);
   if (st) return st;
   H.lev.clear();
@@ -806,17 +967,31 @@ int build(Hier& H, const Csr& A0) {
     int l = (int)H.lev.size() - 1;
     Level& L = H.lev[l];
     if (L.A.n <= p.coarse_max || l == p.max_levels - 1) break;
-    strength(L.A, p.tile_rows, p.delta, p.beta, L.strong, L.iso);
     std::vector<int> agg;
-    int nc = aggregate_all(L.A, L.strong, L.iso, p.tile_rows, p.smin, p.smax, p.dmax, agg, nullptr);
-    if ((double)nc > 0.9 * (double)L.A.n) break;  // coarsening stalled
+    int nc = 0;
+    if (bs > 1) {  // strength and aggregation of the node graph; P = P_nodes (x) I_bs
+      const Csr S = node_weights(L.A, bs);
+      strength(S, p.tile_rows, p.delta, p.beta, L.strong, L.iso);
+      std::vector<int> nagg;
+      const int ncn = aggregate_all(S, L.strong, L.iso, p.tile_rows, p.smin, p.smax, p.dmax, nagg, nullptr);
+      if ((double)ncn > 0.9 * (double)S.n) break;  // coarsening stalled
+      agg.assign(L.A.n, 0);
+      for (int i = 0; i < S.n; ++i)
+        for (int c = 0; c < bs; ++c) agg[i * bs + c] = nagg[i] * bs + c;
+      nc = ncn * bs;
+    } else {
+      strength(L.A, p.tile_rows, p.delta, p.beta, L.strong, L.iso);
+      nc = aggregate_all(L.A, L.strong, L.iso, p.tile_rows, p.smin, p.smax, p.dmax, agg, nullptr);
+      if ((double)nc > 0.9 * (double)L.A.n) break;  // coarsening stalled
+    }
     L.agg = agg;
     L.nc = nc;
     Csr C = galerkin(L.A, agg, nc);
     H.lev.emplace_back();
     H.lev.back().A = C;
   }
-  for (size_t l = 0; l < H.lev.size(); ++l) finish_level(H.lev[l], p, (int)l);
+  for (size_t l = 0; l < H.lev.size(); ++l)
+    if (!finish_level(H.lev[l], p, (int)l)) return ORC_BAD_DIAGONAL;  // singular diagonal block
   Level& Lc = H.lev.back();
   Lc.agg.clear();
   Lc.nc = 0;
@@ -852,6 +1027,7 @@ struct orc_params {
   uint32_t colour_seed;
   int check_symmetry;
   int colour_tile_rows;
+  int block_size;
 };
 
 static Params to_params(const orc_params* q) {
@@ -873,6 +1049,7 @@ static Params to_params(const orc_params* q) {
   p.colour_seed = q->colour_seed;
   p.check_symmetry = q->check_symmetry;
   p.colour_tile_rows = q->colour_tile_rows;
+  p.block_size = q->block_size < 1 ? 1 : q->block_size;
   return p;
 }
 

@@ -260,6 +260,75 @@ def manufactured(n: int) -> tuple:
     return sysm, np.ascontiguousarray(u.ravel()[order])
 
 
+def block_expand(rowptr, colind, blocks: np.ndarray) -> tuple:
+    """Scalar form of a block matrix with bs x bs blocks: node i's unknowns
+    are rows i*bs .. i*bs+bs-1 (node-major), every stored block is stored in
+    full, columns ascend in every row.  blocks[k] is the block of node entry k
+    (row-major, shape (nnzb, bs, bs))."""
+    nb = rowptr.shape[0] - 1
+    bs = blocks.shape[1]
+    cnt = np.diff(rowptr).astype(np.int64)
+    nrow = nb * bs
+    rp = np.zeros(nrow + 1, np.int64)
+    rp[1:] = np.cumsum(np.repeat(cnt * bs, bs))
+    node_of_entry = np.repeat(np.arange(nb), cnt)
+    # scalar entry (i*bs + c, colind[k]*bs + d) at rp[i*bs + c] + (k - rowptr[i]) * bs + d
+    k = np.arange(colind.shape[0])
+    pos_in_row = (k - rowptr[node_of_entry]) * bs
+    ci = np.empty(rp[-1], np.int64)
+    v = np.empty(rp[-1], np.float64)
+    for c in range(bs):
+        base = rp[node_of_entry * bs + c] + pos_in_row
+        for d in range(bs):
+            ci[base + d] = colind * bs + d
+            v[base + d] = blocks[:, c, d]
+    return rp.astype(np.int32), ci.astype(np.int32), v
+
+
+def coupled(n: int, bs: int = 3, seed: int = 6, sigma2: float = 2.0) -> CSRSystem:
+    """A bs-component coupled diffusion system on n^3 cells (point-based AMG
+    workload): A = sum over interior faces f = (i, j) of
+    t_f (e_i - e_j)(e_i - e_j)^T (x) C_f plus, for every boundary face of cell
+    i, 2 K_i e_i e_i^T (x) I, with t_f the harmonic face transmissibility of a
+    lognormal K (sigma^2, 2x2x2 box filter) and C_f = I + v_f v_f^T a face
+    coupling with v_f ~ U[0,1]^bs.  SPD; off-diagonal blocks -t_f C_f have
+    only negative entries, diagonal blocks are dense.  Returned in scalar form,
+    node-major (unknown c of cell-row i is row i*bs + c), cells in Morton order.
+    Draws from default_rng(seed): the field, then v for the x-, y- and z-faces
+    (one vector per cell and axis, lexicographic order), then b."""
+    rng = np.random.default_rng(seed)
+    K = field_lognormal(rng, n, sigma2, 2, math.sqrt(8.0))
+    rowptr, colind, vals, order = ccfv7(K)
+    nc = n * n * n
+    V = [rng.uniform(0.0, 1.0, (nc, bs)) for _ in range(3)]  # faces to the +x, +y, +z neighbour
+    nb = rowptr.shape[0] - 1
+    rows = np.repeat(np.arange(nb), np.diff(rowptr))
+    off = colind != rows
+    lex_i = order[rows]
+    lex_j = order[colind]
+    d = np.abs(lex_j - lex_i)
+    low = np.minimum(lex_i, lex_j)
+    axis = np.where(d == 1, 0, np.where(d == n, 1, 2))
+    I = np.eye(bs)
+    blocks = np.zeros((colind.shape[0], bs, bs))
+    ko = np.nonzero(off)[0]
+    v = np.stack([V[a][l] for a, l in zip(axis[ko], low[ko])]) if ko.size else np.zeros((0, bs))
+    C = I[None, :, :] + v[:, :, None] * v[:, None, :]
+    t = -vals[ko]  # transmissibility of the face
+    blocks[ko] = -t[:, None, None] * C
+    # diagonal block: couplings of the faces plus the boundary faces (identity)
+    kd = np.nonzero(~off)[0]
+    face_sum = np.zeros((nb, bs, bs))
+    np.add.at(face_sum, rows[ko], t[:, None, None] * C)
+    tsum = np.zeros(nb)
+    np.add.at(tsum, rows[ko], t)
+    bnd = vals[kd] - tsum  # boundary faces 2 K of every cell (diagonal entry minus interior faces)
+    blocks[kd] = face_sum + bnd[:, None, None] * I[None, :, :]
+    rp, ci, vv = block_expand(rowptr, colind, blocks)
+    b = rng.uniform(-1.0, 1.0, (nc, bs))[order].reshape(-1)
+    return CSRSystem(rp, ci, vv, np.ascontiguousarray(b), (n, n, n), order)
+
+
 def from_field(K: np.ndarray, seed: int = 0) -> CSRSystem:
     nz, ny, nx = K.shape
     rowptr, colind, vals, order = ccfv7(K)
