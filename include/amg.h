@@ -93,6 +93,19 @@ typedef struct amg_params {
   int32_t tail_rows;         /* levels with at most this many rows (and all    [0]
                                 coarser ones) are cycled by one workgroup per solve */
   int32_t colour_tile_rows;  /* rows per tile of the colouring order (64..1024) [128] */
+  int32_t block_size;        /* unknowns per node, 1..4 (point-based AMG for    [1]
+                                systems, Sec. 4.2): A is given in scalar form with
+                                node i's unknowns in rows i*bs .. i*bs+bs-1 and
+                                every stored bs x bs block stored in full (the
+                                diagonal block included).  Strength (with the
+                                row-sum norms of the blocks as the weights of
+                                Sec. 2.1), aggregation and colouring run on the
+                                node graph; P = P_nodes (x) I; the smoother is
+                                the multicolour block symmetric Gauss-Seidel
+                                with inverted diagonal blocks (smoother must be
+                                MCSGS, tail_rows 0).  With keep_setup_data the
+                                strong / isolated flags of amg_copy_level are
+                                those of the node graph. */
 } amg_params;
 
 typedef struct amg_solve_info {

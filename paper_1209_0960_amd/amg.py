@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("post_sweeps", C.c_int32), ("vcycle_fp32", C.c_int32), ("flexible", C.c_int32),
                 ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int32), ("keep_setup_data", C.c_int32),
                 ("use_graphs", C.c_int32), ("tail_rows", C.c_int32),
-                ("colour_tile_rows", C.c_int32)]
+                ("colour_tile_rows", C.c_int32), ("block_size", C.c_int32)]
 
 
 class CSR(C.Structure):
@@ -422,8 +422,9 @@ class Hierarchy:
         out["colind"] = np.zeros(nnz, np.int32)
         out["vals"] = np.zeros(nnz, np.float64)
         keep = bool(self.params.keep_setup_data) and info["n_next"] > 0
-        out["strong"] = np.zeros(nnz, np.uint8) if keep else None
-        out["iso"] = np.zeros(n, np.uint8) if keep else None
+        bs = max(1, int(self.params.block_size))  # node graph flags on point-based levels
+        out["strong"] = np.zeros(nnz // (bs * bs), np.uint8) if keep else None
+        out["iso"] = np.zeros(n // bs, np.uint8) if keep else None
 
         def p(a):
             return None if a is None else a.ctypes.data_as(C.c_void_p)

@@ -312,6 +312,12 @@ void check_params(const amg_params& p) {
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
   if (p.tail_rows < 0) fail(AMG_ERR_INVALID_ARG, "tail_rows");
   if (p.colour_tile_rows < 64 || p.colour_tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows outside 64..1024");
+  if (p.block_size < 1) fail(AMG_ERR_INVALID_ARG, "block_size");
+  if (p.block_size > 4) fail(AMG_ERR_UNSUPPORTED, "block_size above 4");
+  if (p.block_size > 1 && p.smoother != AMG_SMOOTHER_MCSGS)
+    fail(AMG_ERR_UNSUPPORTED, "point-based levels (block_size > 1) take the multicolour smoother only");
+  if (p.block_size > 1 && p.tail_rows > 0)
+    fail(AMG_ERR_UNSUPPORTED, "point-based levels (block_size > 1) are not cycled by the one-workgroup tail");
 }
 
 void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy& H) {
@@ -327,6 +333,9 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   if (fl & 1) fail(AMG_ERR_INVALID_ARG, "malformed CSR (row pointers, column order/range or non-finite value)");
   if (fl & 2) fail(AMG_ERR_BAD_DIAGONAL, "missing or non-positive diagonal");
   if (fl & 4) fail(AMG_ERR_NOT_SYMMETRIC, "matrix is not symmetric");
+  const int bs = H.p.block_size;
+  if (bs > 1 && validate_blocks(A->n, bs, A->rowptr, A->colind, s))
+    fail(AMG_ERR_INVALID_ARG, "block_size > 1 needs every node's rows to hold whole blocks, the diagonal block included");
 
   H.lev.clear();
   H.lev.emplace_back();
@@ -352,12 +361,18 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     }
     uint8_t *strong, *iso;
     DBuf ts, ti;
-    const int n = H.lev[l].n, nnz = H.lev[l].nnz;
+    // point-based levels: strength and aggregation on the node graph
+    Level S;
+    if (bs > 1) node_graph(H, H.lev[l], bs, S, s);
+    Level& G = bs > 1 ? S : H.lev[l];
+    const int n = G.n, nnz = G.nnz;
     if (p.keep_setup_data) {
       strong = H.alloc<uint8_t>((size_t)nnz, s);
       iso = H.alloc<uint8_t>((size_t)n, s);
       H.lev[l].strong = strong;
       H.lev[l].iso = iso;
+      H.lev[l].nn = n;
+      H.lev[l].nnzb = nnz;
     } else {
       ts = DBuf((size_t)nnz, s);
       ti = DBuf((size_t)n, s);
@@ -365,12 +380,19 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
       iso = ti.as<uint8_t>();
     }
     // level 0's values were checked exactly symmetric; Galerkin sums of a
-    // coarse level need not be (their terms are added in different orders)
-    strength(H.lev[l], p.strength_threshold, p.isolated_threshold, strong, iso, l == 0 && p.check_symmetry != 0, s);
-    const int nc = aggregate(H, H.lev[l], strong, iso, p, s);
+    // coarse level need not be (their terms are added in different orders),
+    // nor are the block norms of the node graph
+    strength(G, p.strength_threshold, p.isolated_threshold, strong, iso, bs == 1 && l == 0 && p.check_symmetry != 0,
+             s);
+    const int nc = aggregate(H, G, strong, iso, p, s);
     if ((double)nc > 0.9 * (double)n) {
+      if (bs > 1) release_level(H, S, s);
       H.lev[l].nc = 0;  // stalled: this level becomes the coarsest
       break;
+    }
+    if (bs > 1) {
+      expand_aggregates(H, S, bs, H.lev[l], s);
+      release_level(H, S, s);
     }
     H.lev.emplace_back();
     galerkin(H, H.lev[l], H.lev[l + 1], s);
@@ -380,10 +402,18 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   const bool f32 = p.vcycle_fp32 != 0;
   const bool hybrid = p.smoother == AMG_SMOOTHER_HYBRID_SGS;
   for (int l = 0; l <= Lc; ++l) {
-    if (hybrid)
+    H.lev[l].bs = bs;
+    if (hybrid) {
       colour_single(H, H.lev[l], s);
-    else
+    } else if (bs > 1) {  // node colours, shared by each node's unknowns
+      Level S;
+      node_graph(H, H.lev[l], bs, S, s);
+      colour(H, S, p.colour_seed + (uint32_t)l, s);
+      expand_colours(H, S, bs, H.lev[l], s);
+      release_level(H, S, s);
+    } else {
       colour(H, H.lev[l], p.colour_seed + (uint32_t)l, s);
+    }
   }
   // Relabel every level above the coarsest into colour order (the coarsest
   // keeps its natural order for the dense solve).
@@ -405,6 +435,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
         l1_diag(L, L.l1, nullptr, s);
       }
     }
+    if (bs > 1) block_inverses(H, L, bs, f32, s);
     build_sell(H, l, s);
     if (hybrid) hybrid_steps(H, L, p.tile_rows, s);
     L.sptr_d = H.alloc<int>(L.sptr.size(), s);
@@ -457,6 +488,7 @@ amg_status amg_default_params(amg_params* p) {
   p->use_graphs = 1;
   p->tail_rows = 0;
   p->colour_tile_rows = 128;
+  p->block_size = 1;
   return AMG_OK;
 }
 
@@ -601,8 +633,9 @@ amg_status amg_copy_level(const amg_hierarchy* h, int32_t l, int32_t* agg, int32
   return guarded([&] {
     AMG_HIP(hipDeviceSynchronize());
     const int n = L.n, nnz = L.nnz;
-    if (strong && L.strong) AMG_HIP(hipMemcpy(strong, L.strong, (size_t)nnz, hipMemcpyDeviceToHost));
-    if (iso && L.iso) AMG_HIP(hipMemcpy(iso, L.iso, (size_t)n, hipMemcpyDeviceToHost));
+    const size_t sflags = L.bs > 1 ? (size_t)L.nnzb : (size_t)nnz, iflags = L.bs > 1 ? (size_t)L.nn : (size_t)n;
+    if (strong && L.strong) AMG_HIP(hipMemcpy(strong, L.strong, sflags, hipMemcpyDeviceToHost));
+    if (iso && L.iso) AMG_HIP(hipMemcpy(iso, L.iso, iflags, hipMemcpyDeviceToHost));
     if (!L.perm) {  // natural order (the coarsest level, or a one-level hierarchy)
       if (agg && L.agg && L.nc > 0) AMG_HIP(hipMemcpy(agg, L.agg, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
       if (colour) AMG_HIP(hipMemcpy(colour, L.colour, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));

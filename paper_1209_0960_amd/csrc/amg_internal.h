@@ -140,9 +140,15 @@ struct Level {
   unsigned short* hsb = nullptr;  // n: backward wavefront step
   int hdf = 0, hdb = 0;           // largest steps
   int hw = 0;                     // most in-tile couplings of a row
-  // optional setup data (natural order)
+  // optional setup data (natural order; on point-based levels per node and node-graph entry)
   uint8_t* strong = nullptr;
   uint8_t* iso = nullptr;
+  // point-based levels (Sec. 4.2): unknowns per node, and for the block smoother
+  // row c of the inverse diagonal block of each row's node (n x bs, solve order)
+  int bs = 1;
+  int nn = 0, nnzb = 0;  // nodes and node-graph entries (setup data sizes)
+  double* dinv = nullptr;
+  float* dinv32 = nullptr;
 };
 
 struct Batch;
@@ -251,6 +257,16 @@ void gather(int n, const int* perm, const double* in, double* out, hipStream_t s
 void build_sell(Hierarchy& H, int l, hipStream_t s);
 void scatter(int n, const int* perm, const double* in, double* out, hipStream_t s);
 void exclusive_scan(const int* in, int* out, int n, hipStream_t s);  // out has n+1 entries
+// Point-based levels: block structure check (returns flag 1 when a node's rows
+// are not whole blocks with the diagonal block), the node graph with the block
+// weights, expansion of node aggregates and colours to the unknowns, inverses
+// of the diagonal blocks (after the level is in solve order, before build_sell).
+int validate_blocks(int n, int bs, const int* rp, const int* ci, hipStream_t s);
+void node_graph(Hierarchy& H, const Level& L, int bs, Level& S, hipStream_t s);
+void release_level(Hierarchy& H, Level& S, hipStream_t s);
+void expand_aggregates(Hierarchy& H, const Level& S, int bs, Level& L, hipStream_t s);
+void expand_colours(Hierarchy& H, const Level& S, int bs, Level& L, hipStream_t s);
+void block_inverses(Hierarchy& H, Level& L, int bs, bool f32, hipStream_t s);
 
 // ------------------------------------------------------------------ solve engine
 // Every solve-phase launch is table driven: block b of a launch reads
@@ -290,6 +306,9 @@ struct BDesc {
   int active;                       // 0: the entry is finished (table launches skip it)
   int n, nc, nsl, nL;
   int nt;                           // 1: SELL entries larger than the last-level cache (streaming loads)
+  int blk;                          // unknowns per node (point-based levels > 1)
+  const double* dinv64;             // row c of the inverse diagonal block of each row's node (n x bs)
+  const float* dinv32;
   double omega;
 };
 
@@ -320,6 +339,7 @@ enum {
   OP_GS_RESID,   // Gauss-Seidel pass that also writes the residual of its rows
   OP_RESID_OFF,  // hybrid smoother: t = b - (couplings to other tiles) x (slices)
   OP_HSGS,       // hybrid smoother: in-tile forward + backward sweeps (tiles; aux = 1: from b, x = 0)
+  OP_BGS,        // point-based level: block Gauss-Seidel on the slices of one colour (whole nodes)
 };
 enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
 

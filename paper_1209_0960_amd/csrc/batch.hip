@@ -198,7 +198,7 @@ struct Batch {
   // All entries start together and are completed at the end (pcg_solve_batched):
   // finished entries are only switched off, the launch plan is kept.
   bool deferred = false;
-  int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0, tile_rows = 0;
+  int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0, tile_rows = 0, bs = 1;
   hipStream_t work = nullptr;
   hipEvent_t ev = nullptr;
   BDesc* desc_d = nullptr;
@@ -254,12 +254,13 @@ void check_uniform(Batch& B, const Hierarchy& H) {
     B.post = H.p.post_sweeps;
     B.flexible = H.flexible;
     B.tile_rows = H.p.tile_rows;
+    B.bs = H.p.block_size;
     return;
   }
   if (B.fp32 != fp32 || B.smoother != H.p.smoother || B.pre != H.p.pre_sweeps || B.post != H.p.post_sweeps ||
-      B.flexible != H.flexible)
+      B.flexible != H.flexible || B.bs != H.p.block_size)
     fail(AMG_ERR_INVALID_ARG,
-         "hierarchies of one batch must share vcycle_fp32, smoother, pre/post sweeps and the CG variant");
+         "hierarchies of one batch must share vcycle_fp32, smoother, pre/post sweeps, block size and the CG variant");
   if (B.smoother == AMG_SMOOTHER_HYBRID_SGS && B.tile_rows != H.p.tile_rows)
     fail(AMG_ERR_INVALID_ARG, "hierarchies of one batch with the hybrid smoother must share tile_rows");
 }
@@ -305,6 +306,9 @@ void level_desc(BDesc& d, const Hierarchy& H, int l) {
   // entries of at least 8 B each (FP32 value and column) beyond the 256 MB
   // last-level cache: every pass streams them from HBM
   d.nt = (L.scol && (double)L.soff_h[L.nsl] * 8.0 > 256.0 * (1 << 20)) ? 1 : 0;
+  d.blk = L.bs;
+  d.dinv64 = L.dinv;
+  d.dinv32 = L.dinv32;
 }
 
 // Allocates the vectors of `slot` for hierarchy H and writes its descriptors.
@@ -530,7 +534,7 @@ double pass0_bytes(const Level& L, int s0, int s1, int R, double vb) {
 // colour-0 rows (their values are written by the first pass before any read),
 // and the last pre-smoothing pass writes the residual of its rows.
 bool colour0_shortcuts(const Batch& B, int e, int l) {
-  return B.smoother == AMG_SMOOTHER_MCSGS && hier(B, e).lev[l].ncol >= 2;
+  return B.smoother == AMG_SMOOTHER_MCSGS && hier(B, e).lev[l].ncol >= 2 && hier(B, e).lev[l].bs == 1;
 }
 // First row after colour 0 (solve order).
 int colour0_rows(const Level& L) { return L.srow_h[L.sptr[1]]; }
@@ -564,13 +568,16 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
         }
         b.end();
       }
-      b.begin(zero ? OP_GS0 : OP_GS, l, kind_at(l, zero ? AMG_KIND_OTHER : AMG_KIND_SWEEP));
+      // point-based levels (every entry of a batch shares the block size):
+      // block passes only, the first one too (the iterate was zero-filled)
+      const bool blk = B.bs > 1;
+      b.begin(blk ? OP_BGS : zero ? OP_GS0 : OP_GS, l, kind_at(l, zero ? AMG_KIND_OTHER : AMG_KIND_SWEEP));
       for (size_t i = 0; i < E.size(); ++i) {
         if (j >= seq[i].size() || last(i)) continue;
         const int e = E[i];
         const Level& L = hier(B, e).lev[l];
         const int c = seq[i][j];
-        if (!zero) {
+        if (!zero || blk) {
           add_slices(b, B, e, l, L.sptr[c], L.sptr[c + 1]);
           continue;
         }

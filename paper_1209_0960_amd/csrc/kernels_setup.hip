@@ -1631,6 +1631,147 @@ __global__ __launch_bounds__(256) void k_sell_fill(int nsl, const int* __restric
   }
 }
 
+
+// ============================================================== point-based levels
+// A level of bs-component nodes (point-based AMG for systems, Sec. 4.2) is a
+// scalar CSR in which node i owns rows i*bs .. i*bs+bs-1 (natural order) and
+// every stored block is full: its bs rows hold the columns J*bs .. J*bs+bs-1
+// side by side.  Coarsening and colouring run on the node graph, weighted by
+// row-sum norms of the blocks (Sec. 2.1); the decisions are expanded to the
+// bs unknowns of each node.
+constexpr int BLK_MAX = 4;  // largest supported block size
+
+// Every node's rows share one pattern of whole blocks, the diagonal block
+// included (flag 1 otherwise).  Runs after the structural checks.
+__global__ void k_validate_blocks(int nn, int bs, const int* __restrict__ rp, const int* __restrict__ ci, int* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int r0 = i * bs, len = rp[r0 + 1] - rp[r0];
+  bool ok = len % bs == 0, diag = false;
+  for (int c = 0; c < bs && ok; ++c) {
+    if (rp[r0 + c + 1] - rp[r0 + c] != len) {
+      ok = false;
+      break;
+    }
+    for (int q = 0; q < len / bs && ok; ++q) {
+      const int J = ci[rp[r0] + q * bs] / bs;
+      for (int d = 0; d < bs; ++d)
+        if (ci[rp[r0 + c] + q * bs + d] != J * bs + d) ok = false;
+      if (J == i) diag = true;
+    }
+  }
+  if (!ok || !diag) atomicOr(flags, 1);
+}
+
+__global__ void k_node_count(int nn, int bs, const int* __restrict__ rp, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn) cnt[i] = (rp[i * bs + 1] - rp[i * bs]) / bs;
+}
+
+// Node graph with the block weights where the scalar criterion reads them:
+// off-diagonal -||A_iJ||_inf (so w_E = max(-a, 0) is the norm), diagonal
+// ||A_ii||_inf; row sums added in column order, then the largest taken.
+__global__ void k_node_fill(int nn, int bs, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const double* __restrict__ v, const int* __restrict__ nrp, int* __restrict__ nci,
+                            double* __restrict__ nv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int r0 = i * bs, nb = nrp[i + 1] - nrp[i];
+  for (int q = 0; q < nb; ++q) {
+    const int J = ci[rp[r0] + q * bs] / bs;
+    double nrm = 0.0;
+    for (int c = 0; c < bs; ++c) {
+      double rs = 0.0;
+      for (int d = 0; d < bs; ++d) rs = rs + fabs(v[rp[r0 + c] + q * bs + d]);
+      nrm = fmax(nrm, rs);
+    }
+    nci[nrp[i] + q] = J;
+    nv[nrp[i] + q] = J == i ? nrm : -nrm;
+  }
+}
+
+// Prolongation P (x) I: unknown c of node i goes to unknown c of the node's
+// aggregate; member lists of coarse unknown (I, c): the members of I, ascending.
+__global__ void k_expand_agg(int n, int bs, const int* __restrict__ nagg, int* __restrict__ agg) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) agg[r] = nagg[r / bs] * bs + r % bs;
+}
+
+__global__ void k_expand_members(int ncn, int bs, const int* __restrict__ nmptr, const int* __restrict__ nmem,
+                                 int* __restrict__ mptr, int* __restrict__ mem) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= ncn) return;
+  const int b = nmptr[I], cnt = nmptr[I + 1] - b;
+  for (int c = 0; c < bs; ++c) {
+    mptr[I * bs + c] = bs * b + c * cnt;
+    for (int k = 0; k < cnt; ++k) mem[bs * b + c * cnt + k] = nmem[b + k] * bs + c;
+  }
+  if (I == ncn - 1) mptr[ncn * bs] = bs * nmptr[ncn];
+}
+
+__global__ void k_expand_colour(int n, int bs, const int* __restrict__ ncol, const int* __restrict__ ncrows,
+                                int* __restrict__ col, int* __restrict__ crows) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  col[r] = ncol[r / bs];
+  crows[r] = ncrows[r / bs] * bs + r % bs;
+}
+
+// Inverse of every node's diagonal block (solve order: node q owns rows
+// q*bs .. q*bs+bs-1), Gauss-Jordan with partial pivoting (largest magnitude,
+// first on ties); row c of the inverse goes to dinv[(q*bs + c)*bs ..].
+// Flag 1: a zero pivot.
+__global__ void k_block_dinv(int nn, int bs, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, double* __restrict__ dinv, int* __restrict__ flag) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nn) return;
+  double m[BLK_MAX * BLK_MAX], e[BLK_MAX * BLK_MAX];
+  for (int k = 0; k < bs * bs; ++k) {
+    m[k] = 0.0;
+    e[k] = 0.0;
+  }
+  for (int c = 0; c < bs; ++c) {
+    e[c * bs + c] = 1.0;
+    const int r = q * bs + c;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) {
+      const int j = ci[k];
+      if (j >= q * bs && j < q * bs + bs) m[c * bs + (j - q * bs)] = v[k];
+    }
+  }
+  for (int c = 0; c < bs; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < bs; ++r)
+      if (fabs(m[r * bs + c]) > fabs(m[piv * bs + c])) piv = r;
+    if (m[piv * bs + c] == 0.0) {
+      atomicOr(flag, 1);
+      return;
+    }
+    if (piv != c)
+      for (int k = 0; k < bs; ++k) {
+        double t = m[c * bs + k];
+        m[c * bs + k] = m[piv * bs + k];
+        m[piv * bs + k] = t;
+        t = e[c * bs + k];
+        e[c * bs + k] = e[piv * bs + k];
+        e[piv * bs + k] = t;
+      }
+    const double p = m[c * bs + c];
+    for (int k = 0; k < bs; ++k) {
+      m[c * bs + k] = m[c * bs + k] / p;
+      e[c * bs + k] = e[c * bs + k] / p;
+    }
+    for (int r = 0; r < bs; ++r) {
+      if (r == c) continue;
+      const double f = m[r * bs + c];
+      for (int k = 0; k < bs; ++k) {
+        m[r * bs + k] = m[r * bs + k] - f * m[c * bs + k];
+        e[r * bs + k] = e[r * bs + k] - f * e[c * bs + k];
+      }
+    }
+  }
+  for (int k = 0; k < bs * bs; ++k) dinv[(size_t)q * bs * bs + k] = e[k];
+}
+
 template <typename T>
 T read1(const T* dptr, hipStream_t s) {
   T v;
@@ -2032,9 +2173,10 @@ void build_sell(Hierarchy& H, int l, hipStream_t s) {
   Level& L = H.lev[l];
   std::vector<int> srow_h;
   L.sptr.assign(L.ncol + 1, 0);
+  const int step = L.bs > 1 ? 64 - 64 % L.bs : 64;  // slices hold whole nodes on point-based levels
   for (int c = 0; c < L.ncol; ++c) {
     L.sptr[c] = (int)srow_h.size();
-    for (int r = L.cptr[c]; r < L.cptr[c + 1]; r += 64) srow_h.push_back(r);
+    for (int r = L.cptr[c]; r < L.cptr[c + 1]; r += step) srow_h.push_back(r);
   }
   L.sptr[L.ncol] = (int)srow_h.size();
   srow_h.push_back(L.n);
@@ -2062,6 +2204,83 @@ void build_sell(Hierarchy& H, int l, hipStream_t s) {
   H.free_one(L.vals, s);
   L.colind = nullptr;
   L.vals = nullptr;
+}
+
+// ---------------------------------------------------------------- point-based levels (host)
+int validate_blocks(int n, int bs, const int* rp, const int* ci, hipStream_t s) {
+  if (bs <= 1) return 0;
+  if (bs > BLK_MAX) fail(AMG_ERR_UNSUPPORTED, "block_size above 4");
+  if (n % bs) return 1;
+  DBuf f(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_validate_blocks, dim3(cdiv(n / bs, 256)), dim3(256), 0, s, n / bs, bs, rp, ci, f.as<int>());
+  AMG_HIP(hipGetLastError());
+  return read1(f.as<int>(), s);
+}
+
+void node_graph(Hierarchy& H, const Level& L, int bs, Level& S, hipStream_t s) {
+  const int nn = L.n / bs;
+  S = Level{};
+  S.n = nn;
+  S.T = L.T;
+  S.rowptr = H.alloc<int>((size_t)nn + 1, s);
+  DBuf cnt((size_t)nn * sizeof(int), s);
+  hipLaunchKernelGGL(k_node_count, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, bs, L.rowptr, cnt.as<int>());
+  exclusive_scan(cnt.as<int>(), S.rowptr, nn, s);
+  S.nnz = read1(S.rowptr + nn, s);
+  S.colind = H.alloc<int>((size_t)S.nnz, s);
+  S.vals = H.alloc<double>((size_t)S.nnz, s);
+  hipLaunchKernelGGL(k_node_fill, dim3(cdiv(nn, 256)), dim3(256), 0, s, nn, bs, L.rowptr, L.colind, L.vals,
+                     S.rowptr, S.colind, S.vals);
+  AMG_HIP(hipGetLastError());
+}
+
+void release_level(Hierarchy& H, Level& S, hipStream_t s) {
+  for (void* p : {(void*)S.rowptr, (void*)S.colind, (void*)S.vals, (void*)S.agg, (void*)S.members, (void*)S.mptr,
+                  (void*)S.tile_off, (void*)S.colour, (void*)S.crows})
+    H.free_one(p, s);
+  S = Level{};
+}
+
+void expand_aggregates(Hierarchy& H, const Level& S, int bs, Level& L, hipStream_t s) {
+  const int n = L.n, ncn = S.nc;
+  L.nc = ncn * bs;
+  L.agg = H.alloc<int>((size_t)n, s);
+  L.mptr = H.alloc<int>((size_t)L.nc + 1, s);
+  L.members = H.alloc<int>((size_t)n, s);
+  L.tile_off = nullptr;
+  L.ntiles = S.ntiles;
+  hipLaunchKernelGGL(k_expand_agg, dim3(cdiv(n, 256)), dim3(256), 0, s, n, bs, S.agg, L.agg);
+  hipLaunchKernelGGL(k_expand_members, dim3(cdiv(ncn, 256)), dim3(256), 0, s, ncn, bs, S.mptr, S.members, L.mptr,
+                     L.members);
+  AMG_HIP(hipGetLastError());
+}
+
+void expand_colours(Hierarchy& H, const Level& S, int bs, Level& L, hipStream_t s) {
+  const int n = L.n;
+  L.colour = H.alloc<int>((size_t)n, s);
+  L.crows = H.alloc<int>((size_t)n, s);
+  hipLaunchKernelGGL(k_expand_colour, dim3(cdiv(n, 256)), dim3(256), 0, s, n, bs, S.colour, S.crows, L.colour,
+                     L.crows);
+  AMG_HIP(hipGetLastError());
+  L.ncol = S.ncol;
+  L.cptr.resize(S.cptr.size());
+  for (size_t c = 0; c < S.cptr.size(); ++c) L.cptr[c] = S.cptr[c] * bs;
+}
+
+void block_inverses(Hierarchy& H, Level& L, int bs, bool f32, hipStream_t s) {
+  const int nn = L.n / bs;
+  L.dinv = H.alloc<double>((size_t)L.n * bs, s);
+  DBuf f(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_block_dinv, dim3(cdiv(nn, 128)), dim3(128), 0, s, nn, bs, L.rowptr, L.colind, L.vals, L.dinv,
+                     f.as<int>());
+  AMG_HIP(hipGetLastError());
+  if (read1(f.as<int>(), s)) fail(AMG_ERR_BAD_DIAGONAL, "singular diagonal block");
+  if (f32) {
+    L.dinv32 = H.alloc<float>((size_t)L.n * bs, s);
+    cast_f32(L.dinv, L.dinv32, (size_t)L.n * bs, s);
+  }
 }
 
 }  // namespace amgx

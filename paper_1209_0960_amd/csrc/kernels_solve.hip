@@ -97,12 +97,14 @@ struct Mat<double> {
   __device__ static const double* sval(const BDesc& d) { return d.sval64; }
   __device__ static const double* dg(const BDesc& d) { return d.dg64; }
   __device__ static const double* l1(const BDesc& d) { return d.l164; }
+  __device__ static const double* dinv(const BDesc& d) { return d.dinv64; }
 };
 template <>
 struct Mat<float> {
   __device__ static const float* sval(const BDesc& d) { return d.sval32; }
   __device__ static const float* dg(const BDesc& d) { return d.dg32; }
   __device__ static const float* l1(const BDesc& d) { return d.l132; }
+  __device__ static const float* dinv(const BDesc& d) { return d.dinv32; }
 };
 
 // Work item of this block.  Table launches read it from tab[blockIdx.x] and
@@ -255,6 +257,60 @@ __global__ __launch_bounds__(NT) void kb_gs(AMG_KARGS) {
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_gsr(AMG_KARGS) {
   AMG_BODY((kb_gs_body<V, R, true>))
+}
+
+// Block Gauss-Seidel pass of a point-based level (Sec. 4.2): the slices
+// [lo, hi) of one colour hold whole nodes of bs consecutive rows (a slice
+// starts at a node and the rows of a node never straddle two slices or two
+// wavefronts).  Row r of node rows [r0, r0 + bs): t_r = b_r - sum of a_rj x_j
+// over its entries outside the node's own block (entry order), then
+// x_r = sum_d dinv[r][d] t_(r0 + d), the node's t exchanged between its
+// lanes.  Nodes of one colour do not couple, so the update is race free.
+template <typename V, int R>
+__device__ __forceinline__ void kb_bgs_body(const Item& it, const BDesc& d) {
+  const int sl = it.lo + (int)(threadIdx.x / WAVE);
+  if (sl >= it.hi) return;  // whole wavefronts only: the shuffles below see every lane
+  const int lane = __lane_id();
+  const int r = d.srow[sl] + lane;
+  const bool act = r < d.srow[sl + 1];
+  const int bs = d.blk, comp = r % bs, r0 = r - comp;
+  const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
+  const V* x = static_cast<const V*>(d.x);
+  const V* sv = Mat<V>::sval(d);
+  V t[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) t[k] = 0;
+  for (int e = 0; e < w; ++e) {
+    const int j = d.scol[base + 64 * e + lane];
+    if (j < r0 || j >= r0 + bs) {  // outside the node's own block (padding names the row itself)
+      const V a = sv[base + 64 * e + lane];
+      V xv[R];
+      ldv<V, R>(x + (size_t)j * R, xv);
+#pragma unroll
+      for (int k = 0; k < R; ++k) t[k] = madd(a, xv[k], t[k]);
+    }
+  }
+  if (act) {
+    V bb[R];
+    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+#pragma unroll
+    for (int k = 0; k < R; ++k) t[k] = bb[k] - t[k];
+  }
+  V o[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) o[k] = 0;
+  const V* dinv = Mat<V>::dinv(d) + (size_t)(act ? r : 0) * bs;
+  for (int q = 0; q < bs; ++q) {
+    const int src = act ? lane - comp + q : lane;  // lane of row r0 + q (same wavefront)
+    const V dq = act ? dinv[q] : (V)0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = madd(dq, __shfl(t[k], src, WAVE), o[k]);
+  }
+  if (act) stv<V, R>(static_cast<V*>(d.x) + (size_t)r * R, o);
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_bgs(AMG_KARGS) {
+  AMG_BODY((kb_bgs_body<V, R>))
 }
 
 // The first Gauss-Seidel pass from x = 0: every off-diagonal product is a
@@ -1281,6 +1337,7 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
         hipLaunchKernelGGL((kb_hsgs<V, R, false>), g, bw, lds, s, t, D, BDesc{}, Item{}, L.aux);
     } break;
     case OP_JACOBI: AMG_LAUNCH(kb_jacobi, (V, R)); break;
+    case OP_BGS: AMG_LAUNCH(kb_bgs, (V, R)); break;
     case OP_RESTRICT: AMG_LAUNCH(kb_restrict, (V, R)); break;
     case OP_PROLONG: AMG_LAUNCH(kb_prolong, (V, R)); break;
     case OP_COARSE: AMG_LAUNCH(kb_coarse, (V, R)); break;
@@ -1309,6 +1366,7 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
     case OP_RESID:
     case OP_RESID_OFF:
     case OP_HSGS:
+    case OP_BGS:
     case OP_JACOBI:
     case OP_RESTRICT:
     case OP_PROLONG:
