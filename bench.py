@@ -22,7 +22,8 @@ jump-coefficient problems beside its published counts), "large" (layered
 reference), "batched" (64 uneven systems with 4 right-hand sides each,
 amg_setup_batched + pcg_solve_batched against a loop of single solves) and
 "serving" (a request stream served with continuous batching against serial
-plain-FP64 solves, with p50/p99 latency).
+plain-FP64 solves, with p50/p99 latency) and "block" (point-based AMG on a
+3-component coupled system against the scalar hierarchy of the same matrix).
 
 Prints one JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
@@ -196,8 +197,23 @@ def serving_section(A, P, seconds: float, rate: float):
     finally:
         srv.close()
     base, bstats, _ = S.serve_serial(reqs, vcycle_fp32=0)
-    unknowns = sum(r.n for r in recs)
+    # a point below capacity: the latency of service rather than of queueing
+    low_rate, low_seconds = rate / 10.0, 5.0 * seconds
     del reqs
+    A.release_cached_memory()
+    torch.cuda.empty_cache()
+    ltrace = P.serving_trace(rate=low_rate, seconds=low_seconds, seed=5)
+    lreqs, _ = S.requests_from_trace(ltrace)
+    lsrv = S.Server(cap_bytes=200e9, max_entries=32, setup_workers=2, vcycle_fp32=1)
+    try:
+        lrecs = lsrv.run(lreqs)
+        lstats = dict(lsrv.stats)
+    finally:
+        lsrv.close()
+    del lreqs
+    lsm = S.summarise(lrecs, **lstats)
+    unknowns = sum(r.n for r in recs)
+    A.release_cached_memory()
     torch.cuda.empty_cache()
     sm, sb = S.summarise(recs, **stats), S.summarise(base, **bstats)
     ok = all(r.status == A.OK for r in recs) and all(r.status == A.OK for r in base)
@@ -214,7 +230,62 @@ def serving_section(A, P, seconds: float, rate: float):
                         "makespan_s": sb.makespan_s, "hits": sb.hits, "setups": sb.setups},
         "throughput_ratio": sm.solves_per_s / sb.solves_per_s,
         "p99_ratio": sb.p99_ms / sm.p99_ms,
+        "below_capacity": {"workload": f"{len(ltrace)} requests: Poisson arrivals at {low_rate:g}/s over "
+                                       f"{low_seconds:g} s (seed 5), same request recipe",
+                           "solves_per_s": lsm.solves_per_s, "p50_ms": lsm.p50_ms, "p99_ms": lsm.p99_ms,
+                           "makespan_s": lsm.makespan_s, "max_running": lsm.max_running,
+                           "all_converged": all(r.status == A.OK for r in lrecs)},
     }
+
+
+def block_section(A, P, n: int = 96, bs: int = 3, seed: int = 6):
+    """Point-based AMG for systems (Sec. 4.2): the 3-component coupled
+    lognormal diffusion system on n^3 cells (problems.coupled), FP64 PCG to
+    1e-8 with the block hierarchy (node graph with row-sum norm weights,
+    P (x) I, block Gauss-Seidel) against the scalar hierarchy of the same
+    matrix; the FP32 block cycle in flexible CG; the level-0 block pass rate
+    from HIP events."""
+    import numpy as np
+    import torch
+
+    t = time.perf_counter()
+    s = P.coupled(n, bs=bs, seed=seed)
+    gen = time.perf_counter() - t
+    rp, ci, v, b = A.to_device(s)
+    out = {"workload": f"{bs}-component coupled lognormal diffusion {n}^3 cells (sigma^2=2, face couplings "
+                       f"I + v v^T, seed {seed}), FP64 PCG to 1e-8",
+           "unknowns": s.n, "nnz": s.nnz, "generation_s": gen}
+    for key, kw in (("block_fp64", dict(block_size=bs)), ("scalar_fp64", dict()),
+                    ("block_fp32_vcycle", dict(block_size=bs, vcycle_fp32=1))):
+        ts = []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            h = A.Hierarchy(rp, ci, v, **kw)
+            x, r = h.solve(b, rtol=1e-8, maxit=500)
+            lev = h.levels
+            h.close()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1e3)
+        out[key] = {"time_to_1e8_ms": float(np.median(ts[1:])), "setup_ms": r.setup_ms, "solve_ms": r.solve_ms,
+                    "iterations": r.iterations, "levels": lev, "true_rel_residual": r.true_rel_residual}
+        log(f"block section {key}: {out[key]}")
+    out["speedup_block_vs_scalar"] = out["scalar_fp64"]["time_to_1e8_ms"] / out["block_fp64"]["time_to_1e8_ms"]
+    h = A.Hierarchy(rp, ci, v, block_size=bs)
+    A.set_kernel_timing([A.KIND_SWEEP])
+    A.reset_kernel_timing()
+    h.solve(b, rtol=1e-8, maxit=500)
+    A.set_kernel_timing(False)
+    h.close()
+    ms, cnt, by = A.kernel_timing(A.KIND_SWEEP)
+    out["kb_bgs_level0"] = {"launches": cnt, "avg_us": ms * 1e3 / max(cnt, 1),
+                            "algorithmic_bytes_per_launch": by / max(cnt, 1),
+                            "GB/s": by / max(ms * 1e-3, 1e-12) / 1e9,
+                            "bytes": "entries 12 B, b, x read and written, diagonal and 3 values of the inverse "
+                                     "block per row"}
+    del rp, ci, v, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def large_section(A, P, n: int = 512, seed: int = 2):
@@ -371,6 +442,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="length of the request stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (per s)")
     ap.add_argument("--large-n", type=int, default=512, help="edge of the layered large section (0: skip)")
+    ap.add_argument("--block-n", type=int, default=96, help="edge of the point-based (block) AMG section (0: skip)")
     ap.add_argument("--no-bicgstab", action="store_true",
                     help="skip the BiCGSTAB / hybrid-smoother solves of the headline system")
     ap.add_argument("--only-headline", action="store_true",
@@ -465,6 +537,7 @@ def main():
     extra = {"step_ms_min": min(per_plain), "step_ms_max": max(per_plain)}
     if args.only_headline:
         args.no_bicgstab, args.large_n, args.batched_systems, args.serve_seconds = True, 0, 0, 0
+        args.block_n = 0
         args.no_cpu_baseline = True
     else:
         extra.update(extra_sections(args, A, P, torch, step, timed, x_plain, ms_per_step))
@@ -521,15 +594,16 @@ def main():
         for m in (80, 256):
             sl = P.poisson(m)
             lrp, lci, lv, lb = A.to_device(sl)
-            for smoother in (0, 2):
+            for smoother, tiles in ((0, 128), (2, 128), (0, 1024)):
                 torch.cuda.synchronize()
                 q0 = time.perf_counter()
-                h = A.Hierarchy(lrp, lci, lv, smoother=smoother)
+                h = A.Hierarchy(lrp, lci, lv, smoother=smoother, tile_rows=tiles)
                 _, rl = h.solve(lb, rtol=1e-8, method="bicgstab")
                 lev = h.levels
                 h.close()
                 torch.cuda.synchronize()
-                lap[f"{m}^3_{'hybrid_sgs' if smoother == 2 else 'mcsgs'}"] = {
+                tag = 'hybrid_sgs' if smoother == 2 else 'mcsgs'
+                lap[f"{m}^3_{tag}" + ("" if tiles == 128 else f"_tiles{tiles}")] = {
                     "levels": lev, "iterations": rl.iterations, "half_step_exit": bool(rl.half_step),
                     "time_to_1e8_ms": (time.perf_counter() - q0) * 1e3, "setup_ms": rl.setup_ms,
                     "solve_ms": rl.solve_ms, "true_rel_residual": rl.true_rel_residual}
@@ -612,6 +686,9 @@ def main():
         },
     }
     out["config"].update(extra)
+    if args.block_n > 0:
+        log(f"block section (coupled 3-component {args.block_n}^3) ...")
+        out["block"] = block_section(A, P, args.block_n)
     if args.large_n > 0:
         log(f"large section (layered {args.large_n}^3) ...")
         out["large"] = large_section(A, P, args.large_n)
@@ -622,6 +699,8 @@ def main():
         out["batched"] = batched_section(A, P, args.batched_systems)
         log(f"batched: {out['batched']['batched_ms']:.0f} ms vs loop {out['batched']['loop_ms']:.0f} ms")
     if args.serve_seconds > 0:
+        A.release_cached_memory()
+        torch.cuda.empty_cache()
         log("serving section ...")
         out["serving"] = serving_section(A, P, args.serve_seconds, args.serve_rate)
         log(f"serving: {out['serving']['served']['solves_per_s']:.1f} solves/s p99 "

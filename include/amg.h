@@ -268,6 +268,13 @@ typedef void *(*amg_alloc_fn)(size_t bytes, void *stream, void *ctx);
 typedef void (*amg_free_fn)(void *ptr, void *stream, void *ctx);
 AMG_API amg_status amg_set_allocator(amg_alloc_fn alloc, amg_free_fn free_fn, void *ctx);
 
+/* Returns the default allocator's cached blocks on the current device (memory
+ * of freed hierarchies, solve contexts and batches, kept for reuse) to the
+ * device, after synchronising the device.  Memory in use is not affected.
+ * Call it while no other call of the library is running, for instance before
+ * handing the memory to another allocator. */
+AMG_API amg_status amg_release_cached_memory(void);
+
 /* Device bytes held by the hierarchy. */
 AMG_API amg_status amg_hierarchy_bytes(const amg_hierarchy *h, size_t *bytes);
 

@@ -90,6 +90,8 @@ def lib():
         L.amg_status_string.argtypes = [st]
         L.amg_last_error.restype = C.c_char_p
         L.amg_last_error.argtypes = []
+        L.amg_release_cached_memory.restype = st
+        L.amg_release_cached_memory.argtypes = []
         L.amg_set_allocator.restype = st
         L.amg_set_allocator.argtypes = [vp, vp, vp]
         L.amg_hierarchy_bytes.restype = st
@@ -332,6 +334,11 @@ def set_allocator(alloc, free, ctx=None):
     """Install ctypes callbacks (ALLOC_FN/FREE_FN) or None to restore the default."""
     _check(lib().amg_set_allocator(C.cast(alloc, C.c_void_p) if alloc else None,
                                    C.cast(free, C.c_void_p) if free else None, ctx))
+
+
+def release_cached_memory():
+    """amg_release_cached_memory: hand the library's cached free blocks back to the device."""
+    _check(lib().amg_release_cached_memory())
 
 
 def set_kernel_timing(kinds=True):

@@ -123,6 +123,28 @@ void release_idle(int dev, hipStream_t s) {
 }
 }  // namespace
 
+// Frees every cached block of the current device after a device-wide
+// synchronisation (no stream can still use a freed block then).
+void release_cached_blocks() {
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  AMG_HIP(hipDeviceSynchronize());
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(g_cmu);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+      if (it->first.dev == dev) {
+        drop.push_back(it->second.p);
+        it = g_cache.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  RelaxedCapture relaxed;
+  for (void* p : drop) (void)hipFree(p);
+}
+
 hipError_t sync_stream_nothrow(hipStream_t s) {
   const unsigned long long gen = free_count();
   const hipError_t e = hipStreamSynchronize(s);
@@ -584,6 +606,10 @@ const char* amg_status_string(amg_status s) {
 }
 
 const char* amg_last_error(void) { return g_err.c_str(); }
+
+amg_status amg_release_cached_memory(void) {
+  return guarded([&] { release_cached_blocks(); });
+}
 
 amg_status amg_set_allocator(amg_alloc_fn alloc, amg_free_fn free_fn, void* ctx) {
   if ((alloc == nullptr) != (free_fn == nullptr)) {

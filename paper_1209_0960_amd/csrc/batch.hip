@@ -577,8 +577,8 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
         const int e = E[i];
         const Level& L = hier(B, e).lev[l];
         const int c = seq[i][j];
-        if (!zero || blk) {
-          add_slices(b, B, e, l, L.sptr[c], L.sptr[c + 1]);
+        if (!zero || blk) {  // a block pass also reads the bs values of its row of the inverse block
+          add_slices(b, B, e, l, L.sptr[c], L.sptr[c + 1], blk ? (double)L.bs / B.R : 0.0);
           continue;
         }
         const int s0 = L.sptr[c], s1 = L.sptr[c + 1];

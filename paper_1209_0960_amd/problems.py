@@ -312,7 +312,7 @@ def coupled(n: int, bs: int = 3, seed: int = 6, sigma2: float = 2.0) -> CSRSyste
     I = np.eye(bs)
     blocks = np.zeros((colind.shape[0], bs, bs))
     ko = np.nonzero(off)[0]
-    v = np.stack([V[a][l] for a, l in zip(axis[ko], low[ko])]) if ko.size else np.zeros((0, bs))
+    v = np.stack(V)[axis[ko], low[ko]]
     C = I[None, :, :] + v[:, :, None] * v[:, None, :]
     t = -vals[ko]  # transmissibility of the face
     blocks[ko] = -t[:, None, None] * C
