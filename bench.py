@@ -172,8 +172,9 @@ def batched_section(A, P, nsys: int, nrhs: int = 4, seed: int = 3):
         "autotune": {"per_class_rows": classes, "rhs_interleave": table["R"],
                      "rhs_interleave_ms": {str(k): v for k, v in table["R_ms"].items()},
                      "tuning_s": table["tuning_s"],
-                     "variants": "tile_rows in {64,128,256,512} x tail_rows in {0,8192} per size class; "
-                                 "right-hand sides per entry in {4,2,1}"},
+                     "variants": "tile_rows in {64,128,256,512} x tail_rows in {0, 8192, 2^30 (whole cycle in "
+                                 "one workgroup)} per size class, then the level-0 SpMV layout (SELL-64 or CSR "
+                                 "with lanes per row); right-hand sides per entry in {4,2,1}"},
         "iterations_max": max(its), "iterations_mean": float(sum(its)) / len(its),
         "all_converged": tst == A.OK and dst == A.OK and all(i["converged"] for inf in tinf for i in inf)
                          and all(r.converged for r in linf),

@@ -106,6 +106,9 @@ typedef struct amg_params {
                                 MCSGS, tail_rows 0).  With keep_setup_data the
                                 strong / isolated flags of amg_copy_level are
                                 those of the node graph. */
+  int32_t spmv_format;       /* level-0 outer product of CG: 0 SELL-64 slices   [0]
+                                (one lane per row); 1 CSR with a group of lanes per
+                                row (keeps the level's CSR arrays, 12 B per entry) */
 } amg_params;
 
 typedef struct amg_solve_info {

@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("post_sweeps", C.c_int32), ("vcycle_fp32", C.c_int32), ("flexible", C.c_int32),
                 ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int32), ("keep_setup_data", C.c_int32),
                 ("use_graphs", C.c_int32), ("tail_rows", C.c_int32),
-                ("colour_tile_rows", C.c_int32), ("block_size", C.c_int32)]
+                ("colour_tile_rows", C.c_int32), ("block_size", C.c_int32), ("spmv_format", C.c_int32)]
 
 
 class CSR(C.Structure):

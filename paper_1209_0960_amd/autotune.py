@@ -7,9 +7,14 @@ Three launch/layout variants are chosen by measurement on the GPU:
   setup's parallelism and per-tile latency, and the hierarchy it builds);
 * cycle variant, per size class: `tail_rows`, below which a system's levels
   are cycled by one workgroup instead of one launch per colour pass;
-* SpMV variant, per batch: R, the right-hand sides interleaved in one entry
+* SpMV variant, per size class: `spmv_format`, the layout of CG's level-0
+  product (SELL-64 slices with one lane per row, or CSR with a group of lanes
+  per row); per batch: R, the right-hand sides interleaved in one entry
   (R > 1 reads every matrix once for R products; R = 1 gives R entries per
   system and more independent work).
+
+`tail_rows` = 2^30 cycles every level of a system by one workgroup (the
+whole V-cycle of an entry in one launch per leg).
 
 A size class is the rows of a system.  For each class the candidates are
 timed on a sample of the batch's own systems (batched setup plus batched
@@ -27,7 +32,8 @@ import torch
 from . import amg as A
 
 TILES = (64, 128, 256, 512)
-TAILS = (0, 8192)
+TAILS = (0, 8192, 1 << 30)
+SPMV = (0, 1)
 RHS = (4, 2, 1)
 
 
@@ -97,11 +103,19 @@ def tune(systems, nrhs: int, sample: int = 4, reps: int = 2, **common) -> dict:
                     ms = min(ms, (a + b) * 1e3)
             if best is None or ms < best[2]:
                 best = (tile, tail, ms)
-        table[rows] = {"tile_rows": best[0], "tail_rows": best[1], "ms": best[2]}
+        fmt, fms = 0, best[2]
+        for f in SPMV[1:]:  # the SpMV layout with the chosen tile and cycle variants
+            ms = float("inf")
+            for _ in range(reps):
+                a, b, _, st, _ = run_batched(pick, lambda i: {"tile_rows": best[0], "tail_rows": best[1],
+                                                              "spmv_format": f}, nrhs, nrhs, **common)
+                if st == A.OK:
+                    ms = min(ms, (a + b) * 1e3)
+            if ms < fms:
+                fmt, fms = f, ms
+        table[rows] = {"tile_rows": best[0], "tail_rows": best[1], "spmv_format": fmt, "ms": fms}
 
-    def params_of(i):
-        c = table[systems[i][0].numel() - 1]
-        return {"tile_rows": c["tile_rows"], "tail_rows": c["tail_rows"]}
+    params_of = params_from(table, systems)
 
     rms = {}
     for R in RHS:
@@ -118,5 +132,5 @@ def tune(systems, nrhs: int, sample: int = 4, reps: int = 2, **common) -> dict:
 def params_from(table: dict, systems) -> callable:
     def params_of(i):
         c = table[systems[i][0].numel() - 1]
-        return {"tile_rows": c["tile_rows"], "tail_rows": c["tail_rows"]}
+        return {"tile_rows": c["tile_rows"], "tail_rows": c["tail_rows"], "spmv_format": c.get("spmv_format", 0)}
     return params_of

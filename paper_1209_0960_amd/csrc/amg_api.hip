@@ -334,6 +334,7 @@ void check_params(const amg_params& p) {
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
   if (p.tail_rows < 0) fail(AMG_ERR_INVALID_ARG, "tail_rows");
   if (p.colour_tile_rows < 64 || p.colour_tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows outside 64..1024");
+  if (p.spmv_format != 0 && p.spmv_format != 1) fail(AMG_ERR_INVALID_ARG, "spmv_format");
   if (p.block_size < 1) fail(AMG_ERR_INVALID_ARG, "block_size");
   if (p.block_size > 4) fail(AMG_ERR_UNSUPPORTED, "block_size above 4");
   if (p.block_size > 1 && p.smoother != AMG_SMOOTHER_MCSGS)
@@ -511,6 +512,7 @@ amg_status amg_default_params(amg_params* p) {
   p->tail_rows = 0;
   p->colour_tile_rows = 128;
   p->block_size = 1;
+  p->spmv_format = 0;
   return AMG_OK;
 }
 
@@ -744,7 +746,7 @@ amg_status amg_setup_batched(const amg_csr* A, int32_t nsys, const amg_params* p
   }
   int dev = 0;
   (void)hipGetDevice(&dev);
-  const int nthreads = std::max(1, std::min<int>(nsys, 8));
+  const int nthreads = std::max(1, std::min<int>(nsys, 16));
   std::atomic<int> next{0};
   std::vector<amg_status> st(nsys, AMG_OK);
   std::vector<std::string> msg(nsys);
@@ -882,8 +884,12 @@ amg_status amg_estimate_bytes(int32_t n, int32_t nnz, const amg_params* p, int32
   // Level 0 in solve order: SELL-64 off-diagonals (column + FP64 value, + FP32
   // copy), diagonal(s), permutation, row pointers, aggregate map and members.
   // The hybrid smoother adds two 16-bit wavefront steps per row.
+  // The CSR form of the outer product (spmv_format 1) keeps 12 B per entry more;
+  // point-based levels keep bs values of the inverse diagonal block per row.
+  const double bs = std::max(1, p->block_size);
   const double lev0 = (f32 ? 16.0 * Z + 12.0 * N : 12.0 * Z + 16.0 * N) +
-                      (p->smoother == AMG_SMOOTHER_HYBRID_SGS ? 4.0 * N : 0.0);
+                      (p->smoother == AMG_SMOOTHER_HYBRID_SGS ? 4.0 * N : 0.0) +
+                      (p->spmv_format == 1 ? 12.0 * Z : 0.0) + (bs > 1 ? (f32 ? 12.0 : 8.0) * bs * N : 0.0);
   // Coarser levels and slice padding stay below 35% of level 0 for aggregates
   // of 8-12 rows; the dense coarsest inverse and its factorisation workspace.
   const double cm = std::min<double>(std::max(p->coarse_max, 1), 4096);

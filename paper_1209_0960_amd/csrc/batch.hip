@@ -473,6 +473,9 @@ struct Builder {
 inline const Hierarchy& hier(const Batch& B, int slot) { return *B.ent[slot].bound; }
 inline int coarsest(const Batch& B, int slot) { return (int)hier(B, slot).lev.size() - 1; }
 inline bool sell0(const Batch& B, int slot) { return hier(B, slot).lev[0].scol != nullptr; }
+// The outer product (and residual) of CG reads level 0 as SELL-64 slices,
+// unless the hierarchy keeps the CSR form for it (spmv_format 1).
+inline bool outer_sell(const Batch& B, int slot) { return sell0(B, slot) && hier(B, slot).p.spmv_format == 0; }
 // First level cycled by the single-workgroup tail: the first with at most
 // tail_rows rows (the coarsest if none).
 inline int tail_start(const Batch& B, int slot) {
@@ -730,7 +733,7 @@ std::vector<int> build_resid_dot(Builder& b, const Batch& B, const std::vector<i
   b.begin(OP_RESID_DOT, 0, kind, which);
   for (size_t i = 0; i < S.size(); ++i) {
     const int e = S[i];
-    if (!sell0(B, e)) continue;
+    if (!outer_sell(B, e)) continue;
     const Level& L = hier(B, e).lev[0];
     const double per_slice = ((double)L.soff_h[L.nsl] * 12.0 + (double)L.n * (8.0 + 24.0 * R)) / L.nsl + 8.0;
     np[i] = b.chunks(B.desc_index(e, 0), L.nsl, red_blocks_slices(L.nsl), per_slice);
@@ -741,7 +744,7 @@ std::vector<int> build_resid_dot(Builder& b, const Batch& B, const std::vector<i
     for (size_t i = 0; i < S.size(); ++i) {
       const int e = S[i];
       const Level& L = hier(B, e).lev[0];
-      if (sell0(B, e) || L.sub != sub) continue;
+      if (outer_sell(B, e) || L.sub != sub) continue;
       const double per_row = (double)L.nnz / L.n * 12.0 + 4.0 + 24.0 * R;
       np[i] = b.chunks(B.desc_index(e, 0), L.n, red_blocks_rows(L.n), per_row);
     }
@@ -778,7 +781,7 @@ void build_iter(Builder& b, const Batch& B, const std::vector<int>& S, size_t* p
   b.begin(OP_SPMV_DOT, 0, AMG_KIND_SPMV_F64);
   for (size_t i = 0; i < S.size(); ++i) {
     const int e = S[i];
-    if (!sell0(B, e)) continue;
+    if (!outer_sell(B, e)) continue;
     const Level& L = hier(B, e).lev[0];
     const double per_slice = ((double)L.soff_h[L.nsl] * 12.0 + (double)L.n * (8.0 + 16.0 * R)) / L.nsl + 8.0;
     ns[i] = b.chunks(B.desc_index(e, 0), L.nsl, red_blocks_slices(L.nsl), per_slice);
@@ -789,7 +792,7 @@ void build_iter(Builder& b, const Batch& B, const std::vector<int>& S, size_t* p
     for (size_t i = 0; i < S.size(); ++i) {
       const int e = S[i];
       const Level& L = hier(B, e).lev[0];
-      if (sell0(B, e) || L.sub != sub) continue;
+      if (outer_sell(B, e) || L.sub != sub) continue;
       const double per_row = (double)L.nnz / L.n * 12.0 + 4.0 + 16.0 * R;
       ns[i] = b.chunks(B.desc_index(e, 0), L.n, red_blocks_rows(L.n), per_row);
     }

@@ -2200,6 +2200,7 @@ void build_sell(Hierarchy& H, int l, hipStream_t s) {
                      L.vals, L.scol, L.sval, L.dg);
   AMG_HIP(hipGetLastError());
   sync_stream(s);
+  if (l == 0 && H.p.spmv_format == 1) return;  // the outer product reads the CSR arrays (solve order)
   H.free_one(L.colind, s);
   H.free_one(L.vals, s);
   L.colind = nullptr;

@@ -356,3 +356,45 @@ def test_free_waits_for_queued_precond_apply(A):
     side.synchronize()
     torch.cuda.synchronize()
     assert torch.equal(z, zref)
+
+
+# ---------------------------------------------------------------- SpMV layout
+def test_csr_outer_product_against_oracle_and_in_batches(A):
+    """spmv_format 1: CG's level-0 product reads the CSR form with a group of
+    lanes per row.  Every FP64 iterate within 1e-10 of the oracle; a batch
+    mixing both layouts gives each entry its solve alone bit for bit."""
+    s = P.lognormal(24, seed=12)
+    rp, ci, v, b = tdev(s.rowptr, s.colind, s.vals, s.b)
+    maxit = 200
+    ho = O.Hierarchy(s.rowptr, s.colind, s.vals)
+    o = ho.pcg(s.b, rtol=1e-8, maxit=maxit, keep_iterates=True)
+    with A.Hierarchy(rp, ci, v, spmv_format=1) as hc, A.Hierarchy(rp, ci, v) as hs:
+        hist = torch.zeros((maxit + 1) * s.n, dtype=torch.float64, device="cuda")
+        x, r = hc.solve(b, rtol=1e-8, maxit=maxit, iter_hist=hist)
+        assert r.status == A.OK and abs(r.iterations - o["iterations"]) <= 1
+        H = hist.cpu().numpy().reshape(maxit + 1, s.n)
+        for it in range(1, min(r.iterations, o["iterations"]) + 1):
+            assert rel(H[it], o["iterates"][it]) <= 1e-10, it
+        xs_alone, rs_alone = hs.solve(b, rtol=1e-8, maxit=maxit)
+        bs = [b.clone(), b.clone()]
+        xs = [torch.zeros_like(b), torch.zeros_like(b)]
+        st, infos = A.pcg_solve_batched([hc.h, hs.h], bs, xs, nrhs=1, rtol=1e-8, maxit=maxit)
+        assert st == A.OK
+        assert torch.equal(xs[0], x) and infos[0][0]["iterations"] == r.iterations
+        assert torch.equal(xs[1], xs_alone) and infos[1][0]["iterations"] == rs_alone.iterations
+
+
+def test_release_cached_memory(A):
+    """The cached free blocks go back to the device; later setups allocate
+    anew and give the same results."""
+    s = P.lognormal(32, seed=13)
+    rp, ci, v, b = tdev(s.rowptr, s.colind, s.vals, s.b)
+    with A.Hierarchy(rp, ci, v) as h:
+        x1, r1 = h.solve(b)
+    free0 = torch.cuda.mem_get_info()[0]
+    A.release_cached_memory()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free1 > free0  # the hierarchy's and solve context's blocks were returned
+    with A.Hierarchy(rp, ci, v) as h:
+        x2, r2 = h.solve(b)
+    assert torch.equal(x1, x2) and r1.iterations == r2.iterations
