@@ -65,8 +65,19 @@ typedef struct amg_csr {
 /* Smoothers: multicolour symmetric Gauss-Seidel over the whole level;
  * l1-Jacobi; the paper's hybrid symmetric Gauss-Seidel (Sec. 3.2: block-
  * Jacobi over the tiles of tile_rows rows, one sequential forward + backward
- * Gauss-Seidel sweep inside each tile, levels kept in natural order). */
-enum { AMG_SMOOTHER_MCSGS = 0, AMG_SMOOTHER_L1_JACOBI = 1, AMG_SMOOTHER_HYBRID_SGS = 2 };
+ * Gauss-Seidel sweep inside each tile, levels kept in natural order); the
+ * same hybrid form with each tile's rows swept in the order of the level's
+ * multicolouring (colour, then row; levels kept in natural order), which
+ * runs a level's whole symmetric step in one launch: one workgroup per tile,
+ * at most one wavefront step per colour and direction (for coarse levels,
+ * where the multicolour smoother's two launches per colour are latency
+ * bound). */
+enum {
+  AMG_SMOOTHER_MCSGS = 0,
+  AMG_SMOOTHER_L1_JACOBI = 1,
+  AMG_SMOOTHER_HYBRID_SGS = 2,
+  AMG_SMOOTHER_TILE_MCSGS = 3
+};
 
 /* Parameters.  Defaults from amg_default_params() in brackets. */
 typedef struct amg_params {
@@ -109,6 +120,11 @@ typedef struct amg_params {
   int32_t spmv_format;       /* level-0 outer product of CG: 0 SELL-64 slices   [0]
                                 (one lane per row); 1 CSR with a group of lanes per
                                 row (keeps the level's CSR arrays, 12 B per entry) */
+  int32_t coarse_smoother;   /* AMG_SMOOTHER_* of levels coarse_from and below;  [-1]
+                                -1: `smoother` on every level.  The tile forms
+                                (HYBRID_SGS, TILE_MCSGS) use tiles of tile_rows
+                                rows on every level they run on. */
+  int32_t coarse_from;       /* first level of coarse_smoother (>= 1)           [1]  */
 } amg_params;
 
 typedef struct amg_solve_info {

@@ -33,14 +33,15 @@ class Params(C.Structure):
                 ("tile_rows", C.c_int), ("smoother", C.c_int), ("pre_sweeps", C.c_int),
                 ("post_sweeps", C.c_int), ("vcycle_fp32", C.c_int), ("flexible", C.c_int),
                 ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int), ("colour_tile_rows", C.c_int),
-                ("block_size", C.c_int)]
+                ("block_size", C.c_int), ("coarse_smoother", C.c_int), ("coarse_from", C.c_int)]
 
 
 def default_params(**kw) -> Params:
     p = Params(strength_threshold=0.08, isolated_threshold=1e-5, agg_min=8, agg_max=12,
                agg_diameter=3, omega=1.6, coarse_max=500, max_levels=25, tile_rows=128,
                smoother=0, pre_sweeps=1, post_sweeps=1, vcycle_fp32=0, flexible=-1,
-               colour_seed=0, check_symmetry=1, colour_tile_rows=128, block_size=1)
+               colour_seed=0, check_symmetry=1, colour_tile_rows=128, block_size=1,
+               coarse_smoother=-1, coarse_from=1)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -76,7 +77,7 @@ def lib():
         L.orc_mcsgs.restype = None
         L.orc_mcsgs.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, I32P, C.c_int, F64P, F64P]
         L.orc_hybrid_sgs.restype = None
-        L.orc_hybrid_sgs.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, C.c_int, F64P, F64P]
+        L.orc_hybrid_sgs.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, C.c_int, F64P, F64P, C.c_void_p]
         L.orc_setup.restype = C.c_void_p
         L.orc_setup.argtypes = [C.c_int, C.c_int, I32P, I32P, F64P, C.POINTER(Params), C.POINTER(C.c_int)]
         L.orc_free.restype = None
@@ -197,11 +198,14 @@ def mcsgs(rowptr, colind, vals, col, ncol, b, x):
     return x
 
 
-def hybrid_sgs(rowptr, colind, vals, tile_rows, b, x):
-    """One hybrid SGS step (block-Jacobi over tiles of tile_rows rows, SGS inside)."""
+def hybrid_sgs(rowptr, colind, vals, tile_rows, b, x, colour=None):
+    """One hybrid SGS step (block-Jacobi over tiles of tile_rows rows, SGS
+    inside); with `colour`, each tile's rows are swept in (colour, row) order."""
     rp, ci, v = _csr(rowptr, colind, vals)
     x = np.ascontiguousarray(x, np.float64).copy()
-    lib().orc_hybrid_sgs(rp.shape[0] - 1, ci.shape[0], rp, ci, v, tile_rows, np.ascontiguousarray(b, np.float64), x)
+    col = None if colour is None else np.ascontiguousarray(colour, np.int32)
+    lib().orc_hybrid_sgs(rp.shape[0] - 1, ci.shape[0], rp, ci, v, tile_rows, np.ascontiguousarray(b, np.float64), x,
+                         None if col is None else col.ctypes.data)
     return x
 
 

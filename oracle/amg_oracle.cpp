@@ -583,9 +583,20 @@ struct Params {
   int check_symmetry;
   int colour_tile_rows;  // rows per tile of the colouring order
   int block_size;        // unknowns per node (point-based AMG for systems); 1: scalar
+  int coarse_smoother;   // smoother of the levels from coarse_from on (-1: `smoother` on every level)
+  int coarse_from;
 };
 
-enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1, SMOOTH_HYBRID = 2 };
+// SMOOTH_TILE_MCSGS (not in the paper): the hybrid form of Sec. 3.2
+// (block-Jacobi over the tiles of tile_rows rows, one symmetric Gauss-Seidel
+// step inside each) with the rows of each tile taken in the order of the
+// level's multicolouring (colour, then row), meant for coarse levels.
+enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1, SMOOTH_HYBRID = 2, SMOOTH_TILE_MCSGS = 3 };
+
+// Smoother of level l.
+int smoother_of(const Params& p, int l) {
+  return (p.coarse_smoother >= 0 && l >= p.coarse_from) ? p.coarse_smoother : p.smoother;
+}
 
 struct Level {
   Csr A;
@@ -755,10 +766,13 @@ void gs_row(const Csr& A, const V* val, int i, const V* b, V* x) {
 // is formed once, before any tile changes); couplings inside the tile use the
 // current values.  Row update: acc = b_i - (couplings to other tiles, CSR
 // order) - (couplings inside the tile except a_ii, CSR order); x_i = acc/a_ii.
+// Rows of a tile are swept in natural order, or, given a colouring, in the
+// order (colour, row) forward and its reverse backward.
 // Parity pin: x + M^-1 (b - A x) with M = (D + L_B) D^-1 (D + U_B), L_B and
-// U_B the strict triangles of the tile-block-diagonal part of A.
+// U_B the strict triangles, in the sweep order, of the tile-block-diagonal
+// part of A.
 template <typename V>
-void hybrid_sgs(const Csr& A, const V* val, int T, const V* b, V* x) {
+void hybrid_sgs(const Csr& A, const V* val, int T, const V* b, V* x, const int* colour = nullptr) {
   const int n = A.n;
   const std::vector<V> xold(x, x + n);
   auto row = [&](int i, int lo, int hi) {
@@ -779,8 +793,11 @@ void hybrid_sgs(const Csr& A, const V* val, int T, const V* b, V* x) {
   };
   for (int lo = 0; lo < n; lo += T) {
     const int hi = std::min(n, lo + T);
-    for (int i = lo; i < hi; ++i) row(i, lo, hi);
-    for (int i = hi - 1; i >= lo; --i) row(i, lo, hi);
+    std::vector<int> ord;  // the tile's rows in sweep order: natural, or (colour, row)
+    for (int i = lo; i < hi; ++i) ord.push_back(i);
+    if (colour) std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return colour[a] < colour[c]; });
+    for (size_t q = 0; q < ord.size(); ++q) row(ord[q], lo, hi);
+    for (size_t q = ord.size(); q-- > 0;) row(ord[q], lo, hi);
   }
 }
 
@@ -811,13 +828,16 @@ void smooth(const Hier& H, int l, const V* b, V* x) {
       for (int i : L.nodes_of_colour[c]) block_gs_node<V>(L.A, val, dinv, bs, i, b, x);
     return;
   }
-  if (H.p.smoother == SMOOTH_MCSGS) {
+  const int sm = smoother_of(H.p, l);
+  if (sm == SMOOTH_MCSGS) {
     for (int c = 0; c < L.ncol; ++c)  // forward sweep
       for (int i : L.rows_of_colour[c]) gs_row<V>(L.A, val, i, b, x);
     for (int c = L.ncol - 1; c >= 0; --c)  // backward sweep
       for (int i : L.rows_of_colour[c]) gs_row<V>(L.A, val, i, b, x);
-  } else if (H.p.smoother == SMOOTH_HYBRID) {
+  } else if (sm == SMOOTH_HYBRID) {
     hybrid_sgs<V>(L.A, val, H.p.tile_rows, b, x);
+  } else if (sm == SMOOTH_TILE_MCSGS) {
+    hybrid_sgs<V>(L.A, val, H.p.tile_rows, b, x, L.colour.data());
   } else {
     // l1-Jacobi (Baker, Falgout, Kolev, Yang 2011, pointwise): x += (b - A x) / d
     const int n = L.A.n;
@@ -935,7 +955,7 @@ bool finish_level(Level& L, const Params& p, int l) {
     }
     L.dinv32.resize(L.dinv.size());
     for (size_t k = 0; k < L.dinv.size(); ++k) L.dinv32[k] = (float)L.dinv[k];
-  } else if (p.smoother == SMOOTH_HYBRID) {  // no multicolouring: one colour, natural order
+  } else if (smoother_of(p, l) == SMOOTH_HYBRID) {  // no multicolouring: one colour, natural order
     L.colour.assign(L.A.n, 0);
     L.ncol = 1;
   } else {
@@ -957,7 +977,12 @@ bool finish_level(Level& L, const Params& p, int l) {
 int build(Hier& H, const Csr& A0) {
   const Params& p = H.p;
   const int bs = p.block_size;
-  if (bs > 1 && (bs > 16 || p.smoother != SMOOTH_MCSGS || !block_structure_ok(A0, bs))) return ORC_INVALID;
+  if (p.smoother < 0 || p.smoother > SMOOTH_TILE_MCSGS || p.coarse_smoother < -1 ||
+      p.coarse_smoother > SMOOTH_TILE_MCSGS || (p.coarse_smoother >= 0 && p.coarse_from < 1))
+    return ORC_INVALID;
+  if (bs > 1 && (bs > 16 || p.smoother != SMOOTH_MCSGS || (p.coarse_smoother >= 0 && p.coarse_smoother != SMOOTH_MCSGS) ||
+                 !block_structure_ok(A0, bs)))
+    return ORC_INVALID;
   int st = validate(A0, p.check_symmetry);
   if (st) return st;
   H.lev.clear();
@@ -1028,6 +1053,7 @@ struct orc_params {
   int check_symmetry;
   int colour_tile_rows;
   int block_size;
+  int coarse_smoother, coarse_from;
 };
 
 static Params to_params(const orc_params* q) {
@@ -1050,6 +1076,8 @@ static Params to_params(const orc_params* q) {
   p.check_symmetry = q->check_symmetry;
   p.colour_tile_rows = q->colour_tile_rows;
   p.block_size = q->block_size < 1 ? 1 : q->block_size;
+  p.coarse_smoother = q->coarse_smoother;
+  p.coarse_from = q->coarse_from;
   return p;
 }
 
@@ -1145,10 +1173,12 @@ void orc_mcsgs(int n, int nnz, const int* ptr, const int* col, const double* val
 }
 
 // One hybrid SGS step with tiles of T rows on x in place.
+// colour: NULL (natural order inside each tile) or n colours (tile rows
+// taken in (colour, row) order).
 void orc_hybrid_sgs(int n, int nnz, const int* ptr, const int* col, const double* val, int T, const double* b,
-                    double* x) {
+                    double* x, const int* colour) {
   Csr A = make_csr(n, nnz, ptr, col, val);
-  hybrid_sgs<double>(A, A.val.data(), T, b, x);
+  hybrid_sgs<double>(A, A.val.data(), T, b, x, colour);
 }
 
 void* orc_setup(int n, int nnz, const int* ptr, const int* col, const double* val, const orc_params* q,

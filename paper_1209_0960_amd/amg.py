@@ -25,7 +25,7 @@ STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID_ARG", 2: "AMG_ERR_BAD_DIAGONAL", 3: "
 ERR_INVALID_ARG, ERR_BAD_DIAGONAL, ERR_NOT_SYMMETRIC, ERR_NOT_SPD = 1, 2, 3, 4
 ERR_COARSENING_STALLED, ERR_OUT_OF_MEMORY, ERR_BREAKDOWN, ERR_NOT_CONVERGED = 5, 6, 7, 8
 ERR_HIP, ERR_UNSUPPORTED = 9, 10
-SMOOTHER_MCSGS, SMOOTHER_L1_JACOBI, SMOOTHER_HYBRID_SGS = 0, 1, 2
+SMOOTHER_MCSGS, SMOOTHER_L1_JACOBI, SMOOTHER_HYBRID_SGS, SMOOTHER_TILE_MCSGS = 0, 1, 2, 3
 KIND_SPMV_F64, KIND_SWEEP, KIND_RESTRICT, KIND_PROLONG, KIND_CG_VEC, KIND_COARSE_LEVELS, KIND_OTHER = range(7)
 
 
@@ -43,7 +43,8 @@ class Params(C.Structure):
                 ("post_sweeps", C.c_int32), ("vcycle_fp32", C.c_int32), ("flexible", C.c_int32),
                 ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int32), ("keep_setup_data", C.c_int32),
                 ("use_graphs", C.c_int32), ("tail_rows", C.c_int32),
-                ("colour_tile_rows", C.c_int32), ("block_size", C.c_int32), ("spmv_format", C.c_int32)]
+                ("colour_tile_rows", C.c_int32), ("block_size", C.c_int32), ("spmv_format", C.c_int32),
+                ("coarse_smoother", C.c_int32), ("coarse_from", C.c_int32)]
 
 
 class CSR(C.Structure):

@@ -328,16 +328,18 @@ void check_params(const amg_params& p) {
   if (p.tile_rows < 64 || p.tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "tile_rows outside 64..1024");
   if (p.coarse_max < 1 || p.max_levels < 1) fail(AMG_ERR_INVALID_ARG, "coarse_max/max_levels");
   if (p.max_levels > MAX_LEVELS) fail(AMG_ERR_UNSUPPORTED, "max_levels above 32");
-  if (p.smoother != AMG_SMOOTHER_MCSGS && p.smoother != AMG_SMOOTHER_L1_JACOBI &&
-      p.smoother != AMG_SMOOTHER_HYBRID_SGS)
-    fail(AMG_ERR_INVALID_ARG, "smoother");
+  if (p.smoother < AMG_SMOOTHER_MCSGS || p.smoother > AMG_SMOOTHER_TILE_MCSGS) fail(AMG_ERR_INVALID_ARG, "smoother");
+  if (p.coarse_smoother < -1 || p.coarse_smoother > AMG_SMOOTHER_TILE_MCSGS)
+    fail(AMG_ERR_INVALID_ARG, "coarse_smoother");
+  if (p.coarse_smoother >= 0 && p.coarse_from < 1) fail(AMG_ERR_INVALID_ARG, "coarse_from");
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
   if (p.tail_rows < 0) fail(AMG_ERR_INVALID_ARG, "tail_rows");
   if (p.colour_tile_rows < 64 || p.colour_tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows outside 64..1024");
   if (p.spmv_format != 0 && p.spmv_format != 1) fail(AMG_ERR_INVALID_ARG, "spmv_format");
   if (p.block_size < 1) fail(AMG_ERR_INVALID_ARG, "block_size");
   if (p.block_size > 4) fail(AMG_ERR_UNSUPPORTED, "block_size above 4");
-  if (p.block_size > 1 && p.smoother != AMG_SMOOTHER_MCSGS)
+  if (p.block_size > 1 && (p.smoother != AMG_SMOOTHER_MCSGS ||
+                           (p.coarse_smoother >= 0 && p.coarse_smoother != AMG_SMOOTHER_MCSGS)))
     fail(AMG_ERR_UNSUPPORTED, "point-based levels (block_size > 1) take the multicolour smoother only");
   if (p.block_size > 1 && p.tail_rows > 0)
     fail(AMG_ERR_UNSUPPORTED, "point-based levels (block_size > 1) are not cycled by the one-workgroup tail");
@@ -423,11 +425,14 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   const int Lc = (int)H.lev.size() - 1;
   H.lev[Lc].nc = 0;
   const bool f32 = p.vcycle_fp32 != 0;
-  const bool hybrid = p.smoother == AMG_SMOOTHER_HYBRID_SGS;
   for (int l = 0; l <= Lc; ++l) {
     H.lev[l].bs = bs;
-    if (hybrid) {
+    H.lev[l].sm = level_smoother(p, l);
+    if (H.lev[l].sm == AMG_SMOOTHER_HYBRID_SGS) {
       colour_single(H, H.lev[l], s);
+    } else if (H.lev[l].sm == AMG_SMOOTHER_TILE_MCSGS) {  // colours set the sweep order inside a tile
+      colour(H, H.lev[l], p.colour_seed + (uint32_t)l, s);
+      tile_colour_order(H, H.lev[l], l < Lc, s);
     } else if (bs > 1) {  // node colours, shared by each node's unknowns
       Level S;
       node_graph(H, H.lev[l], bs, S, s);
@@ -449,7 +454,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   }
   for (int l = 0; l < Lc; ++l) {
     Level& L = H.lev[l];
-    if (p.smoother == AMG_SMOOTHER_L1_JACOBI) {
+    if (L.sm == AMG_SMOOTHER_L1_JACOBI) {
       if (f32) {
         L.l1_32 = H.alloc<float>((size_t)L.n, s);
         l1_diag(L, nullptr, L.l1_32, s);
@@ -460,7 +465,10 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     }
     if (bs > 1) block_inverses(H, L, bs, f32, s);
     build_sell(H, l, s);
-    if (hybrid) hybrid_steps(H, L, p.tile_rows, s);
+    if (tile_sweeps(L.sm)) {
+      hybrid_steps(H, L, p.tile_rows, s);
+      tile_couplings(H, L, f32, s);
+    }
     L.sptr_d = H.alloc<int>(L.sptr.size(), s);
     AMG_HIP(hipMemcpyAsync(L.sptr_d, L.sptr.data(), L.sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
     if (f32) {
@@ -513,6 +521,8 @@ amg_status amg_default_params(amg_params* p) {
   p->colour_tile_rows = 128;
   p->block_size = 1;
   p->spmv_format = 0;
+  p->coarse_smoother = -1;
+  p->coarse_from = 1;
   return AMG_OK;
 }
 
@@ -645,7 +655,7 @@ amg_status amg_level_info(const amg_hierarchy* h, int32_t l, int32_t* n, int32_t
   const Level& L = h->H.lev[l];
   if (n) *n = L.n;
   if (nnz) *nnz = L.nnz;
-  if (ncolours) *ncolours = L.ncol;
+  if (ncolours) *ncolours = L.tcol ? L.tncol : L.ncol;
   if (n_next) *n_next = L.nc;
   return AMG_OK;
 }
@@ -666,7 +676,8 @@ amg_status amg_copy_level(const amg_hierarchy* h, int32_t l, int32_t* agg, int32
     if (iso && L.iso) AMG_HIP(hipMemcpy(iso, L.iso, iflags, hipMemcpyDeviceToHost));
     if (!L.perm) {  // natural order (the coarsest level, or a one-level hierarchy)
       if (agg && L.agg && L.nc > 0) AMG_HIP(hipMemcpy(agg, L.agg, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
-      if (colour) AMG_HIP(hipMemcpy(colour, L.colour, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+      if (colour)
+        AMG_HIP(hipMemcpy(colour, L.tcol ? L.tcol : L.colour, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
       if (rowptr) AMG_HIP(hipMemcpy(rowptr, L.rowptr, ((size_t)n + 1) * sizeof(int), hipMemcpyDeviceToHost));
       if (colind) AMG_HIP(hipMemcpy(colind, L.colind, (size_t)nnz * sizeof(int), hipMemcpyDeviceToHost));
       if (vals) AMG_HIP(hipMemcpy(vals, L.vals, (size_t)nnz * sizeof(double), hipMemcpyDeviceToHost));
@@ -710,9 +721,14 @@ amg_status amg_copy_level(const amg_hierarchy* h, int32_t l, int32_t* agg, int32
       }
     }
     if (rowptr) std::memcpy(rowptr, rp.data(), ((size_t)n + 1) * sizeof(int));
-    if (colour)
+    if (colour && L.tcol) {  // colours of the tile sweep order (solve order)
+      std::vector<int> tc(n);
+      AMG_HIP(hipMemcpy(tc.data(), L.tcol, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+      for (int r = 0; r < n; ++r) colour[perm[r]] = tc[r];
+    } else if (colour) {
       for (int c = 0; c < L.ncol; ++c)
         for (int r = L.cptr[c]; r < L.cptr[c + 1]; ++r) colour[perm[r]] = c;
+    }
     if (agg && L.nc > 0) {
       std::vector<int> pagg(n), nperm;
       AMG_HIP(hipMemcpy(pagg.data(), L.agg, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
@@ -883,12 +899,14 @@ amg_status amg_estimate_bytes(int32_t n, int32_t nnz, const amg_params* p, int32
   const double vb = f32 ? 4.0 : 8.0;
   // Level 0 in solve order: SELL-64 off-diagonals (column + FP64 value, + FP32
   // copy), diagonal(s), permutation, row pointers, aggregate map and members.
-  // The hybrid smoother adds two 16-bit wavefront steps per row.
+  // The hybrid smoother adds two 16-bit wavefront steps per row, its
+  // colour-ordered form the colours as well.
   // The CSR form of the outer product (spmv_format 1) keeps 12 B per entry more;
   // point-based levels keep bs values of the inverse diagonal block per row.
   const double bs = std::max(1, p->block_size);
   const double lev0 = (f32 ? 16.0 * Z + 12.0 * N : 12.0 * Z + 16.0 * N) +
                       (p->smoother == AMG_SMOOTHER_HYBRID_SGS ? 4.0 * N : 0.0) +
+                      (p->smoother == AMG_SMOOTHER_TILE_MCSGS ? 8.0 * N : 0.0) +
                       (p->spmv_format == 1 ? 12.0 * Z : 0.0) + (bs > 1 ? (f32 ? 12.0 : 8.0) * bs * N : 0.0);
   // Coarser levels and slice padding stay below 35% of level 0 for aggregates
   // of 8-12 rows; the dense coarsest inverse and its factorisation workspace.

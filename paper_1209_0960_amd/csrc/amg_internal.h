@@ -135,11 +135,30 @@ struct Level {
   float* sval32 = nullptr;
   double* dg = nullptr;
   float* dg32 = nullptr;
+  // smoother of this level (AMG_SMOOTHER_*)
+  int sm = AMG_SMOOTHER_MCSGS;
+  // tile-ordered multicolour smoother: the level's colours (solve order) and
+  // their count, and per tile of T rows the first tile-local row of each
+  // colour (ntiles x (tncol + 1)); the solve order takes each tile's rows
+  // colour by colour, the slices see one colour of 64 consecutive rows
+  int* tcol = nullptr;
+  int tncol = 0;
+  int* tcb = nullptr;
   // hybrid smoother (natural order, slices of 64 consecutive rows)
   unsigned short* hsf = nullptr;  // n: forward wavefront step inside the tile
   unsigned short* hsb = nullptr;  // n: backward wavefront step
   int hdf = 0, hdb = 0;           // largest steps
   int hw = 0;                     // most in-tile couplings of a row
+  int hg = 1;                     // lanes per row of the in-tile sweeps (1, or HS_G when hw > 8)
+  // in-tile couplings of each row (tile sweeps): icp (n+1) offsets, icc local
+  // column (row - first row of the tile), icv value (FP64, or FP32 on FP32
+  // cycles), in SELL entry order; a tile's couplings are contiguous
+  int* icp = nullptr;
+  unsigned short* icc = nullptr;
+  double* icv = nullptr;
+  float* icv32 = nullptr;
+  int icmax = 0;                  // most in-tile couplings of one tile
+  long long icn = 0;              // in-tile couplings of the level
   // optional setup data (natural order; on point-based levels per node and node-graph entry)
   uint8_t* strong = nullptr;
   uint8_t* iso = nullptr;
@@ -243,6 +262,26 @@ void colour_single(Hierarchy& H, Level& L, hipStream_t s);
 // Wavefront steps of the in-tile sweeps of the hybrid smoother (after
 // build_sell; the level has one colour).
 void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s);
+// After colour() on a level of the tile-ordered multicolour smoother: the
+// solve order takes each tile's rows colour by colour (reorder; the coarsest
+// level keeps natural order), one colour for the slices, the colours in
+// L.tcol (solve order) and each tile's colour bounds in L.tcb.
+void tile_colour_order(Hierarchy& H, Level& L, bool reorder, hipStream_t s);
+// The in-tile couplings of a tile-sweep level (after build_sell and
+// hybrid_steps, before the FP64 SELL values of an FP32 level are dropped).
+void tile_couplings(Hierarchy& H, Level& L, bool f32, hipStream_t s);
+
+// Lanes per row of the in-tile sweeps on levels whose rows have more than 8
+// in-tile couplings (the others take one lane per row).
+constexpr int HS_G = 4;
+
+// Smoother of level l under parameters p.
+inline int level_smoother(const amg_params& p, int l) {
+  return p.coarse_smoother >= 0 && l >= p.coarse_from ? p.coarse_smoother : p.smoother;
+}
+// Whether level l's smoother runs as tile sweeps (the hybrid smoother, in
+// natural or colour order: the same launches, the order is in the steps).
+inline bool tile_sweeps(int sm) { return sm == AMG_SMOOTHER_HYBRID_SGS || sm == AMG_SMOOTHER_TILE_MCSGS; }
 void cast_f32(const double* in, float* out, size_t n, hipStream_t s);
 void l1_diag(const Level& L, double* out64, float* out32, hipStream_t s);
 // Dense FP64 factorisation of the coarsest level and its explicit inverse.
@@ -301,7 +340,15 @@ struct BDesc {
   // hybrid smoother: wavefront step of each row in the forward / backward
   // sweep inside its tile of T rows, and the largest step of each sweep
   const unsigned short *hsf, *hsb;
-  int T, hdf, hdb, hw;
+  int T, hdf, hdb, hw, hg;
+  const int* icp;                   // in-tile couplings (tile sweeps): offsets, local column, value
+  const unsigned short* icc;
+  const double* icv64;
+  const float* icv32;
+  const int* tcb;                   // tile-ordered multicolour levels: colour bounds of each tile (tncol + 1)
+  const int* tcol;                  //   and the colour of each row (solve order)
+  int tncol;
+  int sm;                           // AMG_SMOOTHER_* of the level (tile forms: OP_RESID_OFF + OP_HSGS)
   const int* ctl;                   // [CTL_INTS]
   int active;                       // 0: the entry is finished (table launches skip it)
   int n, nc, nsl, nL;
@@ -340,11 +387,12 @@ enum {
   OP_RESID_OFF,  // hybrid smoother: t = b - (couplings to other tiles) x (slices)
   OP_HSGS,       // hybrid smoother: in-tile forward + backward sweeps (tiles; aux = 1: from b, x = 0)
   OP_BGS,        // point-based level: block Gauss-Seidel on the slices of one colour (whole nodes)
+  OP_TSGS,       // tile-ordered multicolour smoother: in-tile sweeps colour by colour (tiles; aux = 1: from b)
 };
 enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
 
 struct Launch {
-  int op = 0, level = 0, aux = 0, aux2 = 0;
+  int op = 0, level = 0, aux = 0, aux2 = 0, aux3 = 0;
   size_t off = 0;  // first item in the plan's table
   int nblk = 0;
   int kind = KIND_NONE;

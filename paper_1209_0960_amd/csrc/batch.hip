@@ -199,6 +199,7 @@ struct Batch {
   // finished entries are only switched off, the launch plan is kept.
   bool deferred = false;
   int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0, tile_rows = 0, bs = 1;
+  int coarse_smoother = -1, coarse_from = 1;  // per-level smoother choice (shared by the entries)
   hipStream_t work = nullptr;
   hipEvent_t ev = nullptr;
   BDesc* desc_d = nullptr;
@@ -255,14 +256,19 @@ void check_uniform(Batch& B, const Hierarchy& H) {
     B.flexible = H.flexible;
     B.tile_rows = H.p.tile_rows;
     B.bs = H.p.block_size;
+    B.coarse_smoother = H.p.coarse_smoother;
+    B.coarse_from = H.p.coarse_from;
     return;
   }
-  if (B.fp32 != fp32 || B.smoother != H.p.smoother || B.pre != H.p.pre_sweeps || B.post != H.p.post_sweeps ||
-      B.flexible != H.flexible || B.bs != H.p.block_size)
+  const bool same_coarse = B.coarse_smoother == H.p.coarse_smoother &&
+                           (B.coarse_smoother < 0 || B.coarse_from == H.p.coarse_from);
+  if (B.fp32 != fp32 || B.smoother != H.p.smoother || !same_coarse || B.pre != H.p.pre_sweeps ||
+      B.post != H.p.post_sweeps || B.flexible != H.flexible || B.bs != H.p.block_size)
     fail(AMG_ERR_INVALID_ARG,
-         "hierarchies of one batch must share vcycle_fp32, smoother, pre/post sweeps, block size and the CG variant");
-  if (B.smoother == AMG_SMOOTHER_HYBRID_SGS && B.tile_rows != H.p.tile_rows)
-    fail(AMG_ERR_INVALID_ARG, "hierarchies of one batch with the hybrid smoother must share tile_rows");
+         "hierarchies of one batch must share vcycle_fp32, the smoothers, pre/post sweeps, block size and the CG "
+         "variant");
+  if ((tile_sweeps(B.smoother) || tile_sweeps(B.coarse_smoother)) && B.tile_rows != H.p.tile_rows)
+    fail(AMG_ERR_INVALID_ARG, "hierarchies of one batch with a tile smoother must share tile_rows");
 }
 
 // The fields of a level's descriptor that come from the hierarchy (matrix,
@@ -298,6 +304,15 @@ void level_desc(BDesc& d, const Hierarchy& H, int l) {
   d.hdf = L.hdf;
   d.hdb = L.hdb;
   d.hw = L.hw;
+  d.hg = L.hg;
+  d.icp = L.icp;
+  d.icc = L.icc;
+  d.icv64 = L.icv;
+  d.icv32 = L.icv32;
+  d.tcb = L.tcb;
+  d.tcol = L.tcol;
+  d.tncol = L.tncol;
+  d.sm = L.sm;
   d.n = L.n;
   d.nc = L.nc;
   d.nsl = L.nsl;
@@ -421,13 +436,14 @@ struct Builder {
   Launch cur;
   int segs = 0;
   Builder(const Batch& b, bool single_entry) : B(b), single(single_entry) {}
-  void begin(int op, int level, int kind, int aux = 0, int aux2 = 0) {
+  void begin(int op, int level, int kind, int aux = 0, int aux2 = 0, int aux3 = 0) {
     cur = Launch{};
     cur.op = op;
     cur.level = level;
     cur.kind = kind;
     cur.aux = aux;
     cur.aux2 = aux2;
+    cur.aux3 = aux3;
     cur.off = items.size();
     segs = 0;
   }
@@ -537,7 +553,13 @@ double pass0_bytes(const Level& L, int s0, int s1, int R, double vb) {
 // colour-0 rows (their values are written by the first pass before any read),
 // and the last pre-smoothing pass writes the residual of its rows.
 bool colour0_shortcuts(const Batch& B, int e, int l) {
-  return B.smoother == AMG_SMOOTHER_MCSGS && hier(B, e).lev[l].ncol >= 2 && hier(B, e).lev[l].bs == 1;
+  const Level& L = hier(B, e).lev[l];
+  return L.sm == AMG_SMOOTHER_MCSGS && L.ncol >= 2 && L.bs == 1;
+}
+
+// Smoother of level l of the batch's entries (they share the choice).
+int sm_at(const Batch& B, int l) {
+  return B.coarse_smoother >= 0 && l >= B.coarse_from ? B.coarse_smoother : B.smoother;
 }
 // First row after colour 0 (solve order).
 int colour0_rows(const Level& L) { return L.srow_h[L.sptr[1]]; }
@@ -546,7 +568,8 @@ int colour0_rows(const Level& L) { return L.srow_h[L.sptr[1]]; }
 // and (pre-smoothing) each entry's last pass also writes its residual rows.
 void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, int sweeps, bool from_zero) {
   const double vb = B.fp32 ? 4 : 8;
-  if (B.smoother == AMG_SMOOTHER_MCSGS) {
+  const int sm = sm_at(B, l);
+  if (sm == AMG_SMOOTHER_MCSGS) {
     std::vector<std::vector<int>> seq(E.size());
     size_t len = 0;
     for (size_t i = 0; i < E.size(); ++i) {
@@ -595,9 +618,10 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
       }
       b.end();
     }
-  } else if (B.smoother == AMG_SMOOTHER_HYBRID_SGS) {
+  } else if (tile_sweeps(sm)) {
     // per step: t = b - (couplings to other tiles) x, then the in-tile sweeps
-    // (from x = 0: src = b, no residual pass)
+    // (from x = 0: src = b, no residual pass); natural or colour order is in
+    // the steps of the rows
     for (int k = 0; k < sweeps; ++k) {
       const bool zero = from_zero && k == 0;
       if (!zero) {
@@ -605,14 +629,26 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
         for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
         b.end();
       }
-      int W = 0;  // LDS layout of the launch: the most in-tile couplings of a row over its entries
-      for (int e : E) W = std::max(W, hier(B, e).lev[l].hw);
-      b.begin(OP_HSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0, W);
+      // LDS layout of the launch: the most in-tile couplings of a row and the
+      // most steps of a sweep (+ 1) over its entries
+      int W = 0, S = 0, C = 0, NC = 0;
       for (int e : E) {
         const Level& L = hier(B, e).lev[l];
-        // entries read by both sweeps, the source twice, x read and written
-        const double per_tile = (double)L.soff_h[L.nsl] / L.n * L.T * 2.0 * (4.0 + vb) +
-                                L.T * (4.0 + vb + 2.0 * B.R * vb + (zero ? 1.0 : 2.0) * B.R * vb);
+        W = std::max(W, L.hw);
+        S = std::max(S, std::max(L.hdf, L.hdb) + 1);
+        C = std::max(C, L.icmax);
+        NC = std::max(NC, L.tncol);
+      }
+      if (sm == AMG_SMOOTHER_TILE_MCSGS && NC < 64)  // colour by colour, bounds in one wavefront register (at least one coupling slot in LDS)
+        b.begin(OP_TSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0, std::max(C, 1), NC | (std::min(W, 0x7fff) << 16));
+      else  // wavefront steps of the solve order (natural, or colour by colour in each tile)
+        b.begin(OP_HSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0, W | (S << 16), C);
+      for (int e : E) {
+        const Level& L = hier(B, e).lev[l];
+        // in-tile couplings once (value, 16-bit column), per row the coupling
+        // offset, two steps, diagonal, source, x read (not from zero) and written
+        const double per_tile = (double)L.icn / L.n * L.T * (2.0 + vb) +
+                                L.T * (8.0 + vb + B.R * vb + (zero ? 1.0 : 2.0) * B.R * vb);
         b.pieces(B.desc_index(e, l), 0, cdiv(L.n, L.T), 1, per_tile);
       }
       b.end();
@@ -651,7 +687,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool c
     const std::vector<int>& E = below[l];
     b.begin(OP_ZERO, l, l == 0 ? AMG_KIND_OTHER : AMG_KIND_COARSE_LEVELS);
     for (int e : E) {
-      if (B.smoother == AMG_SMOOTHER_HYBRID_SGS && B.pre > 0) continue;  // the first step writes every row
+      if (tile_sweeps(sm_at(B, l)) && B.pre > 0) continue;  // the first step writes every row
       const Level& L = hier(B, e).lev[l];
       const int r0 = B.pre > 0 && colour0_shortcuts(B, e, l) ? colour0_rows(L) : 0;
       b.pieces(B.desc_index(e, l), r0, L.n, ROW_CH, R * vb);
@@ -677,7 +713,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool c
   // up-leg); the coarsest solves of all entries in between, spread over many
   // workgroups.
   auto tail_leg = [&](int op, bool up) {
-    b.begin(op, maxLc, AMG_KIND_COARSE_LEVELS, B.smoother, (B.pre << 8) | B.post);
+    b.begin(op, maxLc, AMG_KIND_COARSE_LEVELS, 0, (B.pre << 8) | B.post);
     for (int e : S) {
       const Hierarchy& H = hier(B, e);
       const int lt = tail_start(B, e), lc = coarsest(B, e);
@@ -687,7 +723,7 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool c
         const Level& L = H.lev[l];
         const double pass = pass_bytes(L, 0, L.nsl, R, vb);
         const int k = up ? B.post : B.pre;
-        const double sweeps = B.smoother == AMG_SMOOTHER_MCSGS
+        const double sweeps = L.sm == AMG_SMOOTHER_MCSGS
                                   ? (double)sgs_passes(L.ncol, k).size() / std::max(1, L.ncol)
                                   : 2.0 * k;
         bytes += up ? sweeps * pass + L.n * (4.0 + 2.0 * R * vb)

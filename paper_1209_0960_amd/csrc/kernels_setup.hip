@@ -1983,14 +1983,16 @@ void colour_single(Hierarchy& H, Level& L, hipStream_t s) {
 constexpr int HS_MAX_T = 1024;
 
 // Wavefront steps of the sequential Gauss-Seidel sweeps inside one tile (one
-// wavefront per tile, rows in natural order, SELL slices of 64 consecutive
-// rows).  Forward: step(i) = 1 + the largest step of the rows j < i of the
-// tile coupled to i (a_ij or a_ji stored), 0 without any; backward the same
-// with j > i.  A row's step exceeds those of all its earlier-swept couplings,
-// so updating the rows step by step reproduces the sequential sweep.  Found by
-// monotone relaxation from 0 (each row pulls from its own entries and pushes
-// to the rows its entries name); it stops at the fixed point, reached after
-// at most nt rounds (a longest path has fewer than nt edges).
+// wavefront per tile, SELL slices of 64 consecutive rows, rows swept in solve
+// order: natural order, or (colour, row) order on levels that sort each
+// tile's rows by colour).  Forward: step(i) = 1 + the largest step of the
+// rows j < i of the tile coupled to i (a_ij or a_ji stored), 0 without any;
+// backward the same with j > i.  A row's step exceeds those of all its
+// earlier-swept couplings, so updating the rows step by step reproduces the
+// sequential sweep.  Found by monotone relaxation from 0 (each row pulls from
+// its own entries and pushes to the rows its entries name); it stops at the
+// fixed point, reached after at most nt rounds (a longest path has fewer than
+// nt edges).
 __global__ __launch_bounds__(64) void k_hybrid_steps(int n, int T, const int* __restrict__ soff,
                                                      const int* __restrict__ scol, unsigned short* __restrict__ sf,
                                                      unsigned short* __restrict__ sb, int* __restrict__ mx) {
@@ -2050,6 +2052,53 @@ __global__ __launch_bounds__(64) void k_hybrid_steps(int n, int T, const int* __
   }
 }
 
+// Rows of each tile of T rows grouped by colour (one wavefront per tile,
+// ballot compaction, colour by colour, ascending row inside a colour): the
+// solve order, the colour of each solve row, and each tile's colour bounds
+// (tcb[t * (C + 1) + c] = first tile-local solve row of colour c).
+__global__ __launch_bounds__(64) void k_tile_colour_order(int n, int T, int C, const int* __restrict__ colour,
+                                                          int* __restrict__ crows, int* __restrict__ tcol,
+                                                          int* __restrict__ tcb) {
+  const int t = blockIdx.x, lo = t * T, hi = min(n, lo + T), nt = hi - lo;
+  const int lane = (int)threadIdx.x;
+  int base = 0;
+  for (int c = 0; c < C; ++c) {
+    if (lane == 0) tcb[(size_t)t * (C + 1) + c] = base;
+    for (int q0 = 0; q0 < nt; q0 += 64) {
+      const int q = q0 + lane;
+      const bool f = q < nt && colour[lo + q] == c;
+      const unsigned long long m = __ballot(f);
+      if (f) {
+        const int p = base + __popcll(m & ((1ull << lane) - 1ull));
+        crows[lo + p] = lo + q;
+        tcol[lo + p] = c;
+      }
+      base += __popcll(m);
+    }
+  }
+  if (lane == 0) tcb[(size_t)t * (C + 1) + C] = base;
+}
+
+void tile_colour_order(Hierarchy& H, Level& L, bool reorder, hipStream_t s) {
+  const int n = L.n, T = L.T, C = L.ncol, ntiles = cdiv(n, T);
+  L.tncol = C;
+  H.free_one(L.crows, s);
+  L.crows = nullptr;
+  if (!reorder) {  // the coarsest level keeps its natural order: colours as they are
+    L.tcol = L.colour;
+    L.colour = nullptr;
+    colour_single(H, L, s);
+    return;
+  }
+  L.tcol = H.alloc<int>((size_t)n, s);
+  L.crows = H.alloc<int>((size_t)n, s);
+  L.tcb = H.alloc<int>((size_t)ntiles * (C + 1), s);
+  hipLaunchKernelGGL(k_tile_colour_order, dim3(ntiles), dim3(64), 0, s, n, T, C, L.colour, L.crows, L.tcol, L.tcb);
+  AMG_HIP(hipGetLastError());
+  L.ncol = 1;
+  L.cptr = {0, n};
+}
+
 void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s) {
   if (T > HS_MAX_T) fail(AMG_ERR_UNSUPPORTED, "the hybrid smoother takes tiles of at most 1024 rows");
   if (L.ncol != 1) fail(AMG_ERR_INVALID_ARG, "hybrid smoother level must have one colour");
@@ -2065,6 +2114,64 @@ void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s) {
   int bad = 0;
   read_ints(s, {{&L.hdf, mx.as<int>()}, {&L.hdb, mx.as<int>() + 1}, {&bad, mx.as<int>() + 2}, {&L.hw, mx.as<int>() + 3}});
   if (bad) fail(AMG_ERR_HIP, "hybrid smoother step relaxation did not converge");
+  if (std::max(L.hdf, L.hdb) >= 0xffff || L.hw >= 0xffff) fail(AMG_ERR_UNSUPPORTED, "hybrid smoother tile too deep");
+  // rows with many in-tile couplings are summed by groups of lanes, except on
+  // levels of the tile-ordered multicolour smoother (one lane per row:
+  // the register form of its sweep keeps each row's couplings in one lane)
+  L.hg = L.hw > 8 && !L.tcb ? HS_G : 1;
+}
+
+// In-tile couplings of row i (one thread per row; tiles of T rows): count,
+// then (icp set) columns relative to the tile and values in SELL entry order.
+__global__ void k_ic_rows(int n, int T, const int* __restrict__ soff, const int* __restrict__ scol,
+                          const double* __restrict__ sval, const int* __restrict__ icp, int* __restrict__ cnt,
+                          unsigned short* __restrict__ icc, double* __restrict__ icv, float* __restrict__ icv32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int lo = i - i % T, hi = min(n, lo + T);
+  const int t = i & 63, base = soff[i >> 6], w = (soff[(i >> 6) + 1] - base) >> 6;
+  int c = icp ? icp[i] : 0;
+  for (int e = 0; e < w; ++e) {
+    const int j = scol[base + 64 * e + t];
+    if (j < lo || j >= hi || j == i) continue;
+    if (icp) {
+      icc[c] = (unsigned short)(j - lo);
+      if (icv) icv[c] = sval[base + 64 * e + t];
+      if (icv32) icv32[c] = (float)sval[base + 64 * e + t];
+    }
+    ++c;
+  }
+  if (!icp) cnt[i] = c;
+}
+
+__global__ void k_ic_tile_max(int n, int T, int ntiles, const int* __restrict__ icp, int* __restrict__ mx) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  atomicMax(mx, icp[min(n, (t + 1) * T)] - icp[t * T]);
+}
+
+void tile_couplings(Hierarchy& H, Level& L, bool f32, hipStream_t s) {
+  const int n = L.n, T = L.T, g = cdiv(n, 256);
+  DBuf cnt((size_t)n * sizeof(int), s);
+  hipLaunchKernelGGL(k_ic_rows, dim3(g), dim3(256), 0, s, n, T, L.soff, L.scol, L.sval, nullptr, cnt.as<int>(),
+                     nullptr, nullptr, nullptr);
+  L.icp = H.alloc<int>((size_t)n + 1, s);
+  exclusive_scan(cnt.as<int>(), L.icp, n, s);
+  const int tot = read1(L.icp + n, s);
+  L.icn = tot;
+  L.icc = H.alloc<unsigned short>((size_t)std::max(tot, 1), s);
+  if (f32)
+    L.icv32 = H.alloc<float>((size_t)std::max(tot, 1), s);
+  else
+    L.icv = H.alloc<double>((size_t)std::max(tot, 1), s);
+  hipLaunchKernelGGL(k_ic_rows, dim3(g), dim3(256), 0, s, n, T, L.soff, L.scol, L.sval, L.icp, nullptr, L.icc,
+                     L.icv, L.icv32);
+  DBuf mx(sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
+  const int ntiles = cdiv(n, T);
+  hipLaunchKernelGGL(k_ic_tile_max, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, n, T, ntiles, L.icp, mx.as<int>());
+  AMG_HIP(hipGetLastError());
+  L.icmax = read1(mx.as<int>(), s);
 }
 
 void cast_f32(const double* in, float* out, size_t n, hipStream_t s) {

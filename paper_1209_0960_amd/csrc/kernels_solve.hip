@@ -98,6 +98,7 @@ struct Mat<double> {
   __device__ static const double* dg(const BDesc& d) { return d.dg64; }
   __device__ static const double* l1(const BDesc& d) { return d.l164; }
   __device__ static const double* dinv(const BDesc& d) { return d.dinv64; }
+  __device__ static const double* icv(const BDesc& d) { return d.icv64; }
 };
 template <>
 struct Mat<float> {
@@ -105,6 +106,7 @@ struct Mat<float> {
   __device__ static const float* dg(const BDesc& d) { return d.dg32; }
   __device__ static const float* l1(const BDesc& d) { return d.l132; }
   __device__ static const float* dinv(const BDesc& d) { return d.dinv32; }
+  __device__ static const float* icv(const BDesc& d) { return d.icv32; }
 };
 
 // Work item of this block.  Table launches read it from tab[blockIdx.x] and
@@ -420,37 +422,77 @@ __global__ __launch_bounds__(NT) void kb_resid_off(AMG_KARGS) {
 // lanes of one wavefront: x_i = (src_i - sum over in-tile j != i of a_ij x_j)
 // / a_ii, rows of one wavefront step together (their couplings lie in earlier
 // steps of the sweep, whose values are final, or in later ones, not yet
-// touched), steps separated by sync().  xt[(i - lo) * R + k] is the tile's
-// iterate (LDS copy or the level's vector itself).  Every caller runs the
-// same number of steps, so sync() may be a workgroup barrier.
+// touched), steps separated by sync().  Rows of backward step 0 have no
+// coupling after them in the sweep order, so the backward sweep would
+// recompute their forward values bit for bit: it starts at step 1.
+// xt[(i - lo) * R + k] is the tile's iterate (LDS copy or the level's vector
+// itself).  Every caller runs the same number of steps, so sync() may be a
+// workgroup barrier.
+//
+// Each row is summed by a group of d.hg lanes (1 or HS_G): lane `sub` of the
+// group adds the row's in-tile couplings sub, sub + hg, ... (SELL entry
+// order) from zero, then group_sum adds the partial sums of lanes at distance
+// 1, then 2.  Every kernel that sweeps tiles uses this order, so the launch
+// path, its LDS-staged form and the one-workgroup tail give the same bits.
+static_assert(HS_G == 4, "group_sum adds lanes at distance 1 and 2");
+
+// Value of the lane at quad position given by the DPP quad permutation
+// CTRL (0xB1: lanes 1,0,3,2 of each quad, i.e. lane ^ 1; 0x4E: 2,3,0,1,
+// lane ^ 2); every lane of the quad must be active.
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, false);
+  p.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, p);
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void group_sum(V (&acc)[R], int G) {
+  if (G == 1) return;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    acc[k] = acc[k] + quad_swap<0xB1>(acc[k]);
+    acc[k] = acc[k] + quad_swap<0x4E>(acc[k]);
+  }
+}
+
 template <typename V, int R, typename Sync>
 __device__ inline void hybrid_tile(const BDesc& d, int lo, int hi, const V* __restrict__ src, V* xt, int lane,
                                    Sync sync) {
-  const V* sv = Mat<V>::sval(d);
+  const V* icv = Mat<V>::icv(d);
   const V* dg = Mat<V>::dg(d);
+  const int G = d.hg, sub = lane % G, ng = WAVE / G;
   for (int dir = 0; dir < 2; ++dir) {
     const unsigned short* st = dir == 0 ? d.hsf : d.hsb;
     const int depth = dir == 0 ? d.hdf : d.hdb;
-    for (int step = 0; step <= depth; ++step) {
-      for (int i = lo + lane; i < hi; i += WAVE) {
-        if (st[i] != step) continue;
-        const int t = i & 63, base = d.soff[i >> 6], w = (d.soff[(i >> 6) + 1] - base) >> 6;
+    for (int step = dir; step <= depth; ++step) {
+      for (int i0 = lo; i0 < hi; i0 += ng) {
+        const int i = i0 + lane / G;
+        const bool on = i < hi && st[i] == step;  // the same in every lane of a group
         V acc[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = 0;
-        for (int e = 0; e < w; ++e) {
-          const int j = d.scol[base + 64 * e + t];
-          if (j >= lo && j < hi && j != i) {
-            const V a = sv[base + 64 * e + t];
+        if (on) {
+          for (int e = d.icp[i] + sub; e < d.icp[i + 1]; e += G) {
+            const V a = icv[e];
+            const int j = d.icc[e];
 #pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] = madd(a, xt[(size_t)(j - lo) * R + k], acc[k]);
+            for (int k = 0; k < R; ++k) acc[k] = madd(a, xt[(size_t)j * R + k], acc[k]);
           }
         }
-        V sr[R];
-        ldv<V, R>(src + (size_t)i * R, sr);
-        const V di = dg[i];
+        group_sum<V, R>(acc, G);
+        if (on && sub == 0) {
+          V sr[R];
+          ldv<V, R>(src + (size_t)i * R, sr);
+          const V di = dg[i];
 #pragma unroll
-        for (int k = 0; k < R; ++k) xt[(size_t)(i - lo) * R + k] = (sr[k] - acc[k]) / di;
+          for (int k = 0; k < R; ++k) xt[(size_t)(i - lo) * R + k] = (sr[k] - acc[k]) / di;
+        }
       }
       sync();
     }
@@ -477,57 +519,127 @@ __global__ __launch_bounds__(WAVE) void kb_hsgs(AMG_KARGS, int from_b) {
   AMG_BODY((kb_hsgs_body<V, R>), from_b)
 }
 
-// LDS bytes of the staged sweep of a tile of T rows with at most W in-tile
-// couplings per row.
-template <typename V>
-__host__ __device__ inline size_t hsgs_lds_bytes(int T, int W, int R) {
-  return (size_t)T * (2 * R + 1 + W) * sizeof(V) + (size_t)T * (W + 3) * sizeof(unsigned short);
+// In-tile sum of one row from LDS couplings ev/ec over [e0, e1): lane `sub`
+// of a group of G adds entries e0 + sub, e0 + sub + G, ... in that order (as
+// hybrid_tile does), eight at a time with their loads and gathers in flight
+// together.
+template <typename V, int R>
+__device__ __forceinline__ void lds_row_sum(const V* __restrict__ ev, const unsigned short* __restrict__ ec,
+                                            const V* xt, int e0, int e1, int sub, int G, V (&acc)[R]) {
+  for (int eb = e0 + sub; eb < e1; eb += 8 * G) {
+    V a[8], xv[8][R];
+    int j[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool v = eb + u * G < e1;
+      a[u] = v ? ev[eb + u * G] : (V)0;
+      j[u] = v ? (int)ec[eb + u * G] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) xv[u][r] = xt[(size_t)j[u] * R + r];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (eb + u * G < e1)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = madd(a[u], xv[u][r], acc[r]);
+  }
 }
 
-// The same sweeps with everything a step reads staged in LDS first: the
-// tile's iterate and source, its diagonal, the wavefront steps, and each row's
-// in-tile couplings (local column, value; SELL entry order, as in
-// hybrid_tile, so the sums and the results are the same).  A step then reads
-// LDS only.
+// LDS layout of the staged sweep of a tile of T rows, at most C in-tile
+// couplings per tile and at most S wavefront steps per sweep: iterate,
+// source, diagonal (V); step bounds, coupling offsets (int); steps and
+// rows by step (16 bit); then, 8-byte aligned, the couplings' values (V) and
+// local columns (16 bit).
+__host__ __device__ inline size_t hsgs_fixed_bytes(int T, int R, int S, size_t vb) {
+  const size_t b = (size_t)T * (2 * R + 1) * vb + (size_t)(2 * (S + 1) + T + 1) * sizeof(int) +
+                   (size_t)4 * T * sizeof(unsigned short);
+  return (b + 7) & ~(size_t)7;
+}
+template <typename V>
+__host__ __device__ inline size_t hsgs_lds_bytes(int T, int C, int R, int S) {
+  return hsgs_fixed_bytes(T, R, S, sizeof(V)) + (size_t)C * (sizeof(V) + sizeof(unsigned short));
+}
+
+// Exclusive prefix sum of c[0..m) in place by one wavefront (returns the total).
+__device__ inline int wave_exclusive_scan(int* c, int m, int lane) {
+  int carry = 0;
+  for (int b0 = 0; b0 < m; b0 += WAVE) {
+    const int s = b0 + lane;
+    const int v = s < m ? c[s] : 0;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int y = __shfl_up(inc, o, WAVE);
+      if (lane >= o) inc += y;
+    }
+    if (s < m) c[s] = carry + inc - v;
+    carry += __shfl(inc, WAVE - 1, WAVE);
+  }
+  return carry;
+}
+
+// The same sweeps with everything a step reads staged in LDS first, by
+// contiguous copies: the tile's iterate and source, its diagonal, its rows'
+// in-tile couplings (the level's compact lists, SELL entry order, as in
+// hybrid_tile) and, for each sweep, the tile's rows listed step by step
+// (counting sort on the step), so that a step's rows sit side by side on the
+// lane groups.  W: the most in-tile couplings of a row, C: of a tile, S: the
+// most steps of a sweep + 1 (over the launch's entries).
 template <typename V, int R>
-__device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d, int from_b, int W) {
+__device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d, int from_b, int W, int S, int C) {
   extern __shared__ double hs_lds[];
   const int T = d.T;
   V* xt = reinterpret_cast<V*>(hs_lds);
   V* sr = xt + (size_t)T * R;
   V* dl = sr + (size_t)T * R;
-  V* ev = dl + T;
-  unsigned short* ec = reinterpret_cast<unsigned short*>(ev + (size_t)T * W);
-  unsigned short* cn = ec + (size_t)T * W;
-  unsigned short* stf = cn + T;
+  int* so = reinterpret_cast<int*>(dl + T);  // [2][S + 1] step bounds
+  int* cp = so + 2 * (S + 1);                // [T + 1] coupling offsets
+  unsigned short* stf = reinterpret_cast<unsigned short*>(cp + T + 1);
   unsigned short* stb = stf + T;
+  unsigned short* lst = stb + T;  // [2][T] rows by step
+  V* ev = reinterpret_cast<V*>(reinterpret_cast<char*>(hs_lds) + hsgs_fixed_bytes(T, R, S, sizeof(V)));
+  unsigned short* ec = reinterpret_cast<unsigned short*>(ev + C);
   const int lo = it.lo * T, hi = min(d.n, lo + T), nt = hi - lo;
   const int lane = (int)threadIdx.x;
   V* x = static_cast<V*>(d.x);
   const V* src = static_cast<const V*>(from_b ? d.b : d.t);
-  const V* sv = Mat<V>::sval(d);
+  const V* icv = Mat<V>::icv(d);
   const V* dg = Mat<V>::dg(d);
-  for (int q = lane; q < nt; q += WAVE) {
-    const int i = lo + q, t = i & 63, base = d.soff[i >> 6], w = (d.soff[(i >> 6) + 1] - base) >> 6;
-    int c = 0;
-    for (int e = 0; e < w; ++e) {
-      const int j = d.scol[base + 64 * e + t];
-      if (j >= lo && j < hi && j != i) {
-        ec[(size_t)q * W + c] = (unsigned short)(j - lo);
-        ev[(size_t)q * W + c] = sv[base + 64 * e + t];
-        ++c;
+  const int c0 = d.icp[lo], m = d.icp[hi] - c0;
+  for (int q = lane; q < 2 * (S + 1); q += WAVE) so[q] = 0;
+  // couplings: four loads of each kind in flight per lane
+  for (int k0 = 0; k0 < m; k0 += 4 * WAVE) {
+    V a[4];
+    unsigned short j[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * WAVE + lane;
+      a[u] = k < m ? icv[c0 + k] : (V)0;
+      j[u] = k < m ? d.icc[c0 + k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * WAVE + lane;
+      if (k < m) {
+        ev[k] = a[u];
+        ec[k] = j[u];
       }
     }
-    cn[q] = (unsigned short)c;
+  }
+  for (int q = lane; q <= nt; q += WAVE) cp[q] = d.icp[lo + q] - c0;
+  for (int q = lane; q < nt; q += WAVE) {
+    const int i = lo + q;
     stf[q] = d.hsf[i];
     stb[q] = d.hsb[i];
     dl[q] = dg[i];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      sr[(size_t)q * R + k] = src[(size_t)i * R + k];
-      xt[(size_t)q * R + k] = from_b ? (V)0 : x[(size_t)i * R + k];
-    }
   }
+  for (int q = lane; q < nt * R; q += WAVE) {
+    sr[q] = src[(size_t)lo * R + q];
+    xt[q] = from_b ? (V)0 : x[(size_t)lo * R + q];
+  }
+  __syncthreads();
   // this tile's deepest steps (the sweeps stop there)
   int df = 0, db = 0;
   for (int q = lane; q < nt; q += WAVE) {
@@ -539,8 +651,7 @@ __device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d,
     df = max(df, __shfl_xor(df, o, WAVE));
     db = max(db, __shfl_xor(db, o, WAVE));
   }
-  __syncthreads();
-  if (T <= 2 * WAVE && W <= 8) {
+  if (T <= 2 * WAVE && W <= 8 && d.hg == 1) {
     // Small tiles with few couplings (the finest levels): each lane keeps its
     // two rows' couplings, steps, source and diagonal in registers, so a step
     // is one round of LDS gathers; same entry order and arithmetic.
@@ -551,7 +662,8 @@ __device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d,
     for (int h = 0; h < 2; ++h) {
       const int q = lane + h * WAVE;
       const bool on = q < nt;
-      cq[h] = on ? (int)cn[q] : 0;
+      const int e0 = on ? cp[q] : 0;
+      cq[h] = on ? cp[q + 1] - e0 : 0;
       sfq[h] = on ? (int)stf[q] : -1;
       sbq[h] = on ? (int)stb[q] : -1;
       dq[h] = on ? dl[q] : (V)1;
@@ -560,13 +672,13 @@ __device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d,
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const bool e = u < cq[h];
-        aq[h][u] = e ? ev[(size_t)q * W + u] : (V)0;
-        jq[h][u] = e ? (int)ec[(size_t)q * W + u] : 0;
+        aq[h][u] = e ? ev[e0 + u] : (V)0;
+        jq[h][u] = e ? (int)ec[e0 + u] : 0;
       }
     }
     for (int dir = 0; dir < 2; ++dir) {
       const int depth = dir == 0 ? df : db;
-      for (int step = 0; step <= depth; ++step) {
+      for (int step = dir; step <= depth; ++step) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           if ((dir == 0 ? sfq[h] : sbq[h]) != step) continue;
@@ -585,56 +697,325 @@ __device__ __forceinline__ void kb_hsgs_lds_body(const Item& it, const BDesc& d,
         __syncthreads();
       }
     }
-  } else
-  for (int dir = 0; dir < 2; ++dir) {
-    const unsigned short* st = dir == 0 ? stf : stb;
-    const int depth = dir == 0 ? df : db;
-    for (int step = 0; step <= depth; ++step) {
-      for (int q = lane; q < nt; q += WAVE) {
-        if (st[q] != step) continue;
-        V acc[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) acc[k] = 0;
-        const int c = cn[q];
-        const V* evq = ev + (size_t)q * W;
-        const unsigned short* ecq = ec + (size_t)q * W;
-        int e = 0;
-        // chunks of 8 couplings: their loads, then their gathers, in flight
-        // together; the sum keeps the entry order
-        for (; e + 8 <= c; e += 8) {
-          V a[8], xv[8][R];
-          int j[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            a[u] = evq[e + u];
-            j[u] = ecq[e + u];
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int k = 0; k < R; ++k) xv[u][k] = xt[(size_t)j[u] * R + k];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] = madd(a[u], xv[u][k], acc[k]);
-        }
-        for (; e < c; ++e) {
-          const V a = evq[e];
-          const int j = ecq[e];
-#pragma unroll
-          for (int k = 0; k < R; ++k) acc[k] = madd(a, xt[(size_t)j * R + k], acc[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < R; ++k) xt[(size_t)q * R + k] = (sr[(size_t)q * R + k] - acc[k]) / dl[q];
-      }
+  } else {
+    // rows by step: counts, bounds, placement (the order inside a step is free)
+    for (int dir = 0; dir < 2; ++dir) {
+      const unsigned short* st = dir == 0 ? stf : stb;
+      int* c = so + dir * (S + 1);
+      for (int q = lane; q < nt; q += WAVE) atomicAdd(&c[st[q]], 1);
       __syncthreads();
+      wave_exclusive_scan(c, S + 1, lane);
+      __syncthreads();
+      for (int q = lane; q < nt; q += WAVE) lst[dir * T + atomicAdd(&c[st[q]], 1)] = (unsigned short)q;
+    }
+    __syncthreads();  // c[s] is now the end of step s's rows
+    const int G = d.hg, sub = lane % G, ng = WAVE / G;
+    for (int dir = 0; dir < 2; ++dir) {
+      const int depth = dir == 0 ? df : db;
+      const int* c = so + dir * (S + 1);
+      const unsigned short* ls = lst + dir * T;
+      for (int step = dir; step <= depth; ++step) {
+        const int r1 = c[step];
+        for (int p0 = step == 0 ? 0 : c[step - 1]; p0 < r1; p0 += ng) {
+          const int p = p0 + lane / G;
+          const bool on = p < r1;
+          const int q = on ? (int)ls[p] : 0;
+          V acc[R];
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] = 0;
+          if (on) lds_row_sum<V, R>(ev, ec, xt, cp[q], cp[q + 1], sub, G, acc);
+          group_sum<V, R>(acc, G);
+          if (on && sub == 0)
+#pragma unroll
+            for (int k = 0; k < R; ++k) xt[(size_t)q * R + k] = (sr[(size_t)q * R + k] - acc[k]) / dl[q];
+        }
+        __syncthreads();
+      }
     }
   }
   for (int q = lane; q < nt * R; q += WAVE) x[(size_t)lo * R + q] = xt[q];
 }
 template <typename V, int R, bool DIRECT>
-__global__ __launch_bounds__(WAVE) void kb_hsgs_lds(AMG_KARGS, int from_b, int W) {
-  AMG_BODY((kb_hsgs_lds_body<V, R>), from_b, W)
+__global__ __launch_bounds__(WAVE) void kb_hsgs_lds(AMG_KARGS, int from_b, int W, int S, int C) {
+  AMG_BODY((kb_hsgs_lds_body<V, R>), from_b, W, S, C)
+}
+
+// LDS bytes of the colour-ordered tile sweep: iterate, source, diagonal (V);
+// coupling offsets and colour bounds (int); then, 8-byte aligned, the
+// couplings' values (V) and local columns (16 bit).
+__host__ __device__ inline size_t tsgs_fixed_bytes(int T, int R, int NC, size_t vb) {
+  const size_t b = (size_t)T * (2 * R + 1) * vb + (size_t)(T + 1 + NC + 1) * sizeof(int);
+  return (b + 7) & ~(size_t)7;
+}
+template <typename V>
+__host__ __device__ inline size_t tsgs_lds_bytes(int T, int C, int R, int NC) {
+  return tsgs_fixed_bytes(T, R, NC, sizeof(V)) + (size_t)C * (sizeof(V) + sizeof(unsigned short));
+}
+
+// The tile-ordered multicolour smoother on one tile (one wavefront, it.lo =
+// tile): the level's solve order takes each tile's rows colour by colour, so
+// the rows of a colour are one contiguous range and the sweeps go colour by
+// colour, forward then backward (the backward sweep starts below the tile's
+// last colour, whose rows it would recompute bit for bit).  Rows of one
+// colour are not coupled, so this is the sequential sweep in (colour, row)
+// order.  Everything is staged in LDS by contiguous copies; rows are summed
+// by groups of d.hg lanes as in hybrid_tile (same couplings, same order), so
+// the one-workgroup tail, which sweeps such a level by its wavefront steps,
+// gives the same bits.  C: the most in-tile couplings of a tile, NC: the
+// most colours (over the launch's entries, below WAVE).
+template <typename V, int R>
+__device__ __forceinline__ void kb_tsgs_body(const Item& it, const BDesc& d, int from_b, int C, int NC) {
+  extern __shared__ double hs_lds[];
+  const int T = d.T;
+  V* xt = reinterpret_cast<V*>(hs_lds);
+  V* sr = xt + (size_t)T * R;
+  V* dl = sr + (size_t)T * R;
+  int* cp = reinterpret_cast<int*>(dl + T);  // [T + 1] coupling offsets
+  int* cb = cp + T + 1;                      // [ncol + 1] colour bounds
+  V* ev = reinterpret_cast<V*>(reinterpret_cast<char*>(hs_lds) + tsgs_fixed_bytes(T, R, NC, sizeof(V)));
+  unsigned short* ec = reinterpret_cast<unsigned short*>(ev + C);
+  const int lo = it.lo * T, hi = min(d.n, lo + T), nt = hi - lo;
+  const int lane = (int)threadIdx.x, ncol = d.tncol;
+  V* x = static_cast<V*>(d.x);
+  const V* src = static_cast<const V*>(from_b ? d.b : d.t);
+  const V* icv = Mat<V>::icv(d);
+  const V* dg = Mat<V>::dg(d);
+  const int c0 = d.icp[lo], m = d.icp[hi] - c0;
+  // row data two rows per lane at a time, then couplings sixteen per lane at
+  // a time: each batch's loads in flight together, then its LDS stores
+  for (int q0 = 0; q0 <= nt; q0 += 2 * WAVE) {
+    int cv[2];
+    V dv[2], sv[2][R], xv[2][R];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = q0 + h * WAVE + lane;
+      const int qr = min(q, nt - 1);  // clamped: loads without branches, stores guarded
+      cv[h] = d.icp[lo + min(q, nt)];
+      dv[h] = dg[lo + qr];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sv[h][r] = src[(size_t)(lo + qr) * R + r];
+        xv[h][r] = from_b ? (V)0 : x[(size_t)(lo + qr) * R + r];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = q0 + h * WAVE + lane;
+      if (q <= nt) cp[q] = cv[h] - c0;
+      if (q < nt) {
+        dl[q] = dv[h];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          sr[(size_t)q * R + r] = sv[h][r];
+          xt[(size_t)q * R + r] = xv[h][r];
+        }
+      }
+    }
+  }
+  for (int q = lane; q <= ncol; q += WAVE) cb[q] = d.tcb[(size_t)it.lo * (ncol + 1) + q];
+  if (m == 0 && lane == 0) {  // no couplings: the clamped reads below find a valid slot
+    ev[0] = (V)0;
+    ec[0] = 0;
+  }
+  for (int k0 = 0; k0 < m; k0 += 16 * WAVE) {
+    V a[16];
+    unsigned short j[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = c0 + min(k0 + u * WAVE + lane, m - 1);
+      a[u] = icv[k];
+      j[u] = d.icc[k];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = k0 + u * WAVE + lane;
+      if (k < m) {
+        ev[k] = a[u];
+        ec[k] = j[u];
+      }
+    }
+  }
+  __syncthreads();
+  // Work units: the rows of a colour in groups of ng (one row per lane
+  // group), forward colours 0..last then backward last-1..0, the tile's last
+  // colour with rows being `last`.  The read-only data of the next unit (row
+  // bounds, source, diagonal, the first eight couplings of each lane) is
+  // loaded while the current unit sums, so a unit waits on its gathers of
+  // the iterate alone; units of one colour need no barrier between them.
+  const int G = d.hg, sub = lane % G, ng = WAVE / G;
+  // colour bounds in one register (lane c holds bound c; ncol < WAVE): the
+  // loop control reads them without waiting on LDS
+  const int cbv = lane <= ncol ? cb[lane] : 0;
+  auto cbu = [&](int c) { return __builtin_amdgcn_readlane(cbv, c); };
+  int last = ncol - 1;
+  while (last > 0 && cbu(last) == cbu(last + 1)) --last;
+  const int K = 2 * last + 1;
+  auto col = [&](int k) { return k <= last ? k : 2 * last - k; };
+  auto first_unit = [&](int k, int& p0) {  // first colour at or after k with rows
+    while (k < K && cbu(col(k)) == cbu(col(k) + 1)) ++k;
+    if (k < K) p0 = cbu(col(k));
+    return k;
+  };
+  struct Unit {
+    int q, e0, e1;
+    bool on;
+    V s[R], dv, a[8];
+    int j[8];
+  };
+  auto load_unit = [&](int c, int p0, Unit& u) {
+    const int r1 = cbu(c + 1);
+    u.q = p0 + lane / G;
+    u.on = u.q < r1;
+    const int qq = u.on ? u.q : r1 - 1;  // a row of the colour: every read stays in range
+    u.e0 = cp[qq];
+    u.e1 = cp[qq + 1];
+    u.dv = dl[qq];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u.s[r] = sr[(size_t)qq * R + r];
+    const int el = u.e1 > 0 ? u.e1 - 1 : 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = min(u.e0 + sub + t * G, el);
+      u.a[t] = ev[e];
+      u.j[t] = ec[e];
+    }
+  };
+  int p0 = 0;
+  int k = first_unit(0, p0);
+  Unit cur, nxt;
+  if (k < K) load_unit(col(k), p0, cur);
+  while (k < K) {
+    const int c = col(k);
+    int np0 = p0 + ng, nk = k;
+    if (np0 >= cbu(c + 1)) nk = first_unit(k + 1, np0);
+    if (nk < K) load_unit(col(nk), np0, nxt);
+    V acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0;
+    {
+      V xv[8][R];
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int r = 0; r < R; ++r) xv[t][r] = xt[(size_t)cur.j[t] * R + r];
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (cur.on && cur.e0 + sub + t * G < cur.e1)
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = madd(cur.a[t], xv[t][r], acc[r]);
+      // rows with more than 8 G couplings go on in the same order
+      if (cur.on && cur.e1 - cur.e0 > 8 * G) lds_row_sum<V, R>(ev, ec, xt, cur.e0 + 8 * G, cur.e1, sub, G, acc);
+    }
+    group_sum<V, R>(acc, G);
+    if (cur.on && sub == 0)
+#pragma unroll
+      for (int r = 0; r < R; ++r) xt[(size_t)cur.q * R + r] = (cur.s[r] - acc[r]) / cur.dv;
+    if (nk != k) __syncthreads();
+    cur = nxt;
+    k = nk;
+    p0 = np0;
+  }
+  for (int q = lane; q < nt * R; q += WAVE) x[(size_t)lo * R + q] = xt[q];
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(WAVE) void kb_tsgs(AMG_KARGS, int from_b, int C, int NC) {
+  AMG_BODY((kb_tsgs_body<V, R>), from_b, C, NC)
+}
+
+// Register form of the colour-ordered tile sweep (one right-hand side,
+// tiles of at most 256 rows, at most WM in-tile couplings per row): one
+// thread per row for the whole sweep, keeping the row's couplings, source,
+// diagonal and colour in registers, so a colour step waits on the gathers of
+// the iterate (in LDS, sixteen in flight) alone.  Each row sums its
+// couplings one after another in SELL entry order (the level's lanes per
+// row is 1), as hybrid_tile does.  The couplings pass through LDS once, by
+// contiguous copies, on their way to the registers.
+template <typename V, int WM>
+__device__ __forceinline__ void kb_tsgs_reg_body(const Item& it, const BDesc& d, int from_b, int C) {
+  extern __shared__ double hs_lds[];
+  const int T = d.T, nthr = (int)blockDim.x;
+  V* xt = reinterpret_cast<V*>(hs_lds);
+  V* ev = xt + T;
+  unsigned short* ec = reinterpret_cast<unsigned short*>(ev + C);
+  const int lo = it.lo * T, hi = min(d.n, lo + T), nt = hi - lo;
+  const int q = (int)threadIdx.x, lane = __lane_id();
+  V* x = static_cast<V*>(d.x);
+  const V* src = static_cast<const V*>(from_b ? d.b : d.t);
+  const V* icv = Mat<V>::icv(d);
+  const V* dg = Mat<V>::dg(d);
+  const int c0 = d.icp[lo], m = d.icp[hi] - c0;
+  const bool on = q < nt;
+  const int qr = min(q, nt - 1);  // clamped: loads without branches
+  const int a0 = d.icp[lo + qr], a1 = d.icp[lo + qr + 1];
+  const int e0 = a0 - c0, cnt = on ? a1 - a0 : 0;
+  const int cl = on ? d.tcol[lo + qr] : -1;
+  const V sv = src[lo + qr], dv = dg[lo + qr];
+  const V x0 = from_b ? (V)0 : x[lo + qr];
+  // the tile's last colour with rows (bounds of colour `lane`, every wavefront alike)
+  const int ncol = d.tncol;
+  const int* cbt = d.tcb + (size_t)it.lo * (ncol + 1);
+  const bool ne = lane < ncol && cbt[lane] < cbt[lane + 1];
+  const unsigned long long nem = __builtin_amdgcn_ballot_w64(ne);
+  const int last = nem ? 63 - __builtin_clzll(nem) : 0;
+  if (on) xt[q] = x0;
+  if (m == 0 && q == 0) {
+    ev[0] = (V)0;
+    ec[0] = 0;
+  }
+  for (int k0 = 0; k0 < m; k0 += 16 * nthr) {
+    V a[16];
+    unsigned short j[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = c0 + min(k0 + u * nthr + q, m - 1);
+      a[u] = icv[k];
+      j[u] = d.icc[k];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = k0 + u * nthr + q;
+      if (k < m) {
+        ev[k] = a[u];
+        ec[k] = j[u];
+      }
+    }
+  }
+  __syncthreads();
+  V a[WM];
+  int j[WM];
+#pragma unroll
+  for (int u = 0; u < WM; ++u) {
+    const int e = u < cnt ? e0 + u : 0;
+    a[u] = ev[e];
+    j[u] = ec[e];
+  }
+  for (int k = 0; k < 2 * last + 1; ++k) {
+    const int c = k <= last ? k : 2 * last - k;
+    const bool act = cl == c;
+    V acc = 0;
+    constexpr int CH = WM % 16 == 0 ? 16 : 8;  // gathers in flight per round
+#pragma unroll
+    for (int u0 = 0; u0 < WM; u0 += CH) {
+      if (!__builtin_amdgcn_ballot_w64(act && cnt > u0)) break;  // no row of this wavefront and colour has more
+      V xv[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) xv[u] = xt[j[u0 + u]];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (u0 + u < cnt) acc = madd(a[u0 + u], xv[u], acc);
+    }
+    if (act) xt[q] = (sv - acc) / dv;
+    __syncthreads();
+  }
+  if (on) x[lo + q] = xt[q];
+}
+template <typename V, int WM, bool DIRECT>
+__global__ __launch_bounds__(256) void kb_tsgs_reg(AMG_KARGS, int from_b, int C) {
+  AMG_BODY((kb_tsgs_reg_body<V, WM>), from_b, C)
+}
+template <typename V>
+__host__ __device__ inline size_t tsgs_reg_lds_bytes(int T, int C) {
+  return (size_t)T * sizeof(V) + (size_t)C * (sizeof(V) + sizeof(unsigned short));
 }
 
 template <typename V, int R>
@@ -774,12 +1155,13 @@ __device__ inline void tail_slices(const BDesc& d, int s0, int s1, int op) {
   __syncthreads();
 }
 
-// The colour passes of the separate launches, in the same order.
+// The colour passes of the separate launches, in the same order (d.sm: the
+// level's smoother).
 template <typename V, int R>
-__device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps, bool from_zero) {
+__device__ inline void tail_smooth(const BDesc& d, int sweeps, bool from_zero) {
   int prev = -1;  // a pass on the colour just updated would repeat its values
   for (int k = 0; k < sweeps; ++k) {
-    if (smoother == AMG_SMOOTHER_MCSGS) {
+    if (d.sm == AMG_SMOOTHER_MCSGS) {
       for (int dir = 0; dir < 2; ++dir)
         for (int q = 0; q < d.ncol; ++q) {
           const int c = dir == 0 ? q : d.ncol - 1 - q;
@@ -787,7 +1169,7 @@ __device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps, boo
           tail_slices<V, R>(d, d.sptr[c], d.sptr[c + 1], from_zero && prev < 0 ? 2 : 1);
           prev = c;
         }
-    } else if (smoother == AMG_SMOOTHER_HYBRID_SGS) {
+    } else if (d.sm == AMG_SMOOTHER_HYBRID_SGS || d.sm == AMG_SMOOTHER_TILE_MCSGS) {
       // wavefronts take tiles; the sweeps work on the level's vector in
       // place (tiles only read their own rows), steps separated by barriers
       const bool zero = from_zero && k == 0;
@@ -815,7 +1197,7 @@ __device__ inline void tail_smooth(const BDesc& d, int smoother, int sweeps, boo
 // it.d: descriptor of level lt (level l at D[it.d + l - lt]); it.lo = lt, it.hi = lc.
 template <typename V, int R>
 __global__ __launch_bounds__(TAIL_NT) void kb_tail(const Item* __restrict__ tab, const BDesc* __restrict__ D,
-                                                    const Item base, int smoother, int pre, int post, int direct,
+                                                    const Item base, int pre, int post, int direct,
                                                     int up) {
   const Item it = direct ? base : tab[blockIdx.x];
   const BDesc* dl = D + it.d;
@@ -827,7 +1209,7 @@ __global__ __launch_bounds__(TAIL_NT) void kb_tail(const Item* __restrict__ tab,
       const BDesc& d = dl[l - lt];
       kb_zero_body<V, R>(Item{0, 0, d.n, 0}, d);
       __syncthreads();
-      tail_smooth<V, R>(d, smoother, pre, true);
+      tail_smooth<V, R>(d, pre, true);
       tail_slices<V, R>(d, 0, d.nsl, 0);
       for (int lo = 0; lo < d.nc; lo += nt) kb_restrict_body<V, R>(Item{0, lo, min(d.nc, lo + nt), 0}, d);
       __syncthreads();
@@ -837,7 +1219,7 @@ __global__ __launch_bounds__(TAIL_NT) void kb_tail(const Item* __restrict__ tab,
       const BDesc& d = dl[l - lt];
       kb_prolong_body<V, R>(Item{0, 0, d.n, 0}, d);
       __syncthreads();
-      tail_smooth<V, R>(d, smoother, post, false);
+      tail_smooth<V, R>(d, post, false);
     }
   }
 }
@@ -1317,17 +1699,63 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
     case OP_RESID_OFF: AMG_LAUNCH(kb_resid_off, (V, R)); break;
     case OP_HSGS: {
       // one wavefront per tile: everything staged in LDS when it fits in
-      // 64 KiB (aux2 = the most in-tile couplings of a row), else the
-      // iterate alone
+      // 64 KiB (aux2 = W | S << 16: the most in-tile couplings of a row, the
+      // most steps of a sweep + 1; aux3: the most in-tile couplings of a
+      // tile), else the iterate alone
       const dim3 bw(WAVE);
       const int T = Dh[L.direct.d].T;
-      const size_t full = hsgs_lds_bytes<V>(T, L.aux2, R);
+      const int W = L.aux2 & 0xffff, S = L.aux2 >> 16, C = L.aux3;
+      const size_t full = hsgs_lds_bytes<V>(T, C, R, S);
       if (full <= 65536) {
         if (L.use_direct)
           hipLaunchKernelGGL((kb_hsgs_lds<V, R, true>), g, bw, full, s, nullptr, nullptr, Dh[L.direct.d], L.direct,
-                             L.aux, L.aux2);
+                             L.aux, W, S, C);
         else
-          hipLaunchKernelGGL((kb_hsgs_lds<V, R, false>), g, bw, full, s, t, D, BDesc{}, Item{}, L.aux, L.aux2);
+          hipLaunchKernelGGL((kb_hsgs_lds<V, R, false>), g, bw, full, s, t, D, BDesc{}, Item{}, L.aux, W, S, C);
+        break;
+      }
+      const size_t lds = (size_t)T * R * sizeof(V);
+      if (L.use_direct)
+        hipLaunchKernelGGL((kb_hsgs<V, R, true>), g, bw, lds, s, nullptr, nullptr, Dh[L.direct.d], L.direct, L.aux);
+      else
+        hipLaunchKernelGGL((kb_hsgs<V, R, false>), g, bw, lds, s, t, D, BDesc{}, Item{}, L.aux);
+    } break;
+    case OP_TSGS: {
+      // one thread per row for one right-hand side, tiles of at most 256
+      // rows and at most 32 in-tile couplings per row (aux3 >> 16: the most
+      // of the launch's entries); else one wavefront per tile, staged in LDS
+      // when it fits in 64 KiB (aux2: the most in-tile couplings of a tile,
+      // aux3 & 0xffff: the most colours), else the hybrid sweeps by
+      // wavefront steps on the iterate alone
+      const dim3 bw(WAVE);
+      const int T = Dh[L.direct.d].T, C = L.aux2, NC = L.aux3 & 0xffff, W = L.aux3 >> 16;
+      if (R == 1 && T <= 256 && W <= 32 && tsgs_reg_lds_bytes<V>(T, C) <= 65536) {
+        const size_t lds = tsgs_reg_lds_bytes<V>(T, C);
+        const dim3 bt((T + WAVE - 1) / WAVE * WAVE);  // one thread per row
+#define AMG_TSGS_REG(WM)                                                                                        \
+  do {                                                                                                         \
+    if (L.use_direct)                                                                                          \
+      hipLaunchKernelGGL((kb_tsgs_reg<V, WM, true>), g, bt, lds, s, nullptr, nullptr, Dh[L.direct.d], L.direct, \
+                         L.aux, C);                                                                            \
+    else                                                                                                       \
+      hipLaunchKernelGGL((kb_tsgs_reg<V, WM, false>), g, bt, lds, s, t, D, BDesc{}, Item{}, L.aux, C);         \
+  } while (0)
+        if (W <= 16)
+          AMG_TSGS_REG(16);
+        else if (W <= 24)
+          AMG_TSGS_REG(24);
+        else
+          AMG_TSGS_REG(32);
+#undef AMG_TSGS_REG
+        break;
+      }
+      const size_t full = tsgs_lds_bytes<V>(T, C, R, NC);
+      if (full <= 65536) {
+        if (L.use_direct)
+          hipLaunchKernelGGL((kb_tsgs<V, R, true>), g, bw, full, s, nullptr, nullptr, Dh[L.direct.d], L.direct, L.aux,
+                             C, NC);
+        else
+          hipLaunchKernelGGL((kb_tsgs<V, R, false>), g, bw, full, s, t, D, BDesc{}, Item{}, L.aux, C, NC);
         break;
       }
       const size_t lds = (size_t)T * R * sizeof(V);
@@ -1345,10 +1773,10 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
     case OP_TAIL_UP: {
       const int up = L.op == OP_TAIL_UP ? 1 : 0;
       if (L.use_direct)
-        hipLaunchKernelGGL((kb_tail<V, R>), dim3(1), dim3(TAIL_NT), 0, s, nullptr, D, L.direct, L.aux, L.aux2 >> 8,
+        hipLaunchKernelGGL((kb_tail<V, R>), dim3(1), dim3(TAIL_NT), 0, s, nullptr, D, L.direct, L.aux2 >> 8,
                            L.aux2 & 255, 1, up);
       else
-        hipLaunchKernelGGL((kb_tail<V, R>), dim3(L.nblk), dim3(TAIL_NT), 0, s, t, D, Item{}, L.aux, L.aux2 >> 8,
+        hipLaunchKernelGGL((kb_tail<V, R>), dim3(L.nblk), dim3(TAIL_NT), 0, s, t, D, Item{}, L.aux2 >> 8,
                            L.aux2 & 255, 0, up);
     } break;
     default: fail(AMG_ERR_HIP, "unknown cycle launch");
@@ -1366,6 +1794,7 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
     case OP_RESID:
     case OP_RESID_OFF:
     case OP_HSGS:
+    case OP_TSGS:
     case OP_BGS:
     case OP_JACOBI:
     case OP_RESTRICT:

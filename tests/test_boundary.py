@@ -41,8 +41,9 @@ def test_params_struct_matches_header_defaults():
     assert (p.smoother, p.pre_sweeps, p.post_sweeps, p.vcycle_fp32, p.flexible) == (0, 1, 1, 0, -1)
     assert p.use_graphs == 1
     assert p.tail_rows == 0
-    assert ctypes.sizeof(A.Params) == 104  # 3 doubles + 18 int32 fields (4 bytes of padding before omega), 8-byte aligned
+    assert ctypes.sizeof(A.Params) == 112  # 3 doubles + 20 int32 fields (4 bytes of padding before omega), 8-byte aligned
     assert p.block_size == 1
+    assert (p.coarse_smoother, p.coarse_from) == (-1, 1)
 
 
 def test_header_compiles_as_c_and_matches_ctypes_layout(tmp_path):

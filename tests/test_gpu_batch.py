@@ -178,7 +178,8 @@ def test_precond_after_solve_matches_fresh(A):
 
 @pytest.mark.parametrize("fp32,pre,post,smoother", [(1, 1, 1, 0), (0, 1, 1, 0), (1, 2, 2, 0), (1, 0, 1, 0),
                                                     (1, 1, 0, 0), (1, 1, 1, 1), (1, 1, 1, 2), (0, 1, 1, 2),
-                                                    (1, 2, 2, 2), (1, 0, 1, 2)])
+                                                    (1, 2, 2, 2), (1, 0, 1, 2), (0, 1, 1, 3), (1, 1, 1, (0, 3, 1)),
+                                                    (0, 2, 2, (0, 3, 2)), (0, 1, 1, (2, 0, 1))])
 def test_tail_bit_identical(A, fp32, pre, post, smoother):
     """Levels cycled by one workgroup per entry (tail_rows: below that many
     rows; the coarsest solve stays a many-block launch) give the same bits as
@@ -190,6 +191,8 @@ def test_tail_bit_identical(A, fp32, pre, post, smoother):
     d = dev(systems(4, seed=5))
     ref = None
     kw = dict(vcycle_fp32=fp32, pre_sweeps=pre, post_sweeps=post, smoother=smoother)
+    if isinstance(smoother, tuple):  # (smoother, coarse_smoother, coarse_from)
+        kw.update(smoother=smoother[0], coarse_smoother=smoother[1], coarse_from=smoother[2])
     if pre + post == 0 or (fp32 == 0 and smoother == 1):
         pytest.skip("not a symmetric positive definite preconditioner")
     for tail in (0, 600, 1 << 30):

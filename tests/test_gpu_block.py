@@ -148,6 +148,7 @@ def test_block_input_errors(A):
     assert status(block_size=5) == A.ERR_UNSUPPORTED
     assert status(block_size=3, smoother=1) == A.ERR_UNSUPPORTED
     assert status(block_size=3, tail_rows=1000) == A.ERR_UNSUPPORTED
+    assert status(block_size=3, coarse_smoother=3) == A.ERR_UNSUPPORTED
     # one entry of the first node's first row removed: no longer whole blocks
     rp2 = rp.clone()
     rp2[1:] -= 1

@@ -1,0 +1,181 @@
+"""GPU parity of the tile-ordered multicolour smoother (the hybrid form of
+Sec. 3.2 with each tile's rows swept in colour order) and of per-level
+smoother choice (coarse_smoother from level coarse_from on), against the CPU
+oracle through the C ABI.
+
+Setup outputs (colours of the tile levels included) are bit-exact; the FP64
+V-cycle agrees to 1e-12 and every FP64 PCG iterate to 1e-10, element-wise and
+norm-wise, with iteration counts within one; the FP32 V-cycle to 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1209_0960_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "hetero_24": lambda: P.lognormal(24),                 # 13824 rows, 4 levels
+    "k1_20": lambda: P.poisson(20),                       # ragged last tile
+    "box_13x17x11": lambda: P.poisson(0, shape=(13, 17, 11)),
+    "layered_16": lambda: P.layered(16),
+}
+
+# (smoother, coarse_smoother, coarse_from, tile_rows)
+CONFIGS = [(3, -1, 1, 128), (0, 3, 1, 128), (0, 3, 2, 64), (0, 3, 1, 200), (0, 2, 1, 128), (0, 1, 1, 128),
+           (2, 0, 1, 128), (3, 0, 2, 1024)]
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1209_0960_amd import amg
+    amg.lib()
+    return amg
+
+
+_SYS = {}
+
+
+def system(name):
+    if name not in _SYS:
+        _SYS[name] = CASES[name]()
+    return _SYS[name]
+
+
+def kw_of(cfg):
+    sm, cs, cf, T = cfg
+    return dict(smoother=sm, coarse_smoother=cs, coarse_from=cf, tile_rows=T)
+
+
+def rel(a, b):
+    """max of the norm-wise and the element-wise relative difference."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    d = a - b
+    nrm = np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300)
+    ele = np.abs(d).max(initial=0.0) / max(np.abs(b).max(initial=0.0), 1e-300)
+    return float(max(nrm, ele))
+
+
+@pytest.mark.parametrize("cfg", CONFIGS[:4])
+def test_setup_bit_exact(A, cfg):
+    """Every level's matrix, aggregates and colours match the oracle; tile
+    levels report their colouring (the sweep order) although they are kept
+    in natural order."""
+    s = system("hetero_24")
+    rp, ci, v, _ = A.to_device(s)
+    kw = kw_of(cfg)
+    with A.Hierarchy(rp, ci, v, keep_setup_data=1, **kw) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, **kw)
+        assert hg.levels == ho.levels >= 3
+        for l in range(ho.levels):
+            g, o = hg.level(l), ho.level(l)
+            assert g["n"] == o.n and np.array_equal(g["rowptr"], o.rowptr) and np.array_equal(g["colind"], o.colind)
+            assert np.array_equal(g["vals"].view(np.int64), o.vals.view(np.int64)), (cfg, l)
+            assert g["ncolours"] == o.ncol and np.array_equal(g["colour"], o.colour), (cfg, l)
+            if l < ho.levels - 1:
+                assert np.array_equal(g["agg"], o.agg), (cfg, l)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_vcycle_fp64_parity(A, name, cfg):
+    s = system(name)
+    rp, ci, v, b = A.to_device(s)
+    kw = kw_of(cfg)
+    with A.Hierarchy(rp, ci, v, **kw) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, **kw)
+        z = hg.precond(b)
+        torch.cuda.synchronize()
+        assert rel(z.cpu().numpy(), ho.vcycle(s.b)) <= 1e-12, (name, cfg)
+
+
+@pytest.mark.parametrize("cfg", [CONFIGS[1], CONFIGS[2], CONFIGS[7]])
+def test_vcycle_fp32_parity(A, cfg):
+    s = system("hetero_24")
+    rp, ci, v, b = A.to_device(s)
+    kw = kw_of(cfg)
+    with A.Hierarchy(rp, ci, v, vcycle_fp32=1, **kw) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, vcycle_fp32=1, **kw)
+        z = hg.precond(b)
+        torch.cuda.synchronize()
+        assert rel(z.cpu().numpy(), ho.vcycle(s.b)) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["hetero_24", "layered_16"])
+@pytest.mark.parametrize("cfg", [CONFIGS[0], CONFIGS[1], CONFIGS[2]])
+def test_pcg_fp64_iterates(A, name, cfg):
+    s = system(name)
+    rp, ci, v, b = A.to_device(s)
+    kw = kw_of(cfg)
+    maxit = 200
+    with A.Hierarchy(rp, ci, v, **kw) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, **kw)
+        hist = torch.zeros((maxit + 1) * s.n, dtype=torch.float64, device="cuda")
+        x, r = hg.solve(b, rtol=1e-8, maxit=maxit, iter_hist=hist)
+        o = ho.pcg(s.b, rtol=1e-8, maxit=maxit, keep_iterates=True)
+        assert r.status == A.OK and o["status"] == O.OK
+        assert abs(r.iterations - o["iterations"]) <= 1
+        k = min(r.iterations, o["iterations"])
+        H = hist.cpu().numpy().reshape(maxit + 1, s.n)
+        for it in range(1, k + 1):
+            assert rel(H[it], o["iterates"][it]) <= 1e-10, (name, cfg, it)
+        assert r.true_rel_residual <= 1.01e-8
+
+
+def test_batched_entries_equal_single_solves(A):
+    """Two systems with the coarse tile smoother in one batch (two
+    right-hand sides each) give the bits of their single solves."""
+    kw = dict(coarse_smoother=3, coarse_from=1)
+    sys = [P.lognormal(20, seed=2), P.poisson(16)]
+    hs, bs, ref = [], [], []
+    try:
+        for s in sys:
+            rp, ci, v, b = A.to_device(s)
+            h = A.Hierarchy(rp, ci, v, **kw)
+            hs.append(h)
+            B = torch.cat([b, 0.5 * b.flip(0)]).contiguous()  # right-hand side k at k * n
+            bs.append(B)
+            xs = []
+            for k in range(2):
+                x, r = h.solve(B[k * s.n:(k + 1) * s.n].contiguous(), rtol=1e-8, maxit=200)
+                xs.append(x.cpu().numpy())
+            ref.append(np.concatenate(xs))
+        xs = [torch.zeros_like(B) for B in bs]
+        st, infos = A.pcg_solve_batched([h.h for h in hs], bs, xs, nrhs=2, rtol=1e-8, maxit=200)
+        assert st == A.OK
+        for x, r in zip(xs, ref):
+            assert rel(x.cpu().numpy(), r) <= 1e-12
+    finally:
+        for h in hs:
+            h.close()
+
+
+def test_batch_rejects_mixed_coarse_smoothers(A):
+    s = P.poisson(16)
+    rp, ci, v, b = A.to_device(s)
+    with A.Hierarchy(rp, ci, v, coarse_smoother=3) as h1, A.Hierarchy(rp, ci, v) as h2:
+        xs = [torch.zeros_like(b), torch.zeros_like(b)]
+        with pytest.raises(A.AMGError) as e:
+            A.pcg_solve_batched([h1.h, h2.h], [b.clone(), b.clone()], xs, nrhs=1, rtol=1e-8, maxit=50)
+        assert e.value.status == A.ERR_INVALID_ARG
+
+
+def test_input_errors(A):
+    s = P.poisson(12)
+    rp, ci, v, _ = A.to_device(s)
+
+    def status(**kw):
+        try:
+            A.Hierarchy(rp, ci, v, **kw).close()
+            return A.OK
+        except A.AMGError as e:
+            return e.status
+    assert status(smoother=4) == A.ERR_INVALID_ARG
+    assert status(coarse_smoother=4) == A.ERR_INVALID_ARG
+    assert status(coarse_smoother=-2) == A.ERR_INVALID_ARG
+    assert status(coarse_smoother=3, coarse_from=0) == A.ERR_INVALID_ARG
+    assert status(coarse_smoother=-1, coarse_from=0) == A.OK  # start level unused
+    assert status(coarse_smoother=3, coarse_from=40) == A.OK  # no level that deep: MC-SGS everywhere

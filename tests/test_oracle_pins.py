@@ -404,6 +404,43 @@ def test_hybrid_sgs_closed_form(T):
         assert np.abs(x - (x0 + (b - A @ x0) / np.diag(A))).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("T", [1, 7, 64, 1000])
+@pytest.mark.parametrize("labels", ["colouring", "random"])
+def test_tile_mcsgs_closed_form(T, labels):
+    """Hybrid SGS with each tile's rows swept in (colour, row) order is, in
+    that order, x + M^-1 (b - A x) with M = (D + L_B) D^-1 (D + U_B): the
+    closed form above on the matrix permuted inside each tile.  Labels from
+    the multicolouring, and arbitrary labels (the closed form holds for any
+    order; only a proper colouring makes the sweep parallel).  T >= n is the
+    sequential SGS in colour order, the multicolour smoother itself."""
+    s = P.lognormal(6, seed=12)
+    rng = np.random.default_rng(2)
+    if labels == "colouring":
+        c, _ = O.colour(s.rowptr, s.colind, seed=3, tile_rows=64)
+    else:
+        c = rng.integers(0, 5, s.n).astype(np.int32)
+    b = rng.standard_normal(s.n)
+    x0 = rng.standard_normal(s.n)
+    x = O.hybrid_sgs(s.rowptr, s.colind, s.vals, T, b, x0, colour=c)
+    A = dense(s.rowptr, s.colind, s.vals)
+    o = np.lexsort((np.arange(s.n), c, np.arange(s.n) // T))  # tile, colour, row
+    Ap = A[np.ix_(o, o)]
+    tile = o // T
+    Ab = np.where(tile[:, None] == tile[None, :], Ap, 0.0)
+    D = np.diag(np.diag(Ap))
+    M = (D + np.tril(Ab, -1)) @ np.diag(1.0 / np.diag(Ap)) @ (D + np.triu(Ab, 1))
+    ref = np.empty(s.n)
+    ref[o] = x0[o] + np.linalg.solve(M, b[o] - Ap @ x0[o])
+    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the colour order matters: the natural-order sweep is another smoother
+    nat = O.hybrid_sgs(s.rowptr, s.colind, s.vals, T, b, x0)
+    if T > 1:
+        assert np.abs(nat - ref).max() > 1e-6 * np.abs(ref).max()
+    if T >= s.n and labels == "colouring":
+        ncol = int(c.max()) + 1
+        assert np.abs(x - O.mcsgs(s.rowptr, s.colind, s.vals, c, ncol, b, x0)).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_hybrid_hierarchy_has_one_colour_and_smooths():
     """With the hybrid smoother no level is coloured (one colour, natural
     order); the V-cycle is a convergent preconditioner for PCG and BiCGSTAB."""

@@ -65,21 +65,32 @@ def l1_jacobi_dense(A):
     return apply
 
 
-def hybrid_dense(A, T):
+def tile_order(n, T, colour=None):
+    """Rows tile by tile (tiles of T consecutive rows, in order); inside a
+    tile natural order, or (colour, row) order given colours."""
+    if colour is None:
+        return np.arange(n)
+    return np.lexsort((np.arange(n), colour, np.arange(n) // T))
+
+
+def hybrid_dense(A, T, colour=None):
     """Block-Jacobi over row tiles of T with one symmetric Gauss-Seidel step
-    inside each block (Sec. 3.2): x += M^-1 (b - A x),
-    M = (D + L_B) D^-1 (D + U_B), L_B / U_B the strict triangles of the
-    tile-block-diagonal part of A."""
+    inside each block (Sec. 3.2), the rows of a tile swept in natural order
+    or, with colours, in (colour, row) order: in that order,
+    x += M^-1 (b - A x), M = (D + L_B) D^-1 (D + U_B), L_B / U_B the strict
+    triangles of the tile-block-diagonal part of A."""
     n = A.shape[0]
-    B = np.zeros_like(A)
-    for lo in range(0, n, T):
-        hi = min(n, lo + T)
-        B[lo:hi, lo:hi] = A[lo:hi, lo:hi]
-    D = np.diag(np.diag(A))
+    o = tile_order(n, T, colour)
+    Ap = A[np.ix_(o, o)]
+    tile = np.arange(n)[o] // T
+    B = np.where(tile[:, None] == tile[None, :], Ap, 0.0)
+    D = np.diag(np.diag(Ap))
     M = (D + np.tril(B, -1)) @ np.linalg.inv(D) @ (D + np.triu(B, 1))
 
     def apply(b, x):
-        return x + np.linalg.solve(M, b - A @ x)
+        out = np.empty_like(x)
+        out[o] = x[o] + np.linalg.solve(M, b[o] - Ap @ x[o])
+        return out
     return apply
 
 
@@ -87,8 +98,11 @@ def paper_cycle(H, A0, omega, smoother, pre, post, tile_rows):
     """Dense V-cycle of Sec. 2 with the paper's coarse operators
     A_{l+1} = (1/omega) P_l^T A_l P_l and x_l += P_l x_{l+1}.  Only the
     aggregates and the colours of each level are taken from the hierarchy
-    (both are pinned on their own); every operator is formed here."""
+    (both are pinned on their own); every operator is formed here.
+    smoother: one smoother for every level, or a list with one per level
+    (0 MC-SGS, 1 l1-Jacobi, 2 hybrid SGS, 3 hybrid SGS in colour order)."""
     L = H.levels
+    sms = smoother if isinstance(smoother, (list, tuple)) else [smoother] * L
     As, Ps, smooths = [A0], [], []
     for l in range(L - 1):
         lv = H.level(l)
@@ -97,14 +111,16 @@ def paper_cycle(H, A0, omega, smoother, pre, post, tile_rows):
         As.append((Pm.T @ As[l] @ Pm) / omega)
     for l in range(L - 1):
         A = As[l]
-        if smoother == 0:
-            lv = H.level(l)
+        lv = H.level(l)
+        if sms[l] == 0:
             order = np.lexsort((np.arange(lv.n), lv.colour))  # colour, then row
             smooths.append(sgs_dense(A, order))
-        elif smoother == 1:
+        elif sms[l] == 1:
             smooths.append(l1_jacobi_dense(A))
-        else:
+        elif sms[l] == 2:
             smooths.append(hybrid_dense(A, tile_rows))
+        else:
+            smooths.append(hybrid_dense(A, tile_rows, lv.colour))
 
     def cycle(l, b):
         if l == L - 1:
@@ -125,6 +141,7 @@ CYCLE_CASES = [
     (0, 1.6, 1, 1), (0, 1.0, 1, 1), (0, 1.6, 2, 1), (0, 1.6, 1, 0), (0, 1.6, 0, 2),
     (1, 1.6, 1, 1), (1, 1.0, 2, 2), (1, 1.6, 0, 1),
     (2, 1.6, 1, 1), (2, 1.0, 1, 0),
+    (3, 1.6, 1, 1), (3, 1.0, 0, 1),
 ]
 
 
@@ -162,6 +179,50 @@ def test_three_level_coarse_correction_closed_form(omega):
     Bref = omega ** 2 * Q @ np.linalg.solve(Q.T @ A @ Q, Q.T)
     B = np.column_stack([H.vcycle(e) for e in np.eye(s.n)])
     assert np.abs(B - Bref).max() <= 1e-10 * np.abs(Bref).max()
+
+
+# One smoother on the first levels, another from coarse_from on.  An index
+# mistake (from coarse_from + 1, or from coarse_from - 1) changes one level's
+# smoother, and with it the cycle.
+PER_LEVEL_CASES = [
+    # (smoother, coarse_smoother, coarse_from)
+    (0, 3, 1), (0, 3, 2), (0, 3, 3), (0, 1, 2), (0, 2, 1), (2, 0, 2), (3, 0, 1),
+]
+
+
+@pytest.mark.parametrize("smoother,coarse,start", PER_LEVEL_CASES)
+def test_vcycle_per_level_smoothers_equal_paper_cycle(smoother, coarse, start):
+    """Four or more levels of a lognormal 12^3 problem (64-row tiles) with
+    `smoother` on levels 0..start-1 and `coarse` from level `start` on: the
+    oracle's cycle equals the dense cycle of Sec. 2 with those smoothers."""
+    s = P.lognormal(12, seed=7)
+    T = 64
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=8, smoother=smoother, coarse_smoother=coarse,
+                    coarse_from=start, tile_rows=T, colour_tile_rows=64)
+    assert H.levels >= 4, H.levels
+    sms = [smoother if l < start else coarse for l in range(H.levels)]
+    for l in range(H.levels - 1):  # the tile order needs the level's colouring
+        assert (H.level(l).ncol > 1) == (sms[l] in (0, 1, 3)), (l, sms[l], H.level(l).ncol)
+    A0 = dense(s.rowptr, s.colind, s.vals)
+    ref, _ = paper_cycle(H, A0, 1.6, sms, 1, 1, T)
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        b = rng.uniform(-1, 1, s.n)
+        zr = ref(b)
+        assert np.abs(H.vcycle(b) - zr).max() <= 1e-11 * np.abs(zr).max()
+
+
+def test_per_level_smoother_input_errors():
+    """Smoother ids outside 0..3, a coarse smoother below -1 and a start level
+    below 1 are rejected; point-based levels take the multicolour smoother on
+    every level."""
+    s = P.lognormal(6, seed=1)
+    for kw in (dict(smoother=4), dict(smoother=-1), dict(coarse_smoother=4), dict(coarse_smoother=-2),
+               dict(coarse_smoother=3, coarse_from=0)):
+        with pytest.raises(O.OracleError) as e:
+            O.Hierarchy(s.rowptr, s.colind, s.vals, **kw)
+        assert e.value.status == O.INVALID, kw
+    O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_smoother=-1, coarse_from=0)  # unused start level
 
 
 # ------------------------------------------------------------------ l1-Jacobi

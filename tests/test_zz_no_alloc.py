@@ -25,14 +25,17 @@ def dev(s):
     return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (s.rowptr, s.colind, s.vals, s.b)]
 
 
-@pytest.mark.parametrize("fp32,smoother", [(0, 0), (1, 0), (0, 1), (1, 2), (0, 2)])
+@pytest.mark.parametrize("fp32,smoother", [(0, 0), (1, 0), (0, 1), (1, 2), (0, 2), (0, (0, 3)), (1, (3, 0))])
 def test_noalloc_equals_precond_apply(A, fp32, smoother):
     big, small = P.lognormal(40, seed=6), P.lognormal(24, seed=7)
+    kw = dict(smoother=smoother)
+    if isinstance(smoother, tuple):  # (smoother, coarse_smoother from level 1)
+        kw = dict(smoother=smoother[0], coarse_smoother=smoother[1], coarse_from=1)
     hs = []
     try:
         for s in (big, small):
             rp, ci, v, b = dev(s)
-            hs.append((A.Hierarchy(rp, ci, v, vcycle_fp32=fp32, smoother=smoother), b))
+            hs.append((A.Hierarchy(rp, ci, v, vcycle_fp32=fp32, **kw), b))
         # two calls in a row, the smaller system second, then the larger again
         for h, b in (hs[0], hs[1], hs[0]):
             z_ref = h.precond(b)
