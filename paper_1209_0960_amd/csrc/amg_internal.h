@@ -157,6 +157,13 @@ struct Level {
   unsigned short* icc = nullptr;
   double* icv = nullptr;
   float* icv32 = nullptr;
+  // couplings to other tiles (tile sweeps), likewise: ocp (n+1), global
+  // column (solve order), value
+  int* ocp = nullptr;
+  int* occ = nullptr;
+  double* ocv = nullptr;
+  float* ocv32 = nullptr;
+  long long ocn = 0;
   int icmax = 0;                  // most in-tile couplings of one tile
   long long icn = 0;              // in-tile couplings of the level
   // optional setup data (natural order; on point-based levels per node and node-graph entry)
@@ -345,6 +352,9 @@ struct BDesc {
   const unsigned short* icc;
   const double* icv64;
   const float* icv32;
+  const int *ocp, *occ;             // couplings to other tiles (tile sweeps): offsets, column, value
+  const double* ocv64;
+  const float* ocv32;
   const int* tcb;                   // tile-ordered multicolour levels: colour bounds of each tile (tncol + 1)
   const int* tcol;                  //   and the colour of each row (solve order)
   int tncol;
@@ -387,8 +397,20 @@ enum {
   OP_RESID_OFF,  // hybrid smoother: t = b - (couplings to other tiles) x (slices)
   OP_HSGS,       // hybrid smoother: in-tile forward + backward sweeps (tiles; aux = 1: from b, x = 0)
   OP_BGS,        // point-based level: block Gauss-Seidel on the slices of one colour (whole nodes)
-  OP_TSGS,       // tile-ordered multicolour smoother: in-tile sweeps colour by colour (tiles; aux = 1: from b)
+  OP_TSGS,       // tile-ordered multicolour smoother: in-tile sweeps colour by colour (tiles; aux bit 0: from
+                 // b, bit 1: also the in-tile sums of the residual into t)
+  OP_RESID_TILE, // tile-sweep level: t = b - A x from the compact couplings (rows; aux = 1: in-tile sums in t)
 };
+
+// LDS bytes and eligibility of the register form of the colour-ordered tile
+// sweep (one thread per row, tiles of at most 256 rows, at most 32 in-tile
+// couplings per row W, at most C per tile, one right-hand side).
+inline size_t tsgs_reg_lds_bytes(int T, int C, size_t vb) {
+  return (size_t)T * vb + (size_t)C * (vb + sizeof(unsigned short));
+}
+inline bool tsgs_reg_ok(int R, int T, int W, int C, size_t vb) {
+  return R == 1 && T <= 256 && W <= 32 && tsgs_reg_lds_bytes(T, C, vb) <= 65536;
+}
 enum { FIN_STORE = 0, FIN_ALPHA, FIN_BETA_PCG, FIN_BETA_FCG, FIN_INIT };
 
 struct Launch {

@@ -309,6 +309,10 @@ void level_desc(BDesc& d, const Hierarchy& H, int l) {
   d.icc = L.icc;
   d.icv64 = L.icv;
   d.icv32 = L.icv32;
+  d.ocp = L.ocp;
+  d.occ = L.occ;
+  d.ocv64 = L.ocv;
+  d.ocv32 = L.ocv32;
   d.tcb = L.tcb;
   d.tcol = L.tcol;
   d.tncol = L.tncol;
@@ -564,6 +568,35 @@ int sm_at(const Batch& B, int l) {
 // First row after colour 0 (solve order).
 int colour0_rows(const Level& L) { return L.srow_h[L.sptr[1]]; }
 
+// Launch limits of the tile sweeps of level l over entries E: the most
+// in-tile couplings of a row (W) and of a tile (C), the most wavefront steps
+// of a sweep + 1 (S) and the most colours (NC).
+struct TileLimits {
+  int W = 0, S = 0, C = 0, NC = 0;
+};
+TileLimits tile_limits(const Batch& B, const std::vector<int>& E, int l) {
+  TileLimits t;
+  for (int e : E) {
+    const Level& L = hier(B, e).lev[l];
+    t.W = std::max(t.W, L.hw);
+    t.S = std::max(t.S, std::max(L.hdf, L.hdb) + 1);
+    t.C = std::max(t.C, L.icmax);
+    t.NC = std::max(t.NC, L.tncol);
+  }
+  return t;
+}
+// Level l sweeps colour by colour (bounds in one wavefront register).
+bool colour_sweeps(const Batch& B, const std::vector<int>& E, int l) {
+  return sm_at(B, l) == AMG_SMOOTHER_TILE_MCSGS && tile_limits(B, E, l).NC < 64;
+}
+// The last pre-smoothing sweep of level l also leaves the in-tile sums of
+// the residual in t (register form of the colour-ordered sweep).
+bool fused_resid(const Batch& B, const std::vector<int>& E, int l) {
+  if (B.pre == 0 || !colour_sweeps(B, E, l)) return false;
+  const TileLimits t = tile_limits(B, E, l);
+  return tsgs_reg_ok(B.R, hier(B, E[0]).lev[l].T, t.W, std::max(t.C, 1), B.fp32 ? 4 : 8);
+}
+
 // `sweeps` smoothing steps on level l; from_zero: the iterate is zero before,
 // and (pre-smoothing) each entry's last pass also writes its residual rows.
 void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, int sweeps, bool from_zero) {
@@ -626,21 +659,21 @@ void build_smooth(Builder& b, const Batch& B, const std::vector<int>& E, int l, 
       const bool zero = from_zero && k == 0;
       if (!zero) {
         b.begin(OP_RESID_OFF, l, kind_at(l, AMG_KIND_SWEEP));
-        for (int e : E) add_slices(b, B, e, l, 0, hier(B, e).lev[l].nsl);
+        for (int e : E) {
+          const Level& L = hier(B, e).lev[l];
+          // per row the offset, its couplings to other tiles (column, value, gathered x), b read, t written
+          b.pieces(B.desc_index(e, l), L.n, 256,  // one row per thread (blocks of 256 threads)
+                   4.0 + (double)L.ocn / L.n * (4.0 + vb + B.R * vb) + 2.0 * B.R * vb);
+        }
         b.end();
       }
-      // LDS layout of the launch: the most in-tile couplings of a row and the
-      // most steps of a sweep (+ 1) over its entries
-      int W = 0, S = 0, C = 0, NC = 0;
-      for (int e : E) {
-        const Level& L = hier(B, e).lev[l];
-        W = std::max(W, L.hw);
-        S = std::max(S, std::max(L.hdf, L.hdb) + 1);
-        C = std::max(C, L.icmax);
-        NC = std::max(NC, L.tncol);
-      }
-      if (sm == AMG_SMOOTHER_TILE_MCSGS && NC < 64)  // colour by colour, bounds in one wavefront register (at least one coupling slot in LDS)
-        b.begin(OP_TSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0, std::max(C, 1), NC | (std::min(W, 0x7fff) << 16));
+      // LDS layout of the launch: limits over its entries
+      const TileLimits tl = tile_limits(B, E, l);
+      const int W = tl.W, S = tl.S, C = tl.C, NC = tl.NC;
+      const bool emit = from_zero && k + 1 == sweeps && fused_resid(B, E, l);
+      if (colour_sweeps(B, E, l))  // colour by colour (at least one coupling slot in LDS)
+        b.begin(OP_TSGS, l, kind_at(l, AMG_KIND_SWEEP), (zero ? 1 : 0) | (emit ? 2 : 0), std::max(C, 1),
+                NC | (std::min(W, 0x7fff) << 16));
       else  // wavefront steps of the solve order (natural, or colour by colour in each tile)
         b.begin(OP_HSGS, l, kind_at(l, AMG_KIND_SWEEP), zero ? 1 : 0, W | (S << 16), C);
       for (int e : E) {
@@ -694,12 +727,24 @@ void build_precond(Builder& b, const Batch& B, const std::vector<int>& S, bool c
     }
     b.end();
     build_smooth(b, B, E, l, B.pre, true);
-    b.begin(OP_RESID, l, kind_at(l, AMG_KIND_RESTRICT));
-    for (int e : E) {
-      const Level& L = hier(B, e).lev[l];
-      add_slices(b, B, e, l, B.pre > 0 && colour0_shortcuts(B, e, l) ? L.sptr[1] : 0, L.nsl);
+    if (tile_sweeps(sm_at(B, l))) {  // from the compact couplings (in-tile part from the sweep if fused)
+      const bool fused = fused_resid(B, E, l);
+      b.begin(OP_RESID_TILE, l, kind_at(l, AMG_KIND_RESTRICT), fused ? 1 : 0);
+      for (int e : E) {
+        const Level& L = hier(B, e).lev[l];
+        const double in = fused ? B.R * vb : 4.0 + (double)L.icn / L.n * (2.0 + vb + B.R * vb);
+        b.pieces(B.desc_index(e, l), L.n, 256,
+                 in + 4.0 + (double)L.ocn / L.n * (4.0 + vb + B.R * vb) + vb + 3.0 * B.R * vb);
+      }
+      b.end();
+    } else {
+      b.begin(OP_RESID, l, kind_at(l, AMG_KIND_RESTRICT));
+      for (int e : E) {
+        const Level& L = hier(B, e).lev[l];
+        add_slices(b, B, e, l, B.pre > 0 && colour0_shortcuts(B, e, l) ? L.sptr[1] : 0, L.nsl);
+      }
+      b.end();
     }
-    b.end();
     b.begin(OP_RESTRICT, l, kind_at(l, AMG_KIND_RESTRICT));
     for (int e : E) {
       const Level& L = hier(B, e).lev[l];

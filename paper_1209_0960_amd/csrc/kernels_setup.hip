@@ -2121,27 +2121,31 @@ void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s) {
   L.hg = L.hw > 8 && !L.tcb ? HS_G : 1;
 }
 
-// In-tile couplings of row i (one thread per row; tiles of T rows): count,
-// then (icp set) columns relative to the tile and values in SELL entry order.
-__global__ void k_ic_rows(int n, int T, const int* __restrict__ soff, const int* __restrict__ scol,
-                          const double* __restrict__ sval, const int* __restrict__ icp, int* __restrict__ cnt,
-                          unsigned short* __restrict__ icc, double* __restrict__ icv, float* __restrict__ icv32) {
+// In-tile (ext = 0) or other-tile (ext = 1) couplings of row i (one thread
+// per row; tiles of T rows): count, then (ptr set) columns (relative to the
+// tile, or global) and values in SELL entry order.
+__global__ void k_tile_rows(int n, int T, int ext, const int* __restrict__ soff, const int* __restrict__ scol,
+                            const double* __restrict__ sval, const int* __restrict__ ptr, int* __restrict__ cnt,
+                            unsigned short* __restrict__ col16, int* __restrict__ col32, double* __restrict__ v64,
+                            float* __restrict__ v32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int lo = i - i % T, hi = min(n, lo + T);
   const int t = i & 63, base = soff[i >> 6], w = (soff[(i >> 6) + 1] - base) >> 6;
-  int c = icp ? icp[i] : 0;
+  int c = ptr ? ptr[i] : 0;
   for (int e = 0; e < w; ++e) {
     const int j = scol[base + 64 * e + t];
-    if (j < lo || j >= hi || j == i) continue;
-    if (icp) {
-      icc[c] = (unsigned short)(j - lo);
-      if (icv) icv[c] = sval[base + 64 * e + t];
-      if (icv32) icv32[c] = (float)sval[base + 64 * e + t];
+    const bool in = j >= lo && j < hi;
+    if (ext ? in : (!in || j == i)) continue;
+    if (ptr) {
+      if (col16) col16[c] = (unsigned short)(j - lo);
+      if (col32) col32[c] = j;
+      if (v64) v64[c] = sval[base + 64 * e + t];
+      if (v32) v32[c] = (float)sval[base + 64 * e + t];
     }
     ++c;
   }
-  if (!icp) cnt[i] = c;
+  if (!ptr) cnt[i] = c;
 }
 
 __global__ void k_ic_tile_max(int n, int T, int ntiles, const int* __restrict__ icp, int* __restrict__ mx) {
@@ -2153,19 +2157,26 @@ __global__ void k_ic_tile_max(int n, int T, int ntiles, const int* __restrict__ 
 void tile_couplings(Hierarchy& H, Level& L, bool f32, hipStream_t s) {
   const int n = L.n, T = L.T, g = cdiv(n, 256);
   DBuf cnt((size_t)n * sizeof(int), s);
-  hipLaunchKernelGGL(k_ic_rows, dim3(g), dim3(256), 0, s, n, T, L.soff, L.scol, L.sval, nullptr, cnt.as<int>(),
-                     nullptr, nullptr, nullptr);
-  L.icp = H.alloc<int>((size_t)n + 1, s);
-  exclusive_scan(cnt.as<int>(), L.icp, n, s);
-  const int tot = read1(L.icp + n, s);
-  L.icn = tot;
-  L.icc = H.alloc<unsigned short>((size_t)std::max(tot, 1), s);
-  if (f32)
-    L.icv32 = H.alloc<float>((size_t)std::max(tot, 1), s);
-  else
-    L.icv = H.alloc<double>((size_t)std::max(tot, 1), s);
-  hipLaunchKernelGGL(k_ic_rows, dim3(g), dim3(256), 0, s, n, T, L.soff, L.scol, L.sval, L.icp, nullptr, L.icc,
-                     L.icv, L.icv32);
+  for (int ext = 0; ext < 2; ++ext) {
+    int*& ptr = ext ? L.ocp : L.icp;
+    hipLaunchKernelGGL(k_tile_rows, dim3(g), dim3(256), 0, s, n, T, ext, L.soff, L.scol, L.sval, nullptr,
+                       cnt.as<int>(), nullptr, nullptr, nullptr, nullptr);
+    ptr = H.alloc<int>((size_t)n + 1, s);
+    exclusive_scan(cnt.as<int>(), ptr, n, s);
+    const int tot = read1(ptr + n, s);
+    const size_t m = (size_t)std::max(tot, 1);
+    unsigned short* c16 = ext ? nullptr : (L.icc = H.alloc<unsigned short>(m, s));
+    int* c32 = ext ? (L.occ = H.alloc<int>(m, s)) : nullptr;
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+    if (f32)
+      v32 = (ext ? L.ocv32 : L.icv32) = H.alloc<float>(m, s);
+    else
+      v64 = (ext ? L.ocv : L.icv) = H.alloc<double>(m, s);
+    hipLaunchKernelGGL(k_tile_rows, dim3(g), dim3(256), 0, s, n, T, ext, L.soff, L.scol, L.sval, ptr, nullptr, c16,
+                       c32, v64, v32);
+    (ext ? L.ocn : L.icn) = tot;
+  }
   DBuf mx(sizeof(int), s);
   AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
   const int ntiles = cdiv(n, T);

@@ -99,6 +99,7 @@ struct Mat<double> {
   __device__ static const double* l1(const BDesc& d) { return d.l164; }
   __device__ static const double* dinv(const BDesc& d) { return d.dinv64; }
   __device__ static const double* icv(const BDesc& d) { return d.icv64; }
+  __device__ static const double* ocv(const BDesc& d) { return d.ocv64; }
 };
 template <>
 struct Mat<float> {
@@ -107,6 +108,7 @@ struct Mat<float> {
   __device__ static const float* l1(const BDesc& d) { return d.l132; }
   __device__ static const float* dinv(const BDesc& d) { return d.dinv32; }
   __device__ static const float* icv(const BDesc& d) { return d.icv32; }
+  __device__ static const float* ocv(const BDesc& d) { return d.ocv32; }
 };
 
 // Work item of this block.  Table launches read it from tab[blockIdx.x] and
@@ -381,38 +383,113 @@ __global__ __launch_bounds__(NT) void kb_resid(AMG_KARGS) {
 // from before the step); the in-tile sweeps then use t and the tile's own
 // current values only, so tiles never read each other's updates.
 
-// t = b - (couplings to other tiles) x on the slices [lo, hi).  Padding
-// entries name their own row and fall inside the tile.
+// t = b - (couplings to other tiles) x on rows [lo, hi) (one thread per row,
+// the level's compact list of each row's couplings to other tiles, SELL
+// entry order).
 template <typename V, int R>
 __device__ __forceinline__ void kb_resid_off_body(const Item& it, const BDesc& d) {
-  const int sl = it.lo + (int)(threadIdx.x / WAVE);
-  if (sl >= it.hi) return;
-  const int lane = __lane_id();
-  const int r = d.srow[sl] + lane;
-  if (r >= d.srow[sl + 1]) return;
-  const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
-  const int lo = r - r % d.T, hi = lo + d.T;
   const V* x = static_cast<const V*>(d.x);
-  const V* sv = Mat<V>::sval(d);
-  V acc[R];
+  const V* ocv = Mat<V>::ocv(d);
+  for (int r = it.lo + (int)threadIdx.x; r < it.hi; r += (int)blockDim.x) {
+    V acc[R];
 #pragma unroll
-  for (int k = 0; k < R; ++k) acc[k] = 0;
-  for (int e = 0; e < w; ++e) {
-    const int j = d.scol[base + 64 * e + lane];
-    if (j < lo || j >= hi) {
-      const V a = sv[base + 64 * e + lane];
-      V xv[R];
-      ldv<V, R>(x + (size_t)j * R, xv);
+    for (int k = 0; k < R; ++k) acc[k] = 0;
+    const int e1 = d.ocp[r + 1];
+    // four entries at a time: their loads, then their gathers, in flight together
+    for (int e0 = d.ocp[r]; e0 < e1; e0 += 4) {
+      V a[4], xv[4][R];
+      int j[4];
 #pragma unroll
-      for (int k = 0; k < R; ++k) acc[k] = madd(a, xv[k], acc[k]);
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u, e1 - 1);
+        a[u] = ocv[e];
+        j[u] = d.occ[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ldv<V, R>(x + (size_t)j[u] * R, xv[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u < e1)
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] = madd(a[u], xv[u][k], acc[k]);
     }
-  }
-  V bb[R], o[R];
-  ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+    V bb[R], o[R];
+    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
 #pragma unroll
-  for (int k = 0; k < R; ++k) o[k] = bb[k] - acc[k];
-  stv<V, R>(static_cast<V*>(d.t) + (size_t)r * R, o);
+    for (int k = 0; k < R; ++k) o[k] = bb[k] - acc[k];
+    stv<V, R>(static_cast<V*>(d.t) + (size_t)r * R, o);
+  }
 }
+// Residual of a tile-sweep level, t = b - (a_ii x_i + acc) on rows [lo, hi)
+// (one thread per row), acc the sum over the row's in-tile couplings (compact
+// order), then on over its couplings to other tiles.  from_t: the in-tile
+// part is already in t (written by the last smoothing sweep, which holds the
+// couplings and the final iterate); every path that forms this residual
+// follows the same order, so all give the same bits.
+template <typename V, int R>
+__device__ __forceinline__ void kb_resid_tile_body(const Item& it, const BDesc& d, int from_t) {
+  const V* x = static_cast<const V*>(d.x);
+  V* t = static_cast<V*>(d.t);
+  const V* icv = Mat<V>::icv(d);
+  const V* ocv = Mat<V>::ocv(d);
+  for (int r = it.lo + (int)threadIdx.x; r < it.hi; r += (int)blockDim.x) {
+    V acc[R];
+    if (from_t) {
+      ldv<V, R>(t + (size_t)r * R, acc);
+    } else {
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc[k] = 0;
+      const int lo = r - r % d.T, e1 = d.icp[r + 1];
+      for (int e0 = d.icp[r]; e0 < e1; e0 += 4) {
+        V a[4], xv[4][R];
+        int j[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u, e1 - 1);
+          a[u] = icv[e];
+          j[u] = lo + (int)d.icc[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ldv<V, R>(x + (size_t)j[u] * R, xv[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (e0 + u < e1)
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] = madd(a[u], xv[u][k], acc[k]);
+      }
+    }
+    const int e1 = d.ocp[r + 1];
+    for (int e0 = d.ocp[r]; e0 < e1; e0 += 4) {
+      V a[4], xv[4][R];
+      int j[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u, e1 - 1);
+        a[u] = ocv[e];
+        j[u] = d.occ[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ldv<V, R>(x + (size_t)j[u] * R, xv[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u < e1)
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] = madd(a[u], xv[u][k], acc[k]);
+    }
+    V bb[R], xr[R], o[R];
+    ldv<V, R>(static_cast<const V*>(d.b) + (size_t)r * R, bb);
+    ldv<V, R>(x + (size_t)r * R, xr);
+    const V dg = Mat<V>::dg(d)[r];
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = bb[k] - madd(dg, xr[k], acc[k]);
+    stv<V, R>(t + (size_t)r * R, o);
+  }
+}
+template <typename V, int R, bool DIRECT>
+__global__ __launch_bounds__(NT) void kb_resid_tile(AMG_KARGS, int from_t) {
+  AMG_BODY((kb_resid_tile_body<V, R>), from_t)
+}
+
 template <typename V, int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_resid_off(AMG_KARGS) {
   AMG_BODY((kb_resid_off_body<V, R>))
@@ -931,7 +1008,11 @@ __global__ __launch_bounds__(WAVE) void kb_tsgs(AMG_KARGS, int from_b, int C, in
 // row is 1), as hybrid_tile does.  The couplings pass through LDS once, by
 // contiguous copies, on their way to the registers.
 template <typename V, int WM>
-__device__ __forceinline__ void kb_tsgs_reg_body(const Item& it, const BDesc& d, int from_b, int C) {
+__device__ __forceinline__ void kb_tsgs_reg_body(const Item& it, const BDesc& d, int mode, int C) {
+  // mode bit 0: the iterate is zero before the sweep (source b); bit 1: also
+  // write each row's in-tile sum with the final iterate to t (the first part
+  // of kb_resid_tile's residual)
+  const int from_b = mode & 1;
   extern __shared__ double hs_lds[];
   const int T = d.T, nthr = (int)blockDim.x;
   V* xt = reinterpret_cast<V*>(hs_lds);
@@ -1008,14 +1089,24 @@ __device__ __forceinline__ void kb_tsgs_reg_body(const Item& it, const BDesc& d,
     __syncthreads();
   }
   if (on) x[lo + q] = xt[q];
+  if (mode & 2) {
+    V acc = 0;
+#pragma unroll
+    for (int u0 = 0; u0 < WM; u0 += 8) {
+      if (!__builtin_amdgcn_ballot_w64(cnt > u0)) break;
+      V xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = xt[j[u0 + u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (u0 + u < cnt) acc = madd(a[u0 + u], xv[u], acc);
+    }
+    if (on) static_cast<V*>(d.t)[lo + q] = acc;
+  }
 }
 template <typename V, int WM, bool DIRECT>
-__global__ __launch_bounds__(256) void kb_tsgs_reg(AMG_KARGS, int from_b, int C) {
-  AMG_BODY((kb_tsgs_reg_body<V, WM>), from_b, C)
-}
-template <typename V>
-__host__ __device__ inline size_t tsgs_reg_lds_bytes(int T, int C) {
-  return (size_t)T * sizeof(V) + (size_t)C * (sizeof(V) + sizeof(unsigned short));
+__global__ __launch_bounds__(256) void kb_tsgs_reg(AMG_KARGS, int mode, int C) {
+  AMG_BODY((kb_tsgs_reg_body<V, WM>), mode, C)
 }
 
 template <typename V, int R>
@@ -1136,8 +1227,7 @@ __global__ __launch_bounds__(NT) void kb_coarse(AMG_KARGS) {
 // thread per row), so the result does not depend on where the tail starts.
 constexpr int TAIL_NT = 1024;
 
-// op: 0 residual, 1 Gauss-Seidel pass, 2 Gauss-Seidel pass from x = 0,
-// 3 residual of the couplings to other tiles (hybrid smoother).
+// op: 0 residual, 1 Gauss-Seidel pass, 2 Gauss-Seidel pass from x = 0.
 template <typename V, int R>
 __device__ inline void tail_slices(const BDesc& d, int s0, int s1, int op) {
   const int nw = (int)blockDim.x / WAVE;
@@ -1147,8 +1237,6 @@ __device__ inline void tail_slices(const BDesc& d, int s0, int s1, int op) {
       kb_gs_body<V, R>(it, d);
     else if (op == 2)
       kb_gs0_body<V, R>(it, d);
-    else if (op == 3)
-      kb_resid_off_body<V, R>(it, d);
     else
       kb_resid_body<V, R>(it, d);
   }
@@ -1173,7 +1261,10 @@ __device__ inline void tail_smooth(const BDesc& d, int sweeps, bool from_zero) {
       // wavefronts take tiles; the sweeps work on the level's vector in
       // place (tiles only read their own rows), steps separated by barriers
       const bool zero = from_zero && k == 0;
-      if (!zero) tail_slices<V, R>(d, 0, d.nsl, 3);
+      if (!zero) {
+        kb_resid_off_body<V, R>(Item{0, 0, d.n, 0}, d);
+        __syncthreads();
+      }
       const int nw = (int)blockDim.x / WAVE, wv = (int)threadIdx.x / WAVE;
       const int ntl = (d.n + d.T - 1) / d.T;
       const V* src = static_cast<const V*>(zero ? d.b : d.t);
@@ -1210,7 +1301,12 @@ __global__ __launch_bounds__(TAIL_NT) void kb_tail(const Item* __restrict__ tab,
       kb_zero_body<V, R>(Item{0, 0, d.n, 0}, d);
       __syncthreads();
       tail_smooth<V, R>(d, pre, true);
-      tail_slices<V, R>(d, 0, d.nsl, 0);
+      if (d.sm == AMG_SMOOTHER_HYBRID_SGS || d.sm == AMG_SMOOTHER_TILE_MCSGS) {
+        kb_resid_tile_body<V, R>(Item{0, 0, d.n, 0}, d, 0);
+        __syncthreads();
+      } else {
+        tail_slices<V, R>(d, 0, d.nsl, 0);
+      }
       for (int lo = 0; lo < d.nc; lo += nt) kb_restrict_body<V, R>(Item{0, lo, min(d.nc, lo + nt), 0}, d);
       __syncthreads();
     }
@@ -1729,8 +1825,8 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
       // wavefront steps on the iterate alone
       const dim3 bw(WAVE);
       const int T = Dh[L.direct.d].T, C = L.aux2, NC = L.aux3 & 0xffff, W = L.aux3 >> 16;
-      if (R == 1 && T <= 256 && W <= 32 && tsgs_reg_lds_bytes<V>(T, C) <= 65536) {
-        const size_t lds = tsgs_reg_lds_bytes<V>(T, C);
+      if (tsgs_reg_ok(R, T, W, C, sizeof(V))) {
+        const size_t lds = tsgs_reg_lds_bytes(T, C, sizeof(V));
         const dim3 bt((T + WAVE - 1) / WAVE * WAVE);  // one thread per row
 #define AMG_TSGS_REG(WM)                                                                                        \
   do {                                                                                                         \
@@ -1752,18 +1848,20 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
       const size_t full = tsgs_lds_bytes<V>(T, C, R, NC);
       if (full <= 65536) {
         if (L.use_direct)
-          hipLaunchKernelGGL((kb_tsgs<V, R, true>), g, bw, full, s, nullptr, nullptr, Dh[L.direct.d], L.direct, L.aux,
-                             C, NC);
+          hipLaunchKernelGGL((kb_tsgs<V, R, true>), g, bw, full, s, nullptr, nullptr, Dh[L.direct.d], L.direct,
+                             L.aux & 1, C, NC);
         else
-          hipLaunchKernelGGL((kb_tsgs<V, R, false>), g, bw, full, s, t, D, BDesc{}, Item{}, L.aux, C, NC);
+          hipLaunchKernelGGL((kb_tsgs<V, R, false>), g, bw, full, s, t, D, BDesc{}, Item{}, L.aux & 1, C, NC);
         break;
       }
       const size_t lds = (size_t)T * R * sizeof(V);
       if (L.use_direct)
-        hipLaunchKernelGGL((kb_hsgs<V, R, true>), g, bw, lds, s, nullptr, nullptr, Dh[L.direct.d], L.direct, L.aux);
+        hipLaunchKernelGGL((kb_hsgs<V, R, true>), g, bw, lds, s, nullptr, nullptr, Dh[L.direct.d], L.direct,
+                           L.aux & 1);
       else
-        hipLaunchKernelGGL((kb_hsgs<V, R, false>), g, bw, lds, s, t, D, BDesc{}, Item{}, L.aux);
+        hipLaunchKernelGGL((kb_hsgs<V, R, false>), g, bw, lds, s, t, D, BDesc{}, Item{}, L.aux & 1);
     } break;
+    case OP_RESID_TILE: AMG_LAUNCH(kb_resid_tile, (V, R), L.aux); break;
     case OP_JACOBI: AMG_LAUNCH(kb_jacobi, (V, R)); break;
     case OP_BGS: AMG_LAUNCH(kb_bgs, (V, R)); break;
     case OP_RESTRICT: AMG_LAUNCH(kb_restrict, (V, R)); break;
@@ -1795,6 +1893,7 @@ void launch_r(const Launch& L, const Item* t, const BDesc* D, const BDesc* Dh, i
     case OP_RESID_OFF:
     case OP_HSGS:
     case OP_TSGS:
+    case OP_RESID_TILE:
     case OP_BGS:
     case OP_JACOBI:
     case OP_RESTRICT:
