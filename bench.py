@@ -3,9 +3,10 @@
 
 A step is one pass of the whole hot path on one synthetic system: amg_setup
 (strength, aggregation, Galerkin, colouring, coarse Cholesky), pcg_solve to
-relative residual 1e-8 with the plain FP64 method (FP64 V(1,1) multicolour
-symmetric Gauss-Seidel cycle inside FP64 CG, the paper's precision), and
-amg_free.  The workload is the heterogeneous 256^3 system: cell permeability
+relative residual 1e-8 with the plain FP64 method (FP64 V(1,1) cycle inside
+FP64 CG, the paper's precision; multicolour symmetric Gauss-Seidel on level
+0, the tile-ordered multicolour form of the paper's hybrid smoother on the
+coarser levels), and amg_free.  The workload is the heterogeneous 256^3 system: cell permeability
 K = exp(2 g') with g' a 2x2x2 box-filtered N(0,1) field (seed 1), 7-point
 cell-centred finite volumes with harmonic faces, RHS uniform[-1,1], x0 = 0.
 Inputs are resident in HBM before timing starts.
@@ -38,6 +39,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "AMG-PCG time-to-1e-8 & HBM GB/s at 256^3; solves/s + p99 latency (stream)"
+# Smoothing of the headline method: multicolour SGS on level 0, the hybrid
+# smoother of Sec. 3.2 with each tile's rows in colour order on levels >= 1
+# (one launch per sweep there instead of two per colour).
+HEAD = {"coarse_smoother": 3, "coarse_from": 1}
+HEAD_TEXT = "V(1,1): MC-SGS on level 0, tile-ordered MC-SGS (hybrid, Sec. 3.2, 128-row tiles) on levels >= 1"
 HBM_PEAK_GBS = 8000.0
 SWEEP_SOURCE = os.path.join(ROOT, "paper_1209_0960_amd", "csrc", "kernels_solve.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gs_fp64_hetero256.json")
@@ -81,8 +87,9 @@ def cpu_model() -> str:
 def cpu_baseline(sample_n: int):
     """The oracle (plain single-threaded C++, FP64 throughout) measured on the
     configuration-2 recipe (lognormal sigma^2 = 4, 2x2x2 box filter, seed 1)
-    at sample_n^3 with the headline's method (FP64 V(1,1) multicolour SGS in
-    PCG to 1e-8), the calling thread pinned to one host core.  Measured, not
+    at sample_n^3 with the headline's method (FP64 V(1,1) cycle with the
+    headline's smoothers, in PCG to 1e-8), the calling thread pinned to one
+    host core.  Measured, not
     scaled: the value is that workload's solves/s."""
     import oracle as O
     from paper_1209_0960_amd import problems as P
@@ -93,7 +100,7 @@ def cpu_baseline(sample_n: int):
     os.sched_setaffinity(0, {core})
     try:
         t0 = time.perf_counter()
-        H = O.Hierarchy(s.rowptr, s.colind, s.vals)
+        H = O.Hierarchy(s.rowptr, s.colind, s.vals, **HEAD)
         t1 = time.perf_counter()
         out = H.pcg(s.b, rtol=1e-8)
         t2 = time.perf_counter()
@@ -107,7 +114,7 @@ def cpu_baseline(sample_n: int):
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle setup + FP64 PCG (FP64 V(1,1) MC-SGS) to 1e-8 on the configuration-2 recipe at "
+        "sample": (f"oracle setup + FP64 PCG (FP64 {HEAD_TEXT}) to 1e-8 on the configuration-2 recipe at "
                    f"{sample_n}^3 ({s.n} unknowns, lognormal sigma^2=4, seed 1), one thread pinned to core {core}: "
                    f"TB {t1 - t0:.2f} s, TS {t2 - t1:.2f} s, {out['iterations']} iterations, {levels} levels; "
                    f"measured at this size, not scaled"),
@@ -308,11 +315,11 @@ def large_section(A, P, n: int = 512, seed: int = 2):
     torch.cuda.synchronize()
     gen = time.perf_counter() - t
     out = {"workload": f"layered K {n}^3 (u_z ~ U[-3,3] per 4-cell z-layer times lognormal sigma=1, seed {seed}), "
-                       "FP32 V-cycle in FP64 flexible CG to 1e-8",
+                       f"FP32 cycle ({HEAD_TEXT}) in FP64 flexible CG to 1e-8",
            "unknowns": rp.numel() - 1, "nnz": ci.numel(), "generation_s": gen}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = A.Hierarchy(rp, ci, v, vcycle_fp32=1)
+    h = A.Hierarchy(rp, ci, v, vcycle_fp32=1, **HEAD)
     x, r = h.solve(b, rtol=1e-8, maxit=500)
     torch.cuda.synchronize()
     out.update(time_to_1e8_ms=(time.perf_counter() - t0) * 1e3, setup_ms=r.setup_ms, solve_ms=r.solve_ms,
@@ -333,7 +340,7 @@ def large_section(A, P, n: int = 512, seed: int = 2):
     h.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h64 = A.Hierarchy(rp, ci, v, vcycle_fp32=0)
+    h64 = A.Hierarchy(rp, ci, v, vcycle_fp32=0, **HEAD)
     x64, r64 = h64.solve(b, rtol=1e-8, maxit=500)
     torch.cuda.synchronize()
     out["plain_fp64"] = {"time_to_1e8_ms": (time.perf_counter() - t0) * 1e3, "iterations": r64.iterations}
@@ -350,6 +357,33 @@ def large_section(A, P, n: int = 512, seed: int = 2):
     return out
 
 
+def mcsgs_all_levels(A, args, rp, ci, v, b, timed, infos, ms_per_step):
+    """The headline method with the multicolour smoother on every level,
+    timed like the headline, and the event-timed time of all launches of
+    levels >= 1 per V-cycle for both smoothings (one more solve each)."""
+    _, cinfos, per_mc, ms_mc, _ = timed(False, "plain-fp64-mcsgs-all-levels", smoothing={})
+    coarse = {}
+    for key, sm in (("headline", HEAD), ("mcsgs_all_levels", {})):
+        hc = A.Hierarchy(rp, ci, v, vcycle_fp32=0, **sm)
+        A.set_kernel_timing([A.KIND_COARSE_LEVELS])
+        A.reset_kernel_timing()
+        _, rc = hc.solve(b)
+        A.set_kernel_timing(False)
+        hc.close()
+        cms, cl, _ = A.kernel_timing(A.KIND_COARSE_LEVELS)
+        coarse[key] = {"ms_per_vcycle": cms / max(rc.iterations, 1), "launches_per_vcycle": cl / max(rc.iterations, 1)}
+    lc = cinfos[-1]
+    mcsgs_all = {"method": "V(1,1) MC-SGS on every level, plain FP64 PCG to 1e-8", "ms_per_step": ms_mc,
+                 "step_ms_min": min(per_mc), "step_ms_max": max(per_mc), "setup_ms": lc.setup_ms,
+                 "solve_ms": lc.solve_ms, "iterations": lc.iterations, "true_rel_residual": lc.true_rel_residual,
+                 "headline_speedup": ms_mc / ms_per_step,
+                 "headline_solve_speedup": lc.solve_ms / infos[-1].solve_ms,
+                 "coarse_levels_event_timed": coarse}
+    log(f"mcsgs on all levels: {ms_mc:.1f} ms/step (solve {lc.solve_ms:.1f} ms, it={lc.iterations}); "
+        f"coarse levels per V-cycle {coarse}")
+    return mcsgs_all
+
+
 def extra_sections(args, A, P, torch, step, timed, x_plain, ms_per_step):
     """config.mixed (FP32 cycle, timed like the headline), config.c1 (32^3
     Poisson) and config.c2 (128^3 heterogeneous, plain against mixed)."""
@@ -364,7 +398,7 @@ def extra_sections(args, A, P, torch, step, timed, x_plain, ms_per_step):
     err_plain = float(torch.linalg.norm(x_plain - x_ref) / nref)
     lm = minfos[-1]
     extra["mixed"] = {
-        "method": "FP32 V(1,1) MC-SGS cycle (FP32 values, vectors and accumulation on levels above the "
+        "method": f"FP32 cycle ({HEAD_TEXT}; FP32 values, vectors and accumulation on levels above the "
                   "coarsest) inside FP64 flexible CG (Polak-Ribiere beta), to 1e-8",
         "ms_per_step": ms_mixed, "solves_per_s": 1e3 / ms_mixed, "steps": args.steps, "warmup": args.warmup,
         "step_ms_min": min(per_mixed), "step_ms_max": max(per_mixed),
@@ -388,7 +422,7 @@ def extra_sections(args, A, P, torch, step, timed, x_plain, ms_per_step):
         _, r1, lev1 = step(False, system=d1)
         torch.cuda.synchronize()
         t1s.append((time.perf_counter() - a) * 1e3)
-    h1 = A.Hierarchy(*d1[:3], vcycle_fp32=0)
+    h1 = A.Hierarchy(*d1[:3], vcycle_fp32=0, **HEAD)
     A.set_kernel_timing(True)
     A.reset_kernel_timing()
     _, r1t = h1.solve(d1[3])
@@ -396,7 +430,7 @@ def extra_sections(args, A, P, torch, step, timed, x_plain, ms_per_step):
     h1.close()
     launches = sum(A.kernel_timing(k)[1] for k in range(7))
     extra["c1"] = {"workload": "Poisson K=1 32^3 (32768 unknowns, 223232 nnz), b U[-1,1] seed 0, plain FP64 "
-                               "V(1,1) MC-SGS PCG to 1e-8",
+                               f"PCG to 1e-8, {HEAD_TEXT}",
                    "time_to_1e8_ms": float(np.median(t1s[1:])), "setup_ms": r1.setup_ms, "solve_ms": r1.solve_ms,
                    "iterations": r1.iterations, "levels": lev1, "true_rel_residual": r1.true_rel_residual,
                    "solve_launches_per_iteration": launches / max(r1t.iterations, 1)}
@@ -481,26 +515,26 @@ def main():
     rp, ci, v, b = A.to_device(s)
     torch.cuda.synchronize()
 
-    def step(fp32: bool, x=None, rtol=1e-8, system=None):
+    def step(fp32: bool, x=None, rtol=1e-8, system=None, smoothing=HEAD):
         srp, sci, sv, sb = system if system is not None else (rp, ci, v, b)
-        h = A.Hierarchy(srp, sci, sv, vcycle_fp32=1 if fp32 else 0)
+        h = A.Hierarchy(srp, sci, sv, vcycle_fp32=1 if fp32 else 0, **smoothing)
         x, r = h.solve(sb, x, rtol=rtol)
         levels = h.levels
         h.close()
         return x, r, levels
 
-    def timed(fp32: bool, label: str):
+    def timed(fp32: bool, label: str, smoothing=HEAD):
         """args.warmup untimed steps, then args.steps steps between two device
         synchronisations; per-step wall times give the spread."""
         for w in range(args.warmup):
-            _, r, _ = step(fp32)
+            _, r, _ = step(fp32, smoothing=smoothing)
             log(f"{label} warmup {w}: setup {r.setup_ms:.1f} ms solve {r.solve_ms:.1f} ms it={r.iterations}")
         infos, per = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
             a = time.perf_counter()
-            x, r, levels = step(fp32)
+            x, r, levels = step(fp32, smoothing=smoothing)
             per.append((time.perf_counter() - a) * 1e3)
             infos.append(r)
         torch.cuda.synchronize()
@@ -519,7 +553,7 @@ def main():
     # ran).  Algorithmic bytes of a level-0 colour pass by the survey's
     # count: 12 B per stored entry of the colour's rows (value + column) and
     # 28 B per row (row pointer, b, x read, x written).
-    h = A.Hierarchy(rp, ci, v, vcycle_fp32=0)
+    h = A.Hierarchy(rp, ci, v, vcycle_fp32=0, **HEAD)
     col0 = np.zeros(s.n, np.int32)
     A._check(A.lib().amg_copy_level(h.h, 0, None, col0.ctypes.data_as(A.C.c_void_p), None, None, None, None, None))
     rows_c = np.bincount(col0)
@@ -530,10 +564,18 @@ def main():
     A.set_kernel_timing(False)
     h.close()
     sweep_ms, sweep_launches, sweep_bytes = A.kernel_timing(A.KIND_SWEEP)
+
     log(f"event-timed step: solve {rt.solve_ms:.1f} ms, {sweep_launches} sweep launches, colours {rows_c.tolist()}")
     # the kb_gs passes of a V(1,1) cycle on two colours: pre colour 1, post colours 0, 1, 0
     survey_pass = [12.0 * nnz_c[c] + 28.0 * rows_c[c] for c in range(len(rows_c))]
     survey_bytes = float(np.mean(survey_pass)) if len(rows_c) == 2 else float(12.0 * s.nnz + 28.0 * s.n) / len(rows_c)
+
+    # The same method with the multicolour smoother on every level, timed
+    # the same way, and the event-timed time of all launches of levels >= 1
+    # per V-cycle for both (one more solve each); not in profiler runs.
+    mcsgs_all = None
+    if not args.only_headline:
+        mcsgs_all = mcsgs_all_levels(A, args, rp, ci, v, b, timed, infos, ms_per_step)
 
     extra = {"step_ms_min": min(per_plain), "step_ms_max": max(per_plain)}
     if args.only_headline:
@@ -662,7 +704,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"lognormal-K 7-point CCFV {n}^3 (sigma^2=4, 2x2x2 box filter, seed 1), plain FP64: "
-                        f"V(1,1) MC-SGS cycle in PCG to rtol 1e-8 (setup + solve + free per step)",
+                        f"{HEAD_TEXT}, in PCG to rtol 1e-8 (setup + solve + free per step)",
             "unknowns": s.n, "nnz": s.nnz, "levels": levels, "iterations": last.iterations,
             "setup_ms": last.setup_ms, "solve_ms": last.solve_ms, "time_to_1e8_ms": ms_per_step,
             "true_rel_residual": last.true_rel_residual, "parallelism": "single GPU",
@@ -687,6 +729,8 @@ def main():
         },
     }
     out["config"].update(extra)
+    if mcsgs_all is not None:
+        out["config"]["mcsgs_all_levels"] = mcsgs_all
     if args.block_n > 0:
         log(f"block section (coupled 3-component {args.block_n}^3) ...")
         out["block"] = block_section(A, P, args.block_n)

@@ -466,8 +466,14 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     if (bs > 1) block_inverses(H, L, bs, f32, s);
     build_sell(H, l, s);
     if (tile_sweeps(L.sm)) {
-      hybrid_steps(H, L, p.tile_rows, s);
       tile_couplings(H, L, f32, s);
+      // Wavefront steps: for the hybrid smoother, and on colour-ordered
+      // levels for the sweeps that use them (the one-workgroup tail, levels
+      // of 64 colours or more, tiles whose staged sweep exceeds 64 KiB of
+      // LDS at 8 right-hand sides); the colour-by-colour sweeps need none.
+      const bool steps = L.sm == AMG_SMOOTHER_HYBRID_SGS || p.tail_rows > 0 || L.tncol >= 64 ||
+                         tsgs_lds_bytes(L.T, std::max(L.icmax, 1), 8, L.tncol, 8) > 65536;
+      if (steps) hybrid_steps(H, L, p.tile_rows, s);
     }
     L.sptr_d = H.alloc<int>(L.sptr.size(), s);
     AMG_HIP(hipMemcpyAsync(L.sptr_d, L.sptr.data(), L.sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));

@@ -402,6 +402,19 @@ enum {
   OP_RESID_TILE, // tile-sweep level: t = b - A x from the compact couplings (rows; aux = 1: in-tile sums in t)
 };
 
+// LDS bytes of the LDS-staged colour-ordered tile sweep (tiles of T rows, at
+// most C in-tile couplings per tile, R right-hand sides, NC colours, values
+// of vb bytes): iterate, source, diagonal; coupling offsets and colour
+// bounds (int); then, 8-byte aligned, the couplings' values and 16-bit local
+// columns.
+__host__ __device__ inline size_t tsgs_fixed_bytes(int T, int R, int NC, size_t vb) {
+  const size_t b = (size_t)T * (2 * R + 1) * vb + (size_t)(T + 1 + NC + 1) * sizeof(int);
+  return (b + 7) & ~(size_t)7;
+}
+__host__ __device__ inline size_t tsgs_lds_bytes(int T, int C, int R, int NC, size_t vb) {
+  return tsgs_fixed_bytes(T, R, NC, vb) + (size_t)C * (vb + sizeof(unsigned short));
+}
+
 // LDS bytes and eligibility of the register form of the colour-ordered tile
 // sweep (one thread per row, tiles of at most 256 rows, at most 32 in-tile
 // couplings per row W, at most C per tile, one right-hand side).

@@ -2115,10 +2115,6 @@ void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s) {
   read_ints(s, {{&L.hdf, mx.as<int>()}, {&L.hdb, mx.as<int>() + 1}, {&bad, mx.as<int>() + 2}, {&L.hw, mx.as<int>() + 3}});
   if (bad) fail(AMG_ERR_HIP, "hybrid smoother step relaxation did not converge");
   if (std::max(L.hdf, L.hdb) >= 0xffff || L.hw >= 0xffff) fail(AMG_ERR_UNSUPPORTED, "hybrid smoother tile too deep");
-  // rows with many in-tile couplings are summed by groups of lanes, except on
-  // levels of the tile-ordered multicolour smoother (one lane per row:
-  // the register form of its sweep keeps each row's couplings in one lane)
-  L.hg = L.hw > 8 && !L.tcb ? HS_G : 1;
 }
 
 // In-tile (ext = 0) or other-tile (ext = 1) couplings of row i (one thread
@@ -2127,7 +2123,7 @@ void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s) {
 __global__ void k_tile_rows(int n, int T, int ext, const int* __restrict__ soff, const int* __restrict__ scol,
                             const double* __restrict__ sval, const int* __restrict__ ptr, int* __restrict__ cnt,
                             unsigned short* __restrict__ col16, int* __restrict__ col32, double* __restrict__ v64,
-                            float* __restrict__ v32) {
+                            float* __restrict__ v32, int* __restrict__ cmax) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int lo = i - i % T, hi = min(n, lo + T);
@@ -2145,7 +2141,10 @@ __global__ void k_tile_rows(int n, int T, int ext, const int* __restrict__ soff,
     }
     ++c;
   }
-  if (!ptr) cnt[i] = c;
+  if (!ptr) {
+    cnt[i] = c;
+    if (cmax) atomicMax(cmax, c);
+  }
 }
 
 __global__ void k_ic_tile_max(int n, int T, int ntiles, const int* __restrict__ icp, int* __restrict__ mx) {
@@ -2156,11 +2155,12 @@ __global__ void k_ic_tile_max(int n, int T, int ntiles, const int* __restrict__ 
 
 void tile_couplings(Hierarchy& H, Level& L, bool f32, hipStream_t s) {
   const int n = L.n, T = L.T, g = cdiv(n, 256);
-  DBuf cnt((size_t)n * sizeof(int), s);
+  DBuf cnt((size_t)n * sizeof(int), s), mx(2 * sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), s));
   for (int ext = 0; ext < 2; ++ext) {
     int*& ptr = ext ? L.ocp : L.icp;
     hipLaunchKernelGGL(k_tile_rows, dim3(g), dim3(256), 0, s, n, T, ext, L.soff, L.scol, L.sval, nullptr,
-                       cnt.as<int>(), nullptr, nullptr, nullptr, nullptr);
+                       cnt.as<int>(), nullptr, nullptr, nullptr, nullptr, ext ? nullptr : mx.as<int>() + 1);
     ptr = H.alloc<int>((size_t)n + 1, s);
     exclusive_scan(cnt.as<int>(), ptr, n, s);
     const int tot = read1(ptr + n, s);
@@ -2174,15 +2174,17 @@ void tile_couplings(Hierarchy& H, Level& L, bool f32, hipStream_t s) {
     else
       v64 = (ext ? L.ocv : L.icv) = H.alloc<double>(m, s);
     hipLaunchKernelGGL(k_tile_rows, dim3(g), dim3(256), 0, s, n, T, ext, L.soff, L.scol, L.sval, ptr, nullptr, c16,
-                       c32, v64, v32);
+                       c32, v64, v32, nullptr);
     (ext ? L.ocn : L.icn) = tot;
   }
-  DBuf mx(sizeof(int), s);
-  AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), s));
   const int ntiles = cdiv(n, T);
   hipLaunchKernelGGL(k_ic_tile_max, dim3(cdiv(ntiles, 256)), dim3(256), 0, s, n, T, ntiles, L.icp, mx.as<int>());
   AMG_HIP(hipGetLastError());
-  L.icmax = read1(mx.as<int>(), s);
+  read_ints(s, {{&L.icmax, mx.as<int>()}, {&L.hw, mx.as<int>() + 1}});
+  // rows with many in-tile couplings are summed by groups of lanes, except on
+  // levels of the tile-ordered multicolour smoother (one lane per row:
+  // the register form of its sweep keeps each row's couplings in one lane)
+  L.hg = L.hw > 8 && !L.tcb ? HS_G : 1;
 }
 
 void cast_f32(const double* in, float* out, size_t n, hipStream_t s) {

@@ -817,18 +817,6 @@ __global__ __launch_bounds__(WAVE) void kb_hsgs_lds(AMG_KARGS, int from_b, int W
   AMG_BODY((kb_hsgs_lds_body<V, R>), from_b, W, S, C)
 }
 
-// LDS bytes of the colour-ordered tile sweep: iterate, source, diagonal (V);
-// coupling offsets and colour bounds (int); then, 8-byte aligned, the
-// couplings' values (V) and local columns (16 bit).
-__host__ __device__ inline size_t tsgs_fixed_bytes(int T, int R, int NC, size_t vb) {
-  const size_t b = (size_t)T * (2 * R + 1) * vb + (size_t)(T + 1 + NC + 1) * sizeof(int);
-  return (b + 7) & ~(size_t)7;
-}
-template <typename V>
-__host__ __device__ inline size_t tsgs_lds_bytes(int T, int C, int R, int NC) {
-  return tsgs_fixed_bytes(T, R, NC, sizeof(V)) + (size_t)C * (sizeof(V) + sizeof(unsigned short));
-}
-
 // The tile-ordered multicolour smoother on one tile (one wavefront, it.lo =
 // tile): the level's solve order takes each tile's rows colour by colour, so
 // the rows of a colour are one contiguous range and the sweeps go colour by
@@ -1845,7 +1833,7 @@ void launch_cycle_op(const Launch& L, const Item* t, const BDesc* D, const BDesc
 #undef AMG_TSGS_REG
         break;
       }
-      const size_t full = tsgs_lds_bytes<V>(T, C, R, NC);
+      const size_t full = tsgs_lds_bytes(T, C, R, NC, sizeof(V));
       if (full <= 65536) {
         if (L.use_direct)
           hipLaunchKernelGGL((kb_tsgs<V, R, true>), g, bw, full, s, nullptr, nullptr, Dh[L.direct.d], L.direct,
