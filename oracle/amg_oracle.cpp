@@ -537,6 +537,32 @@ int colour_rows(const Csr& A, int T, uint32_t s, std::vector<int>& colour) {
   return ncol;
 }
 
+// Colouring of the tile-ordered multicolour smoother (not in the paper): each
+// tile of T consecutive rows is coloured on its own, first fit over its rows
+// in ascending order, looking only at couplings inside the tile (the smoother
+// is block-Jacobi across tiles, so a colouring proper inside every tile
+// orders each tile's sweep).  Returns the number of colours.
+int colour_tile_local(const Csr& A, int T, std::vector<int>& colour) {
+  const int n = A.n;
+  colour.assign(n, -1);
+  int ncol = 0;
+  for (int lo = 0; lo < n; lo += T) {
+    const int hi = std::min(n, lo + T);
+    for (int i = lo; i < hi; ++i) {
+      std::set<int> used;
+      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        const int j = A.col[k];
+        if (j != i && j >= lo && j < hi && colour[j] >= 0) used.insert(colour[j]);
+      }
+      int c = 0;
+      while (used.count(c)) ++c;
+      colour[i] = c;
+      ncol = std::max(ncol, c + 1);
+    }
+  }
+  return ncol;
+}
+
 // ---------------------------------------------------------------------------
 // Dense FP64 Cholesky (Cholesky-Banachiewicz, lower triangle of A is read)
 // for the coarsest level (the paper factorises it with a sparse direct solver).
@@ -958,6 +984,8 @@ bool finish_level(Level& L, const Params& p, int l) {
   } else if (smoother_of(p, l) == SMOOTH_HYBRID) {  // no multicolouring: one colour, natural order
     L.colour.assign(L.A.n, 0);
     L.ncol = 1;
+  } else if (smoother_of(p, l) == SMOOTH_TILE_MCSGS) {
+    L.ncol = colour_tile_local(L.A, p.tile_rows, L.colour);
   } else {
     L.ncol = colour_rows(L.A, p.colour_tile_rows, p.colour_seed + (uint32_t)l, L.colour);
   }

@@ -430,8 +430,8 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     H.lev[l].sm = level_smoother(p, l);
     if (H.lev[l].sm == AMG_SMOOTHER_HYBRID_SGS) {
       colour_single(H, H.lev[l], s);
-    } else if (H.lev[l].sm == AMG_SMOOTHER_TILE_MCSGS) {  // colours set the sweep order inside a tile
-      colour(H, H.lev[l], p.colour_seed + (uint32_t)l, s);
+    } else if (H.lev[l].sm == AMG_SMOOTHER_TILE_MCSGS) {  // tile-local colours set the sweep order inside a tile
+      colour_tile_local(H, H.lev[l], s);
       tile_colour_order(H, H.lev[l], l < Lc, s);
     } else if (bs > 1) {  // node colours, shared by each node's unknowns
       Level S;

@@ -269,7 +269,11 @@ void colour_single(Hierarchy& H, Level& L, hipStream_t s);
 // Wavefront steps of the in-tile sweeps of the hybrid smoother (after
 // build_sell; the level has one colour).
 void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s);
-// After colour() on a level of the tile-ordered multicolour smoother: the
+// Colouring of a level of the tile-ordered multicolour smoother: every tile
+// of L.T rows on its own, first fit over its rows ascending on the couplings
+// inside the tile (natural order, before relabelling).
+void colour_tile_local(Hierarchy& H, Level& L, hipStream_t s);
+// After colour_tile_local on a level of the tile-ordered multicolour smoother: the
 // solve order takes each tile's rows colour by colour (reorder; the coarsest
 // level keeps natural order), one colour for the slices, the colours in
 // L.tcol (solve order) and each tile's colour bounds in L.tcb.

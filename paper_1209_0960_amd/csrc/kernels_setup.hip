@@ -2052,6 +2052,76 @@ __global__ __launch_bounds__(64) void k_hybrid_steps(int n, int T, const int* __
   }
 }
 
+// Colouring of a level of the tile-ordered multicolour smoother: each tile of
+// T rows (natural order) on its own, first fit over its rows in ascending
+// order on the couplings inside the tile (one wavefront per tile).  A row
+// takes its colour once every earlier coupled row of the tile has one, so
+// rows are coloured in rounds; the result is the sequential first fit.
+// mx[0]: most colours, mx[1]: set when a row would need more than 256.
+constexpr int TL_MAXC = 256;
+__global__ __launch_bounds__(64) void k_colour_tile_local(int n, int T, const int* __restrict__ rowptr,
+                                                          const int* __restrict__ colind, int* __restrict__ colour,
+                                                          int* __restrict__ mx) {
+  __shared__ int cl[HS_MAX_T];
+  const int lo = (int)blockIdx.x * T, hi = min(n, lo + T), nt = hi - lo;
+  const int lane = (int)threadIdx.x;
+  for (int q = lane; q < nt; q += 64) cl[q] = -1;
+  __syncthreads();
+  for (int round = 0; round <= nt; ++round) {
+    bool left = false;
+    for (int q = lane; q < nt; q += 64) {
+      if (cl[q] >= 0) continue;
+      const int i = lo + q;
+      unsigned long long used[TL_MAXC / 64] = {0, 0, 0, 0};
+      bool ready = true;
+      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int j = colind[k];
+        if (j < lo || j >= i) continue;
+        const int c = cl[j - lo];
+        if (c < 0) {
+          ready = false;
+          break;
+        }
+        used[c >> 6] |= 1ull << (c & 63);
+      }
+      if (!ready) {
+        left = true;
+        continue;
+      }
+      int c = 0;
+      while (c < TL_MAXC && ((used[c >> 6] >> (c & 63)) & 1ull)) ++c;
+      if (c == TL_MAXC) {
+        atomicOr(mx + 1, 1);
+        c = TL_MAXC - 1;
+      }
+      cl[q] = c;
+    }
+    __syncthreads();
+    if (!__ballot(left)) break;
+  }
+  int cmax = 0;
+  for (int q = lane; q < nt; q += 64) {
+    colour[lo + q] = cl[q];
+    cmax = max(cmax, cl[q] + 1);
+  }
+  cmax = wave_max(cmax);
+  if (lane == 0) atomicMax(mx, cmax);
+}
+
+void colour_tile_local(Hierarchy& H, Level& L, hipStream_t s) {
+  const int n = L.n, T = L.T, ntiles = cdiv(n, T);
+  if (T > HS_MAX_T) fail(AMG_ERR_UNSUPPORTED, "tile sweeps take tiles of at most 1024 rows");
+  L.colour = H.alloc<int>((size_t)n, s);
+  DBuf mx(2 * sizeof(int), s);
+  AMG_HIP(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), s));
+  hipLaunchKernelGGL(k_colour_tile_local, dim3(ntiles), dim3(64), 0, s, n, T, L.rowptr, L.colind, L.colour,
+                     mx.as<int>());
+  AMG_HIP(hipGetLastError());
+  int bad = 0;
+  read_ints(s, {{&L.ncol, mx.as<int>()}, {&bad, mx.as<int>() + 1}});
+  if (bad) fail(AMG_ERR_UNSUPPORTED, "a tile row needs more than 256 colours");
+}
+
 // Rows of each tile of T rows grouped by colour (one wavefront per tile,
 // ballot compaction, colour by colour, ascending row inside a colour): the
 // solve order, the colour of each solve row, and each tile's colour bounds

@@ -341,6 +341,34 @@ def test_colouring_proper_and_first_fit():
             assert c[i] == min(set(range(len(nb) + 1)) - used)
 
 
+@pytest.mark.parametrize("T", [64, 100, 128])
+def test_tile_local_colouring_first_fit(T):
+    """Levels of the tile-ordered multicolour smoother are coloured tile by
+    tile: proper on every coupling inside a tile, and each row's colour is the
+    smallest one missing among the earlier rows of its tile it is coupled to
+    (brute force on the output of a hierarchy's coarse levels); couplings
+    between tiles do not constrain it (some such pair shares a colour)."""
+    s = P.lognormal(16, seed=4)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, coarse_max=40, tile_rows=T, coarse_smoother=3, coarse_from=1)
+    assert H.levels >= 3
+    shared_across = 0
+    for l in range(1, H.levels - 1):
+        L = H.level(l)
+        c = L.colour
+        assert c.max() == L.ncol - 1
+        for i in range(L.n):
+            lo = i - i % T
+            nb = L.colind[L.rowptr[i]:L.rowptr[i + 1]]
+            inside = nb[(nb != i) & (nb >= lo) & (nb < lo + T)]
+            assert not np.any(c[inside] == c[i])
+            earlier = inside[inside < i]
+            used = set(c[earlier].tolist())
+            assert c[i] == min(set(range(len(earlier) + 1)) - used)
+            outside = nb[(nb < lo) | (nb >= lo + T)]
+            shared_across += int(np.sum(c[outside] == c[i]))
+    assert shared_across > 0
+
+
 def test_colouring_is_parity_on_aligned_morton_tiles():
     """7-point graph, edges multiples of 8, 512-row tiles (aligned 8^3 Morton
     cubes): every cell except a tile's first has an in-tile neighbour earlier in
