@@ -1141,11 +1141,21 @@ __device__ __forceinline__ void kb_restrict_body(const Item& it, const BDesc& d)
   V s[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) s[k] = 0;
-  for (int p = d.mptr[I]; p < d.mptr[I + 1]; ++p) {
-    V tv[R];
-    ldv<V, R>(t + (size_t)d.members[p] * R, tv);
+  // members eight at a time: their indices, then their residuals, in flight
+  // together; the sum keeps the member order
+  const int p1 = d.mptr[I + 1];
+  for (int p0 = d.mptr[I]; p0 < p1; p0 += 8) {
+    int m[8];
+    V tv[8][R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) s[k] += tv[k];
+    for (int u = 0; u < 8; ++u) m[u] = d.members[min(p0 + u, p1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ldv<V, R>(t + (size_t)m[u] * R, tv[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (p0 + u < p1)
+#pragma unroll
+        for (int k = 0; k < R; ++k) s[k] += tv[u][k];
   }
   stv<V, R>(static_cast<V*>(d.bc) + (size_t)(d.cinv ? d.cinv[I] : I) * R, s);
 }
