@@ -66,12 +66,12 @@ typedef struct amg_csr {
  * l1-Jacobi; the paper's hybrid symmetric Gauss-Seidel (Sec. 3.2: block-
  * Jacobi over the tiles of tile_rows rows, one sequential forward + backward
  * Gauss-Seidel sweep inside each tile, levels kept in natural order); the
- * same hybrid form with each tile's rows swept in the order of the level's
- * multicolouring (colour, then row; levels kept in natural order), which
- * runs a level's whole symmetric step in one launch: one workgroup per tile,
- * at most one wavefront step per colour and direction (for coarse levels,
- * where the multicolour smoother's two launches per colour are latency
- * bound). */
+ * same hybrid form with each tile's rows swept colour by colour (colour, then
+ * row; the colours a first-fit colouring of each tile on its own, rows
+ * ascending, couplings inside the tile only), which runs a level's whole
+ * symmetric step in one launch: one workgroup per tile, one step per colour
+ * and direction (for coarse levels, where the multicolour smoother's two
+ * launches per colour are latency bound). */
 enum {
   AMG_SMOOTHER_MCSGS = 0,
   AMG_SMOOTHER_L1_JACOBI = 1,
@@ -103,7 +103,8 @@ typedef struct amg_params {
                                 larger ones launch directly, which is as fast) */
   int32_t tail_rows;         /* levels with at most this many rows (and all    [0]
                                 coarser ones) are cycled by one workgroup per solve */
-  int32_t colour_tile_rows;  /* rows per tile of the colouring order (64..1024) [128] */
+  int32_t colour_tile_rows;  /* rows per tile of the colouring order of the    [128]
+                                multicolour levels (64..1024)                      */
   int32_t block_size;        /* unknowns per node, 1..4 (point-based AMG for    [1]
                                 systems, Sec. 4.2): A is given in scalar form with
                                 node i's unknowns in rows i*bs .. i*bs+bs-1 and
