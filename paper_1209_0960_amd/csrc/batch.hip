@@ -919,6 +919,13 @@ void build_final(Builder& b, const Batch& B, const std::vector<int>& S) {
 void upload_plan(Plan& P, Builder& b, hipStream_t s) {
   P.drop_graph();
   P.L = std::move(b.L);
+  // Direct launches (the plans of one entry) take their ranges from the block
+  // index: the table is uploaded only if some launch reads it (a plan of a
+  // 256^3 system holds about 12 MB of items, which would cost a staged copy
+  // from pageable memory on every new hierarchy).
+  bool table = false;
+  for (const Launch& L : P.L) table = table || !L.use_direct;
+  if (!table) return;
   if (b.items.size() > P.cap) {
     if (P.tab_d) dfree(P.tab_d, s);
     P.cap = std::max(b.items.size(), (size_t)1024);
