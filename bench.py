@@ -180,8 +180,10 @@ def batched_section(A, P, nsys: int, nrhs: int = 4, seed: int = 3):
                      "rhs_interleave_ms": {str(k): v for k, v in table["R_ms"].items()},
                      "tuning_s": table["tuning_s"],
                      "variants": "tile_rows in {64,128,256,512} x tail_rows in {0, 8192, 2^30 (whole cycle in "
-                                 "one workgroup)} per size class, then the level-0 SpMV layout (SELL-64 or CSR "
-                                 "with lanes per row); right-hand sides per entry in {4,2,1}"},
+                                 "one workgroup)} x coarse smoother {MC-SGS, tile-ordered MC-SGS from level 1} "
+                                 "per size class (every timed variant in variants_ms), then the level-0 SpMV "
+                                 "layout (SELL-64 or CSR with lanes per row); right-hand sides per entry in "
+                                 "{4,2,1}"},
         "iterations_max": max(its), "iterations_mean": float(sum(its)) / len(its),
         "all_converged": tst == A.OK and dst == A.OK and all(i["converged"] for inf in tinf for i in inf)
                          and all(r.converged for r in linf),
@@ -198,13 +200,13 @@ def serving_section(A, P, seconds: float, rate: float):
 
     trace = P.serving_trace(rate=rate, seconds=seconds, seed=4)
     reqs, gen_s = S.requests_from_trace(trace)
-    srv = S.Server(cap_bytes=200e9, max_entries=32, setup_workers=2, vcycle_fp32=1)
+    srv = S.Server(cap_bytes=200e9, max_entries=32, setup_workers=2, vcycle_fp32=1, **HEAD)
     try:
         recs = srv.run(reqs)
         stats = dict(srv.stats)
     finally:
         srv.close()
-    base, bstats, _ = S.serve_serial(reqs, vcycle_fp32=0)
+    base, bstats, _ = S.serve_serial(reqs, vcycle_fp32=0, **HEAD)
     # a point below capacity: the latency of service rather than of queueing
     low_rate, low_seconds = rate / 10.0, 5.0 * seconds
     del reqs
@@ -212,7 +214,7 @@ def serving_section(A, P, seconds: float, rate: float):
     torch.cuda.empty_cache()
     ltrace = P.serving_trace(rate=low_rate, seconds=low_seconds, seed=5)
     lreqs, _ = S.requests_from_trace(ltrace)
-    lsrv = S.Server(cap_bytes=200e9, max_entries=32, setup_workers=2, vcycle_fp32=1)
+    lsrv = S.Server(cap_bytes=200e9, max_entries=32, setup_workers=2, vcycle_fp32=1, **HEAD)
     try:
         lrecs = lsrv.run(lreqs)
         lstats = dict(lsrv.stats)
@@ -232,8 +234,8 @@ def serving_section(A, P, seconds: float, rate: float):
         "served": {"solves_per_s": sm.solves_per_s, "p50_ms": sm.p50_ms, "p99_ms": sm.p99_ms,
                    "makespan_s": sm.makespan_s, "hits": sm.hits, "setups": sm.setups, "evictions": sm.evictions,
                    "max_running": sm.max_running, "peak_reserved_bytes": sm.peak_reserved_bytes,
-                   "policy": "continuous batching (32 slots), FP32 V-cycle + FP64 flexible CG, admission by "
-                             "estimated HBM footprint under 200 GB, LRU hierarchy cache"},
+                   "policy": f"continuous batching (32 slots), FP32 cycle ({HEAD_TEXT}) + FP64 flexible CG, "
+                             "admission by estimated HBM footprint under 200 GB, LRU hierarchy cache"},
         "serial_fp64": {"solves_per_s": sb.solves_per_s, "p50_ms": sb.p50_ms, "p99_ms": sb.p99_ms,
                         "makespan_s": sb.makespan_s, "hits": sb.hits, "setups": sb.setups},
         "throughput_ratio": sm.solves_per_s / sb.solves_per_s,

@@ -6,7 +6,9 @@ Three launch/layout variants are chosen by measurement on the GPU:
   aggregation tile (Alg. 4's unit of independent aggregation; it sets the
   setup's parallelism and per-tile latency, and the hierarchy it builds);
 * cycle variant, per size class: `tail_rows`, below which a system's levels
-  are cycled by one workgroup instead of one launch per colour pass;
+  are cycled by one workgroup instead of one launch per colour pass, and the
+  coarse-level smoother (the multicolour smoother on every level, or the
+  tile-ordered multicolour smoother from level 1 on);
 * SpMV variant, per size class: `spmv_format`, the layout of CG's level-0
   product (SELL-64 slices with one lane per row, or CSR with a group of lanes
   per row); per batch: R, the right-hand sides interleaved in one entry
@@ -33,8 +35,13 @@ from . import amg as A
 
 TILES = (64, 128, 256, 512)
 TAILS = (0, 8192, 1 << 30)
+COARSE = ({}, {"coarse_smoother": A.SMOOTHER_TILE_MCSGS, "coarse_from": 1})
 SPMV = (0, 1)
 RHS = (4, 2, 1)
+
+
+def _variant_name(tile, tail, coarse):
+    return f"tile_rows={tile},tail_rows={tail},coarse={'tile_mcsgs' if coarse else 'mcsgs'}"
 
 
 def _sync():
@@ -81,8 +88,9 @@ def run_batched(systems, params_of, nrhs: int, R: int, rtol: float = 1e-8, maxit
 
 
 def tune(systems, nrhs: int, sample: int = 4, reps: int = 2, **common) -> dict:
-    """Table {rows: {"tile_rows", "tail_rows", "ms"}} per size class, plus
-    {"R": best interleave, "R_ms": {R: ms}} for the whole batch."""
+    """Table {rows: {"tile_rows", "tail_rows", "coarse", "spmv_format", "ms",
+    "variants_ms"}} per size class (every timed variant kept), plus {"R": best
+    interleave, "R_ms": {R: ms}} for the whole batch."""
     by_class = defaultdict(list)
     for i, s in enumerate(systems):
         by_class[s[0].numel() - 1].append(i)
@@ -91,29 +99,33 @@ def tune(systems, nrhs: int, sample: int = 4, reps: int = 2, **common) -> dict:
     for rows, idx in sorted(by_class.items()):
         pick = [systems[i] for i in idx[:sample]]
         best = None
-        for tile, tail in itertools.product(TILES, TAILS):
+        variants = {}
+        for tile, tail, coarse in itertools.product(TILES, TAILS, COARSE):
             ms = float("inf")
             for _ in range(reps):
                 try:
-                    a, b, _, st, _ = run_batched(pick, lambda i: {"tile_rows": tile, "tail_rows": tail}, nrhs,
-                                                 nrhs, **common)
+                    a, b, _, st, _ = run_batched(pick, lambda i: {"tile_rows": tile, "tail_rows": tail, **coarse},
+                                                 nrhs, nrhs, **common)
                 except A.AMGError:  # e.g. a tile graph larger than the LDS
                     break
                 if st == A.OK:
                     ms = min(ms, (a + b) * 1e3)
-            if best is None or ms < best[2]:
-                best = (tile, tail, ms)
-        fmt, fms = 0, best[2]
+            variants[_variant_name(tile, tail, coarse)] = ms
+            if best is None or ms < best[3]:
+                best = (tile, tail, coarse, ms)
+        fmt, fms = 0, best[3]
         for f in SPMV[1:]:  # the SpMV layout with the chosen tile and cycle variants
             ms = float("inf")
             for _ in range(reps):
-                a, b, _, st, _ = run_batched(pick, lambda i: {"tile_rows": best[0], "tail_rows": best[1],
+                a, b, _, st, _ = run_batched(pick, lambda i: {"tile_rows": best[0], "tail_rows": best[1], **best[2],
                                                               "spmv_format": f}, nrhs, nrhs, **common)
                 if st == A.OK:
                     ms = min(ms, (a + b) * 1e3)
+            variants[_variant_name(best[0], best[1], best[2]) + f",spmv_format={f}"] = ms
             if ms < fms:
                 fmt, fms = f, ms
-        table[rows] = {"tile_rows": best[0], "tail_rows": best[1], "spmv_format": fmt, "ms": fms}
+        table[rows] = {"tile_rows": best[0], "tail_rows": best[1], "coarse": dict(best[2]), "spmv_format": fmt,
+                       "ms": fms, "variants_ms": variants}
 
     params_of = params_from(table, systems)
 
@@ -132,5 +144,6 @@ def tune(systems, nrhs: int, sample: int = 4, reps: int = 2, **common) -> dict:
 def params_from(table: dict, systems) -> callable:
     def params_of(i):
         c = table[systems[i][0].numel() - 1]
-        return {"tile_rows": c["tile_rows"], "tail_rows": c["tail_rows"], "spmv_format": c.get("spmv_format", 0)}
+        return {"tile_rows": c["tile_rows"], "tail_rows": c["tail_rows"], "spmv_format": c.get("spmv_format", 0),
+                **c.get("coarse", {})}
     return params_of
