@@ -1435,9 +1435,11 @@ __global__ __launch_bounds__(NT) void kb_update_p(AMG_KARGS, int zx) {
 }
 
 // q = A p (FP64, SELL slices [lo, hi), wavefront w takes lo + w, lo + w + 4, ...)
-// with partials of p.q.
-template <int R>
-__device__ __forceinline__ void kb_spmv_dot_body(const Item& it, const BDesc& d) {
+// with partials of p.q.  (STREAM: the level's entries and diagonal exceed the
+// last-level cache and are loaded with the non-temporal hint, as in the
+// colour passes.)
+template <int R, bool STREAM>
+__device__ __forceinline__ void kb_spmv_dot_body_t(const Item& it, const BDesc& d) {
   const int lane = __lane_id();
   double acc[R];
 #pragma unroll
@@ -1446,11 +1448,11 @@ __device__ __forceinline__ void kb_spmv_dot_body(const Item& it, const BDesc& d)
     const int r = d.srow[sl] + lane;
     const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
     double off[R];
-    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.p, off, d.nt != 0);
+    sell_offdiag_t<double, R, STREAM>(d.scol, d.sval64, base, w, lane, d.p, off);
     if (r < d.srow[sl + 1]) {
       double pr[R], y[R];
       ldv<double, R>(d.p + (size_t)r * R, pr);
-      const double dg = d.dg64[r];
+      const double dg = ld_stream<STREAM>(d.dg64 + r);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         y[k] = madd(dg, pr[k], off[k]);
@@ -1462,6 +1464,13 @@ __device__ __forceinline__ void kb_spmv_dot_body(const Item& it, const BDesc& d)
   block_sums<R>(acc);
   write_partials<R>(d, 0, it.part, acc);
 }
+template <int R>
+__device__ __forceinline__ void kb_spmv_dot_body(const Item& it, const BDesc& d) {
+  if (d.nt)
+    kb_spmv_dot_body_t<R, true>(it, d);
+  else
+    kb_spmv_dot_body_t<R, false>(it, d);
+}
 template <int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_spmv_dot(AMG_KARGS) {
   AMG_BODY((kb_spmv_dot_body<R>))
@@ -1469,8 +1478,8 @@ __global__ __launch_bounds__(NT) void kb_spmv_dot(AMG_KARGS) {
 
 // out = b - A x (FP64, SELL) with partials of out.out; out is r (which = 0)
 // or q (which = 1), b and x the entry's right-hand side and iterate.
-template <int R>
-__device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d, int which) {
+template <int R, bool STREAM>
+__device__ __forceinline__ void kb_resid_dot_body_t(const Item& it, const BDesc& d, int which) {
   const int lane = __lane_id();
   const bool b32 = (which & 2) != 0;
   double* out = (which & 1) ? d.q : d.r;
@@ -1481,12 +1490,12 @@ __device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d
     const int r = d.srow[sl] + lane;
     const int base = d.soff[sl], w = (d.soff[sl + 1] - base) >> 6;
     double off[R];
-    sell_offdiag<double, R>(d.scol, d.sval64, base, w, lane, d.xs, off, d.nt != 0);
+    sell_offdiag_t<double, R, STREAM>(d.scol, d.sval64, base, w, lane, d.xs, off);
     if (r < d.srow[sl + 1]) {
       double xr[R], br[R], o[R];
       ldv<double, R>(d.xs + (size_t)r * R, xr);
       ldv<double, R>(d.bs + (size_t)r * R, br);
-      const double dg = d.dg64[r];
+      const double dg = ld_stream<STREAM>(d.dg64 + r);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         o[k] = br[k] - madd(dg, xr[k], off[k]);
@@ -1498,6 +1507,13 @@ __device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d
   }
   block_sums<R>(acc);
   write_partials<R>(d, 0, it.part, acc);
+}
+template <int R>
+__device__ __forceinline__ void kb_resid_dot_body(const Item& it, const BDesc& d, int which) {
+  if (d.nt)
+    kb_resid_dot_body_t<R, true>(it, d, which);
+  else
+    kb_resid_dot_body_t<R, false>(it, d, which);
 }
 template <int R, bool DIRECT>
 __global__ __launch_bounds__(NT) void kb_resid_dot(AMG_KARGS, int which) {
