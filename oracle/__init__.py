@@ -33,7 +33,8 @@ class Params(C.Structure):
                 ("tile_rows", C.c_int), ("smoother", C.c_int), ("pre_sweeps", C.c_int),
                 ("post_sweeps", C.c_int), ("vcycle_fp32", C.c_int), ("flexible", C.c_int),
                 ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int), ("colour_tile_rows", C.c_int),
-                ("block_size", C.c_int), ("coarse_smoother", C.c_int), ("coarse_from", C.c_int)]
+                ("block_size", C.c_int), ("coarse_smoother", C.c_int), ("coarse_from", C.c_int),
+                ("smooth_tile_rows", C.c_int), ("coarse_smooth_tile_rows", C.c_int)]
 
 
 def default_params(**kw) -> Params:
@@ -41,7 +42,7 @@ def default_params(**kw) -> Params:
                agg_diameter=3, omega=1.6, coarse_max=500, max_levels=25, tile_rows=128,
                smoother=0, pre_sweeps=1, post_sweeps=1, vcycle_fp32=0, flexible=-1,
                colour_seed=0, check_symmetry=1, colour_tile_rows=128, block_size=1,
-               coarse_smoother=-1, coarse_from=1)
+               coarse_smoother=-1, coarse_from=1, smooth_tile_rows=0, coarse_smooth_tile_rows=0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

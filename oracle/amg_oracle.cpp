@@ -611,10 +611,15 @@ struct Params {
   int block_size;        // unknowns per node (point-based AMG for systems); 1: scalar
   int coarse_smoother;   // smoother of the levels from coarse_from on (-1: `smoother` on every level)
   int coarse_from;
+  // Blocks of the hybrid forms (Sec. 3.2: the matrices A_(p) of the block-
+  // Jacobi) above level coarse_from and from it on; 0: tile_rows, and the
+  // finer levels' size respectively.  They need not match the aggregation
+  // tiles.
+  int smooth_tile_rows, coarse_smooth_tile_rows;
 };
 
 // SMOOTH_TILE_MCSGS (not in the paper): the hybrid form of Sec. 3.2
-// (block-Jacobi over the tiles of tile_rows rows, one symmetric Gauss-Seidel
+// (block-Jacobi over tiles of smooth_tile() rows, one symmetric Gauss-Seidel
 // step inside each) with the rows of each tile taken in the order of the
 // level's multicolouring (colour, then row), meant for coarse levels.
 enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1, SMOOTH_HYBRID = 2, SMOOTH_TILE_MCSGS = 3 };
@@ -622,6 +627,12 @@ enum { SMOOTH_MCSGS = 0, SMOOTH_L1JACOBI = 1, SMOOTH_HYBRID = 2, SMOOTH_TILE_MCS
 // Smoother of level l.
 int smoother_of(const Params& p, int l) {
   return (p.coarse_smoother >= 0 && l >= p.coarse_from) ? p.coarse_smoother : p.smoother;
+}
+
+// Rows per block of the hybrid smoothers on level l.
+int smooth_tile(const Params& p, int l) {
+  const int fine = p.smooth_tile_rows > 0 ? p.smooth_tile_rows : p.tile_rows;
+  return (p.coarse_smooth_tile_rows > 0 && l >= p.coarse_from) ? p.coarse_smooth_tile_rows : fine;
 }
 
 struct Level {
@@ -861,9 +872,9 @@ void smooth(const Hier& H, int l, const V* b, V* x) {
     for (int c = L.ncol - 1; c >= 0; --c)  // backward sweep
       for (int i : L.rows_of_colour[c]) gs_row<V>(L.A, val, i, b, x);
   } else if (sm == SMOOTH_HYBRID) {
-    hybrid_sgs<V>(L.A, val, H.p.tile_rows, b, x);
+    hybrid_sgs<V>(L.A, val, smooth_tile(H.p, l), b, x);
   } else if (sm == SMOOTH_TILE_MCSGS) {
-    hybrid_sgs<V>(L.A, val, H.p.tile_rows, b, x, L.colour.data());
+    hybrid_sgs<V>(L.A, val, smooth_tile(H.p, l), b, x, L.colour.data());
   } else {
     // l1-Jacobi (Baker, Falgout, Kolev, Yang 2011, pointwise): x += (b - A x) / d
     const int n = L.A.n;
@@ -985,7 +996,7 @@ bool finish_level(Level& L, const Params& p, int l) {
     L.colour.assign(L.A.n, 0);
     L.ncol = 1;
   } else if (smoother_of(p, l) == SMOOTH_TILE_MCSGS) {
-    L.ncol = colour_tile_local(L.A, p.tile_rows, L.colour);
+    L.ncol = colour_tile_local(L.A, smooth_tile(p, l), L.colour);
   } else {
     L.ncol = colour_rows(L.A, p.colour_tile_rows, p.colour_seed + (uint32_t)l, L.colour);
   }
@@ -1006,7 +1017,8 @@ int build(Hier& H, const Csr& A0) {
   const Params& p = H.p;
   const int bs = p.block_size;
   if (p.smoother < 0 || p.smoother > SMOOTH_TILE_MCSGS || p.coarse_smoother < -1 ||
-      p.coarse_smoother > SMOOTH_TILE_MCSGS || (p.coarse_smoother >= 0 && p.coarse_from < 1))
+      p.coarse_smoother > SMOOTH_TILE_MCSGS || p.smooth_tile_rows < 0 || p.coarse_smooth_tile_rows < 0 ||
+      ((p.coarse_smoother >= 0 || p.coarse_smooth_tile_rows > 0) && p.coarse_from < 1))
     return ORC_INVALID;
   if (bs > 1 && (bs > 16 || p.smoother != SMOOTH_MCSGS || (p.coarse_smoother >= 0 && p.coarse_smoother != SMOOTH_MCSGS) ||
                  !block_structure_ok(A0, bs)))
@@ -1082,6 +1094,7 @@ struct orc_params {
   int colour_tile_rows;
   int block_size;
   int coarse_smoother, coarse_from;
+  int smooth_tile_rows, coarse_smooth_tile_rows;
 };
 
 static Params to_params(const orc_params* q) {
@@ -1106,6 +1119,8 @@ static Params to_params(const orc_params* q) {
   p.block_size = q->block_size < 1 ? 1 : q->block_size;
   p.coarse_smoother = q->coarse_smoother;
   p.coarse_from = q->coarse_from;
+  p.smooth_tile_rows = q->smooth_tile_rows;
+  p.coarse_smooth_tile_rows = q->coarse_smooth_tile_rows;
   return p;
 }
 

@@ -100,9 +100,11 @@ def paper_cycle(H, A0, omega, smoother, pre, post, tile_rows):
     aggregates and the colours of each level are taken from the hierarchy
     (both are pinned on their own); every operator is formed here.
     smoother: one smoother for every level, or a list with one per level
-    (0 MC-SGS, 1 l1-Jacobi, 2 hybrid SGS, 3 hybrid SGS in colour order)."""
+    (0 MC-SGS, 1 l1-Jacobi, 2 hybrid SGS, 3 hybrid SGS in colour order);
+    tile_rows: the hybrid blocks' rows, one for every level or one per level."""
     L = H.levels
     sms = smoother if isinstance(smoother, (list, tuple)) else [smoother] * L
+    Ts = tile_rows if isinstance(tile_rows, (list, tuple)) else [tile_rows] * L
     As, Ps, smooths = [A0], [], []
     for l in range(L - 1):
         lv = H.level(l)
@@ -118,9 +120,9 @@ def paper_cycle(H, A0, omega, smoother, pre, post, tile_rows):
         elif sms[l] == 1:
             smooths.append(l1_jacobi_dense(A))
         elif sms[l] == 2:
-            smooths.append(hybrid_dense(A, tile_rows))
+            smooths.append(hybrid_dense(A, Ts[l]))
         else:
-            smooths.append(hybrid_dense(A, tile_rows, lv.colour))
+            smooths.append(hybrid_dense(A, Ts[l], lv.colour))
 
     def cycle(l, b):
         if l == L - 1:
@@ -212,13 +214,66 @@ def test_vcycle_per_level_smoothers_equal_paper_cycle(smoother, coarse, start):
         assert np.abs(H.vcycle(b) - zr).max() <= 1e-11 * np.abs(zr).max()
 
 
+def first_fit_tile_colours(L, T):
+    """Row by row in ascending order, the smallest colour that no earlier row
+    of the same T-row tile coupled to it holds (brute force)."""
+    c = np.empty(L.n, np.int64)
+    for i in range(L.n):
+        lo = i - i % T
+        nb = L.colind[L.rowptr[i]:L.rowptr[i + 1]]
+        used = set(c[nb[(nb >= lo) & (nb < i)]].tolist())
+        c[i] = min(set(range(len(used) + 1)) - used)
+    return c
+
+
+# Smoothing tiles of their own size: `stile` rows on the levels above
+# coarse_from, `ctile` from it on (0: tile_rows, and the finer levels' size).
+# The sizes neither divide nor are multiples of the 64-row aggregation tiles,
+# so a block size taken from the wrong parameter, or switched at the wrong
+# level, changes the cycle.
+SMOOTH_TILE_CASES = [
+    # (smoother, coarse_smoother, coarse_from, smooth_tile_rows, coarse_smooth_tile_rows)
+    (2, -1, 1, 200, 0), (2, -1, 2, 96, 16), (3, -1, 2, 0, 24), (0, 3, 1, 0, 40), (3, 2, 2, 300, 50),
+    (2, 3, 1, 48, 0),
+]
+
+
+@pytest.mark.parametrize("smoother,coarse,start,stile,ctile", SMOOTH_TILE_CASES)
+def test_vcycle_smoothing_tiles_equal_paper_cycle(smoother, coarse, start, stile, ctile):
+    """Hybrid blocks of a size of their own (Sec. 3.2 with blocks that are
+    not the aggregation tiles): aggregation is that of 64-row tiles whatever
+    the blocks; tile-ordered levels are coloured first-fit per block; the
+    cycle equals the dense cycle of Sec. 2 with hybrid blocks of those
+    sizes."""
+    s = P.lognormal(12, seed=7)
+    kw = dict(coarse_max=8, smoother=smoother, coarse_smoother=coarse, coarse_from=start, tile_rows=64,
+              colour_tile_rows=64)
+    H = O.Hierarchy(s.rowptr, s.colind, s.vals, smooth_tile_rows=stile, coarse_smooth_tile_rows=ctile, **kw)
+    H0 = O.Hierarchy(s.rowptr, s.colind, s.vals, **kw)
+    assert H.levels == H0.levels >= 4
+    sms = [coarse if coarse >= 0 and l >= start else smoother for l in range(H.levels)]
+    Ts = [ctile if ctile and l >= start else (stile or 64) for l in range(H.levels)]
+    for l in range(H.levels - 1):
+        assert np.array_equal(H.level(l).agg, H0.level(l).agg), l
+        if sms[l] == 3:
+            assert np.array_equal(H.level(l).colour, first_fit_tile_colours(H.level(l), Ts[l])), l
+    A0 = dense(s.rowptr, s.colind, s.vals)
+    ref, _ = paper_cycle(H, A0, 1.6, sms, 1, 1, Ts)
+    rng = np.random.default_rng(13)
+    for _ in range(3):
+        b = rng.uniform(-1, 1, s.n)
+        zr = ref(b)
+        assert np.abs(H.vcycle(b) - zr).max() <= 1e-11 * np.abs(zr).max()
+
+
 def test_per_level_smoother_input_errors():
     """Smoother ids outside 0..3, a coarse smoother below -1 and a start level
     below 1 are rejected; point-based levels take the multicolour smoother on
     every level."""
     s = P.lognormal(6, seed=1)
     for kw in (dict(smoother=4), dict(smoother=-1), dict(coarse_smoother=4), dict(coarse_smoother=-2),
-               dict(coarse_smoother=3, coarse_from=0)):
+               dict(coarse_smoother=3, coarse_from=0), dict(coarse_smooth_tile_rows=64, coarse_from=0),
+               dict(smooth_tile_rows=-1), dict(coarse_smooth_tile_rows=-64)):
         with pytest.raises(O.OracleError) as e:
             O.Hierarchy(s.rowptr, s.colind, s.vals, **kw)
         assert e.value.status == O.INVALID, kw
