@@ -613,17 +613,19 @@ def main():
         # With the hybrid smoother (Sec. 3.2; block-Jacobi over the tiles) it
         # is the paper's own solver configuration; CG with it for comparison.
         bic = {}
-        runs = [(0, 1, "bicgstab"), (0, 0, "bicgstab"), (2, 1, "bicgstab"), (2, 0, "bicgstab"), (2, 1, "cg")]
-        for smoother, fp32, method in runs:
+        # (smoother, FP32 cycle, method, the headline's coarse-level smoothing)
+        runs = [(0, 1, "bicgstab", False), (0, 0, "bicgstab", False), (2, 1, "bicgstab", False),
+                (2, 0, "bicgstab", False), (2, 1, "cg", False), (0, 0, "bicgstab", True)]
+        for smoother, fp32, method, head in runs:
             torch.cuda.synchronize()
             q0 = time.perf_counter()
-            h = A.Hierarchy(rp, ci, v, vcycle_fp32=fp32, smoother=smoother)
+            h = A.Hierarchy(rp, ci, v, vcycle_fp32=fp32, smoother=smoother, **(HEAD if head else {}))
             xb, rb = h.solve(b, rtol=1e-8, method=method)
             h.close()
             torch.cuda.synchronize()
             ms = (time.perf_counter() - q0) * 1e3
             key = ("bicgstab" if method == "bicgstab" else "cg") + ("_hybrid_sgs" if smoother == 2 else "_mcsgs") + \
-                ("_fp32_vcycle" if fp32 else "_fp64_vcycle")
+                ("_tile_mcsgs_coarse" if head else "") + ("_fp32_vcycle" if fp32 else "_fp64_vcycle")
             bic[key] = {
                 "time_to_1e8_ms": ms, "setup_ms": rb.setup_ms, "solve_ms": rb.solve_ms,
                 "iterations": rb.iterations, "half_step_exit": bool(rb.half_step),
@@ -634,21 +636,29 @@ def main():
         extra["paper_solver"] = bic
         # Iteration counts on the paper's Laplace problem (K = 1), the
         # setting of its Table 1 (80^3 on one process: 5 levels, It = 8) and
-        # Table 4 (256^3 on one process: It = 6), BiCGSTAB with both smoothers.
+        # Table 4 (256^3 on one process: It = 6), BiCGSTAB with the
+        # multicolour, hybrid and tile-ordered smoothers; the hybrid blocks
+        # also larger on level 0 and smaller on the coarse levels.
         lap = {}
         for m in (80, 256):
             sl = P.poisson(m)
             lrp, lci, lv, lb = A.to_device(sl)
-            for smoother, tiles in ((0, 128), (2, 128), (0, 1024)):
+            # (smoother, aggregation tiles, smoothing blocks above level 1, from level 1)
+            for smoother, tiles, stile, ctile in ((0, 128, 0, 0), (2, 128, 0, 0), (0, 1024, 0, 0), (2, 128, 256, 0),
+                                                  (2, 128, 128, 64), (2, 128, 256, 64), (3, 128, 0, 0)):
                 torch.cuda.synchronize()
                 q0 = time.perf_counter()
-                h = A.Hierarchy(lrp, lci, lv, smoother=smoother, tile_rows=tiles)
+                h = A.Hierarchy(lrp, lci, lv, smoother=smoother, tile_rows=tiles, smooth_tile_rows=stile,
+                                coarse_smooth_tile_rows=ctile)
                 _, rl = h.solve(lb, rtol=1e-8, method="bicgstab")
                 lev = h.levels
                 h.close()
                 torch.cuda.synchronize()
-                tag = 'hybrid_sgs' if smoother == 2 else 'mcsgs'
-                lap[f"{m}^3_{tag}" + ("" if tiles == 128 else f"_tiles{tiles}")] = {
+                tag = {0: 'mcsgs', 2: 'hybrid_sgs', 3: 'tile_mcsgs'}[smoother]
+                tag += "" if tiles == 128 else f"_tiles{tiles}"
+                tag += f"_blocks{stile}" if stile else ""
+                tag += f"_coarse_blocks{ctile}" if ctile else ""
+                lap[f"{m}^3_{tag}"] = {
                     "levels": lev, "iterations": rl.iterations, "half_step_exit": bool(rl.half_step),
                     "time_to_1e8_ms": (time.perf_counter() - q0) * 1e3, "setup_ms": rl.setup_ms,
                     "solve_ms": rl.solve_ms, "true_rel_residual": rl.true_rel_residual}

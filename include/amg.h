@@ -64,8 +64,8 @@ typedef struct amg_csr {
 
 /* Smoothers: multicolour symmetric Gauss-Seidel over the whole level;
  * l1-Jacobi; the paper's hybrid symmetric Gauss-Seidel (Sec. 3.2: block-
- * Jacobi over the tiles of tile_rows rows, one sequential forward + backward
- * Gauss-Seidel sweep inside each tile, levels kept in natural order); the
+ * Jacobi over smoothing tiles of smooth_tile_rows rows, one sequential forward +
+ * backward Gauss-Seidel sweep inside each tile, levels kept in natural order); the
  * same hybrid form with each tile's rows swept colour by colour (colour, then
  * row; the colours a first-fit colouring of each tile on its own, rows
  * ascending, couplings inside the tile only), which runs a level's whole
@@ -122,10 +122,17 @@ typedef struct amg_params {
                                 (one lane per row); 1 CSR with a group of lanes per
                                 row (keeps the level's CSR arrays, 12 B per entry) */
   int32_t coarse_smoother;   /* AMG_SMOOTHER_* of levels coarse_from and below;  [-1]
-                                -1: `smoother` on every level.  The tile forms
-                                (HYBRID_SGS, TILE_MCSGS) use tiles of tile_rows
-                                rows on every level they run on. */
-  int32_t coarse_from;       /* first level of coarse_smoother (>= 1)           [1]  */
+                                -1: `smoother` on every level */
+  int32_t coarse_from;       /* first level of coarse_smoother and of         [1]
+                                coarse_smooth_tile_rows (>= 1 when either is set) */
+  int32_t smooth_tile_rows;  /* rows per block of the tile smoothers          [0]
+                                (HYBRID_SGS, TILE_MCSGS: the blocks of the block-
+                                Jacobi of Sec. 3.2) on levels above coarse_from;
+                                64..1024, 0: tile_rows.  Independent of the
+                                aggregation tiles: a block may span several of
+                                them or split one. */
+  int32_t coarse_smooth_tile_rows; /* the same from level coarse_from on;     [0]
+                                0: as on the finer levels */
 } amg_params;
 
 typedef struct amg_solve_info {

@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("colour_seed", C.c_uint32), ("check_symmetry", C.c_int32), ("keep_setup_data", C.c_int32),
                 ("use_graphs", C.c_int32), ("tail_rows", C.c_int32),
                 ("colour_tile_rows", C.c_int32), ("block_size", C.c_int32), ("spmv_format", C.c_int32),
-                ("coarse_smoother", C.c_int32), ("coarse_from", C.c_int32)]
+                ("coarse_smoother", C.c_int32), ("coarse_from", C.c_int32),
+                ("smooth_tile_rows", C.c_int32), ("coarse_smooth_tile_rows", C.c_int32)]
 
 
 class CSR(C.Structure):

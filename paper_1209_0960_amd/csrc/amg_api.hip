@@ -331,7 +331,12 @@ void check_params(const amg_params& p) {
   if (p.smoother < AMG_SMOOTHER_MCSGS || p.smoother > AMG_SMOOTHER_TILE_MCSGS) fail(AMG_ERR_INVALID_ARG, "smoother");
   if (p.coarse_smoother < -1 || p.coarse_smoother > AMG_SMOOTHER_TILE_MCSGS)
     fail(AMG_ERR_INVALID_ARG, "coarse_smoother");
-  if (p.coarse_smoother >= 0 && p.coarse_from < 1) fail(AMG_ERR_INVALID_ARG, "coarse_from");
+  if ((p.coarse_smoother >= 0 || p.coarse_smooth_tile_rows > 0) && p.coarse_from < 1)
+    fail(AMG_ERR_INVALID_ARG, "coarse_from");
+  if (p.smooth_tile_rows < 0 || p.coarse_smooth_tile_rows < 0) fail(AMG_ERR_INVALID_ARG, "smooth_tile_rows");
+  if ((p.smooth_tile_rows > 0 && (p.smooth_tile_rows < 64 || p.smooth_tile_rows > 1024)) ||
+      (p.coarse_smooth_tile_rows > 0 && (p.coarse_smooth_tile_rows < 64 || p.coarse_smooth_tile_rows > 1024)))
+    fail(AMG_ERR_UNSUPPORTED, "smoothing tiles outside 64..1024 rows");
   if (p.pre_sweeps < 0 || p.post_sweeps < 0) fail(AMG_ERR_INVALID_ARG, "sweeps");
   if (p.tail_rows < 0) fail(AMG_ERR_INVALID_ARG, "tail_rows");
   if (p.colour_tile_rows < 64 || p.colour_tile_rows > 1024) fail(AMG_ERR_UNSUPPORTED, "colour_tile_rows outside 64..1024");
@@ -428,6 +433,9 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   for (int l = 0; l <= Lc; ++l) {
     H.lev[l].bs = bs;
     H.lev[l].sm = level_smoother(p, l);
+    // from here on a level's tiles are its smoothing tiles (aggregation is done)
+    H.lev[l].T = smooth_tile(p, l);
+    H.lev[l].ntiles = (H.lev[l].n + H.lev[l].T - 1) / H.lev[l].T;
     if (H.lev[l].sm == AMG_SMOOTHER_HYBRID_SGS) {
       colour_single(H, H.lev[l], s);
     } else if (H.lev[l].sm == AMG_SMOOTHER_TILE_MCSGS) {  // tile-local colours set the sweep order inside a tile
@@ -473,7 +481,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
       // LDS at 8 right-hand sides); the colour-by-colour sweeps need none.
       const bool steps = L.sm == AMG_SMOOTHER_HYBRID_SGS || p.tail_rows > 0 || L.tncol >= 64 ||
                          tsgs_lds_bytes(L.T, std::max(L.icmax, 1), 8, L.tncol, 8) > 65536;
-      if (steps) hybrid_steps(H, L, p.tile_rows, s);
+      if (steps) hybrid_steps(H, L, L.T, s);
     }
     L.sptr_d = H.alloc<int>(L.sptr.size(), s);
     AMG_HIP(hipMemcpyAsync(L.sptr_d, L.sptr.data(), L.sptr.size() * sizeof(int), hipMemcpyHostToDevice, s));
@@ -529,6 +537,8 @@ amg_status amg_default_params(amg_params* p) {
   p->spmv_format = 0;
   p->coarse_smoother = -1;
   p->coarse_from = 1;
+  p->smooth_tile_rows = 0;
+  p->coarse_smooth_tile_rows = 0;
   return AMG_OK;
 }
 

@@ -293,6 +293,11 @@ inline int level_smoother(const amg_params& p, int l) {
 // Whether level l's smoother runs as tile sweeps (the hybrid smoother, in
 // natural or colour order: the same launches, the order is in the steps).
 inline bool tile_sweeps(int sm) { return sm == AMG_SMOOTHER_HYBRID_SGS || sm == AMG_SMOOTHER_TILE_MCSGS; }
+// Rows per smoothing tile of level l (the blocks of the tile smoothers).
+inline int smooth_tile(const amg_params& p, int l) {
+  const int fine = p.smooth_tile_rows > 0 ? p.smooth_tile_rows : p.tile_rows;
+  return p.coarse_smooth_tile_rows > 0 && l >= p.coarse_from ? p.coarse_smooth_tile_rows : fine;
+}
 void cast_f32(const double* in, float* out, size_t n, hipStream_t s);
 void l1_diag(const Level& L, double* out64, float* out32, hipStream_t s);
 // Dense FP64 factorisation of the coarsest level and its explicit inverse.

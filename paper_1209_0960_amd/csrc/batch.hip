@@ -198,8 +198,9 @@ struct Batch {
   // All entries start together and are completed at the end (pcg_solve_batched):
   // finished entries are only switched off, the launch plan is kept.
   bool deferred = false;
-  int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0, tile_rows = 0, bs = 1;
+  int fp32 = -1, smoother = 0, pre = 0, post = 0, flexible = 0, bs = 1;
   int coarse_smoother = -1, coarse_from = 1;  // per-level smoother choice (shared by the entries)
+  int stile[MAX_LEVELS] = {};                  // smoothing tile of each level (shared with a tile smoother)
   hipStream_t work = nullptr;
   hipEvent_t ev = nullptr;
   BDesc* desc_d = nullptr;
@@ -254,10 +255,10 @@ void check_uniform(Batch& B, const Hierarchy& H) {
     B.pre = H.p.pre_sweeps;
     B.post = H.p.post_sweeps;
     B.flexible = H.flexible;
-    B.tile_rows = H.p.tile_rows;
     B.bs = H.p.block_size;
     B.coarse_smoother = H.p.coarse_smoother;
     B.coarse_from = H.p.coarse_from;
+    for (int l = 0; l < MAX_LEVELS; ++l) B.stile[l] = smooth_tile(H.p, l);
     return;
   }
   const bool same_coarse = B.coarse_smoother == H.p.coarse_smoother &&
@@ -267,8 +268,10 @@ void check_uniform(Batch& B, const Hierarchy& H) {
     fail(AMG_ERR_INVALID_ARG,
          "hierarchies of one batch must share vcycle_fp32, the smoothers, pre/post sweeps, block size and the CG "
          "variant");
-  if ((tile_sweeps(B.smoother) || tile_sweeps(B.coarse_smoother)) && B.tile_rows != H.p.tile_rows)
-    fail(AMG_ERR_INVALID_ARG, "hierarchies of one batch with a tile smoother must share tile_rows");
+  bool same_tiles = true;
+  for (int l = 0; l < MAX_LEVELS; ++l) same_tiles = same_tiles && B.stile[l] == smooth_tile(H.p, l);
+  if ((tile_sweeps(B.smoother) || tile_sweeps(B.coarse_smoother)) && !same_tiles)
+    fail(AMG_ERR_INVALID_ARG, "hierarchies of one batch with a tile smoother must share their smoothing tiles");
 }
 
 // The fields of a level's descriptor that come from the hierarchy (matrix,

@@ -41,9 +41,10 @@ def test_params_struct_matches_header_defaults():
     assert (p.smoother, p.pre_sweeps, p.post_sweeps, p.vcycle_fp32, p.flexible) == (0, 1, 1, 0, -1)
     assert p.use_graphs == 1
     assert p.tail_rows == 0
-    assert ctypes.sizeof(A.Params) == 112  # 3 doubles + 20 int32 fields (4 bytes of padding before omega), 8-byte aligned
+    assert ctypes.sizeof(A.Params) == 120  # 3 doubles + 22 int32 fields (4 bytes of padding before omega), 8-byte aligned
     assert p.block_size == 1
     assert (p.coarse_smoother, p.coarse_from) == (-1, 1)
+    assert (p.smooth_tile_rows, p.coarse_smooth_tile_rows) == (0, 0)
 
 
 def test_header_compiles_as_c_and_matches_ctypes_layout(tmp_path):
@@ -54,15 +55,16 @@ def test_header_compiles_as_c_and_matches_ctypes_layout(tmp_path):
         pytest.skip("no C compiler")
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "amg.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(amg_params), sizeof(amg_solve_info),'
-                   ' sizeof(amg_csr), offsetof(amg_params, use_graphs));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(amg_params), sizeof(amg_solve_info),'
+                   ' sizeof(amg_csr), offsetof(amg_params, use_graphs), offsetof(amg_params, coarse_smooth_tile_rows));'
+                   'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
                            "-o", str(exe)])
     sizes = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     from paper_1209_0960_amd import amg as A
     assert sizes == [ctypes.sizeof(A.Params), ctypes.sizeof(A.SolveInfo), ctypes.sizeof(A.CSR),
-                     A.Params.use_graphs.offset]
+                     A.Params.use_graphs.offset, A.Params.coarse_smooth_tile_rows.offset]
 
 
 def test_bicgstab_and_hybrid_host_checks():

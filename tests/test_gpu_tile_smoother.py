@@ -1,7 +1,8 @@
 """GPU parity of the tile-ordered multicolour smoother (the hybrid form of
-Sec. 3.2 with each tile's rows swept in colour order) and of per-level
-smoother choice (coarse_smoother from level coarse_from on), against the CPU
-oracle through the C ABI.
+Sec. 3.2 with each tile's rows swept in colour order), of per-level smoother
+choice (coarse_smoother from level coarse_from on) and of hybrid blocks of a
+size of their own (smooth_tile_rows, coarse_smooth_tile_rows), against the
+CPU oracle through the C ABI.
 
 Setup outputs (colours of the tile levels included) are bit-exact; the FP64
 V-cycle agrees to 1e-12 and every FP64 PCG iterate to 1e-10, element-wise and
@@ -23,9 +24,12 @@ CASES = {
     "layered_16": lambda: P.layered(16),
 }
 
-# (smoother, coarse_smoother, coarse_from, tile_rows)
+# (smoother, coarse_smoother, coarse_from, tile_rows[, smooth_tile_rows, coarse_smooth_tile_rows])
 CONFIGS = [(3, -1, 1, 128), (0, 3, 1, 128), (0, 3, 2, 64), (0, 3, 1, 200), (0, 2, 1, 128), (0, 1, 1, 128),
            (2, 0, 1, 128), (3, 0, 2, 1024)]
+# smoothing tiles of their own size: larger level-0 blocks, smaller coarse ones
+TILE_CONFIGS = [(2, -1, 1, 128, 256, 64), (0, 3, 1, 128, 0, 64), (3, -1, 2, 64, 200, 96), (2, 3, 2, 128, 1024, 0),
+                (3, 2, 1, 256, 0, 128)]
 
 
 @pytest.fixture(scope="module")
@@ -45,8 +49,11 @@ def system(name):
 
 
 def kw_of(cfg):
-    sm, cs, cf, T = cfg
-    return dict(smoother=sm, coarse_smoother=cs, coarse_from=cf, tile_rows=T)
+    sm, cs, cf, T = cfg[:4]
+    kw = dict(smoother=sm, coarse_smoother=cs, coarse_from=cf, tile_rows=T)
+    if len(cfg) > 4:
+        kw.update(smooth_tile_rows=cfg[4], coarse_smooth_tile_rows=cfg[5])
+    return kw
 
 
 def rel(a, b):
@@ -59,7 +66,7 @@ def rel(a, b):
     return float(max(nrm, ele))
 
 
-@pytest.mark.parametrize("cfg", CONFIGS[:4])
+@pytest.mark.parametrize("cfg", CONFIGS[:4] + TILE_CONFIGS)
 def test_setup_bit_exact(A, cfg):
     """Every level's matrix, aggregates and colours match the oracle; tile
     levels report their colouring (the sweep order) although they are kept
@@ -80,7 +87,7 @@ def test_setup_bit_exact(A, cfg):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("cfg", CONFIGS)
+@pytest.mark.parametrize("cfg", CONFIGS + TILE_CONFIGS)
 def test_vcycle_fp64_parity(A, name, cfg):
     s = system(name)
     rp, ci, v, b = A.to_device(s)
@@ -92,7 +99,7 @@ def test_vcycle_fp64_parity(A, name, cfg):
         assert rel(z.cpu().numpy(), ho.vcycle(s.b)) <= 1e-12, (name, cfg)
 
 
-@pytest.mark.parametrize("cfg", [CONFIGS[1], CONFIGS[2], CONFIGS[7]])
+@pytest.mark.parametrize("cfg", [CONFIGS[1], CONFIGS[2], CONFIGS[7], TILE_CONFIGS[0], TILE_CONFIGS[2]])
 def test_vcycle_fp32_parity(A, cfg):
     s = system("hetero_24")
     rp, ci, v, b = A.to_device(s)
@@ -105,7 +112,7 @@ def test_vcycle_fp32_parity(A, cfg):
 
 
 @pytest.mark.parametrize("name", ["hetero_24", "layered_16"])
-@pytest.mark.parametrize("cfg", [CONFIGS[0], CONFIGS[1], CONFIGS[2]])
+@pytest.mark.parametrize("cfg", [CONFIGS[0], CONFIGS[1], CONFIGS[2], TILE_CONFIGS[0], TILE_CONFIGS[1]])
 def test_pcg_fp64_iterates(A, name, cfg):
     s = system(name)
     rp, ci, v, b = A.to_device(s)
@@ -153,14 +160,37 @@ def test_batched_entries_equal_single_solves(A):
             h.close()
 
 
-def test_batch_rejects_mixed_coarse_smoothers(A):
+@pytest.mark.parametrize("kw1,kw2", [(dict(coarse_smoother=3), {}),
+                                     (dict(coarse_smoother=3, coarse_smooth_tile_rows=64), dict(coarse_smoother=3)),
+                                     (dict(smoother=2, smooth_tile_rows=256), dict(smoother=2))])
+def test_batch_rejects_mixed_coarse_smoothers(A, kw1, kw2):
+    """Entries of a batch share the smoother of every level and, with a tile
+    smoother, its smoothing tiles."""
     s = P.poisson(16)
     rp, ci, v, b = A.to_device(s)
-    with A.Hierarchy(rp, ci, v, coarse_smoother=3) as h1, A.Hierarchy(rp, ci, v) as h2:
+    with A.Hierarchy(rp, ci, v, **kw1) as h1, A.Hierarchy(rp, ci, v, **kw2) as h2:
         xs = [torch.zeros_like(b), torch.zeros_like(b)]
         with pytest.raises(A.AMGError) as e:
             A.pcg_solve_batched([h1.h, h2.h], [b.clone(), b.clone()], xs, nrhs=1, rtol=1e-8, maxit=50)
         assert e.value.status == A.ERR_INVALID_ARG
+
+
+def test_batch_shares_smoothing_tiles_not_aggregation_tiles(A):
+    """Hierarchies aggregated with different tiles but one smoothing tile
+    size batch together, and give the bits of their single solves."""
+    s = P.lognormal(16, seed=5)
+    rp, ci, v, b = A.to_device(s)
+    kw = dict(smoother=2, smooth_tile_rows=128)
+    with A.Hierarchy(rp, ci, v, tile_rows=64, **kw) as h1, A.Hierarchy(rp, ci, v, tile_rows=256, **kw) as h2:
+        ref = []
+        for h in (h1, h2):
+            x, r = h.solve(b, rtol=1e-8, maxit=200)
+            ref.append(x.cpu().numpy())
+        xs = [torch.zeros_like(b), torch.zeros_like(b)]
+        st, _ = A.pcg_solve_batched([h1.h, h2.h], [b.clone(), b.clone()], xs, nrhs=1, rtol=1e-8, maxit=200)
+        assert st == A.OK
+        for x, r in zip(xs, ref):
+            assert rel(x.cpu().numpy(), r) <= 1e-12
 
 
 def test_input_errors(A):
@@ -179,3 +209,8 @@ def test_input_errors(A):
     assert status(coarse_smoother=3, coarse_from=0) == A.ERR_INVALID_ARG
     assert status(coarse_smoother=-1, coarse_from=0) == A.OK  # start level unused
     assert status(coarse_smoother=3, coarse_from=40) == A.OK  # no level that deep: MC-SGS everywhere
+    assert status(coarse_smooth_tile_rows=64, coarse_from=0) == A.ERR_INVALID_ARG
+    assert status(smooth_tile_rows=-1) == A.ERR_INVALID_ARG
+    assert status(smooth_tile_rows=32) == A.ERR_UNSUPPORTED
+    assert status(coarse_smooth_tile_rows=2048) == A.ERR_UNSUPPORTED
+    assert status(smooth_tile_rows=1024, coarse_smooth_tile_rows=64) == A.OK
