@@ -1336,62 +1336,146 @@ __device__ inline void store_block(double* __restrict__ D, int n, int bi, int bj
   }
 }
 
-// Factor the diagonal block p in LDS (lower triangle).
-__global__ __launch_bounds__(256) void k_chol_diag(int n, int p, double* D, int* fail) {
-  __shared__ double B[CB][CB + 1];
-  __shared__ double piv;
-  load_block(D, n, p, p, B);
-  __syncthreads();
-  for (int k = 0; k < CB; ++k) {
-    if (threadIdx.x == 0) {
-      const double d = B[k][k];
-      if (!(d > 0.0)) {
-        *fail = 1;
-        piv = 1.0;
-      } else {
-        piv = sqrt(d);
-      }
-      B[k][k] = piv;
-    }
-    __syncthreads();
-    for (int i = k + 1 + threadIdx.x; i < CB; i += blockDim.x) B[i][k] = B[i][k] / piv;
-    __syncthreads();
-    for (int q = threadIdx.x; q < CB * CB; q += blockDim.x) {
-      const int i = q / CB, j = q % CB;
-      if (j > k && j <= i) B[i][j] = B[i][j] - B[i][k] * B[j][k];
-    }
-    __syncthreads();
+// The triangular kernels run one wavefront per block with a row (or column)
+// of the block per lane in registers; the block products give each of 256
+// threads a 4 x 4 set of entries (rows tr + 16a, columns tc + 16b).  Every
+// entry is computed with the same operations in the same order as a plain
+// per-entry loop over k.
+__device__ inline void load_row(const double* __restrict__ D, int n, int bi, int bj, int r, double (&x)[CB]) {
+  const int i = bi * CB + r;
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int j = bj * CB + c;
+    x[c] = (i < n && j < n) ? D[(size_t)i * n + j] : (i == j ? 1.0 : 0.0);
   }
-  store_block(D, n, p, p, B);
+}
+__device__ inline void store_row(double* __restrict__ D, int n, int bi, int bj, int r, const double (&x)[CB]) {
+  const int i = bi * CB + r;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
+    if (bj * CB + c < n) D[(size_t)i * n + bj * CB + c] = x[c];
 }
 
-// Panel: L_ip = A_ip L_pp^{-T} for the block rows i > p (one workgroup each).
-__global__ __launch_bounds__(256) void k_chol_trsm(int n, int p, double* D) {
-  __shared__ double Lp[CB][CB + 1];
-  __shared__ double X[CB][CB + 1];
-  const int bi = p + 1 + blockIdx.x;
-  load_block(D, n, p, p, Lp);
-  load_block(D, n, bi, p, X);
+// The triangular kernels below are fully unrolled so that the block's rows
+// stay in registers, with their updates as fused multiply-adds; barriers
+// between steps (one wavefront: cheap) keep the compiler from issuing the
+// LDS reads of later steps early, which would not fit in registers.
+//
+// Cholesky steps k = J0 .. J0+31 on columns J0 .. J0+31 of a diagonal block
+// (b[jj] = B_i,J0+jj on lane i): the pivot sqrt(B_kk) from lane k, column k
+// divided by it and broadcast through LDS, then B_ij -= B_ik B_jk for
+// k < j <= i.
+template <int J0>
+__device__ __forceinline__ void chol_steps(double (&b)[CB / 2], int i, double* col, int* fail) {
+#pragma unroll
+  for (int kk = 0; kk < CB / 2; ++kk) {
+    const int k = J0 + kk;
+    const double d = __shfl(b[kk], k, WAVE);
+    const bool ok = d > 0.0;
+    if (!ok && i == 0) *fail = 1;
+    const double piv = ok ? sqrt(d) : 1.0;
+    if (i == k) b[kk] = piv;
+    else if (i > k) b[kk] = b[kk] / piv;
+    col[i] = b[kk];
+    __syncthreads();
+#pragma unroll
+    for (int jj = kk + 1; jj < CB / 2; ++jj)
+      if (J0 + jj <= i) b[jj] = fma(-b[kk], col[J0 + jj], b[jj]);
+    __syncthreads();
+  }
+}
+
+// Factor the diagonal block p (lower triangle), one wavefront, lane i holding
+// row i, 32 columns at a time: the first half takes its steps; then the
+// second half takes the first half's terms (k ascending, as the steps would
+// have applied them) and its own steps.
+__global__ __launch_bounds__(WAVE) void k_chol_diag(int n, int p, double* D, int* fail) {
+  __shared__ double col[CB];
+  __shared__ double Lf[CB][CB / 2 + 1];  // columns 0..31 after their steps
+  constexpr int H = CB / 2;
+  const int i = threadIdx.x, gi = p * CB + i;
+  auto elem = [&](int gj) { return (gi < n && gj < n) ? D[(size_t)gi * n + gj] : (gi == gj ? 1.0 : 0.0); };
+  double b[H], b2[H];
+#pragma unroll
+  for (int jj = 0; jj < H; ++jj) b[jj] = elem(p * CB + jj);
+  chol_steps<0>(b, i, col, fail);
+#pragma unroll
+  for (int jj = 0; jj < H; ++jj) Lf[i][jj] = b[jj];
+#pragma unroll
+  for (int jj = 0; jj < H; ++jj) b2[jj] = elem(p * CB + H + jj);
   __syncthreads();
-  if (threadIdx.x < CB) {
-    const int r = threadIdx.x;
-    for (int c = 0; c < CB; ++c) {
-      double v = X[r][c];
-      for (int k = 0; k < c; ++k) v = v - X[r][k] * Lp[c][k];
-      X[r][c] = v / Lp[c][c];
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj)
+      if (H + jj <= i) b2[jj] = fma(-b[k], Lf[H + jj][k], b2[jj]);
+    __syncthreads();  // (one wavefront: cheap) bounds the LDS reads issued ahead
+  }
+  chol_steps<H>(b2, i, col, fail);
+  if (gi < n) {
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj) {
+      if (p * CB + jj < n) D[(size_t)gi * n + p * CB + jj] = b[jj];
+      if (p * CB + H + jj < n) D[(size_t)gi * n + p * CB + H + jj] = b2[jj];
     }
   }
+}
+
+// Panel: L_ip = A_ip L_pp^{-T} for the block rows i > p (one wavefront each,
+// lane r solving row r by forward substitution, k ascending).
+__global__ __launch_bounds__(WAVE) void k_chol_trsm(int n, int p, double* D) {
+  __shared__ double Lp[CB][CB + 1];
+  const int bi = p + 1 + blockIdx.x, r = threadIdx.x, gr = bi * CB + r;
+  load_block(D, n, p, p, Lp);
+  double x[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int gc = p * CB + c;
+    x[c] = (gr < n && gc < n) ? D[(size_t)gr * n + gc] : 0.0;  // off the diagonal: no identity padding
+  }
   __syncthreads();
-  store_block(D, n, bi, p, X);
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    double v = x[c];
+#pragma unroll
+    for (int k = 0; k < c; ++k) v = fma(-x[k], Lp[c][k], v);
+    x[c] = v / Lp[c][c];
+    __syncthreads();  // (one wavefront: cheap) row c + 1's LDS reads are not issued ahead of row c
+  }
+  if (gr < n) {
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+      if (p * CB + c < n) D[(size_t)gr * n + p * CB + c] = x[c];
+  }
+}
+
+// 4 x 4 entries per thread of a 64 x 64 block product: rows tr + 16a, columns
+// tc + 16b; a(k, a) and b(k, b) read the operands from LDS.
+template <typename FA, typename FB>
+__device__ __forceinline__ void block_dot(FA a, FB b, double (&s)[4][4]) {
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) s[x][y] = 0.0;
+  for (int k = 0; k < CB; ++k) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) av[x] = a(k, x);
+#pragma unroll
+    for (int y = 0; y < 4; ++y) bv[y] = b(k, y);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) s[x][y] += av[x] * bv[y];
+  }
 }
 
 // Trailing update A_ij -= L_ip L_jp^T for p < j <= i (one workgroup per pair).
 __global__ __launch_bounds__(256) void k_chol_update(int n, int p, double* D) {
   __shared__ double Li[CB][CB + 1];
   __shared__ double Lj[CB][CB + 1];
-  const int m = gridDim.x;  // pairs are enumerated as (i, j) with i >= j over the trailing blocks
-  (void)m;
-  int q = blockIdx.x, bi = 0;
+  int q = blockIdx.x, bi = 0;  // pairs (i, j), i >= j, over the trailing blocks
   const int nt = (n + CB - 1) / CB - (p + 1);
   while (q >= bi + 1) {
     q -= bi + 1;
@@ -1402,32 +1486,39 @@ __global__ __launch_bounds__(256) void k_chol_update(int n, int p, double* D) {
   load_block(D, n, I, p, Li);
   load_block(D, n, J, p, Lj);
   __syncthreads();
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e / CB, c = e % CB, i = I * CB + r, j = J * CB + c;
-    if (i >= n || j >= n || (I == J && c > r)) continue;
-    double s = 0.0;
-    for (int k = 0; k < CB; ++k) s += Li[r][k] * Lj[c][k];
-    D[(size_t)i * n + j] -= s;
-  }
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  double s[4][4];
+  block_dot([&](int k, int x) { return Li[tr + 16 * x][k]; }, [&](int k, int y) { return Lj[tc + 16 * y][k]; }, s);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = tr + 16 * x, c = tc + 16 * y, i = I * CB + r, j = J * CB + c;
+      if (i >= n || j >= n || (I == J && c > r)) continue;
+      D[(size_t)i * n + j] -= s[x][y];
+    }
 }
 
-// W = L^{-1}: diagonal blocks W_ii = L_ii^{-1} (one workgroup each).
-__global__ __launch_bounds__(256) void k_trinv_diag(int n, const double* __restrict__ D, double* __restrict__ W) {
+// W = L^{-1}: diagonal blocks W_ii = L_ii^{-1} (one wavefront each; lane c
+// computes column c by forward substitution).
+__global__ __launch_bounds__(WAVE) void k_trinv_diag(int n, const double* __restrict__ D, double* __restrict__ W) {
   __shared__ double L[CB][CB + 1];
-  __shared__ double X[CB][CB + 1];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x, c = threadIdx.x;
   load_block(D, n, b, b, L);
   __syncthreads();
-  if (threadIdx.x < CB) {  // column c of the inverse by forward substitution
-    const int c = threadIdx.x;
-    for (int r = 0; r < CB; ++r) {
-      double v = (r == c) ? 1.0 : 0.0;
-      for (int k = c; k < r; ++k) v = v - L[r][k] * X[k][c];
-      X[r][c] = r < c ? 0.0 : v / L[r][r];
-    }
+  double x[CB];
+#pragma unroll
+  for (int r = 0; r < CB; ++r) {
+    double v = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < r; ++k)
+      if (k >= c) v = fma(-L[r][k], x[k], v);
+    x[r] = r < c ? 0.0 : v / L[r][r];
   }
-  __syncthreads();
-  store_block(W, n, b, b, X);
+  const int j = b * CB + c;
+#pragma unroll
+  for (int r = 0; r < CB; ++r)
+    if (b * CB + r < n && j < n) W[(size_t)(b * CB + r) * n + j] = x[r];
 }
 
 // Block row i of W: W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj for j < i.
@@ -1435,32 +1526,38 @@ __global__ __launch_bounds__(256) void k_trinv_row(int n, int bi, const double* 
                                                    double* __restrict__ W) {
   __shared__ double A[CB][CB + 1];
   __shared__ double Bm[CB][CB + 1];
-  __shared__ double S[CB][CB + 1];
-  const int bj = blockIdx.x;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) S[e / CB][e % CB] = 0.0;
+  const int bj = blockIdx.x, tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  double S[4][4], s[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) S[x][y] = 0.0;
   for (int bk = bj; bk < bi; ++bk) {
     __syncthreads();
     load_block(D, n, bi, bk, A);
     load_block(W, n, bk, bj, Bm);
     __syncthreads();
-    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-      const int r = e / CB, c = e % CB;
-      double s = 0.0;
-      for (int k = 0; k < CB; ++k) s += A[r][k] * Bm[k][c];
-      S[r][c] += s;
-    }
+    block_dot([&](int k, int x) { return A[tr + 16 * x][k]; }, [&](int k, int y) { return Bm[k][tc + 16 * y]; }, s);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) S[x][y] += s[x][y];
   }
   __syncthreads();
   load_block(W, n, bi, bi, A);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) Bm[tr + 16 * x][tc + 16 * y] = S[x][y];
   __syncthreads();
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e / CB, c = e % CB;
-    double s = 0.0;
-    for (int k = 0; k < CB; ++k) s += A[r][k] * S[k][c];
-    Bm[r][c] = -s;
-  }
-  __syncthreads();
-  store_block(W, n, bi, bj, Bm);
+  block_dot([&](int k, int x) { return A[tr + 16 * x][k]; }, [&](int k, int y) { return Bm[k][tc + 16 * y]; }, s);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int i = bi * CB + tr + 16 * x, j = bj * CB + tc + 16 * y;
+      if (i < n && j < n) W[(size_t)i * n + j] = -s[x][y];
+    }
 }
 
 // A^-1 = W^T W: block (I, J), I >= J, sum over k >= I of W_kI^T W_kJ; written
@@ -1475,27 +1572,33 @@ __global__ __launch_bounds__(256) void k_wtw_blocks(int n, const double* __restr
   }
   const int I = bi, J = q;
   const int nb = (n + CB - 1) / CB;
-  double acc[CB * CB / 256];
-  for (int t = 0; t < CB * CB / 256; ++t) acc[t] = 0.0;
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  double acc[4][4], s[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
   for (int bk = I; bk < nb; ++bk) {
     __syncthreads();
     load_block(W, n, bk, I, Wi);
     load_block(W, n, bk, J, Wj);
     __syncthreads();
-    for (int t = 0; t < CB * CB / 256; ++t) {
-      const int e = threadIdx.x + 256 * t, r = e / CB, c = e % CB;
-      double s = 0.0;
-      for (int k = 0; k < CB; ++k) s += Wi[k][r] * Wj[k][c];
-      acc[t] += s;
-    }
+    block_dot([&](int k, int x) { return Wi[k][tr + 16 * x]; }, [&](int k, int y) { return Wj[k][tc + 16 * y]; }, s);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += s[x][y];
   }
-  for (int t = 0; t < CB * CB / 256; ++t) {
-    const int e = threadIdx.x + 256 * t, r = e / CB, c = e % CB, i = I * CB + r, j = J * CB + c;
-    if (i < n && j < n && (I != J || c <= r)) {
-      Ainv[(size_t)i * n + j] = acc[t];
-      Ainv[(size_t)j * n + i] = acc[t];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = tr + 16 * x, c = tc + 16 * y, i = I * CB + r, j = J * CB + c;
+      if (i < n && j < n && (I != J || c <= r)) {
+        Ainv[(size_t)i * n + j] = acc[x][y];
+        Ainv[(size_t)j * n + i] = acc[x][y];
+      }
     }
-  }
 }
 
 // ============================================================== solve order
@@ -2279,16 +2382,16 @@ void coarse_factor(Hierarchy& H, const Level& L, hipStream_t s) {
   AMG_HIP(hipMemsetAsync(f.p, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_densify, dim3(cdiv(n, 256)), dim3(256), 0, s, n, L.rowptr, L.colind, L.vals, D.as<double>());
   for (int p = 0; p < nb; ++p) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, n, p, D.as<double>(), f.as<int>());
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(WAVE), 0, s, n, p, D.as<double>(), f.as<int>());
     const int rest = nb - p - 1;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_trsm, dim3(rest), dim3(256), 0, s, n, p, D.as<double>());
+      hipLaunchKernelGGL(k_chol_trsm, dim3(rest), dim3(WAVE), 0, s, n, p, D.as<double>());
       hipLaunchKernelGGL(k_chol_update, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, n, p, D.as<double>());
     }
   }
   AMG_HIP(hipGetLastError());
   if (read1(f.as<int>(), s)) fail(AMG_ERR_NOT_SPD, "coarsest-level Cholesky pivot <= 0");
-  hipLaunchKernelGGL(k_trinv_diag, dim3(nb), dim3(256), 0, s, n, D.as<double>(), W.as<double>());
+  hipLaunchKernelGGL(k_trinv_diag, dim3(nb), dim3(WAVE), 0, s, n, D.as<double>(), W.as<double>());
   for (int bi = 1; bi < nb; ++bi)
     hipLaunchKernelGGL(k_trinv_row, dim3(bi), dim3(256), 0, s, n, bi, D.as<double>(), W.as<double>());
   H.Ainv = H.alloc<double>(nn, s);

@@ -156,6 +156,27 @@ def test_single_level_is_direct_solve(A):
         assert r.iterations == 1 and r.true_rel_residual <= 1e-12
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (7, 3, 3), (4, 4, 4), (13, 5, 1), (13, 10, 1), (10, 10, 5), (10, 10, 10),
+                                   (16, 16, 16)])
+def test_dense_coarse_inverse(A, shape):
+    """One-level hierarchies (coarse_max >= n): the preconditioner is the
+    dense inverse (blocked Cholesky of 64 x 64 blocks, then the inverse of the
+    factor), so z = A^-1 b for sizes at, below and across the block edges."""
+    nx, ny, nz = shape
+    K = np.exp(0.5 * np.random.default_rng(3).standard_normal((nz, ny, nx)))  # mild contrast: well conditioned
+    s = P.from_field(K, seed=3)
+    rp, ci, v, b = dev(s)
+    with A.Hierarchy(rp, ci, v, coarse_max=s.n) as hg:
+        assert hg.levels == 1
+        z = hg.precond(b)
+        torch.cuda.synchronize()
+        Ad = np.zeros((s.n, s.n))
+        for i in range(s.n):
+            Ad[i, s.colind[s.rowptr[i]:s.rowptr[i + 1]]] = s.vals[s.rowptr[i]:s.rowptr[i + 1]]
+        ref = np.linalg.solve(Ad, s.b)
+        assert rel(z.cpu().numpy(), ref) <= 1e-12, shape
+
+
 def test_setup_deterministic(A):
     s = system("hetero_32_s0")
     rp, ci, v, b = dev(s)
