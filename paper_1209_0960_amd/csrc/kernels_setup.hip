@@ -219,20 +219,77 @@ __device__ inline int find_in_row(const int* __restrict__ rp, const int* __restr
   return -1;
 }
 
-// 8 lanes per row, taking its entries in turn.
+// The row kernels below give each row STR_SUB consecutive lanes, which take
+// its entries in turn (a row's entries are read by neighbouring lanes), and
+// each group of lanes STR_ROWS rows, 32 rows apart: the first STR_SUB entries
+// of all of them (most rows have no more) are loaded together, so that their
+// chains of dependent loads overlap; longer rows finish in a plain loop.
+constexpr int STR_SUB = 8;
+constexpr int STR_ROWS = 4;
+constexpr int STR_GROUPS = 256 / STR_SUB;  // lane groups per block
+constexpr int STR_BLOCK_ROWS = STR_GROUPS * STR_ROWS;
+__device__ inline int str_row(int u) { return ((int)blockIdx.x * STR_ROWS + u) * STR_GROUPS + (int)threadIdx.x / STR_SUB; }
+
+// Every off-diagonal a_ij has a stored a_ji (equal to it when `check`): the
+// binary searches of a group's rows advance together.
 __global__ __launch_bounds__(256) void k_validate_sym(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                       const double* __restrict__ v, int check, int* flags) {
-  const int i = blockIdx.x * 32 + (int)threadIdx.x / 8, q0 = (int)threadIdx.x % 8;
-  if (i >= n) return;
-  for (int k = rp[i] + q0; k < rp[i + 1]; k += 8) {
-    const int j = ci[k];
-    if (j == i) continue;
-    const int q = find_in_row(rp, ci, j, i);
-    if (q < 0 || (check && v[q] != v[k])) {
-      atomicOr(flags, 4);
-      return;
+  const int q0 = (int)threadIdx.x % STR_SUB;
+  int i[STR_ROWS], b[STR_ROWS], e[STR_ROWS];
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    i[u] = str_row(u);
+    b[u] = i[u] < n ? rp[i[u]] : 0;
+    e[u] = i[u] < n ? rp[i[u] + 1] : 0;
+  }
+  int j[STR_ROWS], lo[STR_ROWS], hi[STR_ROWS], q[STR_ROWS];
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    const int k = b[u] + q0;
+    j[u] = k < e[u] ? ci[k] : i[u];
+  }
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    const bool act = j[u] != i[u];
+    lo[u] = act ? rp[j[u]] : 0;
+    hi[u] = act ? rp[j[u] + 1] - 1 : -1;
+    q[u] = -1;
+  }
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < STR_ROWS; ++u) {
+      if (lo[u] > hi[u]) continue;
+      any = true;
+      const int mid = (lo[u] + hi[u]) >> 1;
+      const int c = ci[mid];
+      if (c == i[u]) {
+        q[u] = mid;
+        lo[u] = 1;
+        hi[u] = 0;
+      } else if (c < i[u]) {
+        lo[u] = mid + 1;
+      } else {
+        hi[u] = mid - 1;
+      }
+    }
+    if (!any) break;
+  }
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u)
+    if (j[u] != i[u] && (q[u] < 0 || (check && v[q[u]] != v[b[u] + q0]))) bad = true;
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    if (i[u] >= n) continue;
+    for (int k = b[u] + q0 + STR_SUB; k < e[u] && !bad; k += STR_SUB) {
+      const int jj = ci[k];
+      if (jj == i[u]) continue;
+      const int qq = find_in_row(rp, ci, jj, i[u]);
+      if (qq < 0 || (check && v[qq] != v[k])) bad = true;
     }
   }
+  if (bad) atomicOr(flags, 4);
 }
 
 // ============================================================== strength
@@ -240,6 +297,19 @@ __global__ __launch_bounds__(256) void k_validate_sym(int n, const int* __restri
 // w_E(i,j) = max(-a_ij, 0), w_V(i) = a_ii, s_ij = w_E(i,j) w_E(j,i) / (a_ii a_jj).
 // sym: the values are known to be exactly symmetric (checked at setup), so
 // a_ji is a_ij and the transposed entry need not be looked up.
+__device__ inline double s_edge_v(double aij, double aji, double di, double dj) {
+  const double wij = (-aij > 0.0) ? -aij : 0.0;
+  const double wji = (-aji > 0.0) ? -aji : 0.0;
+  const double num = wij * wji;
+  const double den = di * dj;
+  return num / den;
+}
+__device__ inline double a_ji(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                              int i, int j, double aij, bool sym) {
+  if (sym) return aij;
+  const int q = find_in_row(rp, ci, j, i);
+  return q >= 0 ? v[q] : 0.0;
+}
 __device__ inline double s_edge(const int* __restrict__ rp, const int* __restrict__ ci,
                                 const double* __restrict__ v, const double* __restrict__ d, int i, int j,
                                 double aij, bool sym) {
@@ -248,65 +318,139 @@ __device__ inline double s_edge(const int* __restrict__ rp, const int* __restric
     const int q = find_in_row(rp, ci, j, i);
     aji = q >= 0 ? v[q] : 0.0;
   }
-  const double wij = (-aij > 0.0) ? -aij : 0.0;
-  const double wji = (-aji > 0.0) ? -aji : 0.0;
-  const double num = wij * wji;
-  const double den = d[i] * d[j];
-  return num / den;
+  return s_edge_v(aij, aji, d[i], d[j]);
 }
-
-// The strength kernels give each row STR_SUB consecutive lanes, which take
-// its entries in turn, so a row's entries are read by neighbouring lanes.
-constexpr int STR_SUB = 8;
 
 __global__ __launch_bounds__(256) void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                               const double* __restrict__ v, double* __restrict__ d) {
-  const int i = blockIdx.x * (256 / STR_SUB) + (int)threadIdx.x / STR_SUB, q0 = (int)threadIdx.x % STR_SUB;
-  if (i >= n) return;
-  for (int k = rp[i] + q0; k < rp[i + 1]; k += STR_SUB)
-    if (ci[k] == i) d[i] = v[k];
+  const int q0 = (int)threadIdx.x % STR_SUB;
+  int i[STR_ROWS], b[STR_ROWS], e[STR_ROWS], c[STR_ROWS];
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    i[u] = str_row(u);
+    b[u] = i[u] < n ? rp[i[u]] : 0;
+    e[u] = i[u] < n ? rp[i[u] + 1] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) c[u] = b[u] + q0 < e[u] ? ci[b[u] + q0] : -1;
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    if (c[u] == i[u]) d[i[u]] = v[b[u] + q0];
+    for (int k = b[u] + q0 + STR_SUB; k < e[u]; k += STR_SUB)
+      if (ci[k] == i[u]) d[i[u]] = v[k];
+  }
+}
+
+// Whether the entry (i, j) is an edge of row i's tile subgraph, the edges whose
+// strength eq. (symmetric_strong2) tests.
+__device__ inline bool in_tile_edge(int n, int T, int i, int j) {
+  const int lo = (i / T) * T, hi = min(lo + T, n);
+  return j != i && j >= lo && j < hi;
 }
 
 __global__ __launch_bounds__(256) void k_eta(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
                                              const double* __restrict__ v, const double* __restrict__ d,
                                              double* __restrict__ eta, int sym) {
-  const int i = blockIdx.x * (256 / STR_SUB) + (int)threadIdx.x / STR_SUB, q0 = (int)threadIdx.x % STR_SUB;
-  const bool row = i < n;
-  double e = 0.0;
-  if (row) {
-    const int lo = (i / T) * T, hi = min(lo + T, n);
-    for (int k = rp[i] + q0; k < rp[i + 1]; k += STR_SUB) {
-      const int j = ci[k];
-      if (j == i || j < lo || j >= hi) continue;
-      const double s = s_edge(rp, ci, v, d, i, j, v[k], sym != 0);
-      if (s > e) e = s;
-    }
+  const int q0 = (int)threadIdx.x % STR_SUB;
+  int i[STR_ROWS], b[STR_ROWS], e[STR_ROWS], j[STR_ROWS];
+  double a[STR_ROWS], di[STR_ROWS], dj[STR_ROWS], em[STR_ROWS];
+  bool in[STR_ROWS];
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    i[u] = str_row(u);
+    b[u] = i[u] < n ? rp[i[u]] : 0;
+    e[u] = i[u] < n ? rp[i[u] + 1] : 0;
   }
 #pragma unroll
-  for (int o = STR_SUB / 2; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o, STR_SUB));
-  if (row && q0 == 0) eta[i] = e;
+  for (int u = 0; u < STR_ROWS; ++u) {
+    const int k = b[u] + q0;
+    j[u] = k < e[u] ? ci[k] : i[u];
+    a[u] = k < e[u] ? v[k] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    in[u] = i[u] < n && in_tile_edge(n, T, i[u], j[u]);
+    di[u] = in[u] ? d[i[u]] : 1.0;
+    dj[u] = in[u] ? d[j[u]] : 1.0;
+  }
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    em[u] = 0.0;
+    if (in[u]) {
+      const double s = s_edge_v(a[u], a_ji(rp, ci, v, i[u], j[u], a[u], sym != 0), di[u], dj[u]);
+      if (s > em[u]) em[u] = s;
+    }
+    if (i[u] < n)
+      for (int k = b[u] + q0 + STR_SUB; k < e[u]; k += STR_SUB) {
+        const int jj = ci[k];
+        if (!in_tile_edge(n, T, i[u], jj)) continue;
+        const double s = s_edge(rp, ci, v, d, i[u], jj, v[k], sym != 0);
+        if (s > em[u]) em[u] = s;
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    double x = em[u];
+#pragma unroll
+    for (int o = STR_SUB / 2; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, STR_SUB));
+    if (i[u] < n && q0 == 0) eta[i[u]] = x;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_strong(int n, int T, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const double* __restrict__ v, const double* __restrict__ d,
                                                 const double* __restrict__ eta, double delta, double beta,
                                                 uint8_t* __restrict__ strong, uint8_t* __restrict__ iso, int sym) {
-  const int i = blockIdx.x * (256 / STR_SUB) + (int)threadIdx.x / STR_SUB, q0 = (int)threadIdx.x % STR_SUB;
-  if (i >= n) return;
-  const int lo = (i / T) * T, hi = min(lo + T, n);
-  const double ei = eta[i];
-  for (int k = rp[i] + q0; k < rp[i + 1]; k += STR_SUB) {
-    const int j = ci[k];
-    uint8_t f = 0;
-    if (j != i && j >= lo && j < hi) {
-      const double ej = eta[j];
-      const double m = ei < ej ? ei : ej;
-      const double s = s_edge(rp, ci, v, d, i, j, v[k], sym != 0);
-      f = (s > delta * m) ? 1 : 0;
-    }
-    strong[k] = f;
+  const int q0 = (int)threadIdx.x % STR_SUB;
+  int i[STR_ROWS], b[STR_ROWS], e[STR_ROWS], j[STR_ROWS];
+  double a[STR_ROWS], ei[STR_ROWS], ej[STR_ROWS], di[STR_ROWS], dj[STR_ROWS];
+  bool in[STR_ROWS];
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    i[u] = str_row(u);
+    b[u] = i[u] < n ? rp[i[u]] : 0;
+    e[u] = i[u] < n ? rp[i[u] + 1] : 0;
+    ei[u] = i[u] < n ? eta[i[u]] : 0.0;
   }
-  if (q0 == 0) iso[i] = (ei < beta) ? 1 : 0;
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    const int k = b[u] + q0;
+    j[u] = k < e[u] ? ci[k] : i[u];
+    a[u] = k < e[u] ? v[k] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    in[u] = i[u] < n && in_tile_edge(n, T, i[u], j[u]);
+    ej[u] = in[u] ? eta[j[u]] : 0.0;
+    di[u] = in[u] ? d[i[u]] : 1.0;
+    dj[u] = in[u] ? d[j[u]] : 1.0;
+  }
+#pragma unroll
+  for (int u = 0; u < STR_ROWS; ++u) {
+    if (i[u] >= n) continue;
+    const int k0 = b[u] + q0;
+    if (k0 < e[u]) {
+      uint8_t f = 0;
+      if (in[u]) {
+        const double m = ei[u] < ej[u] ? ei[u] : ej[u];
+        const double s = s_edge_v(a[u], a_ji(rp, ci, v, i[u], j[u], a[u], sym != 0), di[u], dj[u]);
+        f = (s > delta * m) ? 1 : 0;
+      }
+      strong[k0] = f;
+    }
+    for (int k = k0 + STR_SUB; k < e[u]; k += STR_SUB) {
+      const int jj = ci[k];
+      uint8_t f = 0;
+      if (in_tile_edge(n, T, i[u], jj)) {
+        const double ejj = eta[jj];
+        const double m = ei[u] < ejj ? ei[u] : ejj;
+        const double s = s_edge(rp, ci, v, d, i[u], jj, v[k], sym != 0);
+        f = (s > delta * m) ? 1 : 0;
+      }
+      strong[k] = f;
+    }
+    if (q0 == 0) iso[i[u]] = (ei[u] < beta) ? 1 : 0;
+  }
 }
 
 // ============================================================== aggregation
@@ -1615,10 +1759,12 @@ __global__ void k_perm_rowlen(int n, const int* __restrict__ perm, const int* __
   }
 }
 
-// One wavefront per solve row: copy the row's entries (same order) with the
-// columns relabelled.
-// `sub` consecutive threads (a power of two <= 64) copy one row; grid-stride
-// over rows, so the grid stays within the dispatch limits at any n.
+// Copy each solve row's entries (same order) with the columns relabelled.
+// `sub` consecutive threads (a power of two <= 64) copy one row, PERM_ROWS
+// rows per group (`per` rows apart) with the first `sub` entries of all of
+// them loaded together; grid-stride over rows, so the grid stays within the
+// dispatch limits at any n.
+constexpr int PERM_ROWS = 4;
 __global__ __launch_bounds__(256) void k_perm_rows(int n, int sub, const int* __restrict__ perm,
                                                    const int* __restrict__ pinv, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const double* __restrict__ v,
@@ -1626,12 +1772,39 @@ __global__ __launch_bounds__(256) void k_perm_rows(int n, int sub, const int* __
                                                    double* __restrict__ pv) {
   const int per = 256 / sub;
   const int q0 = (int)threadIdx.x % sub;
-  for (long long r = (long long)blockIdx.x * per + threadIdx.x / sub; r < n; r += (long long)gridDim.x * per) {
-    const int i = perm[r];
-    const int b = rp[i], len = rp[i + 1] - b, d = prp[r];
-    for (int q = q0; q < len; q += sub) {
-      pci[d + q] = pinv[ci[b + q]];
-      pv[d + q] = v[b + q];
+  const long long step = (long long)gridDim.x * per * PERM_ROWS;
+  for (long long r0 = (long long)blockIdx.x * per * PERM_ROWS + threadIdx.x / sub; r0 < n; r0 += step) {
+    int i[PERM_ROWS], b[PERM_ROWS], len[PERM_ROWS], d[PERM_ROWS], c[PERM_ROWS], pc[PERM_ROWS];
+    double x[PERM_ROWS];
+#pragma unroll
+    for (int u = 0; u < PERM_ROWS; ++u) {
+      const long long r = r0 + (long long)u * per;
+      i[u] = r < n ? perm[r] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < PERM_ROWS; ++u) {
+      const long long r = r0 + (long long)u * per;
+      b[u] = i[u] >= 0 ? rp[i[u]] : 0;
+      len[u] = i[u] >= 0 ? rp[i[u] + 1] - b[u] : 0;
+      d[u] = i[u] >= 0 ? prp[r] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PERM_ROWS; ++u) {
+      c[u] = q0 < len[u] ? ci[b[u] + q0] : 0;
+      x[u] = q0 < len[u] ? v[b[u] + q0] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PERM_ROWS; ++u) pc[u] = q0 < len[u] ? pinv[c[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < PERM_ROWS; ++u) {
+      if (q0 < len[u]) {
+        pci[d[u] + q0] = pc[u];
+        pv[d[u] + q0] = x[u];
+      }
+      for (int q = q0 + sub; q < len[u]; q += sub) {
+        pci[d[u] + q] = pinv[ci[b[u] + q]];
+        pv[d[u] + q] = v[b[u] + q];
+      }
     }
   }
 }
@@ -1908,14 +2081,15 @@ int validate_csr(int n, int nnz, const int* rp, const int* ci, const double* v, 
   AMG_HIP(hipGetLastError());
   int flags = read1(f.as<int>(), s);
   if (flags) return flags;
-  hipLaunchKernelGGL(k_validate_sym, dim3(cdiv(n, 32)), dim3(256), 0, s, n, rp, ci, v, check_symmetry, f.as<int>());
+  hipLaunchKernelGGL(k_validate_sym, dim3(cdiv(n, STR_BLOCK_ROWS)), dim3(256), 0, s, n, rp, ci, v, check_symmetry,
+                     f.as<int>());
   AMG_HIP(hipGetLastError());
   return read1(f.as<int>(), s);
 }
 
 void strength(const Level& L, double delta, double beta, uint8_t* strong, uint8_t* iso, bool sym, hipStream_t s) {
   DBuf d((size_t)L.n * sizeof(double), s), eta((size_t)L.n * sizeof(double), s);
-  const int g = cdiv(L.n, 256 / STR_SUB);
+  const int g = cdiv(L.n, STR_BLOCK_ROWS);
   AMG_HIP(hipMemsetAsync(d.p, 0, (size_t)L.n * sizeof(double), s));  // rows without a stored diagonal
   hipLaunchKernelGGL(k_diag, dim3(g), dim3(256), 0, s, L.n, L.rowptr, L.colind, L.vals, d.as<double>());
   hipLaunchKernelGGL(k_eta, dim3(g), dim3(256), 0, s, L.n, L.T, L.rowptr, L.colind, L.vals, d.as<double>(),
@@ -2431,7 +2605,8 @@ void permute_level(Hierarchy& H, int l, const int* next_perm, hipStream_t s) {
   double* pv = H.alloc<double>((size_t)nnz, s);
   int sub = 4;
   while (sub < 64 && (long long)sub * n < 2LL * nnz) sub *= 2;  // about the mean row length
-  hipLaunchKernelGGL(k_perm_rows, dim3(std::min(cdiv(n, 256 / sub), 1 << 20)), dim3(256), 0, s, n, sub, perm,
+  hipLaunchKernelGGL(k_perm_rows, dim3(std::min(cdiv(n, 256 / sub * PERM_ROWS), 1 << 20)), dim3(256), 0, s, n, sub,
+                     perm,
                      pinv.as<int>(), L.rowptr, L.colind,
                      L.vals, prp, pci, pv);
   // Coarse solve index of each natural coarse row (NULL: the next level is the
