@@ -2333,17 +2333,57 @@ __global__ __launch_bounds__(64) void k_hybrid_steps(int n, int T, const int* __
 // T rows (natural order) on its own, first fit over its rows in ascending
 // order on the couplings inside the tile (one wavefront per tile).  A row
 // takes its colour once every earlier coupled row of the tile has one, so
-// rows are coloured in rounds; the result is the sequential first fit.
+// rows are coloured in rounds; the result is the sequential first fit.  The
+// tile's couplings to earlier rows are staged in LDS first (16-bit local
+// indices, TL_STAGE_PER_ROW per row of the tile on average; a tile with more
+// reads the matrix in every round instead), so that a round costs a few LDS
+// reads per row.  LDS: colours and offsets (2T + 1 ints), then the staging.
 // mx[0]: most colours, mx[1]: set when a row would need more than 256.
 constexpr int TL_MAXC = 256;
+constexpr int TL_STAGE_PER_ROW = 16;
+inline size_t tile_local_lds_bytes(int T) {
+  return (size_t)(2 * T + 1) * sizeof(int) + (size_t)T * TL_STAGE_PER_ROW * sizeof(unsigned short);
+}
 __global__ __launch_bounds__(64) void k_colour_tile_local(int n, int T, const int* __restrict__ rowptr,
                                                           const int* __restrict__ colind, int* __restrict__ colour,
                                                           int* __restrict__ mx) {
-  __shared__ int cl[HS_MAX_T];
+  extern __shared__ int tl_lds[];
+  int* cl = tl_lds;
+  int* lp = tl_lds + T;
+  unsigned short* la = reinterpret_cast<unsigned short*>(tl_lds + 2 * T + 1);
   const int lo = (int)blockIdx.x * T, hi = min(n, lo + T), nt = hi - lo;
   const int lane = (int)threadIdx.x;
+  // earlier in-tile couplings per row, their offsets
+  int carry = 0;
+  for (int base = 0; base < nt; base += 64) {
+    const int q = base + lane;
+    int cnt = 0;
+    if (q < nt) {
+      const int i = lo + q;
+      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int j = colind[k];
+        cnt += (j >= lo && j < i) ? 1 : 0;
+      }
+    }
+    const int inc = wave_incl_scan(cnt);
+    if (q < nt) lp[q] = carry + inc - cnt;
+    carry += __shfl(inc, 63, 64);
+  }
+  if (lane == 0) lp[nt] = carry;
+  const bool staged = carry <= T * TL_STAGE_PER_ROW;
   for (int q = lane; q < nt; q += 64) cl[q] = -1;
   __syncthreads();
+  if (staged) {
+    for (int q = lane; q < nt; q += 64) {
+      const int i = lo + q;
+      int pos = lp[q];
+      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const int j = colind[k];
+        if (j >= lo && j < i) la[pos++] = (unsigned short)(j - lo);
+      }
+    }
+    __syncthreads();
+  }
   for (int round = 0; round <= nt; ++round) {
     bool left = false;
     for (int q = lane; q < nt; q += 64) {
@@ -2351,15 +2391,29 @@ __global__ __launch_bounds__(64) void k_colour_tile_local(int n, int T, const in
       const int i = lo + q;
       unsigned long long used[TL_MAXC / 64] = {0, 0, 0, 0};
       bool ready = true;
-      for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-        const int j = colind[k];
-        if (j < lo || j >= i) continue;
-        const int c = cl[j - lo];
-        if (c < 0) {
-          ready = false;
-          break;
+      if (staged) {
+        const int e = lp[q + 1];
+        for (int k0 = lp[q]; k0 < e && ready; k0 += 8) {
+          int c8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) c8[u] = k0 + u < e ? cl[la[k0 + u]] : TL_MAXC;  // past the row: no colour
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (c8[u] < 0) ready = false;
+            else if (c8[u] < TL_MAXC) used[c8[u] >> 6] |= 1ull << (c8[u] & 63);
+          }
         }
-        used[c >> 6] |= 1ull << (c & 63);
+      } else {
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+          const int j = colind[k];
+          if (j < lo || j >= i) continue;
+          const int c = cl[j - lo];
+          if (c < 0) {
+            ready = false;
+            break;
+          }
+          used[c >> 6] |= 1ull << (c & 63);
+        }
       }
       if (!ready) {
         left = true;
@@ -2391,8 +2445,8 @@ void colour_tile_local(Hierarchy& H, Level& L, hipStream_t s) {
   L.colour = H.alloc<int>((size_t)n, s);
   DBuf mx(2 * sizeof(int), s);
   AMG_HIP(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), s));
-  hipLaunchKernelGGL(k_colour_tile_local, dim3(ntiles), dim3(64), 0, s, n, T, L.rowptr, L.colind, L.colour,
-                     mx.as<int>());
+  hipLaunchKernelGGL(k_colour_tile_local, dim3(ntiles), dim3(64), tile_local_lds_bytes(T), s, n, T, L.rowptr,
+                     L.colind, L.colour, mx.as<int>());
   AMG_HIP(hipGetLastError());
   int bad = 0;
   read_ints(s, {{&L.ncol, mx.as<int>()}, {&bad, mx.as<int>() + 1}});
