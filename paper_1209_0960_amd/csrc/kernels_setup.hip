@@ -967,9 +967,14 @@ __global__ void k_term_count(int nc, const int* __restrict__ mptr, const int* __
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   int s = 0;
-  for (int p = mptr[I]; p < mptr[I + 1]; ++p) {
-    const int i = members[p];
-    s += rp[i + 1] - rp[i];
+  const int p1 = mptr[I + 1];
+  for (int p0 = mptr[I]; p0 < p1; p0 += 8) {  // 8 members per step, their loads in flight together
+    int mi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) mi[u] = p0 + u < p1 ? members[p0 + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (mi[u] >= 0) s += rp[mi[u] + 1] - rp[mi[u]];
   }
   tcount[I] = s;
   atomicMax(maxm, s);
@@ -2530,17 +2535,28 @@ __global__ void k_tile_rows(int n, int T, int ext, const int* __restrict__ soff,
   const int lo = i - i % T, hi = min(n, lo + T);
   const int t = i & 63, base = soff[i >> 6], w = (soff[(i >> 6) + 1] - base) >> 6;
   int c = ptr ? ptr[i] : 0;
-  for (int e = 0; e < w; ++e) {
-    const int j = scol[base + 64 * e + t];
-    const bool in = j >= lo && j < hi;
-    if (ext ? in : (!in || j == i)) continue;
-    if (ptr) {
-      if (col16) col16[c] = (unsigned short)(j - lo);
-      if (col32) col32[c] = j;
-      if (v64) v64[c] = sval[base + 64 * e + t];
-      if (v32) v32[c] = (float)sval[base + 64 * e + t];
+  const bool vals = v64 || v32;
+  for (int e0 = 0; e0 < w; e0 += 8) {  // 8 slots of the row per step, their loads in flight together
+    int jj[8];
+    double vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) jj[u] = e0 + u < w ? scol[base + 64 * (e0 + u) + t] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vv[u] = vals && e0 + u < w ? sval[base + 64 * (e0 + u) + t] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (e0 + u >= w) break;
+      const int j = jj[u];
+      const bool in = j >= lo && j < hi;
+      if (ext ? in : (!in || j == i)) continue;
+      if (ptr) {
+        if (col16) col16[c] = (unsigned short)(j - lo);
+        if (col32) col32[c] = j;
+        if (v64) v64[c] = vv[u];
+        if (v32) v32[c] = (float)vv[u];
+      }
+      ++c;
     }
-    ++c;
   }
   if (!ptr) {
     cnt[i] = c;
