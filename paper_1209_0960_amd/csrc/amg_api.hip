@@ -779,6 +779,10 @@ amg_status amg_setup_batched(const amg_csr* A, int32_t nsys, const amg_params* p
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int nthreads = std::max(1, std::min<int>(nsys, 16));
+  // largest systems first, so that the last setups to start are short ones
+  std::vector<int> order(nsys);
+  for (int i = 0; i < nsys; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return A[a].nnz > A[b].nnz; });
   std::atomic<int> next{0};
   std::vector<amg_status> st(nsys, AMG_OK);
   std::vector<std::string> msg(nsys);
@@ -786,7 +790,8 @@ amg_status amg_setup_batched(const amg_csr* A, int32_t nsys, const amg_params* p
     (void)hipSetDevice(dev);
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
-    for (int i = next++; i < nsys; i = next++) {
+    for (int k = next++; k < nsys; k = next++) {
+      const int i = order[k];
       if (!s) {
         st[i] = AMG_ERR_HIP;
         msg[i] = "stream creation failed";
