@@ -980,26 +980,46 @@ __global__ void k_term_count(int nc, const int* __restrict__ mptr, const int* __
   atomicMax(maxm, s);
 }
 
-template <typename IdxT>
+// A group of W lanes (W = 64: the wavefront; W = 32: half of it) per coarse
+// row; gl = lane inside the group.  The ballots are taken over the wavefront
+// and cut to the group's bits.
+template <int W>
+__device__ __forceinline__ int group_incl_scan(int v, int gl) {
+#pragma unroll
+  for (int d = 1; d < W; d <<= 1) {
+    const int t = __shfl_up(v, d, W);
+    if (gl >= d) v += t;
+  }
+  return v;
+}
+template <int W>
+__device__ __forceinline__ uint64_t group_ballot(bool p) {
+  const uint64_t b = __ballot(p);
+  if (W == 64) return b;
+  return (b >> (__lane_id() & ~(W - 1))) & ((1ull << W) - 1);
+}
+
+template <typename IdxT, int W>
 __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr, const int* __restrict__ members,
                              const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ va,
                              const int* __restrict__ agg, int* J, double* V, IdxT* Sx, int* __restrict__ tcol,
                              double* __restrict__ tval, int* __restrict__ ucount) {
-  const int lane = __lane_id();
+  const int gl = __lane_id() & (W - 1);
+  const uint64_t lt = (1ull << gl) - 1ull;
   // Terms in member order, CSR order inside a member: lane q takes member q,
   // finds its first term by a scan of the row lengths and copies its entries
   // with their loads in flight together.
   const int p0 = mptr[I], nm = mptr[I + 1] - p0;
   int pos = 0;
-  for (int base = 0; base < nm; base += WAVE) {
-    const int q = base + lane;
+  for (int base = 0; base < nm; base += W) {
+    const int q = base + gl;
     int b = 0, len = 0;
     if (q < nm) {
       const int i = members[p0 + q];
       b = rp[i];
       len = rp[i + 1] - b;
     }
-    const int inc = wave_incl_scan(len);
+    const int inc = group_incl_scan<W>(len, gl);
     const int off = pos + inc - len;
     for (int k0 = 0; k0 < len; k0 += 8) {
       int cc[8];
@@ -1019,13 +1039,13 @@ __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr,
           V[off + k0 + u] = vv[u];
         }
     }
-    pos += __shfl(inc, WAVE - 1, WAVE);
+    pos += __shfl(inc, W - 1, W);
   }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
   // Rank of term t among the terms ordered by (J, position): a stable
   // counting sort, reading 8 terms per step with their loads in flight together.
-  for (int t = lane; t < m; t += WAVE) {
+  for (int t = gl; t < m; t += W) {
     const int Jt = J[t];
     int r = 0, u = 0;
     for (; u + 8 <= m; u += 8) {
@@ -1044,22 +1064,22 @@ __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr,
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
   // Equal-J runs in rank order, each summed sequentially from its first term
-  // by the run's head; the run's end inside this chunk of 64 ranks comes from
+  // by the run's head; the run's end inside this chunk of W ranks comes from
   // the ballot of heads, so its loads are independent of the additions.
   int cnt = 0;
-  for (int base = 0; base < m; base += WAVE) {
-    const int r = base + lane;
+  for (int base = 0; base < m; base += W) {
+    const int r = base + gl;
     bool head = false;
     int Jr = 0;
     if (r < m) {
       Jr = J[Sx[r]];
       head = (r == 0) || (J[Sx[r - 1]] != Jr);
     }
-    const uint64_t hm = __ballot(head);
+    const uint64_t hm = group_ballot<W>(head);
     if (head) {
-      const int o = cnt + __popcll(hm & lanemask_lt());
-      const uint64_t after = lane == WAVE - 1 ? 0ull : (hm >> (lane + 1));
-      const int end = after ? r + 1 + (int)__builtin_ctzll(after) : min(m, base + WAVE);
+      const int o = cnt + __popcll(hm & lt);
+      const uint64_t after = gl == W - 1 ? 0ull : (hm >> (gl + 1));
+      const int end = after ? r + 1 + (int)__builtin_ctzll(after) : min(m, base + W);
       double acc = V[Sx[r]];
 #pragma unroll 4
       for (int q = r + 1; q < end; ++q) acc = acc + V[Sx[q]];
@@ -1070,10 +1090,10 @@ __device__ void galerkin_row(int I, int m, int tb, const int* __restrict__ mptr,
     }
     cnt += __popcll(hm);
   }
-  if (lane == 0) ucount[I] = cnt;
+  if (gl == 0) ucount[I] = cnt;
 }
 
-__global__ __launch_bounds__(GAL_WAVES* WAVE) void k_galerkin_rows(
+__global__ __launch_bounds__(GAL_WAVES* WAVE, 8) void k_galerkin_rows(
     int nc, const int* __restrict__ mptr, const int* __restrict__ members, const int* __restrict__ rp,
     const int* __restrict__ ci, const double* __restrict__ va, const int* __restrict__ agg,
     const int* __restrict__ toff, int* gJ, double* gV, int* gS, int* __restrict__ tcol, double* __restrict__ tval,
@@ -1087,9 +1107,27 @@ __global__ __launch_bounds__(GAL_WAVES* WAVE) void k_galerkin_rows(
   const int tb = toff[I];
   const int m = toff[I + 1] - tb;
   if (m <= GAL_CAP)
-    galerkin_row<short>(I, m, tb, mptr, members, rp, ci, va, agg, sJ[w], sV[w], sS[w], tcol, tval, ucount);
+    galerkin_row<short, WAVE>(I, m, tb, mptr, members, rp, ci, va, agg, sJ[w], sV[w], sS[w], tcol, tval, ucount);
   else
-    galerkin_row<int>(I, m, tb, mptr, members, rp, ci, va, agg, gJ + tb, gV + tb, gS + tb, tcol, tval, ucount);
+    galerkin_row<int, WAVE>(I, m, tb, mptr, members, rp, ci, va, agg, gJ + tb, gV + tb, gS + tb, tcol, tval, ucount);
+}
+
+// The same with half a wavefront per coarse row, for levels whose rows all
+// have at most GAL_CAP / 2 terms: twice the rows in flight in the same LDS.
+__global__ __launch_bounds__(GAL_WAVES* WAVE) void k_galerkin_rows_half(
+    int nc, const int* __restrict__ mptr, const int* __restrict__ members, const int* __restrict__ rp,
+    const int* __restrict__ ci, const double* __restrict__ va, const int* __restrict__ agg,
+    const int* __restrict__ toff, int* __restrict__ tcol, double* __restrict__ tval, int* __restrict__ ucount) {
+  constexpr int HW = WAVE / 2, CAP = GAL_CAP / 2;
+  __shared__ int sJ[2 * GAL_WAVES][CAP];
+  __shared__ double sV[2 * GAL_WAVES][CAP];
+  __shared__ short sS[2 * GAL_WAVES][CAP];
+  const int w = threadIdx.x / HW;
+  const int I = blockIdx.x * 2 * GAL_WAVES + w;
+  if (I >= nc) return;
+  const int tb = toff[I];
+  const int m = toff[I + 1] - tb;
+  galerkin_row<short, HW>(I, m, tb, mptr, members, rp, ci, va, agg, sJ[w], sV[w], sS[w], tcol, tval, ucount);
 }
 
 // 16 lanes per coarse row, so the copies are contiguous across lanes.
@@ -2160,9 +2198,14 @@ void galerkin(Hierarchy& H, const Level& L, Level& C, hipStream_t s) {
     gV = DBuf((size_t)total * sizeof(double), s);
     gS = DBuf((size_t)total * sizeof(int), s);
   }
-  hipLaunchKernelGGL(k_galerkin_rows, dim3(cdiv(nc, GAL_WAVES)), dim3(GAL_WAVES * WAVE), 0, s, nc, L.mptr,
-                     L.members, L.rowptr, L.colind, L.vals, L.agg, toff.as<int>(), gJ.as<int>(), gV.as<double>(),
-                     gS.as<int>(), tcol.as<int>(), tval.as<double>(), ucount.as<int>());
+  if (maxm <= GAL_CAP / 2)
+    hipLaunchKernelGGL(k_galerkin_rows_half, dim3(cdiv(nc, 2 * GAL_WAVES)), dim3(GAL_WAVES * WAVE), 0, s, nc, L.mptr,
+                       L.members, L.rowptr, L.colind, L.vals, L.agg, toff.as<int>(), tcol.as<int>(),
+                       tval.as<double>(), ucount.as<int>());
+  else
+    hipLaunchKernelGGL(k_galerkin_rows, dim3(cdiv(nc, GAL_WAVES)), dim3(GAL_WAVES * WAVE), 0, s, nc, L.mptr,
+                       L.members, L.rowptr, L.colind, L.vals, L.agg, toff.as<int>(), gJ.as<int>(), gV.as<double>(),
+                       gS.as<int>(), tcol.as<int>(), tval.as<double>(), ucount.as<int>());
   AMG_HIP(hipGetLastError());
   C.n = nc;
   C.rowptr = H.alloc<int>((size_t)nc + 1, s);
