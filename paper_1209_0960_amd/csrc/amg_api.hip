@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cstring>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <unordered_map>
 #include <mutex>
@@ -208,14 +210,16 @@ void dfree(void* p, hipStream_t s) {
 
 void Hierarchy::free_one(void* ptr, hipStream_t s) {
   if (!ptr) return;
-  for (size_t k = 0; k < owned.size(); ++k)
-    if (owned[k].first == ptr) {
-      bytes -= owned[k].second;
-      owned[k] = owned.back();
-      owned.pop_back();
-      dfree(ptr, s);
-      return;
-    }
+  {
+    std::lock_guard<std::mutex> g(owned_mu);
+    size_t k = 0;
+    while (k < owned.size() && owned[k].first != ptr) ++k;
+    if (k == owned.size()) return;
+    bytes -= owned[k].second;
+    owned[k] = owned.back();
+    owned.pop_back();
+  }
+  dfree(ptr, s);
 }
 
 void Hierarchy::release(hipStream_t s) {
@@ -350,7 +354,118 @@ void check_params(const amg_params& p) {
     fail(AMG_ERR_UNSUPPORTED, "point-based levels (block_size > 1) are not cycled by the one-workgroup tail");
 }
 
-void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy& H) {
+// Colouring of level l for its smoother (the colour-ordered relabelling comes
+// later, once the coarsest level is known).
+void colour_level(Hierarchy& H, int l, hipStream_t s) {
+  const amg_params& p = H.p;
+  Level& L = H.lev[l];
+  const int sm = level_smoother(p, l), bs = p.block_size;
+  if (sm == AMG_SMOOTHER_HYBRID_SGS) {
+    colour_single(H, L, s);
+  } else if (sm == AMG_SMOOTHER_TILE_MCSGS) {  // tile-local colours set the sweep order inside a tile
+    colour_tile_local(H, L, smooth_tile(p, l), s);
+  } else if (bs > 1) {  // node colours, shared by each node's unknowns
+    Level S;
+    node_graph(H, L, bs, S, s);
+    colour(H, S, p.colour_seed + (uint32_t)l, s);
+    expand_colours(H, S, bs, L, s);
+    release_level(H, S, s);
+  } else {
+    colour(H, L, p.colour_seed + (uint32_t)l, s);
+  }
+}
+
+// Colours the levels beside the coarsening: a second host thread, with a
+// stream of its own, colours level l as soon as its matrix exists (level 0 at
+// once, level l + 1 after its Galerkin product), so that the colouring's
+// chains of small launches and host round trips overlap the aggregation's.
+// The two threads touch different fields of a level; the level vector is
+// reserved in full beforehand so that it never moves.
+class ColourWorker {
+ public:
+  // threaded = false: every level is coloured at once on the caller's thread
+  // and stream (push).
+  ColourWorker(Hierarchy& H, bool threaded) : H_(H), threaded_(threaded) {
+    if (!threaded_) return;
+    (void)hipGetDevice(&dev_);
+    s2_ = stream_take();
+    th_ = std::thread([this] { run(); });
+  }
+  ~ColourWorker() { stop(); }
+  ColourWorker(const ColourWorker&) = delete;
+  ColourWorker& operator=(const ColourWorker&) = delete;
+  // Level l's matrix is complete once stream s reaches this point.
+  void push(int l, hipStream_t s) {
+    if (!threaded_) {
+      colour_level(H_, l, s);
+      return;
+    }
+    hipEvent_t e = event_take();
+    AMG_HIP(hipEventRecord(e, s));
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      q_.emplace_back(l, e);
+    }
+    cv_.notify_one();
+  }
+  // Waits for every pushed level; the first failure is raised here.
+  void finish() {
+    stop();
+    if (st_ != AMG_OK) fail(st_, msg_);
+  }
+
+ private:
+  void stop() {
+    if (!th_.joinable()) return;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      done_ = true;
+    }
+    cv_.notify_one();
+    th_.join();
+    stream_give(s2_);
+  }
+  void run() {
+    (void)hipSetDevice(dev_);
+    for (;;) {
+      std::pair<int, hipEvent_t> item;
+      {
+        std::unique_lock<std::mutex> g(mu_);
+        cv_.wait(g, [&] { return done_ || !q_.empty(); });
+        if (q_.empty()) break;
+        item = q_.front();
+        q_.pop_front();
+      }
+      if (st_ == AMG_OK) {
+        try {
+          AMG_HIP(hipStreamWaitEvent(s2_, item.second, 0));
+          colour_level(H_, item.first, s2_);
+        } catch (const Failure& e) {
+          st_ = e.st;
+          msg_ = amg_last_error();
+        } catch (const std::bad_alloc&) {
+          st_ = AMG_ERR_OUT_OF_MEMORY;
+          msg_ = "host allocation failed";
+        }
+      }
+      event_give(item.second);
+    }
+    (void)sync_stream_nothrow(s2_);
+  }
+  Hierarchy& H_;
+  bool threaded_;
+  int dev_ = 0;
+  hipStream_t s2_ = nullptr;
+  std::thread th_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::pair<int, hipEvent_t>> q_;
+  bool done_ = false;
+  amg_status st_ = AMG_OK;
+  std::string msg_;
+};
+
+void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy& H, bool overlap) {
   const double t0 = now_ms();
   if (!A || !pp) fail(AMG_ERR_INVALID_ARG, "NULL argument");
   H.p = *pp;
@@ -368,6 +483,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     fail(AMG_ERR_INVALID_ARG, "block_size > 1 needs every node's rows to hold whole blocks, the diagonal block included");
 
   H.lev.clear();
+  H.lev.reserve(MAX_LEVELS + 1);  // never reallocated while the colouring thread reads it
   H.lev.emplace_back();
   {
     Level& L0 = H.lev[0];
@@ -381,14 +497,13 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     AMG_HIP(hipMemcpyAsync(L0.vals, A->vals, (size_t)A->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   const amg_params& p = H.p;
+  H.lev[0].T = p.tile_rows;
+  H.lev[0].ntiles = (H.lev[0].n + p.tile_rows - 1) / p.tile_rows;
+  ColourWorker colouring(H, overlap);
+  colouring.push(0, s);
   for (;;) {
     const int l = (int)H.lev.size() - 1;
-    {
-      Level& L = H.lev[l];
-      L.T = p.tile_rows;
-      L.ntiles = (L.n + L.T - 1) / L.T;
-      if (L.n <= p.coarse_max || l == p.max_levels - 1) break;
-    }
+    if (H.lev[l].n <= p.coarse_max || l == p.max_levels - 1) break;
     uint8_t *strong, *iso;
     DBuf ts, ti;
     // point-based levels: strength and aggregation on the node graph
@@ -426,7 +541,11 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     }
     H.lev.emplace_back();
     galerkin(H, H.lev[l], H.lev[l + 1], s);
+    H.lev[l + 1].T = p.tile_rows;
+    H.lev[l + 1].ntiles = (H.lev[l + 1].n + p.tile_rows - 1) / p.tile_rows;
+    colouring.push(l + 1, s);
   }
+  colouring.finish();
   const int Lc = (int)H.lev.size() - 1;
   H.lev[Lc].nc = 0;
   const bool f32 = p.vcycle_fp32 != 0;
@@ -436,20 +555,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     // from here on a level's tiles are its smoothing tiles (aggregation is done)
     H.lev[l].T = smooth_tile(p, l);
     H.lev[l].ntiles = (H.lev[l].n + H.lev[l].T - 1) / H.lev[l].T;
-    if (H.lev[l].sm == AMG_SMOOTHER_HYBRID_SGS) {
-      colour_single(H, H.lev[l], s);
-    } else if (H.lev[l].sm == AMG_SMOOTHER_TILE_MCSGS) {  // tile-local colours set the sweep order inside a tile
-      colour_tile_local(H, H.lev[l], s);
-      tile_colour_order(H, H.lev[l], l < Lc, s);
-    } else if (bs > 1) {  // node colours, shared by each node's unknowns
-      Level S;
-      node_graph(H, H.lev[l], bs, S, s);
-      colour(H, S, p.colour_seed + (uint32_t)l, s);
-      expand_colours(H, S, bs, H.lev[l], s);
-      release_level(H, S, s);
-    } else {
-      colour(H, H.lev[l], p.colour_seed + (uint32_t)l, s);
-    }
+    if (H.lev[l].sm == AMG_SMOOTHER_TILE_MCSGS) tile_colour_order(H, H.lev[l], l < Lc, s);
   }
   // Relabel every level above the coarsest into colour order (the coarsest
   // keeps its natural order for the dense solve).
@@ -542,7 +648,10 @@ amg_status amg_default_params(amg_params* p) {
   return AMG_OK;
 }
 
-amg_status amg_setup(const amg_csr* A, const amg_params* p, void* stream, amg_hierarchy** out) {
+namespace {
+// overlap: colour the levels from a second host thread beside the coarsening
+// (a single setup); the setups of a batch already overlap one another.
+amg_status setup_one(const amg_csr* A, const amg_params* p, hipStream_t stream, amg_hierarchy** out, bool overlap) {
   if (!out) {
     set_error("out is NULL");
     return AMG_ERR_INVALID_ARG;
@@ -555,16 +664,21 @@ amg_status amg_setup(const amg_csr* A, const amg_params* p, void* stream, amg_hi
     set_error("host allocation failed");
     return AMG_ERR_OUT_OF_MEMORY;
   }
-  amg_status st = guarded([&] { setup_impl(A, p, S(stream), h->H); });
+  amg_status st = guarded([&] { setup_impl(A, p, stream, h->H, overlap); });
   if (st != AMG_OK) {
-    (void)sync_stream_nothrow(S(stream));
-    h->H.release(S(stream));
-    (void)sync_stream_nothrow(S(stream));
+    (void)sync_stream_nothrow(stream);
+    h->H.release(stream);
+    (void)sync_stream_nothrow(stream);
     delete h;
     return st;
   }
   *out = h;
   return AMG_OK;
+}
+}  // namespace
+
+amg_status amg_setup(const amg_csr* A, const amg_params* p, void* stream, amg_hierarchy** out) {
+  return setup_one(A, p, S(stream), out, true);
 }
 
 amg_status amg_precond_apply(amg_hierarchy* h, const double* r, double* z, void* stream) {
@@ -797,7 +911,7 @@ amg_status amg_setup_batched(const amg_csr* A, int32_t nsys, const amg_params* p
         msg[i] = "stream creation failed";
         continue;
       }
-      st[i] = amg_setup(&A[i], p, s, &out[i]);
+      st[i] = setup_one(&A[i], p, s, &out[i], false);
       if (st[i] != AMG_OK) msg[i] = amg_last_error();
       if (out[i]) out[i]->H.setup_stream = us;
     }

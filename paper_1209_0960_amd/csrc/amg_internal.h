@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -191,6 +192,7 @@ struct Hierarchy {
   Batch* single = nullptr;
   size_t bytes = 0;
   std::vector<std::pair<void*, size_t>> owned;
+  std::mutex owned_mu;  // alloc / free_one from the setup's two host threads
   hipStream_t setup_stream = nullptr;
   // Recorded on the caller's stream after each amg_precond_apply (which runs
   // there, asynchronously); release() waits for it before any buffer returns
@@ -204,6 +206,7 @@ struct Hierarchy {
     size_t b = count * sizeof(T);
     if (b == 0) b = sizeof(T);
     void* ptr = dalloc(b, s);
+    std::lock_guard<std::mutex> g(owned_mu);
     owned.emplace_back(ptr, b);
     bytes += b;
     return static_cast<T*>(ptr);
@@ -270,9 +273,9 @@ void colour_single(Hierarchy& H, Level& L, hipStream_t s);
 // build_sell; the level has one colour).
 void hybrid_steps(Hierarchy& H, Level& L, int T, hipStream_t s);
 // Colouring of a level of the tile-ordered multicolour smoother: every tile
-// of L.T rows on its own, first fit over its rows ascending on the couplings
+// of T rows (the level's smoothing tiles) on its own, first fit over its rows ascending on the couplings
 // inside the tile (natural order, before relabelling).
-void colour_tile_local(Hierarchy& H, Level& L, hipStream_t s);
+void colour_tile_local(Hierarchy& H, Level& L, int T, hipStream_t s);
 // After colour_tile_local on a level of the tile-ordered multicolour smoother: the
 // solve order takes each tile's rows colour by colour (reorder; the coarsest
 // level keeps natural order), one colour for the slices, the colours in
@@ -290,6 +293,11 @@ constexpr int HS_G = 4;
 inline int level_smoother(const amg_params& p, int l) {
   return p.coarse_smoother >= 0 && l >= p.coarse_from ? p.coarse_smoother : p.smoother;
 }
+// Process-wide pools of streams and events (reused across calls).
+hipStream_t stream_take();
+void stream_give(hipStream_t st);  // synchronises the stream first
+hipEvent_t event_take();
+void event_give(hipEvent_t e);
 // Whether level l's smoother runs as tile sweeps (the hybrid smoother, in
 // natural or colour order: the same launches, the order is in the steps).
 inline bool tile_sweeps(int sm) { return sm == AMG_SMOOTHER_HYBRID_SGS || sm == AMG_SMOOTHER_TILE_MCSGS; }

@@ -74,6 +74,9 @@ int current_device() {
   (void)hipGetDevice(&d);
   return d;
 }
+
+}  // namespace
+
 hipStream_t stream_take() {
   const int dev = current_device();
   {
@@ -117,8 +120,6 @@ void event_give(hipEvent_t e) {
   std::lock_guard<std::mutex> g(g_pool_mu);
   g_events.emplace_back(current_device(), e);
 }
-
-}  // namespace
 
 // Device vectors of one entry (right-hand sides interleaved, solve order),
 // carved from one allocation.

@@ -2487,8 +2487,8 @@ __global__ __launch_bounds__(64) void k_colour_tile_local(int n, int T, const in
   if (lane == 0) atomicMax(mx, cmax);
 }
 
-void colour_tile_local(Hierarchy& H, Level& L, hipStream_t s) {
-  const int n = L.n, T = L.T, ntiles = cdiv(n, T);
+void colour_tile_local(Hierarchy& H, Level& L, int T, hipStream_t s) {
+  const int n = L.n, ntiles = cdiv(n, T);
   if (T > HS_MAX_T) fail(AMG_ERR_UNSUPPORTED, "tile sweeps take tiles of at most 1024 rows");
   L.colour = H.alloc<int>((size_t)n, s);
   DBuf mx(2 * sizeof(int), s);
