@@ -230,6 +230,48 @@ def test_error_paths(A):
         O.Hierarchy(s.rowptr, s.colind, vv)
 
 
+def spoke_matrix(tiles=2100, T=64):
+    """SPD chain (tridiagonal 4, -1) with row 0 also coupled to the first row
+    of each of `tiles` - 1 other T-row tiles: row 0's tile has more
+    neighbour tiles than the multicolour colouring's tile graph holds."""
+    n = tiles * T
+    spokes = np.arange(T, n, T)
+    rows = [np.arange(n), np.arange(1, n), np.arange(n - 1), np.zeros(len(spokes), int), spokes]
+    cols = [np.arange(n), np.arange(n - 1), np.arange(1, n), spokes, np.zeros(len(spokes), int)]
+    vals = [np.full(n, 4.0), np.full(n - 1, -1.0), np.full(n - 1, -1.0), np.full(len(spokes), -0.5),
+            np.full(len(spokes), -0.5)]
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    v[(r == 0) & (c == 0)] += 0.5 * len(spokes)  # diagonally dominant rows: SPD
+    v[(r == c) & (r % T == 0) & (r > 0)] = 4.5
+    o = np.lexsort((c, r))
+    r, c, v = r[o], c[o], v[o]
+    d = np.r_[0, np.cumsum(np.bincount(r, minlength=n))].astype(np.int32)
+    return d, c.astype(np.int32), v, n
+
+
+def test_failure_in_the_colouring_thread(A):
+    """Level 0's multicolour colouring fails (row 0's tile has more than 2048
+    neighbour tiles) while the coarsening goes on beside it: the setup
+    reports UNSUPPORTED, in a single setup (colouring on its own host thread)
+    and in a batch (colouring inline); the hybrid smoother, which needs no
+    such colouring, sets up the same matrix; a later setup works."""
+    d, c, v, n = spoke_matrix()
+    rp, ci, vv = (torch.from_numpy(d).cuda(), torch.from_numpy(c).cuda(), torch.from_numpy(v).cuda())
+    with pytest.raises(A.AMGError) as e:
+        A.Hierarchy(rp, ci, vv, colour_tile_rows=64)
+    assert e.value.status == A.ERR_UNSUPPORTED and "neighbour tiles" in str(e.value)
+    with pytest.raises(A.AMGError) as e:
+        A.Hierarchy.batched([(rp, ci, vv), (rp, ci, vv)], colour_tile_rows=64)
+    assert e.value.status == A.ERR_UNSUPPORTED
+    with A.Hierarchy(rp, ci, vv, colour_tile_rows=64, smoother=2) as h:
+        assert h.levels >= 2
+    s = P.poisson(12)
+    rp2, ci2, v2, b2 = dev(s)
+    with A.Hierarchy(rp2, ci2, v2) as h:
+        x, r = h.solve(b2, rtol=1e-8)
+        assert r.status == A.OK
+
+
 def test_not_converged_keeps_last_iterate(A):
     s = system("hetero_24")
     rp, ci, v, b = dev(s)
