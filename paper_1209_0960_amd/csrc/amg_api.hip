@@ -375,46 +375,74 @@ void colour_level(Hierarchy& H, int l, hipStream_t s) {
   }
 }
 
-// Colours the levels beside the coarsening: a second host thread, with a
-// stream of its own, colours level l as soon as its matrix exists (level 0 at
-// once, level l + 1 after its Galerkin product), so that the colouring's
-// chains of small launches and host round trips overlap the aggregation's.
-// The two threads touch different fields of a level; the level vector is
-// reserved in full beforehand so that it never moves.
-class ColourWorker {
+// Setup work beside the coarsening: a second host thread, with a stream of
+// its own, colours level l as soon as its matrix exists (level 0 at once,
+// level l + 1 after its Galerkin product) and factorises the coarsest level
+// once it is known, so that these chains of small launches and host round
+// trips overlap the coarsening and the relabelling of the finer levels.  The
+// two threads touch different fields of a level; the level vector is
+// reserved in full beforehand so that it never moves.  threaded = false: every
+// task runs at once on the caller's thread and stream.
+class SideThread {
  public:
-  // threaded = false: every level is coloured at once on the caller's thread
-  // and stream (push).
-  ColourWorker(Hierarchy& H, bool threaded) : H_(H), threaded_(threaded) {
+  SideThread(Hierarchy& H, bool threaded) : H_(H), threaded_(threaded) {
     if (!threaded_) return;
     (void)hipGetDevice(&dev_);
     s2_ = stream_take();
     th_ = std::thread([this] { run(); });
   }
-  ~ColourWorker() { stop(); }
-  ColourWorker(const ColourWorker&) = delete;
-  ColourWorker& operator=(const ColourWorker&) = delete;
-  // Level l's matrix is complete once stream s reaches this point.
-  void push(int l, hipStream_t s) {
-    if (!threaded_) {
-      colour_level(H_, l, s);
-      return;
+  ~SideThread() { stop(); }
+  SideThread(const SideThread&) = delete;
+  SideThread& operator=(const SideThread&) = delete;
+  // Colour level l (its matrix is complete once stream s reaches this point).
+  void colour(int l, hipStream_t s) { push(COLOUR, l, s); }
+  // Dense factorisation of the coarsest level l.
+  void factor(int l, hipStream_t s) { push(FACTOR, l, s); }
+  // Waits until every level pushed so far is coloured; raises the first
+  // failure.
+  void wait_colours() {
+    if (!threaded_) return;
+    std::unique_lock<std::mutex> g(mu_);
+    done_cv_.wait(g, [&] { return coloured_ == colours_; });
+    if (st_ != AMG_OK) {
+      g.unlock();
+      stop();
+      fail(st_, msg_);
     }
-    hipEvent_t e = event_take();
-    AMG_HIP(hipEventRecord(e, s));
-    {
-      std::lock_guard<std::mutex> g(mu_);
-      q_.emplace_back(l, e);
-    }
-    cv_.notify_one();
   }
-  // Waits for every pushed level; the first failure is raised here.
+  // Waits for every task; raises the first failure.
   void finish() {
     stop();
     if (st_ != AMG_OK) fail(st_, msg_);
   }
 
  private:
+  enum Kind { COLOUR, FACTOR };
+  struct Task {
+    Kind kind;
+    int l;
+    hipEvent_t ready;
+  };
+  void run_task(Kind kind, int l, hipStream_t s) {
+    if (kind == COLOUR)
+      colour_level(H_, l, s);
+    else
+      coarse_factor(H_, H_.lev[l], s);
+  }
+  void push(Kind kind, int l, hipStream_t s) {
+    if (!threaded_) {
+      run_task(kind, l, s);
+      return;
+    }
+    hipEvent_t e = event_take();
+    AMG_HIP(hipEventRecord(e, s));
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      q_.push_back({kind, l, e});
+      if (kind == COLOUR) ++colours_;
+    }
+    cv_.notify_one();
+  }
   void stop() {
     if (!th_.joinable()) return;
     {
@@ -428,27 +456,39 @@ class ColourWorker {
   void run() {
     (void)hipSetDevice(dev_);
     for (;;) {
-      std::pair<int, hipEvent_t> item;
+      Task t;
       {
         std::unique_lock<std::mutex> g(mu_);
         cv_.wait(g, [&] { return done_ || !q_.empty(); });
         if (q_.empty()) break;
-        item = q_.front();
+        t = q_.front();
         q_.pop_front();
       }
+      amg_status st = AMG_OK;
+      std::string msg;
       if (st_ == AMG_OK) {
         try {
-          AMG_HIP(hipStreamWaitEvent(s2_, item.second, 0));
-          colour_level(H_, item.first, s2_);
+          AMG_HIP(hipStreamWaitEvent(s2_, t.ready, 0));
+          run_task(t.kind, t.l, s2_);
+          if (t.kind == COLOUR) sync_stream(s2_);  // the colours are complete when counted
         } catch (const Failure& e) {
-          st_ = e.st;
-          msg_ = amg_last_error();
+          st = e.st;
+          msg = amg_last_error();
         } catch (const std::bad_alloc&) {
-          st_ = AMG_ERR_OUT_OF_MEMORY;
-          msg_ = "host allocation failed";
+          st = AMG_ERR_OUT_OF_MEMORY;
+          msg = "host allocation failed";
         }
       }
-      event_give(item.second);
+      event_give(t.ready);
+      {
+        std::lock_guard<std::mutex> g(mu_);
+        if (st != AMG_OK && st_ == AMG_OK) {
+          st_ = st;
+          msg_ = msg;
+        }
+        if (t.kind == COLOUR) ++coloured_;
+      }
+      done_cv_.notify_all();
     }
     (void)sync_stream_nothrow(s2_);
   }
@@ -458,9 +498,10 @@ class ColourWorker {
   hipStream_t s2_ = nullptr;
   std::thread th_;
   std::mutex mu_;
-  std::condition_variable cv_;
-  std::deque<std::pair<int, hipEvent_t>> q_;
+  std::condition_variable cv_, done_cv_;
+  std::deque<Task> q_;
   bool done_ = false;
+  int colours_ = 0, coloured_ = 0;  // colouring tasks pushed / done
   amg_status st_ = AMG_OK;
   std::string msg_;
 };
@@ -499,8 +540,8 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
   const amg_params& p = H.p;
   H.lev[0].T = p.tile_rows;
   H.lev[0].ntiles = (H.lev[0].n + p.tile_rows - 1) / p.tile_rows;
-  ColourWorker colouring(H, overlap);
-  colouring.push(0, s);
+  SideThread side(H, overlap);
+  side.colour(0, s);
   for (;;) {
     const int l = (int)H.lev.size() - 1;
     if (H.lev[l].n <= p.coarse_max || l == p.max_levels - 1) break;
@@ -543,10 +584,13 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
     galerkin(H, H.lev[l], H.lev[l + 1], s);
     H.lev[l + 1].T = p.tile_rows;
     H.lev[l + 1].ntiles = (H.lev[l + 1].n + p.tile_rows - 1) / p.tile_rows;
-    colouring.push(l + 1, s);
+    side.colour(l + 1, s);
   }
-  colouring.finish();
   const int Lc = (int)H.lev.size() - 1;
+  if (H.lev[Lc].n > 4096)
+    fail(AMG_ERR_COARSENING_STALLED, "coarsest level has " + std::to_string(H.lev[Lc].n) + " rows");
+  side.factor(Lc, s);
+  side.wait_colours();
   H.lev[Lc].nc = 0;
   const bool f32 = p.vcycle_fp32 != 0;
   for (int l = 0; l <= Lc; ++l) {
@@ -603,11 +647,7 @@ void setup_impl(const amg_csr* A, const amg_params* pp, hipStream_t s, Hierarchy
       }
     }
   }
-  {
-    Level& C = H.lev[Lc];
-    if (C.n > 4096) fail(AMG_ERR_COARSENING_STALLED, "coarsest level has " + std::to_string(C.n) + " rows");
-    coarse_factor(H, C, s);
-  }
+  side.finish();
   sync_stream(s);
   H.setup_ms = now_ms() - t0;
 }
