@@ -157,7 +157,10 @@ AMG_API amg_status amg_default_params(amg_params *p);
  * prolongation), multicolouring for the smoother, optional FP32 copies; the
  * coarsest level (<= coarse_max rows) is factorised by a dense FP64 Cholesky.
  * Validates A first (INVALID_ARG, BAD_DIAGONAL, NOT_SYMMETRIC).  Blocks until
- * the hierarchy is complete.  *out receives the handle (NULL on failure). */
+ * the hierarchy is complete.  *out receives the handle (NULL on failure).
+ * The colourings and the coarsest factorisation run on a second host thread
+ * with a stream of its own (started and joined inside the call), beside the
+ * coarsening on `stream`. */
 AMG_API amg_status amg_setup(const amg_csr *A, const amg_params *p, void *stream, amg_hierarchy **out);
 
 /* One V-cycle z = M r (Sec. 2): pre-smoothing, residual restriction with P^T,
