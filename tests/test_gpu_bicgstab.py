@@ -191,6 +191,32 @@ def test_bicgstab_hybrid_sgs_fp64_iterates(A, name, T):
         assert true_res(s, x.cpu().numpy()) <= 1.01e-8
 
 
+@pytest.mark.parametrize("name", ["hetero_24", "k1_20"])
+@pytest.mark.parametrize("kw", [dict(smoother=2, smooth_tile_rows=256, coarse_smooth_tile_rows=64),
+                                dict(smoother=3), dict(coarse_smoother=3, coarse_from=1)],
+                         ids=["hybrid_blocks256_64", "tile_mcsgs", "headline_smoothing"])
+def test_bicgstab_smoothing_variants_fp64_iterates(A, name, kw):
+    """BiCGSTAB with the hybrid smoother on blocks of their own size (256
+    rows on level 0, 64 below), with the tile-ordered multicolour smoother on
+    every level, and with the headline's smoothing: iterates against the
+    oracle's."""
+    s = system(name)
+    rp, ci, v, b = A.to_device(s)
+    maxit = 100
+    with A.Hierarchy(rp, ci, v, **kw) as hg:
+        ho = O.Hierarchy(s.rowptr, s.colind, s.vals, **kw)
+        hist = torch.zeros((maxit + 1) * s.n, dtype=torch.float64, device="cuda")
+        x, r = hg.solve(b, rtol=1e-8, maxit=maxit, iter_hist=hist, method="bicgstab")
+        o = ho.bicgstab(s.b, rtol=1e-8, maxit=maxit, keep_iterates=True)
+        assert r.status == A.OK and o["status"] == O.OK
+        assert abs(r.iterations - o["iterations"]) <= 1
+        k = min(r.iterations, o["iterations"])
+        H = hist.cpu().numpy().reshape(maxit + 1, s.n)
+        worst = max(rel(H[it], o["iterates"][it]) for it in range(1, k + 1))
+        assert worst <= 1e-10, (name, kw, worst)
+        assert true_res(s, x.cpu().numpy()) <= 1.01e-8
+
+
 def test_hybrid_sgs_fp32_vcycle_and_cg(A):
     s = system("hetero_24")
     rp, ci, v, b = A.to_device(s)
